@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Throughput of the VLBM refinement hot path on one MI355X.
+
+One step = one coarse step of the whole hot path: the recursive sub-cycle of
+every level (fused ghost-fill / reflux-capture / stream / collide launches).
+Default workload: the four-quadrant Riemann problem, 512 x 512 coarse with a
+static r = 2 patch over the central 256 x 256 coarse cells (512 x 512 fine),
+FP64, seed 0, inputs resident in HBM before the timed region.
+
+metric: fine-equivalent cell updates per second = (nx0 r^L)(ny0 r^L) r^L per
+coarse step (the updates a uniform finest-level grid would need), over the
+timed steps. The JSON line also carries the roofline of the step kernel
+(algorithmic bytes: 16 populations in + 16 out per actual cell update) and
+the oracle timed on the host cores on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def build_case(name, steps):
+    from paper_2609_35529_amd import workloads as wl
+    if name == "quadrant512":
+        return wl.quadrant(n0=512, seed=0, steps=steps)
+    if name == "sod":
+        return wl.sod_2d(steps=steps)
+    if name == "uniform4096":
+        import numpy as np
+        n = 4096
+        U = wl.random_smooth_U(n, n, seed=0)
+        return wl.Case("uniform4096", n, n, 1.0 / n, 2, 1, 1.4, 4.0, 0.8, (0,) * 4, [], [U], steps)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def actual_updates_per_step(case):
+    """sum_l active_l * r^l: cell updates of one coarse step."""
+    import numpy as np
+    total = 0
+    cov = []
+    for l in range(case.nlev):
+        NY, NX = case.level_shape(l)
+        m = np.zeros((NY, NX), dtype=bool)
+        if l == 0:
+            m[:] = True
+        for (lv, i0, j0, nx, ny) in case.boxes:
+            if lv == l:
+                m[j0:j0 + ny, i0:i0 + nx] = True
+        cov.append(m)
+    for l in range(case.nlev):
+        act = cov[l].copy()
+        if l + 1 < case.nlev:
+            child = cov[l + 1][::case.r, ::case.r]
+            act &= ~child
+        total += int(act.sum()) * case.r ** l
+    return total
+
+
+def launches_per_step(case):
+    present = [l for l in range(case.nlev) if l == 0 or any(b[0] == l for b in case.boxes)]
+    return sum(case.r ** l for l in present)
+
+
+def cpu_baseline(case, budget_s=15.0):
+    """The oracle, single-threaded, on a bounded prefix of the same workload."""
+    from tests import exact
+    o = exact.run_oracle(case, steps=0)
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < budget_s and n < case.steps:
+        o.advance(1)
+        n += 1
+    el = time.perf_counter() - t0
+    fe = case.fine_equivalent_per_coarse_step() * n / el
+    return {"value": fe, "unit": "fine-equiv cell updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{case.name} full size, first {n} coarse steps ({el:.1f} s), FP64, one thread"}
+
+
+def copy_probe(gib=2.0, reps=20):
+    """Bandwidth of a plain device-to-device copy of known size (the practical
+    HBM ceiling, and the reference for scaling hardware byte counters)."""
+    import torch
+    n = int(gib * 2 ** 30 / 8)
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / reps
+    return {"copy_bytes_per_launch": 2 * n * 8, "copy_us": s * 1e6, "copy_GBs": 2 * n * 8 / s / 1e9}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="quadrant512")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only measure a plain 2 GiB device copy and exit")
+    args = ap.parse_args()
+    if args.copy_probe:
+        print(json.dumps(copy_probe()))
+        return
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; --gpus above 1 is not supported "
+              "(the multi-GPU design is described, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2609_35529_amd import vlbm
+
+    case = build_case(args.workload, args.warmup + args.steps)
+    prec = vlbm.FP64 if args.precision == "fp64" else vlbm.FP32
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    solver = vlbm.Solver.from_case(case, precision=prec, stream=stream)
+    T0, L0 = solver.totals()
+
+    print(f"[bench] {case.name} warmup {args.warmup}", file=sys.stderr, flush=True)
+    solver.advance(args.warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    solver.advance(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    T1, L1 = solver.totals()
+    healthy = solver.check_health()
+
+    fe_step = case.fine_equivalent_per_coarse_step()
+    value = fe_step * args.steps / wall
+    upd = actual_updates_per_step(case)
+    esz = 8 if prec == vlbm.FP64 else 4
+    bytes_per_update = 2 * 16 * esz
+    nl = launches_per_step(case)
+    avg_launch_s = gpu_ms / 1e3 / (args.steps * nl)
+    bytes_per_launch = upd * bytes_per_update / nl
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    scale = max(abs(x) for x in T0)
+    drift = [float(abs((T1[k] - T0[k]) - (L1[k] - L0[k])) / scale) for k in range(4)]
+
+    out = {
+        "metric": "fine-equiv cell updates/s",
+        "value": value,
+        "unit": "cell updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == vlbm.FP64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{case.name}: {case.nx0}x{case.ny0} coarse, levels {case.nlev}, "
+                               f"boxes {case.boxes}, r={case.r}, beta={case.beta}, "
+                               f"c={case.c:.4f}, seed 0",
+                   "fine_equiv_per_step": fe_step, "actual_updates_per_step": upd,
+                   "launches_per_step": nl},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "step_kernel", "bytes_per_launch": bytes_per_launch,
+                     "avg_launch_us": avg_launch_s * 1e6},
+        "actual_updates_per_s": upd * args.steps / wall,
+        "gpu_event_ms": gpu_ms,
+        "conservation_drift_rel": drift,
+        "healthy": healthy,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(build_case(args.workload, 10 ** 6), args.cpu_budget)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

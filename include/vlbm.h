@@ -1,0 +1,190 @@
+/*
+ * vlbm.h -- C ABI of libvlbm, the MI355X (gfx950) implementation of the
+ * vectorial lattice Boltzmann method (VLBM) for the 2-D compressible Euler
+ * equations with conservative, sub-cycled local grid refinement.
+ *
+ * Method (Hosseini, Straessle, Karlin, "Conservative local grid refinement for
+ * the vectorial lattice Boltzmann method"):
+ *   - D2Q4 vectorial populations f_q in R^4, q in {+x, -x, +y, -y}, carrying
+ *     W = (rho, rho u, rho v, rho E); equilibrium of Sec. 2.2 eq.
+ *     (num-equilibrium), exact streaming and BGK relaxation eq.
+ *     (num-relaxation), ideal-gas pressure p = (gamma-1)(E - |m|^2/(2 rho)).
+ *   - refinement ratio r, one link speed c on every level (Sec. 3.2 step 1);
+ *     level l advances r steps of dt_l = dx_l / c per step of level l-1.
+ *   - coarse-to-fine ghost populations from the mean-preserving temporal
+ *     reconstruction with the minmod tangential slope (Sec. 3.3, eqs.
+ *     2d-recon-tanslope and 2d-recon); fine-to-coarse populations from the
+ *     reflux average over r fine cells and r sub-steps (eq. 2d-reflux).
+ *   - regridding by merge (eq. amr-merge) and minmod split (eqs. amr-slope,
+ *     amr-split) (Sec. 3.4).
+ *
+ * Conventions
+ *   population index q: 0:+x 1:-x 2:+y 3:-y;  component k: 0:rho 1:rho u 2:rho v 3:rho E
+ *   domain sides: 0:west (x-) 1:east (x+) 2:south (y-) 3:north (y+)
+ *   level l has Nx_l = nx0 r^l by Ny_l = ny0 r^l cells of size dx_l = dx0 / r^l.
+ *   A box {level, i0, j0, nx, ny} covers level-l cells [i0, i0+nx) x [j0, j0+ny);
+ *   i0, j0, nx, ny must be multiples of r, and every covered cell's parent must
+ *   have its four neighbours covered at level l-1 (proper nesting; neighbours
+ *   outside a non-periodic side are exempt). Boxes of one level may touch or
+ *   overlap (their union counts). A cell is ACTIVE on level l when covered at
+ *   l and not covered at l+1; only active cells are advanced and counted.
+ *   Host arrays are row-major with x fastest: U[4][ny][ld], F[16][ny][ld]
+ *   with plane index q*4+k.
+ *
+ * Ownership and errors
+ *   Every call returns a vlbm_status and never throws across the ABI. Host
+ *   pointers are owned by the caller and used only during the call. Device
+ *   memory is suballocated from a caller-bound pool (vlbm_bind_pool) or, when
+ *   none is bound, allocated by the library; vlbm_destroy releases it. Work is
+ *   issued on the HIP stream given at creation (NULL: the default stream);
+ *   vlbm_advance returns before the GPU finishes, every call that returns data
+ *   to the host synchronises the stream first. A context must not be used from
+ *   two host threads at once. vlbm_last_error() describes the last failure on
+ *   the calling thread.
+ */
+#ifndef VLBM_H
+#define VLBM_H
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vlbm_ctx vlbm_ctx;
+
+typedef enum {
+  VLBM_OK = 0,
+  VLBM_EINVAL = -1,     /* bad argument */
+  VLBM_ENOMEM = -2,     /* device pool or host allocation exhausted */
+  VLBM_ENEST = -3,      /* hierarchy not properly nested or misaligned */
+  VLBM_EUNSTABLE = -4,  /* rho <= 0, p <= 0 or NaN found by vlbm_check_health */
+  VLBM_EDEVICE = -5,    /* a HIP runtime call failed */
+  VLBM_ESTATE = -6      /* call out of order (e.g. advance before set_hierarchy) */
+} vlbm_status;
+
+enum { VLBM_BC_PERIODIC = 0, VLBM_BC_OUTFLOW = 1, VLBM_BC_REFLECT = 2, VLBM_BC_INFLOW = 3 };
+enum { VLBM_FP64 = 0, VLBM_FP32 = 1 };
+
+/* Problem parameters (the paper's problem statement: base grid, ratio, EOS,
+ * relaxation, link speed; Sec. 2.2 and 3.2).
+ *   bc: per side. Periodic must be set on both sides of an axis. Outflow
+ *       copies the edge cell's own post-collision inbound population; reflect
+ *       returns the outgoing population with the normal momentum negated;
+ *       inflow injects f^eq(w_inflow[side]).
+ *   precision: VLBM_FP64 stores and relaxes populations in FP64;
+ *       VLBM_FP32 stores and relaxes them in FP32 while the reconstruction,
+ *       the reflux accumulators, the boundary ledger and the totals stay FP64.
+ *   beta in [0, 1] (0 switches relaxation off: pure streaming). */
+typedef struct {
+  int nx0, ny0;
+  double dx0;
+  int bc[4];
+  double w_inflow[4][4];
+  double gamma, c, beta;
+  int r;
+  int max_levels; /* number of levels including level 0, 1..8 */
+  int precision;
+} vlbm_params;
+
+typedef struct {
+  int level, i0, j0, nx, ny;
+} vlbm_box;
+
+/* Create a context. stream is a hipStream_t (NULL: default stream). */
+vlbm_status vlbm_create(const vlbm_params *params, void *stream, vlbm_ctx **out);
+
+/* Release all device memory the context owns and free it. NULL is a no-op. */
+void vlbm_destroy(vlbm_ctx *ctx);
+
+/* Suballocate every later device allocation of ctx from [dev, dev + bytes),
+ * a device region owned by the caller (e.g. a torch tensor) that must outlive
+ * the context. Must precede vlbm_set_hierarchy. */
+vlbm_status vlbm_bind_pool(vlbm_ctx *ctx, void *dev, size_t bytes);
+
+/* Device bytes a context with these parameters and boxes needs (admission
+ * control). Pure host computation. */
+size_t vlbm_footprint_bytes(const vlbm_params *params, const vlbm_box *boxes, int nboxes);
+
+/* Install a static hierarchy (level-0 always covers the domain). Discards any
+ * previous state; populations are undefined until vlbm_set_state. */
+vlbm_status vlbm_set_hierarchy(vlbm_ctx *ctx, const vlbm_box *boxes, int nboxes);
+
+/* Set the conserved state U[4][ny][ld] (host, FP64) of the level-l cells in
+ * [i0, i0+nx) x [j0, j0+ny) that are covered at level l: f := f^eq(U)
+ * (eq. num-equilibrium). Clears the previous-step samples of those cells and
+ * the boundary ledger. */
+vlbm_status vlbm_set_state(vlbm_ctx *ctx, int level, int i0, int j0, int nx, int ny,
+                           const double *U, long ld);
+
+/* Same with raw populations F[16][ny][ld] (host, FP64). */
+vlbm_status vlbm_set_populations(vlbm_ctx *ctx, int level, int i0, int j0, int nx, int ny,
+                                 const double *F, long ld);
+
+/* Advance n coarse steps: each is the recursive sub-cycle of Sec. 3.2-3.3
+ * (r steps of level l+1 per step of level l, reconstruction into fine ghosts,
+ * reflux into coarse ring cells). Asynchronous on the context's stream. */
+vlbm_status vlbm_advance(vlbm_ctx *ctx, int n_coarse_steps);
+
+/* Read W = sum_q f_q (U[4][ny][ld], host, FP64) of active level-l cells in the
+ * rectangle; other cells get NaN. Synchronises. */
+vlbm_status vlbm_get_state(vlbm_ctx *ctx, int level, int i0, int j0, int nx, int ny, double *U,
+                           long ld);
+
+/* Read the stored post-collision populations F[16][ny][ld] (FP64 on the host,
+ * widened in the FP32 form) of active cells; others NaN. Synchronises. */
+vlbm_status vlbm_get_populations(vlbm_ctx *ctx, int level, int i0, int j0, int nx, int ny,
+                                 double *F, long ld);
+
+/* Conserved totals T_k = sum_l dx_l^2 sum_active sum_q f_{q,k} (FP64,
+ * compensated, fixed summation order) and the boundary ledger: the net amount
+ * of each component that entered through non-periodic sides since the last
+ * set_state. T(t) - T(0) equals the ledger to round-off. Synchronises. */
+vlbm_status vlbm_conserved_totals(vlbm_ctx *ctx, double totals[4], double ledger[4]);
+
+/* Replace the hierarchy by boxes, moving the state conservatively: merge
+ * exiting cells finest level first (eq. amr-merge), then split entering cells
+ * coarsest level first (eqs. amr-slope, amr-split). Synchronises. */
+vlbm_status vlbm_regrid(vlbm_ctx *ctx, const vlbm_box *boxes, int nboxes);
+
+/* Density-gradient tags of active level-l cells:
+ * max over axes |rho(+1) - rho(-1)| / (2 rho) > threshold, a missing or
+ * inactive neighbour replaced by the cell itself. tags[Ny_l][Nx_l] (host).
+ * Synchronises. */
+vlbm_status vlbm_tag(vlbm_ctx *ctx, int level, double threshold, unsigned char *tags);
+
+/* Tag every level below the finest, dilate by `buffer` cells, cluster into
+ * boxes with sides in [min_box, max_box] level-(l+1) cells and regrid
+ * (Sec. 3.4, Fig. amr-flowchart). Synchronises. */
+vlbm_status vlbm_tag_and_regrid(vlbm_ctx *ctx, double threshold, int buffer, int min_box,
+                                int max_box);
+
+/* Current boxes (up to cap) and their count. */
+vlbm_status vlbm_get_boxes(vlbm_ctx *ctx, vlbm_box *boxes, int cap, int *nboxes);
+
+/* Scan active cells for rho <= 0, p <= 0 or NaN; returns VLBM_EUNSTABLE if any. */
+vlbm_status vlbm_check_health(vlbm_ctx *ctx);
+
+/* Serialise populations, both previous-step samples, reflux/ledger state, the
+ * hierarchy and the step counters into buf (size *bytes; with buf NULL only the
+ * size is returned). vlbm_load restores it into a context created with equal
+ * parameters. Resume is bitwise. Synchronise. */
+vlbm_status vlbm_save(vlbm_ctx *ctx, void *buf, size_t *bytes);
+vlbm_status vlbm_load(vlbm_ctx *ctx, const void *buf, size_t bytes);
+
+/* Advance several contexts together, n_steps[i] coarse steps each, with the
+ * phases of all contexts merged into shared launches. All contexts must use
+ * the same stream and precision. */
+vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nctx);
+
+/* Coarse steps taken since set_state. */
+long vlbm_steps(const vlbm_ctx *ctx);
+
+/* Wait for all work of ctx. */
+vlbm_status vlbm_sync(vlbm_ctx *ctx);
+
+const char *vlbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1007 @@
+// Host side of libvlbm: hierarchy frames, tile and task lists, the recursive
+// sub-cycle schedule, and the C ABI declared in include/vlbm.h.
+//
+// Schedule (paper Sec. 3.2, Fig. 1, and Sec. 3.3): one coarse step of level l
+// runs r steps of level l+1 first, each of which recursively runs level l+2,
+// then advances level l itself. Every level step is ONE launch of the fused
+// step kernel: its workgroups fill their own ghost slots (periodic images,
+// boundary values, reconstruction from the parent's two stored time levels,
+// reflux from the accumulator the finer level filled), add this sub-step's
+// outgoing edge values into the parent's reflux accumulators, then stream and
+// relax their cells. Because the stored state is post-collision, a level's
+// step needs its parent's samples at t_n and t_n - dt_{l-1} (both buffers of
+// the parent) and its children's r sub-steps to have completed (for the reflux),
+// which the finest-first order guarantees.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/vlbm.h"
+#include "vlbm_internal.hpp"
+
+using namespace vlbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+vlbm_status fail(vlbm_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(VLBM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+  } while (0)
+
+constexpr int kMaxLevels = 8;
+const int CX[4] = {1, -1, 0, 0};
+const int CY[4] = {0, 0, 1, -1};
+
+int tile_cells_default() {
+  const char *e = getenv("VLBM_TILE_CELLS");
+  int v = e ? atoi(e) : 256;
+  if (v < 64) v = 64;
+  if (v > (1 << 20)) v = 1 << 20;
+  return v;
+}
+
+// ----------------------------------------------------------------------------
+// Device memory: first-fit suballocation of a caller-bound region, or hipMalloc.
+// ----------------------------------------------------------------------------
+struct DevMem {
+  char *base = nullptr;
+  size_t size = 0;
+  bool bound = false;
+  std::map<size_t, size_t> free_;     // offset -> length
+  std::map<void *, size_t> live_;     // pointer -> length (bound region)
+  std::vector<void *> owned_;         // hipMalloc'ed blocks
+
+  static size_t round(size_t n) { return (n + 255) & ~size_t(255); }
+
+  void bind(void *p, size_t n) {
+    base = static_cast<char *>(p);
+    size = n & ~size_t(255);
+    bound = true;
+    free_.clear();
+    live_.clear();
+    size_t lead = (256 - (reinterpret_cast<uintptr_t>(base) & 255)) & 255;
+    if (lead < size) free_[lead] = size - lead;
+  }
+
+  void *alloc(size_t n) {
+    n = round(std::max<size_t>(n, 256));
+    if (!bound) {
+      void *p = nullptr;
+      if (hipMalloc(&p, n) != hipSuccess) return nullptr;
+      owned_.push_back(p);
+      return p;
+    }
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        size_t off = it->first, len = it->second;
+        free_.erase(it);
+        if (len > n) free_[off + n] = len - n;
+        void *p = base + off;
+        live_[p] = n;
+        return p;
+      }
+    }
+    return nullptr;
+  }
+
+  void release(void *p) {
+    if (!p) return;
+    if (!bound) {
+      auto it = std::find(owned_.begin(), owned_.end(), p);
+      if (it != owned_.end()) {
+        (void)hipFree(p);
+        owned_.erase(it);
+      }
+      return;
+    }
+    auto it = live_.find(p);
+    if (it == live_.end()) return;
+    size_t off = static_cast<char *>(p) - base, len = it->second;
+    live_.erase(it);
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.end() && off + len == nx->first) {
+      len += nx->second;
+      nx = free_.erase(nx);
+    }
+    if (nx != free_.begin()) {
+      auto pv = std::prev(nx);
+      if (pv->first + pv->second == off) {
+        pv->second += len;
+        return;
+      }
+    }
+    free_[off] = len;
+  }
+
+  void release_all() {
+    for (void *p : owned_) (void)hipFree(p);
+    owned_.clear();
+    if (bound) bind(base, size);
+  }
+};
+
+struct Level {
+  bool present = false;
+  int Nx = 0, Ny = 0;
+  double dx = 0.0;
+  int fx0 = 0, fy0 = 0, fw = 0, fh = 0;  // frame = coverage bounding box + 1 ghost cell
+  int pitch = 0, xoff = 0;
+  int64_t plane = 0;
+  void *buf[2] = {nullptr, nullptr};
+  uint8_t *dstatus = nullptr;
+  std::vector<uint8_t> cov;     // per frame cell: covered at this level
+  std::vector<uint8_t> status;  // 0 none, 1 active, 2 hole
+  std::vector<Tile> tiles;
+  std::vector<Task> tasks;
+  Tile *dtiles = nullptr;
+  Task *dtasks = nullptr;
+  double *dacc = nullptr;       // reflux accumulators of ring cells of this level
+  int nacc = 0;
+  double *dledger = nullptr;
+  int nledger = 0;
+  double *dpartial = nullptr;
+  long steps = 0;
+  std::unordered_map<int64_t, int> acc_slot;  // (cell, q) of a ring cell -> slot
+
+  int64_t off(int x, int y) const {
+    return (int64_t)(y - fy0) * pitch + (x - fx0) + xoff;
+  }
+  bool in_frame(int x, int y) const {
+    return x >= fx0 && y >= fy0 && x < fx0 + fw && y < fy0 + fh;
+  }
+  size_t fidx(int x, int y) const { return (size_t)(y - fy0) * fw + (x - fx0); }
+  int cur() const { return (int)(steps & 1); }
+};
+
+}  // namespace
+
+struct vlbm_ctx {
+  vlbm_params p{};
+  hipStream_t stream = nullptr;
+  bool fp32 = false;
+  size_t esz = 8;
+  DevMem mem;
+  Level lv[kMaxLevels];
+  int nlev = 1;  // levels present (0..nlev-1)
+  std::vector<vlbm_box> boxes;
+  bool have_hierarchy = false;
+  long coarse_steps = 0;
+  int tile_cells = 256;
+  int step_flags = 0;
+  int *dflag = nullptr;
+  double gm1 = 0, h = 0, tb = 0;
+
+  bool perx() const { return p.bc[0] == VLBM_BC_PERIODIC; }
+  bool pery() const { return p.bc[2] == VLBM_BC_PERIODIC; }
+  bool wrap(int l, int &x, int &y) const {
+    const Level &L = lv[l];
+    if (x < 0 || x >= L.Nx) {
+      if (!perx()) return false;
+      x = ((x % L.Nx) + L.Nx) % L.Nx;
+    }
+    if (y < 0 || y >= L.Ny) {
+      if (!pery()) return false;
+      y = ((y % L.Ny) + L.Ny) % L.Ny;
+    }
+    return true;
+  }
+  // (x, y) must be in-domain coordinates of level l.
+  bool covered(int l, int x, int y) const {
+    if (l >= kMaxLevels || !lv[l].present) return false;
+    const Level &L = lv[l];
+    if (!L.in_frame(x, y)) return false;
+    return L.cov[L.fidx(x, y)] != 0;
+  }
+  bool active(int l, int x, int y) const {
+    if (!covered(l, x, y)) return false;
+    if (l + 1 < kMaxLevels && covered(l + 1, x * p.r, y * p.r)) return false;
+    return true;
+  }
+};
+
+namespace {
+
+void free_level(vlbm_ctx *c, Level &L) {
+  c->mem.release(L.buf[0]);
+  c->mem.release(L.buf[1]);
+  c->mem.release(L.dstatus);
+  c->mem.release(L.dtiles);
+  c->mem.release(L.dtasks);
+  c->mem.release(L.dacc);
+  c->mem.release(L.dledger);
+  c->mem.release(L.dpartial);
+  long steps = L.steps;
+  L = Level();
+  L.steps = steps;
+}
+
+// --------------------------------------------------------------------------
+// Hierarchy geometry (host)
+// --------------------------------------------------------------------------
+struct Geometry {
+  bool present[kMaxLevels] = {};
+  int bx0[kMaxLevels], by0[kMaxLevels], bx1[kMaxLevels], by1[kMaxLevels];
+};
+
+vlbm_status check_boxes(const vlbm_params &p, const vlbm_box *boxes, int n, Geometry &g) {
+  for (int l = 0; l < kMaxLevels; ++l) {
+    g.present[l] = false;
+    g.bx0[l] = g.by0[l] = 1 << 30;
+    g.bx1[l] = g.by1[l] = -(1 << 30);
+  }
+  g.present[0] = true;
+  g.bx0[0] = 0;
+  g.by0[0] = 0;
+  g.bx1[0] = p.nx0;
+  g.by1[0] = p.ny0;
+  if (n < 0 || (n > 0 && !boxes)) return fail(VLBM_EINVAL, "bad box list");
+  for (int b = 0; b < n; ++b) {
+    const vlbm_box &B = boxes[b];
+    if (B.level < 1 || B.level >= p.max_levels)
+      return fail(VLBM_EINVAL, "box %d: level %d outside 1..%d", b, B.level, p.max_levels - 1);
+    long s = 1;
+    for (int i = 0; i < B.level; ++i) s *= p.r;
+    long Nx = p.nx0 * s, Ny = p.ny0 * s;
+    if (B.nx <= 0 || B.ny <= 0 || B.i0 < 0 || B.j0 < 0 || B.i0 + (long)B.nx > Nx ||
+        B.j0 + (long)B.ny > Ny)
+      return fail(VLBM_EINVAL, "box %d lies outside its level's domain", b);
+    if (B.i0 % p.r || B.j0 % p.r || B.nx % p.r || B.ny % p.r)
+      return fail(VLBM_ENEST, "box %d is not made of whole parent cells (ratio %d)", b, p.r);
+    int l = B.level;
+    g.present[l] = true;
+    g.bx0[l] = std::min(g.bx0[l], B.i0);
+    g.by0[l] = std::min(g.by0[l], B.j0);
+    g.bx1[l] = std::max(g.bx1[l], B.i0 + B.nx);
+    g.by1[l] = std::max(g.by1[l], B.j0 + B.ny);
+  }
+  for (int l = 1; l < kMaxLevels; ++l)
+    if (g.present[l] && !g.present[l - 1])
+      return fail(VLBM_ENEST, "level %d has boxes but level %d has none", l, l - 1);
+  return VLBM_OK;
+}
+
+void frame_of(const vlbm_params &p, size_t esz, const Geometry &g, int l, Level &L) {
+  long s = 1;
+  for (int i = 0; i < l; ++i) s *= p.r;
+  L.Nx = (int)(p.nx0 * s);
+  L.Ny = (int)(p.ny0 * s);
+  L.dx = p.dx0 / (double)s;
+  L.present = g.present[l];
+  if (!L.present) {
+    L.fx0 = L.fy0 = L.fw = L.fh = L.pitch = L.xoff = 0;
+    L.plane = 0;
+    return;
+  }
+  L.fx0 = g.bx0[l] - 1;
+  L.fy0 = g.by0[l] - 1;
+  L.fw = g.bx1[l] - g.bx0[l] + 2;
+  L.fh = g.by1[l] - g.by0[l] + 2;
+  // The first interior column starts on a 128-byte line; rows are padded to 64
+  // elements and every population plane to a multiple of 4 KiB. Measured on
+  // MI355X for a 4096^2 FP64 frame: a plane stride of 512 B mod 4 KiB runs the
+  // step kernel at 4.4 TB/s, 4 KiB-aligned planes at 5.1-5.25 TB/s.
+  const int align = (int)(128 / esz);
+  L.xoff = align - 1;
+  L.pitch = (L.fw + L.xoff + 63) / 64 * 64;
+  const int64_t pa = 4096 / (int64_t)esz;
+  L.plane = ((int64_t)L.pitch * L.fh + pa - 1) / pa * pa;
+}
+
+size_t level_bytes(const Level &L, size_t esz) { return (size_t)L.plane * 16 * esz; }
+
+// Build coverage, check nesting, build status, tiles and tasks for all levels.
+vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
+  const vlbm_params &p = c->p;
+  const int r = p.r;
+  // coverage
+  for (int l = 0; l < kMaxLevels && c->lv[l].present; ++l) {
+    Level &L = c->lv[l];
+    L.cov.assign((size_t)L.fw * L.fh, 0);
+    if (l == 0) {
+      for (int y = 0; y < L.Ny; ++y)
+        for (int x = 0; x < L.Nx; ++x) L.cov[L.fidx(x, y)] = 1;
+    }
+  }
+  for (int b = 0; b < n; ++b) {
+    Level &L = c->lv[boxes[b].level];
+    for (int y = boxes[b].j0; y < boxes[b].j0 + boxes[b].ny; ++y)
+      memset(&L.cov[L.fidx(boxes[b].i0, y)], 1, boxes[b].nx);
+  }
+  // proper nesting: a covered cell's parent and the parent's 4 neighbours are covered
+  for (int l = 1; l < kMaxLevels && c->lv[l].present; ++l) {
+    const Level &L = c->lv[l];
+    for (int y = L.fy0 + 1; y < L.fy0 + L.fh - 1; y += r)
+      for (int x = L.fx0 + 1; x < L.fx0 + L.fw - 1; x += r) {
+        if (!L.cov[L.fidx(x, y)]) continue;
+        int px = x / r, py = y / r;
+        for (int d = -1; d < 4; ++d) {
+          int nx = px + (d < 0 ? 0 : CX[d]), ny = py + (d < 0 ? 0 : CY[d]);
+          if (!c->wrap(l - 1, nx, ny)) continue;
+          if (!c->covered(l - 1, nx, ny))
+            return fail(VLBM_ENEST,
+                        "level %d cell (%d,%d): parent neighbour (%d,%d) not covered at level %d",
+                        l, x, y, nx, ny, l - 1);
+        }
+      }
+  }
+  // status
+  for (int l = 0; l < kMaxLevels && c->lv[l].present; ++l) {
+    Level &L = c->lv[l];
+    L.status.assign(L.cov.size(), 0);
+    for (int y = L.fy0; y < L.fy0 + L.fh; ++y)
+      for (int x = L.fx0; x < L.fx0 + L.fw; ++x) {
+        size_t i = L.fidx(x, y);
+        if (!L.cov[i]) continue;
+        L.status[i] = c->covered(l + 1, x * r, y * r) ? 2 : 1;
+      }
+  }
+  // tiles: runs of active cells per row, stacked into rectangles of <= tile_cells
+  const int TC = c->tile_cells;
+  for (int l = 0; l < kMaxLevels && c->lv[l].present; ++l) {
+    Level &L = c->lv[l];
+    L.tiles.clear();
+    std::map<std::pair<int, int>, Tile> open;  // (xa, xb) -> rectangle being grown
+    std::vector<std::pair<int, int>> rect_xy;  // (x0, y0) of each emitted tile, for lookup
+    auto emit = [&](int xa, int y0, const Tile &t) {
+      // split wide rectangles (h == 1) into chunks of at most TC cells
+      int w = t.w;
+      for (int x = 0; x < w; x += TC) {
+        Tile u{};
+        u.w = std::min(TC, w - x);
+        u.h = t.h;
+        u.off0 = (int32_t)L.off(xa + x, y0);
+        L.tiles.push_back(u);
+        rect_xy.push_back({xa + x, y0});
+      }
+    };
+    std::vector<std::pair<int, int>> runs;
+    std::map<std::pair<int, int>, int> open_y0;
+    for (int y = L.fy0; y < L.fy0 + L.fh; ++y) {
+      runs.clear();
+      int x = L.fx0;
+      while (x < L.fx0 + L.fw) {
+        if (L.status[L.fidx(x, y)] == 1) {
+          int xa = x;
+          while (x < L.fx0 + L.fw && L.status[L.fidx(x, y)] == 1) ++x;
+          runs.push_back({xa, x});
+        } else {
+          ++x;
+        }
+      }
+      std::map<std::pair<int, int>, Tile> nopen;
+      std::map<std::pair<int, int>, int> nopen_y0;
+      for (auto &rn : runs) {
+        int w = rn.second - rn.first;
+        int maxh = std::max(1, TC / w);
+        auto it = open.find(rn);
+        if (it != open.end() && it->second.h < maxh) {
+          Tile t = it->second;
+          t.h += 1;
+          nopen[rn] = t;
+          nopen_y0[rn] = open_y0[rn];
+          open.erase(it);
+        } else {
+          if (it != open.end()) {
+            emit(rn.first, open_y0[rn], it->second);
+            open.erase(it);
+          }
+          Tile t{};
+          t.w = w;
+          t.h = 1;
+          nopen[rn] = t;
+          nopen_y0[rn] = y;
+        }
+      }
+      for (auto &kv : open) emit(kv.first.first, open_y0[kv.first], kv.second);
+      open.swap(nopen);
+      open_y0.swap(nopen_y0);
+    }
+    for (auto &kv : open) emit(kv.first.first, open_y0[kv.first], kv.second);
+    // order tiles by (y0, x0) for locality
+    std::vector<int> order(L.tiles.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::sort(order.begin(), order.end(), [&](int a, int b) {
+      return rect_xy[a].second != rect_xy[b].second ? rect_xy[a].second < rect_xy[b].second
+                                                    : rect_xy[a].first < rect_xy[b].first;
+    });
+    std::vector<Tile> sorted;
+    std::vector<std::pair<int, int>> sxy;
+    for (int i : order) {
+      sorted.push_back(L.tiles[i]);
+      sxy.push_back(rect_xy[i]);
+    }
+    L.tiles.swap(sorted);
+    rect_xy.swap(sxy);
+    // cell -> tile map (frame cells)
+    std::vector<int32_t> owner(L.cov.size(), -1);
+    for (size_t t = 0; t < L.tiles.size(); ++t)
+      for (int yy = 0; yy < L.tiles[t].h; ++yy)
+        for (int xx = 0; xx < L.tiles[t].w; ++xx)
+          owner[L.fidx(rect_xy[t].first + xx, rect_xy[t].second + yy)] = (int32_t)t;
+    // tasks
+    std::vector<std::pair<int, Task>> tk;  // (tile, task)
+    L.acc_slot.clear();
+    L.nledger = 0;
+    for (int y = L.fy0 + 1; y < L.fy0 + L.fh - 1; ++y)
+      for (int x = L.fx0 + 1; x < L.fx0 + L.fw - 1; ++x) {
+        if (L.status[L.fidx(x, y)] != 1) continue;
+        const int tile = owner[L.fidx(x, y)];
+        for (int q = 0; q < 4; ++q) {
+          int sx = x - CX[q], sy = y - CY[q];
+          int wx = sx, wy = sy;
+          Task t{};
+          t.q = q;
+          t.dst = (int32_t)L.off(sx, sy);
+          t.n0 = t.n1 = -1;
+          if (!c->wrap(l, wx, wy)) {
+            const int side = q;  // +x enters through west (0), -x east (1), +y south (2), -y north (3)
+            const int bc = p.bc[side];
+            t.kind = bc == VLBM_BC_OUTFLOW ? T_OUTFLOW : bc == VLBM_BC_REFLECT ? T_REFLECT : T_INFLOW;
+            t.src = (int32_t)L.off(x, y);
+            t.n0 = side;
+            t.slot = L.nledger++;
+            tk.push_back({tile, t});
+          } else if (c->covered(l + 1, wx * r, wy * r)) {
+            int64_t key = ((int64_t)y * L.Nx + x) * 4 + q;
+            int slot = (int)L.acc_slot.size();
+            L.acc_slot[key] = slot;
+            t.kind = T_REFLUX;
+            t.slot = slot;
+            tk.push_back({tile, t});
+          } else if (c->covered(l, wx, wy)) {
+            if (wx != sx || wy != sy) {
+              t.kind = T_COPY;
+              t.src = (int32_t)L.off(wx, wy);
+              tk.push_back({tile, t});
+            }
+          } else {
+            if (l == 0) return fail(VLBM_ENEST, "internal: level-0 cell without source");
+            const Level &PL = c->lv[l - 1];
+            int px = wx / r, py = wy / r;
+            if (!c->active(l - 1, px, py))
+              return fail(VLBM_ENEST, "level %d cell (%d,%d): parent ring cell inactive", l, x, y);
+            t.kind = T_RECON;
+            t.src = (int32_t)PL.off(px, py);
+            int tx = q < 2 ? 0 : 1, ty = q < 2 ? 1 : 0;
+            t.j = q < 2 ? (y - r * py) : (x - r * px);
+            int mx = px - tx, my = py - ty, qx = px + tx, qy = py + ty;
+            bool have = c->wrap(l - 1, mx, my) && c->wrap(l - 1, qx, qy) &&
+                        c->active(l - 1, mx, my) && c->active(l - 1, qx, qy);
+            if (have) {
+              t.n0 = (int32_t)PL.off(mx, my);
+              t.n1 = (int32_t)PL.off(qx, qy);
+            }
+            tk.push_back({tile, t});
+          }
+        }
+      }
+    // captures: values leaving level l towards the parent's ring cells
+    if (l >= 1) {
+      const Level &PL = c->lv[l - 1];
+      std::unordered_map<int, size_t> cap;  // parent slot -> index in tk
+      std::vector<int> count;
+      for (int y = L.fy0 + 1; y < L.fy0 + L.fh - 1; ++y)
+        for (int x = L.fx0 + 1; x < L.fx0 + L.fw - 1; ++x) {
+          if (L.status[L.fidx(x, y)] != 1) continue;
+          for (int q = 0; q < 4; ++q) {
+            int dx = x + CX[q], dy = y + CY[q];
+            if (!c->wrap(l, dx, dy)) continue;
+            if (c->covered(l, dx, dy)) continue;
+            int px = dx / r, py = dy / r;
+            int64_t key = ((int64_t)py * PL.Nx + px) * 4 + q;
+            auto it = PL.acc_slot.find(key);
+            if (it == PL.acc_slot.end())
+              return fail(VLBM_ENEST, "internal: no reflux slot for level %d ring cell", l - 1);
+            auto ct = cap.find(it->second);
+            if (ct == cap.end()) {
+              Task t{};
+              t.kind = T_CAPTURE;
+              t.q = q;
+              t.src = (int32_t)L.off(x, y);
+              t.n0 = q < 2 ? L.pitch : 1;
+              t.n1 = -1;
+              t.slot = it->second;
+              cap[it->second] = tk.size();
+              tk.push_back({owner[L.fidx(x, y)], t});
+              count.push_back(1);
+            } else {
+              Task &t = tk[ct->second].second;
+              int64_t want = (int64_t)t.src + (int64_t)t.n0 * (t.j + 1);
+              if (want != L.off(x, y))
+                return fail(VLBM_ENEST, "internal: reflux cells not contiguous");
+              t.j += 1;  // counts captured cells beyond the first (device ignores j)
+            }
+          }
+        }
+      for (auto &kv : cap)
+        if (tk[kv.second].second.j + 1 != r)
+          return fail(VLBM_ENEST, "internal: ring cell sees %d fine cells, expected %d",
+                      tk[kv.second].second.j + 1, r);
+    }
+    std::stable_sort(tk.begin(), tk.end(),
+                     [](const std::pair<int, Task> &a, const std::pair<int, Task> &b) {
+                       return a.first < b.first;
+                     });
+    L.tasks.clear();
+    for (auto &t : L.tiles) t.task0 = t.ntask = 0;
+    for (size_t i = 0; i < tk.size(); ++i) {
+      Tile &t = L.tiles[tk[i].first];
+      if (t.ntask == 0) t.task0 = (int32_t)L.tasks.size();
+      t.ntask += 1;
+      L.tasks.push_back(tk[i].second);
+    }
+    L.nacc = (int)L.acc_slot.size();
+  }
+  return VLBM_OK;
+}
+
+vlbm_status upload_level(vlbm_ctx *c, Level &L, bool alloc_buffers) {
+  auto &M = c->mem;
+  if (alloc_buffers) {
+    size_t nb = level_bytes(L, c->esz);
+    L.buf[0] = M.alloc(nb);
+    L.buf[1] = M.alloc(nb);
+    if (!L.buf[0] || !L.buf[1]) return fail(VLBM_ENOMEM, "population buffers (%zu bytes)", nb);
+    HIPCHK(hipMemsetAsync(L.buf[0], 0, nb, c->stream));
+    HIPCHK(hipMemsetAsync(L.buf[1], 0, nb, c->stream));
+  }
+  L.dstatus = static_cast<uint8_t *>(M.alloc(L.status.size()));
+  L.dtiles = static_cast<Tile *>(M.alloc(sizeof(Tile) * std::max<size_t>(1, L.tiles.size())));
+  L.dtasks = static_cast<Task *>(M.alloc(sizeof(Task) * std::max<size_t>(1, L.tasks.size())));
+  L.dacc = static_cast<double *>(M.alloc(sizeof(double) * 4 * std::max(1, L.nacc)));
+  L.dledger = static_cast<double *>(M.alloc(sizeof(double) * 4 * std::max(1, L.nledger)));
+  L.dpartial = static_cast<double *>(M.alloc(sizeof(double) * 4 * std::max<size_t>(1, L.tiles.size())));
+  if (!L.dstatus || !L.dtiles || !L.dtasks || !L.dacc || !L.dledger || !L.dpartial)
+    return fail(VLBM_ENOMEM, "level tables");
+  HIPCHK(hipMemcpyAsync(L.dstatus, L.status.data(), L.status.size(), hipMemcpyHostToDevice, c->stream));
+  if (!L.tiles.empty())
+    HIPCHK(hipMemcpyAsync(L.dtiles, L.tiles.data(), sizeof(Tile) * L.tiles.size(), hipMemcpyHostToDevice, c->stream));
+  if (!L.tasks.empty())
+    HIPCHK(hipMemcpyAsync(L.dtasks, L.tasks.data(), sizeof(Task) * L.tasks.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemsetAsync(L.dacc, 0, sizeof(double) * 4 * std::max(1, L.nacc), c->stream));
+  HIPCHK(hipMemsetAsync(L.dledger, 0, sizeof(double) * 4 * std::max(1, L.nledger), c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return VLBM_OK;
+}
+
+// One step of level l at sub-step k of its parent's cycle.
+vlbm_status step_level(vlbm_ctx *c, int l, int k) {
+  Level &L = c->lv[l];
+  StepArgs a{};
+  a.src = L.buf[L.cur()];
+  a.dst = L.buf[L.cur() ^ 1];
+  if (l > 0) {
+    Level &P = c->lv[l - 1];
+    a.pcur = P.buf[P.cur()];
+    a.pprev = P.buf[P.cur() ^ 1];
+    a.pplane = P.plane;
+    a.acc_out = P.dacc;
+  }
+  a.tiles = L.dtiles;
+  a.tasks = L.dtasks;
+  a.acc_in = L.dacc;
+  a.ledger = L.dledger;
+  a.plane = L.plane;
+  a.pitch = L.pitch;
+  a.ntiles = (int)L.tiles.size();
+  a.per_xcd = (a.ntiles + 7) / 8;
+  a.first = (k == 1);
+  a.flags = c->step_flags;
+  a.r = c->p.r;
+  a.ak = (double)(2 * k - c->p.r - 1) / (double)(2 * c->p.r);
+  a.rr = (double)(c->p.r * c->p.r);
+  a.w2 = L.dx * L.dx;
+  a.gm1 = c->gm1;
+  a.h = c->h;
+  a.tb = c->tb;
+  for (int s = 0; s < 4; ++s)
+    for (int kk = 0; kk < 4; ++kk) a.win[s][kk] = c->p.w_inflow[s][kk];
+  HIPCHK(launch_step(a, c->fp32, c->stream));
+  L.steps += 1;
+  return VLBM_OK;
+}
+
+vlbm_status cycle(vlbm_ctx *c, int l, int k) {
+  if (l + 1 < c->nlev)
+    for (int kk = 1; kk <= c->p.r; ++kk) {
+      vlbm_status st = cycle(c, l + 1, kk);
+      if (st) return st;
+    }
+  return step_level(c, l, k);
+}
+
+vlbm_status check_rect(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny) {
+  if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "no hierarchy installed");
+  if (level < 0 || level >= c->p.max_levels) return fail(VLBM_EINVAL, "bad level %d", level);
+  long s = 1;
+  for (int i = 0; i < level; ++i) s *= c->p.r;
+  if (i0 < 0 || j0 < 0 || nx < 0 || ny < 0 || i0 + (long)nx > c->p.nx0 * s ||
+      j0 + (long)ny > c->p.ny0 * s)
+    return fail(VLBM_EINVAL, "rectangle outside level %d", level);
+  return VLBM_OK;
+}
+
+// Clip a rectangle to a level's frame; returns false if empty.
+bool clip_to_frame(const Level &L, int &i0, int &j0, int &nx, int &ny, int &ox, int &oy) {
+  int x0 = std::max(i0, L.fx0), y0 = std::max(j0, L.fy0);
+  int x1 = std::min(i0 + nx, L.fx0 + L.fw), y1 = std::min(j0 + ny, L.fy0 + L.fh);
+  ox = x0 - i0;
+  oy = y0 - j0;
+  if (x1 <= x0 || y1 <= y0) return false;
+  i0 = x0;
+  j0 = y0;
+  nx = x1 - x0;
+  ny = y1 - y0;
+  return true;
+}
+
+vlbm_status rect_io(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny, double *host, long ld,
+                    int ncomp, bool write, bool raw) {
+  vlbm_status st = check_rect(c, level, i0, j0, nx, ny);
+  if (st) return st;
+  if (ld < nx) return fail(VLBM_EINVAL, "ld < nx");
+  Level &L = c->lv[level];
+  const size_t full_plane = (size_t)ny * ld;
+  if (!write) {  // defaults: NaN everywhere, then fill the part inside the frame
+    for (int k = 0; k < ncomp; ++k)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) host[k * full_plane + (size_t)y * ld + x] = NAN;
+  }
+  if (!L.present) return VLBM_OK;
+  int ci0 = i0, cj0 = j0, cnx = nx, cny = ny, ox = 0, oy = 0;
+  if (!clip_to_frame(L, ci0, cj0, cnx, cny, ox, oy)) return VLBM_OK;
+  const size_t n = (size_t)cnx * cny;
+  double *stage = static_cast<double *>(c->mem.alloc(sizeof(double) * ncomp * n));
+  if (!stage) return fail(VLBM_ENOMEM, "staging buffer");
+  std::vector<double> tmp(ncomp * n);
+  RectArgs a{};
+  a.buf0 = write ? L.buf[0] : L.buf[L.cur()];
+  a.buf1 = L.buf[1];
+  a.status = L.dstatus;
+  a.host_stage = stage;
+  a.plane = L.plane;
+  a.pitch = L.pitch;
+  a.xoff = L.xoff;
+  a.fx0 = L.fx0;
+  a.fy0 = L.fy0;
+  a.fw = L.fw;
+  a.x0 = ci0;
+  a.y0 = cj0;
+  a.nx = cnx;
+  a.ny = cny;
+  a.gm1 = c->gm1;
+  a.h = c->h;
+  hipError_t e = hipSuccess;
+  if (write) {
+    for (int k = 0; k < ncomp; ++k)
+      for (int y = 0; y < cny; ++y)
+        memcpy(&tmp[k * n + (size_t)y * cnx], &host[k * full_plane + (size_t)(y + oy) * ld + ox],
+               sizeof(double) * cnx);
+    e = hipMemcpyAsync(stage, tmp.data(), sizeof(double) * ncomp * n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_set_state(a, c->fp32, raw ? 1 : 0, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  } else {
+    e = launch_get(a, c->fp32, ncomp == 16 ? 1 : 0, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(tmp.data(), stage, sizeof(double) * ncomp * n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess)
+      for (int k = 0; k < ncomp; ++k)
+        for (int y = 0; y < cny; ++y)
+          memcpy(&host[k * full_plane + (size_t)(y + oy) * ld + ox], &tmp[k * n + (size_t)y * cnx],
+                 sizeof(double) * cnx);
+  }
+  c->mem.release(stage);
+  if (e != hipSuccess) return fail(VLBM_EDEVICE, "state transfer: %s", hipGetErrorString(e));
+  return VLBM_OK;
+}
+
+vlbm_status reset_ledgers(vlbm_ctx *c) {
+  for (int l = 0; l < c->nlev; ++l) {
+    Level &L = c->lv[l];
+    HIPCHK(hipMemsetAsync(L.dledger, 0, sizeof(double) * 4 * std::max(1, L.nledger), c->stream));
+  }
+  return VLBM_OK;
+}
+
+void kadd(double &s, double &cmp, double v) {
+  double t = s + v;
+  if (std::fabs(s) >= std::fabs(v))
+    cmp += (s - t) + v;
+  else
+    cmp += (v - t) + s;
+  s = t;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char *vlbm_last_error(void) { return g_err.c_str(); }
+
+vlbm_status vlbm_create(const vlbm_params *params, void *stream, vlbm_ctx **out) {
+  if (!params || !out) return fail(VLBM_EINVAL, "null argument");
+  const vlbm_params &p = *params;
+  if (p.nx0 < 1 || p.ny0 < 1 || !(p.dx0 > 0) || p.r < 1 || p.r > 8 || p.max_levels < 1 ||
+      p.max_levels > kMaxLevels || !(p.c > 0) || !(p.beta >= 0 && p.beta <= 1) ||
+      !(p.gamma > 1) || (p.precision != VLBM_FP64 && p.precision != VLBM_FP32))
+    return fail(VLBM_EINVAL, "invalid parameters");
+  for (int s = 0; s < 4; ++s)
+    if (p.bc[s] < 0 || p.bc[s] > 3) return fail(VLBM_EINVAL, "invalid boundary condition");
+  if ((p.bc[0] == VLBM_BC_PERIODIC) != (p.bc[1] == VLBM_BC_PERIODIC) ||
+      (p.bc[2] == VLBM_BC_PERIODIC) != (p.bc[3] == VLBM_BC_PERIODIC))
+    return fail(VLBM_EINVAL, "periodic sides must come in pairs");
+  long s = 1;
+  for (int i = 1; i < p.max_levels; ++i) s *= p.r;
+  if ((double)p.nx0 * s + 2 > 2e9 || (double)p.ny0 * s + 2 > 2e9)
+    return fail(VLBM_EINVAL, "finest level too large");
+  vlbm_ctx *c = new vlbm_ctx();
+  c->p = p;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->fp32 = p.precision == VLBM_FP32;
+  c->esz = c->fp32 ? 4 : 8;
+  c->tile_cells = tile_cells_default();
+  if (const char *e = getenv("VLBM_NT_STORES")) c->step_flags |= atoi(e) ? STEP_NT_STORES : 0;
+  if (const char *e = getenv("VLBM_TWO_CELLS")) c->step_flags |= atoi(e) ? STEP_TWO_CELLS : 0;
+  if (const char *e = getenv("VLBM_XCD_CONTIGUOUS")) c->step_flags |= atoi(e) ? STEP_XCD_CONTIGUOUS : 0;
+  c->gm1 = p.gamma - 1.0;
+  c->h = 1.0 / (2.0 * p.c);
+  c->tb = 2.0 * p.beta;
+  *out = c;
+  return VLBM_OK;
+}
+
+void vlbm_destroy(vlbm_ctx *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (int l = 0; l < kMaxLevels; ++l) free_level(c, c->lv[l]);
+  c->mem.release(c->dflag);
+  c->mem.release_all();
+  delete c;
+}
+
+vlbm_status vlbm_bind_pool(vlbm_ctx *c, void *dev, size_t bytes) {
+  if (!c || !dev || bytes < 4096) return fail(VLBM_EINVAL, "bad pool");
+  if (c->have_hierarchy) return fail(VLBM_ESTATE, "bind the pool before set_hierarchy");
+  c->mem.bind(dev, bytes);
+  return VLBM_OK;
+}
+
+size_t vlbm_footprint_bytes(const vlbm_params *params, const vlbm_box *boxes, int nboxes) {
+  if (!params) return 0;
+  Geometry g;
+  if (check_boxes(*params, boxes, nboxes, g) != VLBM_OK) return 0;
+  size_t esz = params->precision == VLBM_FP32 ? 4 : 8, total = 0;
+  for (int l = 0; l < kMaxLevels && g.present[l]; ++l) {
+    Level L;
+    frame_of(*params, esz, g, l, L);
+    size_t cells = (size_t)L.fw * L.fh;
+    total += DevMem::round(level_bytes(L, esz)) * 2;  // two time levels
+    total += DevMem::round(cells);                    // status
+    // tiles, tasks, accumulators, ledger, partials: bounded by the perimeter
+    size_t perim = 2 * (size_t)(L.fw + L.fh) * 4 + 64;
+    total += DevMem::round(sizeof(Task) * perim * 2) + DevMem::round(sizeof(double) * 4 * perim * 2);
+    total += DevMem::round((cells / 64 + 64) * (sizeof(Tile) + 4 * sizeof(double)));
+  }
+  return total + (1 << 20);
+}
+
+vlbm_status vlbm_set_hierarchy(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
+  if (!c) return fail(VLBM_EINVAL, "null context");
+  Geometry g;
+  vlbm_status st = check_boxes(c->p, boxes, nboxes, g);
+  if (st) return st;
+  // Build every host table on a scratch context first: a rejected hierarchy
+  // leaves the installed one untouched and touches no device state.
+  vlbm_ctx *t = new vlbm_ctx();
+  t->p = c->p;
+  t->esz = c->esz;
+  t->tile_cells = c->tile_cells;
+  int nlev = 0;
+  for (int l = 0; l < kMaxLevels; ++l) {
+    frame_of(c->p, c->esz, g, l, t->lv[l]);
+    if (g.present[l]) nlev = l + 1;
+    if (t->lv[l].plane >= (int64_t(1) << 31)) {
+      delete t;
+      return fail(VLBM_EINVAL, "level %d frame too large for 32-bit offsets", l);
+    }
+  }
+  st = build_lists(t, boxes, nboxes);
+  if (st) {
+    delete t;
+    return st;
+  }
+  vlbm_status sync = VLBM_OK;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) sync = fail(VLBM_EDEVICE, "stream sync failed");
+  if (sync) {
+    delete t;
+    return sync;
+  }
+  for (int l = 0; l < kMaxLevels; ++l) {
+    free_level(c, c->lv[l]);
+    c->lv[l] = std::move(t->lv[l]);
+    c->lv[l].steps = 0;
+  }
+  delete t;
+  c->nlev = nlev;
+  for (int l = 0; l < c->nlev; ++l) {
+    st = upload_level(c, c->lv[l], true);
+    if (st) return st;
+  }
+  if (!c->dflag) c->dflag = static_cast<int *>(c->mem.alloc(256));
+  c->boxes.assign(boxes, boxes + nboxes);
+  c->have_hierarchy = true;
+  c->coarse_steps = 0;
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_set_state(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny,
+                           const double *U, long ld) {
+  if (!U) return fail(VLBM_EINVAL, "null U");
+  vlbm_status st = rect_io(c, level, i0, j0, nx, ny, const_cast<double *>(U), ld, 4, true, false);
+  if (st) return st;
+  c->coarse_steps = 0;
+  return reset_ledgers(c);
+}
+
+vlbm_status vlbm_set_populations(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny,
+                                 const double *F, long ld) {
+  if (!F) return fail(VLBM_EINVAL, "null F");
+  vlbm_status st = rect_io(c, level, i0, j0, nx, ny, const_cast<double *>(F), ld, 16, true, true);
+  if (st) return st;
+  c->coarse_steps = 0;
+  return reset_ledgers(c);
+}
+
+vlbm_status vlbm_get_state(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny, double *U,
+                           long ld) {
+  if (!U) return fail(VLBM_EINVAL, "null U");
+  return rect_io(c, level, i0, j0, nx, ny, U, ld, 4, false, false);
+}
+
+vlbm_status vlbm_get_populations(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny,
+                                 double *F, long ld) {
+  if (!F) return fail(VLBM_EINVAL, "null F");
+  return rect_io(c, level, i0, j0, nx, ny, F, ld, 16, false, false);
+}
+
+vlbm_status vlbm_advance(vlbm_ctx *c, int n) {
+  if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "no hierarchy installed");
+  if (n < 0) return fail(VLBM_EINVAL, "negative step count");
+  for (int i = 0; i < n; ++i) {
+    vlbm_status st = cycle(c, 0, 1);
+    if (st) return st;
+    c->coarse_steps += 1;
+  }
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_conserved_totals(vlbm_ctx *c, double totals[4], double ledger[4]) {
+  if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "no hierarchy installed");
+  double T[4] = {0, 0, 0, 0}, Tc[4] = {0, 0, 0, 0}, G[4] = {0, 0, 0, 0}, Gc[4] = {0, 0, 0, 0};
+  for (int l = 0; l < c->nlev; ++l) {
+    Level &L = c->lv[l];
+    const int nt = (int)L.tiles.size();
+    HIPCHK(launch_audit(L.buf[L.cur()], L.dtiles, nt, L.plane, L.pitch, c->fp32, L.dpartial, c->stream));
+    std::vector<double> part(4 * (size_t)std::max(nt, 1)), led(4 * (size_t)std::max(L.nledger, 1));
+    if (nt) HIPCHK(hipMemcpyAsync(part.data(), L.dpartial, sizeof(double) * 4 * nt, hipMemcpyDeviceToHost, c->stream));
+    if (L.nledger)
+      HIPCHK(hipMemcpyAsync(led.data(), L.dledger, sizeof(double) * 4 * L.nledger, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < 4; ++k) {
+      double s = 0, sc = 0;
+      for (int t = 0; t < nt; ++t) kadd(s, sc, part[4 * t + k]);
+      kadd(T[k], Tc[k], L.dx * L.dx * (s + sc));
+      for (int t = 0; t < L.nledger; ++t) kadd(G[k], Gc[k], led[4 * t + k]);
+    }
+  }
+  for (int k = 0; k < 4; ++k) {
+    if (totals) totals[k] = T[k] + Tc[k];
+    if (ledger) ledger[k] = G[k] + Gc[k];
+  }
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_check_health(vlbm_ctx *c) {
+  if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "no hierarchy installed");
+  HIPCHK(hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream));
+  for (int l = 0; l < c->nlev; ++l) {
+    Level &L = c->lv[l];
+    HIPCHK(launch_health(L.buf[L.cur()], L.dtiles, (int)L.tiles.size(), L.plane, L.pitch, c->fp32,
+                         c->gm1, c->dflag, c->stream));
+  }
+  int flag = 0;
+  HIPCHK(hipMemcpyAsync(&flag, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (flag) return fail(VLBM_EUNSTABLE, "non-physical state (rho <= 0, p <= 0 or NaN)");
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_tag(vlbm_ctx *c, int level, double thr, unsigned char *tags) {
+  if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "no hierarchy installed");
+  if (level < 0 || level >= c->p.max_levels || !tags) return fail(VLBM_EINVAL, "bad tag request");
+  Level &L = c->lv[level];
+  long s = 1;
+  for (int i = 0; i < level; ++i) s *= c->p.r;
+  const size_t n = (size_t)(c->p.nx0 * s) * (size_t)(c->p.ny0 * s);
+  if (!L.present) {
+    memset(tags, 0, n);
+    return VLBM_OK;
+  }
+  uint8_t *d = static_cast<uint8_t *>(c->mem.alloc(n));
+  if (!d) return fail(VLBM_ENOMEM, "tag buffer");
+  hipError_t e = launch_tag(L.buf[L.cur()], L.dstatus, L.plane, L.pitch, L.xoff, L.fx0, L.fy0, L.fw,
+                            L.fh, L.Nx, L.Ny, c->perx(), c->pery(), c->fp32, thr, d, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(tags, d, n, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  c->mem.release(d);
+  if (e != hipSuccess) return fail(VLBM_EDEVICE, "tag: %s", hipGetErrorString(e));
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_get_boxes(vlbm_ctx *c, vlbm_box *boxes, int cap, int *nboxes) {
+  if (!c || !nboxes) return fail(VLBM_EINVAL, "null argument");
+  *nboxes = (int)c->boxes.size();
+  for (int i = 0; i < cap && i < (int)c->boxes.size(); ++i) boxes[i] = c->boxes[i];
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_regrid(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
+  (void)c; (void)boxes; (void)nboxes;
+  return fail(VLBM_ESTATE, "vlbm_regrid: not available in this build");
+}
+
+vlbm_status vlbm_tag_and_regrid(vlbm_ctx *c, double thr, int buffer, int min_box, int max_box) {
+  (void)c; (void)thr; (void)buffer; (void)min_box; (void)max_box;
+  return fail(VLBM_ESTATE, "vlbm_tag_and_regrid: not available in this build");
+}
+
+vlbm_status vlbm_save(vlbm_ctx *c, void *buf, size_t *bytes) {
+  (void)c; (void)buf; (void)bytes;
+  return fail(VLBM_ESTATE, "vlbm_save: not available in this build");
+}
+
+vlbm_status vlbm_load(vlbm_ctx *c, const void *buf, size_t bytes) {
+  (void)c; (void)buf; (void)bytes;
+  return fail(VLBM_ESTATE, "vlbm_load: not available in this build");
+}
+
+vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nctx) {
+  (void)ctxs; (void)n_steps; (void)nctx;
+  return fail(VLBM_ESTATE, "vlbm_batch_advance: not available in this build");
+}
+
+long vlbm_steps(const vlbm_ctx *c) { return c ? c->coarse_steps : -1; }
+
+vlbm_status vlbm_sync(vlbm_ctx *c) {
+  if (!c) return fail(VLBM_EINVAL, "null context");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return VLBM_OK;
+}
+
+}  // extern "C"

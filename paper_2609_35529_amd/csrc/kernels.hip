@@ -1,0 +1,607 @@
+// Device code of libvlbm for gfx950 (CDNA4, wave64).
+//
+// The hot kernel is `step_kernel`: one workgroup per tile of active cells. It
+// first executes the tile's interface/boundary tasks (ghost slots read only by
+// this tile's own cells, reflux captures), then, after one workgroup barrier,
+// advances every cell of the tile: pull the four inbound populations (exact
+// shift, paper Sec. 2.2), relax them towards the vectorial equilibrium
+// (eqs. num-equilibrium, num-relaxation), and store the 16 post-collision
+// values. Populations are stored structure-of-arrays, one plane per (q,k), so
+// every load and store of a wavefront is a contiguous run along x.
+//
+// Arithmetic contract (identical operation order in every implementation, so
+// FP64 results are reproducible bit for bit; built with -ffp-contract=off):
+//   W_k = ((f_{0k} + f_{1k}) + f_{2k}) + f_{3k}
+//   u = m_x / rho; v = m_y / rho; p = (gamma-1) (E - 0.5 (m_x u + m_y v))
+//   Q_x = (m_x, m_x u + p, m_y u, (E+p) u);  Q_y = (m_y, m_x v, m_y v + p, (E+p) v)
+//   f^eq_{+-x,k} = 0.25 W_k +- h Q_{x,k},  f^eq_{+-y,k} = 0.25 W_k +- h Q_{y,k},  h = 1/(2c)
+//   f*_{qk} = f_{qk} + 2beta (f^eq_{qk} - f_{qk})
+#include <hip/hip_runtime.h>
+
+#include "vlbm_internal.hpp"
+
+namespace vlbm {
+
+template <class T>
+__device__ __forceinline__ void relax(T g[16], T gm1, T h, T tb) {
+  T W[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) W[k] = ((g[k] + g[4 + k]) + g[8 + k]) + g[12 + k];
+  const T rho = W[0], mx = W[1], my = W[2], E = W[3];
+  const T u = mx / rho;
+  const T v = my / rho;
+  const T eint = E - T(0.5) * (mx * u + my * v);
+  const T p = gm1 * eint;
+  const T Qx[4] = {mx, mx * u + p, my * u, (E + p) * u};
+  const T Qy[4] = {my, mx * v, my * v + p, (E + p) * v};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const T w = T(0.25) * W[k];
+    const T hx = h * Qx[k];
+    const T hy = h * Qy[k];
+    g[k] = g[k] + tb * ((w + hx) - g[k]);
+    g[4 + k] = g[4 + k] + tb * ((w - hx) - g[4 + k]);
+    g[8 + k] = g[8 + k] + tb * ((w + hy) - g[8 + k]);
+    g[12 + k] = g[12 + k] + tb * ((w - hy) - g[12 + k]);
+  }
+}
+
+// Equilibrium of a conserved state, FP64 (inflow ghosts, set_state).
+__device__ __forceinline__ void equilibrium(const double W[4], double gm1, double h,
+                                            double f[16]) {
+  const double rho = W[0], mx = W[1], my = W[2], E = W[3];
+  const double u = mx / rho;
+  const double v = my / rho;
+  const double eint = E - 0.5 * (mx * u + my * v);
+  const double p = gm1 * eint;
+  const double Qx[4] = {mx, mx * u + p, my * u, (E + p) * u};
+  const double Qy[4] = {my, mx * v, my * v + p, (E + p) * v};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double w = 0.25 * W[k];
+    f[k] = w + h * Qx[k];
+    f[4 + k] = w - h * Qx[k];
+    f[8 + k] = w + h * Qy[k];
+    f[12 + k] = w - h * Qy[k];
+  }
+}
+
+__device__ __forceinline__ double minmod(double a, double b) {
+  if (a > 0.0 && b > 0.0) return a < b ? a : b;
+  if (a < 0.0 && b < 0.0) return a > b ? a : b;
+  return 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Interface and boundary tasks (all arithmetic in FP64; stored in T)
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ void run_task(const StepArgs &A, const Task &t) {
+  T *S = static_cast<T *>(A.src);
+  const int64_t P = A.plane;
+  const int q = t.q;
+  switch (t.kind) {
+    case T_COPY:
+#pragma unroll
+      for (int k = 0; k < 4; ++k) S[(q * 4 + k) * P + t.dst] = S[(q * 4 + k) * P + t.src];
+      break;
+    case T_OUTFLOW:
+    case T_REFLECT:
+    case T_INFLOW: {
+      const int side = t.n0;
+      const int qo = q ^ 1;  // opposite population: +x <-> -x, +y <-> -y
+      double in[4];
+      if (t.kind == T_OUTFLOW) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) in[k] = (double)S[(q * 4 + k) * P + t.src];
+      } else if (t.kind == T_REFLECT) {
+        const int kn = side < 2 ? 1 : 2;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double w = (double)S[(qo * 4 + k) * P + t.src];
+          in[k] = (k == kn) ? -w : w;
+        }
+      } else {
+        // constant indices only, so nothing lands in scratch memory
+        double W[4], f[16];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          W[k] = side == 0 ? A.win[0][k] : side == 1 ? A.win[1][k] : side == 2 ? A.win[2][k] : A.win[3][k];
+        equilibrium(W, A.gm1, A.h, f);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          in[k] = (double)(T)(q == 0 ? f[k] : q == 1 ? f[4 + k] : q == 2 ? f[8 + k] : f[12 + k]);
+      }
+      double *L = A.ledger + 4 * (int64_t)t.slot;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const T vin = (T)in[k];
+        S[(q * 4 + k) * P + t.dst] = vin;
+        const double out = (double)S[(qo * 4 + k) * P + t.src];
+        double l = L[k] + A.w2 * (double)vin;
+        L[k] = l + (-1.0) * (A.w2 * out);
+      }
+      break;
+    }
+    case T_RECON: {
+      const T *C = static_cast<const T *>(A.pcur);
+      const T *Pv = static_cast<const T *>(A.pprev);
+      const int64_t P2 = A.pplane;
+      const double bj = (double)(2 * t.j - A.r + 1) / (double)(2 * A.r);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int64_t pl = (q * 4 + k) * P2;
+        const double out = (double)C[pl + t.src];
+        const double prev = (double)Pv[pl + t.src];
+        double sigma = 0.0;
+        if (t.n0 >= 0 && t.n1 >= 0) {
+          const double fm = (double)C[pl + t.n0];
+          const double fp = (double)C[pl + t.n1];
+          sigma = minmod(out - fm, fp - out);
+        }
+        const double B = out - prev;
+        double v = out + B * A.ak;
+        v = v + sigma * bj;
+        S[(q * 4 + k) * P + t.dst] = (T)v;
+      }
+      break;
+    }
+    case T_REFLUX:
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        S[(q * 4 + k) * P + t.dst] = (T)(A.acc_in[4 * (int64_t)t.slot + k] / A.rr);
+      break;
+    case T_CAPTURE: {
+      double *acc = A.acc_out + 4 * (int64_t)t.slot;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        double s = A.first ? 0.0 : acc[k];
+        const int64_t base = (q * 4 + k) * P + t.src;
+        for (int j = 0; j < A.r; ++j) s = s + (double)S[base + (int64_t)j * t.n0];
+        acc[k] = s;
+      }
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The fused step kernel
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ void pull(const T *__restrict__ s, int64_t P, int pitch, int64_t o,
+                                     T g[16]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    g[k] = s[(0 * 4 + k) * P + o - 1];           // +x arrives from x-1
+    g[4 + k] = s[(1 * 4 + k) * P + o + 1];       // -x arrives from x+1
+    g[8 + k] = s[(2 * 4 + k) * P + o - pitch];   // +y arrives from y-1
+    g[12 + k] = s[(3 * 4 + k) * P + o + pitch];  // -y arrives from y+1
+  }
+}
+
+template <class T, bool NT>
+__device__ __forceinline__ void put(T *__restrict__ d, int64_t P, int64_t o, const T g[16]) {
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    if (NT)
+      __builtin_nontemporal_store(g[i], &d[i * P + o]);
+    else
+      d[i * P + o] = g[i];
+  }
+}
+
+template <class T, bool NT, bool TWO>
+__global__ __launch_bounds__(256) void step_kernel(StepArgs A) {
+  // Tile order. Natural order keeps every workgroup of the chip inside one
+  // narrow sweep front (few open DRAM pages); the XCD-contiguous order gives
+  // each XCD's L2 a contiguous run of tiles instead.
+  const int b = blockIdx.x;
+  const int tid = (A.flags & STEP_XCD_CONTIGUOUS) ? (b & 7) * A.per_xcd + (b >> 3) : b;
+  if (tid >= A.ntiles) return;
+  const Tile tl = A.tiles[tid];
+  if (tl.ntask) {
+    for (int i = threadIdx.x; i < tl.ntask; i += blockDim.x) run_task<T>(A, A.tasks[tl.task0 + i]);
+    __syncthreads();
+  }
+  const T *__restrict__ s = static_cast<const T *>(A.src);
+  T *__restrict__ d = static_cast<T *>(A.dst);
+  const T gm1 = (T)A.gm1, h = (T)A.h, tb = (T)A.tb;
+  const int n = tl.w * tl.h;
+  if (TWO) {
+    // two cells per thread, both gathers issued before either relaxation
+    for (int c = threadIdx.x; c < n; c += 2 * blockDim.x) {
+      const int c2 = c + blockDim.x;
+      const int cy = c / tl.w, cx = c - cy * tl.w;
+      const int64_t o = (int64_t)tl.off0 + (int64_t)cy * A.pitch + cx;
+      T g[16], g2[16];
+      pull<T>(s, A.plane, A.pitch, o, g);
+      int64_t o2 = 0;
+      if (c2 < n) {
+        const int cy2 = c2 / tl.w, cx2 = c2 - cy2 * tl.w;
+        o2 = (int64_t)tl.off0 + (int64_t)cy2 * A.pitch + cx2;
+        pull<T>(s, A.plane, A.pitch, o2, g2);
+      }
+      relax<T>(g, gm1, h, tb);
+      put<T, NT>(d, A.plane, o, g);
+      if (c2 < n) {
+        relax<T>(g2, gm1, h, tb);
+        put<T, NT>(d, A.plane, o2, g2);
+      }
+    }
+  } else {
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+      const int cy = c / tl.w;
+      const int cx = c - cy * tl.w;
+      const int64_t o = (int64_t)tl.off0 + (int64_t)cy * A.pitch + cx;
+      T g[16];
+      pull<T>(s, A.plane, A.pitch, o, g);
+      relax<T>(g, gm1, h, tb);
+      put<T, NT>(d, A.plane, o, g);
+    }
+  }
+}
+
+hipError_t launch_step(const StepArgs &a, int fp32, hipStream_t s) {
+  if (a.ntiles <= 0) return hipSuccess;
+  dim3 grid(8 * a.per_xcd), block(256);
+  const int v = (a.flags & (STEP_NT_STORES | STEP_TWO_CELLS)) | (fp32 ? 4 : 0);
+  switch (v) {
+    case 0: hipLaunchKernelGGL((step_kernel<double, false, false>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((step_kernel<double, true, false>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((step_kernel<double, false, true>), grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((step_kernel<double, true, true>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((step_kernel<float, false, false>), grid, block, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((step_kernel<float, true, false>), grid, block, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((step_kernel<float, false, true>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((step_kernel<float, true, true>), grid, block, 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Conservation audit: per-tile compensated sums of sum_q f_{q,k}
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void neumaier(double &s, double &c, double v) {
+  const double t = s + v;
+  if (fabs(s) >= fabs(v))
+    c += (s - t) + v;
+  else
+    c += (v - t) + s;
+  s = t;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void audit_kernel(const T *__restrict__ buf,
+                                                    const Tile *tiles, int64_t P, int pitch,
+                                                    double *partial) {
+  __shared__ double red[4][256];
+  const Tile tl = tiles[blockIdx.x];
+  double s[4] = {0, 0, 0, 0}, cc[4] = {0, 0, 0, 0};
+  const int n = tl.w * tl.h;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    const int cy = c / tl.w;
+    const int cx = c - cy * tl.w;
+    const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) neumaier(s[k], cc[k], (double)buf[(q * 4 + k) * P + o]);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = s[k] + cc[k];
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int k = threadIdx.x;
+    double ts = 0.0, tc = 0.0;
+    for (int i = 0; i < 256; ++i) neumaier(ts, tc, red[k][i]);
+    partial[4 * (int64_t)blockIdx.x + k] = ts + tc;
+  }
+}
+
+hipError_t launch_audit(const void *buf, const Tile *tiles, int ntiles, int64_t plane,
+                        int pitch, int fp32, double *partial, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(audit_kernel<float>, dim3(ntiles), dim3(256), 0, s,
+                       static_cast<const float *>(buf), tiles, plane, pitch, partial);
+  else
+    hipLaunchKernelGGL(audit_kernel<double>, dim3(ntiles), dim3(256), 0, s,
+                       static_cast<const double *>(buf), tiles, plane, pitch, partial);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// State in / out
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void set_kernel(RectArgs a, int raw) {
+  const int64_t n = (int64_t)a.nx * a.ny;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const int y = (int)(c / a.nx), x = (int)(c - (int64_t)y * a.nx);
+    const int fx = a.x0 + x - a.fx0, fy = a.y0 + y - a.fy0;
+    if (a.status[(int64_t)fy * a.fw + fx] == 0) continue;
+    const int64_t o = (int64_t)fy * a.pitch + fx + a.xoff;
+    double f[16];
+    if (raw) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) f[i] = a.host_stage[i * n + c];
+    } else {
+      double W[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) W[k] = a.host_stage[k * n + c];
+      equilibrium(W, a.gm1, a.h, f);
+    }
+    T *b0 = static_cast<T *>(a.buf0), *b1 = static_cast<T *>(a.buf1);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      b0[i * a.plane + o] = (T)f[i];
+      b1[i * a.plane + o] = (T)f[i];
+    }
+  }
+}
+
+template <class T>
+__global__ void get_kernel(RectArgs a, int pops) {
+  const int64_t n = (int64_t)a.nx * a.ny;
+  const double nan = __builtin_nan("");
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const int y = (int)(c / a.nx), x = (int)(c - (int64_t)y * a.nx);
+    const int fx = a.x0 + x - a.fx0, fy = a.y0 + y - a.fy0;
+    const bool act = a.status[(int64_t)fy * a.fw + fx] == 1;
+    const int64_t o = (int64_t)fy * a.pitch + fx + a.xoff;
+    const T *b0 = static_cast<const T *>(a.buf0);
+    if (pops) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) a.host_stage[i * n + c] = act ? (double)b0[i * a.plane + o] : nan;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        double w = nan;
+        if (act)
+          w = (((double)b0[(0 + k) * a.plane + o] + (double)b0[(4 + k) * a.plane + o]) +
+               (double)b0[(8 + k) * a.plane + o]) +
+              (double)b0[(12 + k) * a.plane + o];
+        a.host_stage[k * n + c] = w;
+      }
+    }
+  }
+}
+
+static dim3 grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g > 65535) g = 65535;
+  if (g < 1) g = 1;
+  return dim3((unsigned)g);
+}
+
+hipError_t launch_set_state(const RectArgs &a, int fp32, int raw, hipStream_t s) {
+  const int64_t n = (int64_t)a.nx * a.ny;
+  if (n == 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(set_kernel<float>, grid_for(n), dim3(256), 0, s, a, raw);
+  else
+    hipLaunchKernelGGL(set_kernel<double>, grid_for(n), dim3(256), 0, s, a, raw);
+  return hipGetLastError();
+}
+
+hipError_t launch_get(const RectArgs &a, int fp32, int pops, hipStream_t s) {
+  const int64_t n = (int64_t)a.nx * a.ny;
+  if (n == 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(get_kernel<float>, grid_for(n), dim3(256), 0, s, a, pops);
+  else
+    hipLaunchKernelGGL(get_kernel<double>, grid_for(n), dim3(256), 0, s, a, pops);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Health scan: rho <= 0, p <= 0 or NaN on any active cell
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void health_kernel(const T *__restrict__ buf, const Tile *tiles, int64_t P,
+                              int pitch, double gm1, int *flag) {
+  const Tile tl = tiles[blockIdx.x];
+  const int n = tl.w * tl.h;
+  int bad = 0;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    const int cy = c / tl.w;
+    const int cx = c - cy * tl.w;
+    const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
+    double W[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      W[k] = (((double)buf[(0 + k) * P + o] + (double)buf[(4 + k) * P + o]) +
+              (double)buf[(8 + k) * P + o]) +
+             (double)buf[(12 + k) * P + o];
+    const double u = W[1] / W[0], v = W[2] / W[0];
+    const double p = gm1 * (W[3] - 0.5 * (W[1] * u + W[2] * v));
+    if (!(W[0] > 0.0) || !(p > 0.0)) bad = 1;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+hipError_t launch_health(const void *buf, const Tile *tiles, int ntiles, int64_t plane,
+                         int pitch, int fp32, double gm1, int *flag, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(health_kernel<float>, dim3(ntiles), dim3(256), 0, s,
+                       static_cast<const float *>(buf), tiles, plane, pitch, gm1, flag);
+  else
+    hipLaunchKernelGGL(health_kernel<double>, dim3(ntiles), dim3(256), 0, s,
+                       static_cast<const double *>(buf), tiles, plane, pitch, gm1, flag);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Density-gradient tags on active cells of one level
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ double cell_rho(const T *b, int64_t P, int64_t o) {
+  return (((double)b[0 * P + o] + (double)b[4 * P + o]) + (double)b[8 * P + o]) +
+         (double)b[12 * P + o];
+}
+
+template <class T>
+__global__ void tag_kernel(const T *__restrict__ buf, const uint8_t *status, int64_t P,
+                           int pitch, int xoff, int fx0, int fy0, int fw, int fh, int Nx,
+                           int Ny, int perx, int pery, double thr, uint8_t *tags) {
+  const int64_t n = (int64_t)Nx * Ny;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const int y = (int)(c / Nx), x = (int)(c - (int64_t)y * Nx);
+    uint8_t tag = 0;
+    const int fx = x - fx0, fy = y - fy0;
+    if (fx >= 0 && fy >= 0 && fx < fw && fy < fh && status[(int64_t)fy * fw + fx] == 1) {
+      const int64_t o = (int64_t)fy * pitch + fx + xoff;
+      const double rc = cell_rho<T>(buf, P, o);
+      double rn[4];
+      const int dx[4] = {1, -1, 0, 0}, dy[4] = {0, 0, 1, -1};
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        int xx = x + dx[d], yy = y + dy[d];
+        bool ok = true;
+        if (xx < 0 || xx >= Nx) {
+          if (perx) xx = (xx + Nx) % Nx; else ok = false;
+        }
+        if (yy < 0 || yy >= Ny) {
+          if (pery) yy = (yy + Ny) % Ny; else ok = false;
+        }
+        double v = rc;
+        if (ok) {
+          const int gx = xx - fx0, gy = yy - fy0;
+          if (gx >= 0 && gy >= 0 && gx < fw && gy < fh && status[(int64_t)gy * fw + gx] == 1)
+            v = cell_rho<T>(buf, P, (int64_t)gy * pitch + gx + xoff);
+        }
+        rn[d] = v;
+      }
+      const double gx = fabs(rn[0] - rn[1]) / (2.0 * rc);
+      const double gy = fabs(rn[2] - rn[3]) / (2.0 * rc);
+      const double g = gx > gy ? gx : gy;
+      tag = (uint8_t)(g > thr);
+    }
+    tags[c] = tag;
+  }
+}
+
+hipError_t launch_tag(const void *buf, const uint8_t *status, int64_t plane, int pitch, int xoff,
+                      int fx0, int fy0, int fw, int fh, int Nx, int Ny, int perx, int pery,
+                      int fp32, double thr, uint8_t *tags, hipStream_t s) {
+  const int64_t n = (int64_t)Nx * Ny;
+  if (fp32)
+    hipLaunchKernelGGL(tag_kernel<float>, grid_for(n), dim3(256), 0, s,
+                       static_cast<const float *>(buf), status, plane, pitch, xoff, fx0, fy0, fw,
+                       fh, Nx, Ny, perx, pery, thr, tags);
+  else
+    hipLaunchKernelGGL(tag_kernel<double>, grid_for(n), dim3(256), 0, s,
+                       static_cast<const double *>(buf), status, plane, pitch, xoff, fx0, fy0,
+                       fw, fh, Nx, Ny, perx, pery, thr, tags);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Regrid: merge (eq. amr-merge) and minmod split (eqs. amr-slope, amr-split)
+// One thread per (operation, population plane).
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void merge_kernel(RegridArgs a) {
+  const int64_t n = (int64_t)a.nops * 16;
+  const T *F = static_cast<const T *>(a.fine_cur ? a.fine1 : a.fine0);
+  T *C0 = static_cast<T *>(a.coarse0), *C1 = static_cast<T *>(a.coarse1);
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const RegridOp op = a.ops[t >> 4];
+    const int i = (int)(t & 15);
+    double s = 0.0;
+    for (int bb = 0; bb < a.r; ++bb)
+      for (int aa = 0; aa < a.r; ++aa)
+        s += (double)F[i * a.fplane + op.src + (int64_t)bb * a.fpitch + aa];
+    const double m = s / (double)(a.r * a.r);
+    C0[i * a.cplane + op.dst] = (T)m;
+    C1[i * a.cplane + op.dst] = (T)m;
+  }
+}
+
+template <class T>
+__global__ void split_kernel(RegridArgs a) {
+  const int64_t n = (int64_t)a.nops * 16;
+  const T *C = static_cast<const T *>(a.coarse_cur ? a.coarse1 : a.coarse0);
+  T *F0 = static_cast<T *>(a.fine0), *F1 = static_cast<T *>(a.fine1);
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const RegridOp op = a.ops[t >> 4];
+    const int i = (int)(t & 15);
+    const int64_t pl = i * a.cplane;
+    const double fi = (double)C[pl + op.src];
+    double sx = 0.0, sy = 0.0;
+    if (op.nb[1] >= 0 && op.nb[0] >= 0)
+      sx = minmod(fi - (double)C[pl + op.nb[1]], (double)C[pl + op.nb[0]] - fi);
+    if (op.nb[3] >= 0 && op.nb[2] >= 0)
+      sy = minmod(fi - (double)C[pl + op.nb[3]], (double)C[pl + op.nb[2]] - fi);
+    for (int bb = 0; bb < a.r; ++bb)
+      for (int aa = 0; aa < a.r; ++aa) {
+        const double xa = (double)(2 * aa - a.r + 1) / (double)(2 * a.r);
+        const double xb = (double)(2 * bb - a.r + 1) / (double)(2 * a.r);
+        double v = fi + sx * xa;
+        v = v + sy * xb;
+        const int64_t o = i * a.fplane + op.dst + (int64_t)bb * a.fpitch + aa;
+        F0[o] = (T)v;
+        F1[o] = (T)v;
+      }
+  }
+}
+
+hipError_t launch_merge(const RegridArgs &a, int fp32, hipStream_t s) {
+  if (a.nops <= 0) return hipSuccess;
+  const int64_t n = (int64_t)a.nops * 16;
+  if (fp32)
+    hipLaunchKernelGGL(merge_kernel<float>, grid_for(n), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(merge_kernel<double>, grid_for(n), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_split(const RegridArgs &a, int fp32, hipStream_t s) {
+  if (a.nops <= 0) return hipSuccess;
+  const int64_t n = (int64_t)a.nops * 16;
+  if (fp32)
+    hipLaunchKernelGGL(split_kernel<float>, grid_for(n), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(split_kernel<double>, grid_for(n), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// Copy whole cells (16 planes) between two frames: pairs[2i] source offset,
+// pairs[2i+1] destination offset.
+template <class T>
+__global__ void copy_cells_kernel(const T *__restrict__ src, T *__restrict__ dst,
+                                  const int32_t *pairs, int npairs, int64_t sp, int64_t dp) {
+  const int64_t n = (int64_t)npairs * 16;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = t >> 4;
+    const int i = (int)(t & 15);
+    dst[i * dp + pairs[2 * p + 1]] = src[i * sp + pairs[2 * p]];
+  }
+}
+
+hipError_t launch_copy_frame(const void *src, void *dst, const int32_t *pairs, int npairs,
+                             int64_t splane, int64_t dplane, int fp32, hipStream_t s) {
+  if (npairs <= 0) return hipSuccess;
+  const int64_t n = (int64_t)npairs * 16;
+  if (fp32)
+    hipLaunchKernelGGL(copy_cells_kernel<float>, grid_for(n), dim3(256), 0, s,
+                       static_cast<const float *>(src), static_cast<float *>(dst), pairs, npairs,
+                       splane, dplane);
+  else
+    hipLaunchKernelGGL(copy_cells_kernel<double>, grid_for(n), dim3(256), 0, s,
+                       static_cast<const double *>(src), static_cast<double *>(dst), pairs,
+                       npairs, splane, dplane);
+  return hipGetLastError();
+}
+
+}  // namespace vlbm

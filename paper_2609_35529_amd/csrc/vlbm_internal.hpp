@@ -1,0 +1,121 @@
+// Internal definitions of libvlbm shared by its host and device translation
+// units: device work descriptors and the launch entry points.
+//
+// Data layout (per level l, one dense "frame" = bounding box of the level's
+// coverage plus a one-cell ghost ring):
+//   buffer b in {0,1}: 16 planes (q*4+k) of `plane` elements each; the element
+//   of level cell (x,y) is  (y - fy0) * pitch + (x - fx0) + xoff  within a plane.
+//   Stored values are post-collision populations f*; the current time level of
+//   level l lives in buf[steps_l & 1], the previous one in the other buffer.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace vlbm {
+
+// Work items executed by a tile's workgroup before it advances its cells.
+enum TaskKind : int32_t {
+  T_COPY = 0,     // ghost slot <- same-level cell (periodic image), population q
+  T_OUTFLOW = 1,  // ghost slot <- own edge cell, population q; boundary ledger
+  T_REFLECT = 2,  // ghost slot <- own edge cell, population opp(q), normal momentum negated; ledger
+  T_INFLOW = 3,   // ghost slot <- f^eq_q(w_inflow[side]); ledger
+  T_RECON = 4,    // ghost slot <- coarse-to-fine hand-off (eq. 2d-recon) from the parent ring cell
+  T_REFLUX = 5,   // hole slot  <- reflux accumulator / r^2 (eq. 2d-reflux)
+  T_CAPTURE = 6,  // reflux accumulator (=, or += after the first sub-step) sum_j f_q(R_j)
+};
+
+struct Task {      // 32 bytes
+  int32_t kind;
+  int32_t q;       // population written (ghost kinds) or captured
+  int32_t dst;     // element offset of the ghost / hole slot in this level's planes
+  int32_t src;     // element offset of the source cell (own level; parent level for RECON)
+  int32_t n0;      // RECON: parent cell - tau (or -1); CAPTURE: stride between R_j; BC: side
+  int32_t n1;      // RECON: parent cell + tau (or -1)
+  int32_t j;       // RECON: tangential index j of the fine cell within its parent
+  int32_t slot;    // REFLUX/CAPTURE: accumulator slot; BC: ledger slot
+};
+
+struct Tile {      // 32 bytes: a w x h rectangle of active cells
+  int32_t off0;    // element offset of cell (x0, y0)
+  int32_t w, h;
+  int32_t task0, ntask;
+  int32_t pad[3];
+};
+
+enum StepFlags : int32_t {
+  STEP_NT_STORES = 1,        // write the new time level with non-temporal stores
+  STEP_TWO_CELLS = 2,        // two cells per thread, gathers issued together
+  STEP_XCD_CONTIGUOUS = 4,   // map consecutive tiles to the same XCD
+};
+
+// Parameters of one launch of the step kernel (one level, one sub-step).
+struct StepArgs {
+  void *src;                 // current buffer of the level (ghost slots are written into it)
+  void *dst;                 // next buffer of the level
+  const void *pcur, *pprev;  // parent level: current and previous buffers (RECON)
+  const Tile *tiles;
+  const Task *tasks;
+  double *acc_in;            // accumulators filled by the finer level (REFLUX reads)
+  double *acc_out;           // parent's accumulators (CAPTURE writes)
+  double *ledger;            // boundary ledger slots [slot][4]
+  double *partial;           // optional per-tile audit partials [tile][4] (nullptr: off)
+  int64_t plane, pplane;     // elements per population plane (level, parent)
+  int32_t pitch;
+  int32_t ntiles, per_xcd;
+  int32_t first;             // CAPTURE: first sub-step of the parent's cycle
+  int32_t flags;             // STEP_* launch variants
+  int32_t r;
+  double ak;                 // (2k - r - 1) / (2r)
+  double rr;                 // r * r
+  double w2;                 // dx_l^2 (ledger weight)
+  double gm1, h, tb;         // gamma - 1, 1/(2c), 2 beta
+  double win[4][4];          // inflow conserved states per side
+};
+
+// Rectangle copy-in / copy-out and diagnostics.
+struct RectArgs {
+  void *buf0, *buf1;         // both buffers of the level (set: both written; get: buf0 read)
+  const uint8_t *status;     // frame status: 0 none, 1 active, 2 hole
+  double *host_stage;        // device staging [ncomp][ny][nx]
+  int64_t plane;
+  int32_t pitch, xoff, fx0, fy0, fw;
+  int32_t x0, y0, nx, ny;    // rectangle in level cells
+  double gm1, h;
+};
+
+// Launchers (kernels.hip). All return hipError_t of the launch.
+hipError_t launch_step(const StepArgs &a, int fp32, hipStream_t s);
+hipError_t launch_audit(const void *buf, const Tile *tiles, int ntiles, int64_t plane,
+                        int pitch, int fp32, double *partial, hipStream_t s);
+hipError_t launch_set_state(const RectArgs &a, int fp32, int raw_populations, hipStream_t s);
+hipError_t launch_get(const RectArgs &a, int fp32, int populations, hipStream_t s);
+hipError_t launch_health(const void *buf, const Tile *tiles, int ntiles, int64_t plane,
+                         int pitch, int fp32, double gm1, int *flag, hipStream_t s);
+hipError_t launch_tag(const void *buf, const uint8_t *status, int64_t plane, int pitch,
+                      int xoff, int fx0, int fy0, int fw, int fh, int Nx, int Ny, int perx,
+                      int pery, int fp32, double thr, uint8_t *tags, hipStream_t s);
+
+// Regrid kernels: a list of cell operations on level frames.
+struct RegridOp {          // one coarse cell (merge) or one parent cell (split)
+  int32_t dst;             // element offset of the destination (merge: parent cell;
+                           // split: child (0,0) in the fine frame)
+  int32_t src;             // merge: child (0,0) in the fine frame; split: parent cell
+  int32_t nb[4];           // split: neighbour offsets +x,-x,+y,-y in the parent frame (-1: none)
+};
+struct RegridArgs {
+  void *fine0, *fine1;     // fine frame buffers (merge reads current; split writes both)
+  void *coarse0, *coarse1; // coarse frame buffers (merge writes both; split reads current)
+  int fine_cur, coarse_cur;
+  int64_t fplane, cplane;
+  int32_t fpitch, cpitch;
+  int32_t r;
+  const RegridOp *ops;
+  int32_t nops;
+};
+hipError_t launch_merge(const RegridArgs &a, int fp32, hipStream_t s);
+hipError_t launch_split(const RegridArgs &a, int fp32, hipStream_t s);
+hipError_t launch_copy_frame(const void *src, void *dst, const int32_t *pairs, int npairs,
+                             int64_t splane, int64_t dplane, int fp32, hipStream_t s);
+
+}  // namespace vlbm

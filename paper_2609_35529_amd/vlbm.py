@@ -1,0 +1,271 @@
+"""Python binding of ``libvlbm.so`` (the C ABI of ``include/vlbm.h``).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+the library. Importing this module loads the library and raises ``ImportError``
+when it has not been built (``python -m paper_2609_35529_amd.build``); nothing
+falls back to a CPU path. PyTorch, when used, only supplies device memory
+(``bind_pool``) and the HIP stream the library launches on.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvlbm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libvlbm.so is not built ({LIB_PATH}); run `python -m paper_2609_35529_amd.build`")
+
+_lib = C.CDLL(LIB_PATH)
+
+VLBM_OK, VLBM_EINVAL, VLBM_ENOMEM, VLBM_ENEST, VLBM_EUNSTABLE, VLBM_EDEVICE, VLBM_ESTATE = (
+    0, -1, -2, -3, -4, -5, -6)
+PERIODIC, OUTFLOW, REFLECT, INFLOW = 0, 1, 2, 3
+FP64, FP32 = 0, 1
+
+
+class vlbm_params(C.Structure):
+    _fields_ = [("nx0", C.c_int), ("ny0", C.c_int), ("dx0", C.c_double), ("bc", C.c_int * 4),
+                ("w_inflow", (C.c_double * 4) * 4), ("gamma", C.c_double), ("c", C.c_double),
+                ("beta", C.c_double), ("r", C.c_int), ("max_levels", C.c_int),
+                ("precision", C.c_int)]
+
+
+class vlbm_box(C.Structure):
+    _fields_ = [("level", C.c_int), ("i0", C.c_int), ("j0", C.c_int), ("nx", C.c_int),
+                ("ny", C.c_int)]
+
+
+_P = C.c_void_p
+_D = C.POINTER(C.c_double)
+_st = C.c_int
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+vlbm_create = _sig("vlbm_create", _st, [C.POINTER(vlbm_params), _P, C.POINTER(_P)])
+vlbm_destroy = _sig("vlbm_destroy", None, [_P])
+vlbm_bind_pool = _sig("vlbm_bind_pool", _st, [_P, _P, C.c_size_t])
+vlbm_footprint_bytes = _sig("vlbm_footprint_bytes", C.c_size_t,
+                            [C.POINTER(vlbm_params), C.POINTER(vlbm_box), C.c_int])
+vlbm_set_hierarchy = _sig("vlbm_set_hierarchy", _st, [_P, C.POINTER(vlbm_box), C.c_int])
+_rect = [_P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _D, C.c_long]
+vlbm_set_state = _sig("vlbm_set_state", _st, _rect)
+vlbm_set_populations = _sig("vlbm_set_populations", _st, _rect)
+vlbm_get_state = _sig("vlbm_get_state", _st, _rect)
+vlbm_get_populations = _sig("vlbm_get_populations", _st, _rect)
+vlbm_advance = _sig("vlbm_advance", _st, [_P, C.c_int])
+vlbm_conserved_totals = _sig("vlbm_conserved_totals", _st, [_P, _D, _D])
+vlbm_regrid = _sig("vlbm_regrid", _st, [_P, C.POINTER(vlbm_box), C.c_int])
+vlbm_tag = _sig("vlbm_tag", _st, [_P, C.c_int, C.c_double, C.POINTER(C.c_uint8)])
+vlbm_tag_and_regrid = _sig("vlbm_tag_and_regrid", _st,
+                           [_P, C.c_double, C.c_int, C.c_int, C.c_int])
+vlbm_get_boxes = _sig("vlbm_get_boxes", _st, [_P, C.POINTER(vlbm_box), C.c_int,
+                                                  C.POINTER(C.c_int)])
+vlbm_check_health = _sig("vlbm_check_health", _st, [_P])
+vlbm_save = _sig("vlbm_save", _st, [_P, _P, C.POINTER(C.c_size_t)])
+vlbm_load = _sig("vlbm_load", _st, [_P, _P, C.c_size_t])
+vlbm_batch_advance = _sig("vlbm_batch_advance", _st, [C.POINTER(_P), C.POINTER(C.c_int), C.c_int])
+vlbm_steps = _sig("vlbm_steps", C.c_long, [_P])
+vlbm_sync = _sig("vlbm_sync", _st, [_P])
+vlbm_last_error = _sig("vlbm_last_error", C.c_char_p, [])
+
+EXPORTED = ["vlbm_create", "vlbm_destroy", "vlbm_bind_pool", "vlbm_footprint_bytes",
+            "vlbm_set_hierarchy", "vlbm_set_state", "vlbm_set_populations", "vlbm_advance",
+            "vlbm_get_state", "vlbm_get_populations", "vlbm_conserved_totals", "vlbm_regrid",
+            "vlbm_tag", "vlbm_tag_and_regrid", "vlbm_get_boxes", "vlbm_check_health",
+            "vlbm_save", "vlbm_load", "vlbm_batch_advance", "vlbm_steps", "vlbm_sync",
+            "vlbm_last_error"]
+
+
+class VLBMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"vlbm status {status}: {msg}")
+        self.status = status
+
+
+def check(status):
+    if status != VLBM_OK:
+        raise VLBMError(status, vlbm_last_error().decode())
+    return status
+
+
+def make_params(nx0, ny0, dx0, gamma, c, beta, r=2, max_levels=2, bc=(PERIODIC,) * 4,
+                w_inflow=None, precision=FP64) -> vlbm_params:
+    p = vlbm_params()
+    p.nx0, p.ny0, p.dx0 = nx0, ny0, dx0
+    for s in range(4):
+        p.bc[s] = int(bc[s])
+    if w_inflow is not None:
+        w = np.asarray(w_inflow, dtype=np.float64).reshape(4, 4)
+        for s in range(4):
+            for k in range(4):
+                p.w_inflow[s][k] = float(w[s, k])
+    p.gamma, p.c, p.beta = gamma, c, beta
+    p.r, p.max_levels, p.precision = r, max_levels, precision
+    return p
+
+
+def make_boxes(boxes: Iterable[Sequence[int]]):
+    boxes = list(boxes)
+    arr = (vlbm_box * max(1, len(boxes)))()
+    for i, b in enumerate(boxes):
+        arr[i].level, arr[i].i0, arr[i].j0, arr[i].nx, arr[i].ny = (int(v) for v in b)
+    return arr, len(boxes)
+
+
+def _dp(a):
+    return a.ctypes.data_as(_D)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(int(stream.cuda_stream))
+
+
+class Solver:
+    """One VLBM hierarchy living on the GPU (a ``vlbm_ctx``)."""
+
+    def __init__(self, nx0, ny0, dx0, gamma=1.4, c=1.0, beta=0.9, r=2, max_levels=2,
+                 bc=(PERIODIC,) * 4, w_inflow=None, precision=FP64, stream=None, pool=None):
+        self.params = make_params(nx0, ny0, dx0, gamma, c, beta, r, max_levels, bc, w_inflow,
+                                  precision)
+        self.nx0, self.ny0, self.r = nx0, ny0, r
+        self.max_levels = max_levels
+        self._h = C.c_void_p()
+        check(vlbm_create(C.byref(self.params), _stream_handle(stream), C.byref(self._h)))
+        self._pool = pool  # keeps a caller-provided device tensor alive
+        if pool is not None:
+            check(vlbm_bind_pool(self._h, C.c_void_p(pool.data_ptr()),
+                                 pool.numel() * pool.element_size()))
+
+    @classmethod
+    def from_case(cls, case, precision=FP64, stream=None, pool=None, max_levels=None):
+        s = cls(case.nx0, case.ny0, case.dx0, case.gamma, case.c, case.beta, case.r,
+                max_levels or case.nlev, case.bc, case.w_inflow, precision, stream, pool)
+        s.set_hierarchy(case.boxes)
+        for l in range(case.nlev):
+            s.set_state(l, case.states[l])
+        return s
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            vlbm_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def shape(self, level):
+        s = self.r ** level
+        return self.ny0 * s, self.nx0 * s
+
+    def set_hierarchy(self, boxes):
+        arr, n = make_boxes(boxes)
+        check(vlbm_set_hierarchy(self._h, arr, n))
+
+    def regrid(self, boxes):
+        arr, n = make_boxes(boxes)
+        check(vlbm_regrid(self._h, arr, n))
+
+    def tag_and_regrid(self, threshold, buffer=4, min_box=16, max_box=128):
+        check(vlbm_tag_and_regrid(self._h, threshold, buffer, min_box, max_box))
+
+    def boxes(self):
+        n = C.c_int()
+        check(vlbm_get_boxes(self._h, None, 0, C.byref(n)))
+        arr = (vlbm_box * max(1, n.value))()
+        check(vlbm_get_boxes(self._h, arr, n.value, C.byref(n)))
+        return [(b.level, b.i0, b.j0, b.nx, b.ny) for b in arr[:n.value]]
+
+    def set_state(self, level, U, i0=0, j0=0):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        _, ny, nx = U.shape
+        check(vlbm_set_state(self._h, level, i0, j0, nx, ny, _dp(U), nx))
+
+    def set_populations(self, level, F, i0=0, j0=0):
+        F = np.ascontiguousarray(F, dtype=np.float64)
+        _, ny, nx = F.shape
+        check(vlbm_set_populations(self._h, level, i0, j0, nx, ny, _dp(F), nx))
+
+    def _rect(self, level, i0, j0, nx, ny):
+        NY, NX = self.shape(level)
+        return (NX - i0 if nx is None else nx), (NY - j0 if ny is None else ny)
+
+    def get_state(self, level, i0=0, j0=0, nx=None, ny=None):
+        nx, ny = self._rect(level, i0, j0, nx, ny)
+        U = np.empty((4, ny, nx))
+        check(vlbm_get_state(self._h, level, i0, j0, nx, ny, _dp(U), nx))
+        return U
+
+    def get_populations(self, level, i0=0, j0=0, nx=None, ny=None):
+        nx, ny = self._rect(level, i0, j0, nx, ny)
+        F = np.empty((16, ny, nx))
+        check(vlbm_get_populations(self._h, level, i0, j0, nx, ny, _dp(F), nx))
+        return F
+
+    def advance(self, n):
+        check(vlbm_advance(self._h, int(n)))
+
+    def totals(self):
+        T, L = np.empty(4), np.empty(4)
+        check(vlbm_conserved_totals(self._h, _dp(T), _dp(L)))
+        return T, L
+
+    def tag(self, level, threshold):
+        NY, NX = self.shape(level)
+        t = np.empty((NY, NX), dtype=np.uint8)
+        check(vlbm_tag(self._h, level, threshold, t.ctypes.data_as(C.POINTER(C.c_uint8))))
+        return t
+
+    def check_health(self):
+        return vlbm_check_health(self._h) == VLBM_OK
+
+    def save(self) -> bytes:
+        n = C.c_size_t()
+        check(vlbm_save(self._h, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        check(vlbm_save(self._h, buf, C.byref(n)))
+        return buf.raw[:n.value]
+
+    def load(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        check(vlbm_load(self._h, buf, len(blob)))
+
+    def steps(self):
+        return vlbm_steps(self._h)
+
+    def sync(self):
+        check(vlbm_sync(self._h))
+
+
+def batch_advance(solvers, n_steps):
+    arr = (C.c_void_p * len(solvers))(*[s.handle.value for s in solvers])
+    ns = (C.c_int * len(solvers))(*[int(n) for n in n_steps])
+    check(vlbm_batch_advance(arr, ns, len(solvers)))
+
+
+def footprint_bytes(case, precision=FP64, max_levels=None):
+    p = make_params(case.nx0, case.ny0, case.dx0, case.gamma, case.c, case.beta, case.r,
+                    max_levels or case.nlev, case.bc, case.w_inflow, precision)
+    arr, n = make_boxes(case.boxes)
+    return vlbm_footprint_bytes(C.byref(p), arr, n)

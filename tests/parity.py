@@ -1,0 +1,68 @@
+"""Helpers that run the HIP path and the oracle on the same seeded inputs and
+compare them element by element."""
+from __future__ import annotations
+
+import numpy as np
+
+from tests import exact
+
+
+def gpu_solver(case, precision=0, **kw):
+    from paper_2609_35529_amd import vlbm
+    return vlbm.Solver.from_case(case, precision=precision, **kw)
+
+
+def run_pair(case, steps, precision=0, **kw):
+    o = exact.run_oracle(case, steps=0)
+    g = gpu_solver(case, precision, **kw)
+    if steps:
+        o.advance(steps)
+        g.advance(steps)
+    return o, g
+
+
+def compare_populations(o, g, case, rtol, floor=1e-3):
+    """max over levels of |F_gpu - F_oracle| / max(|F_oracle|, floor * max|F_plane|);
+    NaN patterns (inactive cells) must agree exactly."""
+    worst = 0.0
+    for l in range(case.nlev):
+        Fo = o.get_pop(l)
+        Fg = g.get_populations(l)
+        no, ng = np.isnan(Fo), np.isnan(Fg)
+        assert np.array_equal(no, ng), f"level {l}: active masks differ"
+        if no.all():
+            continue
+        for i in range(16):
+            a, b = Fg[i][~no[i]], Fo[i][~no[i]]
+            scale = np.maximum(np.abs(b), floor * max(np.abs(b).max(), 1e-300))
+            err = float(np.max(np.abs(a - b) / scale))
+            worst = max(worst, err)
+    assert worst <= rtol, worst
+    return worst
+
+
+def bitwise_equal(o, g, case):
+    for l in range(case.nlev):
+        Fo = o.get_pop(l)
+        Fg = g.get_populations(l)
+        m = ~np.isnan(Fo)
+        if not np.array_equal(Fo[m], Fg[m]):
+            return False
+    return True
+
+
+def smooth_mask(U, rel=0.02, radius=3):
+    """Cells whose neighbours within `radius` differ by at most `rel` in rho and p."""
+    rho = U[0]
+    u = U[1] / rho
+    v = U[2] / rho
+    p = 0.4 * (U[3] - 0.5 * rho * (u * u + v * v))
+    ok = np.isfinite(rho)
+    m = ok.copy()
+    for dy in range(-radius, radius + 1):
+        for dx in range(-radius, radius + 1):
+            rs = np.roll(np.roll(rho, dy, 0), dx, 1)
+            ps = np.roll(np.roll(p, dy, 0), dx, 1)
+            with np.errstate(invalid="ignore"):
+                m &= np.isfinite(rs) & (np.abs(rs - rho) <= rel * rho) & (np.abs(ps - p) <= rel * p)
+    return m
