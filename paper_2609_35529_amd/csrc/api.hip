@@ -192,6 +192,7 @@ struct vlbm_ctx {
   int step_flags = 0;
   int *dflag = nullptr;
   double gm1 = 0, h = 0, tb = 0;
+  double ledger_carry[4] = {0, 0, 0, 0}, ledger_carry_c[4] = {0, 0, 0, 0};
 
   bool perx() const { return p.bc[0] == VLBM_BC_PERIODIC; }
   bool pery() const { return p.bc[2] == VLBM_BC_PERIODIC; }
@@ -719,6 +720,7 @@ vlbm_status rect_io(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny, doub
 }
 
 vlbm_status reset_ledgers(vlbm_ctx *c) {
+  for (int k = 0; k < 4; ++k) c->ledger_carry[k] = c->ledger_carry_c[k] = 0.0;
   for (int l = 0; l < c->nlev; ++l) {
     Level &L = c->lv[l];
     HIPCHK(hipMemsetAsync(L.dledger, 0, sizeof(double) * 4 * std::max(1, L.nledger), c->stream));
@@ -733,6 +735,283 @@ void kadd(double &s, double &cmp, double v) {
   else
     cmp += (v - t) + s;
   s = t;
+}
+
+bool same_frame(const Level &a, const Level &b) {
+  return a.present && b.present && a.fx0 == b.fx0 && a.fy0 == b.fy0 && a.fw == b.fw &&
+         a.fh == b.fh && a.pitch == b.pitch && a.plane == b.plane && a.xoff == b.xoff;
+}
+
+// Move the sum of every ledger slot into the host-side carry (before the slots
+// are rebuilt by a regrid).
+vlbm_status carry_ledgers(vlbm_ctx *c) {
+  for (int l = 0; l < c->nlev; ++l) {
+    Level &L = c->lv[l];
+    if (!L.nledger) continue;
+    std::vector<double> led(4 * (size_t)L.nledger);
+    HIPCHK(hipMemcpyAsync(led.data(), L.dledger, sizeof(double) * led.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int t = 0; t < L.nledger; ++t)
+      for (int k = 0; k < 4; ++k) kadd(c->ledger_carry[k], c->ledger_carry_c[k], led[4 * t + k]);
+  }
+  return VLBM_OK;
+}
+
+// Conservative regrid (paper Sec. 3.4): merge exiting cells finest level
+// first (eq. amr-merge) in the old frames, move the surviving data into the new
+// frames, then split entering cells coarsest level first (eqs. amr-slope,
+// amr-split). Merged and split cells get the same value in both time levels,
+// so their first hand-off has no temporal slope. A split slope uses a
+// neighbour only if it is covered at that level in the new hierarchy and holds
+// data (i.e. it is not a hole both before and after).
+vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
+  Geometry g;
+  vlbm_status st = check_boxes(c->p, boxes, nboxes, g);
+  if (st) return st;
+  vlbm_ctx *t = new vlbm_ctx();
+  t->p = c->p;
+  t->esz = c->esz;
+  t->tile_cells = c->tile_cells;
+  int nlev = 0;
+  for (int l = 0; l < kMaxLevels; ++l) {
+    frame_of(c->p, c->esz, g, l, t->lv[l]);
+    if (g.present[l]) nlev = l + 1;
+    if (t->lv[l].plane >= (int64_t(1) << 31)) {
+      delete t;
+      return fail(VLBM_EINVAL, "level %d frame too large for 32-bit offsets", l);
+    }
+  }
+  st = build_lists(t, boxes, nboxes);
+  if (st) {
+    delete t;
+    return st;
+  }
+  const int r = c->p.r;
+  auto done = [&](vlbm_status s2) {
+    delete t;
+    return s2;
+  };
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return done(fail(VLBM_EDEVICE, "sync"));
+  st = carry_ledgers(c);
+  if (st) return done(st);
+  RegridOp *dops = nullptr;
+  auto upload_ops = [&](const std::vector<RegridOp> &ops) -> vlbm_status {
+    c->mem.release(dops);
+    dops = static_cast<RegridOp *>(c->mem.alloc(sizeof(RegridOp) * std::max<size_t>(1, ops.size())));
+    if (!dops) return fail(VLBM_ENOMEM, "regrid op list");
+    if (!ops.empty())
+      HIPCHK(hipMemcpyAsync(dops, ops.data(), sizeof(RegridOp) * ops.size(), hipMemcpyHostToDevice, c->stream));
+    return VLBM_OK;
+  };
+  // 1. merges, finest level first, inside the old frames
+  for (int l = c->nlev - 1; l >= 1; --l) {
+    Level &F = c->lv[l], &C = c->lv[l - 1];
+    std::vector<RegridOp> ops;
+    for (int y = F.fy0 + 1; y < F.fy0 + F.fh - 1; y += r)
+      for (int x = F.fx0 + 1; x < F.fx0 + F.fw - 1; x += r) {
+        if (!F.cov[F.fidx(x, y)] || t->covered(l, x, y)) continue;
+        RegridOp op{};
+        op.dst = (int32_t)C.off(x / r, y / r);
+        op.src = (int32_t)F.off(x, y);
+        op.nb[0] = op.nb[1] = op.nb[2] = op.nb[3] = -1;
+        ops.push_back(op);
+      }
+    if (ops.empty()) continue;
+    st = upload_ops(ops);
+    if (st) return done(st);
+    RegridArgs a{};
+    a.fine0 = F.buf[0];
+    a.fine1 = F.buf[1];
+    a.coarse0 = C.buf[0];
+    a.coarse1 = C.buf[1];
+    a.fine_cur = F.cur();
+    a.coarse_cur = C.cur();
+    a.fplane = F.plane;
+    a.cplane = C.plane;
+    a.fpitch = F.pitch;
+    a.cpitch = C.pitch;
+    a.r = r;
+    a.ops = dops;
+    a.nops = (int32_t)ops.size();
+    HIPCHK(launch_merge(a, c->fp32, c->stream));
+  }
+  // 2. new frames: keep identical ones, otherwise allocate and copy the overlap
+  for (int l = 0; l < kMaxLevels; ++l) {
+    Level &O = c->lv[l], &N = t->lv[l];
+    N.steps = O.present ? O.steps : 0;
+    if (!N.present) continue;
+    if (same_frame(O, N)) {
+      N.buf[0] = O.buf[0];
+      N.buf[1] = O.buf[1];
+      O.buf[0] = O.buf[1] = nullptr;
+      continue;
+    }
+    size_t nb = level_bytes(N, c->esz);
+    N.buf[0] = c->mem.alloc(nb);
+    N.buf[1] = c->mem.alloc(nb);
+    if (!N.buf[0] || !N.buf[1]) return done(fail(VLBM_ENOMEM, "population buffers (%zu bytes)", nb));
+    HIPCHK(hipMemsetAsync(N.buf[0], 0, nb, c->stream));
+    HIPCHK(hipMemsetAsync(N.buf[1], 0, nb, c->stream));
+    if (!O.present) continue;
+    int x0 = std::max(O.fx0, N.fx0), y0 = std::max(O.fy0, N.fy0);
+    int x1 = std::min(O.fx0 + O.fw, N.fx0 + N.fw), y1 = std::min(O.fy0 + O.fh, N.fy0 + N.fh);
+    if (x1 <= x0 || y1 <= y0) continue;
+    for (int b = 0; b < 2; ++b)
+      for (int i = 0; i < 16; ++i) {
+        char *dst = static_cast<char *>(N.buf[b]) + (i * N.plane + N.off(x0, y0)) * c->esz;
+        const char *src = static_cast<const char *>(O.buf[b]) + (i * O.plane + O.off(x0, y0)) * c->esz;
+        HIPCHK(hipMemcpy2DAsync(dst, N.pitch * c->esz, src, O.pitch * c->esz, (x1 - x0) * c->esz,
+                                y1 - y0, hipMemcpyDeviceToDevice, c->stream));
+      }
+  }
+  // 3. splits, coarsest level first, inside the new frames
+  for (int l = 0; l + 1 < nlev; ++l) {
+    Level &Cn = t->lv[l], &Fn = t->lv[l + 1];
+    std::vector<RegridOp> ops;
+    for (int y = Fn.fy0 + 1; y < Fn.fy0 + Fn.fh - 1; y += r)
+      for (int x = Fn.fx0 + 1; x < Fn.fx0 + Fn.fw - 1; x += r) {
+        if (!Fn.cov[Fn.fidx(x, y)] || c->covered(l + 1, x, y)) continue;
+        const int px = x / r, py = y / r;
+        RegridOp op{};
+        op.src = (int32_t)Cn.off(px, py);
+        op.dst = (int32_t)Fn.off(x, y);
+        for (int d = 0; d < 4; ++d) {
+          int nx = px + CX[d], ny = py + CY[d];
+          op.nb[d] = -1;
+          if (!t->wrap(l, nx, ny)) continue;
+          const bool persistent_hole = c->covered(l + 1, nx * r, ny * r) && t->covered(l + 1, nx * r, ny * r);
+          if (t->covered(l, nx, ny) && !persistent_hole) op.nb[d] = (int32_t)Cn.off(nx, ny);
+        }
+        ops.push_back(op);
+      }
+    if (ops.empty()) continue;
+    st = upload_ops(ops);
+    if (st) return done(st);
+    RegridArgs a{};
+    a.fine0 = Fn.buf[0];
+    a.fine1 = Fn.buf[1];
+    a.coarse0 = Cn.buf[0];
+    a.coarse1 = Cn.buf[1];
+    a.fine_cur = (int)(Fn.steps & 1);
+    a.coarse_cur = (int)(Cn.steps & 1);
+    a.fplane = Fn.plane;
+    a.cplane = Cn.plane;
+    a.fpitch = Fn.pitch;
+    a.cpitch = Cn.pitch;
+    a.r = r;
+    a.ops = dops;
+    a.nops = (int32_t)ops.size();
+    HIPCHK(launch_split(a, c->fp32, c->stream));
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return done(fail(VLBM_EDEVICE, "regrid kernels failed"));
+  c->mem.release(dops);
+  // 4. install the new hierarchy
+  for (int l = 0; l < kMaxLevels; ++l) {
+    free_level(c, c->lv[l]);
+    c->lv[l] = std::move(t->lv[l]);
+  }
+  delete t;
+  c->nlev = nlev;
+  for (int l = 0; l < c->nlev; ++l) {
+    st = upload_level(c, c->lv[l], false);
+    if (st) return st;
+  }
+  c->boxes.assign(boxes, boxes + nboxes);
+  return VLBM_OK;
+}
+
+// Clustering for tag_and_regrid: level-l tags (after dilation) restricted to
+// cells whose four neighbours are covered at level l, covered by a tile grid of
+// side ceil(min_box / r) level-l cells; marked tiles merge greedily into
+// rectangles, first along rows, then stacking equal row runs, with sides of at
+// most max_box level-(l+1) cells.
+void cluster_level(vlbm_ctx *c, int l, const std::vector<uint8_t> &tags, const std::vector<uint8_t> &cov,
+                   int buffer, int min_box, int max_box, std::vector<vlbm_box> &out) {
+  const int r = c->p.r;
+  long s = 1;
+  for (int i = 0; i < l; ++i) s *= r;
+  const int Nx = (int)(c->p.nx0 * s), Ny = (int)(c->p.ny0 * s);
+  auto at = [&](const std::vector<uint8_t> &m, int x, int y) -> bool {
+    if (x < 0 || x >= Nx) {
+      if (!c->perx()) return false;
+      x = ((x % Nx) + Nx) % Nx;
+    }
+    if (y < 0 || y >= Ny) {
+      if (!c->pery()) return false;
+      y = ((y % Ny) + Ny) % Ny;
+    }
+    return m[(size_t)y * Nx + x] != 0;
+  };
+  // dilation (square neighbourhood of radius `buffer`), separable
+  std::vector<uint8_t> tx(tags.size(), 0), dil(tags.size(), 0);
+  for (int y = 0; y < Ny; ++y)
+    for (int x = 0; x < Nx; ++x) {
+      bool any = false;
+      for (int d = -buffer; d <= buffer && !any; ++d) any = at(tags, x + d, y);
+      tx[(size_t)y * Nx + x] = any;
+    }
+  for (int y = 0; y < Ny; ++y)
+    for (int x = 0; x < Nx; ++x) {
+      bool any = false;
+      for (int d = -buffer; d <= buffer && !any; ++d) any = at(tx, x, y + d);
+      dil[(size_t)y * Nx + x] = any;
+    }
+  // allowed region: covered with all four neighbours covered (proper nesting)
+  auto allowed = [&](int x, int y) {
+    if (!cov[(size_t)y * Nx + x]) return false;
+    for (int d = 0; d < 4; ++d) {
+      int xx = x + CX[d], yy = y + CY[d];
+      bool outside = (xx < 0 || xx >= Nx) ? !c->perx() : (yy < 0 || yy >= Ny) ? !c->pery() : false;
+      if (outside) continue;
+      if (!at(cov, xx, yy)) return false;
+    }
+    return true;
+  };
+  const int T = std::max(1, (min_box + r - 1) / r);
+  const int maxT = std::max(1, max_box / (T * r));
+  const int ntx = (Nx + T - 1) / T, nty = (Ny + T - 1) / T;
+  std::vector<uint8_t> mark((size_t)ntx * nty, 0);
+  for (int ty = 0; ty < nty; ++ty)
+    for (int tx2 = 0; tx2 < ntx; ++tx2) {
+      bool any = false, ok = true;
+      for (int y = ty * T; y < std::min(Ny, (ty + 1) * T); ++y)
+        for (int x = tx2 * T; x < std::min(Nx, (tx2 + 1) * T); ++x) {
+          any = any || dil[(size_t)y * Nx + x];
+          ok = ok && allowed(x, y);
+        }
+      mark[(size_t)ty * ntx + tx2] = any && ok;
+    }
+  // greedy merge: row runs of at most maxT tiles, stacked while identical
+  struct Run { int a, b, y0, h; };
+  std::vector<Run> open, next;
+  auto emit = [&](const Run &u) {
+    int x0 = u.a * T, x1 = std::min(Nx, u.b * T), y0 = u.y0 * T, y1 = std::min(Ny, (u.y0 + u.h) * T);
+    out.push_back({l + 1, x0 * r, y0 * r, (x1 - x0) * r, (y1 - y0) * r});
+  };
+  for (int ty = 0; ty <= nty; ++ty) {
+    next.clear();
+    if (ty < nty) {
+      int tx2 = 0;
+      while (tx2 < ntx) {
+        if (!mark[(size_t)ty * ntx + tx2]) { ++tx2; continue; }
+        int a = tx2;
+        while (tx2 < ntx && mark[(size_t)ty * ntx + tx2] && tx2 - a < maxT) ++tx2;
+        next.push_back({a, tx2, ty, 1});
+      }
+    }
+    for (auto &o : open) {
+      bool cont = false;
+      for (auto &n : next)
+        if (n.a == o.a && n.b == o.b && n.h == 1 && o.h < maxT) {
+          n.y0 = o.y0;
+          n.h = o.h + 1;
+          cont = true;
+          break;
+        }
+      if (!cont) emit(o);
+    }
+    open = next;
+  }
 }
 
 }  // namespace
@@ -921,6 +1200,8 @@ vlbm_status vlbm_conserved_totals(vlbm_ctx *c, double totals[4], double ledger[4
     }
   }
   for (int k = 0; k < 4; ++k) {
+    kadd(G[k], Gc[k], c->ledger_carry[k]);
+    kadd(G[k], Gc[k], c->ledger_carry_c[k]);
     if (totals) totals[k] = T[k] + Tc[k];
     if (ledger) ledger[k] = G[k] + Gc[k];
   }
@@ -972,23 +1253,157 @@ vlbm_status vlbm_get_boxes(vlbm_ctx *c, vlbm_box *boxes, int cap, int *nboxes) {
 }
 
 vlbm_status vlbm_regrid(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
-  (void)c; (void)boxes; (void)nboxes;
-  return fail(VLBM_ESTATE, "vlbm_regrid: not available in this build");
+  if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "no hierarchy installed");
+  return regrid_impl(c, boxes, nboxes);
 }
 
 vlbm_status vlbm_tag_and_regrid(vlbm_ctx *c, double thr, int buffer, int min_box, int max_box) {
-  (void)c; (void)thr; (void)buffer; (void)min_box; (void)max_box;
-  return fail(VLBM_ESTATE, "vlbm_tag_and_regrid: not available in this build");
+  if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "no hierarchy installed");
+  if (buffer < 0 || min_box < 1 || max_box < min_box) return fail(VLBM_EINVAL, "bad clustering sizes");
+  const int r = c->p.r, ML = c->p.max_levels;
+  if (ML < 2) return VLBM_OK;
+  std::vector<std::vector<uint8_t>> tags(ML);
+  std::vector<int> Nx(ML), Ny(ML);
+  for (int l = 0; l < ML; ++l) {
+    long s = 1;
+    for (int i = 0; i < l; ++i) s *= r;
+    Nx[l] = (int)(c->p.nx0 * s);
+    Ny[l] = (int)(c->p.ny0 * s);
+    if (l + 1 < ML || l < c->nlev) {
+      tags[l].assign((size_t)Nx[l] * Ny[l], 0);
+      if (l < c->nlev) {
+        vlbm_status st = vlbm_tag(c, l, thr, tags[l].data());
+        if (st) return st;
+      }
+    }
+  }
+  // a tagged finer cell tags its parent: refined features keep their levels
+  for (int l = std::min(c->nlev, ML) - 1; l >= 1; --l)
+    for (int y = 0; y < Ny[l]; ++y)
+      for (int x = 0; x < Nx[l]; ++x)
+        if (tags[l][(size_t)y * Nx[l] + x]) tags[l - 1][(size_t)(y / r) * Nx[l - 1] + x / r] = 1;
+  std::vector<vlbm_box> boxes;
+  std::vector<uint8_t> cov((size_t)Nx[0] * Ny[0], 1);
+  for (int l = 0; l + 1 < ML; ++l) {
+    size_t before = boxes.size();
+    cluster_level(c, l, tags[l], cov, buffer, min_box, max_box, boxes);
+    if (boxes.size() == before) break;
+    std::vector<uint8_t> ncov((size_t)Nx[l + 1] * Ny[l + 1], 0);
+    for (size_t b = before; b < boxes.size(); ++b)
+      for (int y = boxes[b].j0; y < boxes[b].j0 + boxes[b].ny; ++y)
+        memset(&ncov[(size_t)y * Nx[l + 1] + boxes[b].i0], 1, boxes[b].nx);
+    cov.swap(ncov);
+  }
+  return vlbm_regrid(c, boxes.data(), (int)boxes.size());
 }
 
+// Checkpoint layout: header, boxes, per present level {steps, both buffers,
+// reflux accumulators, ledger slots}, ledger carry.
+struct CkptHeader {
+  char magic[8];
+  vlbm_params p;
+  int32_t nboxes, nlev;
+  int64_t coarse_steps;
+  double carry[4], carry_c[4];
+};
+
 vlbm_status vlbm_save(vlbm_ctx *c, void *buf, size_t *bytes) {
-  (void)c; (void)buf; (void)bytes;
-  return fail(VLBM_ESTATE, "vlbm_save: not available in this build");
+  if (!c || !c->have_hierarchy || !bytes) return fail(VLBM_ESTATE, "nothing to save");
+  size_t need = sizeof(CkptHeader) + sizeof(vlbm_box) * c->boxes.size();
+  for (int l = 0; l < c->nlev; ++l) {
+    const Level &L = c->lv[l];
+    need += sizeof(int64_t) + 2 * level_bytes(L, c->esz) + sizeof(double) * 4 * (L.nacc + L.nledger);
+  }
+  if (!buf) {
+    *bytes = need;
+    return VLBM_OK;
+  }
+  if (*bytes < need) return fail(VLBM_EINVAL, "checkpoint buffer too small (%zu < %zu)", *bytes, need);
+  char *p = static_cast<char *>(buf);
+  CkptHeader h{};
+  memcpy(h.magic, "VLBMCK1", 8);
+  h.p = c->p;
+  h.nboxes = (int32_t)c->boxes.size();
+  h.nlev = c->nlev;
+  h.coarse_steps = c->coarse_steps;
+  for (int k = 0; k < 4; ++k) {
+    h.carry[k] = c->ledger_carry[k];
+    h.carry_c[k] = c->ledger_carry_c[k];
+  }
+  memcpy(p, &h, sizeof h);
+  p += sizeof h;
+  memcpy(p, c->boxes.data(), sizeof(vlbm_box) * c->boxes.size());
+  p += sizeof(vlbm_box) * c->boxes.size();
+  for (int l = 0; l < c->nlev; ++l) {
+    const Level &L = c->lv[l];
+    int64_t steps = L.steps;
+    memcpy(p, &steps, sizeof steps);
+    p += sizeof steps;
+    const size_t nb = level_bytes(L, c->esz);
+    for (int b = 0; b < 2; ++b) {
+      HIPCHK(hipMemcpyAsync(p, L.buf[b], nb, hipMemcpyDeviceToHost, c->stream));
+      p += nb;
+    }
+    if (L.nacc) HIPCHK(hipMemcpyAsync(p, L.dacc, sizeof(double) * 4 * L.nacc, hipMemcpyDeviceToHost, c->stream));
+    p += sizeof(double) * 4 * L.nacc;
+    if (L.nledger)
+      HIPCHK(hipMemcpyAsync(p, L.dledger, sizeof(double) * 4 * L.nledger, hipMemcpyDeviceToHost, c->stream));
+    p += sizeof(double) * 4 * L.nledger;
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  *bytes = need;
+  return VLBM_OK;
 }
 
 vlbm_status vlbm_load(vlbm_ctx *c, const void *buf, size_t bytes) {
-  (void)c; (void)buf; (void)bytes;
-  return fail(VLBM_ESTATE, "vlbm_load: not available in this build");
+  if (!c || !buf || bytes < sizeof(CkptHeader)) return fail(VLBM_EINVAL, "bad checkpoint");
+  const char *p = static_cast<const char *>(buf);
+  CkptHeader h;
+  memcpy(&h, p, sizeof h);
+  p += sizeof h;
+  if (memcmp(h.magic, "VLBMCK1", 8) != 0) return fail(VLBM_EINVAL, "not a checkpoint");
+  {
+    const vlbm_params &a = h.p, &b = c->p;
+    bool same = a.nx0 == b.nx0 && a.ny0 == b.ny0 && a.dx0 == b.dx0 && a.gamma == b.gamma &&
+                a.c == b.c && a.beta == b.beta && a.r == b.r && a.max_levels == b.max_levels &&
+                a.precision == b.precision;
+    for (int s = 0; s < 4; ++s) {
+      same = same && a.bc[s] == b.bc[s];
+      for (int k = 0; k < 4; ++k) same = same && a.w_inflow[s][k] == b.w_inflow[s][k];
+    }
+    if (!same) return fail(VLBM_EINVAL, "checkpoint parameters differ from the context's");
+  }
+  std::vector<vlbm_box> boxes(h.nboxes);
+  memcpy(boxes.data(), p, sizeof(vlbm_box) * h.nboxes);
+  p += sizeof(vlbm_box) * h.nboxes;
+  vlbm_status st = vlbm_set_hierarchy(c, boxes.data(), h.nboxes);
+  if (st) return st;
+  if (c->nlev != h.nlev) return fail(VLBM_EINVAL, "checkpoint level count mismatch");
+  for (int l = 0; l < c->nlev; ++l) {
+    Level &L = c->lv[l];
+    int64_t steps;
+    memcpy(&steps, p, sizeof steps);
+    p += sizeof steps;
+    L.steps = steps;
+    const size_t nb = level_bytes(L, c->esz);
+    if ((size_t)(p - static_cast<const char *>(buf)) + 2 * nb > bytes) return fail(VLBM_EINVAL, "truncated checkpoint");
+    for (int b = 0; b < 2; ++b) {
+      HIPCHK(hipMemcpyAsync(L.buf[b], p, nb, hipMemcpyHostToDevice, c->stream));
+      p += nb;
+    }
+    if (L.nacc) HIPCHK(hipMemcpyAsync(L.dacc, p, sizeof(double) * 4 * L.nacc, hipMemcpyHostToDevice, c->stream));
+    p += sizeof(double) * 4 * L.nacc;
+    if (L.nledger)
+      HIPCHK(hipMemcpyAsync(L.dledger, p, sizeof(double) * 4 * L.nledger, hipMemcpyHostToDevice, c->stream));
+    p += sizeof(double) * 4 * L.nledger;
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->coarse_steps = h.coarse_steps;
+  for (int k = 0; k < 4; ++k) {
+    c->ledger_carry[k] = h.carry[k];
+    c->ledger_carry_c[k] = h.carry_c[k];
+  }
+  return VLBM_OK;
 }
 
 vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nctx) {
