@@ -131,7 +131,7 @@ def main():
     prec = vlbm.FP64 if args.precision == "fp64" else vlbm.FP32
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()  # a dedicated stream (default priority): graphs need one
     solver = vlbm.Solver.from_case(case, precision=prec, stream=stream)
     T0, L0 = solver.totals()
 

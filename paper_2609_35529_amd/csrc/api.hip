@@ -193,6 +193,17 @@ struct vlbm_ctx {
   int *dflag = nullptr;
   double gm1 = 0, h = 0, tb = 0;
   double ledger_carry[4] = {0, 0, 0, 0}, ledger_carry_c[4] = {0, 0, 0, 0};
+  // schedule tables: phases of one coarse step and their descriptors for the
+  // two parities of the coarse step counter relative to table_base
+  std::vector<std::pair<int, int>> phases;  // (level, k)
+  std::vector<int32_t> phase_blocks;
+  std::vector<LevelDesc> hdesc;  // host copy of the descriptor table
+  LevelDesc *ddesc = nullptr;
+  Segment *dseg = nullptr;
+  long table_base = 0;
+  bool use_graphs = false;
+  hipGraphExec_t graph = nullptr;  // two coarse steps from an even table parity
+  long graph_key = -1;
 
   bool perx() const { return p.bc[0] == VLBM_BC_PERIODIC; }
   bool pery() const { return p.bc[2] == VLBM_BC_PERIODIC; }
@@ -587,16 +598,29 @@ vlbm_status upload_level(vlbm_ctx *c, Level &L, bool alloc_buffers) {
   return VLBM_OK;
 }
 
-// One step of level l at sub-step k of its parent's cycle.
-vlbm_status step_level(vlbm_ctx *c, int l, int k) {
-  Level &L = c->lv[l];
-  StepArgs a{};
-  a.src = L.buf[L.cur()];
-  a.dst = L.buf[L.cur() ^ 1];
+// Phases of one coarse step in execution order: level l+1 takes r steps
+// before each step of level l (finest first).
+void schedule(int l, int k, int nlev, int r, std::vector<std::pair<int, int>> &out) {
+  if (l + 1 < nlev)
+    for (int kk = 1; kk <= r; ++kk) schedule(l + 1, kk, nlev, r, out);
+  out.push_back({l, k});
+}
+
+long ipow(int r, int l) {
+  long s = 1;
+  for (int i = 0; i < l; ++i) s *= r;
+  return s;
+}
+
+LevelDesc make_desc(const vlbm_ctx *c, int l, const long *st) {
+  const Level &L = c->lv[l];
+  LevelDesc a{};
+  a.src = L.buf[st[l] & 1];
+  a.dst = L.buf[(st[l] + 1) & 1];
   if (l > 0) {
-    Level &P = c->lv[l - 1];
-    a.pcur = P.buf[P.cur()];
-    a.pprev = P.buf[P.cur() ^ 1];
+    const Level &P = c->lv[l - 1];
+    a.pcur = P.buf[st[l - 1] & 1];
+    a.pprev = P.buf[(st[l - 1] + 1) & 1];
     a.pplane = P.plane;
     a.acc_out = P.dacc;
   }
@@ -606,31 +630,127 @@ vlbm_status step_level(vlbm_ctx *c, int l, int k) {
   a.ledger = L.dledger;
   a.plane = L.plane;
   a.pitch = L.pitch;
-  a.ntiles = (int)L.tiles.size();
-  a.per_xcd = (a.ntiles + 7) / 8;
-  a.first = (k == 1);
-  a.flags = c->step_flags;
+  a.ntiles = (int32_t)L.tiles.size();
   a.r = c->p.r;
-  a.ak = (double)(2 * k - c->p.r - 1) / (double)(2 * c->p.r);
   a.rr = (double)(c->p.r * c->p.r);
   a.w2 = L.dx * L.dx;
   a.gm1 = c->gm1;
   a.h = c->h;
   a.tb = c->tb;
-  for (int s = 0; s < 4; ++s)
-    for (int kk = 0; kk < 4; ++kk) a.win[s][kk] = c->p.w_inflow[s][kk];
-  HIPCHK(launch_step(a, c->fp32, c->stream));
-  L.steps += 1;
+  for (int s2 = 0; s2 < 4; ++s2)
+    for (int k = 0; k < 4; ++k) a.win[s2][k] = c->p.w_inflow[s2][k];
+  return a;
+}
+
+void drop_graph(vlbm_ctx *c) {
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  c->graph = nullptr;
+  c->graph_key = -1;
+}
+
+// (Re)build the descriptor tables after any change of buffers, lists or
+// step counters.
+vlbm_status build_tables(vlbm_ctx *c) {
+  drop_graph(c);
+  c->phases.clear();
+  schedule(0, 1, c->nlev, c->p.r, c->phases);
+  const size_t P = c->phases.size();
+  std::vector<LevelDesc> descs(2 * P);
+  std::vector<Segment> segs(2 * P);
+  c->mem.release(c->ddesc);
+  c->mem.release(c->dseg);
+  c->ddesc = static_cast<LevelDesc *>(c->mem.alloc(sizeof(LevelDesc) * 2 * P));
+  c->dseg = static_cast<Segment *>(c->mem.alloc(sizeof(Segment) * 2 * P));
+  if (!c->ddesc || !c->dseg) return fail(VLBM_ENOMEM, "schedule tables");
+  c->phase_blocks.assign(P, 0);
+  for (int e = 0; e < 2; ++e) {
+    long st[kMaxLevels];
+    for (int l = 0; l < kMaxLevels; ++l) st[l] = c->lv[l].steps + e * ipow(c->p.r, l);
+    for (size_t p = 0; p < P; ++p) {
+      const int l = c->phases[p].first;
+      descs[e * P + p] = make_desc(c, l, st);
+      st[l] += 1;
+      const int nb = ((int)c->lv[l].tiles.size() + 7) / 8 * 8;
+      segs[e * P + p] = {c->ddesc + e * P + p, 0, nb};
+      c->phase_blocks[p] = nb;
+    }
+  }
+  c->hdesc = descs;
+  HIPCHK(hipMemcpyAsync(c->ddesc, descs.data(), sizeof(LevelDesc) * descs.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->dseg, segs.data(), sizeof(Segment) * segs.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->table_base = c->coarse_steps;
   return VLBM_OK;
 }
 
-vlbm_status cycle(vlbm_ctx *c, int l, int k) {
-  if (l + 1 < c->nlev)
-    for (int kk = 1; kk <= c->p.r; ++kk) {
-      vlbm_status st = cycle(c, l + 1, kk);
+double ak_of(int k, int r) { return (double)(2 * k - r - 1) / (double)(2 * r); }
+
+// Launch every phase of one coarse step of table parity e.
+vlbm_status launch_coarse_step(vlbm_ctx *c, int e) {
+  const size_t P = c->phases.size();
+  for (size_t p = 0; p < P; ++p) {
+    StepLaunch a{};
+    a.d0 = c->ddesc + e * P + p;
+    a.segs = nullptr;
+    a.nseg = 0;
+    a.nblocks = c->phase_blocks[p];
+    a.first = c->phases[p].second == 1;
+    a.flags = c->step_flags;
+    a.ak = ak_of(c->phases[p].second, c->p.r);
+    HIPCHK(launch_step(a, c->fp32, c->stream));
+  }
+  return VLBM_OK;
+}
+
+void count_steps(vlbm_ctx *c, long n) {
+  for (int l = 0; l < c->nlev; ++l) c->lv[l].steps += n * ipow(c->p.r, l);
+  c->coarse_steps += n;
+}
+
+int table_parity(const vlbm_ctx *c) { return (int)((c->coarse_steps - c->table_base) & 1); }
+
+// Capture two coarse steps (table parities 0 then 1) into a graph.
+vlbm_status ensure_graph(vlbm_ctx *c) {
+  if (c->graph) return VLBM_OK;
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  vlbm_status st = launch_coarse_step(c, 0);
+  if (!st) st = launch_coarse_step(c, 1);
+  hipError_t e = hipStreamEndCapture(c->stream, &g);
+  if (st) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(VLBM_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    c->graph = nullptr;
+    return fail(VLBM_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+  }
+  return VLBM_OK;
+}
+
+vlbm_status advance_impl(vlbm_ctx *c, long n) {
+  const bool graphs = c->use_graphs && c->stream != nullptr && n >= 4;
+  while (n > 0) {
+    const int e = table_parity(c);
+    if (graphs && e == 0 && n >= 2) {
+      vlbm_status st = ensure_graph(c);
       if (st) return st;
+      while (n >= 2) {
+        HIPCHK(hipGraphLaunch(c->graph, c->stream));
+        count_steps(c, 2);
+        n -= 2;
+      }
+      continue;
     }
-  return step_level(c, l, k);
+    vlbm_status st = launch_coarse_step(c, e);
+    if (st) return st;
+    count_steps(c, 1);
+    n -= 1;
+  }
+  return VLBM_OK;
 }
 
 vlbm_status check_rect(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny) {
@@ -917,7 +1037,7 @@ vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
     if (st) return st;
   }
   c->boxes.assign(boxes, boxes + nboxes);
-  return VLBM_OK;
+  return build_tables(c);
 }
 
 // Clustering for tag_and_regrid: level-l tags (after dilation) restricted to
@@ -1048,6 +1168,7 @@ vlbm_status vlbm_create(const vlbm_params *params, void *stream, vlbm_ctx **out)
   if (const char *e = getenv("VLBM_NT_STORES")) c->step_flags |= atoi(e) ? STEP_NT_STORES : 0;
   if (const char *e = getenv("VLBM_TWO_CELLS")) c->step_flags |= atoi(e) ? STEP_TWO_CELLS : 0;
   if (const char *e = getenv("VLBM_XCD_CONTIGUOUS")) c->step_flags |= atoi(e) ? STEP_XCD_CONTIGUOUS : 0;
+  if (const char *e = getenv("VLBM_GRAPHS")) c->use_graphs = atoi(e) != 0;
   c->gm1 = p.gamma - 1.0;
   c->h = 1.0 / (2.0 * p.c);
   c->tb = 2.0 * p.beta;
@@ -1058,7 +1179,10 @@ vlbm_status vlbm_create(const vlbm_params *params, void *stream, vlbm_ctx **out)
 void vlbm_destroy(vlbm_ctx *c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  drop_graph(c);
   for (int l = 0; l < kMaxLevels; ++l) free_level(c, c->lv[l]);
+  c->mem.release(c->ddesc);
+  c->mem.release(c->dseg);
   c->mem.release(c->dflag);
   c->mem.release_all();
   delete c;
@@ -1136,7 +1260,7 @@ vlbm_status vlbm_set_hierarchy(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
   c->boxes.assign(boxes, boxes + nboxes);
   c->have_hierarchy = true;
   c->coarse_steps = 0;
-  return VLBM_OK;
+  return build_tables(c);
 }
 
 vlbm_status vlbm_set_state(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny,
@@ -1144,6 +1268,7 @@ vlbm_status vlbm_set_state(vlbm_ctx *c, int level, int i0, int j0, int nx, int n
   if (!U) return fail(VLBM_EINVAL, "null U");
   vlbm_status st = rect_io(c, level, i0, j0, nx, ny, const_cast<double *>(U), ld, 4, true, false);
   if (st) return st;
+  c->table_base -= c->coarse_steps;  // keep the table parity while restarting the count
   c->coarse_steps = 0;
   return reset_ledgers(c);
 }
@@ -1153,6 +1278,7 @@ vlbm_status vlbm_set_populations(vlbm_ctx *c, int level, int i0, int j0, int nx,
   if (!F) return fail(VLBM_EINVAL, "null F");
   vlbm_status st = rect_io(c, level, i0, j0, nx, ny, const_cast<double *>(F), ld, 16, true, true);
   if (st) return st;
+  c->table_base -= c->coarse_steps;
   c->coarse_steps = 0;
   return reset_ledgers(c);
 }
@@ -1172,12 +1298,7 @@ vlbm_status vlbm_get_populations(vlbm_ctx *c, int level, int i0, int j0, int nx,
 vlbm_status vlbm_advance(vlbm_ctx *c, int n) {
   if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "no hierarchy installed");
   if (n < 0) return fail(VLBM_EINVAL, "negative step count");
-  for (int i = 0; i < n; ++i) {
-    vlbm_status st = cycle(c, 0, 1);
-    if (st) return st;
-    c->coarse_steps += 1;
-  }
-  return VLBM_OK;
+  return advance_impl(c, n);
 }
 
 vlbm_status vlbm_conserved_totals(vlbm_ctx *c, double totals[4], double ledger[4]) {
@@ -1403,12 +1524,105 @@ vlbm_status vlbm_load(vlbm_ctx *c, const void *buf, size_t bytes) {
     c->ledger_carry[k] = h.carry[k];
     c->ledger_carry_c[k] = h.carry_c[k];
   }
-  return VLBM_OK;
+  return build_tables(c);
 }
 
 vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nctx) {
-  (void)ctxs; (void)n_steps; (void)nctx;
-  return fail(VLBM_ESTATE, "vlbm_batch_advance: not available in this build");
+  if (nctx <= 0) return VLBM_OK;
+  if (!ctxs || !n_steps) return fail(VLBM_EINVAL, "null argument");
+  vlbm_ctx *c0 = ctxs[0];
+  for (int i = 0; i < nctx; ++i) {
+    vlbm_ctx *c = ctxs[i];
+    if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "context %d has no hierarchy", i);
+    if (n_steps[i] < 0) return fail(VLBM_EINVAL, "negative step count");
+    if (c->stream != c0->stream || c->fp32 != c0->fp32 || c->p.r != c0->p.r)
+      return fail(VLBM_EINVAL, "batched contexts must share stream, precision and ratio");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == c) return fail(VLBM_EINVAL, "context %d listed twice", i);
+  }
+  std::vector<long> rem(n_steps, n_steps + nctx);
+  const int r = c0->p.r;
+  for (;;) {
+    std::vector<int> act;
+    long m = 0;
+    for (int i = 0; i < nctx; ++i)
+      if (rem[i] > 0) {
+        act.push_back(i);
+        m = m == 0 ? rem[i] : std::min(m, rem[i]);
+      }
+    if (act.empty()) break;
+    if (act.size() == 1) {
+      vlbm_status st = advance_impl(ctxs[act[0]], m);
+      if (st) return st;
+      rem[act[0]] -= m;
+      continue;
+    }
+    // merged schedule of the deepest context; shallower ones join the
+    // phases of the levels they have, occurrence by occurrence
+    int D = 0;
+    for (int i : act) D = std::max(D, ctxs[i]->nlev);
+    std::vector<std::pair<int, int>> ph;
+    schedule(0, 1, D, r, ph);
+    const size_t P = ph.size();
+    std::vector<std::vector<int>> occ_index(act.size());  // per context: phase index of the j-th phase of level l
+    for (size_t a = 0; a < act.size(); ++a) {
+      vlbm_ctx *c = ctxs[act[a]];
+      std::vector<int> seen(kMaxLevels, 0);
+      std::vector<std::vector<int>> idx(kMaxLevels);
+      for (size_t p = 0; p < c->phases.size(); ++p) idx[c->phases[p].first].push_back((int)p);
+      std::vector<int> &oi = occ_index[a];
+      for (size_t p = 0; p < P; ++p) {
+        const int l = ph[p].first;
+        oi.push_back(l < c->nlev ? idx[l][seen[l]++] : -1);
+      }
+    }
+    std::vector<Segment> segs;
+    std::vector<int32_t> seg0(2 * P), nseg(2 * P), nblk(2 * P);
+    for (int e = 0; e < 2; ++e)
+      for (size_t p = 0; p < P; ++p) {
+        seg0[e * P + p] = (int32_t)segs.size();
+        int32_t fb = 0;
+        for (size_t a = 0; a < act.size(); ++a) {
+          vlbm_ctx *c = ctxs[act[a]];
+          const int pi = occ_index[a][p];
+          if (pi < 0 || c->phase_blocks[pi] == 0) continue;
+          const int ei = table_parity(c) ^ e;
+          const size_t Pi = c->phases.size();
+          segs.push_back({c->ddesc + ei * Pi + pi, fb, c->phase_blocks[pi]});
+          fb += c->phase_blocks[pi];
+        }
+        nseg[e * P + p] = (int32_t)segs.size() - seg0[e * P + p];
+        nblk[e * P + p] = fb;
+      }
+    Segment *dseg = static_cast<Segment *>(c0->mem.alloc(sizeof(Segment) * std::max<size_t>(1, segs.size())));
+    if (!dseg) return fail(VLBM_ENOMEM, "batch segment table");
+    HIPCHK(hipMemcpyAsync(dseg, segs.data(), sizeof(Segment) * segs.size(), hipMemcpyHostToDevice, c0->stream));
+    for (long s2 = 0; s2 < m; ++s2) {
+      const int e = (int)(s2 & 1);
+      for (size_t p = 0; p < P; ++p) {
+        if (nseg[e * P + p] == 0) continue;
+        StepLaunch L{};
+        L.segs = dseg + seg0[e * P + p];
+        L.nseg = nseg[e * P + p];
+        L.nblocks = nblk[e * P + p];
+        L.first = ph[p].second == 1;
+        L.flags = c0->step_flags;
+        L.ak = ak_of(ph[p].second, r);
+        hipError_t err = launch_step(L, c0->fp32, c0->stream);
+        if (err != hipSuccess) {
+          c0->mem.release(dseg);
+          return fail(VLBM_EDEVICE, "batched launch: %s", hipGetErrorString(err));
+        }
+      }
+    }
+    HIPCHK(hipStreamSynchronize(c0->stream));
+    c0->mem.release(dseg);
+    for (int i : act) {
+      count_steps(ctxs[i], m);
+      rem[i] -= m;
+    }
+  }
+  return VLBM_OK;
 }
 
 long vlbm_steps(const vlbm_ctx *c) { return c ? c->coarse_steps : -1; }

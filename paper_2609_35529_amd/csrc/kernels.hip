@@ -76,7 +76,7 @@ __device__ __forceinline__ double minmod(double a, double b) {
 // Interface and boundary tasks (all arithmetic in FP64; stored in T)
 // ---------------------------------------------------------------------------
 template <class T>
-__device__ void run_task(const StepArgs &A, const Task &t) {
+__device__ __forceinline__ void run_task(const LevelDesc &A, int first, double ak, const Task &t) {
   T *S = static_cast<T *>(A.src);
   const int64_t P = A.plane;
   const int q = t.q;
@@ -140,7 +140,7 @@ __device__ void run_task(const StepArgs &A, const Task &t) {
           sigma = minmod(out - fm, fp - out);
         }
         const double B = out - prev;
-        double v = out + B * A.ak;
+        double v = out + B * ak;
         v = v + sigma * bj;
         S[(q * 4 + k) * P + t.dst] = (T)v;
       }
@@ -155,7 +155,7 @@ __device__ void run_task(const StepArgs &A, const Task &t) {
       double *acc = A.acc_out + 4 * (int64_t)t.slot;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        double s = A.first ? 0.0 : acc[k];
+        double s = first ? 0.0 : acc[k];
         const int64_t base = (q * 4 + k) * P + t.src;
         for (int j = 0; j < A.r; ++j) s = s + (double)S[base + (int64_t)j * t.n0];
         acc[k] = s;
@@ -193,60 +193,88 @@ __device__ __forceinline__ void put(T *__restrict__ d, int64_t P, int64_t o, con
   }
 }
 
+// One workgroup's work on tile `lb` of descriptor A (inlined twice below, so
+// that A is either plain kernel-argument memory or plain global memory).
 template <class T, bool NT, bool TWO>
-__global__ __launch_bounds__(256) void step_kernel(StepArgs A) {
+__device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks, int first,
+                                         double ak, int flags) {
   // Tile order. Natural order keeps every workgroup of the chip inside one
   // narrow sweep front (few open DRAM pages); the XCD-contiguous order gives
   // each XCD's L2 a contiguous run of tiles instead.
-  const int b = blockIdx.x;
-  const int tid = (A.flags & STEP_XCD_CONTIGUOUS) ? (b & 7) * A.per_xcd + (b >> 3) : b;
-  if (tid >= A.ntiles) return;
+  const int tid = (flags & STEP_XCD_CONTIGUOUS) ? (lb & 7) * (nblocks >> 3) + (lb >> 3) : lb;
+  // Everything the cell loop needs is read before the first store, so it stays
+  // in scalar registers (loads after a store may not be scalarised).
+  const int ntiles = A.ntiles;
+  if (tid >= ntiles) return;
   const Tile tl = A.tiles[tid];
-  if (tl.ntask) {
-    for (int i = threadIdx.x; i < tl.ntask; i += blockDim.x) run_task<T>(A, A.tasks[tl.task0 + i]);
-    __syncthreads();
-  }
   const T *__restrict__ s = static_cast<const T *>(A.src);
   T *__restrict__ d = static_cast<T *>(A.dst);
+  const int64_t plane = A.plane;
+  const int pitch = A.pitch;
   const T gm1 = (T)A.gm1, h = (T)A.h, tb = (T)A.tb;
+  if (tl.ntask) {
+    for (int i = threadIdx.x; i < tl.ntask; i += blockDim.x)
+      run_task<T>(A, first, ak, A.tasks[tl.task0 + i]);
+    __syncthreads();
+  }
   const int n = tl.w * tl.h;
   if (TWO) {
     // two cells per thread, both gathers issued before either relaxation
     for (int c = threadIdx.x; c < n; c += 2 * blockDim.x) {
       const int c2 = c + blockDim.x;
       const int cy = c / tl.w, cx = c - cy * tl.w;
-      const int64_t o = (int64_t)tl.off0 + (int64_t)cy * A.pitch + cx;
+      const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
       T g[16], g2[16];
-      pull<T>(s, A.plane, A.pitch, o, g);
+      pull<T>(s, plane, pitch, o, g);
       int64_t o2 = 0;
       if (c2 < n) {
         const int cy2 = c2 / tl.w, cx2 = c2 - cy2 * tl.w;
-        o2 = (int64_t)tl.off0 + (int64_t)cy2 * A.pitch + cx2;
-        pull<T>(s, A.plane, A.pitch, o2, g2);
+        o2 = (int64_t)tl.off0 + (int64_t)cy2 * pitch + cx2;
+        pull<T>(s, plane, pitch, o2, g2);
       }
       relax<T>(g, gm1, h, tb);
-      put<T, NT>(d, A.plane, o, g);
+      put<T, NT>(d, plane, o, g);
       if (c2 < n) {
         relax<T>(g2, gm1, h, tb);
-        put<T, NT>(d, A.plane, o2, g2);
+        put<T, NT>(d, plane, o2, g2);
       }
     }
   } else {
     for (int c = threadIdx.x; c < n; c += blockDim.x) {
       const int cy = c / tl.w;
       const int cx = c - cy * tl.w;
-      const int64_t o = (int64_t)tl.off0 + (int64_t)cy * A.pitch + cx;
+      const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
       T g[16];
-      pull<T>(s, A.plane, A.pitch, o, g);
+      pull<T>(s, plane, pitch, o, g);
       relax<T>(g, gm1, h, tb);
-      put<T, NT>(d, A.plane, o, g);
+      put<T, NT>(d, plane, o, g);
     }
   }
 }
 
-hipError_t launch_step(const StepArgs &a, int fp32, hipStream_t s) {
-  if (a.ntiles <= 0) return hipSuccess;
-  dim3 grid(8 * a.per_xcd), block(256);
+
+template <class T, bool NT, bool TWO>
+__global__ __launch_bounds__(256) void step_kernel(StepLaunch Lc) {
+  const int b = blockIdx.x;
+  const LevelDesc *dp = Lc.d0;
+  int first_block = 0, nblocks = Lc.nblocks;
+  if (Lc.nseg > 0) {  // uniform scalar search of this workgroup's segment
+    int lo = 0, hi = Lc.nseg - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (Lc.segs[mid].first_block <= b) lo = mid; else hi = mid - 1;
+    }
+    const Segment sg = Lc.segs[lo];
+    dp = sg.d;
+    first_block = sg.first_block;
+    nblocks = sg.nblocks;
+  }
+  run_tile<T, NT, TWO>(*dp, b - first_block, nblocks, Lc.first, Lc.ak, Lc.flags);
+}
+
+hipError_t launch_step(const StepLaunch &a, int fp32, hipStream_t s) {
+  if (a.nblocks <= 0 || a.nseg < 0) return hipSuccess;
+  dim3 grid(a.nblocks), block(256);
   const int v = (a.flags & (STEP_NT_STORES | STEP_TWO_CELLS)) | (fp32 ? 4 : 0);
   switch (v) {
     case 0: hipLaunchKernelGGL((step_kernel<double, false, false>), grid, block, 0, s, a); break;

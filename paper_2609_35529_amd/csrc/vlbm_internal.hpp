@@ -49,8 +49,9 @@ enum StepFlags : int32_t {
   STEP_XCD_CONTIGUOUS = 4,   // map consecutive tiles to the same XCD
 };
 
-// Parameters of one launch of the step kernel (one level, one sub-step).
-struct StepArgs {
+// Everything the step kernel needs about one (context, level) at one phase of
+// the schedule. Lives in device memory; a launch covers one or more of them.
+struct LevelDesc {
   void *src;                 // current buffer of the level (ghost slots are written into it)
   void *dst;                 // next buffer of the level
   const void *pcur, *pprev;  // parent level: current and previous buffers (RECON)
@@ -59,18 +60,33 @@ struct StepArgs {
   double *acc_in;            // accumulators filled by the finer level (REFLUX reads)
   double *acc_out;           // parent's accumulators (CAPTURE writes)
   double *ledger;            // boundary ledger slots [slot][4]
-  double *partial;           // optional per-tile audit partials [tile][4] (nullptr: off)
   int64_t plane, pplane;     // elements per population plane (level, parent)
-  int32_t pitch;
-  int32_t ntiles, per_xcd;
-  int32_t first;             // CAPTURE: first sub-step of the parent's cycle
-  int32_t flags;             // STEP_* launch variants
-  int32_t r;
-  double ak;                 // (2k - r - 1) / (2r)
+  int32_t pitch, ntiles, r, pad;
   double rr;                 // r * r
   double w2;                 // dx_l^2 (ledger weight)
   double gm1, h, tb;         // gamma - 1, 1/(2c), 2 beta
   double win[4][4];          // inflow conserved states per side
+};
+
+// A run of workgroups of one launch that works on one LevelDesc. first_block
+// and nblocks are multiples of 8 so that the XCD of a workgroup (blockIdx % 8)
+// is also its index modulo 8 inside the segment.
+struct Segment {
+  const LevelDesc *d;
+  int32_t first_block, nblocks;
+};
+
+// Launch-uniform parameters of one phase (level l, sub-step k of its parent).
+// A launch over a single descriptor passes its address directly (d0 with
+// nseg == 0); a batched launch passes a segment table instead.
+struct StepLaunch {
+  const LevelDesc *d0;
+  const Segment *segs;
+  int32_t nseg;
+  int32_t nblocks;           // total workgroups
+  int32_t first;             // CAPTURE: k == 1 (first sub-step of the parent's cycle)
+  int32_t flags;             // STEP_* variants
+  double ak;                 // (2k - r - 1) / (2r)
 };
 
 // Rectangle copy-in / copy-out and diagnostics.
@@ -85,7 +101,7 @@ struct RectArgs {
 };
 
 // Launchers (kernels.hip). All return hipError_t of the launch.
-hipError_t launch_step(const StepArgs &a, int fp32, hipStream_t s);
+hipError_t launch_step(const StepLaunch &a, int fp32, hipStream_t s);
 hipError_t launch_audit(const void *buf, const Tile *tiles, int ntiles, int64_t plane,
                         int pitch, int fp32, double *partial, hipStream_t s);
 hipError_t launch_set_state(const RectArgs &a, int fp32, int raw_populations, hipStream_t s);
