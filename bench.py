@@ -24,6 +24,20 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic per step-kernel launch of the default workload (quadrant512, FP64,
+# 256-cell tiles, XCD-contiguous order), from rocprofv3 FETCH_SIZE x 2.000 and
+# WRITE_SIZE x 1.000 (scales measured on a plain 2 GiB copy); valid only for the
+# kernel source it was measured on.
+MEASURED_TRAFFIC = {"kernel_sha256_16": "07565bc57f0e9761", "workload": "quadrant512",
+                    "precision": "fp64", "tile_cells": 256, "flags": 4,
+                    "bytes_per_launch": 63242009.1}
+
+
+def kernel_hash():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2609_35529_amd", "csrc", "kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
 
 def build_case(name, steps):
     from paper_2609_35529_amd import workloads as wl
@@ -113,6 +127,11 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch autotuner")
+    ap.add_argument("--tile-cells", type=int, default=0, help="fixed launch tuning (skips the autotuner)")
+    ap.add_argument("--flags", type=int, default=0, help="launch flags with --tile-cells")
+    ap.add_argument("--tune-steps", type=int, default=5,
+                    help="coarse steps timed per autotuner candidate (real steps of the run)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only measure a plain 2 GiB device copy and exit")
     args = ap.parse_args()
@@ -135,6 +154,14 @@ def main():
     solver = vlbm.Solver.from_case(case, precision=prec, stream=stream)
     T0, L0 = solver.totals()
 
+    tuning = None
+    if args.tile_cells:
+        solver.set_tuning(args.tile_cells, args.flags)
+        tuning = {"tile_cells": args.tile_cells, "flags": args.flags}
+    elif not args.no_tune:
+        print(f"[bench] {case.name} autotune", file=sys.stderr, flush=True)
+        tile, flags = solver.autotune(steps_per_trial=args.tune_steps)
+        tuning = {"tile_cells": tile, "flags": flags}
     print(f"[bench] {case.name} warmup {args.warmup}", file=sys.stderr, flush=True)
     solver.advance(args.warmup)
     torch.cuda.synchronize()
@@ -159,6 +186,12 @@ def main():
     avg_launch_s = gpu_ms / 1e3 / (args.steps * nl)
     bytes_per_launch = upd * bytes_per_update / nl
     achieved = bytes_per_launch / avg_launch_s / 1e9
+    traffic = None
+    m = MEASURED_TRAFFIC
+    if (kernel_hash() == m["kernel_sha256_16"] and args.workload == m["workload"]
+            and args.precision == m["precision"] and tuning
+            and tuning["tile_cells"] == m["tile_cells"] and tuning["flags"] == m["flags"]):
+        traffic = m["bytes_per_launch"]
     scale = max(abs(x) for x in T0)
     drift = [float(abs((T1[k] - T0[k]) - (L1[k] - L0[k])) / scale) for k in range(4)]
 
@@ -179,9 +212,10 @@ def main():
                                f"boxes {case.boxes}, r={case.r}, beta={case.beta}, "
                                f"c={case.c:.4f}, seed 0",
                    "fine_equiv_per_step": fe_step, "actual_updates_per_step": upd,
-                   "launches_per_step": nl},
+                   "launches_per_step": nl, "tuning": tuning,
+                   "precision": args.precision},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "step_kernel", "bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": avg_launch_s * 1e6},
         "actual_updates_per_s": upd * args.steps / wall,

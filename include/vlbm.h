@@ -176,6 +176,20 @@ vlbm_status vlbm_load(vlbm_ctx *ctx, const void *buf, size_t bytes);
  * the same stream and precision. */
 vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nctx);
 
+/* Launch tuning (no effect on results, which are identical for every
+ * setting): tile_cells is the largest number of cells one workgroup advances
+ * (64..2^20); flags: 1 non-temporal stores, 2 two cells per thread,
+ * 4 XCD-contiguous workgroup order. Rebuilds the launch tables. */
+vlbm_status vlbm_set_tuning(vlbm_ctx *ctx, int tile_cells, int flags);
+
+/* Autotuner: time tile sizes {128, 256, 512, 1024} x workgroup orders on real
+ * coarse steps of this context (every trial advances the solution by
+ * 1 + steps_per_trial coarse steps) and keep the fastest. The choice is cached
+ * per geometry (base grid, ratio, precision, boxes) for the process, so a
+ * repeated call advances nothing. Reports the choice in tile_cells/flags
+ * (either may be NULL). */
+vlbm_status vlbm_autotune(vlbm_ctx *ctx, int steps_per_trial, int *tile_cells, int *flags);
+
 /* Coarse steps taken since set_state. */
 long vlbm_steps(const vlbm_ctx *ctx);
 

@@ -1625,6 +1625,75 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
   return VLBM_OK;
 }
 
+vlbm_status vlbm_set_tuning(vlbm_ctx *c, int tile_cells, int flags) {
+  if (!c) return fail(VLBM_EINVAL, "null context");
+  if (tile_cells < 64 || tile_cells > (1 << 20) || (flags & ~(STEP_NT_STORES | STEP_TWO_CELLS | STEP_XCD_CONTIGUOUS)))
+    return fail(VLBM_EINVAL, "bad tuning (tile_cells %d, flags %d)", tile_cells, flags);
+  c->tile_cells = tile_cells;
+  c->step_flags = flags;
+  if (!c->have_hierarchy) return VLBM_OK;
+  std::vector<vlbm_box> boxes = c->boxes;  // same hierarchy, new tile decomposition
+  return regrid_impl(c, boxes.data(), (int)boxes.size());
+}
+
+// Tuning cache: one entry per geometry (base grid, ratio, precision, boxes).
+static std::map<std::string, std::pair<int, int>> g_tuned;
+
+static std::string tuning_key(const vlbm_ctx *c) {
+  std::string k = std::to_string(c->p.nx0) + "x" + std::to_string(c->p.ny0) + "r" +
+                  std::to_string(c->p.r) + "p" + std::to_string(c->p.precision);
+  for (const vlbm_box &b : c->boxes)
+    k += ":" + std::to_string(b.level) + "," + std::to_string(b.i0) + "," + std::to_string(b.j0) +
+         "," + std::to_string(b.nx) + "," + std::to_string(b.ny);
+  return k;
+}
+
+vlbm_status vlbm_autotune(vlbm_ctx *c, int steps_per_trial, int *tile_cells, int *flags) {
+  if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "no hierarchy installed");
+  if (steps_per_trial < 1) return fail(VLBM_EINVAL, "steps_per_trial < 1");
+  const std::string key = tuning_key(c);
+  auto hit = g_tuned.find(key);
+  vlbm_status st;
+  if (hit == g_tuned.end()) {
+    const int tiles[] = {128, 256, 512, 1024};
+    const int orders[] = {0, STEP_XCD_CONTIGUOUS};
+    float best = 1e30f;
+    std::pair<int, int> choice{c->tile_cells, c->step_flags};
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    for (int tcell : tiles)
+      for (int ord : orders) {
+        const int fl = (c->step_flags & ~STEP_XCD_CONTIGUOUS) | ord;
+        st = vlbm_set_tuning(c, tcell, fl);
+        if (!st) st = advance_impl(c, 1);  // warm
+        if (!st && hipEventRecord(e0, c->stream) != hipSuccess) st = fail(VLBM_EDEVICE, "event");
+        if (!st) st = advance_impl(c, steps_per_trial);
+        if (!st && hipEventRecord(e1, c->stream) != hipSuccess) st = fail(VLBM_EDEVICE, "event");
+        float ms = 0.f;
+        if (!st && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          st = fail(VLBM_EDEVICE, "event timing");
+        if (st) {
+          (void)hipEventDestroy(e0);
+          (void)hipEventDestroy(e1);
+          return st;
+        }
+        if (ms < best) {
+          best = ms;
+          choice = {tcell, fl};
+        }
+      }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    hit = g_tuned.emplace(key, choice).first;
+  }
+  st = vlbm_set_tuning(c, hit->second.first, hit->second.second);
+  if (st) return st;
+  if (tile_cells) *tile_cells = c->tile_cells;
+  if (flags) *flags = c->step_flags;
+  return VLBM_OK;
+}
+
 long vlbm_steps(const vlbm_ctx *c) { return c ? c->coarse_steps : -1; }
 
 vlbm_status vlbm_sync(vlbm_ctx *c) {

@@ -75,6 +75,8 @@ vlbm_check_health = _sig("vlbm_check_health", _st, [_P])
 vlbm_save = _sig("vlbm_save", _st, [_P, _P, C.POINTER(C.c_size_t)])
 vlbm_load = _sig("vlbm_load", _st, [_P, _P, C.c_size_t])
 vlbm_batch_advance = _sig("vlbm_batch_advance", _st, [C.POINTER(_P), C.POINTER(C.c_int), C.c_int])
+vlbm_set_tuning = _sig("vlbm_set_tuning", _st, [_P, C.c_int, C.c_int])
+vlbm_autotune = _sig("vlbm_autotune", _st, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)])
 vlbm_steps = _sig("vlbm_steps", C.c_long, [_P])
 vlbm_sync = _sig("vlbm_sync", _st, [_P])
 vlbm_last_error = _sig("vlbm_last_error", C.c_char_p, [])
@@ -83,8 +85,8 @@ EXPORTED = ["vlbm_create", "vlbm_destroy", "vlbm_bind_pool", "vlbm_footprint_byt
             "vlbm_set_hierarchy", "vlbm_set_state", "vlbm_set_populations", "vlbm_advance",
             "vlbm_get_state", "vlbm_get_populations", "vlbm_conserved_totals", "vlbm_regrid",
             "vlbm_tag", "vlbm_tag_and_regrid", "vlbm_get_boxes", "vlbm_check_health",
-            "vlbm_save", "vlbm_load", "vlbm_batch_advance", "vlbm_steps", "vlbm_sync",
-            "vlbm_last_error"]
+            "vlbm_save", "vlbm_load", "vlbm_batch_advance", "vlbm_set_tuning", "vlbm_autotune",
+            "vlbm_steps", "vlbm_sync", "vlbm_last_error"]
 
 
 class VLBMError(RuntimeError):
@@ -253,6 +255,14 @@ class Solver:
 
     def steps(self):
         return vlbm_steps(self._h)
+
+    def set_tuning(self, tile_cells, flags=0):
+        check(vlbm_set_tuning(self._h, int(tile_cells), int(flags)))
+
+    def autotune(self, steps_per_trial=5):
+        t, f = C.c_int(), C.c_int()
+        check(vlbm_autotune(self._h, int(steps_per_trial), C.byref(t), C.byref(f)))
+        return t.value, f.value
 
     def sync(self):
         check(vlbm_sync(self._h))
