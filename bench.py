@@ -54,31 +54,11 @@ def build_case(name, steps):
 
 
 def actual_updates_per_step(case):
-    """sum_l active_l * r^l: cell updates of one coarse step."""
-    import numpy as np
-    total = 0
-    cov = []
-    for l in range(case.nlev):
-        NY, NX = case.level_shape(l)
-        m = np.zeros((NY, NX), dtype=bool)
-        if l == 0:
-            m[:] = True
-        for (lv, i0, j0, nx, ny) in case.boxes:
-            if lv == l:
-                m[j0:j0 + ny, i0:i0 + nx] = True
-        cov.append(m)
-    for l in range(case.nlev):
-        act = cov[l].copy()
-        if l + 1 < case.nlev:
-            child = cov[l + 1][::case.r, ::case.r]
-            act &= ~child
-        total += int(act.sum()) * case.r ** l
-    return total
+    return case.actual_updates_per_coarse_step()
 
 
 def launches_per_step(case):
-    present = [l for l in range(case.nlev) if l == 0 or any(b[0] == l for b in case.boxes)]
-    return sum(case.r ** l for l in present)
+    return case.launches_per_coarse_step()
 
 
 def cpu_baseline(case, budget_s=15.0):
@@ -118,6 +98,40 @@ def copy_probe(gib=2.0, reps=20):
     return {"copy_bytes_per_launch": 2 * n * 8, "copy_us": s * 1e6, "copy_GBs": 2 * n * 8 / s / 1e9}
 
 
+def serve_benchmark(n_requests=32, rate=8.0, seed=0, budget_gib=64.0, quantum=25,
+                    check_accuracy=True):
+    """Served stream: continuous batching (FP32 bulk, FP64 interfaces) against
+    sequential plain FP64, same requests, same arrival times."""
+    import numpy as np
+    import torch
+    from paper_2609_35529_amd import serve, vlbm, workloads as wl
+    from tests.parity import smooth_mask
+    stream = torch.cuda.Stream()
+    reqs = wl.request_stream(n_requests, rate, seed=seed)
+    srv = serve.Server(int(budget_gib * 2 ** 30), precision=vlbm.FP32, quantum=quantum,
+                       stream=stream, keep_states=check_accuracy)
+    print("[bench] served stream (batched FP32)", file=sys.stderr, flush=True)
+    served, wall_s = srv.run(reqs)
+    print("[bench] sequential FP64", file=sys.stderr, flush=True)
+    seq, wall_q = serve.run_sequential(reqs, precision=vlbm.FP64, stream=stream,
+                                       keep_states=check_accuracy)
+    out = {"requests": n_requests, "rate_per_s": rate, "seed": seed, "quantum": quantum,
+           "batched_fp32": serve.summarize(served, wall_s),
+           "sequential_fp64": serve.summarize(seq, wall_q)}
+    if check_accuracy:
+        ref = {r.rid: r.state for r in seq}
+        worst = 0.0
+        for r in served:
+            Uo = ref[r.rid]
+            m = smooth_mask(Uo)
+            for k in range(4):
+                scale = np.nanmax(np.abs(Uo[k]))
+                if m.any():
+                    worst = max(worst, float(np.max(np.abs(r.state[k][m] - Uo[k][m])) / scale))
+        out["fp32_vs_fp64_smooth_rel_err"] = worst
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,11 +146,19 @@ def main():
     ap.add_argument("--flags", type=int, default=0, help="launch flags with --tile-cells")
     ap.add_argument("--tune-steps", type=int, default=5,
                     help="coarse steps timed per autotuner candidate (real steps of the run)")
+    ap.add_argument("--serve", action="store_true",
+                    help="also run the served-stream benchmark (batched FP32 vs sequential FP64)")
+    ap.add_argument("--serve-only", action="store_true", help="only the served-stream benchmark")
+    ap.add_argument("--requests", type=int, default=32)
+    ap.add_argument("--rate", type=float, default=8.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only measure a plain 2 GiB device copy and exit")
     args = ap.parse_args()
     if args.copy_probe:
         print(json.dumps(copy_probe()))
+        return
+    if args.serve_only:
+        print(json.dumps(serve_benchmark(args.requests, args.rate)))
         return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; --gpus above 1 is not supported "
@@ -223,6 +245,8 @@ def main():
         "conservation_drift_rel": drift,
         "healthy": healthy,
     }
+    if args.serve:
+        out["served"] = serve_benchmark(args.requests, args.rate)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(build_case(args.workload, 10 ** 6), args.cpu_budget)

@@ -89,6 +89,35 @@ class Case:
         s = self.r ** (self.nlev - 1)
         return self.nx0 * s * self.ny0 * s * s
 
+    def coverage(self):
+        """Per level, the boolean mask of covered cells (level 0: everything)."""
+        cov = []
+        for l in range(self.nlev):
+            NY, NX = self.level_shape(l)
+            m = np.zeros((NY, NX), dtype=bool)
+            if l == 0:
+                m[:] = True
+            for (lv, i0, j0, nx, ny) in self.boxes:
+                if lv == l:
+                    m[j0:j0 + ny, i0:i0 + nx] = True
+            cov.append(m)
+        return cov
+
+    def actual_updates_per_coarse_step(self):
+        """sum_l (active cells of level l) * r^l."""
+        cov = self.coverage()
+        total = 0
+        for l in range(self.nlev):
+            act = cov[l].copy()
+            if l + 1 < self.nlev:
+                act &= ~cov[l + 1][::self.r, ::self.r]
+            total += int(act.sum()) * self.r ** l
+        return total
+
+    def launches_per_coarse_step(self):
+        present = [l for l in range(self.nlev) if l == 0 or any(b[0] == l for b in self.boxes)]
+        return sum(self.r ** l for l in present)
+
 
 def _states_for(nx0, ny0, dx0, r, nlev, fn, x0=0.0, y0=0.0):
     out = []
