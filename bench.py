@@ -98,8 +98,8 @@ def copy_probe(gib=2.0, reps=20):
     return {"copy_bytes_per_launch": 2 * n * 8, "copy_us": s * 1e6, "copy_GBs": 2 * n * 8 / s / 1e9}
 
 
-def serve_benchmark(n_requests=32, rate=8.0, seed=0, budget_gib=64.0, quantum=25,
-                    check_accuracy=True):
+def serve_benchmark(n_requests=48, rate=64.0, seed=0, budget_gib=64.0, quantum=25,
+                    check_accuracy=True, precision="fp32s", policy="share"):
     """Served stream: continuous batching (FP32 bulk, FP64 interfaces) against
     sequential plain FP64, same requests, same arrival times."""
     import numpy as np
@@ -108,15 +108,17 @@ def serve_benchmark(n_requests=32, rate=8.0, seed=0, budget_gib=64.0, quantum=25
     from tests.parity import smooth_mask
     stream = torch.cuda.Stream()
     reqs = wl.request_stream(n_requests, rate, seed=seed)
-    srv = serve.Server(int(budget_gib * 2 ** 30), precision=vlbm.FP32, quantum=quantum,
-                       stream=stream, keep_states=check_accuracy)
-    print("[bench] served stream (batched FP32)", file=sys.stderr, flush=True)
+    prec = {"fp32": vlbm.FP32, "fp32s": vlbm.FP32_STORAGE, "fp64": vlbm.FP64}[precision]
+    srv = serve.Server(int(budget_gib * 2 ** 30), precision=prec, quantum=quantum,
+                       stream=stream, keep_states=check_accuracy, policy=policy)
+    print(f"[bench] served stream (batched {precision})", file=sys.stderr, flush=True)
     served, wall_s = srv.run(reqs)
     print("[bench] sequential FP64", file=sys.stderr, flush=True)
     seq, wall_q = serve.run_sequential(reqs, precision=vlbm.FP64, stream=stream,
                                        keep_states=check_accuracy)
-    out = {"requests": n_requests, "rate_per_s": rate, "seed": seed, "quantum": quantum,
-           "batched_fp32": serve.summarize(served, wall_s),
+    out = {"requests": n_requests, "rate_per_s": rate, "seed": seed,
+           "served_precision": precision, "policy": policy,
+           "batched": serve.summarize(served, wall_s),
            "sequential_fp64": serve.summarize(seq, wall_q)}
     if check_accuracy:
         ref = {r.rid: r.state for r in seq}
@@ -128,7 +130,7 @@ def serve_benchmark(n_requests=32, rate=8.0, seed=0, budget_gib=64.0, quantum=25
                 scale = np.nanmax(np.abs(Uo[k]))
                 if m.any():
                     worst = max(worst, float(np.max(np.abs(r.state[k][m] - Uo[k][m])) / scale))
-        out["fp32_vs_fp64_smooth_rel_err"] = worst
+        out["served_vs_fp64_smooth_rel_err"] = worst
     return out
 
 
@@ -138,7 +140,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="quadrant512")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "fp32s"],
+                    help="fp32s: FP32 storage, relaxation evaluated in FP64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-tune", action="store_true", help="skip the launch autotuner")
@@ -146,11 +149,13 @@ def main():
     ap.add_argument("--flags", type=int, default=0, help="launch flags with --tile-cells")
     ap.add_argument("--tune-steps", type=int, default=5,
                     help="coarse steps timed per autotuner candidate (real steps of the run)")
-    ap.add_argument("--serve", action="store_true",
-                    help="also run the served-stream benchmark (batched FP32 vs sequential FP64)")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the served-stream benchmark (batched FP32 storage vs sequential FP64)")
     ap.add_argument("--serve-only", action="store_true", help="only the served-stream benchmark")
-    ap.add_argument("--requests", type=int, default=32)
-    ap.add_argument("--rate", type=float, default=8.0)
+    ap.add_argument("--requests", type=int, default=48)
+    ap.add_argument("--rate", type=float, default=64.0)
+    ap.add_argument("--serve-precision", default="fp32s", choices=["fp32", "fp32s", "fp64"])
+    ap.add_argument("--serve-policy", default="share", choices=["share", "srpt", "fixed"])
     ap.add_argument("--copy-probe", action="store_true",
                     help="only measure a plain 2 GiB device copy and exit")
     args = ap.parse_args()
@@ -158,7 +163,9 @@ def main():
         print(json.dumps(copy_probe()))
         return
     if args.serve_only:
-        print(json.dumps(serve_benchmark(args.requests, args.rate)))
+        print(json.dumps(serve_benchmark(args.requests, args.rate,
+                                         precision=args.serve_precision,
+                                         policy=args.serve_policy)))
         return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; --gpus above 1 is not supported "
@@ -169,7 +176,7 @@ def main():
     from paper_2609_35529_amd import vlbm
 
     case = build_case(args.workload, args.warmup + args.steps)
-    prec = vlbm.FP64 if args.precision == "fp64" else vlbm.FP32
+    prec = {"fp64": vlbm.FP64, "fp32": vlbm.FP32, "fp32s": vlbm.FP32_STORAGE}[args.precision]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.Stream()  # a dedicated stream (default priority): graphs need one
@@ -228,7 +235,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == vlbm.FP64 else "f32",
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp32s": "f64 math, f32 storage"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{case.name}: {case.nx0}x{case.ny0} coarse, levels {case.nlev}, "
                                f"boxes {case.boxes}, r={case.r}, beta={case.beta}, "
@@ -245,8 +252,10 @@ def main():
         "conservation_drift_rel": drift,
         "healthy": healthy,
     }
-    if args.serve:
-        out["served"] = serve_benchmark(args.requests, args.rate)
+    if not args.no_serve:
+        out["served"] = serve_benchmark(args.requests, args.rate,
+                                        precision=args.serve_precision,
+                                        policy=args.serve_policy)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(build_case(args.workload, 10 ** 6), args.cpu_budget)

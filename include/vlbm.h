@@ -63,7 +63,7 @@ typedef enum {
 } vlbm_status;
 
 enum { VLBM_BC_PERIODIC = 0, VLBM_BC_OUTFLOW = 1, VLBM_BC_REFLECT = 2, VLBM_BC_INFLOW = 3 };
-enum { VLBM_FP64 = 0, VLBM_FP32 = 1 };
+enum { VLBM_FP64 = 0, VLBM_FP32 = 1, VLBM_FP32_STORAGE = 2 };
 
 /* Problem parameters (the paper's problem statement: base grid, ratio, EOS,
  * relaxation, link speed; Sec. 2.2 and 3.2).
@@ -73,7 +73,9 @@ enum { VLBM_FP64 = 0, VLBM_FP32 = 1 };
  *       inflow injects f^eq(w_inflow[side]).
  *   precision: VLBM_FP64 stores and relaxes populations in FP64;
  *       VLBM_FP32 stores and relaxes them in FP32 while the reconstruction,
- *       the reflux accumulators, the boundary ledger and the totals stay FP64.
+ *       the reflux accumulators, the boundary ledger and the totals stay FP64;
+ *       VLBM_FP32_STORAGE stores them in FP32 (same bytes as VLBM_FP32) but
+ *       evaluates the relaxation in FP64, rounding once per stored value.
  *   beta in [0, 1] (0 switches relaxation off: pure streaming). */
 typedef struct {
   int nx0, ny0;

@@ -1148,7 +1148,8 @@ vlbm_status vlbm_create(const vlbm_params *params, void *stream, vlbm_ctx **out)
   const vlbm_params &p = *params;
   if (p.nx0 < 1 || p.ny0 < 1 || !(p.dx0 > 0) || p.r < 1 || p.r > 8 || p.max_levels < 1 ||
       p.max_levels > kMaxLevels || !(p.c > 0) || !(p.beta >= 0 && p.beta <= 1) ||
-      !(p.gamma > 1) || (p.precision != VLBM_FP64 && p.precision != VLBM_FP32))
+      !(p.gamma > 1) ||
+      (p.precision != VLBM_FP64 && p.precision != VLBM_FP32 && p.precision != VLBM_FP32_STORAGE))
     return fail(VLBM_EINVAL, "invalid parameters");
   for (int s = 0; s < 4; ++s)
     if (p.bc[s] < 0 || p.bc[s] > 3) return fail(VLBM_EINVAL, "invalid boundary condition");
@@ -1162,7 +1163,8 @@ vlbm_status vlbm_create(const vlbm_params *params, void *stream, vlbm_ctx **out)
   vlbm_ctx *c = new vlbm_ctx();
   c->p = p;
   c->stream = static_cast<hipStream_t>(stream);
-  c->fp32 = p.precision == VLBM_FP32;
+  c->fp32 = p.precision != VLBM_FP64;
+  if (p.precision == VLBM_FP32_STORAGE) c->step_flags |= STEP_F64_MATH;
   c->esz = c->fp32 ? 4 : 8;
   c->tile_cells = tile_cells_default();
   if (const char *e = getenv("VLBM_NT_STORES")) c->step_flags |= atoi(e) ? STEP_NT_STORES : 0;
@@ -1535,7 +1537,7 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
     vlbm_ctx *c = ctxs[i];
     if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "context %d has no hierarchy", i);
     if (n_steps[i] < 0) return fail(VLBM_EINVAL, "negative step count");
-    if (c->stream != c0->stream || c->fp32 != c0->fp32 || c->p.r != c0->p.r)
+    if (c->stream != c0->stream || c->p.precision != c0->p.precision || c->p.r != c0->p.r)
       return fail(VLBM_EINVAL, "batched contexts must share stream, precision and ratio");
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == c) return fail(VLBM_EINVAL, "context %d listed twice", i);
@@ -1630,7 +1632,7 @@ vlbm_status vlbm_set_tuning(vlbm_ctx *c, int tile_cells, int flags) {
   if (tile_cells < 64 || tile_cells > (1 << 20) || (flags & ~(STEP_NT_STORES | STEP_TWO_CELLS | STEP_XCD_CONTIGUOUS)))
     return fail(VLBM_EINVAL, "bad tuning (tile_cells %d, flags %d)", tile_cells, flags);
   c->tile_cells = tile_cells;
-  c->step_flags = flags;
+  c->step_flags = flags | (c->step_flags & STEP_F64_MATH);
   if (!c->have_hierarchy) return VLBM_OK;
   std::vector<vlbm_box> boxes = c->boxes;  // same hierarchy, new tile decomposition
   return regrid_impl(c, boxes.data(), (int)boxes.size());
@@ -1664,7 +1666,7 @@ vlbm_status vlbm_autotune(vlbm_ctx *c, int steps_per_trial, int *tile_cells, int
     HIPCHK(hipEventCreate(&e1));
     for (int tcell : tiles)
       for (int ord : orders) {
-        const int fl = (c->step_flags & ~STEP_XCD_CONTIGUOUS) | ord;
+        const int fl = (c->step_flags & ~(STEP_XCD_CONTIGUOUS | STEP_F64_MATH)) | ord;
         st = vlbm_set_tuning(c, tcell, fl);
         if (!st) st = advance_impl(c, 1);  // warm
         if (!st && hipEventRecord(e0, c->stream) != hipSuccess) st = fail(VLBM_EDEVICE, "event");
@@ -1690,7 +1692,7 @@ vlbm_status vlbm_autotune(vlbm_ctx *c, int steps_per_trial, int *tile_cells, int
   st = vlbm_set_tuning(c, hit->second.first, hit->second.second);
   if (st) return st;
   if (tile_cells) *tile_cells = c->tile_cells;
-  if (flags) *flags = c->step_flags;
+  if (flags) *flags = c->step_flags & ~STEP_F64_MATH;
   return VLBM_OK;
 }
 

@@ -170,32 +170,34 @@ __device__ __forceinline__ void run_task(const LevelDesc &A, int first, double a
 // ---------------------------------------------------------------------------
 // The fused step kernel
 // ---------------------------------------------------------------------------
-template <class T>
-__device__ __forceinline__ void pull(const T *__restrict__ s, int64_t P, int pitch, int64_t o,
-                                     T g[16]) {
+// S: storage type of the populations, C: type the relaxation computes in.
+template <class S, class C>
+__device__ __forceinline__ void pull(const S *__restrict__ s, int64_t P, int pitch, int64_t o,
+                                     C g[16]) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    g[k] = s[(0 * 4 + k) * P + o - 1];           // +x arrives from x-1
-    g[4 + k] = s[(1 * 4 + k) * P + o + 1];       // -x arrives from x+1
-    g[8 + k] = s[(2 * 4 + k) * P + o - pitch];   // +y arrives from y-1
-    g[12 + k] = s[(3 * 4 + k) * P + o + pitch];  // -y arrives from y+1
+    g[k] = (C)s[(0 * 4 + k) * P + o - 1];           // +x arrives from x-1
+    g[4 + k] = (C)s[(1 * 4 + k) * P + o + 1];       // -x arrives from x+1
+    g[8 + k] = (C)s[(2 * 4 + k) * P + o - pitch];   // +y arrives from y-1
+    g[12 + k] = (C)s[(3 * 4 + k) * P + o + pitch];  // -y arrives from y+1
   }
 }
 
-template <class T, bool NT>
-__device__ __forceinline__ void put(T *__restrict__ d, int64_t P, int64_t o, const T g[16]) {
+template <class S, class C, bool NT>
+__device__ __forceinline__ void put(S *__restrict__ d, int64_t P, int64_t o, const C g[16]) {
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
+    const S v = (S)g[i];
     if (NT)
-      __builtin_nontemporal_store(g[i], &d[i * P + o]);
+      __builtin_nontemporal_store(v, &d[i * P + o]);
     else
-      d[i * P + o] = g[i];
+      d[i * P + o] = v;
   }
 }
 
 // One workgroup's work on tile `lb` of descriptor A (inlined twice below, so
 // that A is either plain kernel-argument memory or plain global memory).
-template <class T, bool NT, bool TWO>
+template <class T, class C, bool NT, bool TWO>
 __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks, int first,
                                          double ak, int flags) {
   // Tile order. Natural order keeps every workgroup of the chip inside one
@@ -211,7 +213,7 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
   T *__restrict__ d = static_cast<T *>(A.dst);
   const int64_t plane = A.plane;
   const int pitch = A.pitch;
-  const T gm1 = (T)A.gm1, h = (T)A.h, tb = (T)A.tb;
+  const C gm1 = (C)A.gm1, h = (C)A.h, tb = (C)A.tb;
   if (tl.ntask) {
     for (int i = threadIdx.x; i < tl.ntask; i += blockDim.x)
       run_task<T>(A, first, ak, A.tasks[tl.task0 + i]);
@@ -224,19 +226,19 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
       const int c2 = c + blockDim.x;
       const int cy = c / tl.w, cx = c - cy * tl.w;
       const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
-      T g[16], g2[16];
-      pull<T>(s, plane, pitch, o, g);
+      C g[16], g2[16];
+      pull<T, C>(s, plane, pitch, o, g);
       int64_t o2 = 0;
       if (c2 < n) {
         const int cy2 = c2 / tl.w, cx2 = c2 - cy2 * tl.w;
         o2 = (int64_t)tl.off0 + (int64_t)cy2 * pitch + cx2;
-        pull<T>(s, plane, pitch, o2, g2);
+        pull<T, C>(s, plane, pitch, o2, g2);
       }
-      relax<T>(g, gm1, h, tb);
-      put<T, NT>(d, plane, o, g);
+      relax<C>(g, gm1, h, tb);
+      put<T, C, NT>(d, plane, o, g);
       if (c2 < n) {
-        relax<T>(g2, gm1, h, tb);
-        put<T, NT>(d, plane, o2, g2);
+        relax<C>(g2, gm1, h, tb);
+        put<T, C, NT>(d, plane, o2, g2);
       }
     }
   } else {
@@ -244,16 +246,16 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
       const int cy = c / tl.w;
       const int cx = c - cy * tl.w;
       const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
-      T g[16];
-      pull<T>(s, plane, pitch, o, g);
-      relax<T>(g, gm1, h, tb);
-      put<T, NT>(d, plane, o, g);
+      C g[16];
+      pull<T, C>(s, plane, pitch, o, g);
+      relax<C>(g, gm1, h, tb);
+      put<T, C, NT>(d, plane, o, g);
     }
   }
 }
 
 
-template <class T, bool NT, bool TWO>
+template <class T, class C, bool NT, bool TWO>
 __global__ __launch_bounds__(256) void step_kernel(StepLaunch Lc) {
   const int b = blockIdx.x;
   const LevelDesc *dp = Lc.d0;
@@ -269,23 +271,27 @@ __global__ __launch_bounds__(256) void step_kernel(StepLaunch Lc) {
     first_block = sg.first_block;
     nblocks = sg.nblocks;
   }
-  run_tile<T, NT, TWO>(*dp, b - first_block, nblocks, Lc.first, Lc.ak, Lc.flags);
+  run_tile<T, C, NT, TWO>(*dp, b - first_block, nblocks, Lc.first, Lc.ak, Lc.flags);
 }
 
 hipError_t launch_step(const StepLaunch &a, int fp32, hipStream_t s) {
   if (a.nblocks <= 0 || a.nseg < 0) return hipSuccess;
   dim3 grid(a.nblocks), block(256);
-  const int v = (a.flags & (STEP_NT_STORES | STEP_TWO_CELLS)) | (fp32 ? 4 : 0);
-  switch (v) {
-    case 0: hipLaunchKernelGGL((step_kernel<double, false, false>), grid, block, 0, s, a); break;
-    case 1: hipLaunchKernelGGL((step_kernel<double, true, false>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((step_kernel<double, false, true>), grid, block, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((step_kernel<double, true, true>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((step_kernel<float, false, false>), grid, block, 0, s, a); break;
-    case 5: hipLaunchKernelGGL((step_kernel<float, true, false>), grid, block, 0, s, a); break;
-    case 6: hipLaunchKernelGGL((step_kernel<float, false, true>), grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL((step_kernel<float, true, true>), grid, block, 0, s, a); break;
-  }
+  const bool nt = (a.flags & STEP_NT_STORES) != 0, two = (a.flags & STEP_TWO_CELLS) != 0;
+#define VLBM_STEP(S, C)                                                                        \
+  do {                                                                                         \
+    if (nt && two) hipLaunchKernelGGL((step_kernel<S, C, true, true>), grid, block, 0, s, a);   \
+    else if (nt) hipLaunchKernelGGL((step_kernel<S, C, true, false>), grid, block, 0, s, a);    \
+    else if (two) hipLaunchKernelGGL((step_kernel<S, C, false, true>), grid, block, 0, s, a);   \
+    else hipLaunchKernelGGL((step_kernel<S, C, false, false>), grid, block, 0, s, a);           \
+  } while (0)
+  if (!fp32)
+    VLBM_STEP(double, double);
+  else if (a.flags & STEP_F64_MATH)
+    VLBM_STEP(float, double);
+  else
+    VLBM_STEP(float, float);
+#undef VLBM_STEP
   return hipGetLastError();
 }
 

@@ -47,6 +47,7 @@ enum StepFlags : int32_t {
   STEP_NT_STORES = 1,        // write the new time level with non-temporal stores
   STEP_TWO_CELLS = 2,        // two cells per thread, gathers issued together
   STEP_XCD_CONTIGUOUS = 4,   // map consecutive tiles to the same XCD
+  STEP_F64_MATH = 8,         // FP32 storage, relaxation evaluated in FP64
 };
 
 // Everything the step kernel needs about one (context, level) at one phase of

@@ -66,11 +66,16 @@ class Server:
     BANDWIDTH = 4.5e12
     LAUNCH_S = 6e-6
 
-    def __init__(self, budget_bytes: int, precision=vlbm.FP32, quantum=25, max_resident=64,
-                 stream=None, keep_states=False, slice_s=0.02):
-        """quantum: fixed coarse steps per iteration when slice_s is None; else
-        every resident solve gets an equal share of a slice_s-second iteration,
-        converted to steps with the cost model (processor sharing)."""
+    def __init__(self, budget_bytes: int, precision=vlbm.FP32_STORAGE, quantum=25,
+                 max_resident=64, stream=None, keep_states=False, slice_s=0.02,
+                 policy="share"):
+        """Per iteration, resident solves advance together in shared launches.
+        policy "fixed": every solve takes `quantum` coarse steps.
+        policy "share": every solve gets an equal share of a slice_s-second
+        iteration, converted to steps with the cost model (processor sharing).
+        policy "srpt": the slice is filled in order of least remaining work
+        (whole remainders first), every solve still taking at least one step, so
+        short solves finish early and long ones never stall."""
         self.budget = int(budget_bytes)
         self.precision = precision
         self.quantum = int(quantum)
@@ -78,17 +83,29 @@ class Server:
         self.stream = stream
         self.keep_states = keep_states
         self.slice_s = slice_s
+        self.policy = policy
 
     def step_cost(self, case):
         esz = 4 if self.precision == vlbm.FP32 else 8
         return (case.actual_updates_per_coarse_step() * 32 * esz / self.BANDWIDTH
                 + case.launches_per_coarse_step() * self.LAUNCH_S)
 
-    def _steps_for(self, entry, nres):
-        if self.slice_s is None:
-            return min(self.quantum, entry["left"])
-        share = self.slice_s / max(1, nres)
-        return int(max(1, min(entry["left"], share // entry["cost"])))
+    def plan(self, resident):
+        """Coarse steps each resident solve takes this iteration."""
+        if self.policy == "fixed":
+            return [min(self.quantum, e["left"]) for e in resident]
+        if self.policy == "share":
+            share = self.slice_s / max(1, len(resident))
+            return [int(max(1, min(e["left"], share // e["cost"]))) for e in resident]
+        budget = self.slice_s
+        n = [1] * len(resident)
+        budget -= sum(e["cost"] for e in resident)
+        for i in sorted(range(len(resident)), key=lambda i: resident[i]["left"] * resident[i]["cost"]):
+            e = resident[i]
+            extra = int(min(e["left"] - 1, max(0.0, budget) // e["cost"]))
+            n[i] += extra
+            budget -= extra * e["cost"]
+        return n
 
     def run(self, requests: List[dict], time_scale: float = 1.0) -> (List[Result], float):
         """Serve requests (arrival times in seconds, scaled by time_scale)."""
@@ -126,7 +143,7 @@ class Server:
                     if wait > 0:
                         time.sleep(min(wait, 0.05))
                 continue
-            n = [self._steps_for(e, len(resident)) for e in resident]
+            n = self.plan(resident)
             vlbm.batch_advance([e["solver"] for e in resident], n)
             for e, k in zip(resident, n):
                 e["left"] -= k

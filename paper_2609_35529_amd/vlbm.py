@@ -25,7 +25,7 @@ _lib = C.CDLL(LIB_PATH)
 VLBM_OK, VLBM_EINVAL, VLBM_ENOMEM, VLBM_ENEST, VLBM_EUNSTABLE, VLBM_EDEVICE, VLBM_ESTATE = (
     0, -1, -2, -3, -4, -5, -6)
 PERIODIC, OUTFLOW, REFLECT, INFLOW = 0, 1, 2, 3
-FP64, FP32 = 0, 1
+FP64, FP32, FP32_STORAGE = 0, 1, 2
 
 
 class vlbm_params(C.Structure):

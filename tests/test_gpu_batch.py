@@ -31,7 +31,7 @@ def _mix():
     return [wl.request_case(dict(r, steps=0)) for r in reqs]
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_batch_equals_alone(precision):
     import torch
     stream = torch.cuda.Stream()

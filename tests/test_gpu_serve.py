@@ -18,7 +18,7 @@ def _requests():
     return reqs
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_served_results_equal_alone(precision):
     import torch
     from paper_2609_35529_amd import serve, vlbm
