@@ -45,6 +45,8 @@ def build_case(name, steps):
         return wl.quadrant(n0=512, seed=0, steps=steps)
     if name == "sod":
         return wl.sod_2d(steps=steps)
+    if name == "shock_bubble":
+        return wl.shock_bubble(steps=steps)
     if name == "uniform4096":
         import numpy as np
         n = 4096
@@ -144,6 +146,10 @@ def main():
                     help="fp32s: FP32 storage, relaxation evaluated in FP64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--amr-threshold", type=float, default=0.05)
+    ap.add_argument("--amr-buffer", type=int, default=4)
+    ap.add_argument("--amr-min-box", type=int, default=16)
+    ap.add_argument("--amr-max-box", type=int, default=64)
     ap.add_argument("--no-tune", action="store_true", help="skip the launch autotuner")
     ap.add_argument("--tile-cells", type=int, default=0, help="fixed launch tuning (skips the autotuner)")
     ap.add_argument("--flags", type=int, default=0, help="launch flags with --tile-cells")
@@ -162,6 +168,8 @@ def main():
     if args.copy_probe:
         print(json.dumps(copy_probe()))
         return
+    if args.workload == "shock_bubble":
+        args.no_tune = True  # the hierarchy changes every few steps
     if args.serve_only:
         print(json.dumps(serve_benchmark(args.requests, args.rate,
                                          precision=args.serve_precision,
@@ -191,14 +199,45 @@ def main():
         print(f"[bench] {case.name} autotune", file=sys.stderr, flush=True)
         tile, flags = solver.autotune(steps_per_trial=args.tune_steps)
         tuning = {"tile_cells": tile, "flags": flags}
+    dynamic = case.name == "shock_bubble"
+    regrid_every = 5
+    amr = {"regrids": 0, "boxes": [], "regrid_s": 0.0, "updates": 0, "launches": 0}
+
+    def run(n):
+        """n coarse steps; the dynamic-AMR workload re-tags and regrids every
+        regrid_every coarse steps (inside the timed region)."""
+        if not dynamic:
+            solver.advance(n)
+            return
+        done = 0
+        while done < n:
+            if solver.steps() % regrid_every == 0:
+                t = time.perf_counter()
+                solver.tag_and_regrid(args.amr_threshold, buffer=args.amr_buffer,
+                                      min_box=args.amr_min_box, max_box=args.amr_max_box)
+                amr["regrid_s"] += time.perf_counter() - t
+                amr["regrids"] += 1
+                amr["boxes"].append(len(solver.boxes()))
+            k = min(n - done, regrid_every - solver.steps() % regrid_every)
+            solver.advance(k)
+            act = [solver.active_cells(l) for l in range(case.nlev)]
+            amr["updates"] += k * sum(a * case.r ** l for l, a in enumerate(act))
+            amr["launches"] += k * sum(case.r ** l for l, a in enumerate(act) if a > 0)
+            done += k
+
+    if dynamic:  # build the hierarchy before tuning and timing
+        for _ in range(case.nlev - 1):
+            solver.tag_and_regrid(args.amr_threshold, buffer=args.amr_buffer,
+                                  min_box=args.amr_min_box, max_box=args.amr_max_box)
     print(f"[bench] {case.name} warmup {args.warmup}", file=sys.stderr, flush=True)
-    solver.advance(args.warmup)
+    run(args.warmup)
     torch.cuda.synchronize()
+    amr.update(regrids=0, boxes=[], regrid_s=0.0, updates=0, launches=0)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record(stream)
-    solver.advance(args.steps)
+    run(args.steps)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -208,10 +247,10 @@ def main():
 
     fe_step = case.fine_equivalent_per_coarse_step()
     value = fe_step * args.steps / wall
-    upd = actual_updates_per_step(case)
+    upd = actual_updates_per_step(case) if not dynamic else amr["updates"] / args.steps
     esz = 8 if prec == vlbm.FP64 else 4
     bytes_per_update = 2 * 16 * esz
-    nl = launches_per_step(case)
+    nl = launches_per_step(case) if not dynamic else amr["launches"] / args.steps
     avg_launch_s = gpu_ms / 1e3 / (args.steps * nl)
     bytes_per_launch = upd * bytes_per_update / nl
     achieved = bytes_per_launch / avg_launch_s / 1e9
@@ -248,6 +287,9 @@ def main():
                      "kernel": "step_kernel", "bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": avg_launch_s * 1e6},
         "actual_updates_per_s": upd * args.steps / wall,
+        "amr": ({"regrid_every": regrid_every, "regrids": amr["regrids"],
+                 "boxes_min": min(amr["boxes"]), "boxes_max": max(amr["boxes"]),
+                 "regrid_s": amr["regrid_s"]} if dynamic and amr["boxes"] else None),
         "gpu_event_ms": gpu_ms,
         "conservation_drift_rel": drift,
         "healthy": healthy,

@@ -195,6 +195,9 @@ vlbm_status vlbm_autotune(vlbm_ctx *ctx, int steps_per_trial, int *tile_cells, i
 /* Coarse steps taken since set_state. */
 long vlbm_steps(const vlbm_ctx *ctx);
 
+/* Number of active cells of a level (0 for an absent level). */
+long vlbm_active_cells(const vlbm_ctx *ctx, int level);
+
 /* Wait for all work of ctx. */
 vlbm_status vlbm_sync(vlbm_ctx *ctx);
 

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -51,6 +52,21 @@ vlbm_status fail(vlbm_status st, const char *fmt, ...) {
   } while (0)
 
 constexpr int kMaxLevels = 8;
+
+// VLBM_TIMING=1 prints host-side phase timings of hierarchy changes to stderr.
+struct PhaseTimer {
+  bool on;
+  std::chrono::steady_clock::time_point t;
+  const char *what;
+  explicit PhaseTimer(const char *w) : on(getenv("VLBM_TIMING") != nullptr), t(std::chrono::steady_clock::now()), what(w) {}
+  void mark(const char *phase) {
+    if (!on) return;
+    auto now = std::chrono::steady_clock::now();
+    fprintf(stderr, "[vlbm] %s %s %.3f ms\n", what, phase,
+            std::chrono::duration<double, std::milli>(now - t).count());
+    t = now;
+  }
+};
 const int CX[4] = {1, -1, 0, 0};
 const int CY[4] = {0, 0, 1, -1};
 
@@ -456,10 +472,17 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
     std::vector<std::pair<int, Task>> tk;  // (tile, task)
     L.acc_slot.clear();
     L.nledger = 0;
+    const int fw = L.fw;
     for (int y = L.fy0 + 1; y < L.fy0 + L.fh - 1; ++y)
       for (int x = L.fx0 + 1; x < L.fx0 + L.fw - 1; ++x) {
-        if (L.status[L.fidx(x, y)] != 1) continue;
-        const int tile = owner[L.fidx(x, y)];
+        const size_t ci = L.fidx(x, y);
+        if (L.status[ci] != 1) continue;
+        // interior cell: all four upwind neighbours active at this level (hence
+        // inside the domain) -> plain pulls, no task
+        if (L.status[ci - 1] == 1 && L.status[ci + 1] == 1 && L.status[ci - fw] == 1 &&
+            L.status[ci + fw] == 1)
+          continue;
+        const int tile = owner[ci];
         for (int q = 0; q < 4; ++q) {
           int sx = x - CX[q], sy = y - CY[q];
           int wx = sx, wy = sy;
@@ -516,7 +539,9 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
       std::vector<int> count;
       for (int y = L.fy0 + 1; y < L.fy0 + L.fh - 1; ++y)
         for (int x = L.fx0 + 1; x < L.fx0 + L.fw - 1; ++x) {
-          if (L.status[L.fidx(x, y)] != 1) continue;
+          const size_t ci = L.fidx(x, y);
+          if (L.status[ci] != 1) continue;
+          if (L.cov[ci - 1] && L.cov[ci + 1] && L.cov[ci - L.fw] && L.cov[ci + L.fw]) continue;
           for (int q = 0; q < 4; ++q) {
             int dx = x + CX[q], dy = y + CY[q];
             if (!c->wrap(l, dx, dy)) continue;
@@ -885,9 +910,21 @@ vlbm_status carry_ledgers(vlbm_ctx *c) {
 // neighbour only if it is covered at that level in the new hierarchy and holds
 // data (i.e. it is not a hole both before and after).
 vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
+  PhaseTimer tm("regrid");
   Geometry g;
   vlbm_status st = check_boxes(c->p, boxes, nboxes, g);
   if (st) return st;
+  // Frames only grow while a level persists: when the new coverage fits in the
+  // current frame the frame (and its buffers) is kept, so a moving refinement
+  // zone does not reallocate every regrid.
+  for (int l = 1; l < kMaxLevels; ++l) {
+    const Level &O = c->lv[l];
+    if (!g.present[l] || !O.present) continue;
+    g.bx0[l] = std::min(g.bx0[l], O.fx0 + 1);
+    g.by0[l] = std::min(g.by0[l], O.fy0 + 1);
+    g.bx1[l] = std::max(g.bx1[l], O.fx0 + O.fw - 1);
+    g.by1[l] = std::max(g.by1[l], O.fy0 + O.fh - 1);
+  }
   vlbm_ctx *t = new vlbm_ctx();
   t->p = c->p;
   t->esz = c->esz;
@@ -906,6 +943,7 @@ vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
     delete t;
     return st;
   }
+  tm.mark("lists");
   const int r = c->p.r;
   auto done = [&](vlbm_status s2) {
     delete t;
@@ -1024,6 +1062,7 @@ vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
     HIPCHK(launch_split(a, c->fp32, c->stream));
   }
   if (hipStreamSynchronize(c->stream) != hipSuccess) return done(fail(VLBM_EDEVICE, "regrid kernels failed"));
+  tm.mark("merge/copy/split");
   c->mem.release(dops);
   // 4. install the new hierarchy
   for (int l = 0; l < kMaxLevels; ++l) {
@@ -1037,7 +1076,9 @@ vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
     if (st) return st;
   }
   c->boxes.assign(boxes, boxes + nboxes);
-  return build_tables(c);
+  st = build_tables(c);
+  tm.mark("upload");
+  return st;
 }
 
 // Clustering for tag_and_regrid: level-l tags (after dilation) restricted to
@@ -1051,41 +1092,52 @@ void cluster_level(vlbm_ctx *c, int l, const std::vector<uint8_t> &tags, const s
   long s = 1;
   for (int i = 0; i < l; ++i) s *= r;
   const int Nx = (int)(c->p.nx0 * s), Ny = (int)(c->p.ny0 * s);
-  auto at = [&](const std::vector<uint8_t> &m, int x, int y) -> bool {
-    if (x < 0 || x >= Nx) {
-      if (!c->perx()) return false;
-      x = ((x % Nx) + Nx) % Nx;
-    }
-    if (y < 0 || y >= Ny) {
-      if (!c->pery()) return false;
-      y = ((y % Ny) + Ny) % Ny;
-    }
-    return m[(size_t)y * Nx + x] != 0;
+  // dilation by a square of radius `buffer`: two 1-D passes with running
+  // counts (periodic axes wrap, other axes clip)
+  auto dilate1d = [&](const uint8_t *src, uint8_t *dst, int n, size_t stride, bool periodic) {
+    std::vector<int> pre(n + 1, 0);
+    for (int i = 0; i < n; ++i) pre[i + 1] = pre[i] + (src[i * stride] ? 1 : 0);
+    auto cnt = [&](int a, int b) {  // tags in [a, b], a <= b, possibly outside [0, n)
+      if (!periodic) {
+        a = std::max(a, 0);
+        b = std::min(b, n - 1);
+        return a <= b ? pre[b + 1] - pre[a] : 0;
+      }
+      if (b - a + 1 >= n) return pre[n];
+      int am = ((a % n) + n) % n, bm = ((b % n) + n) % n;
+      return am <= bm ? pre[bm + 1] - pre[am] : (pre[n] - pre[am]) + pre[bm + 1];
+    };
+    for (int i = 0; i < n; ++i) dst[i * stride] = cnt(i - buffer, i + buffer) > 0;
   };
-  // dilation (square neighbourhood of radius `buffer`), separable
   std::vector<uint8_t> tx(tags.size(), 0), dil(tags.size(), 0);
+  for (int y = 0; y < Ny; ++y) dilate1d(&tags[(size_t)y * Nx], &tx[(size_t)y * Nx], Nx, 1, c->perx());
+  for (int x = 0; x < Nx; ++x) dilate1d(&tx[x], &dil[x], Ny, (size_t)Nx, c->pery());
+  // allowed region: covered with all four neighbours covered (proper nesting);
+  // neighbours outside a non-periodic side are exempt
+  std::vector<uint8_t> bad((size_t)Nx * Ny, 0);
+  for (int y = 0; y < Ny; ++y) {
+    const int ym = y > 0 ? y - 1 : (c->pery() ? Ny - 1 : -1);
+    const int yp = y + 1 < Ny ? y + 1 : (c->pery() ? 0 : -1);
+    for (int x = 0; x < Nx; ++x) {
+      const int xm = x > 0 ? x - 1 : (c->perx() ? Nx - 1 : -1);
+      const int xp = x + 1 < Nx ? x + 1 : (c->perx() ? 0 : -1);
+      const size_t row = (size_t)y * Nx;
+      bool ok = cov[row + x] && (xm < 0 || cov[row + xm]) && (xp < 0 || cov[row + xp]) &&
+                (ym < 0 || cov[(size_t)ym * Nx + x]) && (yp < 0 || cov[(size_t)yp * Nx + x]);
+      bad[row + x] = !ok;
+    }
+  }
+  // 2-D prefix sums: O(1) "any dilated tag" and "any disallowed cell" per tile
+  std::vector<int32_t> pt((size_t)(Nx + 1) * (Ny + 1), 0), pb((size_t)(Nx + 1) * (Ny + 1), 0);
   for (int y = 0; y < Ny; ++y)
     for (int x = 0; x < Nx; ++x) {
-      bool any = false;
-      for (int d = -buffer; d <= buffer && !any; ++d) any = at(tags, x + d, y);
-      tx[(size_t)y * Nx + x] = any;
+      const size_t i = (size_t)(y + 1) * (Nx + 1) + (x + 1);
+      pt[i] = dil[(size_t)y * Nx + x] + pt[i - 1] + pt[i - (Nx + 1)] - pt[i - (Nx + 1) - 1];
+      pb[i] = bad[(size_t)y * Nx + x] + pb[i - 1] + pb[i - (Nx + 1)] - pb[i - (Nx + 1) - 1];
     }
-  for (int y = 0; y < Ny; ++y)
-    for (int x = 0; x < Nx; ++x) {
-      bool any = false;
-      for (int d = -buffer; d <= buffer && !any; ++d) any = at(tx, x, y + d);
-      dil[(size_t)y * Nx + x] = any;
-    }
-  // allowed region: covered with all four neighbours covered (proper nesting)
-  auto allowed = [&](int x, int y) {
-    if (!cov[(size_t)y * Nx + x]) return false;
-    for (int d = 0; d < 4; ++d) {
-      int xx = x + CX[d], yy = y + CY[d];
-      bool outside = (xx < 0 || xx >= Nx) ? !c->perx() : (yy < 0 || yy >= Ny) ? !c->pery() : false;
-      if (outside) continue;
-      if (!at(cov, xx, yy)) return false;
-    }
-    return true;
+  auto rect = [&](const std::vector<int32_t> &P, int x0, int y0, int x1, int y1) {
+    const size_t W = Nx + 1;
+    return P[(size_t)y1 * W + x1] - P[(size_t)y0 * W + x1] - P[(size_t)y1 * W + x0] + P[(size_t)y0 * W + x0];
   };
   const int T = std::max(1, (min_box + r - 1) / r);
   const int maxT = std::max(1, max_box / (T * r));
@@ -1093,13 +1145,8 @@ void cluster_level(vlbm_ctx *c, int l, const std::vector<uint8_t> &tags, const s
   std::vector<uint8_t> mark((size_t)ntx * nty, 0);
   for (int ty = 0; ty < nty; ++ty)
     for (int tx2 = 0; tx2 < ntx; ++tx2) {
-      bool any = false, ok = true;
-      for (int y = ty * T; y < std::min(Ny, (ty + 1) * T); ++y)
-        for (int x = tx2 * T; x < std::min(Nx, (tx2 + 1) * T); ++x) {
-          any = any || dil[(size_t)y * Nx + x];
-          ok = ok && allowed(x, y);
-        }
-      mark[(size_t)ty * ntx + tx2] = any && ok;
+      const int x0 = tx2 * T, y0 = ty * T, x1 = std::min(Nx, x0 + T), y1 = std::min(Ny, y0 + T);
+      mark[(size_t)ty * ntx + tx2] = rect(pt, x0, y0, x1, y1) > 0 && rect(pb, x0, y0, x1, y1) == 0;
     }
   // greedy merge: row runs of at most maxT tiles, stacked while identical
   struct Run { int a, b, y0, h; };
@@ -1383,6 +1430,7 @@ vlbm_status vlbm_regrid(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
 vlbm_status vlbm_tag_and_regrid(vlbm_ctx *c, double thr, int buffer, int min_box, int max_box) {
   if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "no hierarchy installed");
   if (buffer < 0 || min_box < 1 || max_box < min_box) return fail(VLBM_EINVAL, "bad clustering sizes");
+  PhaseTimer tm("tag_and_regrid");
   const int r = c->p.r, ML = c->p.max_levels;
   if (ML < 2) return VLBM_OK;
   std::vector<std::vector<uint8_t>> tags(ML);
@@ -1400,11 +1448,28 @@ vlbm_status vlbm_tag_and_regrid(vlbm_ctx *c, double thr, int buffer, int min_box
       }
     }
   }
+  tm.mark("tags");
   // a tagged finer cell tags its parent: refined features keep their levels
-  for (int l = std::min(c->nlev, ML) - 1; l >= 1; --l)
-    for (int y = 0; y < Ny[l]; ++y)
-      for (int x = 0; x < Nx[l]; ++x)
-        if (tags[l][(size_t)y * Nx[l] + x]) tags[l - 1][(size_t)(y / r) * Nx[l - 1] + x / r] = 1;
+  for (int l = std::min(c->nlev, ML) - 1; l >= 1; --l) {
+    const uint8_t *t = tags[l].data();
+    const size_t n = tags[l].size();
+    size_t i = 0;
+    while (i < n) {
+      if (i + 8 <= n && (i & 7) == 0) {  // skip untagged words
+        uint64_t w;
+        memcpy(&w, t + i, 8);
+        if (!w) {
+          i += 8;
+          continue;
+        }
+      }
+      if (t[i]) {
+        const int y = (int)(i / Nx[l]), x = (int)(i % Nx[l]);
+        tags[l - 1][(size_t)(y / r) * Nx[l - 1] + x / r] = 1;
+      }
+      ++i;
+    }
+  }
   std::vector<vlbm_box> boxes;
   std::vector<uint8_t> cov((size_t)Nx[0] * Ny[0], 1);
   for (int l = 0; l + 1 < ML; ++l) {
@@ -1417,6 +1482,7 @@ vlbm_status vlbm_tag_and_regrid(vlbm_ctx *c, double thr, int buffer, int min_box
         memset(&ncov[(size_t)y * Nx[l + 1] + boxes[b].i0], 1, boxes[b].nx);
     cov.swap(ncov);
   }
+  tm.mark("cluster");
   return vlbm_regrid(c, boxes.data(), (int)boxes.size());
 }
 
@@ -1697,6 +1763,13 @@ vlbm_status vlbm_autotune(vlbm_ctx *c, int steps_per_trial, int *tile_cells, int
 }
 
 long vlbm_steps(const vlbm_ctx *c) { return c ? c->coarse_steps : -1; }
+
+long vlbm_active_cells(const vlbm_ctx *c, int level) {
+  if (!c || !c->have_hierarchy || level < 0 || level >= kMaxLevels || !c->lv[level].present) return 0;
+  long n = 0;
+  for (const Tile &t : c->lv[level].tiles) n += (long)t.w * t.h;
+  return n;
+}
 
 vlbm_status vlbm_sync(vlbm_ctx *c) {
   if (!c) return fail(VLBM_EINVAL, "null context");

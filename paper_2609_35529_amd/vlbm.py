@@ -20,6 +20,16 @@ LIB_PATH = os.path.join(HERE, "libvlbm.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libvlbm.so is not built ({LIB_PATH}); run `python -m paper_2609_35529_amd.build`")
 
+# One HIP runtime per process: PyTorch ships its own libamdhip64 (same SONAME as
+# the system one). Loading torch first makes libvlbm bind to that already-loaded
+# runtime, so the streams torch hands over are streams of the runtime that
+# launches the kernels; loading libvlbm first would put two runtimes in the
+# process.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    torch = None
+
 _lib = C.CDLL(LIB_PATH)
 
 VLBM_OK, VLBM_EINVAL, VLBM_ENOMEM, VLBM_ENEST, VLBM_EUNSTABLE, VLBM_EDEVICE, VLBM_ESTATE = (
@@ -78,6 +88,7 @@ vlbm_batch_advance = _sig("vlbm_batch_advance", _st, [C.POINTER(_P), C.POINTER(C
 vlbm_set_tuning = _sig("vlbm_set_tuning", _st, [_P, C.c_int, C.c_int])
 vlbm_autotune = _sig("vlbm_autotune", _st, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)])
 vlbm_steps = _sig("vlbm_steps", C.c_long, [_P])
+vlbm_active_cells = _sig("vlbm_active_cells", C.c_long, [_P, C.c_int])
 vlbm_sync = _sig("vlbm_sync", _st, [_P])
 vlbm_last_error = _sig("vlbm_last_error", C.c_char_p, [])
 
@@ -86,7 +97,7 @@ EXPORTED = ["vlbm_create", "vlbm_destroy", "vlbm_bind_pool", "vlbm_footprint_byt
             "vlbm_get_state", "vlbm_get_populations", "vlbm_conserved_totals", "vlbm_regrid",
             "vlbm_tag", "vlbm_tag_and_regrid", "vlbm_get_boxes", "vlbm_check_health",
             "vlbm_save", "vlbm_load", "vlbm_batch_advance", "vlbm_set_tuning", "vlbm_autotune",
-            "vlbm_steps", "vlbm_sync", "vlbm_last_error"]
+            "vlbm_steps", "vlbm_active_cells", "vlbm_sync", "vlbm_last_error"]
 
 
 class VLBMError(RuntimeError):
@@ -255,6 +266,9 @@ class Solver:
 
     def steps(self):
         return vlbm_steps(self._h)
+
+    def active_cells(self, level):
+        return vlbm_active_cells(self._h, int(level))
 
     def set_tuning(self, tile_cells, flags=0):
         check(vlbm_set_tuning(self._h, int(tile_cells), int(flags)))
