@@ -145,7 +145,9 @@ vlbm_status vlbm_conserved_totals(vlbm_ctx *ctx, double totals[4], double ledger
 
 /* Replace the hierarchy by boxes, moving the state conservatively: merge
  * exiting cells finest level first (eq. amr-merge), then split entering cells
- * coarsest level first (eqs. amr-slope, amr-split). Synchronises. */
+ * coarsest level first (eqs. amr-slope, amr-split). Every interface of the
+ * new hierarchy restarts its temporal reconstruction: the first coarse-to-fine
+ * hand-off after a regrid has no temporal slope. Synchronises. */
 vlbm_status vlbm_regrid(vlbm_ctx *ctx, const vlbm_box *boxes, int nboxes);
 
 /* Density-gradient tags of active level-l cells:
@@ -175,16 +177,22 @@ vlbm_status vlbm_load(vlbm_ctx *ctx, const void *buf, size_t bytes);
 
 /* Advance several contexts together, n_steps[i] coarse steps each, with the
  * phases of all contexts merged into shared launches. All contexts must use
- * the same stream and precision. */
+ * the same stream, precision and refinement ratio, and none may have fused
+ * sub-steps (tuning flag 16) in effect: VLBM_EINVAL otherwise. */
 vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nctx);
 
 /* Launch tuning (no effect on results, which are identical for every
  * setting): tile_cells is the largest number of cells one workgroup advances
  * (64..2^20); flags: 1 non-temporal stores, 2 two cells per thread,
- * 4 XCD-contiguous workgroup order. Rebuilds the launch tables. */
+ * 4 XCD-contiguous workgroup order, 16 fused sub-steps: with r = 2 and at
+ * least two levels, one launch advances the finest level by both sub-steps of
+ * its parent's step, the intermediate time level kept in LDS (temporal
+ * blocking of the sub-cycling of Sec. 3). Rebuilds the launch tables; the
+ * hierarchy and the time history are kept. VLBM_EINVAL for other values. */
 vlbm_status vlbm_set_tuning(vlbm_ctx *ctx, int tile_cells, int flags);
 
-/* Autotuner: time tile sizes {128, 256, 512, 1024} x workgroup orders on real
+/* Autotuner: time tile sizes {128, 256, 512, 1024} x workgroup orders (x fused
+ * sub-steps on or off, where they apply) on real
  * coarse steps of this context (every trial advances the solution by
  * 1 + steps_per_trial coarse steps) and keep the fastest. The choice is cached
  * per geometry (base grid, ratio, precision, boxes) for the process, so a

@@ -28,7 +28,9 @@
  * sub-step k, i.e. post-collision values at its start; the first cycle after an
  * interface appears has no older coarse sample, so prev := out (slope 0); the
  * tangential slope uses the cells at L0 -+ tau when they are active at the
- * same level, else sigma = 0; relaxation is evaluated as f + 2 beta (feq - f);
+ * same level, else sigma = 0; after a regrid every interface restarts its
+ * temporal reconstruction (slope 0 on the first cycle); relaxation is
+ * evaluated as f + 2 beta (feq - f);
  * merges run finest level first and splits coarsest level first; split slopes
  * use neighbours covered at that level in the new hierarchy that hold data.
  *
@@ -714,10 +716,13 @@ int orc_regrid(orc *o, const int *boxes, int nboxes) {
           for (int a = 0; a < r; ++a) o->pok[l + 1][cidx(o, l + 1, px * r + a, py * r + b)] = 0;
       }
   }
-  /* 3. adopt the new coverage; previous-step samples survive only on cells
-   *    active both before and after. */
+  /* 3. adopt the new coverage. A regrid rebuilds every interface, and each
+   *    interface starts its temporal reconstruction afresh: no cell keeps a
+   *    previous-step sample, so the first hand-off after a regrid has no
+   *    temporal slope. */
   for (int l = 0; l < L; ++l) {
     memcpy(o->cov[l], ncov[l], (size_t)o->Nx[l] * o->Ny[l]);
+    memset(o->pok[l], 0, (size_t)o->Nx[l] * o->Ny[l]);
     free(ncov[l]);
   }
   return 0;

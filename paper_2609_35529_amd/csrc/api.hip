@@ -173,12 +173,18 @@ struct Level {
   std::vector<Task> tasks;
   Tile *dtiles = nullptr;
   Task *dtasks = nullptr;
+  // fused two-sub-step launch (finest level, r = 2): tiles of at most
+  // FUSE_SIDE x FUSE_SIDE cells and their task lists
+  std::vector<Tile> ftiles;
+  std::vector<Task> ftasks;
+  Tile *dftiles = nullptr;
+  Task *dftasks = nullptr;
   double *dacc = nullptr;       // reflux accumulators of ring cells of this level
   int nacc = 0;
   double *dledger = nullptr;
   int nledger = 0;
   double *dpartial = nullptr;
-  long steps = 0;
+  long steps = 0;  // buffer flips so far; its parity selects the current buffer
   std::unordered_map<int64_t, int> acc_slot;  // (cell, q) of a ring cell -> slot
 
   int64_t off(int x, int y) const {
@@ -217,6 +223,7 @@ struct vlbm_ctx {
   LevelDesc *ddesc = nullptr;
   Segment *dseg = nullptr;
   long table_base = 0;
+  long flips[kMaxLevels] = {};  // buffer flips of each level per coarse step
   bool use_graphs = false;
   hipGraphExec_t graph = nullptr;  // two coarse steps from an even table parity
   long graph_key = -1;
@@ -257,6 +264,8 @@ void free_level(vlbm_ctx *c, Level &L) {
   c->mem.release(L.dstatus);
   c->mem.release(L.dtiles);
   c->mem.release(L.dtasks);
+  c->mem.release(L.dftiles);
+  c->mem.release(L.dftasks);
   c->mem.release(L.dacc);
   c->mem.release(L.dledger);
   c->mem.release(L.dpartial);
@@ -340,9 +349,235 @@ void frame_of(const vlbm_params &p, size_t esz, const Geometry &g, int l, Level 
 size_t level_bytes(const Level &L, size_t esz) { return (size_t)L.plane * 16 * esz; }
 
 // Build coverage, check nesting, build status, tiles and tasks for all levels.
+// What fills the slot from which active cell (x, y) of level l pulls f_q
+// (t.kind == T_NONE: an active cell of the same level, read in place). t.dst is
+// the slot's element offset; slots of BC and REFLUX tasks are assigned by the
+// caller.
+vlbm_status ghost_task(const vlbm_ctx *c, int l, int x, int y, int q, Task &t) {
+  const vlbm_params &p = c->p;
+  const int r = p.r;
+  const Level &L = c->lv[l];
+  const int sx = x - CX[q], sy = y - CY[q];
+  int wx = sx, wy = sy;
+  t = Task{};
+  t.kind = T_NONE;
+  t.q = q;
+  t.dst = (int32_t)L.off(sx, sy);
+  t.n0 = t.n1 = -1;
+  if (!c->wrap(l, wx, wy)) {
+    const int side = q;  // +x enters through west (0), -x east (1), +y south (2), -y north (3)
+    const int bc = p.bc[side];
+    t.kind = (bc == VLBM_BC_OUTFLOW ? T_OUTFLOW : bc == VLBM_BC_REFLECT ? T_REFLECT : T_INFLOW) | TASK_LEDGER;
+    t.src = (int32_t)L.off(x, y);
+    t.n0 = side;
+  } else if (c->covered(l + 1, wx * r, wy * r)) {
+    t.kind = T_REFLUX;
+  } else if (c->covered(l, wx, wy)) {
+    if (wx != sx || wy != sy) {
+      t.kind = T_COPY;
+      t.src = (int32_t)L.off(wx, wy);
+    }
+  } else {
+    if (l == 0) return fail(VLBM_ENEST, "internal: level-0 cell without source");
+    const Level &PL = c->lv[l - 1];
+    int px = wx / r, py = wy / r;
+    if (!c->active(l - 1, px, py))
+      return fail(VLBM_ENEST, "level %d cell (%d,%d): parent ring cell inactive", l, x, y);
+    t.kind = T_RECON;
+    t.src = (int32_t)PL.off(px, py);
+    int tx = q < 2 ? 0 : 1, ty = q < 2 ? 1 : 0;
+    t.j = q < 2 ? (y - r * py) : (x - r * px);
+    int mx = px - tx, my = py - ty, qx = px + tx, qy = py + ty;
+    bool have = c->wrap(l - 1, mx, my) && c->wrap(l - 1, qx, qy) && c->active(l - 1, mx, my) &&
+                c->active(l - 1, qx, qy);
+    if (have) {
+      t.n0 = (int32_t)PL.off(mx, my);
+      t.n1 = (int32_t)PL.off(qx, qy);
+    }
+  }
+  return VLBM_OK;
+}
+
+// Lists of the fused two-sub-step launch of level l (the finest, r = 2).
+// Active cells are cut into rectangles of at most FUSE_SIDE x FUSE_SIDE cells
+// aligned to a FUSE_SIDE grid. Per tile, in this order:
+//   ntask  sub-step-1 ghost tasks of every cell whose sub-step-1 value the tile
+//          needs (its own cells, which book the ledger, and the sources of its
+//          ring positions, which do not);
+//   nring  ring positions holding an active cell (T_RING: global source cell,
+//          the periodic partner for a wrapped position; LDS destination);
+//   nk2    sub-step-2 ghost values of the remaining ring positions (TASK_K2:
+//          boundary tasks read the tile cell's LDS value, RECON reads the parent);
+//   ncap   reflux captures whose first cell R_0 lies in the tile (T_CAPTURE2).
+// A ring position touches exactly one tile cell, which pulls exactly one
+// population from it, so every ring entry is that one (cell, q) pair.
+vlbm_status build_fused(vlbm_ctx *c, int l, const std::unordered_map<int64_t, int> &bc_slot,
+                        const std::vector<std::pair<int64_t, Task>> &caps) {
+  Level &L = c->lv[l];
+  const int F = FUSE_SIDE;
+  // rectangles: per row, runs of active cells cut at the FUSE_SIDE grid; equal
+  // runs on consecutive rows of one FUSE_SIDE band stack into one rectangle
+  struct Rect { int x0, y0, w, h; };
+  std::vector<Rect> rects;
+  std::map<std::pair<int, int>, int> open;  // (x0, w) -> index in rects (current band)
+  for (int y = L.fy0 + 1; y < L.fy0 + L.fh - 1; ++y) {
+    if ((y - L.fy0 - 1) % F == 0) open.clear();
+    std::map<std::pair<int, int>, int> next;
+    int x = L.fx0 + 1;
+    const int xe = L.fx0 + L.fw - 1;
+    while (x < xe) {
+      if (L.status[L.fidx(x, y)] != 1) {
+        ++x;
+        continue;
+      }
+      const int xa = x;
+      const int cut = L.fx0 + 1 + ((x - L.fx0 - 1) / F + 1) * F;
+      while (x < xe && x < cut && L.status[L.fidx(x, y)] == 1) ++x;
+      const std::pair<int, int> key{xa, x - xa};
+      auto it = open.find(key);
+      if (it != open.end() && rects[it->second].y0 + rects[it->second].h == y) {
+        rects[it->second].h += 1;
+        next[key] = it->second;
+      } else {
+        rects.push_back({xa, y, x - xa, 1});
+        next[key] = (int)rects.size() - 1;
+      }
+    }
+    open.swap(next);
+  }
+  std::sort(rects.begin(), rects.end(), [](const Rect &a, const Rect &b) {
+    return a.y0 != b.y0 ? a.y0 < b.y0 : a.x0 < b.x0;
+  });
+  std::vector<int32_t> owner(L.cov.size(), -1);
+  for (size_t t = 0; t < rects.size(); ++t)
+    for (int yy = 0; yy < rects[t].h; ++yy)
+      for (int xx = 0; xx < rects[t].w; ++xx) owner[L.fidx(rects[t].x0 + xx, rects[t].y0 + yy)] = (int32_t)t;
+  std::vector<std::vector<Task>> capt(rects.size());
+  for (const auto &ct : caps) {
+    const int x = (int)(ct.first % L.Nx), y = (int)(ct.first / L.Nx);
+    const int t = owner[L.fidx(x, y)];
+    const Rect &R = rects[t];
+    const int rw = R.w + 2;
+    Task u = ct.second;
+    u.kind = T_CAPTURE2;
+    u.n1 = (y - R.y0 + 1) * rw + (x - R.x0 + 1);
+    u.j = ct.second.q < 2 ? rw : 1;
+    // R_1 is the tile's or a ring cell (adjacent to R_0), so it is in the window
+    const int x1 = x + (u.q < 2 ? 0 : 1), y1 = y + (u.q < 2 ? 1 : 0);
+    if (x1 < R.x0 - 1 || x1 > R.x0 + R.w || y1 < R.y0 - 1 || y1 > R.y0 + R.h)
+      return fail(VLBM_ENEST, "internal: capture cells outside the fused window");
+    capt[t].push_back(u);
+  }
+  std::vector<uint8_t> mark(L.cov.size(), 0);
+  std::vector<size_t> marked;
+  L.ftiles.clear();
+  L.ftasks.clear();
+  for (size_t ti = 0; ti < rects.size(); ++ti) {
+    const Rect &R = rects[ti];
+    const int rw = R.w + 2;
+    auto lds = [&](int x, int y) { return (int32_t)((y - R.y0 + 1) * rw + (x - R.x0 + 1)); };
+    auto in_tile = [&](int x, int y) { return x >= R.x0 && y >= R.y0 && x < R.x0 + R.w && y < R.y0 + R.h; };
+    std::vector<std::pair<int, int>> src_cells;  // ring sources outside the tile
+    std::vector<Task> ring, k2;
+    for (int y = R.y0; y < R.y0 + R.h; ++y)
+      for (int x = R.x0; x < R.x0 + R.w; ++x) {
+        if (x > R.x0 && x < R.x0 + R.w - 1 && y > R.y0 && y < R.y0 + R.h - 1) continue;
+        for (int q = 0; q < 4; ++q) {
+          const int sx = x - CX[q], sy = y - CY[q];
+          if (in_tile(sx, sy)) continue;
+          Task t{};
+          vlbm_status gs = ghost_task(c, l, x, y, q, t);
+          if (gs) return gs;
+          const int kind = t.kind == T_NONE ? T_NONE : t.kind & 0xFF;
+          Task u = t;
+          u.dst = lds(sx, sy);
+          if (kind == T_NONE || kind == T_COPY) {
+            int wx = sx, wy = sy;
+            c->wrap(l, wx, wy);
+            u.kind = T_RING;
+            u.src = (int32_t)L.off(wx, wy);
+            ring.push_back(u);
+            if (!in_tile(wx, wy)) {
+              const size_t fi = L.fidx(wx, wy);
+              if (!mark[fi]) {
+                mark[fi] = 1;
+                marked.push_back(fi);
+                src_cells.push_back({wx, wy});
+              }
+            }
+          } else if (kind == T_RECON) {
+            u.kind = T_RECON | TASK_K2;
+            k2.push_back(u);
+          } else if (kind == T_OUTFLOW || kind == T_REFLECT || kind == T_INFLOW) {
+            auto it = bc_slot.find(((int64_t)y * L.Nx + x) * 4 + q);
+            if (it == bc_slot.end()) return fail(VLBM_ENEST, "internal: no ledger slot for a fused boundary task");
+            u.kind = kind | TASK_K2 | TASK_LEDGER;
+            u.src = lds(x, y);
+            u.slot = it->second;
+            k2.push_back(u);
+          } else {
+            return fail(VLBM_ENEST, "internal: reflux slot on the finest level");
+          }
+        }
+      }
+    for (size_t fi : marked) mark[fi] = 0;
+    marked.clear();
+    // sub-step-1 ghost tasks: tile cells (with ledger) then ring sources (without)
+    Tile tl{};
+    tl.off0 = (int32_t)L.off(R.x0, R.y0);
+    tl.w = R.w;
+    tl.h = R.h;
+    tl.task0 = (int32_t)L.ftasks.size();
+    auto add_cell = [&](int x, int y, bool own) -> vlbm_status {
+      const size_t ci = L.fidx(x, y);
+      if (L.status[ci - 1] == 1 && L.status[ci + 1] == 1 && L.status[ci - L.fw] == 1 &&
+          L.status[ci + L.fw] == 1)
+        return VLBM_OK;
+      for (int q = 0; q < 4; ++q) {
+        Task t{};
+        vlbm_status gs = ghost_task(c, l, x, y, q, t);
+        if (gs) return gs;
+        if (t.kind == T_NONE) continue;
+        const int kind = t.kind & 0xFF;
+        if (kind == T_REFLUX) return fail(VLBM_ENEST, "internal: reflux slot on the finest level");
+        if (kind == T_OUTFLOW || kind == T_REFLECT || kind == T_INFLOW) {
+          auto it = bc_slot.find(((int64_t)y * L.Nx + x) * 4 + q);
+          if (it == bc_slot.end()) return fail(VLBM_ENEST, "internal: no ledger slot for a fused boundary task");
+          t.slot = it->second;
+          if (!own) t.kind &= ~TASK_LEDGER;
+        }
+        L.ftasks.push_back(t);
+      }
+      return VLBM_OK;
+    };
+    for (int y = R.y0; y < R.y0 + R.h; ++y)
+      for (int x = R.x0; x < R.x0 + R.w; ++x) {
+        vlbm_status as = add_cell(x, y, true);
+        if (as) return as;
+      }
+    for (auto &sc : src_cells) {
+      vlbm_status as = add_cell(sc.first, sc.second, false);
+      if (as) return as;
+    }
+    tl.ntask = (int32_t)L.ftasks.size() - tl.task0;
+    tl.nring = (int32_t)ring.size();
+    tl.nk2 = (int32_t)k2.size();
+    tl.ncap = (int32_t)capt[ti].size();
+    L.ftasks.insert(L.ftasks.end(), ring.begin(), ring.end());
+    L.ftasks.insert(L.ftasks.end(), k2.begin(), k2.end());
+    L.ftasks.insert(L.ftasks.end(), capt[ti].begin(), capt[ti].end());
+    if ((R.w + 2) * (R.h + 2) > FUSE_POS || R.w * R.h + tl.nring > 4 * 256)
+      return fail(VLBM_ENEST, "internal: fused tile too large");
+    L.ftiles.push_back(tl);
+  }
+  return VLBM_OK;
+}
+
 vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
   const vlbm_params &p = c->p;
   const int r = p.r;
+  int nlev = 0;
+  while (nlev < kMaxLevels && c->lv[nlev].present) ++nlev;
   // coverage
   for (int l = 0; l < kMaxLevels && c->lv[l].present; ++l) {
     Level &L = c->lv[l];
@@ -472,6 +707,11 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
     std::vector<std::pair<int, Task>> tk;  // (tile, task)
     L.acc_slot.clear();
     L.nledger = 0;
+    // the finest level of a two-level-or-deeper hierarchy with r = 2 also gets
+    // the lists of the fused two-sub-step launch
+    const bool fuse = (c->step_flags & STEP_FUSE2) && l >= 1 && l == nlev - 1 && r == 2;
+    std::unordered_map<int64_t, int> bc_slot;     // (cell, q) -> ledger slot
+    std::vector<std::pair<int64_t, Task>> caps;   // (cell R_0 as y * Nx + x, capture)
     const int fw = L.fw;
     for (int y = L.fy0 + 1; y < L.fy0 + L.fh - 1; ++y)
       for (int x = L.fx0 + 1; x < L.fx0 + L.fw - 1; ++x) {
@@ -484,52 +724,21 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
           continue;
         const int tile = owner[ci];
         for (int q = 0; q < 4; ++q) {
-          int sx = x - CX[q], sy = y - CY[q];
-          int wx = sx, wy = sy;
           Task t{};
-          t.q = q;
-          t.dst = (int32_t)L.off(sx, sy);
-          t.n0 = t.n1 = -1;
-          if (!c->wrap(l, wx, wy)) {
-            const int side = q;  // +x enters through west (0), -x east (1), +y south (2), -y north (3)
-            const int bc = p.bc[side];
-            t.kind = bc == VLBM_BC_OUTFLOW ? T_OUTFLOW : bc == VLBM_BC_REFLECT ? T_REFLECT : T_INFLOW;
-            t.src = (int32_t)L.off(x, y);
-            t.n0 = side;
+          vlbm_status gs = ghost_task(c, l, x, y, q, t);
+          if (gs) return gs;
+          if (t.kind == T_NONE) continue;
+          const int kind = t.kind & 0xFF;
+          if (kind == T_OUTFLOW || kind == T_REFLECT || kind == T_INFLOW) {
             t.slot = L.nledger++;
-            tk.push_back({tile, t});
-          } else if (c->covered(l + 1, wx * r, wy * r)) {
+            if (fuse) bc_slot[((int64_t)y * L.Nx + x) * 4 + q] = t.slot;
+          } else if (kind == T_REFLUX) {
             int64_t key = ((int64_t)y * L.Nx + x) * 4 + q;
             int slot = (int)L.acc_slot.size();
             L.acc_slot[key] = slot;
-            t.kind = T_REFLUX;
             t.slot = slot;
-            tk.push_back({tile, t});
-          } else if (c->covered(l, wx, wy)) {
-            if (wx != sx || wy != sy) {
-              t.kind = T_COPY;
-              t.src = (int32_t)L.off(wx, wy);
-              tk.push_back({tile, t});
-            }
-          } else {
-            if (l == 0) return fail(VLBM_ENEST, "internal: level-0 cell without source");
-            const Level &PL = c->lv[l - 1];
-            int px = wx / r, py = wy / r;
-            if (!c->active(l - 1, px, py))
-              return fail(VLBM_ENEST, "level %d cell (%d,%d): parent ring cell inactive", l, x, y);
-            t.kind = T_RECON;
-            t.src = (int32_t)PL.off(px, py);
-            int tx = q < 2 ? 0 : 1, ty = q < 2 ? 1 : 0;
-            t.j = q < 2 ? (y - r * py) : (x - r * px);
-            int mx = px - tx, my = py - ty, qx = px + tx, qy = py + ty;
-            bool have = c->wrap(l - 1, mx, my) && c->wrap(l - 1, qx, qy) &&
-                        c->active(l - 1, mx, my) && c->active(l - 1, qx, qy);
-            if (have) {
-              t.n0 = (int32_t)PL.off(mx, my);
-              t.n1 = (int32_t)PL.off(qx, qy);
-            }
-            tk.push_back({tile, t});
           }
+          tk.push_back({tile, t});
         }
       }
     // captures: values leaving level l towards the parent's ring cells
@@ -562,6 +771,7 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
               t.slot = it->second;
               cap[it->second] = tk.size();
               tk.push_back({owner[L.fidx(x, y)], t});
+              if (fuse) caps.push_back({(int64_t)y * L.Nx + x, t});
               count.push_back(1);
             } else {
               Task &t = tk[ct->second].second;
@@ -590,6 +800,12 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
       L.tasks.push_back(tk[i].second);
     }
     L.nacc = (int)L.acc_slot.size();
+    L.ftiles.clear();
+    L.ftasks.clear();
+    if (fuse) {
+      vlbm_status fs = build_fused(c, l, bc_slot, caps);
+      if (fs) return fs;
+    }
   }
   return VLBM_OK;
 }
@@ -612,6 +828,14 @@ vlbm_status upload_level(vlbm_ctx *c, Level &L, bool alloc_buffers) {
   L.dpartial = static_cast<double *>(M.alloc(sizeof(double) * 4 * std::max<size_t>(1, L.tiles.size())));
   if (!L.dstatus || !L.dtiles || !L.dtasks || !L.dacc || !L.dledger || !L.dpartial)
     return fail(VLBM_ENOMEM, "level tables");
+  if (!L.ftiles.empty()) {
+    L.dftiles = static_cast<Tile *>(M.alloc(sizeof(Tile) * L.ftiles.size()));
+    L.dftasks = static_cast<Task *>(M.alloc(sizeof(Task) * std::max<size_t>(1, L.ftasks.size())));
+    if (!L.dftiles || !L.dftasks) return fail(VLBM_ENOMEM, "fused level tables");
+    HIPCHK(hipMemcpyAsync(L.dftiles, L.ftiles.data(), sizeof(Tile) * L.ftiles.size(), hipMemcpyHostToDevice, c->stream));
+    if (!L.ftasks.empty())
+      HIPCHK(hipMemcpyAsync(L.dftasks, L.ftasks.data(), sizeof(Task) * L.ftasks.size(), hipMemcpyHostToDevice, c->stream));
+  }
   HIPCHK(hipMemcpyAsync(L.dstatus, L.status.data(), L.status.size(), hipMemcpyHostToDevice, c->stream));
   if (!L.tiles.empty())
     HIPCHK(hipMemcpyAsync(L.dtiles, L.tiles.data(), sizeof(Tile) * L.tiles.size(), hipMemcpyHostToDevice, c->stream));
@@ -624,20 +848,26 @@ vlbm_status upload_level(vlbm_ctx *c, Level &L, bool alloc_buffers) {
 }
 
 // Phases of one coarse step in execution order: level l+1 takes r steps
-// before each step of level l (finest first).
-void schedule(int l, int k, int nlev, int r, std::vector<std::pair<int, int>> &out) {
-  if (l + 1 < nlev)
-    for (int kk = 1; kk <= r; ++kk) schedule(l + 1, kk, nlev, r, out);
+// before each step of level l (finest first). With `fused` the finest level's
+// r = 2 sub-steps of one parent step form one phase, k = 0.
+void schedule(int l, int k, int nlev, int r, std::vector<std::pair<int, int>> &out,
+              bool fused = false) {
+  if (l + 1 < nlev) {
+    if (fused && l + 2 == nlev)
+      out.push_back({l + 1, 0});
+    else
+      for (int kk = 1; kk <= r; ++kk) schedule(l + 1, kk, nlev, r, out, fused);
+  }
   out.push_back({l, k});
 }
 
-long ipow(int r, int l) {
-  long s = 1;
-  for (int i = 0; i < l; ++i) s *= r;
-  return s;
+// Whether the finest level runs fused two-sub-step launches.
+bool fused_active(const vlbm_ctx *c) {
+  return (c->step_flags & STEP_FUSE2) && c->nlev >= 2 && !c->lv[c->nlev - 1].ftiles.empty();
 }
 
-LevelDesc make_desc(const vlbm_ctx *c, int l, const long *st) {
+
+LevelDesc make_desc(const vlbm_ctx *c, int l, const long *st, bool fused = false) {
   const Level &L = c->lv[l];
   LevelDesc a{};
   a.src = L.buf[st[l] & 1];
@@ -649,13 +879,13 @@ LevelDesc make_desc(const vlbm_ctx *c, int l, const long *st) {
     a.pplane = P.plane;
     a.acc_out = P.dacc;
   }
-  a.tiles = L.dtiles;
-  a.tasks = L.dtasks;
+  a.tiles = fused ? L.dftiles : L.dtiles;
+  a.tasks = fused ? L.dftasks : L.dtasks;
   a.acc_in = L.dacc;
   a.ledger = L.dledger;
   a.plane = L.plane;
   a.pitch = L.pitch;
-  a.ntiles = (int32_t)L.tiles.size();
+  a.ntiles = (int32_t)(fused ? L.ftiles.size() : L.tiles.size());
   a.r = c->p.r;
   a.rr = (double)(c->p.r * c->p.r);
   a.w2 = L.dx * L.dx;
@@ -678,8 +908,11 @@ void drop_graph(vlbm_ctx *c) {
 vlbm_status build_tables(vlbm_ctx *c) {
   drop_graph(c);
   c->phases.clear();
-  schedule(0, 1, c->nlev, c->p.r, c->phases);
+  schedule(0, 1, c->nlev, c->p.r, c->phases, fused_active(c));
   const size_t P = c->phases.size();
+  // buffer flips of each level per coarse step: one per phase
+  for (int l = 0; l < kMaxLevels; ++l) c->flips[l] = 0;
+  for (const auto &ph : c->phases) c->flips[ph.first] += 1;
   std::vector<LevelDesc> descs(2 * P);
   std::vector<Segment> segs(2 * P);
   c->mem.release(c->ddesc);
@@ -690,12 +923,13 @@ vlbm_status build_tables(vlbm_ctx *c) {
   c->phase_blocks.assign(P, 0);
   for (int e = 0; e < 2; ++e) {
     long st[kMaxLevels];
-    for (int l = 0; l < kMaxLevels; ++l) st[l] = c->lv[l].steps + e * ipow(c->p.r, l);
+    for (int l = 0; l < kMaxLevels; ++l) st[l] = c->lv[l].steps + e * c->flips[l];
     for (size_t p = 0; p < P; ++p) {
       const int l = c->phases[p].first;
-      descs[e * P + p] = make_desc(c, l, st);
+      const bool fused = c->phases[p].second == 0;
+      descs[e * P + p] = make_desc(c, l, st, fused);
       st[l] += 1;
-      const int nb = ((int)c->lv[l].tiles.size() + 7) / 8 * 8;
+      const int nb = ((int)(fused ? c->lv[l].ftiles.size() : c->lv[l].tiles.size()) + 7) / 8 * 8;
       segs[e * P + p] = {c->ddesc + e * P + p, 0, nb};
       c->phase_blocks[p] = nb;
     }
@@ -720,7 +954,7 @@ vlbm_status launch_coarse_step(vlbm_ctx *c, int e) {
     a.nseg = 0;
     a.nblocks = c->phase_blocks[p];
     a.first = c->phases[p].second == 1;
-    a.flags = c->step_flags;
+    a.flags = c->step_flags | (c->phases[p].second == 0 ? STEP_FUSED_PHASE : 0);
     a.ak = ak_of(c->phases[p].second, c->p.r);
     HIPCHK(launch_step(a, c->fp32, c->stream));
   }
@@ -728,7 +962,7 @@ vlbm_status launch_coarse_step(vlbm_ctx *c, int e) {
 }
 
 void count_steps(vlbm_ctx *c, long n) {
-  for (int l = 0; l < c->nlev; ++l) c->lv[l].steps += n * ipow(c->p.r, l);
+  for (int l = 0; l < c->nlev; ++l) c->lv[l].steps += n * c->flips[l];
   c->coarse_steps += n;
 }
 
@@ -909,7 +1143,11 @@ vlbm_status carry_ledgers(vlbm_ctx *c) {
 // so their first hand-off has no temporal slope. A split slope uses a
 // neighbour only if it is covered at that level in the new hierarchy and holds
 // data (i.e. it is not a hole both before and after).
-vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
+//
+// With restart_history every level that has a finer level gets its current
+// values copied into its other buffer, so every interface of the new hierarchy
+// restarts its temporal reconstruction (no temporal slope on the first cycle).
+vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes, bool restart_history) {
   PhaseTimer tm("regrid");
   Geometry g;
   vlbm_status st = check_boxes(c->p, boxes, nboxes, g);
@@ -929,6 +1167,7 @@ vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
   t->p = c->p;
   t->esz = c->esz;
   t->tile_cells = c->tile_cells;
+  t->step_flags = c->step_flags;
   int nlev = 0;
   for (int l = 0; l < kMaxLevels; ++l) {
     frame_of(c->p, c->esz, g, l, t->lv[l]);
@@ -1061,6 +1300,12 @@ vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
     a.nops = (int32_t)ops.size();
     HIPCHK(launch_split(a, c->fp32, c->stream));
   }
+  if (restart_history)
+    for (int l = 0; l + 1 < nlev; ++l) {
+      Level &N = t->lv[l];
+      const int cur = (int)(N.steps & 1);
+      HIPCHK(hipMemcpyAsync(N.buf[cur ^ 1], N.buf[cur], level_bytes(N, c->esz), hipMemcpyDeviceToDevice, c->stream));
+    }
   if (hipStreamSynchronize(c->stream) != hipSuccess) return done(fail(VLBM_EDEVICE, "regrid kernels failed"));
   tm.mark("merge/copy/split");
   c->mem.release(dops);
@@ -1274,6 +1519,7 @@ vlbm_status vlbm_set_hierarchy(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
   t->p = c->p;
   t->esz = c->esz;
   t->tile_cells = c->tile_cells;
+  t->step_flags = c->step_flags;
   int nlev = 0;
   for (int l = 0; l < kMaxLevels; ++l) {
     frame_of(c->p, c->esz, g, l, t->lv[l]);
@@ -1424,7 +1670,7 @@ vlbm_status vlbm_get_boxes(vlbm_ctx *c, vlbm_box *boxes, int cap, int *nboxes) {
 
 vlbm_status vlbm_regrid(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
   if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "no hierarchy installed");
-  return regrid_impl(c, boxes, nboxes);
+  return regrid_impl(c, boxes, nboxes, true);
 }
 
 vlbm_status vlbm_tag_and_regrid(vlbm_ctx *c, double thr, int buffer, int min_box, int max_box) {
@@ -1605,6 +1851,8 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
     if (n_steps[i] < 0) return fail(VLBM_EINVAL, "negative step count");
     if (c->stream != c0->stream || c->p.precision != c0->p.precision || c->p.r != c0->p.r)
       return fail(VLBM_EINVAL, "batched contexts must share stream, precision and ratio");
+    if (fused_active(c))
+      return fail(VLBM_EINVAL, "context %d uses fused sub-steps, which batched launches do not take", i);
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == c) return fail(VLBM_EINVAL, "context %d listed twice", i);
   }
@@ -1695,13 +1943,15 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
 
 vlbm_status vlbm_set_tuning(vlbm_ctx *c, int tile_cells, int flags) {
   if (!c) return fail(VLBM_EINVAL, "null context");
-  if (tile_cells < 64 || tile_cells > (1 << 20) || (flags & ~(STEP_NT_STORES | STEP_TWO_CELLS | STEP_XCD_CONTIGUOUS)))
+  if (tile_cells < 64 || tile_cells > (1 << 20) ||
+      (flags & ~(STEP_NT_STORES | STEP_TWO_CELLS | STEP_XCD_CONTIGUOUS | STEP_FUSE2)))
     return fail(VLBM_EINVAL, "bad tuning (tile_cells %d, flags %d)", tile_cells, flags);
   c->tile_cells = tile_cells;
   c->step_flags = flags | (c->step_flags & STEP_F64_MATH);
   if (!c->have_hierarchy) return VLBM_OK;
-  std::vector<vlbm_box> boxes = c->boxes;  // same hierarchy, new tile decomposition
-  return regrid_impl(c, boxes.data(), (int)boxes.size());
+  // same hierarchy and time history, new tile decomposition
+  std::vector<vlbm_box> boxes = c->boxes;
+  return regrid_impl(c, boxes.data(), (int)boxes.size(), false);
 }
 
 // Tuning cache: one entry per geometry (base grid, ratio, precision, boxes).
@@ -1724,15 +1974,18 @@ vlbm_status vlbm_autotune(vlbm_ctx *c, int steps_per_trial, int *tile_cells, int
   vlbm_status st;
   if (hit == g_tuned.end()) {
     const int tiles[] = {128, 256, 512, 1024};
-    const int orders[] = {0, STEP_XCD_CONTIGUOUS};
+    const bool can_fuse = c->p.r == 2 && c->nlev >= 2;
+    const int orders[] = {0, STEP_XCD_CONTIGUOUS, STEP_FUSE2, STEP_FUSE2 | STEP_XCD_CONTIGUOUS};
+    const int norders = can_fuse ? 4 : 2;
     float best = 1e30f;
     std::pair<int, int> choice{c->tile_cells, c->step_flags};
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     for (int tcell : tiles)
-      for (int ord : orders) {
-        const int fl = (c->step_flags & ~(STEP_XCD_CONTIGUOUS | STEP_F64_MATH)) | ord;
+      for (int oi = 0; oi < norders; ++oi) {
+        const int ord = orders[oi];
+        const int fl = (c->step_flags & ~(STEP_XCD_CONTIGUOUS | STEP_FUSE2 | STEP_F64_MATH)) | ord;
         st = vlbm_set_tuning(c, tcell, fl);
         if (!st) st = advance_impl(c, 1);  // warm
         if (!st && hipEventRecord(e0, c->stream) != hipSuccess) st = fail(VLBM_EDEVICE, "event");

@@ -80,7 +80,8 @@ __device__ __forceinline__ void run_task(const LevelDesc &A, int first, double a
   T *S = static_cast<T *>(A.src);
   const int64_t P = A.plane;
   const int q = t.q;
-  switch (t.kind) {
+  const bool book = (t.kind & TASK_LEDGER) != 0;
+  switch (t.kind & 0xFF) {
     case T_COPY:
 #pragma unroll
       for (int k = 0; k < 4; ++k) S[(q * 4 + k) * P + t.dst] = S[(q * 4 + k) * P + t.src];
@@ -90,11 +91,12 @@ __device__ __forceinline__ void run_task(const LevelDesc &A, int first, double a
     case T_INFLOW: {
       const int side = t.n0;
       const int qo = q ^ 1;  // opposite population: +x <-> -x, +y <-> -y
+      const int kind = t.kind & 0xFF;
       double in[4];
-      if (t.kind == T_OUTFLOW) {
+      if (kind == T_OUTFLOW) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) in[k] = (double)S[(q * 4 + k) * P + t.src];
-      } else if (t.kind == T_REFLECT) {
+      } else if (kind == T_REFLECT) {
         const int kn = side < 2 ? 1 : 2;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -117,9 +119,11 @@ __device__ __forceinline__ void run_task(const LevelDesc &A, int first, double a
       for (int k = 0; k < 4; ++k) {
         const T vin = (T)in[k];
         S[(q * 4 + k) * P + t.dst] = vin;
-        const double out = (double)S[(qo * 4 + k) * P + t.src];
-        double l = L[k] + A.w2 * (double)vin;
-        L[k] = l + (-1.0) * (A.w2 * out);
+        if (book) {
+          const double out = (double)S[(qo * 4 + k) * P + t.src];
+          double l = L[k] + A.w2 * (double)vin;
+          L[k] = l + (-1.0) * (A.w2 * out);
+        }
       }
       break;
     }
@@ -274,9 +278,184 @@ __global__ __launch_bounds__(256) void step_kernel(StepLaunch Lc) {
   run_tile<T, C, NT, TWO>(*dp, b - first_block, nblocks, Lc.first, Lc.ak, Lc.flags);
 }
 
+// ---------------------------------------------------------------------------
+// Fused two-sub-step launch of the finest level (r = 2). One workgroup per
+// tile of at most FUSE_SIDE x FUSE_SIDE cells:
+//   1. sub-step-1 ghost values of the tile and of its one-cell ring go into the
+//      global ghost slots (neighbouring tiles write the same values);
+//   2. sub-step 1 of the tile and ring cells, rounded to the storage type, into
+//      LDS (position (cy+1)*(w+2) + cx+1, one LDS plane per population);
+//   3. sub-step-2 ghost values into the LDS ring positions, and the parent's
+//      reflux accumulators receive both sub-steps' outgoing values;
+//   4. sub-step 2 of the tile, pulled from LDS, stored to the next buffer.
+// The arithmetic and its rounding points are those of two separate launches,
+// so results are bit-identical; F(t + dt) never travels to HBM.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ void run_task_k2(const LevelDesc &A, double ak2, const Task &t,
+                                            T *F1, int np) {
+  const int q = t.q;
+  const int kind = t.kind & 0xFF;
+  if (kind == T_RECON) {
+    const T *C = static_cast<const T *>(A.pcur);
+    const T *Pv = static_cast<const T *>(A.pprev);
+    const int64_t P2 = A.pplane;
+    const double bj = (double)(2 * t.j - A.r + 1) / (double)(2 * A.r);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t pl = (q * 4 + k) * P2;
+      const double out = (double)C[pl + t.src];
+      const double prev = (double)Pv[pl + t.src];
+      double sigma = 0.0;
+      if (t.n0 >= 0 && t.n1 >= 0) sigma = minmod(out - (double)C[pl + t.n0], (double)C[pl + t.n1] - out);
+      const double B = out - prev;
+      double v = out + B * ak2;
+      v = v + sigma * bj;
+      F1[(q * 4 + k) * np + t.dst] = (T)v;
+    }
+    return;
+  }
+  // boundary kinds: the source is the tile cell's own sub-step-1 value in LDS
+  const int side = t.n0;
+  const int qo = q ^ 1;
+  double in[4];
+  if (kind == T_OUTFLOW) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) in[k] = (double)F1[(q * 4 + k) * np + t.src];
+  } else if (kind == T_REFLECT) {
+    const int kn = side < 2 ? 1 : 2;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double w = (double)F1[(qo * 4 + k) * np + t.src];
+      in[k] = (k == kn) ? -w : w;
+    }
+  } else {
+    double W[4], f[16];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      W[k] = side == 0 ? A.win[0][k] : side == 1 ? A.win[1][k] : side == 2 ? A.win[2][k] : A.win[3][k];
+    equilibrium(W, A.gm1, A.h, f);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      in[k] = (double)(T)(q == 0 ? f[k] : q == 1 ? f[4 + k] : q == 2 ? f[8 + k] : f[12 + k]);
+  }
+  double *L = A.ledger + 4 * (int64_t)t.slot;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const T vin = (T)in[k];
+    F1[(q * 4 + k) * np + t.dst] = vin;
+    const double out = (double)F1[(qo * 4 + k) * np + t.src];
+    double l = L[k] + A.w2 * (double)vin;
+    L[k] = l + (-1.0) * (A.w2 * out);
+  }
+}
+
+template <class T, class C>
+__device__ __forceinline__ void fused_tile(const LevelDesc &A, int tid) {
+  __shared__ T F1[16 * FUSE_POS];
+  const int ntiles = A.ntiles;
+  if (tid >= ntiles) return;
+  const Tile tl = A.tiles[tid];
+  const T *__restrict__ s = static_cast<const T *>(A.src);
+  T *__restrict__ d = static_cast<T *>(A.dst);
+  const int64_t plane = A.plane;
+  const int pitch = A.pitch;
+  const C gm1 = (C)A.gm1, h = (C)A.h, tb = (C)A.tb;
+  const int w = tl.w, np = FUSE_POS, rw = w + 2;
+  const double ak1 = (double)(1 - A.r) / (double)(2 * A.r);   // k = 1
+  const double ak2 = (double)(3 - A.r) / (double)(2 * A.r);   // k = 2
+  const Task *tk = A.tasks + tl.task0;
+  // 1. sub-step-1 ghost values (global)
+  for (int i = threadIdx.x; i < tl.ntask; i += blockDim.x) run_task<T>(A, 1, ak1, tk[i]);
+  __syncthreads();
+  // 2. sub-step 1 of tile and ring cells into LDS
+  const int ncell = w * tl.h;
+  const Task *ring = tk + tl.ntask;
+  for (int i = threadIdx.x; i < ncell + tl.nring; i += blockDim.x) {
+    int64_t o;
+    int lp;
+    if (i < ncell) {
+      const int cy = i / w, cx = i - cy * w;
+      o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
+      lp = (cy + 1) * rw + cx + 1;
+    } else {
+      o = ring[i - ncell].src;
+      lp = ring[i - ncell].dst;
+    }
+    C g[16];
+    pull<T, C>(s, plane, pitch, o, g);
+    relax<C>(g, gm1, h, tb);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) F1[k * np + lp] = (T)g[k];
+  }
+  __syncthreads();
+  // 3. sub-step-2 ghost values into LDS; both sub-steps' reflux captures
+  const Task *k2 = ring + tl.nring;
+  const Task *cap = k2 + tl.nk2;
+  for (int i = threadIdx.x; i < tl.nk2 + tl.ncap; i += blockDim.x) {
+    if (i < tl.nk2) {
+      run_task_k2<T>(A, ak2, k2[i], F1, np);
+    } else {
+      const Task &t = cap[i - tl.nk2];
+      double *acc = A.acc_out + 4 * (int64_t)t.slot;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int pl = t.q * 4 + k;
+        double v = 0.0;
+        for (int j = 0; j < A.r; ++j) v = v + (double)s[pl * plane + t.src + (int64_t)j * t.n0];
+        for (int j = 0; j < A.r; ++j) v = v + (double)F1[pl * np + t.n1 + j * t.j];
+        acc[k] = v;
+      }
+    }
+  }
+  __syncthreads();
+  // 4. sub-step 2 of the tile from LDS
+  for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
+    const int cy = i / w, cx = i - cy * w;
+    const int lp = (cy + 1) * rw + cx + 1;
+    C g[16];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      g[k] = (C)F1[k * np + lp - 1];
+      g[4 + k] = (C)F1[(4 + k) * np + lp + 1];
+      g[8 + k] = (C)F1[(8 + k) * np + lp - rw];
+      g[12 + k] = (C)F1[(12 + k) * np + lp + rw];
+    }
+    relax<C>(g, gm1, h, tb);
+    const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
+    put<T, C, false>(d, plane, o, g);
+  }
+}
+
+template <class T, class C>
+__global__ __launch_bounds__(256) void fused_kernel(StepLaunch Lc) {
+  const int b = blockIdx.x;
+  const LevelDesc *dp = Lc.d0;
+  int first_block = 0;
+  if (Lc.nseg > 0) {
+    int lo = 0, hi = Lc.nseg - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (Lc.segs[mid].first_block <= b) lo = mid; else hi = mid - 1;
+    }
+    dp = Lc.segs[lo].d;
+    first_block = Lc.segs[lo].first_block;
+  }
+  fused_tile<T, C>(*dp, b - first_block);
+}
+
 hipError_t launch_step(const StepLaunch &a, int fp32, hipStream_t s) {
   if (a.nblocks <= 0 || a.nseg < 0) return hipSuccess;
   dim3 grid(a.nblocks), block(256);
+  if (a.flags & STEP_FUSED_PHASE) {
+    if (!fp32)
+      hipLaunchKernelGGL((fused_kernel<double, double>), grid, block, 0, s, a);
+    else if (a.flags & STEP_F64_MATH)
+      hipLaunchKernelGGL((fused_kernel<float, double>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((fused_kernel<float, float>), grid, block, 0, s, a);
+    return hipGetLastError();
+  }
   const bool nt = (a.flags & STEP_NT_STORES) != 0, two = (a.flags & STEP_TWO_CELLS) != 0;
 #define VLBM_STEP(S, C)                                                                        \
   do {                                                                                         \

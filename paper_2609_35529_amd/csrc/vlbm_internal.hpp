@@ -23,6 +23,12 @@ enum TaskKind : int32_t {
   T_RECON = 4,    // ghost slot <- coarse-to-fine hand-off (eq. 2d-recon) from the parent ring cell
   T_REFLUX = 5,   // hole slot  <- reflux accumulator / r^2 (eq. 2d-reflux)
   T_CAPTURE = 6,  // reflux accumulator (=, or += after the first sub-step) sum_j f_q(R_j)
+  // fused two-sub-step launches of the finest level (r = 2):
+  T_RING = 7,      // sub-step 1 of a ring cell: global cell src -> LDS position dst
+  T_CAPTURE2 = 8,  // both sub-steps' captures: global R_0 src (stride n0), LDS R_0 n1 (stride j)
+  T_NONE = -1,     // host-side only: the slot is an active cell, no task
+  TASK_LEDGER = 0x100,  // flag: this task books the boundary ledger (owner tile)
+  TASK_K2 = 0x200,      // flag: sub-step-2 ghost value into LDS position dst (BC source: LDS src)
 };
 
 struct Task {      // 32 bytes
@@ -40,14 +46,22 @@ struct Tile {      // 32 bytes: a w x h rectangle of active cells
   int32_t off0;    // element offset of cell (x0, y0)
   int32_t w, h;
   int32_t task0, ntask;
-  int32_t pad[3];
+  // fused tiles: ntask counts sub-step-1 ghost tasks, then follow nring ring
+  // cells, nk2 sub-step-2 ghost tasks and ncap captures
+  int32_t nring, nk2, ncap;
 };
+
+// Largest fused tile (cells per side); its LDS window is (F+2)^2 positions.
+constexpr int FUSE_SIDE = 16;
+constexpr int FUSE_POS = (FUSE_SIDE + 2) * (FUSE_SIDE + 2);
 
 enum StepFlags : int32_t {
   STEP_NT_STORES = 1,        // write the new time level with non-temporal stores
   STEP_TWO_CELLS = 2,        // two cells per thread, gathers issued together
   STEP_XCD_CONTIGUOUS = 4,   // map consecutive tiles to the same XCD
   STEP_F64_MATH = 8,         // FP32 storage, relaxation evaluated in FP64
+  STEP_FUSE2 = 16,           // tuning: the finest level takes both sub-steps per launch
+  STEP_FUSED_PHASE = 32,     // launch-uniform: this phase is a fused two-sub-step launch
 };
 
 // Everything the step kernel needs about one (context, level) at one phase of

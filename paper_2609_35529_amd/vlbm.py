@@ -36,6 +36,8 @@ VLBM_OK, VLBM_EINVAL, VLBM_ENOMEM, VLBM_ENEST, VLBM_EUNSTABLE, VLBM_EDEVICE, VLB
     0, -1, -2, -3, -4, -5, -6)
 PERIODIC, OUTFLOW, REFLECT, INFLOW = 0, 1, 2, 3
 FP64, FP32, FP32_STORAGE = 0, 1, 2
+# vlbm_set_tuning flags
+TUNE_NT_STORES, TUNE_TWO_CELLS, TUNE_XCD_ORDER, TUNE_FUSE2 = 1, 2, 4, 16
 
 
 class vlbm_params(C.Structure):

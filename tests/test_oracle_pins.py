@@ -454,6 +454,75 @@ def test_regrid_conserves_and_roundtrips():
         T0, _ = o.totals()
 
 
+def _shift_boxes(boxes, shift0, Nx0, r):
+    """Boxes translated by shift0 level-0 cells along periodic x; a box that
+    crosses the seam is cut in two."""
+    out = []
+    for (l, i0, j0, nx, ny) in boxes:
+        s, N = shift0 * r ** l, Nx0 * r ** l
+        a = (i0 + s) % N
+        if a + nx <= N:
+            out.append((l, a, j0, nx, ny))
+        else:
+            out.append((l, a, j0, N - a, ny))
+            out.append((l, 0, j0, nx - (N - a), ny))
+    return out
+
+
+@pytest.mark.parametrize("shift", [3, 8, 13])
+def test_periodic_translation_equivariance(shift):
+    """With periodic x the method has no preferred origin: translating boxes
+    and state by any whole number of coarse cells translates the result, bit
+    for bit. Fine boxes touching both sides of the seam exercise copies,
+    hand-offs and reflux across it (a coarse cell whose reflux neighbour lies
+    across the seam)."""
+    n, r = 20, 2
+    win = np.tile(wl.conserved(1.1, 0.4, -0.1, 1.2).reshape(4), (4, 1))
+    boxes = [(1, 0, 0, 22, 10), (1, 0, 10, 10, 12), (1, 28, 6, 12, 30)]
+    U = wl.random_state_U(n, 18, seed=1)
+    U1 = wl.prolong_piecewise(U, r) * 1.01
+
+    def run(bx, U0, U1_):
+        case = wl.Case("t", n, 18, 1.0 / n, r, 2, 1.4, 4.0, 0.8, (0, 0, 2, 3), bx, [U0, U1_], 0,
+                       w_inflow=win)
+        return _run(case, 3)
+
+    a = run(boxes, U, U1)
+    b = run(_shift_boxes(boxes, shift, n, r), np.roll(U, shift, axis=2),
+            np.roll(U1, shift * r, axis=2))
+    for l in range(2):
+        Fa = a.get_pop(l)
+        Fb = np.roll(b.get_pop(l), -shift * r ** l, axis=2)
+        assert np.array_equal(Fa, Fb, equal_nan=True), l
+
+
+def test_regrid_restarts_temporal_reconstruction():
+    """Reading: a regrid rebuilds every interface and each starts its temporal
+    reconstruction afresh. Regridding to the same boxes and going on therefore
+    equals restarting from the current populations, and differs from going on
+    without the regrid (the temporal slope is not zero here)."""
+    n = 16
+    U = wl.random_smooth_U(n, n, seed=5)
+    case = wl.Case("t", n, n, 1.0 / n, 2, 3, 1.4, 4.0, 0.8, (1, 1, 2, 2),
+                   [(1, 8, 8, 12, 12), (2, 20, 20, 8, 8)],
+                   [U, wl.prolong_piecewise(U, 2), wl.prolong_piecewise(U, 4)], 0)
+    a = _run(case, 4)
+    snap = [np.nan_to_num(a.get_pop(l)) for l in range(3)]
+    a.regrid(case.boxes)
+    a.advance(3)
+    b = _run(case, 0)
+    for l in range(3):
+        b.set_pop(l, snap[l])
+    b.advance(3)
+    c = _run(case, 7)
+    differs = False
+    for l in range(3):
+        Fa, Fb, Fc = a.get_pop(l), b.get_pop(l), c.get_pop(l)
+        assert np.array_equal(Fa, Fb, equal_nan=True), l
+        differs |= not np.array_equal(Fa, Fc, equal_nan=True)
+    assert differs
+
+
 def test_regrid_rejects_bad_nesting():
     n = 16
     U = wl.random_smooth_U(n, n, seed=2)
