@@ -9,9 +9,11 @@ FP64, seed 0, inputs resident in HBM before the timed region.
 
 metric: fine-equivalent cell updates per second = (nx0 r^L)(ny0 r^L) r^L per
 coarse step (the updates a uniform finest-level grid would need), over the
-timed steps. The JSON line also carries the roofline of the step kernel
-(algorithmic bytes: 16 populations in + 16 out per actual cell update) and
-the oracle timed on the host cores on a bounded sample of the same workload.
+timed steps. The JSON line also carries the roofline of the dominant kernel
+(the level and launch form with the most kernel time; algorithmic bytes: 16
+populations in + 16 out per active cell per launch, over the launch's own
+duration from per-kernel events of the timed region) and the oracle timed on
+the host cores on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -24,13 +26,15 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic per step-kernel launch of the default workload (quadrant512, FP64,
-# 256-cell tiles, XCD-contiguous order), from rocprofv3 FETCH_SIZE x 2.000 and
-# WRITE_SIZE x 1.000 (scales measured on a plain 2 GiB copy); valid only for the
-# kernel source it was measured on.
-MEASURED_TRAFFIC = {"kernel_sha256_16": "07565bc57f0e9761", "workload": "quadrant512",
-                    "precision": "fp64", "tile_cells": 256, "flags": 4,
-                    "bytes_per_launch": 63242009.1}
+# HBM traffic per launch of the dominant kernel of the default workload
+# (quadrant512, FP64, fused sub-steps with XCD-contiguous order: the fused
+# launch of the fine level), from rocprofv3 FETCH_SIZE x 2.000 and WRITE_SIZE
+# x 1.000 (scales measured on a plain 2 GiB copy); valid only for the kernel
+# source it was measured on. The fused tile shape does not depend on
+# tile_cells, so any tile_cells matches.
+MEASURED_TRAFFIC = {"kernel_sha256_16": "452cc9b0e1bc9c84", "workload": "quadrant512",
+                    "precision": "fp64", "tile_cells": None, "flags": 20, "kernel": "fused_kernel",
+                    "bytes_per_launch": 77724347.6}
 
 
 def kernel_hash():
@@ -57,10 +61,6 @@ def build_case(name, steps):
 
 def actual_updates_per_step(case):
     return case.actual_updates_per_coarse_step()
-
-
-def launches_per_step(case):
-    return case.launches_per_coarse_step()
 
 
 def cpu_baseline(case, budget_s=15.0):
@@ -201,7 +201,15 @@ def main():
         tuning = {"tile_cells": tile, "flags": flags}
     dynamic = case.name == "shock_bubble"
     regrid_every = 5
-    amr = {"regrids": 0, "boxes": [], "regrid_s": 0.0, "updates": 0, "launches": 0}
+    amr = {"regrids": 0, "boxes": [], "regrid_s": 0.0, "updates": 0}
+
+    cell_launches = {}  # (level, fused) -> sum over launches of the level's active cells
+
+    def count_cells(before, after):
+        for key, (_, calls) in after.items():
+            dn = calls - before.get(key, (0.0, 0))[1]
+            if dn:
+                cell_launches[key] = cell_launches.get(key, 0) + dn * solver.active_cells(key[0])
 
     def run(n):
         """n coarse steps; the dynamic-AMR workload re-tags and regrids every
@@ -219,10 +227,11 @@ def main():
                 amr["regrids"] += 1
                 amr["boxes"].append(len(solver.boxes()))
             k = min(n - done, regrid_every - solver.steps() % regrid_every)
+            before = solver.kernel_times()
             solver.advance(k)
+            count_cells(before, solver.kernel_times())
             act = [solver.active_cells(l) for l in range(case.nlev)]
             amr["updates"] += k * sum(a * case.r ** l for l, a in enumerate(act))
-            amr["launches"] += k * sum(case.r ** l for l, a in enumerate(act) if a > 0)
             done += k
 
     if dynamic:  # build the hierarchy before tuning and timing
@@ -232,7 +241,7 @@ def main():
     print(f"[bench] {case.name} warmup {args.warmup}", file=sys.stderr, flush=True)
     run(args.warmup)
     torch.cuda.synchronize()
-    amr.update(regrids=0, boxes=[], regrid_s=0.0, updates=0, launches=0)
+    amr.update(regrids=0, boxes=[], regrid_s=0.0, updates=0)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -242,23 +251,44 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = ev0.elapsed_time(ev1)
+    upd_timed = amr["updates"]
+    # Per-kernel durations come from a second region of the same run: every
+    # step launch records its own start and end (launch-extension events on
+    # the solver's stream). Those events lengthen the gaps between launches,
+    # so they stay out of the throughput region above.
+    prof_steps = min(args.steps, 100)
+    solver.set_profiling(True)
+    tp = time.perf_counter()
+    run(prof_steps)
+    ktimes = solver.kernel_times()
+    prof_wall = time.perf_counter() - tp
+    solver.set_profiling(False)
+    if not dynamic:
+        count_cells({}, ktimes)
     T1, L1 = solver.totals()
     healthy = solver.check_health()
 
     fe_step = case.fine_equivalent_per_coarse_step()
     value = fe_step * args.steps / wall
-    upd = actual_updates_per_step(case) if not dynamic else amr["updates"] / args.steps
+    upd = actual_updates_per_step(case) if not dynamic else upd_timed / args.steps
     esz = 8 if prec == vlbm.FP64 else 4
     bytes_per_update = 2 * 16 * esz
-    nl = launches_per_step(case) if not dynamic else amr["launches"] / args.steps
-    avg_launch_s = gpu_ms / 1e3 / (args.steps * nl)
-    bytes_per_launch = upd * bytes_per_update / nl
+    nl = sum(c for _, c in ktimes.values()) / prof_steps
+    # dominant kernel: the (level, launch form) with the largest kernel time;
+    # algorithmic bytes of one launch: 16 populations read and 16 written per
+    # active cell of the level (a fused launch keeps the intermediate time
+    # level on chip, so it moves the same bytes for two sub-steps)
+    dom = max(ktimes, key=lambda k: ktimes[k][0])
+    dom_ms, dom_calls = ktimes[dom]
+    avg_launch_s = dom_ms / 1e3 / dom_calls
+    bytes_per_launch = cell_launches[dom] / dom_calls * bytes_per_update
     achieved = bytes_per_launch / avg_launch_s / 1e9
+    kernel_name = "fused_kernel" if dom[1] else "step_kernel"
     traffic = None
     m = MEASURED_TRAFFIC
     if (kernel_hash() == m["kernel_sha256_16"] and args.workload == m["workload"]
-            and args.precision == m["precision"] and tuning
-            and tuning["tile_cells"] == m["tile_cells"] and tuning["flags"] == m["flags"]):
+            and args.precision == m["precision"] and tuning and m["kernel"] == kernel_name
+            and m["tile_cells"] in (None, tuning["tile_cells"]) and tuning["flags"] == m["flags"]):
         traffic = m["bytes_per_launch"]
     scale = max(abs(x) for x in T0)
     drift = [float(abs((T1[k] - T0[k]) - (L1[k] - L0[k])) / scale) for k in range(4)]
@@ -284,8 +314,11 @@ def main():
                    "precision": args.precision},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "step_kernel", "bytes_per_launch": bytes_per_launch,
-                     "avg_launch_us": avg_launch_s * 1e6},
+                     "kernel": kernel_name, "level": dom[0], "bytes_per_launch": bytes_per_launch,
+                     "avg_launch_us": avg_launch_s * 1e6, "launches": dom_calls,
+                     "kernel_share": dom_ms / sum(t for t, _ in ktimes.values()),
+                     "timing": f"per-kernel events over {prof_steps} further coarse steps "
+                               f"({prof_wall * 1e3 / prof_steps:.4f} ms/step with events)"},
         "actual_updates_per_s": upd * args.steps / wall,
         "amr": ({"regrid_every": regrid_every, "regrids": amr["regrids"],
                  "boxes_min": min(amr["boxes"]), "boxes_max": max(amr["boxes"]),

@@ -44,6 +44,8 @@
  */
 #ifndef VLBM_H
 #define VLBM_H
+
+#define VLBM_MAX_LEVELS 8 /* levels of a hierarchy, level 0 included */
 #include <stddef.h>
 
 #ifdef __cplusplus
@@ -199,6 +201,19 @@ vlbm_status vlbm_set_tuning(vlbm_ctx *ctx, int tile_cells, int flags);
  * repeated call advances nothing. Reports the choice in tile_cells/flags
  * (either may be NULL). */
 vlbm_status vlbm_autotune(vlbm_ctx *ctx, int steps_per_trial, int *tile_cells, int *flags);
+
+/* Per-kernel timing of the step launches of vlbm_advance. With enable != 0
+ * every launch records its own start and end (events of the AMD launch
+ * extension: no extra work on the stream) and the accumulators restart at
+ * zero; graph replay is bypassed meanwhile. enable = 0 stops recording and
+ * keeps the totals. Launches of vlbm_batch_advance are not recorded. */
+vlbm_status vlbm_set_profiling(vlbm_ctx *ctx, int enable);
+
+/* Accumulated kernel time in ms and launch count per level and launch form,
+ * at index 2 * level + f with f = 1 for fused two-sub-step launches; ms and
+ * calls hold 2 * VLBM_MAX_LEVELS entries each. Synchronises with the
+ * recorded launches. */
+vlbm_status vlbm_kernel_times(vlbm_ctx *ctx, double *ms, long *calls);
 
 /* Coarse steps taken since set_state. */
 long vlbm_steps(const vlbm_ctx *ctx);

@@ -51,7 +51,7 @@ vlbm_status fail(vlbm_status st, const char *fmt, ...) {
       return fail(VLBM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));          \
   } while (0)
 
-constexpr int kMaxLevels = 8;
+constexpr int kMaxLevels = VLBM_MAX_LEVELS;
 
 // VLBM_TIMING=1 prints host-side phase timings of hierarchy changes to stderr.
 struct PhaseTimer {
@@ -174,7 +174,7 @@ struct Level {
   Tile *dtiles = nullptr;
   Task *dtasks = nullptr;
   // fused two-sub-step launch (finest level, r = 2): tiles of at most
-  // FUSE_SIDE x FUSE_SIDE cells and their task lists
+  // FUSE_W x FUSE_H cells and their task lists
   std::vector<Tile> ftiles;
   std::vector<Task> ftasks;
   Tile *dftiles = nullptr;
@@ -226,6 +226,13 @@ struct vlbm_ctx {
   long flips[kMaxLevels] = {};  // buffer flips of each level per coarse step
   bool use_graphs = false;
   hipGraphExec_t graph = nullptr;  // two coarse steps from an even table parity
+  // per-kernel timing (vlbm_set_profiling): start and end events of every
+  // step launch, read back in batches
+  bool prof = false;
+  std::vector<hipEvent_t> pev;  // event pool, two per pending launch
+  std::vector<int> pend;        // pending launches: 2 * level + fused
+  double prof_ms[2 * kMaxLevels] = {};
+  long prof_calls[2 * kMaxLevels] = {};
   long graph_key = -1;
 
   bool perx() const { return p.bc[0] == VLBM_BC_PERIODIC; }
@@ -399,8 +406,12 @@ vlbm_status ghost_task(const vlbm_ctx *c, int l, int x, int y, int q, Task &t) {
 }
 
 // Lists of the fused two-sub-step launch of level l (the finest, r = 2).
-// Active cells are cut into rectangles of at most FUSE_SIDE x FUSE_SIDE cells
-// aligned to a FUSE_SIDE grid. Per tile, in this order:
+// Active cells are cut into rectangles of at most FUSE_W x FUSE_H cells
+// aligned to a FUSE_W x FUSE_H grid from the frame's first interior cell.
+// Coverage of the finest level is a union of r x r blocks aligned like that
+// cell, and both sides are even, so every rectangle is too: both cells of a reflux
+// capture lie in one tile. LDS positions follow the per-population layout of
+// the fused kernel (see FUSE_POS). Per tile, in this order:
 //   ntask  sub-step-1 ghost tasks of every cell whose sub-step-1 value the tile
 //          needs (its own cells, which book the ledger, and the sources of its
 //          ring positions, which do not);
@@ -414,14 +425,13 @@ vlbm_status ghost_task(const vlbm_ctx *c, int l, int x, int y, int q, Task &t) {
 vlbm_status build_fused(vlbm_ctx *c, int l, const std::unordered_map<int64_t, int> &bc_slot,
                         const std::vector<std::pair<int64_t, Task>> &caps) {
   Level &L = c->lv[l];
-  const int F = FUSE_SIDE;
-  // rectangles: per row, runs of active cells cut at the FUSE_SIDE grid; equal
-  // runs on consecutive rows of one FUSE_SIDE band stack into one rectangle
+  // rectangles: per row, runs of active cells cut at the FUSE_W grid; equal
+  // runs on consecutive rows of one FUSE_H band stack into one rectangle
   struct Rect { int x0, y0, w, h; };
   std::vector<Rect> rects;
   std::map<std::pair<int, int>, int> open;  // (x0, w) -> index in rects (current band)
   for (int y = L.fy0 + 1; y < L.fy0 + L.fh - 1; ++y) {
-    if ((y - L.fy0 - 1) % F == 0) open.clear();
+    if ((y - L.fy0 - 1) % FUSE_H == 0) open.clear();
     std::map<std::pair<int, int>, int> next;
     int x = L.fx0 + 1;
     const int xe = L.fx0 + L.fw - 1;
@@ -431,7 +441,7 @@ vlbm_status build_fused(vlbm_ctx *c, int l, const std::unordered_map<int64_t, in
         continue;
       }
       const int xa = x;
-      const int cut = L.fx0 + 1 + ((x - L.fx0 - 1) / F + 1) * F;
+      const int cut = L.fx0 + 1 + ((x - L.fx0 - 1) / FUSE_W + 1) * FUSE_W;
       while (x < xe && x < cut && L.status[L.fidx(x, y)] == 1) ++x;
       const std::pair<int, int> key{xa, x - xa};
       auto it = open.find(key);
@@ -453,19 +463,27 @@ vlbm_status build_fused(vlbm_ctx *c, int l, const std::unordered_map<int64_t, in
     for (int yy = 0; yy < rects[t].h; ++yy)
       for (int xx = 0; xx < rects[t].w; ++xx) owner[L.fidx(rects[t].x0 + xx, rects[t].y0 + yy)] = (int32_t)t;
   std::vector<std::vector<Task>> capt(rects.size());
+  // LDS position of cell (x, y) in the plane group of population q, for tile R
+  auto pos = [](const Rect &R, int q, int x, int y) -> int32_t {
+    const int cx = x - R.x0, cy = y - R.y0;
+    switch (q) {
+      case 0: return cy * (R.w + 1) + cx + 1;
+      case 1: return cy * (R.w + 1) + cx;
+      case 2: return (cy + 1) * R.w + cx;
+      default: return cy * R.w + cx;
+    }
+  };
   for (const auto &ct : caps) {
     const int x = (int)(ct.first % L.Nx), y = (int)(ct.first / L.Nx);
     const int t = owner[L.fidx(x, y)];
     const Rect &R = rects[t];
-    const int rw = R.w + 2;
     Task u = ct.second;
     u.kind = T_CAPTURE2;
-    u.n1 = (y - R.y0 + 1) * rw + (x - R.x0 + 1);
-    u.j = ct.second.q < 2 ? rw : 1;
-    // R_1 is the tile's or a ring cell (adjacent to R_0), so it is in the window
+    u.n1 = pos(R, u.q, x, y);
+    u.j = u.q < 2 ? R.w + 1 : 1;
     const int x1 = x + (u.q < 2 ? 0 : 1), y1 = y + (u.q < 2 ? 1 : 0);
-    if (x1 < R.x0 - 1 || x1 > R.x0 + R.w || y1 < R.y0 - 1 || y1 > R.y0 + R.h)
-      return fail(VLBM_ENEST, "internal: capture cells outside the fused window");
+    if (x1 >= R.x0 + R.w || y1 >= R.y0 + R.h)
+      return fail(VLBM_ENEST, "internal: reflux capture split across fused tiles");
     capt[t].push_back(u);
   }
   std::vector<uint8_t> mark(L.cov.size(), 0);
@@ -474,8 +492,6 @@ vlbm_status build_fused(vlbm_ctx *c, int l, const std::unordered_map<int64_t, in
   L.ftasks.clear();
   for (size_t ti = 0; ti < rects.size(); ++ti) {
     const Rect &R = rects[ti];
-    const int rw = R.w + 2;
-    auto lds = [&](int x, int y) { return (int32_t)((y - R.y0 + 1) * rw + (x - R.x0 + 1)); };
     auto in_tile = [&](int x, int y) { return x >= R.x0 && y >= R.y0 && x < R.x0 + R.w && y < R.y0 + R.h; };
     std::vector<std::pair<int, int>> src_cells;  // ring sources outside the tile
     std::vector<Task> ring, k2;
@@ -490,7 +506,7 @@ vlbm_status build_fused(vlbm_ctx *c, int l, const std::unordered_map<int64_t, in
           if (gs) return gs;
           const int kind = t.kind == T_NONE ? T_NONE : t.kind & 0xFF;
           Task u = t;
-          u.dst = lds(sx, sy);
+          u.dst = pos(R, q, sx, sy);
           if (kind == T_NONE || kind == T_COPY) {
             int wx = sx, wy = sy;
             c->wrap(l, wx, wy);
@@ -512,7 +528,8 @@ vlbm_status build_fused(vlbm_ctx *c, int l, const std::unordered_map<int64_t, in
             auto it = bc_slot.find(((int64_t)y * L.Nx + x) * 4 + q);
             if (it == bc_slot.end()) return fail(VLBM_ENEST, "internal: no ledger slot for a fused boundary task");
             u.kind = kind | TASK_K2 | TASK_LEDGER;
-            u.src = lds(x, y);
+            u.src = pos(R, q, x, y);
+            u.n1 = pos(R, q ^ 1, x, y);
             u.slot = it->second;
             k2.push_back(u);
           } else {
@@ -566,8 +583,8 @@ vlbm_status build_fused(vlbm_ctx *c, int l, const std::unordered_map<int64_t, in
     L.ftasks.insert(L.ftasks.end(), ring.begin(), ring.end());
     L.ftasks.insert(L.ftasks.end(), k2.begin(), k2.end());
     L.ftasks.insert(L.ftasks.end(), capt[ti].begin(), capt[ti].end());
-    if ((R.w + 2) * (R.h + 2) > FUSE_POS || R.w * R.h + tl.nring > 4 * 256)
-      return fail(VLBM_ENEST, "internal: fused tile too large");
+    if (R.w > FUSE_W || R.h > FUSE_H || R.x0 % 2 || R.y0 % 2 || R.w % 2 || R.h % 2)
+      return fail(VLBM_ENEST, "internal: fused tile %dx%d at (%d,%d) not block aligned", R.w, R.h, R.x0, R.y0);
     L.ftiles.push_back(tl);
   }
   return VLBM_OK;
@@ -944,6 +961,20 @@ vlbm_status build_tables(vlbm_ctx *c) {
 
 double ak_of(int k, int r) { return (double)(2 * k - r - 1) / (double)(2 * r); }
 
+// Read back the pending launch timings into the accumulators.
+vlbm_status prof_flush(vlbm_ctx *c) {
+  if (c->pend.empty()) return VLBM_OK;
+  HIPCHK(hipEventSynchronize(c->pev[2 * c->pend.size() - 1]));
+  for (size_t i = 0; i < c->pend.size(); ++i) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->pev[2 * i], c->pev[2 * i + 1]));
+    c->prof_ms[c->pend[i]] += ms;
+    c->prof_calls[c->pend[i]] += 1;
+  }
+  c->pend.clear();
+  return VLBM_OK;
+}
+
 // Launch every phase of one coarse step of table parity e.
 vlbm_status launch_coarse_step(vlbm_ctx *c, int e) {
   const size_t P = c->phases.size();
@@ -956,7 +987,23 @@ vlbm_status launch_coarse_step(vlbm_ctx *c, int e) {
     a.first = c->phases[p].second == 1;
     a.flags = c->step_flags | (c->phases[p].second == 0 ? STEP_FUSED_PHASE : 0);
     a.ak = ak_of(c->phases[p].second, c->p.r);
-    HIPCHK(launch_step(a, c->fp32, c->stream));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->prof && a.nblocks > 0) {
+      if (c->pend.size() >= 4096) {
+        vlbm_status st = prof_flush(c);
+        if (st) return st;
+      }
+      const size_t i = 2 * c->pend.size();
+      while (c->pev.size() < i + 2) {
+        hipEvent_t ev;
+        HIPCHK(hipEventCreate(&ev));
+        c->pev.push_back(ev);
+      }
+      e0 = c->pev[i];
+      e1 = c->pev[i + 1];
+      c->pend.push_back(2 * c->phases[p].first + (c->phases[p].second == 0 ? 1 : 0));
+    }
+    HIPCHK(launch_step(a, c->fp32, c->stream, e0, e1));
   }
   return VLBM_OK;
 }
@@ -991,7 +1038,7 @@ vlbm_status ensure_graph(vlbm_ctx *c) {
 }
 
 vlbm_status advance_impl(vlbm_ctx *c, long n) {
-  const bool graphs = c->use_graphs && c->stream != nullptr && n >= 4;
+  const bool graphs = c->use_graphs && !c->prof && c->stream != nullptr && n >= 4;
   while (n > 0) {
     const int e = table_parity(c);
     if (graphs && e == 0 && n >= 2) {
@@ -1474,6 +1521,7 @@ void vlbm_destroy(vlbm_ctx *c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   drop_graph(c);
+  for (hipEvent_t ev : c->pev) (void)hipEventDestroy(ev);
   for (int l = 0; l < kMaxLevels; ++l) free_level(c, c->lv[l]);
   c->mem.release(c->ddesc);
   c->mem.release(c->dseg);
@@ -2012,6 +2060,30 @@ vlbm_status vlbm_autotune(vlbm_ctx *c, int steps_per_trial, int *tile_cells, int
   if (st) return st;
   if (tile_cells) *tile_cells = c->tile_cells;
   if (flags) *flags = c->step_flags & ~STEP_F64_MATH;
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_set_profiling(vlbm_ctx *c, int enable) {
+  if (!c) return fail(VLBM_EINVAL, "null context");
+  vlbm_status st = prof_flush(c);
+  if (st) return st;
+  c->prof = enable != 0;
+  if (c->prof)
+    for (int i = 0; i < 2 * kMaxLevels; ++i) {
+      c->prof_ms[i] = 0.0;
+      c->prof_calls[i] = 0;
+    }
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_kernel_times(vlbm_ctx *c, double *ms, long *calls) {
+  if (!c || !ms || !calls) return fail(VLBM_EINVAL, "null argument");
+  vlbm_status st = prof_flush(c);
+  if (st) return st;
+  for (int i = 0; i < 2 * kMaxLevels; ++i) {
+    ms[i] = c->prof_ms[i];
+    calls[i] = c->prof_calls[i];
+  }
   return VLBM_OK;
 }
 

@@ -16,6 +16,7 @@
 //   Q_x = (m_x, m_x u + p, m_y u, (E+p) u);  Q_y = (m_y, m_x v, m_y v + p, (E+p) v)
 //   f^eq_{+-x,k} = 0.25 W_k +- h Q_{x,k},  f^eq_{+-y,k} = 0.25 W_k +- h Q_{y,k},  h = 1/(2c)
 //   f*_{qk} = f_{qk} + 2beta (f^eq_{qk} - f_{qk})
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "vlbm_internal.hpp"
@@ -280,20 +281,23 @@ __global__ __launch_bounds__(256) void step_kernel(StepLaunch Lc) {
 
 // ---------------------------------------------------------------------------
 // Fused two-sub-step launch of the finest level (r = 2). One workgroup per
-// tile of at most FUSE_SIDE x FUSE_SIDE cells:
-//   1. sub-step-1 ghost values of the tile and of its one-cell ring go into the
-//      global ghost slots (neighbouring tiles write the same values);
-//   2. sub-step 1 of the tile and ring cells, rounded to the storage type, into
-//      LDS (position (cy+1)*(w+2) + cx+1, one LDS plane per population);
+// tile of at most FUSE_W x FUSE_H cells, aligned to the 2 x 2 blocks of
+// parent cells (so both cells of every reflux capture lie in one tile):
+//   1. sub-step-1 ghost values of the tile's cells and of the sources of its
+//      ring go into the global ghost slots (neighbouring tiles write the same
+//      values);
+//   2. sub-step 1 of the tile cells (all populations) and of the active ring
+//      cells (the one population the tile pulls from each), rounded to the
+//      storage type, into LDS;
 //   3. sub-step-2 ghost values into the LDS ring positions, and the parent's
 //      reflux accumulators receive both sub-steps' outgoing values;
 //   4. sub-step 2 of the tile, pulled from LDS, stored to the next buffer.
 // The arithmetic and its rounding points are those of two separate launches,
-// so results are bit-identical; F(t + dt) never travels to HBM.
+// so results are bit-identical; the intermediate level never travels to HBM.
 // ---------------------------------------------------------------------------
 template <class T>
-__device__ __forceinline__ void run_task_k2(const LevelDesc &A, double ak2, const Task &t,
-                                            T *F1, int np) {
+__device__ __forceinline__ void run_task_k2(const LevelDesc &A, double ak2, const Task &t, T *F1) {
+  constexpr int np = FUSE_POS;
   const int q = t.q;
   const int kind = t.kind & 0xFF;
   if (kind == T_RECON) {
@@ -326,7 +330,7 @@ __device__ __forceinline__ void run_task_k2(const LevelDesc &A, double ak2, cons
     const int kn = side < 2 ? 1 : 2;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const double w = (double)F1[(qo * 4 + k) * np + t.src];
+      const double w = (double)F1[(qo * 4 + k) * np + t.n1];
       in[k] = (k == kn) ? -w : w;
     }
   } else {
@@ -344,15 +348,19 @@ __device__ __forceinline__ void run_task_k2(const LevelDesc &A, double ak2, cons
   for (int k = 0; k < 4; ++k) {
     const T vin = (T)in[k];
     F1[(q * 4 + k) * np + t.dst] = vin;
-    const double out = (double)F1[(qo * 4 + k) * np + t.src];
+    const double out = (double)F1[(qo * 4 + k) * np + t.n1];
     double l = L[k] + A.w2 * (double)vin;
     L[k] = l + (-1.0) * (A.w2 * out);
   }
 }
 
 template <class T, class C>
-__device__ __forceinline__ void fused_tile(const LevelDesc &A, int tid) {
+__device__ __forceinline__ void fused_tile(const LevelDesc &A, int lb, int nblocks, int flags) {
+  constexpr int np = FUSE_POS;
   __shared__ T F1[16 * FUSE_POS];
+  // XCD-contiguous order: a tile's ring cells belong to its neighbours, whose
+  // lines then sit in the same XCD's L2
+  const int tid = (flags & STEP_XCD_CONTIGUOUS) ? (lb & 7) * (nblocks >> 3) + (lb >> 3) : lb;
   const int ntiles = A.ntiles;
   if (tid >= ntiles) return;
   const Tile tl = A.tiles[tid];
@@ -361,7 +369,7 @@ __device__ __forceinline__ void fused_tile(const LevelDesc &A, int tid) {
   const int64_t plane = A.plane;
   const int pitch = A.pitch;
   const C gm1 = (C)A.gm1, h = (C)A.h, tb = (C)A.tb;
-  const int w = tl.w, np = FUSE_POS, rw = w + 2;
+  const int w = tl.w, w1 = w + 1;
   const double ak1 = (double)(1 - A.r) / (double)(2 * A.r);   // k = 1
   const double ak2 = (double)(3 - A.r) / (double)(2 * A.r);   // k = 2
   const Task *tk = A.tasks + tl.task0;
@@ -372,21 +380,32 @@ __device__ __forceinline__ void fused_tile(const LevelDesc &A, int tid) {
   const int ncell = w * tl.h;
   const Task *ring = tk + tl.ntask;
   for (int i = threadIdx.x; i < ncell + tl.nring; i += blockDim.x) {
-    int64_t o;
-    int lp;
     if (i < ncell) {
       const int cy = i / w, cx = i - cy * w;
-      o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
-      lp = (cy + 1) * rw + cx + 1;
-    } else {
-      o = ring[i - ncell].src;
-      lp = ring[i - ncell].dst;
-    }
-    C g[16];
-    pull<T, C>(s, plane, pitch, o, g);
-    relax<C>(g, gm1, h, tb);
+      const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
+      C g[16];
+      pull<T, C>(s, plane, pitch, o, g);
+      relax<C>(g, gm1, h, tb);
+      const int p0 = cy * w1 + cx + 1, p1 = cy * w1 + cx, p2 = (cy + 1) * w + cx, p3 = cy * w + cx;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) F1[k * np + lp] = (T)g[k];
+      for (int k = 0; k < 4; ++k) {
+        F1[k * np + p0] = (T)g[k];
+        F1[(4 + k) * np + p1] = (T)g[4 + k];
+        F1[(8 + k) * np + p2] = (T)g[8 + k];
+        F1[(12 + k) * np + p3] = (T)g[12 + k];
+      }
+    } else {
+      const Task &t = ring[i - ncell];
+      C g[16];
+      pull<T, C>(s, plane, pitch, (int64_t)t.src, g);
+      relax<C>(g, gm1, h, tb);
+      const int q = t.q;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const C v = q == 0 ? g[k] : q == 1 ? g[4 + k] : q == 2 ? g[8 + k] : g[12 + k];
+        F1[(q * 4 + k) * np + t.dst] = (T)v;
+      }
+    }
   }
   __syncthreads();
   // 3. sub-step-2 ghost values into LDS; both sub-steps' reflux captures
@@ -394,7 +413,7 @@ __device__ __forceinline__ void fused_tile(const LevelDesc &A, int tid) {
   const Task *cap = k2 + tl.nk2;
   for (int i = threadIdx.x; i < tl.nk2 + tl.ncap; i += blockDim.x) {
     if (i < tl.nk2) {
-      run_task_k2<T>(A, ak2, k2[i], F1, np);
+      run_task_k2<T>(A, ak2, k2[i], F1);
     } else {
       const Task &t = cap[i - tl.nk2];
       double *acc = A.acc_out + 4 * (int64_t)t.slot;
@@ -412,14 +431,14 @@ __device__ __forceinline__ void fused_tile(const LevelDesc &A, int tid) {
   // 4. sub-step 2 of the tile from LDS
   for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
     const int cy = i / w, cx = i - cy * w;
-    const int lp = (cy + 1) * rw + cx + 1;
+    const int p0 = cy * w1 + cx, p1 = cy * w1 + cx + 1, p2 = cy * w + cx, p3 = (cy + 1) * w + cx;
     C g[16];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      g[k] = (C)F1[k * np + lp - 1];
-      g[4 + k] = (C)F1[(4 + k) * np + lp + 1];
-      g[8 + k] = (C)F1[(8 + k) * np + lp - rw];
-      g[12 + k] = (C)F1[(12 + k) * np + lp + rw];
+      g[k] = (C)F1[k * np + p0];
+      g[4 + k] = (C)F1[(4 + k) * np + p1];
+      g[8 + k] = (C)F1[(8 + k) * np + p2];
+      g[12 + k] = (C)F1[(12 + k) * np + p3];
     }
     relax<C>(g, gm1, h, tb);
     const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
@@ -428,41 +447,50 @@ __device__ __forceinline__ void fused_tile(const LevelDesc &A, int tid) {
 }
 
 template <class T, class C>
-__global__ __launch_bounds__(256) void fused_kernel(StepLaunch Lc) {
+__global__ __launch_bounds__(FUSE_THREADS) void fused_kernel(StepLaunch Lc) {
   const int b = blockIdx.x;
   const LevelDesc *dp = Lc.d0;
-  int first_block = 0;
+  int first_block = 0, nblocks = Lc.nblocks;
   if (Lc.nseg > 0) {
     int lo = 0, hi = Lc.nseg - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (Lc.segs[mid].first_block <= b) lo = mid; else hi = mid - 1;
     }
-    dp = Lc.segs[lo].d;
-    first_block = Lc.segs[lo].first_block;
+    const Segment sg = Lc.segs[lo];
+    dp = sg.d;
+    first_block = sg.first_block;
+    nblocks = sg.nblocks;
   }
-  fused_tile<T, C>(*dp, b - first_block);
+  fused_tile<T, C>(*dp, b - first_block, nblocks, Lc.flags);
 }
 
-hipError_t launch_step(const StepLaunch &a, int fp32, hipStream_t s) {
+// ev0/ev1 (may be null): events that take the kernel's own start and end
+// times (AMD launch extension), for per-kernel timing without stream markers.
+hipError_t launch_step(const StepLaunch &a, int fp32, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (a.nblocks <= 0 || a.nseg < 0) return hipSuccess;
   dim3 grid(a.nblocks), block(256);
   if (a.flags & STEP_FUSED_PHASE) {
+    block = dim3(FUSE_THREADS);
     if (!fp32)
-      hipLaunchKernelGGL((fused_kernel<double, double>), grid, block, 0, s, a);
+      hipExtLaunchKernelGGL((fused_kernel<double, double>), grid, block, 0, s, ev0, ev1, 0, a);
     else if (a.flags & STEP_F64_MATH)
-      hipLaunchKernelGGL((fused_kernel<float, double>), grid, block, 0, s, a);
+      hipExtLaunchKernelGGL((fused_kernel<float, double>), grid, block, 0, s, ev0, ev1, 0, a);
     else
-      hipLaunchKernelGGL((fused_kernel<float, float>), grid, block, 0, s, a);
+      hipExtLaunchKernelGGL((fused_kernel<float, float>), grid, block, 0, s, ev0, ev1, 0, a);
     return hipGetLastError();
   }
   const bool nt = (a.flags & STEP_NT_STORES) != 0, two = (a.flags & STEP_TWO_CELLS) != 0;
-#define VLBM_STEP(S, C)                                                                        \
-  do {                                                                                         \
-    if (nt && two) hipLaunchKernelGGL((step_kernel<S, C, true, true>), grid, block, 0, s, a);   \
-    else if (nt) hipLaunchKernelGGL((step_kernel<S, C, true, false>), grid, block, 0, s, a);    \
-    else if (two) hipLaunchKernelGGL((step_kernel<S, C, false, true>), grid, block, 0, s, a);   \
-    else hipLaunchKernelGGL((step_kernel<S, C, false, false>), grid, block, 0, s, a);           \
+#define VLBM_STEP(S, C)                                                                          \
+  do {                                                                                           \
+    if (nt && two)                                                                               \
+      hipExtLaunchKernelGGL((step_kernel<S, C, true, true>), grid, block, 0, s, ev0, ev1, 0, a);   \
+    else if (nt)                                                                                 \
+      hipExtLaunchKernelGGL((step_kernel<S, C, true, false>), grid, block, 0, s, ev0, ev1, 0, a);  \
+    else if (two)                                                                                \
+      hipExtLaunchKernelGGL((step_kernel<S, C, false, true>), grid, block, 0, s, ev0, ev1, 0, a);  \
+    else                                                                                         \
+      hipExtLaunchKernelGGL((step_kernel<S, C, false, false>), grid, block, 0, s, ev0, ev1, 0, a); \
   } while (0)
   if (!fp32)
     VLBM_STEP(double, double);

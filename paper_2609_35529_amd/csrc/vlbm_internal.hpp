@@ -24,11 +24,12 @@ enum TaskKind : int32_t {
   T_REFLUX = 5,   // hole slot  <- reflux accumulator / r^2 (eq. 2d-reflux)
   T_CAPTURE = 6,  // reflux accumulator (=, or += after the first sub-step) sum_j f_q(R_j)
   // fused two-sub-step launches of the finest level (r = 2):
-  T_RING = 7,      // sub-step 1 of a ring cell: global cell src -> LDS position dst
+  T_RING = 7,      // sub-step 1 of a ring cell: global cell src -> LDS position dst of population q
   T_CAPTURE2 = 8,  // both sub-steps' captures: global R_0 src (stride n0), LDS R_0 n1 (stride j)
   T_NONE = -1,     // host-side only: the slot is an active cell, no task
   TASK_LEDGER = 0x100,  // flag: this task books the boundary ledger (owner tile)
-  TASK_K2 = 0x200,      // flag: sub-step-2 ghost value into LDS position dst (BC source: LDS src)
+  TASK_K2 = 0x200,      // flag: sub-step-2 ghost value into LDS position dst (boundary kinds:
+                        // the tile cell at LDS position src for population q, n1 for q^1)
 };
 
 struct Task {      // 32 bytes
@@ -51,9 +52,22 @@ struct Tile {      // 32 bytes: a w x h rectangle of active cells
   int32_t nring, nk2, ncap;
 };
 
-// Largest fused tile (cells per side); its LDS window is (F+2)^2 positions.
-constexpr int FUSE_SIDE = 16;
-constexpr int FUSE_POS = (FUSE_SIDE + 2) * (FUSE_SIDE + 2);
+// Largest fused tile: FUSE_W x FUSE_H cells (both even). The LDS copy of the
+// intermediate time level keeps, per population q, the tile's cells and the
+// one ring side from which the tile pulls f_q: (w+1) x h positions for q = +-x,
+// w x (h+1) for q = +-y, at most FUSE_POS each. Position of tile-relative cell
+// (cx, cy) in the plane group of q:
+//   +x: cy (w+1) + cx + 1   -x: cy (w+1) + cx   +y: (cy+1) w + cx   -y: cy w + cx
+#ifndef VLBM_FUSE_W
+#define VLBM_FUSE_W 64
+#define VLBM_FUSE_H 4
+#endif
+constexpr int FUSE_W = VLBM_FUSE_W;
+constexpr int FUSE_H = VLBM_FUSE_H;
+constexpr int FUSE_POS = (FUSE_W + 1) * FUSE_H > FUSE_W * (FUSE_H + 1) ? (FUSE_W + 1) * FUSE_H
+                                                                      : FUSE_W * (FUSE_H + 1);
+constexpr int FUSE_THREADS = 256;
+static_assert(FUSE_W % 2 == 0 && FUSE_H % 2 == 0 && FUSE_W * FUSE_H <= FUSE_THREADS, "fused tile shape");
 
 enum StepFlags : int32_t {
   STEP_NT_STORES = 1,        // write the new time level with non-temporal stores
@@ -116,7 +130,8 @@ struct RectArgs {
 };
 
 // Launchers (kernels.hip). All return hipError_t of the launch.
-hipError_t launch_step(const StepLaunch &a, int fp32, hipStream_t s);
+hipError_t launch_step(const StepLaunch &a, int fp32, hipStream_t s, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr);
 hipError_t launch_audit(const void *buf, const Tile *tiles, int ntiles, int64_t plane,
                         int pitch, int fp32, double *partial, hipStream_t s);
 hipError_t launch_set_state(const RectArgs &a, int fp32, int raw_populations, hipStream_t s);

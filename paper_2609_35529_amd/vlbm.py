@@ -92,6 +92,9 @@ vlbm_autotune = _sig("vlbm_autotune", _st, [_P, C.c_int, C.POINTER(C.c_int), C.P
 vlbm_steps = _sig("vlbm_steps", C.c_long, [_P])
 vlbm_active_cells = _sig("vlbm_active_cells", C.c_long, [_P, C.c_int])
 vlbm_sync = _sig("vlbm_sync", _st, [_P])
+vlbm_set_profiling = _sig("vlbm_set_profiling", _st, [_P, C.c_int])
+vlbm_kernel_times = _sig("vlbm_kernel_times", _st, [_P, _D, C.POINTER(C.c_long)])
+MAX_LEVELS = 8
 vlbm_last_error = _sig("vlbm_last_error", C.c_char_p, [])
 
 EXPORTED = ["vlbm_create", "vlbm_destroy", "vlbm_bind_pool", "vlbm_footprint_bytes",
@@ -99,7 +102,8 @@ EXPORTED = ["vlbm_create", "vlbm_destroy", "vlbm_bind_pool", "vlbm_footprint_byt
             "vlbm_get_state", "vlbm_get_populations", "vlbm_conserved_totals", "vlbm_regrid",
             "vlbm_tag", "vlbm_tag_and_regrid", "vlbm_get_boxes", "vlbm_check_health",
             "vlbm_save", "vlbm_load", "vlbm_batch_advance", "vlbm_set_tuning", "vlbm_autotune",
-            "vlbm_steps", "vlbm_active_cells", "vlbm_sync", "vlbm_last_error"]
+            "vlbm_steps", "vlbm_active_cells", "vlbm_sync", "vlbm_last_error",
+            "vlbm_set_profiling", "vlbm_kernel_times"]
 
 
 class VLBMError(RuntimeError):
@@ -271,6 +275,17 @@ class Solver:
 
     def active_cells(self, level):
         return vlbm_active_cells(self._h, int(level))
+
+    def set_profiling(self, enable=True):
+        check(vlbm_set_profiling(self._h, int(bool(enable))))
+
+    def kernel_times(self):
+        """{(level, fused): (total_ms, launches)} for the launches recorded
+        since set_profiling(True)."""
+        ms = (C.c_double * (2 * MAX_LEVELS))()
+        calls = (C.c_long * (2 * MAX_LEVELS))()
+        check(vlbm_kernel_times(self._h, ms, calls))
+        return {(i // 2, bool(i % 2)): (ms[i], calls[i]) for i in range(2 * MAX_LEVELS) if calls[i]}
 
     def set_tuning(self, tile_cells, flags=0):
         check(vlbm_set_tuning(self._h, int(tile_cells), int(flags)))

@@ -185,3 +185,25 @@ def test_batch_rejects_fused_contexts():
         vlbm.batch_advance([a, b], [1, 1])
     b.set_tuning(256, 0)
     vlbm.batch_advance([a, b], [1, 1])
+
+
+def test_kernel_times_count_launches():
+    """Per-kernel timing records every step launch: r^l launches of level l per
+    coarse step, one fused launch per parent step for the finest level."""
+    case = wl.quadrant(n0=64, seed=1, steps=6)
+    g = gpu_solver(case)
+    g.set_profiling(True)
+    g.advance(6)
+    t = g.kernel_times()
+    assert set(t) == {(0, False), (1, False)}
+    assert t[(0, False)][1] == 6 and t[(1, False)][1] == 12
+    assert all(ms > 0 for ms, _ in t.values())
+    g.set_tuning(256, FUSE)
+    g.set_profiling(True)
+    g.advance(5)
+    t = g.kernel_times()
+    assert set(t) == {(0, False), (1, True)}
+    assert t[(0, False)][1] == 5 and t[(1, True)][1] == 5
+    g.set_profiling(False)
+    g.advance(2)
+    assert g.kernel_times() == t
