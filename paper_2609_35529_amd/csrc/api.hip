@@ -22,6 +22,8 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <functional>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -591,6 +593,7 @@ vlbm_status build_fused(vlbm_ctx *c, int l, const std::unordered_map<int64_t, in
 }
 
 vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
+  PhaseTimer tm("build_lists");
   const vlbm_params &p = c->p;
   const int r = p.r;
   int nlev = 0;
@@ -599,106 +602,127 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
   for (int l = 0; l < kMaxLevels && c->lv[l].present; ++l) {
     Level &L = c->lv[l];
     L.cov.assign((size_t)L.fw * L.fh, 0);
-    if (l == 0) {
-      for (int y = 0; y < L.Ny; ++y)
-        for (int x = 0; x < L.Nx; ++x) L.cov[L.fidx(x, y)] = 1;
-    }
+    if (l == 0)
+      for (int y = 0; y < L.Ny; ++y) memset(&L.cov[L.fidx(0, y)], 1, L.Nx);
   }
   for (int b = 0; b < n; ++b) {
     Level &L = c->lv[boxes[b].level];
     for (int y = boxes[b].j0; y < boxes[b].j0 + boxes[b].ny; ++y)
       memset(&L.cov[L.fidx(boxes[b].i0, y)], 1, boxes[b].nx);
   }
-  // proper nesting: a covered cell's parent and the parent's 4 neighbours are covered
-  for (int l = 1; l < kMaxLevels && c->lv[l].present; ++l) {
-    const Level &L = c->lv[l];
-    for (int y = L.fy0 + 1; y < L.fy0 + L.fh - 1; y += r)
-      for (int x = L.fx0 + 1; x < L.fx0 + L.fw - 1; x += r) {
-        if (!L.cov[L.fidx(x, y)]) continue;
-        int px = x / r, py = y / r;
-        for (int d = -1; d < 4; ++d) {
-          int nx = px + (d < 0 ? 0 : CX[d]), ny = py + (d < 0 ? 0 : CY[d]);
-          if (!c->wrap(l - 1, nx, ny)) continue;
-          if (!c->covered(l - 1, nx, ny))
-            return fail(VLBM_ENEST,
-                        "level %d cell (%d,%d): parent neighbour (%d,%d) not covered at level %d",
-                        l, x, y, nx, ny, l - 1);
+  // proper nesting: a covered cell's parent and the parent's 4 neighbours are
+  // covered. Per box: its parent rectangle, widened by one cell along x on its
+  // rows and along y on its columns (wrapped on periodic axes; cells outside a
+  // non-periodic side are exempt).
+  for (int b = 0; b < n; ++b) {
+    const int l = boxes[b].level;
+    if (l < 1) continue;
+    const Level &PL = c->lv[l - 1];
+    const int x0 = boxes[b].i0 / r, x1 = (boxes[b].i0 + boxes[b].nx) / r;
+    const int y0 = boxes[b].j0 / r, y1 = (boxes[b].j0 + boxes[b].ny) / r;
+    auto need = [&](int qx, int qy, int px, int py) -> vlbm_status {
+      int wx = qx, wy = qy;
+      if (!c->wrap(l - 1, wx, wy) || c->covered(l - 1, wx, wy)) return VLBM_OK;
+      return fail(VLBM_ENEST, "level %d cell (%d,%d): parent neighbour (%d,%d) not covered at level %d",
+                  l, px * r, py * r, wx, wy, l - 1);
+    };
+    for (int y = y0; y < y1; ++y) {
+      if (PL.in_frame(x0, y) && PL.in_frame(x1 - 1, y)) {
+        const uint8_t *row = &PL.cov[PL.fidx(x0, y)];
+        const void *z = memchr(row, 0, x1 - x0);
+        if (z) {
+          const int x = x0 + (int)(static_cast<const uint8_t *>(z) - row);
+          return need(x, y, x, y);
+        }
+      } else {
+        for (int x = x0; x < x1; ++x) {
+          vlbm_status st = need(x, y, x, y);
+          if (st) return st;
         }
       }
+      vlbm_status st = need(x0 - 1, y, x0, y);
+      if (!st) st = need(x1, y, x1 - 1, y);
+      if (st) return st;
+    }
+    for (int x = x0; x < x1; ++x) {
+      vlbm_status st = need(x, y0 - 1, x, y0);
+      if (!st) st = need(x, y1, x, y1 - 1);
+      if (st) return st;
+    }
   }
-  // status
-  for (int l = 0; l < kMaxLevels && c->lv[l].present; ++l) {
-    Level &L = c->lv[l];
-    L.status.assign(L.cov.size(), 0);
-    for (int y = L.fy0; y < L.fy0 + L.fh; ++y)
-      for (int x = L.fx0; x < L.fx0 + L.fw; ++x) {
-        size_t i = L.fidx(x, y);
-        if (!L.cov[i]) continue;
-        L.status[i] = c->covered(l + 1, x * r, y * r) ? 2 : 1;
-      }
+  tm.mark("coverage+nesting");
+  // status: covered cells are active (1), those under a finer box are holes (2)
+  for (int l = 0; l < kMaxLevels && c->lv[l].present; ++l) c->lv[l].status = c->lv[l].cov;
+  for (int b = 0; b < n; ++b) {
+    const int l = boxes[b].level;
+    if (l < 1) continue;
+    Level &PL = c->lv[l - 1];
+    const int x0 = boxes[b].i0 / r, x1 = (boxes[b].i0 + boxes[b].nx) / r;
+    for (int y = boxes[b].j0 / r; y < (boxes[b].j0 + boxes[b].ny) / r; ++y)
+      memset(&PL.status[PL.fidx(x0, y)], 2, x1 - x0);
   }
-  // tiles: runs of active cells per row, stacked into rectangles of <= tile_cells
+  tm.mark("status");
+  // Per level, two passes; the levels of a pass run on threads of their own.
+  // Pass A: tiles, cell -> tile map, ghost tasks, reflux and ledger slots.
+  // Pass B (needs the parent's reflux slots): captures, task order, fused lists.
+  struct Work {
+    std::vector<int32_t> owner;                 // frame cell -> tile
+    std::vector<std::pair<int, Task>> tk;       // (tile, task)
+    std::unordered_map<int64_t, int> bc_slot;   // (cell, q) -> ledger slot (fused level)
+    std::vector<std::pair<int64_t, Task>> caps; // (cell R_0 as y * Nx + x, capture) (fused level)
+    bool fuse = false;
+    vlbm_status st = VLBM_OK;
+    std::string err;
+  };
+  std::vector<Work> W(nlev);
   const int TC = c->tile_cells;
-  for (int l = 0; l < kMaxLevels && c->lv[l].present; ++l) {
+  auto passA = [&](int l) -> vlbm_status {
     Level &L = c->lv[l];
+    Work &w = W[l];
+    // tiles: runs of active cells per row, stacked into rectangles of <= TC cells
     L.tiles.clear();
-    std::map<std::pair<int, int>, Tile> open;  // (xa, xb) -> rectangle being grown
-    std::vector<std::pair<int, int>> rect_xy;  // (x0, y0) of each emitted tile, for lookup
-    auto emit = [&](int xa, int y0, const Tile &t) {
+    struct Open { int xa, xb, y0, h; };
+    std::vector<Open> open, nopen;
+    std::vector<std::pair<int, int>> rect_xy;  // (x0, y0) of each emitted tile
+    auto emit = [&](const Open &o) {
       // split wide rectangles (h == 1) into chunks of at most TC cells
-      int w = t.w;
-      for (int x = 0; x < w; x += TC) {
+      for (int x = o.xa; x < o.xb; x += TC) {
         Tile u{};
-        u.w = std::min(TC, w - x);
-        u.h = t.h;
-        u.off0 = (int32_t)L.off(xa + x, y0);
+        u.w = std::min(TC, o.xb - x);
+        u.h = o.h;
+        u.off0 = (int32_t)L.off(x, o.y0);
         L.tiles.push_back(u);
-        rect_xy.push_back({xa + x, y0});
+        rect_xy.push_back({x, o.y0});
       }
     };
-    std::vector<std::pair<int, int>> runs;
-    std::map<std::pair<int, int>, int> open_y0;
     for (int y = L.fy0; y < L.fy0 + L.fh; ++y) {
-      runs.clear();
-      int x = L.fx0;
-      while (x < L.fx0 + L.fw) {
-        if (L.status[L.fidx(x, y)] == 1) {
-          int xa = x;
-          while (x < L.fx0 + L.fw && L.status[L.fidx(x, y)] == 1) ++x;
-          runs.push_back({xa, x});
-        } else {
+      nopen.clear();
+      const uint8_t *row = &L.status[L.fidx(L.fx0, y)];
+      size_t j = 0;  // open rectangles are ordered by xa, like the runs of a row
+      int x = 0;
+      while (x < L.fw) {
+        if (row[x] != 1) {
           ++x;
+          continue;
         }
-      }
-      std::map<std::pair<int, int>, Tile> nopen;
-      std::map<std::pair<int, int>, int> nopen_y0;
-      for (auto &rn : runs) {
-        int w = rn.second - rn.first;
-        int maxh = std::max(1, TC / w);
-        auto it = open.find(rn);
-        if (it != open.end() && it->second.h < maxh) {
-          Tile t = it->second;
-          t.h += 1;
-          nopen[rn] = t;
-          nopen_y0[rn] = open_y0[rn];
-          open.erase(it);
-        } else {
-          if (it != open.end()) {
-            emit(rn.first, open_y0[rn], it->second);
-            open.erase(it);
+        const int xa = x;
+        while (x < L.fw && row[x] == 1) ++x;
+        const int a = L.fx0 + xa, b = L.fx0 + x, maxh = std::max(1, TC / (b - a));
+        while (j < open.size() && open[j].xa < a) emit(open[j++]);
+        if (j < open.size() && open[j].xa == a && open[j].xb == b) {
+          if (open[j].h < maxh) {
+            nopen.push_back({a, b, open[j].y0, open[j].h + 1});
+            ++j;
+            continue;
           }
-          Tile t{};
-          t.w = w;
-          t.h = 1;
-          nopen[rn] = t;
-          nopen_y0[rn] = y;
+          emit(open[j++]);
         }
+        nopen.push_back({a, b, y, 1});
       }
-      for (auto &kv : open) emit(kv.first.first, open_y0[kv.first], kv.second);
+      while (j < open.size()) emit(open[j++]);
       open.swap(nopen);
-      open_y0.swap(nopen_y0);
     }
-    for (auto &kv : open) emit(kv.first.first, open_y0[kv.first], kv.second);
+    for (const Open &o : open) emit(o);
     // order tiles by (y0, x0) for locality
     std::vector<int> order(L.tiles.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
@@ -706,40 +730,37 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
       return rect_xy[a].second != rect_xy[b].second ? rect_xy[a].second < rect_xy[b].second
                                                     : rect_xy[a].first < rect_xy[b].first;
     });
-    std::vector<Tile> sorted;
-    std::vector<std::pair<int, int>> sxy;
-    for (int i : order) {
-      sorted.push_back(L.tiles[i]);
-      sxy.push_back(rect_xy[i]);
+    std::vector<Tile> sorted(order.size());
+    std::vector<std::pair<int, int>> sxy(order.size());
+    for (size_t i = 0; i < order.size(); ++i) {
+      sorted[i] = L.tiles[order[i]];
+      sxy[i] = rect_xy[order[i]];
     }
     L.tiles.swap(sorted);
     rect_xy.swap(sxy);
     // cell -> tile map (frame cells)
-    std::vector<int32_t> owner(L.cov.size(), -1);
+    w.owner.assign(L.cov.size(), -1);
     for (size_t t = 0; t < L.tiles.size(); ++t)
-      for (int yy = 0; yy < L.tiles[t].h; ++yy)
-        for (int xx = 0; xx < L.tiles[t].w; ++xx)
-          owner[L.fidx(rect_xy[t].first + xx, rect_xy[t].second + yy)] = (int32_t)t;
-    // tasks
-    std::vector<std::pair<int, Task>> tk;  // (tile, task)
+      for (int yy = 0; yy < L.tiles[t].h; ++yy) {
+        int32_t *o = &w.owner[L.fidx(rect_xy[t].first, rect_xy[t].second + yy)];
+        std::fill(o, o + L.tiles[t].w, (int32_t)t);
+      }
+    // ghost tasks
     L.acc_slot.clear();
     L.nledger = 0;
     // the finest level of a two-level-or-deeper hierarchy with r = 2 also gets
     // the lists of the fused two-sub-step launch
-    const bool fuse = (c->step_flags & STEP_FUSE2) && l >= 1 && l == nlev - 1 && r == 2;
-    std::unordered_map<int64_t, int> bc_slot;     // (cell, q) -> ledger slot
-    std::vector<std::pair<int64_t, Task>> caps;   // (cell R_0 as y * Nx + x, capture)
+    w.fuse = (c->step_flags & STEP_FUSE2) && l >= 1 && l == nlev - 1 && r == 2;
     const int fw = L.fw;
-    for (int y = L.fy0 + 1; y < L.fy0 + L.fh - 1; ++y)
-      for (int x = L.fx0 + 1; x < L.fx0 + L.fw - 1; ++x) {
-        const size_t ci = L.fidx(x, y);
-        if (L.status[ci] != 1) continue;
+    for (int y = L.fy0 + 1; y < L.fy0 + L.fh - 1; ++y) {
+      const uint8_t *st = &L.status[L.fidx(L.fx0, y)];
+      for (int xi = 1; xi < fw - 1; ++xi) {
+        if (st[xi] != 1) continue;
         // interior cell: all four upwind neighbours active at this level (hence
         // inside the domain) -> plain pulls, no task
-        if (L.status[ci - 1] == 1 && L.status[ci + 1] == 1 && L.status[ci - fw] == 1 &&
-            L.status[ci + fw] == 1)
-          continue;
-        const int tile = owner[ci];
+        if (st[xi - 1] == 1 && st[xi + 1] == 1 && st[xi - fw] == 1 && st[xi + fw] == 1) continue;
+        const int x = L.fx0 + xi;
+        const int tile = w.owner[L.fidx(x, y)];
         for (int q = 0; q < 4; ++q) {
           Task t{};
           vlbm_status gs = ghost_task(c, l, x, y, q, t);
@@ -748,26 +769,35 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
           const int kind = t.kind & 0xFF;
           if (kind == T_OUTFLOW || kind == T_REFLECT || kind == T_INFLOW) {
             t.slot = L.nledger++;
-            if (fuse) bc_slot[((int64_t)y * L.Nx + x) * 4 + q] = t.slot;
+            if (w.fuse) w.bc_slot[((int64_t)y * L.Nx + x) * 4 + q] = t.slot;
           } else if (kind == T_REFLUX) {
             int64_t key = ((int64_t)y * L.Nx + x) * 4 + q;
             int slot = (int)L.acc_slot.size();
             L.acc_slot[key] = slot;
             t.slot = slot;
           }
-          tk.push_back({tile, t});
+          w.tk.push_back({tile, t});
         }
       }
+    }
+    L.nacc = (int)L.acc_slot.size();
+    return VLBM_OK;
+  };
+  auto passB = [&](int l) -> vlbm_status {
+    Level &L = c->lv[l];
+    Work &w = W[l];
+    std::vector<std::pair<int, Task>> &tk = w.tk;
     // captures: values leaving level l towards the parent's ring cells
     if (l >= 1) {
       const Level &PL = c->lv[l - 1];
       std::unordered_map<int, size_t> cap;  // parent slot -> index in tk
-      std::vector<int> count;
-      for (int y = L.fy0 + 1; y < L.fy0 + L.fh - 1; ++y)
-        for (int x = L.fx0 + 1; x < L.fx0 + L.fw - 1; ++x) {
-          const size_t ci = L.fidx(x, y);
-          if (L.status[ci] != 1) continue;
-          if (L.cov[ci - 1] && L.cov[ci + 1] && L.cov[ci - L.fw] && L.cov[ci + L.fw]) continue;
+      for (int y = L.fy0 + 1; y < L.fy0 + L.fh - 1; ++y) {
+        const uint8_t *st = &L.status[L.fidx(L.fx0, y)];
+        const uint8_t *cv = &L.cov[L.fidx(L.fx0, y)];
+        for (int xi = 1; xi < L.fw - 1; ++xi) {
+          if (st[xi] != 1) continue;
+          if (cv[xi - 1] && cv[xi + 1] && cv[xi - L.fw] && cv[xi + L.fw]) continue;
+          const int x = L.fx0 + xi;
           for (int q = 0; q < 4; ++q) {
             int dx = x + CX[q], dy = y + CY[q];
             if (!c->wrap(l, dx, dy)) continue;
@@ -787,9 +817,8 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
               t.n1 = -1;
               t.slot = it->second;
               cap[it->second] = tk.size();
-              tk.push_back({owner[L.fidx(x, y)], t});
-              if (fuse) caps.push_back({(int64_t)y * L.Nx + x, t});
-              count.push_back(1);
+              tk.push_back({w.owner[L.fidx(x, y)], t});
+              if (w.fuse) w.caps.push_back({(int64_t)y * L.Nx + x, t});
             } else {
               Task &t = tk[ct->second].second;
               int64_t want = (int64_t)t.src + (int64_t)t.n0 * (t.j + 1);
@@ -799,6 +828,7 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
             }
           }
         }
+      }
       for (auto &kv : cap)
         if (tk[kv.second].second.j + 1 != r)
           return fail(VLBM_ENEST, "internal: ring cell sees %d fine cells, expected %d",
@@ -809,6 +839,7 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
                        return a.first < b.first;
                      });
     L.tasks.clear();
+    L.tasks.reserve(tk.size());
     for (auto &t : L.tiles) t.task0 = t.ntask = 0;
     for (size_t i = 0; i < tk.size(); ++i) {
       Tile &t = L.tiles[tk[i].first];
@@ -816,15 +847,35 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
       t.ntask += 1;
       L.tasks.push_back(tk[i].second);
     }
-    L.nacc = (int)L.acc_slot.size();
     L.ftiles.clear();
     L.ftasks.clear();
-    if (fuse) {
-      vlbm_status fs = build_fused(c, l, bc_slot, caps);
-      if (fs) return fs;
-    }
-  }
-  return VLBM_OK;
+    if (w.fuse) return build_fused(c, l, w.bc_slot, w.caps);
+    return VLBM_OK;
+  };
+  // Run one pass over all levels, each on its own thread (level 0 on this
+  // one). Failure messages are per thread; the lowest failing level's is kept.
+  auto run_pass = [&](const std::function<vlbm_status(int)> &pass) -> vlbm_status {
+    std::vector<std::thread> th;
+    for (int l = 1; l < nlev; ++l)
+      th.emplace_back([&, l] {
+        W[l].st = pass(l);
+        if (W[l].st) W[l].err = g_err;
+      });
+    W[0].st = pass(0);
+    if (W[0].st) W[0].err = g_err;
+    for (auto &t : th) t.join();
+    for (int l = 0; l < nlev; ++l)
+      if (W[l].st) {
+        g_err = W[l].err;
+        return W[l].st;
+      }
+    return VLBM_OK;
+  };
+  vlbm_status st = run_pass(passA);
+  tm.mark("tiles+tasks");
+  if (!st) st = run_pass(passB);
+  tm.mark("captures+order+fused");
+  return st;
 }
 
 vlbm_status upload_level(vlbm_ctx *c, Level &L, bool alloc_buffers) {
@@ -1373,72 +1424,97 @@ vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes, bool res
   return st;
 }
 
-// Clustering for tag_and_regrid: level-l tags (after dilation) restricted to
-// cells whose four neighbours are covered at level l, covered by a tile grid of
-// side ceil(min_box / r) level-l cells; marked tiles merge greedily into
-// rectangles, first along rows, then stacking equal row runs, with sides of at
-// most max_box level-(l+1) cells.
+int level_nx(const vlbm_ctx *c, int l);
+int level_ny(const vlbm_ctx *c, int l);
+
+// Clustering for tag_and_regrid: level-l tags, dilated by a square of radius
+// `buffer` (periodic axes wrap, other axes clip), restricted to cells whose
+// four neighbours are covered at level l (neighbours outside a non-periodic
+// side exempt), covered by a tile grid of side ceil(min_box / r) level-l
+// cells; marked tiles merge greedily into rectangles, first along rows, then
+// stacking equal row runs, with sides of at most max_box level-(l+1) cells.
+// Work is per tagged cell and per reached tile, not per level cell: a tile
+// holds a dilated tag iff a tag lies within `buffer` of it, and it is free of
+// disallowed cells iff its rows widened by one column and its columns widened
+// by one row are covered.
 void cluster_level(vlbm_ctx *c, int l, const std::vector<uint8_t> &tags, const std::vector<uint8_t> &cov,
                    int buffer, int min_box, int max_box, std::vector<vlbm_box> &out) {
   const int r = c->p.r;
-  long s = 1;
-  for (int i = 0; i < l; ++i) s *= r;
-  const int Nx = (int)(c->p.nx0 * s), Ny = (int)(c->p.ny0 * s);
-  // dilation by a square of radius `buffer`: two 1-D passes with running
-  // counts (periodic axes wrap, other axes clip)
-  auto dilate1d = [&](const uint8_t *src, uint8_t *dst, int n, size_t stride, bool periodic) {
-    std::vector<int> pre(n + 1, 0);
-    for (int i = 0; i < n; ++i) pre[i + 1] = pre[i] + (src[i * stride] ? 1 : 0);
-    auto cnt = [&](int a, int b) {  // tags in [a, b], a <= b, possibly outside [0, n)
-      if (!periodic) {
-        a = std::max(a, 0);
-        b = std::min(b, n - 1);
-        return a <= b ? pre[b + 1] - pre[a] : 0;
-      }
-      if (b - a + 1 >= n) return pre[n];
-      int am = ((a % n) + n) % n, bm = ((b % n) + n) % n;
-      return am <= bm ? pre[bm + 1] - pre[am] : (pre[n] - pre[am]) + pre[bm + 1];
-    };
-    for (int i = 0; i < n; ++i) dst[i * stride] = cnt(i - buffer, i + buffer) > 0;
-  };
-  std::vector<uint8_t> tx(tags.size(), 0), dil(tags.size(), 0);
-  for (int y = 0; y < Ny; ++y) dilate1d(&tags[(size_t)y * Nx], &tx[(size_t)y * Nx], Nx, 1, c->perx());
-  for (int x = 0; x < Nx; ++x) dilate1d(&tx[x], &dil[x], Ny, (size_t)Nx, c->pery());
-  // allowed region: covered with all four neighbours covered (proper nesting);
-  // neighbours outside a non-periodic side are exempt
-  std::vector<uint8_t> bad((size_t)Nx * Ny, 0);
-  for (int y = 0; y < Ny; ++y) {
-    const int ym = y > 0 ? y - 1 : (c->pery() ? Ny - 1 : -1);
-    const int yp = y + 1 < Ny ? y + 1 : (c->pery() ? 0 : -1);
-    for (int x = 0; x < Nx; ++x) {
-      const int xm = x > 0 ? x - 1 : (c->perx() ? Nx - 1 : -1);
-      const int xp = x + 1 < Nx ? x + 1 : (c->perx() ? 0 : -1);
-      const size_t row = (size_t)y * Nx;
-      bool ok = cov[row + x] && (xm < 0 || cov[row + xm]) && (xp < 0 || cov[row + xp]) &&
-                (ym < 0 || cov[(size_t)ym * Nx + x]) && (yp < 0 || cov[(size_t)yp * Nx + x]);
-      bad[row + x] = !ok;
-    }
-  }
-  // 2-D prefix sums: O(1) "any dilated tag" and "any disallowed cell" per tile
-  std::vector<int32_t> pt((size_t)(Nx + 1) * (Ny + 1), 0), pb((size_t)(Nx + 1) * (Ny + 1), 0);
-  for (int y = 0; y < Ny; ++y)
-    for (int x = 0; x < Nx; ++x) {
-      const size_t i = (size_t)(y + 1) * (Nx + 1) + (x + 1);
-      pt[i] = dil[(size_t)y * Nx + x] + pt[i - 1] + pt[i - (Nx + 1)] - pt[i - (Nx + 1) - 1];
-      pb[i] = bad[(size_t)y * Nx + x] + pb[i - 1] + pb[i - (Nx + 1)] - pb[i - (Nx + 1) - 1];
-    }
-  auto rect = [&](const std::vector<int32_t> &P, int x0, int y0, int x1, int y1) {
-    const size_t W = Nx + 1;
-    return P[(size_t)y1 * W + x1] - P[(size_t)y0 * W + x1] - P[(size_t)y1 * W + x0] + P[(size_t)y0 * W + x0];
-  };
+  const int Nx = level_nx(c, l), Ny = level_ny(c, l);
+  const bool px = c->perx(), py = c->pery();
   const int T = std::max(1, (min_box + r - 1) / r);
   const int maxT = std::max(1, max_box / (T * r));
   const int ntx = (Nx + T - 1) / T, nty = (Ny + T - 1) / T;
+  // tiles reached by the dilation of each tag
+  std::vector<uint8_t> hit((size_t)ntx * nty, 0);
+  std::vector<int> cols, rows;
+  auto tiles_in = [&](int a, int b, int n, bool periodic, std::vector<int> &v) {
+    v.clear();
+    if (periodic && b - a + 1 >= n) a = 0, b = n - 1, periodic = false;
+    if (!periodic) {
+      a = std::max(a, 0);
+      b = std::min(b, n - 1);
+      for (int t = a / T; a <= b && t <= b / T; ++t) v.push_back(t);
+      return;
+    }
+    const int am = ((a % n) + n) % n, bm = ((b % n) + n) % n;
+    if (am <= bm) {
+      for (int t = am / T; t <= bm / T; ++t) v.push_back(t);
+    } else {  // wraps: [am, n) and [0, bm]
+      for (int t = 0; t <= bm / T; ++t) v.push_back(t);
+      for (int t = am / T; t <= (n - 1) / T; ++t)
+        if (v.empty() || t > v.back()) v.push_back(t);
+    }
+  };
+  const uint8_t *tg = tags.data();
+  const size_t n = tags.size();
+  for (size_t i = 0; i < n;) {
+    if (i + 8 <= n && (i & 7) == 0) {
+      uint64_t w;
+      memcpy(&w, tg + i, 8);
+      if (!w) {
+        i += 8;
+        continue;
+      }
+    }
+    if (tg[i]) {
+      const int y = (int)(i / Nx), x = (int)(i % Nx);
+      tiles_in(x - buffer, x + buffer, Nx, px, cols);
+      tiles_in(y - buffer, y + buffer, Ny, py, rows);
+      for (int ty : rows)
+        for (int tx : cols) hit[(size_t)ty * ntx + tx] = 1;
+    }
+    ++i;
+  }
+  // reached tiles that hold no disallowed cell
+  auto covered_at = [&](int x, int y) {  // true outside a non-periodic side
+    if (x < 0 || x >= Nx) {
+      if (!px) return true;
+      x = (x + Nx) % Nx;
+    }
+    if (y < 0 || y >= Ny) {
+      if (!py) return true;
+      y = (y + Ny) % Ny;
+    }
+    return cov[(size_t)y * Nx + x] != 0;
+  };
   std::vector<uint8_t> mark((size_t)ntx * nty, 0);
   for (int ty = 0; ty < nty; ++ty)
-    for (int tx2 = 0; tx2 < ntx; ++tx2) {
-      const int x0 = tx2 * T, y0 = ty * T, x1 = std::min(Nx, x0 + T), y1 = std::min(Ny, y0 + T);
-      mark[(size_t)ty * ntx + tx2] = rect(pt, x0, y0, x1, y1) > 0 && rect(pb, x0, y0, x1, y1) == 0;
+    for (int tx = 0; tx < ntx; ++tx) {
+      if (!hit[(size_t)ty * ntx + tx]) continue;
+      const int x0 = tx * T, y0 = ty * T, x1 = std::min(Nx, x0 + T), y1 = std::min(Ny, y0 + T);
+      bool ok = true;
+      for (int y = y0; ok && y < y1; ++y) {
+        const uint8_t *row = &cov[(size_t)y * Nx];
+        for (int x = x0; x < x1; ++x)
+          if (!row[x]) {
+            ok = false;
+            break;
+          }
+        ok = ok && covered_at(x0 - 1, y) && covered_at(x1, y);
+      }
+      for (int x = x0; ok && x < x1; ++x) ok = covered_at(x, y0 - 1) && covered_at(x, y1);
+      mark[(size_t)ty * ntx + tx] = ok;
     }
   // greedy merge: row runs of at most maxT tiles, stacked while identical
   struct Run { int a, b, y0, h; };
@@ -1460,16 +1536,72 @@ void cluster_level(vlbm_ctx *c, int l, const std::vector<uint8_t> &tags, const s
     }
     for (auto &o : open) {
       bool cont = false;
-      for (auto &n : next)
-        if (n.a == o.a && n.b == o.b && n.h == 1 && o.h < maxT) {
-          n.y0 = o.y0;
-          n.h = o.h + 1;
+      for (auto &nx2 : next)
+        if (nx2.a == o.a && nx2.b == o.b && nx2.h == 1 && o.h < maxT) {
+          nx2.y0 = o.y0;
+          nx2.h = o.h + 1;
           cont = true;
           break;
         }
       if (!cont) emit(o);
     }
     open = next;
+  }
+}
+
+
+int level_nx(const vlbm_ctx *c, int l) {
+  long s = 1;
+  for (int i = 0; i < l; ++i) s *= c->p.r;
+  return (int)(c->p.nx0 * s);
+}
+int level_ny(const vlbm_ctx *c, int l) {
+  long s = 1;
+  for (int i = 0; i < l; ++i) s *= c->p.r;
+  return (int)(c->p.ny0 * s);
+}
+
+// Boxes of a new hierarchy from per-level tags (levels 0..max_levels-1; a
+// level without tags is an empty vector or all zero). A tagged finer cell tags
+// its parent, so refined features keep their levels; then each level is
+// clustered inside the coverage of the boxes just made for it.
+void cluster_hierarchy(vlbm_ctx *c, std::vector<std::vector<uint8_t>> &tags, int buffer, int min_box,
+                       int max_box, std::vector<vlbm_box> &boxes) {
+  const int r = c->p.r, ML = c->p.max_levels;
+  for (int l = ML - 1; l >= 1; --l) {
+    if (tags[l].empty() || tags[l - 1].empty()) continue;
+    const int Nxl = level_nx(c, l), Nxp = level_nx(c, l - 1);
+    const uint8_t *t = tags[l].data();
+    const size_t n = tags[l].size();
+    size_t i = 0;
+    while (i < n) {
+      if (i + 8 <= n && (i & 7) == 0) {  // skip untagged words
+        uint64_t w;
+        memcpy(&w, t + i, 8);
+        if (!w) {
+          i += 8;
+          continue;
+        }
+      }
+      if (t[i]) {
+        const int y = (int)(i / Nxl), x = (int)(i % Nxl);
+        tags[l - 1][(size_t)(y / r) * Nxp + x / r] = 1;
+      }
+      ++i;
+    }
+  }
+  std::vector<uint8_t> cov((size_t)level_nx(c, 0) * level_ny(c, 0), 1);
+  for (int l = 0; l + 1 < ML; ++l) {
+    if (tags[l].empty()) break;
+    size_t before = boxes.size();
+    cluster_level(c, l, tags[l], cov, buffer, min_box, max_box, boxes);
+    if (boxes.size() == before || l + 2 >= ML) break;
+    const int Nx1 = level_nx(c, l + 1);
+    std::vector<uint8_t> ncov((size_t)Nx1 * level_ny(c, l + 1), 0);
+    for (size_t b = before; b < boxes.size(); ++b)
+      for (int y = boxes[b].j0; y < boxes[b].j0 + boxes[b].ny; ++y)
+        memset(&ncov[(size_t)y * Nx1 + boxes[b].i0], 1, boxes[b].nx);
+    cov.swap(ncov);
   }
 }
 
@@ -1725,17 +1857,12 @@ vlbm_status vlbm_tag_and_regrid(vlbm_ctx *c, double thr, int buffer, int min_box
   if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "no hierarchy installed");
   if (buffer < 0 || min_box < 1 || max_box < min_box) return fail(VLBM_EINVAL, "bad clustering sizes");
   PhaseTimer tm("tag_and_regrid");
-  const int r = c->p.r, ML = c->p.max_levels;
+  const int ML = c->p.max_levels;
   if (ML < 2) return VLBM_OK;
   std::vector<std::vector<uint8_t>> tags(ML);
-  std::vector<int> Nx(ML), Ny(ML);
   for (int l = 0; l < ML; ++l) {
-    long s = 1;
-    for (int i = 0; i < l; ++i) s *= r;
-    Nx[l] = (int)(c->p.nx0 * s);
-    Ny[l] = (int)(c->p.ny0 * s);
     if (l + 1 < ML || l < c->nlev) {
-      tags[l].assign((size_t)Nx[l] * Ny[l], 0);
+      tags[l].assign((size_t)level_nx(c, l) * level_ny(c, l), 0);
       if (l < c->nlev) {
         vlbm_status st = vlbm_tag(c, l, thr, tags[l].data());
         if (st) return st;
@@ -1743,39 +1870,8 @@ vlbm_status vlbm_tag_and_regrid(vlbm_ctx *c, double thr, int buffer, int min_box
     }
   }
   tm.mark("tags");
-  // a tagged finer cell tags its parent: refined features keep their levels
-  for (int l = std::min(c->nlev, ML) - 1; l >= 1; --l) {
-    const uint8_t *t = tags[l].data();
-    const size_t n = tags[l].size();
-    size_t i = 0;
-    while (i < n) {
-      if (i + 8 <= n && (i & 7) == 0) {  // skip untagged words
-        uint64_t w;
-        memcpy(&w, t + i, 8);
-        if (!w) {
-          i += 8;
-          continue;
-        }
-      }
-      if (t[i]) {
-        const int y = (int)(i / Nx[l]), x = (int)(i % Nx[l]);
-        tags[l - 1][(size_t)(y / r) * Nx[l - 1] + x / r] = 1;
-      }
-      ++i;
-    }
-  }
   std::vector<vlbm_box> boxes;
-  std::vector<uint8_t> cov((size_t)Nx[0] * Ny[0], 1);
-  for (int l = 0; l + 1 < ML; ++l) {
-    size_t before = boxes.size();
-    cluster_level(c, l, tags[l], cov, buffer, min_box, max_box, boxes);
-    if (boxes.size() == before) break;
-    std::vector<uint8_t> ncov((size_t)Nx[l + 1] * Ny[l + 1], 0);
-    for (size_t b = before; b < boxes.size(); ++b)
-      for (int y = boxes[b].j0; y < boxes[b].j0 + boxes[b].ny; ++y)
-        memset(&ncov[(size_t)y * Nx[l + 1] + boxes[b].i0], 1, boxes[b].nx);
-    cov.swap(ncov);
-  }
+  cluster_hierarchy(c, tags, buffer, min_box, max_box, boxes);
   tm.mark("cluster");
   return vlbm_regrid(c, boxes.data(), (int)boxes.size());
 }
