@@ -37,6 +37,13 @@ MEASURED_TRAFFIC = {"kernel_sha256_16": "452cc9b0e1bc9c84", "workload": "quadran
                     "bytes_per_launch": 77724347.6}
 
 
+# dynamic-refinement workloads: re-tag and regrid every few coarse steps
+# (the density-gradient indicator is per cell, so it halves with each level
+# on a smeared layer: the shear layer needs a lower threshold to keep level 3)
+DYNAMIC = {"shock_bubble": {"max_box": 64, "threshold": 0.05},
+           "kh_strip": {"max_box": 128, "threshold": 0.01}}
+
+
 def kernel_hash():
     import hashlib
     path = os.path.join(ROOT, "paper_2609_35529_amd", "csrc", "kernels.hip")
@@ -51,6 +58,8 @@ def build_case(name, steps):
         return wl.sod_2d(steps=steps)
     if name == "shock_bubble":
         return wl.shock_bubble(steps=steps)
+    if name == "kh_strip":
+        return wl.kelvin_helmholtz_strip(steps=steps)
     if name == "uniform4096":
         import numpy as np
         n = 4096
@@ -63,9 +72,20 @@ def actual_updates_per_step(case):
     return case.actual_updates_per_coarse_step()
 
 
-def cpu_baseline(case, budget_s=15.0):
-    """The oracle, single-threaded, on a bounded prefix of the same workload."""
+def cpu_baseline(case, budget_s=15.0, boxes=None, mem_cap=8e9):
+    """The oracle, single-threaded, on a bounded prefix of the same workload.
+    A dynamic workload is sampled on the hierarchy the GPU run starts its timed
+    region with (`boxes`), held fixed. The oracle keeps three dense arrays of
+    16 doubles per cell of every level; above mem_cap bytes it is not run."""
     from tests import exact
+    if boxes is not None:
+        import dataclasses
+        case = dataclasses.replace(case, boxes=list(boxes))
+    need = sum(3 * 16 * 8 * (case.nx0 * case.r ** l) * (case.ny0 * case.r ** l)
+               for l in range(case.nlev))
+    if need > mem_cap:
+        return {"value": None, "unit": "fine-equiv cell updates/s", "cores": 1, "kind": "oracle",
+                "sample": f"not run: the oracle's dense level arrays need {need / 1e9:.0f} GB"}
     o = exact.run_oracle(case, steps=0)
     t0 = time.perf_counter()
     n = 0
@@ -74,8 +94,10 @@ def cpu_baseline(case, budget_s=15.0):
         n += 1
     el = time.perf_counter() - t0
     fe = case.fine_equivalent_per_coarse_step() * n / el
+    held = f", hierarchy of the GPU run's timed region ({len(boxes)} boxes) held fixed" if boxes else ""
     return {"value": fe, "unit": "fine-equiv cell updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{case.name} full size, first {n} coarse steps ({el:.1f} s), FP64, one thread"}
+            "sample": f"{case.name} full size, first {n} coarse steps ({el:.1f} s){held}, FP64, "
+                      f"one thread"}
 
 
 def copy_probe(gib=2.0, reps=20):
@@ -146,10 +168,12 @@ def main():
                     help="fp32s: FP32 storage, relaxation evaluated in FP64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--amr-threshold", type=float, default=0.05)
+    ap.add_argument("--amr-threshold", type=float, default=None,
+                    help="density-gradient tag threshold (default: the workload's)")
     ap.add_argument("--amr-buffer", type=int, default=4)
     ap.add_argument("--amr-min-box", type=int, default=16)
-    ap.add_argument("--amr-max-box", type=int, default=64)
+    ap.add_argument("--amr-max-box", type=int, default=0,
+                    help="largest box side in fine cells (0: the workload's default)")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch autotuner")
     ap.add_argument("--tile-cells", type=int, default=0, help="fixed launch tuning (skips the autotuner)")
     ap.add_argument("--flags", type=int, default=0, help="launch flags with --tile-cells")
@@ -168,7 +192,7 @@ def main():
     if args.copy_probe:
         print(json.dumps(copy_probe()))
         return
-    if args.workload == "shock_bubble":
+    if args.workload in DYNAMIC:
         args.no_tune = True  # the hierarchy changes every few steps
     if args.serve_only:
         print(json.dumps(serve_benchmark(args.requests, args.rate,
@@ -199,7 +223,11 @@ def main():
         print(f"[bench] {case.name} autotune", file=sys.stderr, flush=True)
         tile, flags = solver.autotune(steps_per_trial=args.tune_steps)
         tuning = {"tile_cells": tile, "flags": flags}
-    dynamic = case.name == "shock_bubble"
+    dynamic = case.name in DYNAMIC
+    if dynamic and args.amr_max_box == 0:
+        args.amr_max_box = DYNAMIC[case.name]["max_box"]
+    if dynamic and args.amr_threshold is None:
+        args.amr_threshold = DYNAMIC[case.name]["threshold"]
     regrid_every = 5
     amr = {"regrids": 0, "boxes": [], "regrid_s": 0.0, "updates": 0}
 
@@ -242,6 +270,7 @@ def main():
     run(args.warmup)
     torch.cuda.synchronize()
     amr.update(regrids=0, boxes=[], regrid_s=0.0, updates=0)
+    timed_boxes = solver.boxes() if dynamic else None
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -252,6 +281,7 @@ def main():
     wall = time.perf_counter() - t0
     gpu_ms = ev0.elapsed_time(ev1)
     upd_timed = amr["updates"]
+    amr_timed = {k: (list(v) if isinstance(v, list) else v) for k, v in amr.items()}
     # Per-kernel durations come from a second region of the same run: every
     # step launch records its own start and end (launch-extension events on
     # the solver's stream). Those events lengthen the gaps between launches,
@@ -320,9 +350,12 @@ def main():
                      "timing": f"per-kernel events over {prof_steps} further coarse steps "
                                f"({prof_wall * 1e3 / prof_steps:.4f} ms/step with events)"},
         "actual_updates_per_s": upd * args.steps / wall,
-        "amr": ({"regrid_every": regrid_every, "regrids": amr["regrids"],
-                 "boxes_min": min(amr["boxes"]), "boxes_max": max(amr["boxes"]),
-                 "regrid_s": amr["regrid_s"]} if dynamic and amr["boxes"] else None),
+        "amr": ({"regrid_every": regrid_every, "regrids": amr_timed["regrids"],
+                 "boxes_min": min(amr_timed["boxes"]), "boxes_max": max(amr_timed["boxes"]),
+                 "regrid_s": amr_timed["regrid_s"], "max_box": args.amr_max_box,
+                 "threshold": args.amr_threshold,
+                 "levels": [solver.active_cells(l) for l in range(case.nlev)]}
+                if dynamic and amr_timed["boxes"] else None),
         "gpu_event_ms": gpu_ms,
         "conservation_drift_rel": drift,
         "healthy": healthy,
@@ -333,7 +366,8 @@ def main():
                                         policy=args.serve_policy)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(build_case(args.workload, 10 ** 6), args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(build_case(args.workload, 10 ** 6), args.cpu_budget,
+                                           boxes=timed_boxes if dynamic else None)
     print(json.dumps(out))
 
 

@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <functional>
 #include <thread>
@@ -89,7 +90,14 @@ struct DevMem {
   bool bound = false;
   std::map<size_t, size_t> free_;     // offset -> length
   std::map<void *, size_t> live_;     // pointer -> length (bound region)
-  std::vector<void *> owned_;         // hipMalloc'ed blocks
+  std::unordered_map<void *, size_t> owned_;  // hipMalloc'ed blocks in use -> length
+  // Released hipMalloc'ed blocks kept for reuse (hipFree synchronises the
+  // device; a regrid reallocates dozens of small tables). All of a context's
+  // device work runs on its one stream, so a block reused by a later
+  // stream-ordered operation cannot overlap the work that used it before.
+  std::multimap<size_t, void *> cache_;
+  size_t cached_ = 0;
+  static constexpr size_t kCacheBlock = size_t(16) << 20, kCacheTotal = size_t(64) << 20;
 
   static size_t round(size_t n) { return (n + 255) & ~size_t(255); }
 
@@ -106,9 +114,20 @@ struct DevMem {
   void *alloc(size_t n) {
     n = round(std::max<size_t>(n, 256));
     if (!bound) {
+      auto c = cache_.lower_bound(n);
+      if (c != cache_.end() && c->first <= 2 * n) {
+        void *p = c->second;
+        owned_[p] = c->first;
+        cached_ -= c->first;
+        cache_.erase(c);
+        return p;
+      }
       void *p = nullptr;
-      if (hipMalloc(&p, n) != hipSuccess) return nullptr;
-      owned_.push_back(p);
+      if (hipMalloc(&p, n) != hipSuccess) {
+        drop_cache();
+        if (hipMalloc(&p, n) != hipSuccess) return nullptr;
+      }
+      owned_[p] = n;
       return p;
     }
     for (auto it = free_.begin(); it != free_.end(); ++it) {
@@ -127,10 +146,15 @@ struct DevMem {
   void release(void *p) {
     if (!p) return;
     if (!bound) {
-      auto it = std::find(owned_.begin(), owned_.end(), p);
-      if (it != owned_.end()) {
+      auto it = owned_.find(p);
+      if (it == owned_.end()) return;
+      const size_t n = it->second;
+      owned_.erase(it);
+      if (n <= kCacheBlock && cached_ + n <= kCacheTotal) {
+        cache_.insert({n, p});
+        cached_ += n;
+      } else {
         (void)hipFree(p);
-        owned_.erase(it);
       }
       return;
     }
@@ -153,9 +177,16 @@ struct DevMem {
     free_[off] = len;
   }
 
+  void drop_cache() {
+    for (auto &kv : cache_) (void)hipFree(kv.second);
+    cache_.clear();
+    cached_ = 0;
+  }
+
   void release_all() {
-    for (void *p : owned_) (void)hipFree(p);
+    for (auto &kv : owned_) (void)hipFree(kv.first);
     owned_.clear();
+    drop_cache();
     if (bound) bind(base, size);
   }
 };
@@ -187,7 +218,7 @@ struct Level {
   int nledger = 0;
   double *dpartial = nullptr;
   long steps = 0;  // buffer flips so far; its parity selects the current buffer
-  std::unordered_map<int64_t, int> acc_slot;  // (cell, q) of a ring cell -> slot
+  std::vector<int64_t> reflux_key;  // per reflux slot: (y * Nx + x) * 4 + q of its ring cell
 
   int64_t off(int x, int y) const {
     return (int64_t)(y - fy0) * pitch + (x - fx0) + xoff;
@@ -592,24 +623,51 @@ vlbm_status build_fused(vlbm_ctx *c, int l, const std::unordered_map<int64_t, in
   return VLBM_OK;
 }
 
+// Run f(i) for i in [0, n), each on its own thread (i = 0 on this one). The
+// status of the lowest failing index is returned, with its message (messages
+// are per thread).
+vlbm_status run_parallel(int n, const std::function<vlbm_status(int)> &f) {
+  if (n <= 1) return n == 1 ? f(0) : VLBM_OK;
+  std::vector<vlbm_status> st(n, VLBM_OK);
+  std::vector<std::string> err(n);
+  std::vector<std::thread> th;
+  for (int i = 1; i < n; ++i)
+    th.emplace_back([&, i] {
+      st[i] = f(i);
+      if (st[i]) err[i] = g_err;
+    });
+  st[0] = f(0);
+  if (st[0]) err[0] = g_err;
+  for (auto &t : th) t.join();
+  for (int i = 0; i < n; ++i)
+    if (st[i]) {
+      g_err = err[i];
+      return st[i];
+    }
+  return VLBM_OK;
+}
+
 vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
   PhaseTimer tm("build_lists");
   const vlbm_params &p = c->p;
   const int r = p.r;
   int nlev = 0;
   while (nlev < kMaxLevels && c->lv[nlev].present) ++nlev;
-  // coverage
-  for (int l = 0; l < kMaxLevels && c->lv[l].present; ++l) {
+  // coverage, one level per thread
+  std::vector<std::vector<int>> of_level(nlev + 1);  // box indices per level
+  for (int b = 0; b < n; ++b)
+    if (boxes[b].level >= 0 && boxes[b].level < nlev) of_level[boxes[b].level].push_back(b);
+  vlbm_status cst = run_parallel(nlev, [&](int l) -> vlbm_status {
     Level &L = c->lv[l];
     L.cov.assign((size_t)L.fw * L.fh, 0);
     if (l == 0)
       for (int y = 0; y < L.Ny; ++y) memset(&L.cov[L.fidx(0, y)], 1, L.Nx);
-  }
-  for (int b = 0; b < n; ++b) {
-    Level &L = c->lv[boxes[b].level];
-    for (int y = boxes[b].j0; y < boxes[b].j0 + boxes[b].ny; ++y)
-      memset(&L.cov[L.fidx(boxes[b].i0, y)], 1, boxes[b].nx);
-  }
+    for (int b : of_level[l])
+      for (int y = boxes[b].j0; y < boxes[b].j0 + boxes[b].ny; ++y)
+        memset(&L.cov[L.fidx(boxes[b].i0, y)], 1, boxes[b].nx);
+    return VLBM_OK;
+  });
+  if (cst) return cst;
   // proper nesting: a covered cell's parent and the parent's 4 neighbours are
   // covered. Per box: its parent rectangle, widened by one cell along x on its
   // rows and along y on its columns (wrapped on periodic axes; cells outside a
@@ -651,22 +709,25 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
     }
   }
   tm.mark("coverage+nesting");
-  // status: covered cells are active (1), those under a finer box are holes (2)
-  for (int l = 0; l < kMaxLevels && c->lv[l].present; ++l) c->lv[l].status = c->lv[l].cov;
-  for (int b = 0; b < n; ++b) {
-    const int l = boxes[b].level;
-    if (l < 1) continue;
-    Level &PL = c->lv[l - 1];
-    const int x0 = boxes[b].i0 / r, x1 = (boxes[b].i0 + boxes[b].nx) / r;
-    for (int y = boxes[b].j0 / r; y < (boxes[b].j0 + boxes[b].ny) / r; ++y)
-      memset(&PL.status[PL.fidx(x0, y)], 2, x1 - x0);
-  }
+  // status: covered cells are active (1), those under a finer box are holes
+  // (2); one level per thread
+  cst = run_parallel(nlev, [&](int l) -> vlbm_status {
+    Level &L = c->lv[l];
+    L.status = L.cov;
+    for (int b : of_level[l + 1]) {
+      const int x0 = boxes[b].i0 / r, x1 = (boxes[b].i0 + boxes[b].nx) / r;
+      for (int y = boxes[b].j0 / r; y < (boxes[b].j0 + boxes[b].ny) / r; ++y)
+        memset(&L.status[L.fidx(x0, y)], 2, x1 - x0);
+    }
+    return VLBM_OK;
+  });
+  if (cst) return cst;
   tm.mark("status");
   // Per level, two passes; the levels of a pass run on threads of their own.
   // Pass A: tiles, cell -> tile map, ghost tasks, reflux and ledger slots.
   // Pass B (needs the parent's reflux slots): captures, task order, fused lists.
   struct Work {
-    std::vector<int32_t> owner;                 // frame cell -> tile
+    std::unique_ptr<int32_t[]> owner;           // frame cell -> tile (active cells only)
     std::vector<std::pair<int, Task>> tk;       // (tile, task)
     std::unordered_map<int64_t, int> bc_slot;   // (cell, q) -> ledger slot (fused level)
     std::vector<std::pair<int64_t, Task>> caps; // (cell R_0 as y * Nx + x, capture) (fused level)
@@ -677,6 +738,7 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
   std::vector<Work> W(nlev);
   const int TC = c->tile_cells;
   auto passA = [&](int l) -> vlbm_status {
+    PhaseTimer lt(l == 0 ? "passA l0" : l == 1 ? "passA l1" : l == 2 ? "passA l2" : "passA l3+");
     Level &L = c->lv[l];
     Work &w = W[l];
     // tiles: runs of active cells per row, stacked into rectangles of <= TC cells
@@ -700,12 +762,14 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
       const uint8_t *row = &L.status[L.fidx(L.fx0, y)];
       size_t j = 0;  // open rectangles are ordered by xa, like the runs of a row
       int x = 0;
+      constexpr uint64_t ones = 0x0101010101010101ull;
       while (x < L.fw) {
         if (row[x] != 1) {
           ++x;
           continue;
         }
         const int xa = x;
+        for (uint64_t v; x + 8 <= L.fw && (memcpy(&v, row + x, 8), v == ones);) x += 8;
         while (x < L.fw && row[x] == 1) ++x;
         const int a = L.fx0 + xa, b = L.fx0 + x, maxh = std::max(1, TC / (b - a));
         while (j < open.size() && open[j].xa < a) emit(open[j++]);
@@ -738,139 +802,160 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
     }
     L.tiles.swap(sorted);
     rect_xy.swap(sxy);
-    // cell -> tile map (frame cells)
-    w.owner.assign(L.cov.size(), -1);
-    for (size_t t = 0; t < L.tiles.size(); ++t)
-      for (int yy = 0; yy < L.tiles[t].h; ++yy) {
-        int32_t *o = &w.owner[L.fidx(rect_xy[t].first, rect_xy[t].second + yy)];
-        std::fill(o, o + L.tiles[t].w, (int32_t)t);
-      }
-    // ghost tasks
-    L.acc_slot.clear();
+    lt.mark("tiles");
+    // cell -> tile map over the frame; only active cells are ever looked up
+    w.owner.reset(new int32_t[L.cov.size()]);
+    const int nt = (int)L.tiles.size();
+    const int TB = std::max(1, std::min(8, nt / 256));
+    vlbm_status st = run_parallel(TB, [&](int b) -> vlbm_status {
+      for (int t = (int)((int64_t)nt * b / TB); t < (int)((int64_t)nt * (b + 1) / TB); ++t)
+        for (int yy = 0; yy < L.tiles[t].h; ++yy) {
+          int32_t *o = &w.owner[L.fidx(rect_xy[t].first, rect_xy[t].second + yy)];
+          std::fill(o, o + L.tiles[t].w, (int32_t)t);
+        }
+      return VLBM_OK;
+    });
+    if (st) return st;
+    lt.mark("owner");
+    // ghost tasks, found per band of rows in parallel, then numbered in row order
+    L.reflux_key.clear();
     L.nledger = 0;
     // the finest level of a two-level-or-deeper hierarchy with r = 2 also gets
     // the lists of the fused two-sub-step launch
     w.fuse = (c->step_flags & STEP_FUSE2) && l >= 1 && l == nlev - 1 && r == 2;
-    const int fw = L.fw;
-    for (int y = L.fy0 + 1; y < L.fy0 + L.fh - 1; ++y) {
-      const uint8_t *st = &L.status[L.fidx(L.fx0, y)];
-      for (int xi = 1; xi < fw - 1; ++xi) {
-        if (st[xi] != 1) continue;
-        // interior cell: all four upwind neighbours active at this level (hence
-        // inside the domain) -> plain pulls, no task
-        if (st[xi - 1] == 1 && st[xi + 1] == 1 && st[xi - fw] == 1 && st[xi + fw] == 1) continue;
-        const int x = L.fx0 + xi;
-        const int tile = w.owner[L.fidx(x, y)];
+    const int fw = L.fw, ya = L.fy0 + 1, yb = L.fy0 + L.fh - 1;
+    // 1. active cells with a non-active upwind neighbour, per band of rows
+    const int B = std::max(1, std::min(8, (yb - ya) / 16));
+    std::vector<std::vector<int32_t>> edge(B);  // frame indices, row order
+    st = run_parallel(B, [&](int b) -> vlbm_status {
+      for (int y = ya + (int)((int64_t)(yb - ya) * b / B); y < ya + (int)((int64_t)(yb - ya) * (b + 1) / B); ++y) {
+        const size_t r0 = L.fidx(L.fx0, y);
+        const uint8_t *sr = &L.status[r0];
+        for (int xi = 1; xi < fw - 1; ++xi) {
+          if (sr[xi] != 1) continue;
+          // interior cell: all four upwind neighbours active at this level (hence
+          // inside the domain) -> plain pulls, no task
+          if (sr[xi - 1] == 1 && sr[xi + 1] == 1 && sr[xi - fw] == 1 && sr[xi + fw] == 1) continue;
+          edge[b].push_back((int32_t)(r0 + xi));
+        }
+      }
+      return VLBM_OK;
+    });
+    if (st) return st;
+    std::vector<int32_t> cells;
+    for (auto &e : edge) cells.insert(cells.end(), e.begin(), e.end());
+    // 2. their ghost tasks, in equal shares of the cell list
+    const int E = std::max(1, std::min(8, (int)(cells.size() / 1024)));
+    struct Band {
+      std::vector<std::pair<int, Task>> tk;
+      std::vector<int64_t> key;  // (cell, q) of each task
+    };
+    std::vector<Band> bands(E);
+    st = run_parallel(E, [&](int b) -> vlbm_status {
+      Band &bd = bands[b];
+      const size_t i0 = cells.size() * b / E, i1 = cells.size() * (b + 1) / E;
+      for (size_t i = i0; i < i1; ++i) {
+        const int x = L.fx0 + cells[i] % fw, y = L.fy0 + cells[i] / fw;
+        const int tile = w.owner[cells[i]];
         for (int q = 0; q < 4; ++q) {
           Task t{};
           vlbm_status gs = ghost_task(c, l, x, y, q, t);
           if (gs) return gs;
           if (t.kind == T_NONE) continue;
-          const int kind = t.kind & 0xFF;
-          if (kind == T_OUTFLOW || kind == T_REFLECT || kind == T_INFLOW) {
-            t.slot = L.nledger++;
-            if (w.fuse) w.bc_slot[((int64_t)y * L.Nx + x) * 4 + q] = t.slot;
-          } else if (kind == T_REFLUX) {
-            int64_t key = ((int64_t)y * L.Nx + x) * 4 + q;
-            int slot = (int)L.acc_slot.size();
-            L.acc_slot[key] = slot;
-            t.slot = slot;
-          }
-          w.tk.push_back({tile, t});
+          bd.tk.push_back({tile, t});
+          bd.key.push_back(((int64_t)y * L.Nx + x) * 4 + q);
         }
       }
-    }
-    L.nacc = (int)L.acc_slot.size();
+      return VLBM_OK;
+    });
+    if (st) return st;
+    lt.mark("tasks");
+    size_t ntk = 0;
+    for (const Band &bd : bands) ntk += bd.tk.size();
+    w.tk.reserve(ntk);
+    for (Band &bd : bands)
+      for (size_t i = 0; i < bd.tk.size(); ++i) {
+        Task &t = bd.tk[i].second;
+        const int kind = t.kind & 0xFF;
+        if (kind == T_OUTFLOW || kind == T_REFLECT || kind == T_INFLOW) {
+          t.slot = L.nledger++;
+          if (w.fuse) w.bc_slot[bd.key[i]] = t.slot;
+        } else if (kind == T_REFLUX) {
+          const int slot = (int)L.reflux_key.size();
+          L.reflux_key.push_back(bd.key[i]);
+          t.slot = slot;
+        }
+        w.tk.push_back(bd.tk[i]);
+      }
+    L.nacc = (int)L.reflux_key.size();
     return VLBM_OK;
   };
   auto passB = [&](int l) -> vlbm_status {
+    PhaseTimer lt(l == 0 ? "passB l0" : l == 1 ? "passB l1" : l == 2 ? "passB l2" : "passB l3+");
     Level &L = c->lv[l];
     Work &w = W[l];
     std::vector<std::pair<int, Task>> &tk = w.tk;
-    // captures: values leaving level l towards the parent's ring cells
+    // captures: values leaving level l towards the parent's ring cells. One
+    // per reflux slot (ring cell P, population q) of the parent: the r fine
+    // cells streaming q into P are the children of the hole P - c_q on its
+    // face towards P (all active: by proper nesting no finer level reaches
+    // there). R_0 is the first of them in row order, and captures are kept in
+    // the order of their R_0 (row, column) and q.
     if (l >= 1) {
       const Level &PL = c->lv[l - 1];
-      std::unordered_map<int, size_t> cap;  // parent slot -> index in tk
-      for (int y = L.fy0 + 1; y < L.fy0 + L.fh - 1; ++y) {
-        const uint8_t *st = &L.status[L.fidx(L.fx0, y)];
-        const uint8_t *cv = &L.cov[L.fidx(L.fx0, y)];
-        for (int xi = 1; xi < L.fw - 1; ++xi) {
-          if (st[xi] != 1) continue;
-          if (cv[xi - 1] && cv[xi + 1] && cv[xi - L.fw] && cv[xi + L.fw]) continue;
-          const int x = L.fx0 + xi;
-          for (int q = 0; q < 4; ++q) {
-            int dx = x + CX[q], dy = y + CY[q];
-            if (!c->wrap(l, dx, dy)) continue;
-            if (c->covered(l, dx, dy)) continue;
-            int px = dx / r, py = dy / r;
-            int64_t key = ((int64_t)py * PL.Nx + px) * 4 + q;
-            auto it = PL.acc_slot.find(key);
-            if (it == PL.acc_slot.end())
-              return fail(VLBM_ENEST, "internal: no reflux slot for level %d ring cell", l - 1);
-            auto ct = cap.find(it->second);
-            if (ct == cap.end()) {
-              Task t{};
-              t.kind = T_CAPTURE;
-              t.q = q;
-              t.src = (int32_t)L.off(x, y);
-              t.n0 = q < 2 ? L.pitch : 1;
-              t.n1 = -1;
-              t.slot = it->second;
-              cap[it->second] = tk.size();
-              tk.push_back({w.owner[L.fidx(x, y)], t});
-              if (w.fuse) w.caps.push_back({(int64_t)y * L.Nx + x, t});
-            } else {
-              Task &t = tk[ct->second].second;
-              int64_t want = (int64_t)t.src + (int64_t)t.n0 * (t.j + 1);
-              if (want != L.off(x, y))
-                return fail(VLBM_ENEST, "internal: reflux cells not contiguous");
-              t.j += 1;  // counts captured cells beyond the first (device ignores j)
-            }
-          }
-        }
+      struct Cap {
+        int x, y, q, slot;
+      };
+      std::vector<Cap> caps(PL.reflux_key.size());
+      for (size_t slot = 0; slot < PL.reflux_key.size(); ++slot) {
+        const int64_t key = PL.reflux_key[slot];
+        const int q = (int)(key & 3);
+        const int64_t cell = key >> 2;
+        int hx = (int)(cell % PL.Nx) - CX[q], hy = (int)(cell / PL.Nx) - CY[q];
+        c->wrap(l - 1, hx, hy);
+        const int x = hx * r + (q == 0 ? r - 1 : 0), y = hy * r + (q == 2 ? r - 1 : 0);
+        const int x1 = x + (q < 2 ? 0 : r - 1), y1 = y + (q < 2 ? r - 1 : 0);
+        if (!L.in_frame(x, y) || !L.in_frame(x1, y1) || L.status[L.fidx(x, y)] != 1 ||
+            L.status[L.fidx(x1, y1)] != 1)
+          return fail(VLBM_ENEST, "internal: level %d reflux face without active fine cells", l - 1);
+        caps[slot] = {x, y, q, (int)slot};
       }
-      for (auto &kv : cap)
-        if (tk[kv.second].second.j + 1 != r)
-          return fail(VLBM_ENEST, "internal: ring cell sees %d fine cells, expected %d",
-                      tk[kv.second].second.j + 1, r);
+      std::sort(caps.begin(), caps.end(), [](const Cap &a, const Cap &b) {
+        return a.y != b.y ? a.y < b.y : a.x != b.x ? a.x < b.x : a.q < b.q;
+      });
+      tk.reserve(tk.size() + caps.size());
+      for (const Cap &cd : caps) {
+        Task t{};
+        t.kind = T_CAPTURE;
+        t.q = cd.q;
+        t.src = (int32_t)L.off(cd.x, cd.y);
+        t.n0 = cd.q < 2 ? L.pitch : 1;
+        t.n1 = -1;
+        t.j = r - 1;  // captured cells beyond the first (the device reads r)
+        t.slot = cd.slot;
+        tk.push_back({w.owner[L.fidx(cd.x, cd.y)], t});
+        if (w.fuse) w.caps.push_back({(int64_t)cd.y * L.Nx + cd.x, t});
+      }
     }
-    std::stable_sort(tk.begin(), tk.end(),
-                     [](const std::pair<int, Task> &a, const std::pair<int, Task> &b) {
-                       return a.first < b.first;
-                     });
-    L.tasks.clear();
-    L.tasks.reserve(tk.size());
-    for (auto &t : L.tiles) t.task0 = t.ntask = 0;
-    for (size_t i = 0; i < tk.size(); ++i) {
-      Tile &t = L.tiles[tk[i].first];
-      if (t.ntask == 0) t.task0 = (int32_t)L.tasks.size();
-      t.ntask += 1;
-      L.tasks.push_back(tk[i].second);
+    lt.mark("captures");
+    // tasks grouped by tile, in their order of discovery (a counting sort)
+    const size_t nt = L.tiles.size();
+    std::vector<int32_t> start(nt + 1, 0);
+    for (const auto &e : tk) start[e.first + 1] += 1;
+    for (size_t t = 0; t < nt; ++t) {
+      L.tiles[t].ntask = start[t + 1];
+      start[t + 1] += start[t];
+      L.tiles[t].task0 = L.tiles[t].ntask ? start[t] : 0;
     }
+    L.tasks.resize(tk.size());
+    for (const auto &e : tk) L.tasks[start[e.first]++] = e.second;
     L.ftiles.clear();
     L.ftasks.clear();
     if (w.fuse) return build_fused(c, l, w.bc_slot, w.caps);
     return VLBM_OK;
   };
-  // Run one pass over all levels, each on its own thread (level 0 on this
-  // one). Failure messages are per thread; the lowest failing level's is kept.
-  auto run_pass = [&](const std::function<vlbm_status(int)> &pass) -> vlbm_status {
-    std::vector<std::thread> th;
-    for (int l = 1; l < nlev; ++l)
-      th.emplace_back([&, l] {
-        W[l].st = pass(l);
-        if (W[l].st) W[l].err = g_err;
-      });
-    W[0].st = pass(0);
-    if (W[0].st) W[0].err = g_err;
-    for (auto &t : th) t.join();
-    for (int l = 0; l < nlev; ++l)
-      if (W[l].st) {
-        g_err = W[l].err;
-        return W[l].st;
-      }
-    return VLBM_OK;
-  };
+  // Run one pass over all levels, each on its own thread (level 0 on this one).
+  auto run_pass = [&](const std::function<vlbm_status(int)> &pass) { return run_parallel(nlev, pass); };
   vlbm_status st = run_pass(passA);
   tm.mark("tiles+tasks");
   if (!st) st = run_pass(passB);
@@ -1427,6 +1512,25 @@ vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes, bool res
 int level_nx(const vlbm_ctx *c, int l);
 int level_ny(const vlbm_ctx *c, int l);
 
+// Tags of one level over a rectangle of its cells (a frame); outside it, none.
+struct TagMap {
+  int x0 = 0, y0 = 0, w = 0, h = 0;
+  std::vector<uint8_t> t;
+};
+// Coverage of one level over a rectangle of its cells (outside it: not
+// covered), or of the whole level.
+struct CovMap {
+  bool all = false;
+  int x0 = 0, y0 = 0, w = 0, h = 0;
+  std::vector<uint8_t> m;
+  bool at(int x, int y) const {
+    if (all) return true;
+    x -= x0;
+    y -= y0;
+    return x >= 0 && y >= 0 && x < w && y < h && m[(size_t)y * w + x];
+  }
+};
+
 // Clustering for tag_and_regrid: level-l tags, dilated by a square of radius
 // `buffer` (periodic axes wrap, other axes clip), restricted to cells whose
 // four neighbours are covered at level l (neighbours outside a non-periodic
@@ -1437,8 +1541,8 @@ int level_ny(const vlbm_ctx *c, int l);
 // holds a dilated tag iff a tag lies within `buffer` of it, and it is free of
 // disallowed cells iff its rows widened by one column and its columns widened
 // by one row are covered.
-void cluster_level(vlbm_ctx *c, int l, const std::vector<uint8_t> &tags, const std::vector<uint8_t> &cov,
-                   int buffer, int min_box, int max_box, std::vector<vlbm_box> &out) {
+void cluster_level(vlbm_ctx *c, int l, const TagMap &tags, const CovMap &cov, int buffer, int min_box,
+                   int max_box, std::vector<vlbm_box> &out) {
   const int r = c->p.r;
   const int Nx = level_nx(c, l), Ny = level_ny(c, l);
   const bool px = c->perx(), py = c->pery();
@@ -1466,25 +1570,36 @@ void cluster_level(vlbm_ctx *c, int l, const std::vector<uint8_t> &tags, const s
         if (v.empty() || t > v.back()) v.push_back(t);
     }
   };
-  const uint8_t *tg = tags.data();
-  const size_t n = tags.size();
-  for (size_t i = 0; i < n;) {
-    if (i + 8 <= n && (i & 7) == 0) {
-      uint64_t w;
-      memcpy(&w, tg + i, 8);
-      if (!w) {
-        i += 8;
+  // per row of the tag map, each run of tagged cells reaches one interval of
+  // tile columns on the tile rows within `buffer` of the row
+  for (int fy = 0; fy < tags.h; ++fy) {
+    const uint8_t *row = &tags.t[(size_t)fy * tags.w];
+    const int y = tags.y0 + fy;
+    bool any = false;
+    int fx = 0;
+    while (fx < tags.w) {
+      if (fx + 8 <= tags.w) {  // skip untagged words
+        uint64_t w;
+        memcpy(&w, row + fx, 8);
+        if (!w) {
+          fx += 8;
+          continue;
+        }
+      }
+      if (!row[fx]) {
+        ++fx;
         continue;
       }
-    }
-    if (tg[i]) {
-      const int y = (int)(i / Nx), x = (int)(i % Nx);
-      tiles_in(x - buffer, x + buffer, Nx, px, cols);
-      tiles_in(y - buffer, y + buffer, Ny, py, rows);
+      const int xa = fx;
+      while (fx < tags.w && row[fx]) ++fx;
+      if (!any) {
+        tiles_in(y - buffer, y + buffer, Ny, py, rows);
+        any = true;
+      }
+      tiles_in(tags.x0 + xa - buffer, tags.x0 + fx - 1 + buffer, Nx, px, cols);
       for (int ty : rows)
         for (int tx : cols) hit[(size_t)ty * ntx + tx] = 1;
     }
-    ++i;
   }
   // reached tiles that hold no disallowed cell
   auto covered_at = [&](int x, int y) {  // true outside a non-periodic side
@@ -1496,7 +1611,7 @@ void cluster_level(vlbm_ctx *c, int l, const std::vector<uint8_t> &tags, const s
       if (!py) return true;
       y = (y + Ny) % Ny;
     }
-    return cov[(size_t)y * Nx + x] != 0;
+    return cov.at(x, y);
   };
   std::vector<uint8_t> mark((size_t)ntx * nty, 0);
   for (int ty = 0; ty < nty; ++ty)
@@ -1505,9 +1620,8 @@ void cluster_level(vlbm_ctx *c, int l, const std::vector<uint8_t> &tags, const s
       const int x0 = tx * T, y0 = ty * T, x1 = std::min(Nx, x0 + T), y1 = std::min(Ny, y0 + T);
       bool ok = true;
       for (int y = y0; ok && y < y1; ++y) {
-        const uint8_t *row = &cov[(size_t)y * Nx];
         for (int x = x0; x < x1; ++x)
-          if (!row[x]) {
+          if (!cov.at(x, y)) {
             ok = false;
             break;
           }
@@ -1561,47 +1675,85 @@ int level_ny(const vlbm_ctx *c, int l) {
   return (int)(c->p.ny0 * s);
 }
 
+// Density-gradient tags of level l's active cells, frame-indexed (fw x fh).
+vlbm_status tag_frame(vlbm_ctx *c, int l, double thr, std::vector<uint8_t> &ft) {
+  const Level &L = c->lv[l];
+  const size_t n = (size_t)L.fw * L.fh;
+  ft.assign(n, 0);
+  uint8_t *d = static_cast<uint8_t *>(c->mem.alloc(n));
+  if (!d) return fail(VLBM_ENOMEM, "tag buffer");
+  hipError_t e = launch_tag(L.buf[L.cur()], L.dstatus, L.plane, L.pitch, L.xoff, L.fx0, L.fy0, L.fw,
+                            L.fh, L.Nx, L.Ny, c->perx(), c->pery(), c->fp32, thr, d, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(ft.data(), d, n, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  c->mem.release(d);
+  if (e != hipSuccess) return fail(VLBM_EDEVICE, "tag: %s", hipGetErrorString(e));
+  return VLBM_OK;
+}
+
 // Boxes of a new hierarchy from per-level tags (levels 0..max_levels-1; a
-// level without tags is an empty vector or all zero). A tagged finer cell tags
-// its parent, so refined features keep their levels; then each level is
-// clustered inside the coverage of the boxes just made for it.
-void cluster_hierarchy(vlbm_ctx *c, std::vector<std::vector<uint8_t>> &tags, int buffer, int min_box,
-                       int max_box, std::vector<vlbm_box> &boxes) {
+// level without tags has an empty map). A tagged finer cell tags its parent,
+// so refined features keep their levels; then each level is clustered inside
+// the coverage of the boxes just made for it.
+void cluster_hierarchy(vlbm_ctx *c, std::vector<TagMap> &tags, int buffer, int min_box, int max_box,
+                       std::vector<vlbm_box> &boxes) {
   const int r = c->p.r, ML = c->p.max_levels;
   for (int l = ML - 1; l >= 1; --l) {
-    if (tags[l].empty() || tags[l - 1].empty()) continue;
-    const int Nxl = level_nx(c, l), Nxp = level_nx(c, l - 1);
-    const uint8_t *t = tags[l].data();
-    const size_t n = tags[l].size();
-    size_t i = 0;
-    while (i < n) {
-      if (i + 8 <= n && (i & 7) == 0) {  // skip untagged words
-        uint64_t w;
-        memcpy(&w, t + i, 8);
-        if (!w) {
-          i += 8;
+    const TagMap &F = tags[l];
+    TagMap &P = tags[l - 1];
+    if (F.t.empty() || P.t.empty()) continue;
+    // per row, each run of tagged fine cells tags the run of its parents
+    for (int fy = 0; fy < F.h; ++fy) {
+      const uint8_t *row = &F.t[(size_t)fy * F.w];
+      const int py = (F.y0 + fy) / r - P.y0;
+      if (py < 0 || py >= P.h) continue;
+      int fx = 0;
+      while (fx < F.w) {
+        if (fx + 8 <= F.w) {  // skip untagged words
+          uint64_t w;
+          memcpy(&w, row + fx, 8);
+          if (!w) {
+            fx += 8;
+            continue;
+          }
+        }
+        if (!row[fx]) {
+          ++fx;
           continue;
         }
+        const int xa = fx;
+        while (fx < F.w && row[fx]) ++fx;
+        const int pa = std::max((F.x0 + xa) / r - P.x0, 0);
+        const int pb = std::min((F.x0 + fx - 1) / r - P.x0, P.w - 1);
+        if (pa <= pb) memset(&P.t[(size_t)py * P.w + pa], 1, pb - pa + 1);
       }
-      if (t[i]) {
-        const int y = (int)(i / Nxl), x = (int)(i % Nxl);
-        tags[l - 1][(size_t)(y / r) * Nxp + x / r] = 1;
-      }
-      ++i;
     }
   }
-  std::vector<uint8_t> cov((size_t)level_nx(c, 0) * level_ny(c, 0), 1);
+  CovMap cov;
+  cov.all = true;
   for (int l = 0; l + 1 < ML; ++l) {
-    if (tags[l].empty()) break;
+    if (tags[l].t.empty()) break;
     size_t before = boxes.size();
     cluster_level(c, l, tags[l], cov, buffer, min_box, max_box, boxes);
     if (boxes.size() == before || l + 2 >= ML) break;
-    const int Nx1 = level_nx(c, l + 1);
-    std::vector<uint8_t> ncov((size_t)Nx1 * level_ny(c, l + 1), 0);
+    // coverage of level l+1 over the bounding box of its new boxes
+    CovMap nc;
+    int bx0 = INT32_MAX, by0 = INT32_MAX, bx1 = INT32_MIN, by1 = INT32_MIN;
+    for (size_t b = before; b < boxes.size(); ++b) {
+      bx0 = std::min(bx0, boxes[b].i0);
+      by0 = std::min(by0, boxes[b].j0);
+      bx1 = std::max(bx1, boxes[b].i0 + boxes[b].nx);
+      by1 = std::max(by1, boxes[b].j0 + boxes[b].ny);
+    }
+    nc.x0 = bx0;
+    nc.y0 = by0;
+    nc.w = bx1 - bx0;
+    nc.h = by1 - by0;
+    nc.m.assign((size_t)nc.w * nc.h, 0);
     for (size_t b = before; b < boxes.size(); ++b)
       for (int y = boxes[b].j0; y < boxes[b].j0 + boxes[b].ny; ++y)
-        memset(&ncov[(size_t)y * Nx1 + boxes[b].i0], 1, boxes[b].nx);
-    cov.swap(ncov);
+        memset(&nc.m[(size_t)(y - by0) * nc.w + boxes[b].i0 - bx0], 1, boxes[b].nx);
+    cov = std::move(nc);
   }
 }
 
@@ -1822,22 +1974,15 @@ vlbm_status vlbm_check_health(vlbm_ctx *c) {
 vlbm_status vlbm_tag(vlbm_ctx *c, int level, double thr, unsigned char *tags) {
   if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "no hierarchy installed");
   if (level < 0 || level >= c->p.max_levels || !tags) return fail(VLBM_EINVAL, "bad tag request");
-  Level &L = c->lv[level];
-  long s = 1;
-  for (int i = 0; i < level; ++i) s *= c->p.r;
-  const size_t n = (size_t)(c->p.nx0 * s) * (size_t)(c->p.ny0 * s);
-  if (!L.present) {
-    memset(tags, 0, n);
-    return VLBM_OK;
-  }
-  uint8_t *d = static_cast<uint8_t *>(c->mem.alloc(n));
-  if (!d) return fail(VLBM_ENOMEM, "tag buffer");
-  hipError_t e = launch_tag(L.buf[L.cur()], L.dstatus, L.plane, L.pitch, L.xoff, L.fx0, L.fy0, L.fw,
-                            L.fh, L.Nx, L.Ny, c->perx(), c->pery(), c->fp32, thr, d, c->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(tags, d, n, hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  c->mem.release(d);
-  if (e != hipSuccess) return fail(VLBM_EDEVICE, "tag: %s", hipGetErrorString(e));
+  const Level &L = c->lv[level];
+  const int Nx = level_nx(c, level), Ny = level_ny(c, level);
+  memset(tags, 0, (size_t)Nx * Ny);
+  if (!L.present) return VLBM_OK;
+  std::vector<uint8_t> ft;
+  vlbm_status st = tag_frame(c, level, thr, ft);
+  if (st) return st;
+  for (int fy = 1; fy < L.fh - 1; ++fy)  // the frame's interior lies inside the level
+    memcpy(&tags[(size_t)(L.fy0 + fy) * Nx + L.fx0 + 1], &ft[(size_t)fy * L.fw + 1], L.fw - 2);
   return VLBM_OK;
 }
 
@@ -1859,15 +2004,16 @@ vlbm_status vlbm_tag_and_regrid(vlbm_ctx *c, double thr, int buffer, int min_box
   PhaseTimer tm("tag_and_regrid");
   const int ML = c->p.max_levels;
   if (ML < 2) return VLBM_OK;
-  std::vector<std::vector<uint8_t>> tags(ML);
-  for (int l = 0; l < ML; ++l) {
-    if (l + 1 < ML || l < c->nlev) {
-      tags[l].assign((size_t)level_nx(c, l) * level_ny(c, l), 0);
-      if (l < c->nlev) {
-        vlbm_status st = vlbm_tag(c, l, thr, tags[l].data());
-        if (st) return st;
-      }
-    }
+  std::vector<TagMap> tags(ML);
+  for (int l = 0; l < c->nlev; ++l) {
+    const Level &L = c->lv[l];
+    TagMap &T = tags[l];
+    T.x0 = L.fx0;
+    T.y0 = L.fy0;
+    T.w = L.fw;
+    T.h = L.fh;
+    vlbm_status st = tag_frame(c, l, thr, T.t);
+    if (st) return st;
   }
   tm.mark("tags");
   std::vector<vlbm_box> boxes;

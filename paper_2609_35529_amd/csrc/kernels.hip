@@ -691,13 +691,15 @@ template <class T>
 __global__ void tag_kernel(const T *__restrict__ buf, const uint8_t *status, int64_t P,
                            int pitch, int xoff, int fx0, int fy0, int fw, int fh, int Nx,
                            int Ny, int perx, int pery, double thr, uint8_t *tags) {
-  const int64_t n = (int64_t)Nx * Ny;
+  // one thread per frame cell; tags are frame-indexed (only active cells of
+  // the level, which all lie in its frame, can be tagged)
+  const int64_t n = (int64_t)fw * fh;
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
        c += (int64_t)gridDim.x * blockDim.x) {
-    const int y = (int)(c / Nx), x = (int)(c - (int64_t)y * Nx);
+    const int fy = (int)(c / fw), fx = (int)(c - (int64_t)fy * fw);
+    const int x = fx + fx0, y = fy + fy0;
     uint8_t tag = 0;
-    const int fx = x - fx0, fy = y - fy0;
-    if (fx >= 0 && fy >= 0 && fx < fw && fy < fh && status[(int64_t)fy * fw + fx] == 1) {
+    if (status[c] == 1) {
       const int64_t o = (int64_t)fy * pitch + fx + xoff;
       const double rc = cell_rho<T>(buf, P, o);
       double rn[4];
@@ -732,7 +734,7 @@ __global__ void tag_kernel(const T *__restrict__ buf, const uint8_t *status, int
 hipError_t launch_tag(const void *buf, const uint8_t *status, int64_t plane, int pitch, int xoff,
                       int fx0, int fy0, int fw, int fh, int Nx, int Ny, int perx, int pery,
                       int fp32, double thr, uint8_t *tags, hipStream_t s) {
-  const int64_t n = (int64_t)Nx * Ny;
+  const int64_t n = (int64_t)fw * fh;
   if (fp32)
     hipLaunchKernelGGL(tag_kernel<float>, grid_for(n), dim3(256), 0, s,
                        static_cast<const float *>(buf), status, plane, pitch, xoff, fx0, fy0, fw,

@@ -138,6 +138,7 @@ hipError_t launch_set_state(const RectArgs &a, int fp32, int raw_populations, hi
 hipError_t launch_get(const RectArgs &a, int fp32, int populations, hipStream_t s);
 hipError_t launch_health(const void *buf, const Tile *tiles, int ntiles, int64_t plane,
                          int pitch, int fp32, double gm1, int *flag, hipStream_t s);
+// tags: frame-indexed (fw x fh bytes), 1 on tagged active cells, else 0
 hipError_t launch_tag(const void *buf, const uint8_t *status, int64_t plane, int pitch,
                       int xoff, int fx0, int fy0, int fw, int fh, int Nx, int Ny, int perx,
                       int pery, int fp32, double thr, uint8_t *tags, hipStream_t s);

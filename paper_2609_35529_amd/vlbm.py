@@ -176,7 +176,8 @@ class Solver:
                 max_levels or case.nlev, case.bc, case.w_inflow, precision, stream, pool)
         s.set_hierarchy(case.boxes)
         for l in range(case.nlev):
-            s.set_state(l, case.states[l])
+            if case.states[l] is not None:
+                s.set_state(l, case.states[l])
         return s
 
     @property

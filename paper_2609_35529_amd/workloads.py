@@ -75,7 +75,7 @@ class Case:
     beta: float
     bc: Tuple[int, int, int, int]
     boxes: List[Box]
-    states: List[np.ndarray]          # states[l] = U over the whole level-l domain
+    states: List[np.ndarray]          # states[l] = U over the whole level-l domain (None: unset)
     steps: int
     w_inflow: Optional[np.ndarray] = None  # [4 sides][4] conserved inflow states
     x0: float = 0.0
@@ -410,6 +410,42 @@ def kelvin_helmholtz(n0=4096, seed=0, nlev=4, r=2, beta=0.8, kappa=1.5, steps=50
     c = link_speed(U0, gamma, kappa)
     return Case("kelvin_helmholtz", n0, n0, dx0, r, nlev, gamma, c, beta, (PERIODIC,) * 4,
                 boxes, states, steps)
+
+
+def kelvin_helmholtz_strip(n0=4096, ny0=512, yc=0.25, seed=0, nlev=4, r=2, beta=0.8, kappa=1.5,
+                           steps=5000, band=0.25):
+    """One horizontal strip of the Kelvin-Helmholtz problem above: n0 x ny0
+    coarse cells of the n0 x n0 domain, centred on the shear layer at y = yc.
+    The perturbation is drawn for the whole n0 x n0 domain exactly as in
+    kelvin_helmholtz (same generator, same order) and the strip's rows are
+    taken, so the strip's data equal those rows of the full problem. Periodic
+    in x; the strip's two cut sides are outflow, standing in for the rows that
+    neighbouring strips would exchange. No static boxes: the hierarchy comes
+    from tagging and clustering."""
+    gamma = 1.4
+    dx0 = 1.0 / n0
+    rng = np.random.default_rng(seed)
+    U1 = rng.uniform(0, 1, (n0, n0))
+    U2 = rng.uniform(0, 1, (n0, n0))
+    j0 = int(round(yc * n0)) - ny0 // 2
+    if j0 < 0 or j0 + ny0 > n0:
+        raise ValueError("strip outside the domain")
+    y0 = j0 * dx0
+    U1s, U2s = U1[j0:j0 + ny0], U2[j0:j0 + ny0]
+
+    def ic0(X, Y):
+        inner = np.abs(Y - 0.5) < band
+        rho = np.where(inner, 2.0, 1.0)
+        u = np.where(inner, 0.5, -0.5) + 0.01 * (U2s - 0.5)
+        v = 0.01 * np.sin(4 * np.pi * X) + 0.01 * (U1s - 0.5)
+        return conserved(rho, u, v, 2.5 + 0 * X, gamma)
+
+    X, Y = level_grid(n0, ny0, dx0, r, 0, y0=y0)
+    U0 = ic0(X, Y)
+    c = link_speed(U0, gamma, kappa)
+    # finer levels start empty and are filled by splitting at the first regrids
+    return Case("kh_strip", n0, ny0, dx0, r, nlev, gamma, c, beta,
+                (PERIODIC, PERIODIC, OUTFLOW, OUTFLOW), [], [U0] + [None] * (nlev - 1), steps)
 
 
 # --------------------------------------------------- shock - bubble interaction

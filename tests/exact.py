@@ -152,7 +152,8 @@ def run_oracle(case, steps=None, oracle_cls=None, **kw):
                case.bc, case.w_inflow, **kw)
     o.set_boxes(case.boxes)
     for l in range(case.nlev):
-        o.set_state(l, case.states[l])
+        if case.states[l] is not None:
+            o.set_state(l, case.states[l])
     if steps is None:
         steps = case.steps
     if steps:
