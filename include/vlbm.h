@@ -193,8 +193,8 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
  * hierarchy and the time history are kept. VLBM_EINVAL for other values. */
 vlbm_status vlbm_set_tuning(vlbm_ctx *ctx, int tile_cells, int flags);
 
-/* Autotuner: time tile sizes {128, 256, 512, 1024} x workgroup orders (x fused
- * sub-steps on or off, where they apply) on real
+/* Autotuner: time tile sizes {128, 256, 512, 1024} x workgroup orders x store
+ * kinds (x fused sub-steps on or off, where they apply) on real
  * coarse steps of this context (every trial advances the solution by
  * 1 + steps_per_trial coarse steps) and keep the fastest. The choice is cached
  * per geometry (base grid, ratio, precision, boxes) for the process, so a

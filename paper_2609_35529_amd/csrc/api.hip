@@ -2265,8 +2265,13 @@ vlbm_status vlbm_autotune(vlbm_ctx *c, int steps_per_trial, int *tile_cells, int
   if (hit == g_tuned.end()) {
     const int tiles[] = {128, 256, 512, 1024};
     const bool can_fuse = c->p.r == 2 && c->nlev >= 2;
-    const int orders[] = {0, STEP_XCD_CONTIGUOUS, STEP_FUSE2, STEP_FUSE2 | STEP_XCD_CONTIGUOUS};
-    const int norders = can_fuse ? 4 : 2;
+    // workgroup order x store kind (x fused sub-steps where they apply)
+    std::vector<int> orders;
+    for (int fuse : {0, (int)STEP_FUSE2})
+      for (int nt : {0, (int)STEP_NT_STORES})
+        for (int xcd : {0, (int)STEP_XCD_CONTIGUOUS})
+          if (!fuse || can_fuse) orders.push_back(fuse | nt | xcd);
+    const int norders = (int)orders.size();
     float best = 1e30f;
     std::pair<int, int> choice{c->tile_cells, c->step_flags};
     hipEvent_t e0, e1;
@@ -2275,7 +2280,7 @@ vlbm_status vlbm_autotune(vlbm_ctx *c, int steps_per_trial, int *tile_cells, int
     for (int tcell : tiles)
       for (int oi = 0; oi < norders; ++oi) {
         const int ord = orders[oi];
-        const int fl = (c->step_flags & ~(STEP_XCD_CONTIGUOUS | STEP_FUSE2 | STEP_F64_MATH)) | ord;
+        const int fl = (c->step_flags & ~(STEP_XCD_CONTIGUOUS | STEP_FUSE2 | STEP_NT_STORES | STEP_F64_MATH)) | ord;
         st = vlbm_set_tuning(c, tcell, fl);
         if (!st) st = advance_impl(c, 1);  // warm
         if (!st && hipEventRecord(e0, c->stream) != hipSuccess) st = fail(VLBM_EDEVICE, "event");

@@ -354,7 +354,7 @@ __device__ __forceinline__ void run_task_k2(const LevelDesc &A, double ak2, cons
   }
 }
 
-template <class T, class C>
+template <class T, class C, bool NT>
 __device__ __forceinline__ void fused_tile(const LevelDesc &A, int lb, int nblocks, int flags) {
   constexpr int np = FUSE_POS;
   __shared__ T F1[16 * FUSE_POS];
@@ -442,11 +442,11 @@ __device__ __forceinline__ void fused_tile(const LevelDesc &A, int lb, int nbloc
     }
     relax<C>(g, gm1, h, tb);
     const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
-    put<T, C, false>(d, plane, o, g);
+    put<T, C, NT>(d, plane, o, g);
   }
 }
 
-template <class T, class C>
+template <class T, class C, bool NT>
 __global__ __launch_bounds__(FUSE_THREADS) void fused_kernel(StepLaunch Lc) {
   const int b = blockIdx.x;
   const LevelDesc *dp = Lc.d0;
@@ -462,7 +462,7 @@ __global__ __launch_bounds__(FUSE_THREADS) void fused_kernel(StepLaunch Lc) {
     first_block = sg.first_block;
     nblocks = sg.nblocks;
   }
-  fused_tile<T, C>(*dp, b - first_block, nblocks, Lc.flags);
+  fused_tile<T, C, NT>(*dp, b - first_block, nblocks, Lc.flags);
 }
 
 // ev0/ev1 (may be null): events that take the kernel's own start and end
@@ -470,17 +470,23 @@ __global__ __launch_bounds__(FUSE_THREADS) void fused_kernel(StepLaunch Lc) {
 hipError_t launch_step(const StepLaunch &a, int fp32, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (a.nblocks <= 0 || a.nseg < 0) return hipSuccess;
   dim3 grid(a.nblocks), block(256);
+  const bool nt = (a.flags & STEP_NT_STORES) != 0, two = (a.flags & STEP_TWO_CELLS) != 0;
   if (a.flags & STEP_FUSED_PHASE) {
     block = dim3(FUSE_THREADS);
+#define VLBM_FUSED(S, C)                                                                          \
+  do {                                                                                            \
+    if (nt) hipExtLaunchKernelGGL((fused_kernel<S, C, true>), grid, block, 0, s, ev0, ev1, 0, a);  \
+    else hipExtLaunchKernelGGL((fused_kernel<S, C, false>), grid, block, 0, s, ev0, ev1, 0, a);    \
+  } while (0)
     if (!fp32)
-      hipExtLaunchKernelGGL((fused_kernel<double, double>), grid, block, 0, s, ev0, ev1, 0, a);
+      VLBM_FUSED(double, double);
     else if (a.flags & STEP_F64_MATH)
-      hipExtLaunchKernelGGL((fused_kernel<float, double>), grid, block, 0, s, ev0, ev1, 0, a);
+      VLBM_FUSED(float, double);
     else
-      hipExtLaunchKernelGGL((fused_kernel<float, float>), grid, block, 0, s, ev0, ev1, 0, a);
+      VLBM_FUSED(float, float);
+#undef VLBM_FUSED
     return hipGetLastError();
   }
-  const bool nt = (a.flags & STEP_NT_STORES) != 0, two = (a.flags & STEP_TWO_CELLS) != 0;
 #define VLBM_STEP(S, C)                                                                          \
   do {                                                                                           \
     if (nt && two)                                                                               \

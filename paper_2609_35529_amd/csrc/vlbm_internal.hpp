@@ -66,7 +66,10 @@ constexpr int FUSE_W = VLBM_FUSE_W;
 constexpr int FUSE_H = VLBM_FUSE_H;
 constexpr int FUSE_POS = (FUSE_W + 1) * FUSE_H > FUSE_W * (FUSE_H + 1) ? (FUSE_W + 1) * FUSE_H
                                                                       : FUSE_W * (FUSE_H + 1);
-constexpr int FUSE_THREADS = 256;
+#ifndef VLBM_FUSE_THREADS
+#define VLBM_FUSE_THREADS 256
+#endif
+constexpr int FUSE_THREADS = VLBM_FUSE_THREADS;
 static_assert(FUSE_W % 2 == 0 && FUSE_H % 2 == 0 && FUSE_W * FUSE_H <= FUSE_THREADS, "fused tile shape");
 
 enum StepFlags : int32_t {

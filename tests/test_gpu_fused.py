@@ -128,7 +128,7 @@ def test_lax_liu_staircase_fused():
 
 def test_quadrant_full_size_prefix_fused():
     case = wl.quadrant(n0=512, seed=0, steps=4)
-    o, g = _pair(case, case.steps, flags=FUSE | vlbm.TUNE_XCD_ORDER)
+    o, g = _pair(case, case.steps, flags=FUSE | vlbm.TUNE_XCD_ORDER | vlbm.TUNE_NT_STORES)
     compare_populations(o, g, case, FP64_TOL)
 
 
@@ -150,7 +150,8 @@ def test_toggle_mid_run_keeps_history():
     case = _random_case(40, 36, 3, [(1, 8, 8, 40, 32), (2, 24, 24, 40, 32)], bc=(1, 1, 0, 0))
     o = exact.run_oracle(case, steps=0)
     g = gpu_solver(case)
-    for k, flags in enumerate([0, FUSE, 0, FUSE | vlbm.TUNE_XCD_ORDER, FUSE]):
+    for k, flags in enumerate([0, FUSE, vlbm.TUNE_NT_STORES, FUSE | vlbm.TUNE_XCD_ORDER,
+                               FUSE | vlbm.TUNE_NT_STORES]):
         g.set_tuning(128 if k % 2 else 256, flags)
         o.advance(3)
         g.advance(3)
