@@ -176,9 +176,15 @@ __device__ __forceinline__ void run_task(const LevelDesc &A, int first, double a
 // The fused step kernel
 // ---------------------------------------------------------------------------
 // S: storage type of the populations, C: type the relaxation computes in.
+// Population planes live in global memory: loads and stores through global
+// (not generic) pointers, so no aperture check and no LDS counter in the waits.
+template <class S>
+using gptr = __attribute__((address_space(1))) S *;
+
 template <class S, class C>
-__device__ __forceinline__ void pull(const S *__restrict__ s, int64_t P, int pitch, int64_t o,
+__device__ __forceinline__ void pull(const S *__restrict__ s0, int64_t P, int pitch, int64_t o,
                                      C g[16]) {
+  const auto s = (__attribute__((address_space(1))) const S *)s0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     g[k] = (C)s[(0 * 4 + k) * P + o - 1];           // +x arrives from x-1
@@ -189,7 +195,8 @@ __device__ __forceinline__ void pull(const S *__restrict__ s, int64_t P, int pit
 }
 
 template <class S, class C, bool NT>
-__device__ __forceinline__ void put(S *__restrict__ d, int64_t P, int64_t o, const C g[16]) {
+__device__ __forceinline__ void put(S *__restrict__ d0, int64_t P, int64_t o, const C g[16]) {
+  const auto d = (gptr<S>)d0;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const S v = (S)g[i];
