@@ -231,14 +231,6 @@ def main():
     regrid_every = 5
     amr = {"regrids": 0, "boxes": [], "regrid_s": 0.0, "updates": 0}
 
-    cell_launches = {}  # (level, fused) -> sum over launches of the level's active cells
-
-    def count_cells(before, after):
-        for key, (_, calls) in after.items():
-            dn = calls - before.get(key, (0.0, 0))[1]
-            if dn:
-                cell_launches[key] = cell_launches.get(key, 0) + dn * solver.active_cells(key[0])
-
     def run(n):
         """n coarse steps; the dynamic-AMR workload re-tags and regrids every
         regrid_every coarse steps (inside the timed region)."""
@@ -255,9 +247,7 @@ def main():
                 amr["regrids"] += 1
                 amr["boxes"].append(len(solver.boxes()))
             k = min(n - done, regrid_every - solver.steps() % regrid_every)
-            before = solver.kernel_times()
             solver.advance(k)
-            count_cells(before, solver.kernel_times())
             act = [solver.active_cells(l) for l in range(case.nlev)]
             amr["updates"] += k * sum(a * case.r ** l for l, a in enumerate(act))
             done += k
@@ -293,8 +283,6 @@ def main():
     ktimes = solver.kernel_times()
     prof_wall = time.perf_counter() - tp
     solver.set_profiling(False)
-    if not dynamic:
-        count_cells({}, ktimes)
     T1, L1 = solver.totals()
     healthy = solver.check_health()
 
@@ -303,15 +291,16 @@ def main():
     upd = actual_updates_per_step(case) if not dynamic else upd_timed / args.steps
     esz = 8 if prec == vlbm.FP64 else 4
     bytes_per_update = 2 * 16 * esz
-    nl = sum(c for _, c in ktimes.values()) / prof_steps
+    nl = sum(v[1] for v in ktimes.values()) / prof_steps
     # dominant kernel: the (level, launch form) with the largest kernel time;
     # algorithmic bytes of one launch: 16 populations read and 16 written per
-    # active cell of the level (a fused launch keeps the intermediate time
-    # level on chip, so it moves the same bytes for two sub-steps)
+    # active cell it advances (a fused launch keeps the finest level's
+    # intermediate time level on chip, so it moves the same bytes for two
+    # sub-steps)
     dom = max(ktimes, key=lambda k: ktimes[k][0])
-    dom_ms, dom_calls = ktimes[dom]
+    dom_ms, dom_calls, dom_cells = ktimes[dom]
     avg_launch_s = dom_ms / 1e3 / dom_calls
-    bytes_per_launch = cell_launches[dom] / dom_calls * bytes_per_update
+    bytes_per_launch = dom_cells / dom_calls * bytes_per_update
     achieved = bytes_per_launch / avg_launch_s / 1e9
     kernel_name = "fused_kernel" if dom[1] else "step_kernel"
     traffic = None
@@ -346,7 +335,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel_name, "level": dom[0], "bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": avg_launch_s * 1e6, "launches": dom_calls,
-                     "kernel_share": dom_ms / sum(t for t, _ in ktimes.values()),
+                     "kernel_share": dom_ms / sum(v[0] for v in ktimes.values()),
                      "timing": f"per-kernel events over {prof_steps} further coarse steps "
                                f"({prof_wall * 1e3 / prof_steps:.4f} ms/step with events)"},
         "actual_updates_per_s": upd * args.steps / wall,

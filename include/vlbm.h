@@ -209,11 +209,14 @@ vlbm_status vlbm_autotune(vlbm_ctx *ctx, int steps_per_trial, int *tile_cells, i
  * keeps the totals. Launches of vlbm_batch_advance are not recorded. */
 vlbm_status vlbm_set_profiling(vlbm_ctx *ctx, int enable);
 
-/* Accumulated kernel time in ms and launch count per level and launch form,
- * at index 2 * level + f with f = 1 for fused two-sub-step launches; ms and
- * calls hold 2 * VLBM_MAX_LEVELS entries each. Synchronises with the
- * recorded launches. */
-vlbm_status vlbm_kernel_times(vlbm_ctx *ctx, double *ms, long *calls);
+/* Accumulated kernel time in ms, launch count and active cells advanced
+ * (summed over the launches) per level and launch form, at index
+ * 2 * level + f with f = 1 for fused two-sub-step launches of the finest level
+ * (r = 2 hierarchy with tuning flag 16), which advance each cell by both
+ * sub-steps of its parent's step. ms, calls and cells hold
+ * 2 * VLBM_MAX_LEVELS entries each. Synchronises with the recorded
+ * launches. */
+vlbm_status vlbm_kernel_times(vlbm_ctx *ctx, double *ms, long *calls, double *cells);
 
 /* Coarse steps taken since set_state. */
 long vlbm_steps(const vlbm_ctx *ctx);

@@ -232,6 +232,19 @@ struct Level {
 
 }  // namespace
 
+namespace {
+// One launch of a coarse step: segments [seg0, seg0 + nseg) of the segment
+// table (parity e adds e times the table's half length).
+struct LaunchRec {
+  int32_t seg0 = 0, nseg = 0, nblocks = 0;
+  int32_t first = 0;         // CAPTURE: first sub-step of the parent's cycle (step tiles)
+  double ak = 0.0;           // reconstruction weight of the step tiles' sub-step
+  int32_t fused_kernel = 0;  // launched as the fused kernel
+  int32_t prof_key = 0;      // 2 * level + fused, for per-kernel timing
+  double cells = 0.0;        // active cells the launch advances
+};
+}  // namespace
+
 struct vlbm_ctx {
   vlbm_params p{};
   hipStream_t stream = nullptr;
@@ -263,9 +276,14 @@ struct vlbm_ctx {
   // step launch, read back in batches
   bool prof = false;
   std::vector<hipEvent_t> pev;  // event pool, two per pending launch
-  std::vector<int> pend;        // pending launches: 2 * level + fused
+  std::vector<std::pair<int, double>> pend;  // pending launches: (2 * level + fused, cells)
   double prof_ms[2 * kMaxLevels] = {};
   long prof_calls[2 * kMaxLevels] = {};
+  double prof_cells[2 * kMaxLevels] = {};
+  // launches of one coarse step and their segment table (both parities)
+  std::vector<LaunchRec> launches;
+  std::vector<Segment> hseg;
+  int nseg_table = 0;
   long graph_key = -1;
 
   bool perx() const { return p.bc[0] == VLBM_BC_PERIODIC; }
@@ -1020,6 +1038,7 @@ bool fused_active(const vlbm_ctx *c) {
 }
 
 
+// Descriptor of level l at flip counts st (fused: its fused two-sub-step tiles).
 LevelDesc make_desc(const vlbm_ctx *c, int l, const long *st, bool fused = false) {
   const Level &L = c->lv[l];
   LevelDesc a{};
@@ -1056,8 +1075,18 @@ void drop_graph(vlbm_ctx *c) {
   c->graph_key = -1;
 }
 
+double ak_of(int k, int r) { return (double)(2 * k - r - 1) / (double)(2 * r); }
+
+long tile_cells_sum(const Level &L, bool fused, size_t t0, size_t t1) {
+  const std::vector<Tile> &T = fused ? L.ftiles : L.tiles;
+  long n = 0;
+  for (size_t t = t0; t < std::min(t1, T.size()); ++t) n += (long)T[t].w * T[t].h;
+  return n;
+}
+
 // (Re)build the descriptor tables after any change of buffers, lists or
-// step counters.
+// step counters: one descriptor per phase and parity (e * P + p), one launch
+// per phase, each a run of segments of the segment table.
 vlbm_status build_tables(vlbm_ctx *c) {
   drop_graph(c);
   c->phases.clear();
@@ -1066,27 +1095,61 @@ vlbm_status build_tables(vlbm_ctx *c) {
   // buffer flips of each level per coarse step: one per phase
   for (int l = 0; l < kMaxLevels; ++l) c->flips[l] = 0;
   for (const auto &ph : c->phases) c->flips[ph.first] += 1;
+  auto nb8 = [](long n) { return (int32_t)((n + 7) / 8 * 8); };
   std::vector<LevelDesc> descs(2 * P);
-  std::vector<Segment> segs(2 * P);
-  c->mem.release(c->ddesc);
-  c->mem.release(c->dseg);
-  c->ddesc = static_cast<LevelDesc *>(c->mem.alloc(sizeof(LevelDesc) * 2 * P));
-  c->dseg = static_cast<Segment *>(c->mem.alloc(sizeof(Segment) * 2 * P));
-  if (!c->ddesc || !c->dseg) return fail(VLBM_ENOMEM, "schedule tables");
+  c->launches.clear();
+  std::vector<std::pair<int, int>> seg_desc;  // per parity-0 segment: (desc index e=0, nblocks)
+  std::vector<int> seg_desc1;                 // the same segment's desc index for e=1
   c->phase_blocks.assign(P, 0);
   for (int e = 0; e < 2; ++e) {
     long st[kMaxLevels];
     for (int l = 0; l < kMaxLevels; ++l) st[l] = c->lv[l].steps + e * c->flips[l];
     for (size_t p = 0; p < P; ++p) {
-      const int l = c->phases[p].first;
-      const bool fused = c->phases[p].second == 0;
+      const int l = c->phases[p].first, k = c->phases[p].second;
+      const bool fused = k == 0;
       descs[e * P + p] = make_desc(c, l, st, fused);
-      st[l] += 1;
-      const int nb = ((int)(fused ? c->lv[l].ftiles.size() : c->lv[l].tiles.size()) + 7) / 8 * 8;
-      segs[e * P + p] = {c->ddesc + e * P + p, 0, nb};
+      const int nb = nb8(fused ? c->lv[l].ftiles.size() : c->lv[l].tiles.size());
       c->phase_blocks[p] = nb;
+      if (e == 0) {
+        LaunchRec a{};
+        a.seg0 = (int)seg_desc.size();
+        seg_desc.push_back({(int)(e * P + p), nb});
+        a.nseg = 1;
+        a.first = k == 1;
+        a.ak = ak_of(k, c->p.r);
+        a.fused_kernel = fused;
+        a.prof_key = 2 * l + (fused ? 1 : 0);
+        a.cells = (double)tile_cells_sum(c->lv[l], fused, 0, SIZE_MAX);
+        c->launches.push_back(a);
+      } else {
+        seg_desc1.push_back((int)(e * P + p));
+      }
+      st[l] += 1;
     }
   }
+  const size_t NS = seg_desc.size();
+  if (seg_desc1.size() != NS) return fail(VLBM_EINVAL, "internal: launch tables differ between parities");
+  c->mem.release(c->ddesc);
+  c->mem.release(c->dseg);
+  c->ddesc = static_cast<LevelDesc *>(c->mem.alloc(sizeof(LevelDesc) * descs.size()));
+  c->dseg = static_cast<Segment *>(c->mem.alloc(sizeof(Segment) * std::max<size_t>(1, 2 * NS)));
+  if (!c->ddesc || !c->dseg) return fail(VLBM_ENOMEM, "schedule tables");
+  // segments of one launch are laid out back to back, first_block running on
+  std::vector<Segment> segs(2 * NS);
+  for (const LaunchRec &a : c->launches) {
+    int32_t fb = 0;
+    for (int i = a.seg0; i < a.seg0 + a.nseg; ++i) {
+      segs[i] = {c->ddesc + seg_desc[i].first, fb, seg_desc[i].second};
+      segs[NS + i] = {c->ddesc + seg_desc1[i], fb, seg_desc[i].second};
+      fb += seg_desc[i].second;
+    }
+  }
+  for (LaunchRec &a : c->launches) {
+    a.nblocks = 0;
+    for (int i = a.seg0; i < a.seg0 + a.nseg; ++i) a.nblocks += seg_desc[i].second;
+  }
+  c->nseg_table = (int)NS;
+  c->hseg = segs;
   c->hdesc = descs;
   HIPCHK(hipMemcpyAsync(c->ddesc, descs.data(), sizeof(LevelDesc) * descs.size(), hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(c->dseg, segs.data(), sizeof(Segment) * segs.size(), hipMemcpyHostToDevice, c->stream));
@@ -1095,7 +1158,7 @@ vlbm_status build_tables(vlbm_ctx *c) {
   return VLBM_OK;
 }
 
-double ak_of(int k, int r) { return (double)(2 * k - r - 1) / (double)(2 * r); }
+
 
 // Read back the pending launch timings into the accumulators.
 vlbm_status prof_flush(vlbm_ctx *c) {
@@ -1104,27 +1167,33 @@ vlbm_status prof_flush(vlbm_ctx *c) {
   for (size_t i = 0; i < c->pend.size(); ++i) {
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, c->pev[2 * i], c->pev[2 * i + 1]));
-    c->prof_ms[c->pend[i]] += ms;
-    c->prof_calls[c->pend[i]] += 1;
+    c->prof_ms[c->pend[i].first] += ms;
+    c->prof_calls[c->pend[i].first] += 1;
+    c->prof_cells[c->pend[i].first] += c->pend[i].second;
   }
   c->pend.clear();
   return VLBM_OK;
 }
 
-// Launch every phase of one coarse step of table parity e.
+// Launch every launch of one coarse step of table parity e.
 vlbm_status launch_coarse_step(vlbm_ctx *c, int e) {
-  const size_t P = c->phases.size();
-  for (size_t p = 0; p < P; ++p) {
+  for (const LaunchRec &r : c->launches) {
+    if (r.nblocks <= 0) continue;
     StepLaunch a{};
-    a.d0 = c->ddesc + e * P + p;
-    a.segs = nullptr;
-    a.nseg = 0;
-    a.nblocks = c->phase_blocks[p];
-    a.first = c->phases[p].second == 1;
-    a.flags = c->step_flags | (c->phases[p].second == 0 ? STEP_FUSED_PHASE : 0);
-    a.ak = ak_of(c->phases[p].second, c->p.r);
+    const int s0 = e * c->nseg_table + r.seg0;
+    if (r.nseg == 1) {
+      a.d0 = c->hseg[s0].d;
+      a.nseg = 0;
+    } else {
+      a.segs = c->dseg + s0;
+      a.nseg = r.nseg;
+    }
+    a.nblocks = r.nblocks;
+    a.first = r.first;
+    a.flags = c->step_flags | (r.fused_kernel ? STEP_FUSED_PHASE : 0);
+    a.ak = r.ak;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->prof && a.nblocks > 0) {
+    if (c->prof) {
       if (c->pend.size() >= 4096) {
         vlbm_status st = prof_flush(c);
         if (st) return st;
@@ -1137,7 +1206,7 @@ vlbm_status launch_coarse_step(vlbm_ctx *c, int e) {
       }
       e0 = c->pev[i];
       e1 = c->pev[i + 1];
-      c->pend.push_back(2 * c->phases[p].first + (c->phases[p].second == 0 ? 1 : 0));
+      c->pend.push_back({r.prof_key, r.cells});
     }
     HIPCHK(launch_step(a, c->fp32, c->stream, e0, e1));
   }
@@ -2319,17 +2388,19 @@ vlbm_status vlbm_set_profiling(vlbm_ctx *c, int enable) {
     for (int i = 0; i < 2 * kMaxLevels; ++i) {
       c->prof_ms[i] = 0.0;
       c->prof_calls[i] = 0;
+      c->prof_cells[i] = 0.0;
     }
   return VLBM_OK;
 }
 
-vlbm_status vlbm_kernel_times(vlbm_ctx *c, double *ms, long *calls) {
-  if (!c || !ms || !calls) return fail(VLBM_EINVAL, "null argument");
+vlbm_status vlbm_kernel_times(vlbm_ctx *c, double *ms, long *calls, double *cells) {
+  if (!c || !ms || !calls || !cells) return fail(VLBM_EINVAL, "null argument");
   vlbm_status st = prof_flush(c);
   if (st) return st;
   for (int i = 0; i < 2 * kMaxLevels; ++i) {
     ms[i] = c->prof_ms[i];
     calls[i] = c->prof_calls[i];
+    cells[i] = c->prof_cells[i];
   }
   return VLBM_OK;
 }

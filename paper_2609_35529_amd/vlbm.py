@@ -93,7 +93,7 @@ vlbm_steps = _sig("vlbm_steps", C.c_long, [_P])
 vlbm_active_cells = _sig("vlbm_active_cells", C.c_long, [_P, C.c_int])
 vlbm_sync = _sig("vlbm_sync", _st, [_P])
 vlbm_set_profiling = _sig("vlbm_set_profiling", _st, [_P, C.c_int])
-vlbm_kernel_times = _sig("vlbm_kernel_times", _st, [_P, _D, C.POINTER(C.c_long)])
+vlbm_kernel_times = _sig("vlbm_kernel_times", _st, [_P, _D, C.POINTER(C.c_long), _D])
 MAX_LEVELS = 8
 vlbm_last_error = _sig("vlbm_last_error", C.c_char_p, [])
 
@@ -281,12 +281,15 @@ class Solver:
         check(vlbm_set_profiling(self._h, int(bool(enable))))
 
     def kernel_times(self):
-        """{(level, fused): (total_ms, launches)} for the launches recorded
-        since set_profiling(True)."""
+        """{(level, fused): (total_ms, launches, cells)} for the launches
+        recorded since set_profiling(True); cells: active cells advanced, summed
+        over the launches."""
         ms = (C.c_double * (2 * MAX_LEVELS))()
         calls = (C.c_long * (2 * MAX_LEVELS))()
-        check(vlbm_kernel_times(self._h, ms, calls))
-        return {(i // 2, bool(i % 2)): (ms[i], calls[i]) for i in range(2 * MAX_LEVELS) if calls[i]}
+        cells = (C.c_double * (2 * MAX_LEVELS))()
+        check(vlbm_kernel_times(self._h, ms, calls, cells))
+        return {(i // 2, bool(i % 2)): (ms[i], calls[i], cells[i])
+                for i in range(2 * MAX_LEVELS) if calls[i]}
 
     def set_tuning(self, tile_cells, flags=0):
         check(vlbm_set_tuning(self._h, int(tile_cells), int(flags)))

@@ -198,13 +198,15 @@ def test_kernel_times_count_launches():
     t = g.kernel_times()
     assert set(t) == {(0, False), (1, False)}
     assert t[(0, False)][1] == 6 and t[(1, False)][1] == 12
-    assert all(ms > 0 for ms, _ in t.values())
+    assert t[(0, False)][2] == 6 * g.active_cells(0) and t[(1, False)][2] == 12 * g.active_cells(1)
+    assert all(v[0] > 0 for v in t.values())
     g.set_tuning(256, FUSE)
     g.set_profiling(True)
     g.advance(5)
     t = g.kernel_times()
     assert set(t) == {(0, False), (1, True)}
     assert t[(0, False)][1] == 5 and t[(1, True)][1] == 5
+    assert t[(1, True)][2] == 5 * g.active_cells(1) and t[(0, False)][2] == 5 * g.active_cells(0)
     g.set_profiling(False)
     g.advance(2)
     assert g.kernel_times() == t
