@@ -66,6 +66,12 @@ typedef enum {
 
 enum { VLBM_BC_PERIODIC = 0, VLBM_BC_OUTFLOW = 1, VLBM_BC_REFLECT = 2, VLBM_BC_INFLOW = 3 };
 enum { VLBM_FP64 = 0, VLBM_FP32 = 1, VLBM_FP32_STORAGE = 2 };
+/* Equations of state p(rho, rho e), rho e = E - (m_x^2 + m_y^2) / (2 rho)
+ * (Sec. 2.1 leaves the EOS generic; the coupling is EOS-blind):
+ *   IDEAL      (gamma - 1) rho e
+ *   STIFFENED  (gamma - 1) rho e - gamma a
+ *   VDW        ((gamma - 1) (rho e + a rho^2)) / (1 - b rho) - a rho^2 */
+enum { VLBM_EOS_IDEAL = 0, VLBM_EOS_STIFFENED = 1, VLBM_EOS_VDW = 2 };
 
 /* Problem parameters (the paper's problem statement: base grid, ratio, EOS,
  * relaxation, link speed; Sec. 2.2 and 3.2).
@@ -88,6 +94,8 @@ typedef struct {
   int r;
   int max_levels; /* number of levels including level 0, 1..8 */
   int precision;
+  int eos;        /* VLBM_EOS_*; a zeroed struct is an ideal gas */
+  double eos_a, eos_b; /* EOS constants a and b (b >= 0) */
 } vlbm_params;
 
 typedef struct {

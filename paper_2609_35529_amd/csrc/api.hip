@@ -260,6 +260,7 @@ struct vlbm_ctx {
   int step_flags = 0;
   int *dflag = nullptr;
   double gm1 = 0, h = 0, tb = 0;
+  EosT<double> eos{};
   double ledger_carry[4] = {0, 0, 0, 0}, ledger_carry_c[4] = {0, 0, 0, 0};
   // schedule tables: phases of one coarse step and their descriptors for the
   // two parities of the coarse step counter relative to table_base
@@ -1064,6 +1065,10 @@ LevelDesc make_desc(const vlbm_ctx *c, int l, const long *st, bool fused = false
   a.gm1 = c->gm1;
   a.h = c->h;
   a.tb = c->tb;
+  a.eos = c->eos.kind;
+  a.eos_a = c->eos.a;
+  a.eos_b = c->eos.b;
+  a.eos_ga = c->eos.ga;
   for (int s2 = 0; s2 < 4; ++s2)
     for (int k = 0; k < 4; ++k) a.win[s2][k] = c->p.w_inflow[s2][k];
   return a;
@@ -1325,6 +1330,7 @@ vlbm_status rect_io(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny, doub
   a.ny = cny;
   a.gm1 = c->gm1;
   a.h = c->h;
+  a.eos = c->eos;
   hipError_t e = hipSuccess;
   if (write) {
     for (int k = 0; k < ncomp; ++k)
@@ -1841,7 +1847,8 @@ vlbm_status vlbm_create(const vlbm_params *params, void *stream, vlbm_ctx **out)
   if (p.nx0 < 1 || p.ny0 < 1 || !(p.dx0 > 0) || p.r < 1 || p.r > 8 || p.max_levels < 1 ||
       p.max_levels > kMaxLevels || !(p.c > 0) || !(p.beta >= 0 && p.beta <= 1) ||
       !(p.gamma > 1) ||
-      (p.precision != VLBM_FP64 && p.precision != VLBM_FP32 && p.precision != VLBM_FP32_STORAGE))
+      (p.precision != VLBM_FP64 && p.precision != VLBM_FP32 && p.precision != VLBM_FP32_STORAGE) ||
+      p.eos < VLBM_EOS_IDEAL || p.eos > VLBM_EOS_VDW || !(p.eos_b >= 0.0) || !std::isfinite(p.eos_a))
     return fail(VLBM_EINVAL, "invalid parameters");
   for (int s = 0; s < 4; ++s)
     if (p.bc[s] < 0 || p.bc[s] > 3) return fail(VLBM_EINVAL, "invalid boundary condition");
@@ -1864,6 +1871,7 @@ vlbm_status vlbm_create(const vlbm_params *params, void *stream, vlbm_ctx **out)
   if (const char *e = getenv("VLBM_XCD_CONTIGUOUS")) c->step_flags |= atoi(e) ? STEP_XCD_CONTIGUOUS : 0;
   if (const char *e = getenv("VLBM_GRAPHS")) c->use_graphs = atoi(e) != 0;
   c->gm1 = p.gamma - 1.0;
+  c->eos = EosT<double>{p.eos, p.gamma - 1.0, p.eos_a, p.eos_b, p.gamma * p.eos_a};
   c->h = 1.0 / (2.0 * p.c);
   c->tb = 2.0 * p.beta;
   *out = c;
@@ -2031,7 +2039,7 @@ vlbm_status vlbm_check_health(vlbm_ctx *c) {
   for (int l = 0; l < c->nlev; ++l) {
     Level &L = c->lv[l];
     HIPCHK(launch_health(L.buf[L.cur()], L.dtiles, (int)L.tiles.size(), L.plane, L.pitch, c->fp32,
-                         c->gm1, c->dflag, c->stream));
+                         c->eos, c->dflag, c->stream));
   }
   int flag = 0;
   HIPCHK(hipMemcpyAsync(&flag, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -2160,7 +2168,7 @@ vlbm_status vlbm_load(vlbm_ctx *c, const void *buf, size_t bytes) {
     const vlbm_params &a = h.p, &b = c->p;
     bool same = a.nx0 == b.nx0 && a.ny0 == b.ny0 && a.dx0 == b.dx0 && a.gamma == b.gamma &&
                 a.c == b.c && a.beta == b.beta && a.r == b.r && a.max_levels == b.max_levels &&
-                a.precision == b.precision;
+                a.precision == b.precision && a.eos == b.eos && a.eos_a == b.eos_a && a.eos_b == b.eos_b;
     for (int s = 0; s < 4; ++s) {
       same = same && a.bc[s] == b.bc[s];
       for (int k = 0; k < 4; ++k) same = same && a.w_inflow[s][k] == b.w_inflow[s][k];

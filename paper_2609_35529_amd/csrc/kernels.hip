@@ -23,8 +23,24 @@
 
 namespace vlbm {
 
+// Pressure of the equation of state (EosT); kind is launch-uniform.
 template <class T>
-__device__ __forceinline__ void relax(T g[16], T gm1, T h, T tb) {
+__device__ __forceinline__ T pressure(const EosT<T> &e, T rho, T eint) {
+  if (e.kind == 1) return e.gm1 * eint - e.ga;
+  if (e.kind == 2) {
+    const T ar = (e.a * rho) * rho;
+    return e.gm1 * (eint + ar) / (T(1) - e.b * rho) - ar;
+  }
+  return e.gm1 * eint;
+}
+
+template <class T>
+__device__ __forceinline__ EosT<T> eos_of(const LevelDesc &A) {
+  return EosT<T>{A.eos, (T)A.gm1, (T)A.eos_a, (T)A.eos_b, (T)A.eos_ga};
+}
+
+template <class T>
+__device__ __forceinline__ void relax(T g[16], const EosT<T> &eos, T h, T tb) {
   T W[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) W[k] = ((g[k] + g[4 + k]) + g[8 + k]) + g[12 + k];
@@ -32,7 +48,7 @@ __device__ __forceinline__ void relax(T g[16], T gm1, T h, T tb) {
   const T u = mx / rho;
   const T v = my / rho;
   const T eint = E - T(0.5) * (mx * u + my * v);
-  const T p = gm1 * eint;
+  const T p = pressure<T>(eos, rho, eint);
   const T Qx[4] = {mx, mx * u + p, my * u, (E + p) * u};
   const T Qy[4] = {my, mx * v, my * v + p, (E + p) * v};
 #pragma unroll
@@ -48,13 +64,13 @@ __device__ __forceinline__ void relax(T g[16], T gm1, T h, T tb) {
 }
 
 // Equilibrium of a conserved state, FP64 (inflow ghosts, set_state).
-__device__ __forceinline__ void equilibrium(const double W[4], double gm1, double h,
+__device__ __forceinline__ void equilibrium(const double W[4], const EosT<double> &eos, double h,
                                             double f[16]) {
   const double rho = W[0], mx = W[1], my = W[2], E = W[3];
   const double u = mx / rho;
   const double v = my / rho;
   const double eint = E - 0.5 * (mx * u + my * v);
-  const double p = gm1 * eint;
+  const double p = pressure<double>(eos, rho, eint);
   const double Qx[4] = {mx, mx * u + p, my * u, (E + p) * u};
   const double Qy[4] = {my, mx * v, my * v + p, (E + p) * v};
 #pragma unroll
@@ -110,7 +126,7 @@ __device__ __forceinline__ void run_task(const LevelDesc &A, int first, double a
 #pragma unroll
         for (int k = 0; k < 4; ++k)
           W[k] = side == 0 ? A.win[0][k] : side == 1 ? A.win[1][k] : side == 2 ? A.win[2][k] : A.win[3][k];
-        equilibrium(W, A.gm1, A.h, f);
+        equilibrium(W, eos_of<double>(A), A.h, f);
 #pragma unroll
         for (int k = 0; k < 4; ++k)
           in[k] = (double)(T)(q == 0 ? f[k] : q == 1 ? f[4 + k] : q == 2 ? f[8 + k] : f[12 + k]);
@@ -225,7 +241,8 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
   T *__restrict__ d = static_cast<T *>(A.dst);
   const int64_t plane = A.plane;
   const int pitch = A.pitch;
-  const C gm1 = (C)A.gm1, h = (C)A.h, tb = (C)A.tb;
+  const EosT<C> eos = eos_of<C>(A);
+  const C h = (C)A.h, tb = (C)A.tb;
   if (tl.ntask) {
     for (int i = threadIdx.x; i < tl.ntask; i += blockDim.x)
       run_task<T>(A, first, ak, A.tasks[tl.task0 + i]);
@@ -246,10 +263,10 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
         o2 = (int64_t)tl.off0 + (int64_t)cy2 * pitch + cx2;
         pull<T, C>(s, plane, pitch, o2, g2);
       }
-      relax<C>(g, gm1, h, tb);
+      relax<C>(g, eos, h, tb);
       put<T, C, NT>(d, plane, o, g);
       if (c2 < n) {
-        relax<C>(g2, gm1, h, tb);
+        relax<C>(g2, eos, h, tb);
         put<T, C, NT>(d, plane, o2, g2);
       }
     }
@@ -260,7 +277,7 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
       const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
       C g[16];
       pull<T, C>(s, plane, pitch, o, g);
-      relax<C>(g, gm1, h, tb);
+      relax<C>(g, eos, h, tb);
       put<T, C, NT>(d, plane, o, g);
     }
   }
@@ -345,7 +362,7 @@ __device__ __forceinline__ void run_task_k2(const LevelDesc &A, double ak2, cons
 #pragma unroll
     for (int k = 0; k < 4; ++k)
       W[k] = side == 0 ? A.win[0][k] : side == 1 ? A.win[1][k] : side == 2 ? A.win[2][k] : A.win[3][k];
-    equilibrium(W, A.gm1, A.h, f);
+    equilibrium(W, eos_of<double>(A), A.h, f);
 #pragma unroll
     for (int k = 0; k < 4; ++k)
       in[k] = (double)(T)(q == 0 ? f[k] : q == 1 ? f[4 + k] : q == 2 ? f[8 + k] : f[12 + k]);
@@ -375,7 +392,8 @@ __device__ __forceinline__ void fused_tile(const LevelDesc &A, int lb, int nbloc
   T *__restrict__ d = static_cast<T *>(A.dst);
   const int64_t plane = A.plane;
   const int pitch = A.pitch;
-  const C gm1 = (C)A.gm1, h = (C)A.h, tb = (C)A.tb;
+  const EosT<C> eos = eos_of<C>(A);
+  const C h = (C)A.h, tb = (C)A.tb;
   const int w = tl.w, w1 = w + 1;
   const double ak1 = (double)(1 - A.r) / (double)(2 * A.r);   // k = 1
   const double ak2 = (double)(3 - A.r) / (double)(2 * A.r);   // k = 2
@@ -392,7 +410,7 @@ __device__ __forceinline__ void fused_tile(const LevelDesc &A, int lb, int nbloc
       const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
       C g[16];
       pull<T, C>(s, plane, pitch, o, g);
-      relax<C>(g, gm1, h, tb);
+      relax<C>(g, eos, h, tb);
       const int p0 = cy * w1 + cx + 1, p1 = cy * w1 + cx, p2 = (cy + 1) * w + cx, p3 = cy * w + cx;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -405,7 +423,7 @@ __device__ __forceinline__ void fused_tile(const LevelDesc &A, int lb, int nbloc
       const Task &t = ring[i - ncell];
       C g[16];
       pull<T, C>(s, plane, pitch, (int64_t)t.src, g);
-      relax<C>(g, gm1, h, tb);
+      relax<C>(g, eos, h, tb);
       const int q = t.q;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -447,7 +465,7 @@ __device__ __forceinline__ void fused_tile(const LevelDesc &A, int lb, int nbloc
       g[8 + k] = (C)F1[(8 + k) * np + p2];
       g[12 + k] = (C)F1[(12 + k) * np + p3];
     }
-    relax<C>(g, gm1, h, tb);
+    relax<C>(g, eos, h, tb);
     const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
     put<T, C, NT>(d, plane, o, g);
   }
@@ -587,7 +605,7 @@ __global__ void set_kernel(RectArgs a, int raw) {
       double W[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) W[k] = a.host_stage[k * n + c];
-      equilibrium(W, a.gm1, a.h, f);
+      equilibrium(W, a.eos, a.h, f);
     }
     T *b0 = static_cast<T *>(a.buf0), *b1 = static_cast<T *>(a.buf1);
 #pragma unroll
@@ -658,7 +676,7 @@ hipError_t launch_get(const RectArgs &a, int fp32, int pops, hipStream_t s) {
 // ---------------------------------------------------------------------------
 template <class T>
 __global__ void health_kernel(const T *__restrict__ buf, const Tile *tiles, int64_t P,
-                              int pitch, double gm1, int *flag) {
+                              int pitch, EosT<double> eos, int *flag) {
   const Tile tl = tiles[blockIdx.x];
   const int n = tl.w * tl.h;
   int bad = 0;
@@ -673,21 +691,21 @@ __global__ void health_kernel(const T *__restrict__ buf, const Tile *tiles, int6
               (double)buf[(8 + k) * P + o]) +
              (double)buf[(12 + k) * P + o];
     const double u = W[1] / W[0], v = W[2] / W[0];
-    const double p = gm1 * (W[3] - 0.5 * (W[1] * u + W[2] * v));
+    const double p = pressure<double>(eos, W[0], W[3] - 0.5 * (W[1] * u + W[2] * v));
     if (!(W[0] > 0.0) || !(p > 0.0)) bad = 1;
   }
   if (bad) atomicOr(flag, 1);
 }
 
 hipError_t launch_health(const void *buf, const Tile *tiles, int ntiles, int64_t plane,
-                         int pitch, int fp32, double gm1, int *flag, hipStream_t s) {
+                         int pitch, int fp32, const EosT<double> &eos, int *flag, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (fp32)
     hipLaunchKernelGGL(health_kernel<float>, dim3(ntiles), dim3(256), 0, s,
-                       static_cast<const float *>(buf), tiles, plane, pitch, gm1, flag);
+                       static_cast<const float *>(buf), tiles, plane, pitch, eos, flag);
   else
     hipLaunchKernelGGL(health_kernel<double>, dim3(ntiles), dim3(256), 0, s,
-                       static_cast<const double *>(buf), tiles, plane, pitch, gm1, flag);
+                       static_cast<const double *>(buf), tiles, plane, pitch, eos, flag);
   return hipGetLastError();
 }
 

@@ -72,6 +72,16 @@ constexpr int FUSE_POS = (FUSE_W + 1) * FUSE_H > FUSE_W * (FUSE_H + 1) ? (FUSE_W
 constexpr int FUSE_THREADS = VLBM_FUSE_THREADS;
 static_assert(FUSE_W % 2 == 0 && FUSE_H % 2 == 0 && FUSE_W * FUSE_H <= FUSE_THREADS, "fused tile shape");
 
+// Equation of state p(rho, rho e) (Sec. 2.1 leaves it generic): kind 0 ideal
+// gas (gamma-1) rho e; 1 stiffened gas (gamma-1) rho e - gamma a; 2 van der
+// Waals ((gamma-1) (rho e + a rho rho)) / (1 - b rho) - a rho rho; with
+// rho e = E - 0.5 (m_x u + m_y v) and ga = gamma * a.
+template <class T>
+struct EosT {
+  int32_t kind;
+  T gm1, a, b, ga;
+};
+
 enum StepFlags : int32_t {
   STEP_NT_STORES = 1,        // write the new time level with non-temporal stores
   STEP_TWO_CELLS = 2,        // two cells per thread, gathers issued together
@@ -93,10 +103,12 @@ struct LevelDesc {
   double *acc_out;           // parent's accumulators (CAPTURE writes)
   double *ledger;            // boundary ledger slots [slot][4]
   int64_t plane, pplane;     // elements per population plane (level, parent)
-  int32_t pitch, ntiles, r, pad;
+  int32_t pitch, ntiles, r;
+  int32_t eos;               // equation of state kind (EosT)
   double rr;                 // r * r
   double w2;                 // dx_l^2 (ledger weight)
   double gm1, h, tb;         // gamma - 1, 1/(2c), 2 beta
+  double eos_a, eos_b, eos_ga;  // EOS constants a, b and gamma * a
   double win[4][4];          // inflow conserved states per side
 };
 
@@ -130,6 +142,7 @@ struct RectArgs {
   int32_t pitch, xoff, fx0, fy0, fw;
   int32_t x0, y0, nx, ny;    // rectangle in level cells
   double gm1, h;
+  EosT<double> eos;
 };
 
 // Launchers (kernels.hip). All return hipError_t of the launch.
@@ -140,7 +153,7 @@ hipError_t launch_audit(const void *buf, const Tile *tiles, int ntiles, int64_t 
 hipError_t launch_set_state(const RectArgs &a, int fp32, int raw_populations, hipStream_t s);
 hipError_t launch_get(const RectArgs &a, int fp32, int populations, hipStream_t s);
 hipError_t launch_health(const void *buf, const Tile *tiles, int ntiles, int64_t plane,
-                         int pitch, int fp32, double gm1, int *flag, hipStream_t s);
+                         int pitch, int fp32, const EosT<double> &eos, int *flag, hipStream_t s);
 // tags: frame-indexed (fw x fh bytes), 1 on tagged active cells, else 0
 hipError_t launch_tag(const void *buf, const uint8_t *status, int64_t plane, int pitch,
                       int xoff, int fx0, int fy0, int fw, int fh, int Nx, int Ny, int perx,

@@ -36,6 +36,7 @@ VLBM_OK, VLBM_EINVAL, VLBM_ENOMEM, VLBM_ENEST, VLBM_EUNSTABLE, VLBM_EDEVICE, VLB
     0, -1, -2, -3, -4, -5, -6)
 PERIODIC, OUTFLOW, REFLECT, INFLOW = 0, 1, 2, 3
 FP64, FP32, FP32_STORAGE = 0, 1, 2
+EOS_IDEAL, EOS_STIFFENED, EOS_VDW = 0, 1, 2
 # vlbm_set_tuning flags
 TUNE_NT_STORES, TUNE_TWO_CELLS, TUNE_XCD_ORDER, TUNE_FUSE2 = 1, 2, 4, 16
 
@@ -44,7 +45,8 @@ class vlbm_params(C.Structure):
     _fields_ = [("nx0", C.c_int), ("ny0", C.c_int), ("dx0", C.c_double), ("bc", C.c_int * 4),
                 ("w_inflow", (C.c_double * 4) * 4), ("gamma", C.c_double), ("c", C.c_double),
                 ("beta", C.c_double), ("r", C.c_int), ("max_levels", C.c_int),
-                ("precision", C.c_int)]
+                ("precision", C.c_int), ("eos", C.c_int), ("eos_a", C.c_double),
+                ("eos_b", C.c_double)]
 
 
 class vlbm_box(C.Structure):
@@ -119,7 +121,8 @@ def check(status):
 
 
 def make_params(nx0, ny0, dx0, gamma, c, beta, r=2, max_levels=2, bc=(PERIODIC,) * 4,
-                w_inflow=None, precision=FP64) -> vlbm_params:
+                w_inflow=None, precision=FP64, eos=None) -> vlbm_params:
+    """eos: None (ideal gas) or (kind, a, b) with kind one of EOS_*."""
     p = vlbm_params()
     p.nx0, p.ny0, p.dx0 = nx0, ny0, dx0
     for s in range(4):
@@ -131,6 +134,8 @@ def make_params(nx0, ny0, dx0, gamma, c, beta, r=2, max_levels=2, bc=(PERIODIC,)
                 p.w_inflow[s][k] = float(w[s, k])
     p.gamma, p.c, p.beta = gamma, c, beta
     p.r, p.max_levels, p.precision = r, max_levels, precision
+    if eos is not None:
+        p.eos, p.eos_a, p.eos_b = int(eos[0]), float(eos[1]), float(eos[2])
     return p
 
 
@@ -158,9 +163,10 @@ class Solver:
     """One VLBM hierarchy living on the GPU (a ``vlbm_ctx``)."""
 
     def __init__(self, nx0, ny0, dx0, gamma=1.4, c=1.0, beta=0.9, r=2, max_levels=2,
-                 bc=(PERIODIC,) * 4, w_inflow=None, precision=FP64, stream=None, pool=None):
+                 bc=(PERIODIC,) * 4, w_inflow=None, precision=FP64, stream=None, pool=None,
+                 eos=None):
         self.params = make_params(nx0, ny0, dx0, gamma, c, beta, r, max_levels, bc, w_inflow,
-                                  precision)
+                                  precision, eos)
         self.nx0, self.ny0, self.r = nx0, ny0, r
         self.max_levels = max_levels
         self._h = C.c_void_p()
@@ -173,7 +179,8 @@ class Solver:
     @classmethod
     def from_case(cls, case, precision=FP64, stream=None, pool=None, max_levels=None):
         s = cls(case.nx0, case.ny0, case.dx0, case.gamma, case.c, case.beta, case.r,
-                max_levels or case.nlev, case.bc, case.w_inflow, precision, stream, pool)
+                max_levels or case.nlev, case.bc, case.w_inflow, precision, stream, pool,
+                eos=getattr(case, "eos", None))
         s.set_hierarchy(case.boxes)
         for l in range(case.nlev):
             if case.states[l] is not None:
@@ -311,6 +318,7 @@ def batch_advance(solvers, n_steps):
 
 def footprint_bytes(case, precision=FP64, max_levels=None):
     p = make_params(case.nx0, case.ny0, case.dx0, case.gamma, case.c, case.beta, case.r,
-                    max_levels or case.nlev, case.bc, case.w_inflow, precision)
+                    max_levels or case.nlev, case.bc, case.w_inflow, precision,
+                    getattr(case, "eos", None))
     arr, n = make_boxes(case.boxes)
     return vlbm_footprint_bytes(C.byref(p), arr, n)

@@ -80,6 +80,7 @@ class Case:
     w_inflow: Optional[np.ndarray] = None  # [4 sides][4] conserved inflow states
     x0: float = 0.0
     y0: float = 0.0
+    eos: Optional[Tuple[int, float, float]] = None  # (kind, a, b); None: ideal gas
 
     def level_shape(self, level):
         s = self.r ** level

@@ -148,6 +148,8 @@ def composite_1d_rho(orc, case):
 
 def run_oracle(case, steps=None, oracle_cls=None, **kw):
     from oracle.oracle import Oracle
+    if getattr(case, "eos", None) is not None and "eos" not in kw:
+        kw = dict(kw, eos=case.eos[0], eos_a=case.eos[1], eos_b=case.eos[2])
     o = Oracle(case.nx0, case.ny0, case.dx0, case.r, case.nlev, case.gamma, case.c, case.beta,
                case.bc, case.w_inflow, **kw)
     o.set_boxes(case.boxes)

@@ -212,3 +212,29 @@ def test_fp32_drift_per_step_is_reported(precision):
     rel = np.abs(T1 - T0) / np.maximum(np.abs(T0), 1e-3)
     print("fp32 drift per step", rel / case.steps)
     assert np.all(rel / case.steps < 1e-7)
+
+
+@pytest.mark.parametrize("eos", [(1, 0.4, 0.0), (2, 0.1, 0.05)])
+@pytest.mark.parametrize("flags", [0, 16])
+def test_non_ideal_eos(eos, flags):
+    """Stiffened gas and van der Waals: the bulk relaxation, inflow equilibria
+    and set_state use the EOS; FP64 parity with the oracle through three levels
+    and mixed boundaries, unfused and with fused sub-steps."""
+    import dataclasses
+    win = np.tile(wl.conserved(1.1, 0.4, -0.1, 1.2).reshape(4), (4, 1))
+    case = _random_case(40, 36, 3, [(1, 8, 8, 40, 32), (1, 48, 12, 16, 24),
+                                    (2, 24, 24, 40, 32)], bc=(3, 1, 2, 2), w=win)
+    case = dataclasses.replace(case, eos=eos)
+    o = exact.run_oracle(case, steps=0)
+    g = gpu_solver(case)
+    if flags:
+        g.set_tuning(256, flags)
+    o.advance(6)
+    g.advance(6)
+    compare_populations(o, g, case, FP64_TOL)
+    To, Lo = o.totals()
+    Tg, Lg = g.totals()
+    scale = np.abs(To).max()
+    assert np.all(np.abs(Tg - To) <= 1e-14 * scale)
+    assert np.all(np.abs((Tg - Lg) - (To - Lo)) <= 1e-13 * scale)
+    assert g.check_health()
