@@ -35,6 +35,8 @@ def lib():
         L.orc_free.argtypes = [C.c_void_p]
         L.orc_set_eos.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double]
         L.orc_set_mutation.argtypes = [C.c_void_p, C.c_int]
+        L.orc_set_sensor.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_double]
+        L.orc_get_beta.argtypes = [C.c_void_p, C.c_int, _D]
         L.orc_set_boxes.argtypes = [C.c_void_p, _I, C.c_int]
         L.orc_regrid.argtypes = [C.c_void_p, _I, C.c_int]
         for name in ("orc_set_state", "orc_get_state", "orc_get_pop", "orc_set_pop"):
@@ -125,6 +127,17 @@ class Oracle:
             raise RuntimeError("oracle: " + lib().orc_error().decode())
         if eos != EOS_IDEAL:
             lib().orc_set_eos(self._h, eos, eos_a, eos_b)
+
+    def set_sensor(self, on=True, c_sensor=1.0, beta_min=0.5, beta_max=0.9):
+        """Space/time-adaptive relaxation (eq. sensor-B), from the next step on."""
+        if lib().orc_set_sensor(self._h, int(bool(on)), c_sensor, beta_min, beta_max):
+            raise RuntimeError("oracle: " + lib().orc_error().decode())
+
+    def get_beta(self, level):
+        """beta of every cell of `level` at its last step, (Ny, Nx); 0 where inactive."""
+        out = np.zeros(self.shape(level))
+        lib().orc_get_beta(self._h, level, _dp(out))
+        return out
 
     def __del__(self):
         if getattr(self, "_h", None):

@@ -60,6 +60,9 @@ struct orc {
   double dx0, gamma, c, beta;
   int eos;
   double eos_a, eos_b;
+  int sensor;                        /* adaptive relaxation on (eq. sensor-B) */
+  double c_sensor, beta_min, beta_max;
+  double *beta_f[OMAXL];             /* per-cell beta of the level's last step */
   int mut;
   int bc[4];
   double win[4][4];
@@ -245,8 +248,9 @@ orc *orc_new(int nx0, int ny0, double dx0, int r, int nlev, double gamma, double
     o->accl[l] = (double *)calloc(16 * nc, sizeof(double));
     o->cov[l] = (unsigned char *)calloc(nc, 1);
     o->pok[l] = (unsigned char *)calloc(nc, 1);
+    o->beta_f[l] = (double *)calloc(nc, sizeof(double));
     if (!o->F[l] || !o->Fp[l] || !o->G[l] || !o->acc[l] || !o->accl[l] || !o->cov[l] ||
-        !o->pok[l]) {
+        !o->pok[l] || !o->beta_f[l]) {
       set_err("orc_new: out of memory");
       orc_free(o);
       return NULL;
@@ -267,8 +271,30 @@ void orc_free(orc *o) {
     free(o->accl[l]);
     free(o->cov[l]);
     free(o->pok[l]);
+    free(o->beta_f[l]);
   }
   free(o);
+}
+
+int orc_set_sensor(orc *o, int on, double c_sensor, double beta_min, double beta_max) {
+  if (on && !(beta_min > 0.0 && beta_min <= beta_max && beta_max <= 1.0 && c_sensor >= 0.0)) {
+    set_err("orc_set_sensor: need 0 < beta_min <= beta_max <= 1 and c_sensor >= 0");
+    return -1;
+  }
+  o->sensor = on;
+  o->c_sensor = c_sensor;
+  o->beta_min = beta_min;
+  o->beta_max = beta_max;
+  return 0;
+}
+
+int orc_get_beta(const orc *o, int level, double *beta) {
+  if (level < 0 || level >= o->nlev) {
+    set_err("orc_get_beta: bad level");
+    return -1;
+  }
+  memcpy(beta, o->beta_f[level], sizeof(double) * (size_t)o->Nx[level] * o->Ny[level]);
+  return 0;
 }
 
 int orc_set_eos(orc *o, int eos, double a, double b) {
@@ -490,10 +516,98 @@ static void ledger_add(orc *o, double w, const double v[4], double sign) {
   for (int k = 0; k < 4; ++k) kadd(&o->led[k], &o->ledc[k], sign * (w * v[k]));
 }
 
+/* Space/time-adaptive relaxation parameter (Sec. 2.2, eq. sensor-B) of every
+ * active cell of level l, from the state at the start of its step
+ * (W = sum of the stored populations; relaxation conserves it):
+ *   s_k   = dx (div Q)_k / Qmax_k, with dx (div Q)_k by central differences,
+ *           0.5 ((Qx_k(x+1) - Qx_k(x-1)) + (Qy_k(y+1) - Qy_k(y-1))), and
+ *           Qmax_k = max over the level's active cells and both directions
+ *           of |Q_{alpha,k}| (s_k = 0 where Qmax_k = 0);
+ *   a     = sqrt(0.25 (((s_0^2 + s_1^2) + s_2^2) + s_3^2))      (RMS over k);
+ *   sbar  = mean of a over the active cells of the 3x3 block (box filter S);
+ *   dil   = 0.5 ((u(x+1) - u(x-1)) + (v(y+1) - v(y-1))),
+ *   vort  = 0.5 ((v(x+1) - v(x-1)) - (u(y+1) - u(y-1)))         (times dx);
+ *   theta = dil^2 / (dil^2 + vort^2) where dil < 0 (compression), else 0;
+ *   beta  = beta_max - (beta_max - beta_min) clip(C sbar theta, 0, 1).
+ * A neighbour that is not an active cell of the level (outside the domain on
+ * a non-periodic side, coarser or finer) is replaced by the cell itself. */
+static void sensor_beta(orc *o, int l) {
+  const int Nx = o->Nx[l], Ny = o->Ny[l];
+  const size_t nc = (size_t)Nx * Ny;
+  const double *F = o->F[l];
+  double *beta = o->beta_f[l];
+  double *W = (double *)malloc(sizeof(double) * 4 * nc);
+  double *a = (double *)malloc(sizeof(double) * nc);
+  double *th = (double *)malloc(sizeof(double) * nc);
+  double qmax[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int y = 0; y < Ny; ++y)
+    for (int x = 0; x < Nx; ++x) {
+      if (!active(o, l, x, y)) continue;
+      size_t c = cidx(o, l, x, y);
+      double Wc[4], Qx[4], Qy[4];
+      for (int k = 0; k < 4; ++k)
+        Wc[k] = ((F[pidx(o, l, 0 * 4 + k, x, y)] + F[pidx(o, l, 1 * 4 + k, x, y)]) +
+                 F[pidx(o, l, 2 * 4 + k, x, y)]) + F[pidx(o, l, 3 * 4 + k, x, y)];
+      orc_flux(o->gamma, o->eos, o->eos_a, o->eos_b, Wc, Qx, Qy);
+      for (int k = 0; k < 4; ++k) {
+        W[4 * c + k] = Wc[k];
+        double m = fabs(Qx[k]) > fabs(Qy[k]) ? fabs(Qx[k]) : fabs(Qy[k]);
+        if (m > qmax[k]) qmax[k] = m;
+      }
+    }
+  for (int y = 0; y < Ny; ++y)
+    for (int x = 0; x < Nx; ++x) {
+      if (!active(o, l, x, y)) continue;
+      size_t c = cidx(o, l, x, y);
+      /* neighbours +x, -x, +y, -y (themselves where not active) */
+      size_t nb[4];
+      for (int d = 0; d < 4; ++d) {
+        int xx = x + CX[d], yy = y + CY[d];
+        nb[d] = (wrap(o, l, &xx, &yy) && active(o, l, xx, yy)) ? cidx(o, l, xx, yy) : c;
+      }
+      double Qx[4][4], Qy[4][4], u[4], v[4];
+      for (int d = 0; d < 4; ++d) {
+        orc_flux(o->gamma, o->eos, o->eos_a, o->eos_b, &W[4 * nb[d]], Qx[d], Qy[d]);
+        u[d] = W[4 * nb[d] + 1] / W[4 * nb[d] + 0];
+        v[d] = W[4 * nb[d] + 2] / W[4 * nb[d] + 0];
+      }
+      double sk[4];
+      for (int k = 0; k < 4; ++k) {
+        double dq = (Qx[0][k] - Qx[1][k]) + (Qy[2][k] - Qy[3][k]);
+        sk[k] = qmax[k] > 0.0 ? (0.5 * dq) / qmax[k] : 0.0;
+      }
+      a[c] = sqrt(0.25 * (((sk[0] * sk[0] + sk[1] * sk[1]) + sk[2] * sk[2]) + sk[3] * sk[3]));
+      double dil = 0.5 * ((u[0] - u[1]) + (v[2] - v[3]));
+      double vort = 0.5 * ((v[0] - v[1]) - (u[2] - u[3]));
+      th[c] = dil < 0.0 ? (dil * dil) / (dil * dil + vort * vort) : 0.0;
+    }
+  for (int y = 0; y < Ny; ++y)
+    for (int x = 0; x < Nx; ++x) {
+      if (!active(o, l, x, y)) continue;
+      size_t c = cidx(o, l, x, y);
+      double sum = 0.0;
+      int n = 0;
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          int xx = x + dx, yy = y + dy;
+          if (!wrap(o, l, &xx, &yy) || !active(o, l, xx, yy)) continue;
+          sum += a[cidx(o, l, xx, yy)];
+          ++n;
+        }
+      double z = (o->c_sensor * (sum / n)) * th[c];
+      z = z < 0.0 ? 0.0 : z > 1.0 ? 1.0 : z;
+      beta[c] = o->beta_max - (o->beta_max - o->beta_min) * z;
+    }
+  free(W);
+  free(a);
+  free(th);
+}
+
 static void advance_level(orc *o, int l, int kstep) {
   int Nx = o->Nx[l], Ny = o->Ny[l], r = o->r;
   double w2 = o->dx[l] * o->dx[l];
   double *F = o->F[l];
+  if (o->sensor) sensor_beta(o, l);
 
   /* Values leaving level l during this step are the post-collision values at
    * its start: book them into the parent's reflux accumulator (eq. 2d-reflux)
@@ -571,7 +685,8 @@ static void advance_level(orc *o, int l, int kstep) {
       if (!active(o, l, x, y)) continue;
       double g[16], fs[16];
       for (int i = 0; i < 16; ++i) g[i] = G[pidx(o, l, i, x, y)];
-      orc_collide(o->gamma, o->c, o->beta, o->eos, o->eos_a, o->eos_b, g, fs);
+      const double bx = o->sensor ? o->beta_f[l][cidx(o, l, x, y)] : o->beta;
+      orc_collide(o->gamma, o->c, bx, o->eos, o->eos_a, o->eos_b, g, fs);
       for (int i = 0; i < 16; ++i) G[pidx(o, l, i, x, y)] = fs[i];
     }
 

@@ -34,6 +34,11 @@ orc *orc_new(int nx0, int ny0, double dx0, int r, int nlev, double gamma, double
 void orc_free(orc *o);
 int orc_set_eos(orc *o, int eos, double a, double b);
 int orc_set_mutation(orc *o, int mut);
+/* Space/time-adaptive relaxation (eq. sensor-B): per-cell beta from the state
+ * at the start of each step; c_sensor, beta_min, beta_max as stated there. */
+int orc_set_sensor(orc *o, int on, double c_sensor, double beta_min, double beta_max);
+/* beta of every cell of `level` at its last step (Ny x Nx; 0 where inactive). */
+int orc_get_beta(const orc *o, int level, double *beta);
 int orc_set_boxes(orc *o, const int *boxes, int nboxes);
 int orc_regrid(orc *o, const int *boxes, int nboxes);
 int orc_set_state(orc *o, int level, int i0, int j0, int nx, int ny, const double *U, long ld);

@@ -600,3 +600,96 @@ def test_planted_sigma_sign_mistake_breaks_linear_handoff(axis):
     """A flipped tangential slope sign (eq. 2d-recon-tanslope) breaks the exact
     hand-off of a linear profile: the pin above catches it."""
     assert _linear_profile_run(axis, O.MUT_RECON_SIGMA_SIGN) > 1e-3
+
+
+# ----------------------------------------------------------- adaptive relaxation (Sec. 2.2, eq. sensor-B)
+def _sensor_case(U, bc=(1, 1, 1, 1), beta=0.9, c=6.0):
+    ny, nx = U.shape[1:]
+    return wl.Case("sensor", nx, ny, 1.0 / nx, 2, 1, 1.4, c, beta, bc, [], [U], 0)
+
+
+def _field(fn, n=24):
+    x = (np.arange(n) + 0.5) / n - 0.5
+    X, Y = np.meshgrid(x, x)
+    rho, u, v, p = fn(X, Y)
+    return wl.conserved(rho + 0 * X, u + 0 * X, v + 0 * X, p + 0 * X)
+
+
+def _beta_after_one_step(U, C=5.0, bmin=0.5, bmax=0.9, bc=(1, 1, 1, 1)):
+    o = exact.run_oracle(_sensor_case(U, bc, beta=bmax), steps=0)
+    o.set_sensor(True, C, bmin, bmax)
+    o.advance(1)
+    return o.get_beta(0)
+
+
+def test_sensor_uniform_and_rotation_keep_beta_max():
+    """No flux divergence (uniform state) or no dilatation (solid-body
+    rotation): the sensor leaves beta at beta_max (Ducros gate: a smooth
+    rotational structure is not taken for a shock)."""
+    b = _beta_after_one_step(_field(lambda X, Y: (1.0, 0.3, -0.2, 1.0)), bc=(0, 0, 0, 0))
+    assert np.all(b == 0.9)
+    b = _beta_after_one_step(_field(lambda X, Y: (1.0, -0.8 * Y, 0.8 * X, 5.0)))
+    assert np.all(np.abs(b - 0.9) < 1e-12)
+
+
+def test_sensor_gates_expansion_and_saturates_compression():
+    """Expansion (div u > 0): beta_max. Pure compression (u = -a x, no
+    vorticity): theta = 1, and a large C drives every cell to beta_min."""
+    b = _beta_after_one_step(_field(lambda X, Y: (1.0, 0.6 * X, 0.0, 2.0)))
+    assert np.all(b == 0.9)
+    b = _beta_after_one_step(_field(lambda X, Y: (1.0, -0.6 * X, 0.0, 2.0)), C=1e6)
+    assert np.all(b == 0.5)
+
+
+def test_sensor_with_equal_bounds_is_the_constant_beta_run():
+    """beta_min = beta_max: the adaptive path reproduces the constant-beta
+    run bit for bit, through three levels."""
+    n = 16
+    U = wl.random_state_U(n, n, seed=7)
+    case = wl.Case("t", n, n, 1.0 / n, 2, 3, 1.4, 4.0, 0.8, (0, 0, 1, 1),
+                   [(1, 8, 4, 16, 20), (2, 20, 12, 24, 20)],
+                   [U, wl.prolong_piecewise(U, 2), wl.prolong_piecewise(U, 4)], 0)
+    a = _run(case, 0)
+    b = _run(case, 0)
+    b.set_sensor(True, 3.0, 0.8, 0.8)
+    a.advance(6)
+    b.advance(6)
+    for l in range(3):
+        assert np.array_equal(a.get_pop(l), b.get_pop(l), equal_nan=True), l
+
+
+def test_sensor_conserves_exactly():
+    """Per-cell beta still conserves every cell's W: totals exact to round-off
+    across two refinement interfaces with the sensor active."""
+    n = 16
+    U = wl.random_state_U(n, n, seed=9)
+    case = wl.Case("t", n, n, 1.0 / n, 2, 3, 1.4, 4.0, 0.95, (0,) * 4,
+                   [(1, 8, 4, 16, 20), (2, 20, 12, 24, 20)],
+                   [U, wl.prolong_piecewise(U, 2) * 1.01, wl.prolong_piecewise(U, 4) * 0.99], 0)
+    o = _run(case, 0)
+    o.set_sensor(True, 20.0, 0.5, 0.95)
+    T0, _ = o.totals()
+    o.advance(10)
+    T1, _ = o.totals()
+    assert np.any(o.get_beta(0)[o.active_mask(0)] < 0.95)  # the sensor is doing something
+    scale = np.maximum(np.abs(T0), 1e-2 * np.abs(T0).max())
+    assert np.all(np.abs(T1 - T0) / scale < 1e-13), (T0, T1)
+
+
+def test_sensor_lowers_beta_at_the_sod_shock():
+    """Sod at t = 0.1 on 128 cells: the smallest beta sits at the shock of the
+    exact Riemann solution (compression), not at the contact or in the
+    rarefaction, where beta stays near beta_max."""
+    case = wl.sod_2d(refine=False)
+    o = exact.run_oracle(case, steps=0)
+    o.set_sensor(True, 10.0, 0.5, 0.95)
+    o.advance(100)
+    b = o.get_beta(0)[0]
+    t = 100 * case.dx0 / case.c
+    left, right = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+    xs = (np.arange(case.nx0) + 0.5) * case.dx0
+    rho_ex = exact.riemann_exact(left, right, (xs - 0.5) / t)[0]
+    shock = xs[np.nonzero(np.abs(np.diff(rho_ex)) > 1e-3)[0].max()]  # rightmost jump: the shock
+    assert abs(xs[np.argmin(b)] - shock) <= 3 * case.dx0, (xs[np.argmin(b)], shock)
+    assert b.min() < 0.7
+    assert np.all(b[xs < 0.5 - 1.3 * t] > 0.94)           # undisturbed left state
