@@ -72,7 +72,7 @@ def actual_updates_per_step(case):
     return case.actual_updates_per_coarse_step()
 
 
-def cpu_baseline(case, budget_s=15.0, boxes=None, mem_cap=8e9):
+def cpu_baseline(case, budget_s=15.0, boxes=None, mem_cap=8e9, sensor=None):
     """The oracle, single-threaded, on a bounded prefix of the same workload.
     A dynamic workload is sampled on the hierarchy the GPU run starts its timed
     region with (`boxes`), held fixed. The oracle keeps three dense arrays of
@@ -87,6 +87,8 @@ def cpu_baseline(case, budget_s=15.0, boxes=None, mem_cap=8e9):
         return {"value": None, "unit": "fine-equiv cell updates/s", "cores": 1, "kind": "oracle",
                 "sample": f"not run: the oracle's dense level arrays need {need / 1e9:.0f} GB"}
     o = exact.run_oracle(case, steps=0)
+    if sensor:
+        o.set_sensor(True, *sensor)
     t0 = time.perf_counter()
     n = 0
     while time.perf_counter() - t0 < budget_s and n < case.steps:
@@ -95,6 +97,8 @@ def cpu_baseline(case, budget_s=15.0, boxes=None, mem_cap=8e9):
     el = time.perf_counter() - t0
     fe = case.fine_equivalent_per_coarse_step() * n / el
     held = f", hierarchy of the GPU run's timed region ({len(boxes)} boxes) held fixed" if boxes else ""
+    if sensor:
+        held += f", adaptive beta (C, beta_min, beta_max) = {tuple(sensor)}"
     return {"value": fe, "unit": "fine-equiv cell updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{case.name} full size, first {n} coarse steps ({el:.1f} s){held}, FP64, "
                       f"one thread"}
@@ -186,6 +190,8 @@ def main():
     ap.add_argument("--rate", type=float, default=64.0)
     ap.add_argument("--serve-precision", default="fp32s", choices=["fp32", "fp32s", "fp64"])
     ap.add_argument("--serve-policy", default="share", choices=["share", "srpt", "fixed"])
+    ap.add_argument("--sensor", default=None, metavar="C,BMIN,BMAX",
+                    help="space/time-adaptive beta (eq. sensor-B) with these constants")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only measure a plain 2 GiB device copy and exit")
     args = ap.parse_args()
@@ -213,6 +219,10 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.Stream()  # a dedicated stream (default priority): graphs need one
     solver = vlbm.Solver.from_case(case, precision=prec, stream=stream)
+    sensor = None
+    if args.sensor:
+        sensor = [float(x) for x in args.sensor.split(",")]
+        solver.set_sensor(True, *sensor)
     T0, L0 = solver.totals()
 
     tuning = None
@@ -292,6 +302,8 @@ def main():
     esz = 8 if prec == vlbm.FP64 else 4
     bytes_per_update = 2 * 16 * esz
     nl = sum(v[1] for v in ktimes.values()) / prof_steps
+    if sensor:  # stages 1-3 before every step launch, stage 0 once per coarse step
+        nl = 4 * nl + 1
     # dominant kernel: the (level, launch form) with the largest kernel time;
     # algorithmic bytes of one launch: 16 populations read and 16 written per
     # active cell it advances (a fused launch keeps the finest level's
@@ -330,7 +342,9 @@ def main():
                                f"c={case.c:.4f}, seed 0",
                    "fine_equiv_per_step": fe_step, "actual_updates_per_step": upd,
                    "launches_per_step": nl, "tuning": tuning,
-                   "precision": args.precision},
+                   "precision": args.precision,
+                   "adaptive_beta": (dict(zip(("C", "beta_min", "beta_max"), sensor))
+                                     if sensor else None)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel_name, "level": dom[0], "bytes_per_launch": bytes_per_launch,
@@ -356,7 +370,7 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(build_case(args.workload, 10 ** 6), args.cpu_budget,
-                                           boxes=timed_boxes if dynamic else None)
+                                           boxes=timed_boxes if dynamic else None, sensor=sensor)
     print(json.dumps(out))
 
 

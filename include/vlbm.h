@@ -210,6 +210,35 @@ vlbm_status vlbm_set_tuning(vlbm_ctx *ctx, int tile_cells, int flags);
  * (either may be NULL). */
 vlbm_status vlbm_autotune(vlbm_ctx *ctx, int steps_per_trial, int *tile_cells, int *flags);
 
+/* Space/time-adaptive relaxation parameter (Sec. 2.2, eq. sensor-B). With
+ * on != 0 every step of every level first computes, per active cell and from
+ * the state at the step's start (W = sum_q f_q):
+ *   s_k   = dx (div Q)_k / max |Q_{alpha,k}|, by central differences, the max
+ *           over both directions and the active cells of every level, taken
+ *           once per coarse step from the state at its start, when the whole
+ *           hierarchy holds one time level (s_k = 0 where that max is 0);
+ *   sbar  = mean over the active cells of the 3x3 block of sqrt(mean_k s_k^2);
+ *   theta = dil^2 / (dil^2 + vort^2) where the velocity divergence dil < 0
+ *           (compression), else 0; vort = dv/dx - du/dy;
+ *   beta  = beta_max - (beta_max - beta_min) clip(c_sensor sbar theta, 0, 1),
+ * and relaxes the cell with that beta (vlbm_params.beta is then unused). A
+ * neighbour that is not an active cell of the level stands in as the cell
+ * itself in the differences and is left out of the mean. Arithmetic in FP64
+ * for every precision. Needs 0 < beta_min <= beta_max <= 1 and c_sensor >= 0
+ * (VLBM_EINVAL otherwise). While on, fused sub-steps (tuning flag 16) and two
+ * cells per thread (flag 2) are not used, and each level holds 6 more FP64
+ * planes of its frame (not counted by vlbm_footprint_bytes). on = 0 returns
+ * to the constant beta. Keeps the state and the time history. */
+vlbm_status vlbm_set_sensor(vlbm_ctx *ctx, int on, double c_sensor, double beta_min,
+                            double beta_max);
+
+/* beta[ny][ld] (host) of the active level-l cells in the rectangle, as used
+ * by the level's latest step with the adaptive relaxation on; other cells, and
+ * every cell while it is off, get NaN (0 before the level's first step with
+ * it). Synchronises. */
+vlbm_status vlbm_get_beta(vlbm_ctx *ctx, int level, int i0, int j0, int nx, int ny, double *beta,
+                          long ld);
+
 /* Per-kernel timing of the step launches of vlbm_advance. With enable != 0
  * every launch records its own start and end (events of the AMD launch
  * extension: no extra work on the stream) and the accumulators restart at

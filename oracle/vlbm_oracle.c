@@ -63,6 +63,7 @@ struct orc {
   int sensor;                        /* adaptive relaxation on (eq. sensor-B) */
   double c_sensor, beta_min, beta_max;
   double *beta_f[OMAXL];             /* per-cell beta of the level's last step */
+  double qmax[4];                    /* max |Q_{alpha,k}| of the current coarse step */
   int mut;
   int bc[4];
   double win[4][4];
@@ -516,18 +517,42 @@ static void ledger_add(orc *o, double w, const double v[4], double sign) {
   for (int k = 0; k < 4; ++k) kadd(&o->led[k], &o->ledc[k], sign * (w * v[k]));
 }
 
+/* Qmax_k = max over the active cells of every level and both directions of
+ * |Q_{alpha,k}(W)|, W = sum of the stored populations: the domain-wide
+ * normalisation of eq. sensor-B, taken at the start of a coarse step, the one
+ * instant at which the whole hierarchy holds one time level. */
+static void sensor_qmax(orc *o) {
+  for (int k = 0; k < 4; ++k) o->qmax[k] = 0.0;
+  for (int l = 0; l < o->nlev; ++l) {
+    const double *F = o->F[l];
+    for (int y = 0; y < o->Ny[l]; ++y)
+      for (int x = 0; x < o->Nx[l]; ++x) {
+        if (!active(o, l, x, y)) continue;
+        double Wc[4], Qx[4], Qy[4];
+        for (int k = 0; k < 4; ++k)
+          Wc[k] = ((F[pidx(o, l, 0 * 4 + k, x, y)] + F[pidx(o, l, 1 * 4 + k, x, y)]) +
+                   F[pidx(o, l, 2 * 4 + k, x, y)]) + F[pidx(o, l, 3 * 4 + k, x, y)];
+        orc_flux(o->gamma, o->eos, o->eos_a, o->eos_b, Wc, Qx, Qy);
+        for (int k = 0; k < 4; ++k) {
+          double m = fabs(Qx[k]) > fabs(Qy[k]) ? fabs(Qx[k]) : fabs(Qy[k]);
+          if (m > o->qmax[k]) o->qmax[k] = m;
+        }
+      }
+  }
+}
+
 /* Space/time-adaptive relaxation parameter (Sec. 2.2, eq. sensor-B) of every
  * active cell of level l, from the state at the start of its step
  * (W = sum of the stored populations; relaxation conserves it):
  *   s_k   = dx (div Q)_k / Qmax_k, with dx (div Q)_k by central differences,
  *           0.5 ((Qx_k(x+1) - Qx_k(x-1)) + (Qy_k(y+1) - Qy_k(y-1))), and
- *           Qmax_k = max over the level's active cells and both directions
- *           of |Q_{alpha,k}| (s_k = 0 where Qmax_k = 0);
+ *           Qmax_k of the coarse step (sensor_qmax; s_k = 0 where it is 0);
  *   a     = sqrt(0.25 (((s_0^2 + s_1^2) + s_2^2) + s_3^2))      (RMS over k);
  *   sbar  = mean of a over the active cells of the 3x3 block (box filter S);
  *   dil   = 0.5 ((u(x+1) - u(x-1)) + (v(y+1) - v(y-1))),
  *   vort  = 0.5 ((v(x+1) - v(x-1)) - (u(y+1) - u(y-1)))         (times dx);
- *   theta = dil^2 / (dil^2 + vort^2) where dil < 0 (compression), else 0;
+ *   theta = dil^2 / (dil^2 + vort^2) where dil < 0 (compression), else 0
+ *           (also 0 where dil^2 + vort^2 underflows to 0);
  *   beta  = beta_max - (beta_max - beta_min) clip(C sbar theta, 0, 1).
  * A neighbour that is not an active cell of the level (outside the domain on
  * a non-periodic side, coarser or finer) is replaced by the cell itself. */
@@ -539,21 +564,14 @@ static void sensor_beta(orc *o, int l) {
   double *W = (double *)malloc(sizeof(double) * 4 * nc);
   double *a = (double *)malloc(sizeof(double) * nc);
   double *th = (double *)malloc(sizeof(double) * nc);
-  double qmax[4] = {0.0, 0.0, 0.0, 0.0};
+  const double *qmax = o->qmax;
   for (int y = 0; y < Ny; ++y)
     for (int x = 0; x < Nx; ++x) {
       if (!active(o, l, x, y)) continue;
       size_t c = cidx(o, l, x, y);
-      double Wc[4], Qx[4], Qy[4];
       for (int k = 0; k < 4; ++k)
-        Wc[k] = ((F[pidx(o, l, 0 * 4 + k, x, y)] + F[pidx(o, l, 1 * 4 + k, x, y)]) +
-                 F[pidx(o, l, 2 * 4 + k, x, y)]) + F[pidx(o, l, 3 * 4 + k, x, y)];
-      orc_flux(o->gamma, o->eos, o->eos_a, o->eos_b, Wc, Qx, Qy);
-      for (int k = 0; k < 4; ++k) {
-        W[4 * c + k] = Wc[k];
-        double m = fabs(Qx[k]) > fabs(Qy[k]) ? fabs(Qx[k]) : fabs(Qy[k]);
-        if (m > qmax[k]) qmax[k] = m;
-      }
+        W[4 * c + k] = ((F[pidx(o, l, 0 * 4 + k, x, y)] + F[pidx(o, l, 1 * 4 + k, x, y)]) +
+                        F[pidx(o, l, 2 * 4 + k, x, y)]) + F[pidx(o, l, 3 * 4 + k, x, y)];
     }
   for (int y = 0; y < Ny; ++y)
     for (int x = 0; x < Nx; ++x) {
@@ -579,7 +597,8 @@ static void sensor_beta(orc *o, int l) {
       a[c] = sqrt(0.25 * (((sk[0] * sk[0] + sk[1] * sk[1]) + sk[2] * sk[2]) + sk[3] * sk[3]));
       double dil = 0.5 * ((u[0] - u[1]) + (v[2] - v[3]));
       double vort = 0.5 * ((v[0] - v[1]) - (u[2] - u[3]));
-      th[c] = dil < 0.0 ? (dil * dil) / (dil * dil + vort * vort) : 0.0;
+      const double den = dil * dil + vort * vort;
+      th[c] = (dil < 0.0 && den > 0.0) ? (dil * dil) / den : 0.0;
     }
   for (int y = 0; y < Ny; ++y)
     for (int x = 0; x < Nx; ++x) {
@@ -728,7 +747,10 @@ static void level_cycle(orc *o, int l, int kstep) {
 }
 
 int orc_advance(orc *o, int ncoarse) {
-  for (int n = 0; n < ncoarse; ++n) level_cycle(o, 0, 1);
+  for (int n = 0; n < ncoarse; ++n) {
+    if (o->sensor) sensor_qmax(o);
+    level_cycle(o, 0, 1);
+  }
   return 0;
 }
 

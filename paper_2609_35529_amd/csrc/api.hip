@@ -218,6 +218,10 @@ struct Level {
   int nledger = 0;
   double *dpartial = nullptr;
   long steps = 0;  // buffer flips so far; its parity selects the current buffer
+  // adaptive relaxation planes (SensorPlane, SEN_PLANES x sen_plane doubles),
+  // allocated while the sensor is on
+  double *dsen = nullptr;
+  int64_t sen_plane = 0;
   std::vector<int64_t> reflux_key;  // per reflux slot: (y * Nx + x) * 4 + q of its ring cell
 
   int64_t off(int x, int y) const {
@@ -242,6 +246,7 @@ struct LaunchRec {
   int32_t fused_kernel = 0;  // launched as the fused kernel
   int32_t prof_key = 0;      // 2 * level + fused, for per-kernel timing
   double cells = 0.0;        // active cells the launch advances
+  int32_t sensor_max = 0;    // adaptive relaxation stage 0 over every level (no step)
 };
 }  // namespace
 
@@ -261,6 +266,10 @@ struct vlbm_ctx {
   int *dflag = nullptr;
   double gm1 = 0, h = 0, tb = 0;
   EosT<double> eos{};
+  // space/time-adaptive relaxation parameter (eq. sensor-B)
+  bool sensor = false;
+  double c_sensor = 1.0, beta_min = 1.0, beta_max = 1.0;
+  unsigned long long *dqmax = nullptr;  // [2][4]: max |Q| per coarse-step parity, as bits
   double ledger_carry[4] = {0, 0, 0, 0}, ledger_carry_c[4] = {0, 0, 0, 0};
   // schedule tables: phases of one coarse step and their descriptors for the
   // two parities of the coarse step counter relative to table_base
@@ -328,6 +337,7 @@ void free_level(vlbm_ctx *c, Level &L) {
   c->mem.release(L.dacc);
   c->mem.release(L.dledger);
   c->mem.release(L.dpartial);
+  c->mem.release(L.dsen);
   long steps = L.steps;
   L = Level();
   L.steps = steps;
@@ -1034,8 +1044,43 @@ void schedule(int l, int k, int nlev, int r, std::vector<std::pair<int, int>> &o
 }
 
 // Whether the finest level runs fused two-sub-step launches.
+// Whether the finest level runs fused two-sub-step launches (never with the
+// adaptive relaxation, whose second sub-step needs a level-wide maximum of the
+// intermediate time level).
 bool fused_active(const vlbm_ctx *c) {
-  return (c->step_flags & STEP_FUSE2) && c->nlev >= 2 && !c->lv[c->nlev - 1].ftiles.empty();
+  return (c->step_flags & STEP_FUSE2) && !c->sensor && c->nlev >= 2 &&
+         !c->lv[c->nlev - 1].ftiles.empty();
+}
+
+// Allocate (sensor on) or release (off) the adaptive relaxation planes of
+// every present level; new planes start at zero. Both max |Q| slots restart
+// at zero (stage 0 of a coarse step accumulates into its parity's slot and
+// clears the other one, so every slot is zero when its coarse step begins).
+vlbm_status ensure_sensor(vlbm_ctx *c) {
+  for (int l = 0; l < kMaxLevels; ++l) {
+    Level &L = c->lv[l];
+    const bool want = c->sensor && L.present && l < c->nlev;
+    if (L.dsen && (!want || L.sen_plane != L.plane)) {
+      c->mem.release(L.dsen);
+      L.dsen = nullptr;
+      L.sen_plane = 0;
+    }
+    if (!want || L.dsen) continue;
+    const size_t nb = sizeof(double) * SEN_PLANES * (size_t)L.plane;
+    L.dsen = static_cast<double *>(c->mem.alloc(nb));
+    if (!L.dsen) return fail(VLBM_ENOMEM, "adaptive relaxation planes (%zu bytes)", nb);
+    L.sen_plane = L.plane;
+    HIPCHK(hipMemsetAsync(L.dsen, 0, nb, c->stream));
+  }
+  if (!c->sensor) {
+    c->mem.release(c->dqmax);
+    c->dqmax = nullptr;
+    return VLBM_OK;
+  }
+  if (!c->dqmax) c->dqmax = static_cast<unsigned long long *>(c->mem.alloc(8 * sizeof(unsigned long long)));
+  if (!c->dqmax) return fail(VLBM_ENOMEM, "adaptive relaxation maxima");
+  HIPCHK(hipMemsetAsync(c->dqmax, 0, 8 * sizeof(unsigned long long), c->stream));
+  return VLBM_OK;
 }
 
 
@@ -1071,6 +1116,21 @@ LevelDesc make_desc(const vlbm_ctx *c, int l, const long *st, bool fused = false
   a.eos_ga = c->eos.ga;
   for (int s2 = 0; s2 < 4; ++s2)
     for (int k = 0; k < 4; ++k) a.win[s2][k] = c->p.w_inflow[s2][k];
+  if (c->sensor && !fused) {
+    a.sen = L.dsen;  // qmax and qmax_other: per table parity (build_tables)
+    a.status = L.dstatus;
+    a.fx0 = L.fx0;
+    a.fy0 = L.fy0;
+    a.fw = L.fw;
+    a.fh = L.fh;
+    a.xoff = L.xoff;
+    a.Nx = L.Nx;
+    a.Ny = L.Ny;
+    a.per = (c->perx() ? 1 : 0) | (c->pery() ? 2 : 0);
+    a.c_sensor = c->c_sensor;
+    a.beta_min = c->beta_min;
+    a.beta_max = c->beta_max;
+  }
   return a;
 }
 
@@ -1094,6 +1154,8 @@ long tile_cells_sum(const Level &L, bool fused, size_t t0, size_t t1) {
 // per phase, each a run of segments of the segment table.
 vlbm_status build_tables(vlbm_ctx *c) {
   drop_graph(c);
+  vlbm_status sst = ensure_sensor(c);
+  if (sst) return sst;
   c->phases.clear();
   schedule(0, 1, c->nlev, c->p.r, c->phases, fused_active(c));
   const size_t P = c->phases.size();
@@ -1113,6 +1175,10 @@ vlbm_status build_tables(vlbm_ctx *c) {
       const int l = c->phases[p].first, k = c->phases[p].second;
       const bool fused = k == 0;
       descs[e * P + p] = make_desc(c, l, st, fused);
+      if (descs[e * P + p].sen) {
+        descs[e * P + p].qmax = c->dqmax + 4 * e;
+        descs[e * P + p].qmax_other = c->dqmax + 4 * (e ^ 1);
+      }
       const int nb = nb8(fused ? c->lv[l].ftiles.size() : c->lv[l].tiles.size());
       c->phase_blocks[p] = nb;
       if (e == 0) {
@@ -1131,6 +1197,22 @@ vlbm_status build_tables(vlbm_ctx *c) {
       }
       st[l] += 1;
     }
+  }
+  if (c->sensor) {
+    // stage 0: one segment per level, the descriptor of the level's first
+    // phase (its buffers as at the coarse step's start); launched first
+    LaunchRec a{};
+    a.seg0 = (int)seg_desc.size();
+    a.sensor_max = 1;
+    for (int l = 0; l < c->nlev; ++l) {
+      size_t p0 = 0;
+      while (p0 < P && c->phases[p0].first != l) ++p0;
+      if (p0 == P || c->phases[p0].second == 0) return fail(VLBM_EINVAL, "internal: sensor schedule");
+      seg_desc.push_back({(int)p0, nb8(c->lv[l].tiles.size())});
+      seg_desc1.push_back((int)(P + p0));
+      a.nseg += 1;
+    }
+    c->launches.insert(c->launches.begin(), a);
   }
   const size_t NS = seg_desc.size();
   if (seg_desc1.size() != NS) return fail(VLBM_EINVAL, "internal: launch tables differ between parities");
@@ -1194,9 +1276,17 @@ vlbm_status launch_coarse_step(vlbm_ctx *c, int e) {
       a.nseg = r.nseg;
     }
     a.nblocks = r.nblocks;
+    if (r.sensor_max) {
+      HIPCHK(launch_sensor(a, 0, c->fp32, c->stream));
+      continue;
+    }
     a.first = r.first;
     a.flags = c->step_flags | (r.fused_kernel ? STEP_FUSED_PHASE : 0);
     a.ak = r.ak;
+    if (c->sensor && !r.fused_kernel) {  // per-cell beta from the state at the start of the step
+      for (int stage = 1; stage <= 3; ++stage) HIPCHK(launch_sensor(a, stage, c->fp32, c->stream));
+      a.flags |= STEP_SENSOR;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->prof) {
       if (c->pend.size() >= 4096) {
@@ -1887,6 +1977,7 @@ void vlbm_destroy(vlbm_ctx *c) {
   c->mem.release(c->ddesc);
   c->mem.release(c->dseg);
   c->mem.release(c->dflag);
+  c->mem.release(c->dqmax);
   c->mem.release_all();
   delete c;
 }
@@ -2220,6 +2311,8 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
       return fail(VLBM_EINVAL, "batched contexts must share stream, precision and ratio");
     if (fused_active(c))
       return fail(VLBM_EINVAL, "context %d uses fused sub-steps, which batched launches do not take", i);
+    if (c->sensor != c0->sensor)
+      return fail(VLBM_EINVAL, "batched contexts must all use the adaptive relaxation, or none");
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == c) return fail(VLBM_EINVAL, "context %d listed twice", i);
   }
@@ -2277,11 +2370,43 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
         nseg[e * P + p] = (int32_t)segs.size() - seg0[e * P + p];
         nblk[e * P + p] = fb;
       }
+    // adaptive relaxation stage 0 of every context, one launch per coarse step
+    int32_t s0seg[2] = {0, 0}, s0n[2] = {0, 0}, s0blk[2] = {0, 0};
+    if (c0->sensor)
+      for (int e = 0; e < 2; ++e) {
+        s0seg[e] = (int32_t)segs.size();
+        int32_t fb = 0;
+        for (size_t a = 0; a < act.size(); ++a) {
+          vlbm_ctx *c = ctxs[act[a]];
+          const LaunchRec &R = c->launches.front();
+          if (!R.sensor_max) return fail(VLBM_EINVAL, "internal: sensor launch table");
+          const int ei = table_parity(c) ^ e;
+          for (int i = R.seg0; i < R.seg0 + R.nseg; ++i) {
+            const Segment &S = c->hseg[ei * c->nseg_table + i];
+            if (S.nblocks == 0) continue;
+            segs.push_back({S.d, fb, S.nblocks});
+            fb += S.nblocks;
+          }
+        }
+        s0n[e] = (int32_t)segs.size() - s0seg[e];
+        s0blk[e] = fb;
+      }
     Segment *dseg = static_cast<Segment *>(c0->mem.alloc(sizeof(Segment) * std::max<size_t>(1, segs.size())));
     if (!dseg) return fail(VLBM_ENOMEM, "batch segment table");
     HIPCHK(hipMemcpyAsync(dseg, segs.data(), sizeof(Segment) * segs.size(), hipMemcpyHostToDevice, c0->stream));
     for (long s2 = 0; s2 < m; ++s2) {
       const int e = (int)(s2 & 1);
+      if (c0->sensor && s0n[e] > 0) {
+        StepLaunch L{};
+        L.segs = dseg + s0seg[e];
+        L.nseg = s0n[e];
+        L.nblocks = s0blk[e];
+        hipError_t err = launch_sensor(L, 0, c0->fp32, c0->stream);
+        if (err != hipSuccess) {
+          c0->mem.release(dseg);
+          return fail(VLBM_EDEVICE, "batched launch: %s", hipGetErrorString(err));
+        }
+      }
       for (size_t p = 0; p < P; ++p) {
         if (nseg[e * P + p] == 0) continue;
         StepLaunch L{};
@@ -2291,7 +2416,13 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
         L.first = ph[p].second == 1;
         L.flags = c0->step_flags;
         L.ak = ak_of(ph[p].second, r);
-        hipError_t err = launch_step(L, c0->fp32, c0->stream);
+        hipError_t err = hipSuccess;
+        if (c0->sensor) {
+          for (int stage = 1; stage <= 3 && err == hipSuccess; ++stage)
+            err = launch_sensor(L, stage, c0->fp32, c0->stream);
+          L.flags |= STEP_SENSOR;
+        }
+        if (err == hipSuccess) err = launch_step(L, c0->fp32, c0->stream);
         if (err != hipSuccess) {
           c0->mem.release(dseg);
           return fail(VLBM_EDEVICE, "batched launch: %s", hipGetErrorString(err));
@@ -2326,7 +2457,8 @@ static std::map<std::string, std::pair<int, int>> g_tuned;
 
 static std::string tuning_key(const vlbm_ctx *c) {
   std::string k = std::to_string(c->p.nx0) + "x" + std::to_string(c->p.ny0) + "r" +
-                  std::to_string(c->p.r) + "p" + std::to_string(c->p.precision);
+                  std::to_string(c->p.r) + "p" + std::to_string(c->p.precision) +
+                  (c->sensor ? "s" : "");
   for (const vlbm_box &b : c->boxes)
     k += ":" + std::to_string(b.level) + "," + std::to_string(b.i0) + "," + std::to_string(b.j0) +
          "," + std::to_string(b.nx) + "," + std::to_string(b.ny);
@@ -2341,7 +2473,7 @@ vlbm_status vlbm_autotune(vlbm_ctx *c, int steps_per_trial, int *tile_cells, int
   vlbm_status st;
   if (hit == g_tuned.end()) {
     const int tiles[] = {128, 256, 512, 1024};
-    const bool can_fuse = c->p.r == 2 && c->nlev >= 2;
+    const bool can_fuse = c->p.r == 2 && c->nlev >= 2 && !c->sensor;
     // workgroup order x store kind (x fused sub-steps where they apply)
     std::vector<int> orders;
     for (int fuse : {0, (int)STEP_FUSE2})
@@ -2384,6 +2516,45 @@ vlbm_status vlbm_autotune(vlbm_ctx *c, int steps_per_trial, int *tile_cells, int
   if (st) return st;
   if (tile_cells) *tile_cells = c->tile_cells;
   if (flags) *flags = c->step_flags & ~STEP_F64_MATH;
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_set_sensor(vlbm_ctx *c, int on, double c_sensor, double beta_min, double beta_max) {
+  if (!c) return fail(VLBM_EINVAL, "null context");
+  if (on && !(beta_min > 0.0 && beta_min <= beta_max && beta_max <= 1.0 && c_sensor >= 0.0))
+    return fail(VLBM_EINVAL, "adaptive relaxation needs 0 < beta_min <= beta_max <= 1 and C >= 0");
+  c->sensor = on != 0;
+  if (c->sensor) {
+    c->c_sensor = c_sensor;
+    c->beta_min = beta_min;
+    c->beta_max = beta_max;
+  }
+  if (!c->have_hierarchy) return VLBM_OK;
+  // same buffers and time history; descriptors, planes and fusion follow the setting
+  return build_tables(c);
+}
+
+vlbm_status vlbm_get_beta(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny, double *beta,
+                          long ld) {
+  if (!beta) return fail(VLBM_EINVAL, "null beta");
+  vlbm_status st = check_rect(c, level, i0, j0, nx, ny);
+  if (st) return st;
+  if (ld < nx) return fail(VLBM_EINVAL, "ld < nx");
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) beta[(size_t)y * ld + x] = NAN;
+  const Level &L = c->lv[level];
+  if (!L.present || !L.dsen) return VLBM_OK;
+  int ci0 = i0, cj0 = j0, cnx = nx, cny = ny, ox = 0, oy = 0;
+  if (!clip_to_frame(L, ci0, cj0, cnx, cny, ox, oy)) return VLBM_OK;
+  std::vector<double> rows((size_t)cnx * cny);
+  HIPCHK(hipMemcpy2DAsync(rows.data(), sizeof(double) * cnx, L.dsen + SEN_BETA * L.plane + L.off(ci0, cj0),
+                          sizeof(double) * L.pitch, sizeof(double) * cnx, cny, hipMemcpyDeviceToHost,
+                          c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int y = 0; y < cny; ++y)
+    for (int x = 0; x < cnx; ++x)
+      if (L.status[L.fidx(ci0 + x, cj0 + y)] == 1)
+        beta[(size_t)(y + oy) * ld + x + ox] = rows[(size_t)y * cnx + x];
   return VLBM_OK;
 }
 

@@ -225,7 +225,7 @@ __device__ __forceinline__ void put(S *__restrict__ d0, int64_t P, int64_t o, co
 
 // One workgroup's work on tile `lb` of descriptor A (inlined twice below, so
 // that A is either plain kernel-argument memory or plain global memory).
-template <class T, class C, bool NT, bool TWO>
+template <class T, class C, bool NT, bool TWO, bool SEN>
 __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks, int first,
                                          double ak, int flags) {
   // Tile order. Natural order keeps every workgroup of the chip inside one
@@ -243,13 +243,15 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
   const int pitch = A.pitch;
   const EosT<C> eos = eos_of<C>(A);
   const C h = (C)A.h, tb = (C)A.tb;
+  // per-cell 2 beta from the adaptive relaxation planes (eq. sensor-B)
+  const auto bet = (__attribute__((address_space(1))) const double *)(SEN ? A.sen + SEN_BETA * plane : nullptr);
   if (tl.ntask) {
     for (int i = threadIdx.x; i < tl.ntask; i += blockDim.x)
       run_task<T>(A, first, ak, A.tasks[tl.task0 + i]);
     __syncthreads();
   }
   const int n = tl.w * tl.h;
-  if (TWO) {
+  if (TWO && !SEN) {
     // two cells per thread, both gathers issued before either relaxation
     for (int c = threadIdx.x; c < n; c += 2 * blockDim.x) {
       const int c2 = c + blockDim.x;
@@ -277,30 +279,37 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
       const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
       C g[16];
       pull<T, C>(s, plane, pitch, o, g);
-      relax<C>(g, eos, h, tb);
+      relax<C>(g, eos, h, SEN ? (C)(2.0 * bet[o]) : tb);
       put<T, C, NT>(d, plane, o, g);
     }
   }
 }
 
+// DP_, FB_, NB_ := the descriptor of workgroup b of launch Lc, its
+// segment's first workgroup and workgroup count (uniform scalar binary search
+// of the segment table). A macro, not a function: through a call the compiler
+// loses the descriptor's address space and reads it with vector loads.
+#define VLBM_FIND_SEGMENT(LC_, B_, DP_, FB_, NB_)                          \
+  const LevelDesc *DP_ = (LC_).d0;                                         \
+  int FB_ = 0, NB_ = (LC_).nblocks;                                        \
+  if ((LC_).nseg > 0) {                                                    \
+    int lo_ = 0, hi_ = (LC_).nseg - 1;                                     \
+    while (lo_ < hi_) {                                                    \
+      const int mid_ = (lo_ + hi_ + 1) >> 1;                               \
+      if ((LC_).segs[mid_].first_block <= (B_)) lo_ = mid_; else hi_ = mid_ - 1; \
+    }                                                                      \
+    const Segment sg_ = (LC_).segs[lo_];                                   \
+    DP_ = sg_.d;                                                           \
+    FB_ = sg_.first_block;                                                 \
+    NB_ = sg_.nblocks;                                                     \
+  }
 
-template <class T, class C, bool NT, bool TWO>
+
+template <class T, class C, bool NT, bool TWO, bool SEN>
 __global__ __launch_bounds__(256) void step_kernel(StepLaunch Lc) {
   const int b = blockIdx.x;
-  const LevelDesc *dp = Lc.d0;
-  int first_block = 0, nblocks = Lc.nblocks;
-  if (Lc.nseg > 0) {  // uniform scalar search of this workgroup's segment
-    int lo = 0, hi = Lc.nseg - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (Lc.segs[mid].first_block <= b) lo = mid; else hi = mid - 1;
-    }
-    const Segment sg = Lc.segs[lo];
-    dp = sg.d;
-    first_block = sg.first_block;
-    nblocks = sg.nblocks;
-  }
-  run_tile<T, C, NT, TWO>(*dp, b - first_block, nblocks, Lc.first, Lc.ak, Lc.flags);
+  VLBM_FIND_SEGMENT(Lc, b, dp, first_block, nblocks)
+  run_tile<T, C, NT, TWO, SEN>(*dp, b - first_block, nblocks, Lc.first, Lc.ak, Lc.flags);
 }
 
 // ---------------------------------------------------------------------------
@@ -474,19 +483,7 @@ __device__ __forceinline__ void fused_tile(const LevelDesc &A, int lb, int nbloc
 template <class T, class C, bool NT>
 __global__ __launch_bounds__(FUSE_THREADS) void fused_kernel(StepLaunch Lc) {
   const int b = blockIdx.x;
-  const LevelDesc *dp = Lc.d0;
-  int first_block = 0, nblocks = Lc.nblocks;
-  if (Lc.nseg > 0) {
-    int lo = 0, hi = Lc.nseg - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (Lc.segs[mid].first_block <= b) lo = mid; else hi = mid - 1;
-    }
-    const Segment sg = Lc.segs[lo];
-    dp = sg.d;
-    first_block = sg.first_block;
-    nblocks = sg.nblocks;
-  }
+  VLBM_FIND_SEGMENT(Lc, b, dp, first_block, nblocks)
   fused_tile<T, C, NT>(*dp, b - first_block, nblocks, Lc.flags);
 }
 
@@ -512,16 +509,21 @@ hipError_t launch_step(const StepLaunch &a, int fp32, hipStream_t s, hipEvent_t 
 #undef VLBM_FUSED
     return hipGetLastError();
   }
-#define VLBM_STEP(S, C)                                                                          \
-  do {                                                                                           \
-    if (nt && two)                                                                               \
-      hipExtLaunchKernelGGL((step_kernel<S, C, true, true>), grid, block, 0, s, ev0, ev1, 0, a);   \
-    else if (nt)                                                                                 \
-      hipExtLaunchKernelGGL((step_kernel<S, C, true, false>), grid, block, 0, s, ev0, ev1, 0, a);  \
-    else if (two)                                                                                \
-      hipExtLaunchKernelGGL((step_kernel<S, C, false, true>), grid, block, 0, s, ev0, ev1, 0, a);  \
-    else                                                                                         \
-      hipExtLaunchKernelGGL((step_kernel<S, C, false, false>), grid, block, 0, s, ev0, ev1, 0, a); \
+  const bool sen = (a.flags & STEP_SENSOR) != 0;  // per-cell beta: one cell per thread
+#define VLBM_STEP(S, C)                                                                                 \
+  do {                                                                                                  \
+    if (sen && nt)                                                                                      \
+      hipExtLaunchKernelGGL((step_kernel<S, C, true, false, true>), grid, block, 0, s, ev0, ev1, 0, a);   \
+    else if (sen)                                                                                       \
+      hipExtLaunchKernelGGL((step_kernel<S, C, false, false, true>), grid, block, 0, s, ev0, ev1, 0, a);  \
+    else if (nt && two)                                                                                 \
+      hipExtLaunchKernelGGL((step_kernel<S, C, true, true, false>), grid, block, 0, s, ev0, ev1, 0, a);   \
+    else if (nt)                                                                                        \
+      hipExtLaunchKernelGGL((step_kernel<S, C, true, false, false>), grid, block, 0, s, ev0, ev1, 0, a);  \
+    else if (two)                                                                                       \
+      hipExtLaunchKernelGGL((step_kernel<S, C, false, true, false>), grid, block, 0, s, ev0, ev1, 0, a);  \
+    else                                                                                                \
+      hipExtLaunchKernelGGL((step_kernel<S, C, false, false, false>), grid, block, 0, s, ev0, ev1, 0, a); \
   } while (0)
   if (!fp32)
     VLBM_STEP(double, double);
@@ -530,6 +532,261 @@ hipError_t launch_step(const StepLaunch &a, int fp32, hipStream_t s, hipEvent_t 
   else
     VLBM_STEP(float, float);
 #undef VLBM_STEP
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Space/time-adaptive relaxation parameter (Sec. 2.2, eq. sensor-B) of every
+// active cell of a level, from the state at the start of its step, in FP64
+// for every storage type. Once per coarse step, over the step tiles of every
+// level at the coarse step's start (the one instant the whole hierarchy holds
+// one time level):
+//   0. Qmax_k = max over all active cells and both directions of |Q_{alpha,k}(W)|,
+//      W_k = ((f_0k + f_1k) + f_2k) + f_3k of the stored populations
+//      (non-negative doubles order like their bit patterns, so an unsigned
+//      64-bit atomic max keeps it exactly); the slot of the other coarse-step
+//      parity, read by the previous coarse step, is cleared for the next one.
+// Then before every step of a level, three launches over the step's own tiles:
+//   1. W_k into the W planes;
+//   2. s_k = (0.5 ((Qx_k(x+1) - Qx_k(x-1)) + (Qy_k(y+1) - Qy_k(y-1)))) / Qmax_k
+//      (0 where Qmax_k = 0), a = sqrt(0.25 (((s_0^2 + s_1^2) + s_2^2) + s_3^2));
+//      dil = 0.5 ((u(x+1) - u(x-1)) + (v(y+1) - v(y-1))),
+//      vort = 0.5 ((v(x+1) - v(x-1)) - (u(y+1) - u(y-1))),
+//      theta = dil^2 / (dil^2 + vort^2) under compression (dil < 0), else 0
+//      (0 too where dil^2 + vort^2 underflows to 0);
+//   3. beta = beta_max - (beta_max - beta_min) clip(C sbar theta, 0, 1), with
+//      sbar the mean of a over the active cells of the 3 x 3 block (summed row
+//      by row from (x - 1, y - 1)); beta overwrites theta in place (a cell reads
+//      only its own theta).
+// A neighbour that is not an active cell of the level (across a non-periodic
+// side, outside the frame, a hole, uncovered) stands in as the cell itself in
+// stage 2 and is left out of the mean of stage 3.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void euler_flux(const EosT<double> &eos, const double W[4], double Qx[4],
+                                           double Qy[4]) {
+  const double rho = W[0], mx = W[1], my = W[2], E = W[3];
+  const double u = mx / rho;
+  const double v = my / rho;
+  const double eint = E - 0.5 * (mx * u + my * v);
+  const double p = pressure<double>(eos, rho, eint);
+  Qx[0] = mx;
+  Qx[1] = mx * u + p;
+  Qx[2] = my * u;
+  Qx[3] = (E + p) * u;
+  Qy[0] = my;
+  Qy[1] = mx * v;
+  Qy[2] = my * v + p;
+  Qy[3] = (E + p) * v;
+}
+
+// Element offset of level cell (x + dx, y + dy), |dx|, |dy| <= 1, periodic
+// sides wrapped, or -1 when that is not an active cell of the level.
+__device__ __forceinline__ int64_t sensor_nb(const LevelDesc &A, int x, int y, int dx, int dy) {
+  int xx = x + dx, yy = y + dy;
+  if (xx < 0 || xx >= A.Nx) {
+    if (!(A.per & 1)) return -1;
+    xx = xx < 0 ? xx + A.Nx : xx - A.Nx;
+  }
+  if (yy < 0 || yy >= A.Ny) {
+    if (!(A.per & 2)) return -1;
+    yy = yy < 0 ? yy + A.Ny : yy - A.Ny;
+  }
+  const int fx = xx - A.fx0, fy = yy - A.fy0;
+  if (fx < 0 || fy < 0 || fx >= A.fw || fy >= A.fh) return -1;
+  const auto st = (__attribute__((address_space(1))) const uint8_t *)A.status;
+  if (st[(int64_t)fy * A.fw + fx] != 1) return -1;
+  return (int64_t)fy * A.pitch + fx + A.xoff;
+}
+
+// Level coordinates of a tile's first cell.
+__device__ __forceinline__ void tile_origin(const LevelDesc &A, const Tile &tl, int &x0, int &y0) {
+  const int rel = tl.off0 - A.xoff;
+  const int fy = rel / A.pitch;
+  x0 = A.fx0 + (rel - fy * A.pitch);
+  y0 = A.fy0 + fy;
+}
+
+// W of a cell from its stored populations (FP64 sums in the fixed order).
+template <class T>
+__device__ __forceinline__ void stored_W(const T *s0, int64_t P, int64_t o, double w[4]) {
+  const auto s = (__attribute__((address_space(1))) const T *)s0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    w[k] = (((double)s[(0 * 4 + k) * P + o] + (double)s[(1 * 4 + k) * P + o]) +
+            (double)s[(2 * 4 + k) * P + o]) + (double)s[(3 * 4 + k) * P + o];
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void sensor0_kernel(StepLaunch Lc) {
+  VLBM_FIND_SEGMENT(Lc, (int)blockIdx.x, dp, fb, nb)
+  (void)nb;
+  const LevelDesc &A = *dp;
+  const int tid = blockIdx.x - fb;
+  if (tid == 0 && threadIdx.x < 4) A.qmax_other[threadIdx.x] = 0ull;
+  if (tid >= A.ntiles || !A.sen) return;  // uniform over the workgroup
+  const Tile tl = A.tiles[tid];
+  const int64_t P = A.plane;
+  const int pitch = A.pitch;
+  const EosT<double> eos = eos_of<double>(A);
+  double m[4] = {0.0, 0.0, 0.0, 0.0};
+  const int n = tl.w * tl.h;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    const int cy = c / tl.w, cx = c - cy * tl.w;
+    const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
+    double w[4], qx[4], qy[4];
+    stored_W<T>(static_cast<const T *>(A.src), P, o, w);
+    euler_flux(eos, w, qx, qy);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) m[k] = fmax(m[k], fmax(fabs(qx[k]), fabs(qy[k])));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) m[k] = fmax(m[k], __shfl_xor(m[k], off));
+  __shared__ double red[4][4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) red[k][wv] = m[k];
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int k = threadIdx.x;
+    double v = red[k][0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) v = fmax(v, red[k][i]);
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+    unsigned long long *q = A.qmax + k;
+    // the running maximum only grows: a stale read can only let an update through
+    if (bits > __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(q, bits);
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void sensor1_kernel(StepLaunch Lc) {
+  VLBM_FIND_SEGMENT(Lc, (int)blockIdx.x, dp, fb, nb)
+  (void)nb;
+  const LevelDesc &A = *dp;
+  const int tid = blockIdx.x - fb;
+  if (tid >= A.ntiles || !A.sen) return;
+  const Tile tl = A.tiles[tid];
+  const auto Wp = (gptr<double>)A.sen;
+  const int64_t P = A.plane;
+  const int pitch = A.pitch;
+  const int n = tl.w * tl.h;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    const int cy = c / tl.w, cx = c - cy * tl.w;
+    const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
+    double w[4];
+    stored_W<T>(static_cast<const T *>(A.src), P, o, w);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Wp[(SEN_W + k) * P + o] = w[k];
+  }
+}
+
+__global__ __launch_bounds__(256) void sensor2_kernel(StepLaunch Lc) {
+  VLBM_FIND_SEGMENT(Lc, (int)blockIdx.x, dp, fb, nb)
+  (void)nb;
+  const LevelDesc &A = *dp;
+  const int tid = blockIdx.x - fb;
+  if (tid >= A.ntiles || !A.sen) return;
+  const Tile tl = A.tiles[tid];
+  const auto Sp = (gptr<double>)A.sen;
+  const int64_t P = A.plane;
+  const int pitch = A.pitch;
+  const EosT<double> eos = eos_of<double>(A);
+  double qm[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) qm[k] = __longlong_as_double((long long)A.qmax[k]);
+  int x0, y0;
+  tile_origin(A, tl, x0, y0);
+  const int n = tl.w * tl.h;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    const int cy = c / tl.w, cx = c - cy * tl.w;
+    const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
+    const int x = x0 + cx, y = y0 + cy;
+    int64_t nbo[4] = {sensor_nb(A, x, y, 1, 0), sensor_nb(A, x, y, -1, 0), sensor_nb(A, x, y, 0, 1),
+                      sensor_nb(A, x, y, 0, -1)};
+    double Qd[4][4], u[4], v[4];  // Qd: Qx of the x neighbours, Qy of the y neighbours
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const int64_t e = nbo[d] < 0 ? o : nbo[d];
+      double w[4], qx[4], qy[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) w[k] = Sp[(SEN_W + k) * P + e];
+      euler_flux(eos, w, qx, qy);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Qd[d][k] = d < 2 ? qx[k] : qy[k];
+      u[d] = w[1] / w[0];
+      v[d] = w[2] / w[0];
+    }
+    double sk[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double dq = (Qd[0][k] - Qd[1][k]) + (Qd[2][k] - Qd[3][k]);
+      sk[k] = qm[k] > 0.0 ? (0.5 * dq) / qm[k] : 0.0;
+    }
+    const double a = sqrt(0.25 * (((sk[0] * sk[0] + sk[1] * sk[1]) + sk[2] * sk[2]) + sk[3] * sk[3]));
+    const double dil = 0.5 * ((u[0] - u[1]) + (v[2] - v[3]));
+    const double vort = 0.5 * ((v[0] - v[1]) - (u[2] - u[3]));
+    const double den = dil * dil + vort * vort;
+    const double th = (dil < 0.0 && den > 0.0) ? (dil * dil) / den : 0.0;
+    Sp[SEN_A * P + o] = a;
+    Sp[SEN_BETA * P + o] = th;
+  }
+}
+
+__global__ __launch_bounds__(256) void sensor3_kernel(StepLaunch Lc) {
+  VLBM_FIND_SEGMENT(Lc, (int)blockIdx.x, dp, fb, nb)
+  (void)nb;
+  const LevelDesc &A = *dp;
+  const int tid = blockIdx.x - fb;
+  if (tid >= A.ntiles || !A.sen) return;
+  const Tile tl = A.tiles[tid];
+  const auto Sp = (gptr<double>)A.sen;
+  const int64_t P = A.plane;
+  const int pitch = A.pitch;
+  const double cs = A.c_sensor, bmax = A.beta_max, bspan = A.beta_max - A.beta_min;
+  int x0, y0;
+  tile_origin(A, tl, x0, y0);
+  const int n = tl.w * tl.h;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    const int cy = c / tl.w, cx = c - cy * tl.w;
+    const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
+    const int x = x0 + cx, y = y0 + cy;
+    double sum = 0.0;
+    int cnt = 0;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int64_t e = sensor_nb(A, x, y, dx, dy);
+        if (e < 0) continue;
+        sum += Sp[SEN_A * P + e];
+        ++cnt;
+      }
+    double z = (cs * (sum / (double)cnt)) * Sp[SEN_BETA * P + o];
+    z = z < 0.0 ? 0.0 : z > 1.0 ? 1.0 : z;
+    Sp[SEN_BETA * P + o] = bmax - bspan * z;
+  }
+}
+
+hipError_t launch_sensor(const StepLaunch &a, int stage, int fp32, hipStream_t s) {
+  if (a.nblocks <= 0 || a.nseg < 0) return hipSuccess;
+  const dim3 grid(a.nblocks), block(256);
+  if (stage == 0) {
+    if (fp32)
+      hipLaunchKernelGGL(sensor0_kernel<float>, grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL(sensor0_kernel<double>, grid, block, 0, s, a);
+  } else if (stage == 1) {
+    if (fp32)
+      hipLaunchKernelGGL(sensor1_kernel<float>, grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL(sensor1_kernel<double>, grid, block, 0, s, a);
+  } else if (stage == 2) {
+    hipLaunchKernelGGL(sensor2_kernel, grid, block, 0, s, a);
+  } else {
+    hipLaunchKernelGGL(sensor3_kernel, grid, block, 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -89,7 +89,13 @@ enum StepFlags : int32_t {
   STEP_F64_MATH = 8,         // FP32 storage, relaxation evaluated in FP64
   STEP_FUSE2 = 16,           // tuning: the finest level takes both sub-steps per launch
   STEP_FUSED_PHASE = 32,     // launch-uniform: this phase is a fused two-sub-step launch
+  STEP_SENSOR = 64,          // launch-uniform: relax with the per-cell beta of the sensor planes
 };
+
+// Adaptive relaxation planes of a level (FP64, `plane` elements each, same
+// element offsets as the populations): W_0..W_3 at the start of the step, the
+// activity a, and theta (overwritten in place by beta).
+enum SensorPlane : int32_t { SEN_W = 0, SEN_A = 4, SEN_BETA = 5, SEN_PLANES = 6 };
 
 // Everything the step kernel needs about one (context, level) at one phase of
 // the schedule. Lives in device memory; a launch covers one or more of them.
@@ -110,6 +116,14 @@ struct LevelDesc {
   double gm1, h, tb;         // gamma - 1, 1/(2c), 2 beta
   double eos_a, eos_b, eos_ga;  // EOS constants a, b and gamma * a
   double win[4][4];          // inflow conserved states per side
+  // adaptive relaxation (eq. sensor-B); sen == nullptr when it is off
+  double *sen;               // SEN_PLANES planes (SensorPlane)
+  unsigned long long *qmax;        // [4] max |Q_{alpha,k}| of this coarse step, as bits
+  unsigned long long *qmax_other;  // [4] the slot of the other coarse-step parity
+  const uint8_t *status;     // frame status: 0 none, 1 active, 2 hole
+  int32_t fx0, fy0, fw, fh, xoff;  // frame geometry (level cells)
+  int32_t Nx, Ny, per;       // level domain; per: bit 0 periodic in x, bit 1 in y
+  double c_sensor, beta_min, beta_max;
 };
 
 // A run of workgroups of one launch that works on one LevelDesc. first_block
@@ -148,6 +162,10 @@ struct RectArgs {
 // Launchers (kernels.hip). All return hipError_t of the launch.
 hipError_t launch_step(const StepLaunch &a, int fp32, hipStream_t s, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr);
+// Adaptive relaxation stage 0 (the coarse step's max |Q|, a launch over the
+// first-phase descriptors of every level) or stages 1..3 over the tiles of the
+// step launch `a` (same segments and descriptors), to run just before it.
+hipError_t launch_sensor(const StepLaunch &a, int stage, int fp32, hipStream_t s);
 hipError_t launch_audit(const void *buf, const Tile *tiles, int ntiles, int64_t plane,
                         int pitch, int fp32, double *partial, hipStream_t s);
 hipError_t launch_set_state(const RectArgs &a, int fp32, int raw_populations, hipStream_t s);

@@ -96,6 +96,8 @@ vlbm_active_cells = _sig("vlbm_active_cells", C.c_long, [_P, C.c_int])
 vlbm_sync = _sig("vlbm_sync", _st, [_P])
 vlbm_set_profiling = _sig("vlbm_set_profiling", _st, [_P, C.c_int])
 vlbm_kernel_times = _sig("vlbm_kernel_times", _st, [_P, _D, C.POINTER(C.c_long), _D])
+vlbm_set_sensor = _sig("vlbm_set_sensor", _st, [_P, C.c_int, C.c_double, C.c_double, C.c_double])
+vlbm_get_beta = _sig("vlbm_get_beta", _st, _rect)
 MAX_LEVELS = 8
 vlbm_last_error = _sig("vlbm_last_error", C.c_char_p, [])
 
@@ -105,7 +107,7 @@ EXPORTED = ["vlbm_create", "vlbm_destroy", "vlbm_bind_pool", "vlbm_footprint_byt
             "vlbm_tag", "vlbm_tag_and_regrid", "vlbm_get_boxes", "vlbm_check_health",
             "vlbm_save", "vlbm_load", "vlbm_batch_advance", "vlbm_set_tuning", "vlbm_autotune",
             "vlbm_steps", "vlbm_active_cells", "vlbm_sync", "vlbm_last_error",
-            "vlbm_set_profiling", "vlbm_kernel_times"]
+            "vlbm_set_profiling", "vlbm_kernel_times", "vlbm_set_sensor", "vlbm_get_beta"]
 
 
 class VLBMError(RuntimeError):
@@ -297,6 +299,18 @@ class Solver:
         check(vlbm_kernel_times(self._h, ms, calls, cells))
         return {(i // 2, bool(i % 2)): (ms[i], calls[i], cells[i])
                 for i in range(2 * MAX_LEVELS) if calls[i]}
+
+    def set_sensor(self, on=True, c_sensor=1.0, beta_min=0.5, beta_max=0.9):
+        """Space/time-adaptive relaxation parameter (Sec. 2.2, eq. sensor-B)."""
+        check(vlbm_set_sensor(self._h, int(bool(on)), float(c_sensor), float(beta_min),
+                              float(beta_max)))
+
+    def get_beta(self, level, i0=0, j0=0, nx=None, ny=None):
+        """beta of the level's latest step per active cell (NaN elsewhere)."""
+        nx, ny = self._rect(level, i0, j0, nx, ny)
+        b = np.empty((ny, nx))
+        check(vlbm_get_beta(self._h, level, i0, j0, nx, ny, _dp(b), nx))
+        return b
 
     def set_tuning(self, tile_cells, flags=0):
         check(vlbm_set_tuning(self._h, int(tile_cells), int(flags)))

@@ -66,3 +66,18 @@ def smooth_mask(U, rel=0.02, radius=3):
             with np.errstate(invalid="ignore"):
                 m &= np.isfinite(rs) & (np.abs(rs - rho) <= rel * rho) & (np.abs(ps - p) <= rel * p)
     return m
+
+
+def fp32_error(o, g, case):
+    """Largest |W_gpu - W_oracle| on smooth cells, per component, relative to
+    the component's largest magnitude over the whole hierarchy (momentum
+    crosses zero, where a pointwise ratio measures nothing)."""
+    Uo = [o.get_state(l) for l in range(case.nlev)]
+    Ug = [g.get_state(l) for l in range(case.nlev)]
+    scale = [max(np.nanmax(np.abs(U[k])) for U in Uo) for k in range(4)]
+    worst = np.zeros((case.nlev, 4))
+    for l in range(case.nlev):
+        m = smooth_mask(Uo[l])
+        for k in range(4):
+            worst[l, k] = np.max(np.abs(Ug[l][k][m] - Uo[l][k][m])) / scale[k]
+    return worst

@@ -11,7 +11,8 @@ import pytest
 
 from paper_2609_35529_amd import workloads as wl
 from tests import exact
-from tests.parity import bitwise_equal, compare_populations, gpu_solver, run_pair, smooth_mask
+from tests.parity import (bitwise_equal, compare_populations, fp32_error, gpu_solver, run_pair,
+                          smooth_mask)
 
 pytestmark = pytest.mark.gpu
 FP64_TOL = 1e-12
@@ -172,21 +173,6 @@ def test_quadrant_full_size_conservation_1000_steps():
     scale = np.abs(T0).max()
     assert np.all(np.abs((T1 - T0) - (L1 - L0)) <= 1e-12 * scale), (T1 - T0, L1 - L0)
     assert g.check_health()
-
-
-def fp32_error(o, g, case):
-    """Largest |W_gpu - W_oracle| on smooth cells, per component, relative to
-    the component's largest magnitude over the whole hierarchy (momentum
-    crosses zero, where a pointwise ratio measures nothing)."""
-    Uo = [o.get_state(l) for l in range(case.nlev)]
-    Ug = [g.get_state(l) for l in range(case.nlev)]
-    scale = [max(np.nanmax(np.abs(U[k])) for U in Uo) for k in range(4)]
-    worst = np.zeros((case.nlev, 4))
-    for l in range(case.nlev):
-        m = smooth_mask(Uo[l])
-        for k in range(4):
-            worst[l, k] = np.max(np.abs(Ug[l][k][m] - Uo[l][k][m])) / scale[k]
-    return worst
 
 
 @pytest.mark.parametrize("precision", [1, 2])

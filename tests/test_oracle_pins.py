@@ -641,6 +641,42 @@ def test_sensor_gates_expansion_and_saturates_compression():
     assert np.all(b == 0.5)
 
 
+def test_sensor_gate_is_finite_when_the_velocity_gradients_underflow():
+    """A compression with velocities of order 1e-165: dil^2 + vort^2 underflows
+    to 0, and the gate is 0 (beta_max) instead of 0/0."""
+    b = _beta_after_one_step(_field(lambda X, Y: (1.0, -1e-165 * X, 0.0, 2.0)), C=1e6)
+    assert np.all(b == 0.9)
+
+
+def test_sensor_normalisation_is_domain_wide():
+    """max_{x,alpha} |Q_{alpha,k}| runs over the whole domain: a refined patch
+    over the strongest feature, holding the same values piecewise constant,
+    leaves the level-0 beta away from the patch bit for bit as on the single
+    grid (a per-level max would drop to the far field's and raise the sensor
+    there)."""
+    n = 32
+    x = (np.arange(n) + 0.5) / n - 0.5
+    X, Y = np.meshgrid(x, x)
+    B = wl.random_smooth_U(n, n, seed=11)
+    rho = B[0]
+    u, v = B[1] / rho, B[2] / rho
+    p = 0.4 * (B[3] - 0.5 * rho * (u * u + v * v)) + 3.0 * np.exp(-(X * X + Y * Y) / 0.004)
+    U = wl.conserved(rho, u, v, p)
+    one = wl.Case("t", n, n, 1.0 / n, 2, 1, 1.4, 6.0, 0.9, (0,) * 4, [], [U], 0)
+    two = wl.Case("t", n, n, 1.0 / n, 2, 2, 1.4, 6.0, 0.9, (0,) * 4, [(1, 24, 24, 16, 16)],
+                  [U, wl.prolong_piecewise(U, 2)], 0)
+    betas = []
+    for case in (one, two):
+        o = exact.run_oracle(case, steps=0)
+        o.set_sensor(True, 40.0, 0.5, 0.9)
+        o.advance(1)
+        betas.append(o.get_beta(0))
+    far = np.ones((n, n), bool)
+    far[9:23, 9:23] = False  # 3 cells or more from the patch (level-0 cells 12..19)
+    assert np.array_equal(betas[0][far], betas[1][far])
+    assert betas[0][far].min() < 0.85  # the far field's own estimate is not negligible
+
+
 def test_sensor_with_equal_bounds_is_the_constant_beta_run():
     """beta_min = beta_max: the adaptive path reproduces the constant-beta
     run bit for bit, through three levels."""
