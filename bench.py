@@ -302,8 +302,8 @@ def main():
     esz = 8 if prec == vlbm.FP64 else 4
     bytes_per_update = 2 * 16 * esz
     nl = sum(v[1] for v in ktimes.values()) / prof_steps
-    if sensor:  # stages 1-3 before every step launch, stage 0 once per coarse step
-        nl = 4 * nl + 1
+    if sensor:  # stage 2 before every step launch
+        nl = 2 * nl
     # dominant kernel: the (level, launch form) with the largest kernel time;
     # algorithmic bytes of one launch: 16 populations read and 16 written per
     # active cell it advances (a fused launch keeps the finest level's

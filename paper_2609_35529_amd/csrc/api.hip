@@ -218,9 +218,10 @@ struct Level {
   int nledger = 0;
   double *dpartial = nullptr;
   long steps = 0;  // buffer flips so far; its parity selects the current buffer
-  // adaptive relaxation planes (SensorPlane, SEN_PLANES x sen_plane doubles),
-  // allocated while the sensor is on
+  // adaptive relaxation planes (SensorPlane, SEN_PLANES x sen_plane doubles)
+  // and neighbour masks (sen_plane bytes), allocated while the sensor is on
   double *dsen = nullptr;
+  uint8_t *dmask = nullptr;
   int64_t sen_plane = 0;
   std::vector<int64_t> reflux_key;  // per reflux slot: (y * Nx + x) * 4 + q of its ring cell
 
@@ -246,7 +247,6 @@ struct LaunchRec {
   int32_t fused_kernel = 0;  // launched as the fused kernel
   int32_t prof_key = 0;      // 2 * level + fused, for per-kernel timing
   double cells = 0.0;        // active cells the launch advances
-  int32_t sensor_max = 0;    // adaptive relaxation stage 0 over every level (no step)
 };
 }  // namespace
 
@@ -270,6 +270,8 @@ struct vlbm_ctx {
   bool sensor = false;
   double c_sensor = 1.0, beta_min = 1.0, beta_max = 1.0;
   unsigned long long *dqmax = nullptr;  // [2][4]: max |Q| per coarse-step parity, as bits
+  bool sensor_stale = true;  // W planes and this coarse step's max |Q| need stage 0
+  int32_t s0_seg0 = 0, s0_nseg = 0, s0_nblocks = 0;  // stage 0: segments over every level
   double ledger_carry[4] = {0, 0, 0, 0}, ledger_carry_c[4] = {0, 0, 0, 0};
   // schedule tables: phases of one coarse step and their descriptors for the
   // two parities of the coarse step counter relative to table_base
@@ -338,6 +340,7 @@ void free_level(vlbm_ctx *c, Level &L) {
   c->mem.release(L.dledger);
   c->mem.release(L.dpartial);
   c->mem.release(L.dsen);
+  c->mem.release(L.dmask);
   long steps = L.steps;
   L = Level();
   L.steps = steps;
@@ -1053,24 +1056,32 @@ bool fused_active(const vlbm_ctx *c) {
 }
 
 // Allocate (sensor on) or release (off) the adaptive relaxation planes of
-// every present level; new planes start at zero. Both max |Q| slots restart
-// at zero (stage 0 of a coarse step accumulates into its parity's slot and
-// clears the other one, so every slot is zero when its coarse step begins).
+// every present level (new planes start at zero) and rebuild the neighbour
+// masks from the current status. The W planes and maxima then need stage 0.
 vlbm_status ensure_sensor(vlbm_ctx *c) {
+  c->sensor_stale = true;
   for (int l = 0; l < kMaxLevels; ++l) {
     Level &L = c->lv[l];
     const bool want = c->sensor && L.present && l < c->nlev;
     if (L.dsen && (!want || L.sen_plane != L.plane)) {
       c->mem.release(L.dsen);
+      c->mem.release(L.dmask);
       L.dsen = nullptr;
+      L.dmask = nullptr;
       L.sen_plane = 0;
     }
-    if (!want || L.dsen) continue;
-    const size_t nb = sizeof(double) * SEN_PLANES * (size_t)L.plane;
-    L.dsen = static_cast<double *>(c->mem.alloc(nb));
-    if (!L.dsen) return fail(VLBM_ENOMEM, "adaptive relaxation planes (%zu bytes)", nb);
-    L.sen_plane = L.plane;
-    HIPCHK(hipMemsetAsync(L.dsen, 0, nb, c->stream));
+    if (!want) continue;
+    if (!L.dsen) {
+      const size_t nb = sizeof(double) * SEN_PLANES * (size_t)L.plane;
+      L.dsen = static_cast<double *>(c->mem.alloc(nb));
+      L.dmask = static_cast<uint8_t *>(c->mem.alloc((size_t)L.plane));
+      if (!L.dsen || !L.dmask) return fail(VLBM_ENOMEM, "adaptive relaxation planes (%zu bytes)", nb);
+      L.sen_plane = L.plane;
+      HIPCHK(hipMemsetAsync(L.dsen, 0, nb, c->stream));
+    }
+    HIPCHK(hipMemsetAsync(L.dmask, 0, (size_t)L.plane, c->stream));
+    HIPCHK(launch_sensor_mask(L.dstatus, L.dmask, L.fx0, L.fy0, L.fw, L.fh, L.pitch, L.xoff, L.Nx, L.Ny,
+                              (c->perx() ? 1 : 0) | (c->pery() ? 2 : 0), c->stream));
   }
   if (!c->sensor) {
     c->mem.release(c->dqmax);
@@ -1079,7 +1090,6 @@ vlbm_status ensure_sensor(vlbm_ctx *c) {
   }
   if (!c->dqmax) c->dqmax = static_cast<unsigned long long *>(c->mem.alloc(8 * sizeof(unsigned long long)));
   if (!c->dqmax) return fail(VLBM_ENOMEM, "adaptive relaxation maxima");
-  HIPCHK(hipMemsetAsync(c->dqmax, 0, 8 * sizeof(unsigned long long), c->stream));
   return VLBM_OK;
 }
 
@@ -1117,16 +1127,13 @@ LevelDesc make_desc(const vlbm_ctx *c, int l, const long *st, bool fused = false
   for (int s2 = 0; s2 < 4; ++s2)
     for (int k = 0; k < 4; ++k) a.win[s2][k] = c->p.w_inflow[s2][k];
   if (c->sensor && !fused) {
-    a.sen = L.dsen;  // qmax and qmax_other: per table parity (build_tables)
-    a.status = L.dstatus;
+    a.sen = L.dsen;  // qmax, qmax_next, clear_next, emit_qmax: per phase (build_tables)
+    a.mask = L.dmask;
     a.fx0 = L.fx0;
     a.fy0 = L.fy0;
-    a.fw = L.fw;
-    a.fh = L.fh;
     a.xoff = L.xoff;
     a.Nx = L.Nx;
     a.Ny = L.Ny;
-    a.per = (c->perx() ? 1 : 0) | (c->pery() ? 2 : 0);
     a.c_sensor = c->c_sensor;
     a.beta_min = c->beta_min;
     a.beta_max = c->beta_max;
@@ -1176,8 +1183,14 @@ vlbm_status build_tables(vlbm_ctx *c) {
       const bool fused = k == 0;
       descs[e * P + p] = make_desc(c, l, st, fused);
       if (descs[e * P + p].sen) {
-        descs[e * P + p].qmax = c->dqmax + 4 * e;
-        descs[e * P + p].qmax_other = c->dqmax + 4 * (e ^ 1);
+        LevelDesc &D = descs[e * P + p];
+        D.qmax = c->dqmax + 4 * e;
+        D.qmax_next = c->dqmax + 4 * (e ^ 1);
+        D.clear_next = p == 0;
+        size_t last = p;
+        for (size_t q = p + 1; q < P; ++q)
+          if (c->phases[q].first == l) last = q;
+        D.emit_qmax = last == p;
       }
       const int nb = nb8(fused ? c->lv[l].ftiles.size() : c->lv[l].tiles.size());
       c->phase_blocks[p] = nb;
@@ -1198,21 +1211,20 @@ vlbm_status build_tables(vlbm_ctx *c) {
       st[l] += 1;
     }
   }
+  c->s0_seg0 = (int32_t)seg_desc.size();
+  c->s0_nseg = 0;
+  c->s0_nblocks = 0;
   if (c->sensor) {
     // stage 0: one segment per level, the descriptor of the level's first
-    // phase (its buffers as at the coarse step's start); launched first
-    LaunchRec a{};
-    a.seg0 = (int)seg_desc.size();
-    a.sensor_max = 1;
+    // phase (its buffers as at the coarse step's start)
     for (int l = 0; l < c->nlev; ++l) {
       size_t p0 = 0;
       while (p0 < P && c->phases[p0].first != l) ++p0;
       if (p0 == P || c->phases[p0].second == 0) return fail(VLBM_EINVAL, "internal: sensor schedule");
       seg_desc.push_back({(int)p0, nb8(c->lv[l].tiles.size())});
       seg_desc1.push_back((int)(P + p0));
-      a.nseg += 1;
+      c->s0_nseg += 1;
     }
-    c->launches.insert(c->launches.begin(), a);
   }
   const size_t NS = seg_desc.size();
   if (seg_desc1.size() != NS) return fail(VLBM_EINVAL, "internal: launch tables differ between parities");
@@ -1223,14 +1235,17 @@ vlbm_status build_tables(vlbm_ctx *c) {
   if (!c->ddesc || !c->dseg) return fail(VLBM_ENOMEM, "schedule tables");
   // segments of one launch are laid out back to back, first_block running on
   std::vector<Segment> segs(2 * NS);
-  for (const LaunchRec &a : c->launches) {
+  auto lay = [&](int seg0, int nseg) {
     int32_t fb = 0;
-    for (int i = a.seg0; i < a.seg0 + a.nseg; ++i) {
+    for (int i = seg0; i < seg0 + nseg; ++i) {
       segs[i] = {c->ddesc + seg_desc[i].first, fb, seg_desc[i].second};
       segs[NS + i] = {c->ddesc + seg_desc1[i], fb, seg_desc[i].second};
       fb += seg_desc[i].second;
     }
-  }
+    return fb;
+  };
+  for (const LaunchRec &a : c->launches) lay(a.seg0, a.nseg);
+  c->s0_nblocks = lay(c->s0_seg0, c->s0_nseg);
   for (LaunchRec &a : c->launches) {
     a.nblocks = 0;
     for (int i = a.seg0; i < a.seg0 + a.nseg; ++i) a.nblocks += seg_desc[i].second;
@@ -1276,15 +1291,11 @@ vlbm_status launch_coarse_step(vlbm_ctx *c, int e) {
       a.nseg = r.nseg;
     }
     a.nblocks = r.nblocks;
-    if (r.sensor_max) {
-      HIPCHK(launch_sensor(a, 0, c->fp32, c->stream));
-      continue;
-    }
     a.first = r.first;
     a.flags = c->step_flags | (r.fused_kernel ? STEP_FUSED_PHASE : 0);
     a.ak = r.ak;
     if (c->sensor && !r.fused_kernel) {  // per-cell beta from the state at the start of the step
-      for (int stage = 1; stage <= 3; ++stage) HIPCHK(launch_sensor(a, stage, c->fp32, c->stream));
+      HIPCHK(launch_sensor(a, 2, c->fp32, c->stream));
       a.flags |= STEP_SENSOR;
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1305,6 +1316,26 @@ vlbm_status launch_coarse_step(vlbm_ctx *c, int e) {
     }
     HIPCHK(launch_step(a, c->fp32, c->stream, e0, e1));
   }
+  return VLBM_OK;
+}
+
+// Stage 0 before a coarse step of table parity e: W planes of every level and
+// the coarse step's max |Q| from the stored populations (both slots cleared
+// first; eager, never inside a graph).
+vlbm_status sensor_init(vlbm_ctx *c, int e) {
+  if (!c->sensor || !c->sensor_stale) return VLBM_OK;
+  HIPCHK(hipMemsetAsync(c->dqmax, 0, 8 * sizeof(unsigned long long), c->stream));
+  StepLaunch a{};
+  const int s0 = e * c->nseg_table + c->s0_seg0;
+  if (c->s0_nseg == 1) {
+    a.d0 = c->hseg[s0].d;
+  } else {
+    a.segs = c->dseg + s0;
+    a.nseg = c->s0_nseg;
+  }
+  a.nblocks = c->s0_nblocks;
+  HIPCHK(launch_sensor(a, 0, c->fp32, c->stream));
+  c->sensor_stale = false;
   return VLBM_OK;
 }
 
@@ -1338,6 +1369,10 @@ vlbm_status ensure_graph(vlbm_ctx *c) {
 }
 
 vlbm_status advance_impl(vlbm_ctx *c, long n) {
+  if (n > 0) {
+    vlbm_status st = sensor_init(c, table_parity(c));
+    if (st) return st;
+  }
   const bool graphs = c->use_graphs && !c->prof && c->stream != nullptr && n >= 4;
   while (n > 0) {
     const int e = table_parity(c);
@@ -1429,6 +1464,7 @@ vlbm_status rect_io(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny, doub
                sizeof(double) * cnx);
     e = hipMemcpyAsync(stage, tmp.data(), sizeof(double) * ncomp * n, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_set_state(a, c->fp32, raw ? 1 : 0, c->stream);
+    c->sensor_stale = true;
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   } else {
     e = launch_get(a, c->fp32, ncomp == 16 ? 1 : 0, c->stream);
@@ -2370,43 +2406,15 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
         nseg[e * P + p] = (int32_t)segs.size() - seg0[e * P + p];
         nblk[e * P + p] = fb;
       }
-    // adaptive relaxation stage 0 of every context, one launch per coarse step
-    int32_t s0seg[2] = {0, 0}, s0n[2] = {0, 0}, s0blk[2] = {0, 0};
-    if (c0->sensor)
-      for (int e = 0; e < 2; ++e) {
-        s0seg[e] = (int32_t)segs.size();
-        int32_t fb = 0;
-        for (size_t a = 0; a < act.size(); ++a) {
-          vlbm_ctx *c = ctxs[act[a]];
-          const LaunchRec &R = c->launches.front();
-          if (!R.sensor_max) return fail(VLBM_EINVAL, "internal: sensor launch table");
-          const int ei = table_parity(c) ^ e;
-          for (int i = R.seg0; i < R.seg0 + R.nseg; ++i) {
-            const Segment &S = c->hseg[ei * c->nseg_table + i];
-            if (S.nblocks == 0) continue;
-            segs.push_back({S.d, fb, S.nblocks});
-            fb += S.nblocks;
-          }
-        }
-        s0n[e] = (int32_t)segs.size() - s0seg[e];
-        s0blk[e] = fb;
-      }
+    for (int i : act) {  // adaptive relaxation stage 0 where the state changed
+      vlbm_status st = sensor_init(ctxs[i], table_parity(ctxs[i]));
+      if (st) return st;
+    }
     Segment *dseg = static_cast<Segment *>(c0->mem.alloc(sizeof(Segment) * std::max<size_t>(1, segs.size())));
     if (!dseg) return fail(VLBM_ENOMEM, "batch segment table");
     HIPCHK(hipMemcpyAsync(dseg, segs.data(), sizeof(Segment) * segs.size(), hipMemcpyHostToDevice, c0->stream));
     for (long s2 = 0; s2 < m; ++s2) {
       const int e = (int)(s2 & 1);
-      if (c0->sensor && s0n[e] > 0) {
-        StepLaunch L{};
-        L.segs = dseg + s0seg[e];
-        L.nseg = s0n[e];
-        L.nblocks = s0blk[e];
-        hipError_t err = launch_sensor(L, 0, c0->fp32, c0->stream);
-        if (err != hipSuccess) {
-          c0->mem.release(dseg);
-          return fail(VLBM_EDEVICE, "batched launch: %s", hipGetErrorString(err));
-        }
-      }
       for (size_t p = 0; p < P; ++p) {
         if (nseg[e * P + p] == 0) continue;
         StepLaunch L{};
@@ -2418,8 +2426,7 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
         L.ak = ak_of(ph[p].second, r);
         hipError_t err = hipSuccess;
         if (c0->sensor) {
-          for (int stage = 1; stage <= 3 && err == hipSuccess; ++stage)
-            err = launch_sensor(L, stage, c0->fp32, c0->stream);
+          err = launch_sensor(L, 2, c0->fp32, c0->stream);
           L.flags |= STEP_SENSOR;
         }
         if (err == hipSuccess) err = launch_step(L, c0->fp32, c0->stream);

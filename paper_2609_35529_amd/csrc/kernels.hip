@@ -223,6 +223,104 @@ __device__ __forceinline__ void put(S *__restrict__ d0, int64_t P, int64_t o, co
   }
 }
 
+// Euler flux of a conserved state in FP64 (the order of the arithmetic
+// contract above).
+__device__ __forceinline__ void euler_flux(const EosT<double> &eos, const double W[4], double Qx[4],
+                                           double Qy[4]) {
+  const double rho = W[0], mx = W[1], my = W[2], E = W[3];
+  const double u = mx / rho;
+  const double v = my / rho;
+  const double eint = E - 0.5 * (mx * u + my * v);
+  const double p = pressure<double>(eos, rho, eint);
+  Qx[0] = mx;
+  Qx[1] = mx * u + p;
+  Qx[2] = my * u;
+  Qx[3] = (E + p) * u;
+  Qy[0] = my;
+  Qy[1] = mx * v;
+  Qy[2] = my * v + p;
+  Qy[3] = (E + p) * v;
+}
+
+// m_k := max(m_k, |Qx_k(W)|, |Qy_k(W)|)
+__device__ __forceinline__ void flux_absmax(const EosT<double> &eos, const double W[4], double m[4]) {
+  double qx[4], qy[4];
+  euler_flux(eos, W, qx, qy);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) m[k] = fmax(m[k], fmax(fabs(qx[k]), fabs(qy[k])));
+}
+
+// Workgroup maximum of m[4] into qmax[4] (bit patterns: non-negative doubles
+// order like them, so an unsigned 64-bit atomic max is exact). Every thread of
+// the workgroup must call it.
+__device__ __forceinline__ void block_qmax(double m[4], unsigned long long *qmax) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) m[k] = fmax(m[k], __shfl_xor(m[k], off));
+  __shared__ double red[4][4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) red[k][wv] = m[k];
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int k = threadIdx.x;
+    double v = red[k][0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) v = fmax(v, red[k][i]);
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+    unsigned long long *q = qmax + k;
+    // the running maximum only grows: a stale read can only let an update through
+    if (bits > __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(q, bits);
+  }
+}
+
+// Offset of level cell (x + dx, y + dy) (active, per its mask bit), periodic
+// wrap applied: a neighbour across the domain edge sits Nx columns (Ny rows)
+// back in the frame.
+__device__ __forceinline__ int64_t nb_offset(int64_t o, int x, int y, int dx, int dy, int pitch, int Nx,
+                                             int Ny) {
+  int64_t e = o + dx + (int64_t)dy * pitch;
+  if (x + dx < 0) e += Nx;
+  if (x + dx >= Nx) e -= Nx;
+  if (y + dy < 0) e += (int64_t)Ny * pitch;
+  if (y + dy >= Ny) e -= (int64_t)Ny * pitch;
+  return e;
+}
+
+// Level coordinates of a tile's first cell.
+__device__ __forceinline__ void tile_origin(const LevelDesc &A, const Tile &tl, int &x0, int &y0) {
+  const int rel = tl.off0 - A.xoff;
+  const int fy = rel / A.pitch;
+  x0 = A.fx0 + (rel - fy * A.pitch);
+  y0 = A.fy0 + fy;
+}
+
+// beta = beta_max - (beta_max - beta_min) clip(C sbar theta, 0, 1) of the cell
+// at offset o, level (x, y): sbar the mean of a over the active cells of its
+// 3 x 3 block (row by row from (x - 1, y - 1)), theta its own.
+__device__ __forceinline__ double cell_beta(__attribute__((address_space(1))) const double *Sp,
+                                            int mk, int64_t P, int64_t o, int x, int y, int pitch,
+                                            int Nx, int Ny, double cs, double bmax, double bspan) {
+  double sum = 0.0;
+  int cnt = 0;
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      if (dx == 0 && dy == 0) {
+        sum += Sp[SEN_A * P + o];
+        ++cnt;
+      } else if ((mk >> mask_bit(dx, dy)) & 1) {
+        sum += Sp[SEN_A * P + nb_offset(o, x, y, dx, dy, pitch, Nx, Ny)];
+        ++cnt;
+      }
+    }
+  double z = (cs * (sum / (double)cnt)) * Sp[SEN_BETA * P + o];
+  z = z < 0.0 ? 0.0 : z > 1.0 ? 1.0 : z;
+  return bmax - bspan * z;
+}
+
 // One workgroup's work on tile `lb` of descriptor A (inlined twice below, so
 // that A is either plain kernel-argument memory or plain global memory).
 template <class T, class C, bool NT, bool TWO, bool SEN>
@@ -243,8 +341,17 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
   const int pitch = A.pitch;
   const EosT<C> eos = eos_of<C>(A);
   const C h = (C)A.h, tb = (C)A.tb;
-  // per-cell 2 beta from the adaptive relaxation planes (eq. sensor-B)
-  const auto bet = (__attribute__((address_space(1))) const double *)(SEN ? A.sen + SEN_BETA * plane : nullptr);
+  // adaptive relaxation (eq. sensor-B): per-cell 2 beta in, W of the stored
+  // result out, and on a level's last step of the coarse step the next max |Q|
+  const auto Sp = (gptr<double>)(SEN ? A.sen : nullptr);
+  const auto M = (__attribute__((address_space(1))) const uint8_t *)(SEN ? A.mask : nullptr);
+  const bool emit = SEN && A.emit_qmax != 0;
+  const EosT<double> eosd = eos_of<double>(A);
+  const double cs = A.c_sensor, bmax = A.beta_max, bspan = A.beta_max - A.beta_min;
+  const int Nx = A.Nx, Ny = A.Ny;
+  int x0 = 0, y0 = 0;
+  if (SEN) tile_origin(A, tl, x0, y0);
+  double m[4] = {0.0, 0.0, 0.0, 0.0};
   if (tl.ntask) {
     for (int i = threadIdx.x; i < tl.ntask; i += blockDim.x)
       run_task<T>(A, first, ak, A.tasks[tl.task0 + i]);
@@ -279,10 +386,26 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
       const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
       C g[16];
       pull<T, C>(s, plane, pitch, o, g);
-      relax<C>(g, eos, h, SEN ? (C)(2.0 * bet[o]) : tb);
+      C tbc = tb;
+      if (SEN) {
+        const double beta = cell_beta(Sp, M[o], plane, o, x0 + cx, y0 + cy, pitch, Nx, Ny, cs, bmax, bspan);
+        Sp[SEN_BETA * plane + o] = beta;
+        tbc = (C)(2.0 * beta);
+      }
+      relax<C>(g, eos, h, tbc);
       put<T, C, NT>(d, plane, o, g);
+      if (SEN) {
+        double w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          w[k] = (((double)(T)g[k] + (double)(T)g[4 + k]) + (double)(T)g[8 + k]) + (double)(T)g[12 + k];
+          Sp[(SEN_W + k) * plane + o] = w[k];
+        }
+        if (emit) flux_absmax(eosd, w, m);
+      }
     }
   }
+  if (emit) block_qmax(m, A.qmax_next);
 }
 
 // DP_, FB_, NB_ := the descriptor of workgroup b of launch Lc, its
@@ -537,84 +660,34 @@ hipError_t launch_step(const StepLaunch &a, int fp32, hipStream_t s, hipEvent_t 
 
 // ---------------------------------------------------------------------------
 // Space/time-adaptive relaxation parameter (Sec. 2.2, eq. sensor-B) of every
-// active cell of a level, from the state at the start of its step, in FP64
-// for every storage type. Once per coarse step, over the step tiles of every
-// level at the coarse step's start (the one instant the whole hierarchy holds
-// one time level):
-//   0. Qmax_k = max over all active cells and both directions of |Q_{alpha,k}(W)|,
-//      W_k = ((f_0k + f_1k) + f_2k) + f_3k of the stored populations
-//      (non-negative doubles order like their bit patterns, so an unsigned
-//      64-bit atomic max keeps it exactly); the slot of the other coarse-step
-//      parity, read by the previous coarse step, is cleared for the next one.
-// Then before every step of a level, three launches over the step's own tiles:
-//   1. W_k into the W planes;
-//   2. s_k = (0.5 ((Qx_k(x+1) - Qx_k(x-1)) + (Qy_k(y+1) - Qy_k(y-1)))) / Qmax_k
+// active cell of a level, from the state at the start of its step, FP64 for
+// every storage type:
+//   Qmax_k = max over both directions and the active cells of every level of
+//      |Q_{alpha,k}(W)|, taken at the start of each coarse step (the one
+//      instant at which the whole hierarchy holds one time level);
+//   s_k = (0.5 ((Qx_k(x+1) - Qx_k(x-1)) + (Qy_k(y+1) - Qy_k(y-1)))) / Qmax_k
 //      (0 where Qmax_k = 0), a = sqrt(0.25 (((s_0^2 + s_1^2) + s_2^2) + s_3^2));
-//      dil = 0.5 ((u(x+1) - u(x-1)) + (v(y+1) - v(y-1))),
-//      vort = 0.5 ((v(x+1) - v(x-1)) - (u(y+1) - u(y-1))),
-//      theta = dil^2 / (dil^2 + vort^2) under compression (dil < 0), else 0
+//   dil = 0.5 ((u(x+1) - u(x-1)) + (v(y+1) - v(y-1))),
+//   vort = 0.5 ((v(x+1) - v(x-1)) - (u(y+1) - u(y-1))),
+//   theta = dil^2 / (dil^2 + vort^2) under compression (dil < 0), else 0
 //      (0 too where dil^2 + vort^2 underflows to 0);
-//   3. beta = beta_max - (beta_max - beta_min) clip(C sbar theta, 0, 1), with
-//      sbar the mean of a over the active cells of the 3 x 3 block (summed row
-//      by row from (x - 1, y - 1)); beta overwrites theta in place (a cell reads
-//      only its own theta).
+//   beta = beta_max - (beta_max - beta_min) clip(C sbar theta, 0, 1), sbar the
+//      mean of a over the active cells of the 3 x 3 block (summed row by row
+//      from (x - 1, y - 1)).
 // A neighbour that is not an active cell of the level (across a non-periodic
 // side, outside the frame, a hole, uncovered) stands in as the cell itself in
-// stage 2 and is left out of the mean of stage 3.
+// the differences and is left out of the mean.
+//
+// Pipeline. Before every step of a level, stage 2 puts a and theta into their
+// planes (the context's first phase of the coarse step also clears the next
+// Qmax slot). The step kernel (SEN variant) then takes beta from them
+// (cell_beta; beta overwrites theta in place, as a cell reads only its own
+// theta), writes W of every cell it advances into the W planes (the sums of
+// the values it stores), and on a level's last step of a coarse step
+// accumulates the next coarse step's Qmax from them. Stage 0 fills the W
+// planes of every level and this coarse step's Qmax from the stored
+// populations, once after any change of state.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void euler_flux(const EosT<double> &eos, const double W[4], double Qx[4],
-                                           double Qy[4]) {
-  const double rho = W[0], mx = W[1], my = W[2], E = W[3];
-  const double u = mx / rho;
-  const double v = my / rho;
-  const double eint = E - 0.5 * (mx * u + my * v);
-  const double p = pressure<double>(eos, rho, eint);
-  Qx[0] = mx;
-  Qx[1] = mx * u + p;
-  Qx[2] = my * u;
-  Qx[3] = (E + p) * u;
-  Qy[0] = my;
-  Qy[1] = mx * v;
-  Qy[2] = my * v + p;
-  Qy[3] = (E + p) * v;
-}
-
-// Element offset of level cell (x + dx, y + dy), |dx|, |dy| <= 1, periodic
-// sides wrapped, or -1 when that is not an active cell of the level.
-__device__ __forceinline__ int64_t sensor_nb(const LevelDesc &A, int x, int y, int dx, int dy) {
-  int xx = x + dx, yy = y + dy;
-  if (xx < 0 || xx >= A.Nx) {
-    if (!(A.per & 1)) return -1;
-    xx = xx < 0 ? xx + A.Nx : xx - A.Nx;
-  }
-  if (yy < 0 || yy >= A.Ny) {
-    if (!(A.per & 2)) return -1;
-    yy = yy < 0 ? yy + A.Ny : yy - A.Ny;
-  }
-  const int fx = xx - A.fx0, fy = yy - A.fy0;
-  if (fx < 0 || fy < 0 || fx >= A.fw || fy >= A.fh) return -1;
-  const auto st = (__attribute__((address_space(1))) const uint8_t *)A.status;
-  if (st[(int64_t)fy * A.fw + fx] != 1) return -1;
-  return (int64_t)fy * A.pitch + fx + A.xoff;
-}
-
-// Level coordinates of a tile's first cell.
-__device__ __forceinline__ void tile_origin(const LevelDesc &A, const Tile &tl, int &x0, int &y0) {
-  const int rel = tl.off0 - A.xoff;
-  const int fy = rel / A.pitch;
-  x0 = A.fx0 + (rel - fy * A.pitch);
-  y0 = A.fy0 + fy;
-}
-
-// W of a cell from its stored populations (FP64 sums in the fixed order).
-template <class T>
-__device__ __forceinline__ void stored_W(const T *s0, int64_t P, int64_t o, double w[4]) {
-  const auto s = (__attribute__((address_space(1))) const T *)s0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-    w[k] = (((double)s[(0 * 4 + k) * P + o] + (double)s[(1 * 4 + k) * P + o]) +
-            (double)s[(2 * 4 + k) * P + o]) + (double)s[(3 * 4 + k) * P + o];
-}
 
 template <class T>
 __global__ __launch_bounds__(256) void sensor0_kernel(StepLaunch Lc) {
@@ -622,9 +695,10 @@ __global__ __launch_bounds__(256) void sensor0_kernel(StepLaunch Lc) {
   (void)nb;
   const LevelDesc &A = *dp;
   const int tid = blockIdx.x - fb;
-  if (tid == 0 && threadIdx.x < 4) A.qmax_other[threadIdx.x] = 0ull;
   if (tid >= A.ntiles || !A.sen) return;  // uniform over the workgroup
   const Tile tl = A.tiles[tid];
+  const auto s = (__attribute__((address_space(1))) const T *)A.src;
+  const auto Wp = (gptr<double>)A.sen;
   const int64_t P = A.plane;
   const int pitch = A.pitch;
   const EosT<double> eos = eos_of<double>(A);
@@ -633,53 +707,16 @@ __global__ __launch_bounds__(256) void sensor0_kernel(StepLaunch Lc) {
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
     const int cy = c / tl.w, cx = c - cy * tl.w;
     const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
-    double w[4], qx[4], qy[4];
-    stored_W<T>(static_cast<const T *>(A.src), P, o, w);
-    euler_flux(eos, w, qx, qy);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) m[k] = fmax(m[k], fmax(fabs(qx[k]), fabs(qy[k])));
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) m[k] = fmax(m[k], __shfl_xor(m[k], off));
-  __shared__ double red[4][4];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) red[k][wv] = m[k];
-  __syncthreads();
-  if (threadIdx.x < 4) {
-    const int k = threadIdx.x;
-    double v = red[k][0];
-    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) v = fmax(v, red[k][i]);
-    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
-    unsigned long long *q = A.qmax + k;
-    // the running maximum only grows: a stale read can only let an update through
-    if (bits > __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(q, bits);
-  }
-}
-
-template <class T>
-__global__ __launch_bounds__(256) void sensor1_kernel(StepLaunch Lc) {
-  VLBM_FIND_SEGMENT(Lc, (int)blockIdx.x, dp, fb, nb)
-  (void)nb;
-  const LevelDesc &A = *dp;
-  const int tid = blockIdx.x - fb;
-  if (tid >= A.ntiles || !A.sen) return;
-  const Tile tl = A.tiles[tid];
-  const auto Wp = (gptr<double>)A.sen;
-  const int64_t P = A.plane;
-  const int pitch = A.pitch;
-  const int n = tl.w * tl.h;
-  for (int c = threadIdx.x; c < n; c += blockDim.x) {
-    const int cy = c / tl.w, cx = c - cy * tl.w;
-    const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
     double w[4];
-    stored_W<T>(static_cast<const T *>(A.src), P, o, w);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) Wp[(SEN_W + k) * P + o] = w[k];
+    for (int k = 0; k < 4; ++k) {
+      w[k] = (((double)s[(0 * 4 + k) * P + o] + (double)s[(1 * 4 + k) * P + o]) +
+              (double)s[(2 * 4 + k) * P + o]) + (double)s[(3 * 4 + k) * P + o];
+      Wp[(SEN_W + k) * P + o] = w[k];
+    }
+    flux_absmax(eos, w, m);
   }
+  block_qmax(m, A.qmax);
 }
 
 __global__ __launch_bounds__(256) void sensor2_kernel(StepLaunch Lc) {
@@ -687,15 +724,18 @@ __global__ __launch_bounds__(256) void sensor2_kernel(StepLaunch Lc) {
   (void)nb;
   const LevelDesc &A = *dp;
   const int tid = blockIdx.x - fb;
+  if (tid == 0 && A.clear_next && threadIdx.x < 4) A.qmax_next[threadIdx.x] = 0ull;
   if (tid >= A.ntiles || !A.sen) return;
   const Tile tl = A.tiles[tid];
   const auto Sp = (gptr<double>)A.sen;
+  const auto M = (__attribute__((address_space(1))) const uint8_t *)A.mask;
   const int64_t P = A.plane;
   const int pitch = A.pitch;
   const EosT<double> eos = eos_of<double>(A);
   double qm[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) qm[k] = __longlong_as_double((long long)A.qmax[k]);
+  const int Nx = A.Nx, Ny = A.Ny;
   int x0, y0;
   tile_origin(A, tl, x0, y0);
   const int n = tl.w * tl.h;
@@ -703,12 +743,12 @@ __global__ __launch_bounds__(256) void sensor2_kernel(StepLaunch Lc) {
     const int cy = c / tl.w, cx = c - cy * tl.w;
     const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
     const int x = x0 + cx, y = y0 + cy;
-    int64_t nbo[4] = {sensor_nb(A, x, y, 1, 0), sensor_nb(A, x, y, -1, 0), sensor_nb(A, x, y, 0, 1),
-                      sensor_nb(A, x, y, 0, -1)};
+    const int mk = M[o];
+    constexpr int DX[4] = {1, -1, 0, 0}, DY[4] = {0, 0, 1, -1};
     double Qd[4][4], u[4], v[4];  // Qd: Qx of the x neighbours, Qy of the y neighbours
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
-      const int64_t e = nbo[d] < 0 ? o : nbo[d];
+      const int64_t e = (mk >> mask_bit(DX[d], DY[d])) & 1 ? nb_offset(o, x, y, DX[d], DY[d], pitch, Nx, Ny) : o;
       double w[4], qx[4], qy[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) w[k] = Sp[(SEN_W + k) * P + e];
@@ -734,39 +774,45 @@ __global__ __launch_bounds__(256) void sensor2_kernel(StepLaunch Lc) {
   }
 }
 
-__global__ __launch_bounds__(256) void sensor3_kernel(StepLaunch Lc) {
-  VLBM_FIND_SEGMENT(Lc, (int)blockIdx.x, dp, fb, nb)
-  (void)nb;
-  const LevelDesc &A = *dp;
-  const int tid = blockIdx.x - fb;
-  if (tid >= A.ntiles || !A.sen) return;
-  const Tile tl = A.tiles[tid];
-  const auto Sp = (gptr<double>)A.sen;
-  const int64_t P = A.plane;
-  const int pitch = A.pitch;
-  const double cs = A.c_sensor, bmax = A.beta_max, bspan = A.beta_max - A.beta_min;
-  int x0, y0;
-  tile_origin(A, tl, x0, y0);
-  const int n = tl.w * tl.h;
-  for (int c = threadIdx.x; c < n; c += blockDim.x) {
-    const int cy = c / tl.w, cx = c - cy * tl.w;
-    const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
-    const int x = x0 + cx, y = y0 + cy;
-    double sum = 0.0;
-    int cnt = 0;
-#pragma unroll
+// One thread per frame element; writes the mask of every active cell and 0
+// elsewhere.
+__global__ __launch_bounds__(256) void sensor_mask_kernel(const uint8_t *status, uint8_t *mask, int fx0,
+                                                          int fy0, int fw, int fh, int pitch, int xoff,
+                                                          int Nx, int Ny, int per) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)fw * fh) return;
+  const int fy = (int)(i / fw), fx = (int)(i - (int64_t)fy * fw);
+  const int64_t o = (int64_t)fy * pitch + fx + xoff;
+  int mk = 0;
+  if (status[i] == 1) {
+    const int x = fx0 + fx, y = fy0 + fy;
     for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
-        const int64_t e = sensor_nb(A, x, y, dx, dy);
-        if (e < 0) continue;
-        sum += Sp[SEN_A * P + e];
-        ++cnt;
+        if (dx == 0 && dy == 0) continue;
+        int xx = x + dx, yy = y + dy;
+        if (xx < 0 || xx >= Nx) {
+          if (!(per & 1)) continue;
+          xx = xx < 0 ? xx + Nx : xx - Nx;
+        }
+        if (yy < 0 || yy >= Ny) {
+          if (!(per & 2)) continue;
+          yy = yy < 0 ? yy + Ny : yy - Ny;
+        }
+        const int gx = xx - fx0, gy = yy - fy0;
+        if (gx < 0 || gy < 0 || gx >= fw || gy >= fh) continue;
+        if (status[(int64_t)gy * fw + gx] == 1) mk |= 1 << mask_bit(dx, dy);
       }
-    double z = (cs * (sum / (double)cnt)) * Sp[SEN_BETA * P + o];
-    z = z < 0.0 ? 0.0 : z > 1.0 ? 1.0 : z;
-    Sp[SEN_BETA * P + o] = bmax - bspan * z;
   }
+  mask[o] = (uint8_t)mk;
+}
+
+hipError_t launch_sensor_mask(const uint8_t *status, uint8_t *mask, int fx0, int fy0, int fw, int fh,
+                              int pitch, int xoff, int Nx, int Ny, int per, hipStream_t s) {
+  const int64_t n = (int64_t)fw * fh;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sensor_mask_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, status, mask,
+                     fx0, fy0, fw, fh, pitch, xoff, Nx, Ny, per);
+  return hipGetLastError();
 }
 
 hipError_t launch_sensor(const StepLaunch &a, int stage, int fp32, hipStream_t s) {
@@ -777,15 +823,10 @@ hipError_t launch_sensor(const StepLaunch &a, int stage, int fp32, hipStream_t s
       hipLaunchKernelGGL(sensor0_kernel<float>, grid, block, 0, s, a);
     else
       hipLaunchKernelGGL(sensor0_kernel<double>, grid, block, 0, s, a);
-  } else if (stage == 1) {
-    if (fp32)
-      hipLaunchKernelGGL(sensor1_kernel<float>, grid, block, 0, s, a);
-    else
-      hipLaunchKernelGGL(sensor1_kernel<double>, grid, block, 0, s, a);
   } else if (stage == 2) {
     hipLaunchKernelGGL(sensor2_kernel, grid, block, 0, s, a);
   } else {
-    hipLaunchKernelGGL(sensor3_kernel, grid, block, 0, s, a);
+    return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

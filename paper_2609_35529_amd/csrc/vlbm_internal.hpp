@@ -93,9 +93,18 @@ enum StepFlags : int32_t {
 };
 
 // Adaptive relaxation planes of a level (FP64, `plane` elements each, same
-// element offsets as the populations): W_0..W_3 at the start of the step, the
-// activity a, and theta (overwritten in place by beta).
+// element offsets as the populations): W_0..W_3 of the current time level
+// (written by the step that produced it), the activity a, and theta
+// (overwritten in place by beta).
 enum SensorPlane : int32_t { SEN_W = 0, SEN_A = 4, SEN_BETA = 5, SEN_PLANES = 6 };
+
+// Neighbour mask of an active cell (one byte per frame element): bit
+// (dy + 1) * 3 + (dx + 1), the centre bit 4 left out (bits 5..8 stored one
+// lower), set when level cell (x + dx, y + dy), periodic sides wrapped, is an
+// active cell of the level.
+__host__ __device__ constexpr int mask_bit(int dx, int dy) {
+  return (dy + 1) * 3 + (dx + 1) - ((dy + 1) * 3 + (dx + 1) > 4 ? 1 : 0);
+}
 
 // Everything the step kernel needs about one (context, level) at one phase of
 // the schedule. Lives in device memory; a launch covers one or more of them.
@@ -118,11 +127,13 @@ struct LevelDesc {
   double win[4][4];          // inflow conserved states per side
   // adaptive relaxation (eq. sensor-B); sen == nullptr when it is off
   double *sen;               // SEN_PLANES planes (SensorPlane)
-  unsigned long long *qmax;        // [4] max |Q_{alpha,k}| of this coarse step, as bits
-  unsigned long long *qmax_other;  // [4] the slot of the other coarse-step parity
-  const uint8_t *status;     // frame status: 0 none, 1 active, 2 hole
-  int32_t fx0, fy0, fw, fh, xoff;  // frame geometry (level cells)
-  int32_t Nx, Ny, per;       // level domain; per: bit 0 periodic in x, bit 1 in y
+  const uint8_t *mask;       // neighbour masks (mask_bit), `plane` bytes
+  unsigned long long *qmax;       // [4] max |Q_{alpha,k}| of this coarse step, as bits
+  unsigned long long *qmax_next;  // [4] the next coarse step's, accumulated by its last steps
+  int32_t clear_next;        // this phase is the context's first of the coarse step: clear qmax_next
+  int32_t emit_qmax;         // this phase is the level's last of the coarse step: accumulate qmax_next
+  int32_t fx0, fy0, xoff;    // frame origin (level cells)
+  int32_t Nx, Ny;            // level domain
   double c_sensor, beta_min, beta_max;
 };
 
@@ -162,10 +173,15 @@ struct RectArgs {
 // Launchers (kernels.hip). All return hipError_t of the launch.
 hipError_t launch_step(const StepLaunch &a, int fp32, hipStream_t s, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr);
-// Adaptive relaxation stage 0 (the coarse step's max |Q|, a launch over the
-// first-phase descriptors of every level) or stages 1..3 over the tiles of the
-// step launch `a` (same segments and descriptors), to run just before it.
+// Adaptive relaxation: stage 0 (W planes of every level and the coarse step's
+// max |Q| from the stored populations, over the first-phase descriptors of
+// every level; after any change of state) or stage 2 (activity and gate) over
+// the tiles of the step launch `a` (same segments and descriptors), to run
+// just before it.
 hipError_t launch_sensor(const StepLaunch &a, int stage, int fp32, hipStream_t s);
+// Neighbour masks of a level frame from its status (fw x fh bytes, 1 = active).
+hipError_t launch_sensor_mask(const uint8_t *status, uint8_t *mask, int fx0, int fy0, int fw, int fh,
+                              int pitch, int xoff, int Nx, int Ny, int per, hipStream_t s);
 hipError_t launch_audit(const void *buf, const Tile *tiles, int ntiles, int64_t plane,
                         int pitch, int fp32, double *partial, hipStream_t s);
 hipError_t launch_set_state(const RectArgs &a, int fp32, int raw_populations, hipStream_t s);
