@@ -1,0 +1,41 @@
+/* Plain FP64 CPU oracle of the three-dimensional D3Q6 VLBM with conservative
+ * local grid refinement -- TEST INFRASTRUCTURE ONLY (see vlbm3_oracle.c). */
+#ifndef VLBM3_ORACLE_H
+#define VLBM3_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC3_BC_PERIODIC 0
+#define ORC3_BC_OUTFLOW 1
+#define ORC3_BC_REFLECT 2
+
+typedef struct orc3 orc3;
+
+/* Populations: index q * 5 + k, q in (+x, -x, +y, -y, +z, -z), k in
+ * (rho, rho u, rho v, rho w, E). Level arrays are [comp][Nz][Ny][Nx]. */
+void orc3_flux(double gamma, const double W[5], double Qx[5], double Qy[5], double Qz[5]);
+void orc3_feq(double gamma, double c, const double W[5], double f[30]);
+void orc3_collide(double gamma, double c, double beta, const double g[30], double fstar[30]);
+
+/* bc[6]: sides -x, +x, -y, +y, -z, +z (periodic sides in pairs). */
+orc3 *orc3_new(int nx0, int ny0, int nz0, double dx0, int r, int nlev, double gamma, double c,
+               double beta, const int bc[6]);
+void orc3_free(orc3 *o);
+/* boxes[n][7] = (level, i0, j0, k0, nx, ny, nz) in level cells, whole parent cells. */
+int orc3_set_boxes(orc3 *o, const int *boxes, int nboxes);
+int orc3_set_state(orc3 *o, int level, const double *U);   /* U[5][Nz][Ny][Nx]: covered cells */
+int orc3_set_pop(orc3 *o, int level, const double *F);     /* F[30][Nz][Ny][Nx] */
+int orc3_get_pop(const orc3 *o, int level, double *F);     /* NaN where not active */
+int orc3_get_state(const orc3 *o, int level, double *U);   /* NaN where not active */
+int orc3_active_mask(const orc3 *o, int level, unsigned char *mask);
+int orc3_advance(orc3 *o, int ncoarse);
+void orc3_totals(const orc3 *o, double T[5], double ledger[5]);
+int orc3_shape(const orc3 *o, int level, int shape[3]);     /* (Nx, Ny, Nz) */
+const char *orc3_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

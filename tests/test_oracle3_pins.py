@@ -1,0 +1,295 @@
+"""Pins of the three-dimensional (D3Q6) FP64 oracle against what the paper and
+the mathematics fix. CPU only; each test names the passage it follows."""
+import numpy as np
+import pytest
+
+from oracle import oracle3 as O3
+from tests import exact
+
+RNG = np.random.default_rng(2026)
+
+
+def _random_W(n, rng):
+    rho = rng.uniform(0.3, 2.5, n)
+    u, v, w = (rng.uniform(-1.2, 1.2, n) for _ in range(3))
+    p = rng.uniform(0.2, 2.5, n)
+    return _cons(rho, u, v, w, p).T
+
+
+def _cons(rho, u, v, w, p, gamma=1.4):
+    return np.stack([rho, rho * u, rho * v, rho * w,
+                     p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)])
+
+
+def _random_state(nz, ny, nx, rng, amp=0.15):
+    """A smooth-ish random state: a uniform base plus low modes and noise."""
+    z, y, x = np.meshgrid(np.arange(nz) / nz, np.arange(ny) / ny, np.arange(nx) / nx, indexing="ij")
+    f = lambda a, b, c: np.sin(2 * np.pi * (a * x + b * y + c * z) + rng.uniform(0, 6.3))
+    rho = 1.0 + amp * f(1, 0, 1) + 0.02 * rng.normal(size=x.shape)
+    u = 0.3 * f(0, 1, 1)
+    v = -0.2 * f(1, 1, 0)
+    w = 0.25 * f(1, 0, 0)
+    p = 1.0 + amp * f(0, 1, 0)
+    return _cons(rho, u, v, w, p)
+
+
+def _prolong(U, r):
+    return U.repeat(r, axis=1).repeat(r, axis=2).repeat(r, axis=3)
+
+
+def _oracle(U0, nlev=1, boxes=(), r=2, c=4.0, beta=0.8, bc=(0,) * 6, fine=None):
+    nz, ny, nx = U0.shape[1:]
+    o = O3.Oracle3(nx, ny, nz, 1.0 / nx, r=r, nlev=nlev, c=c, beta=beta, bc=bc)
+    o.set_boxes(boxes)
+    o.set_state(0, U0)
+    for l in range(1, nlev):
+        o.set_state(l, fine[l - 1] if fine else _prolong(U0, r ** l))
+    return o
+
+
+# ----------------------------------------------------------- single cell (Sec. 2.2)
+def test_equilibrium_moments_and_flux():
+    """sum_i f_i^eq = W and sum_i c_i f_i^eq = Q(W) with W/(2D), D = 3
+    (eq. num-equilibrium); Q is the textbook 3-D Euler flux."""
+    c = 2.7
+    for W in _random_W(40, RNG):
+        f = O3.feq(W, 1.4, c)
+        assert np.allclose(f.sum(axis=0), W, rtol=0, atol=8e-16 * np.abs(W).max())
+        Q = O3.flux(W)
+        for a in range(3):
+            assert np.allclose(c * (f[2 * a] - f[2 * a + 1]), Q[a], rtol=0,
+                               atol=8e-16 * c * np.abs(Q).max())
+        rho, mx, my, mz, E = W
+        u, v, w = mx / rho, my / rho, mz / rho
+        p = 0.4 * (E - 0.5 * rho * (u * u + v * v + w * w))
+        want = np.array([[mx, mx * u + p, my * u, mz * u, (E + p) * u],
+                         [my, mx * v, my * v + p, mz * v, (E + p) * v],
+                         [mz, mx * w, my * w, mz * w + p, (E + p) * w]])
+        assert np.allclose(Q, want, rtol=1e-14, atol=1e-14)
+
+
+def test_collision_conserves_and_special_betas():
+    """Relaxation conserves W for any beta; beta = 1/2 gives f^eq, 0 the identity
+    (eq. num-relaxation)."""
+    for _ in range(50):
+        W = _random_W(1, RNG)[0]
+        g = O3.feq(W, 1.4, 3.0) + RNG.normal(0, 0.03, (6, 5))
+        Wg = g.sum(axis=0)
+        b = RNG.uniform(0.0, 1.0)
+        assert np.allclose(O3.collide(g, 1.4, 3.0, b).sum(axis=0), Wg, rtol=0,
+                           atol=4e-15 * (np.abs(g).sum(axis=0) + 1))
+    assert np.array_equal(O3.collide(g, 1.4, 3.0, 0.0), g)
+    assert np.allclose(O3.collide(g, 1.4, 3.0, 0.5), O3.feq(g.sum(axis=0), 1.4, 3.0), atol=1e-15)
+
+
+# ----------------------------------------------------------- streaming (Sec. 2.2)
+def test_streaming_is_an_exact_shift():
+    """beta = 0: one step shifts each population one cell along its axis; N
+    steps on a periodic N^3 grid return every value bitwise."""
+    n = 6
+    o = O3.Oracle3(n, n, n, 1.0 / n, nlev=1, c=2.0, beta=0.0)
+    F0 = RNG.normal(1.0, 0.1, (30, n, n, n))
+    o.set_pop(0, F0)
+    o.advance(1)
+    F1 = o.get_pop(0)
+    for q, (axis, s) in enumerate([(3, 1), (3, -1), (2, 1), (2, -1), (1, 1), (1, -1)]):
+        for k in range(5):
+            assert np.array_equal(F1[q * 5 + k], np.roll(F0[q * 5 + k], s, axis=axis - 1))
+    o.advance(n - 1)
+    assert np.array_equal(o.get_pop(0), F0)
+
+
+def _lax_friedrichs_3d(U, c, gamma=1.4):
+    rho, mx, my, mz, E = U
+    u, v, w = mx / rho, my / rho, mz / rho
+    p = (gamma - 1.0) * (E - 0.5 * rho * (u * u + v * v + w * w))
+    F = [np.stack([mx, mx * u + p, my * u, mz * u, (E + p) * u]),
+         np.stack([my, mx * v, my * v + p, mz * v, (E + p) * v]),
+         np.stack([mz, mx * w, my * w, mz * w + p, (E + p) * w])]
+    avg = sum(np.roll(U, s, axis=ax) for ax in (1, 2, 3) for s in (1, -1)) / 6.0
+    div = sum(np.roll(F[a], -1, axis=3 - a) - np.roll(F[a], 1, axis=3 - a) for a in range(3))
+    return avg - div / (2.0 * c)
+
+
+def test_beta_half_is_lax_friedrichs_3d():
+    """beta = 1/2: f* = f^eq(W) and one step is the 3-D Lax-Friedrichs scheme
+    with dt/dx = 1/c (eqs. num-equilibrium, num-relaxation)."""
+    n, c = 8, 3.0
+    U = _random_state(n, n, n, RNG)
+    o = _oracle(U, c=c, beta=0.5)
+    W = U.copy()
+    for _ in range(5):
+        o.advance(1)
+        W = _lax_friedrichs_3d(W, c)
+    assert np.allclose(o.get_state(0), W, rtol=0, atol=2e-13)
+
+
+# ----------------------------------------------------------- refinement (Sec. 3)
+BOX = [(1, 4, 4, 2, 8, 6, 8)]  # level-1 cells x 4..11, y 4..9, z 2..9 of 16 x 16 x 12
+
+
+def test_uniform_flow_is_preserved_through_a_patch():
+    n = (6, 8, 8)  # nz, ny, nx
+    U = _cons(*(np.full(n, v) for v in (1.3, 0.4, -0.3, 0.2, 0.9)))
+    o = _oracle(U, nlev=2, boxes=BOX, c=4.0, beta=0.9)
+    o.advance(6)
+    for l in range(2):
+        S = o.get_state(l)
+        m = o.active_mask(l)
+        assert np.allclose(S[:, m], U[:, :1, :1, :1].reshape(5, 1), rtol=0, atol=2e-14)
+
+
+@pytest.mark.parametrize("beta,c", [(0.6, 4.0), (0.95, 6.0)])
+def test_conservation_periodic_two_interfaces(beta, c):
+    """Totals stay constant to round-off across a refined patch for any beta and c
+    (Sec. 3.3, exact conservation of the coupling, one face at a time)."""
+    U = _random_state(6, 8, 8, RNG, amp=0.3)
+    o = _oracle(U, nlev=2, boxes=BOX, c=c, beta=beta)
+    T0, _ = o.totals()
+    o.advance(8)
+    T1, _ = o.totals()
+    scale = np.abs(T0) + 1e-3 * np.abs(T0).max()
+    assert np.all(np.abs(T1 - T0) / scale < 2e-14), (T1 - T0) / scale
+
+
+@pytest.mark.parametrize("bc", [(1,) * 6, (2,) * 6, (0, 0, 1, 1, 2, 2)])
+def test_boundary_ledger_balances(bc):
+    """Non-periodic sides: T(t) - T(0) equals the ledger of what crossed them."""
+    U = _random_state(6, 8, 8, RNG, amp=0.3)
+    o = _oracle(U, nlev=2, boxes=[(1, 0, 4, 2, 8, 6, 8)], c=4.0, beta=0.8, bc=bc)
+    T0, L0 = o.totals()
+    o.advance(6)
+    T1, L1 = o.totals()
+    scale = np.abs(T0).max()
+    assert np.all(np.abs((T1 - T0) - (L1 - L0)) <= 1e-14 * scale)
+
+
+def test_ratio_one_patch_is_the_uniform_grid_bitwise():
+    """r = 1: the hand-off returns the coarse value (a_k = b_j = 0) and the
+    reflux the fine value itself, so a partial patch changes nothing, bit for bit."""
+    U = _random_state(6, 8, 8, RNG, amp=0.3)
+    a = _oracle(U, nlev=1, r=1, c=4.0, beta=0.8)
+    b = _oracle(U, nlev=2, r=1, boxes=[(1, 2, 1, 1, 4, 5, 3)], c=4.0, beta=0.8, fine=[U])
+    a.advance(5)
+    b.advance(5)
+    Fa = a.get_pop(0)
+    Fb0, Fb1 = b.get_pop(0), b.get_pop(1)
+    m1 = b.active_mask(1)
+    assert m1.sum() == 4 * 5 * 3
+    assert np.array_equal(Fa[:, ~m1], Fb0[:, ~m1])
+    assert np.array_equal(Fa[:, m1], Fb1[:, m1])
+
+
+@pytest.mark.parametrize("shift", [3, 5])
+def test_periodic_translation_equivariance(shift):
+    """Translating state and boxes by whole coarse cells along x (periodic)
+    translates the result bit for bit: the patch wraps across the seam."""
+    U = _random_state(6, 8, 8, RNG, amp=0.3)
+    boxes = [(1, 10, 4, 2, 6, 6, 8)]
+    a = _oracle(U, nlev=2, boxes=boxes, c=4.0, beta=0.8)
+    Us = np.roll(U, shift, axis=3)
+    b = _oracle(Us, nlev=2, boxes=[(1, (10 + 2 * shift) % 16, 4, 2, 6, 6, 8)], c=4.0, beta=0.8)
+    if (10 + 2 * shift) % 16 + 6 > 16:
+        pytest.skip("shifted box would cross the seam")
+    a.advance(4)
+    b.advance(4)
+    for l, s in ((0, shift), (1, 2 * shift)):
+        assert np.array_equal(np.roll(a.get_pop(l), s, axis=3), b.get_pop(l), equal_nan=True), l
+
+
+def test_axis_permutation_equivariance():
+    """Relabelling the axes (x, y, z) -> (y, z, x), with momenta and boxes,
+    relabels the result (to round-off: the sums over populations run in
+    another order)."""
+    U = _random_state(8, 8, 8, RNG, amp=0.3)
+    box = (1, 4, 6, 2, 8, 6, 10)  # (level, i0, j0, k0, nx, ny, nz)
+    a = _oracle(U, nlev=2, boxes=[box], c=4.0, beta=0.8)
+    # new axes: x' = y, y' = z, z' = x; arrays are [k][z][y][x]
+    Up = np.transpose(U, (0, 3, 1, 2))[[0, 2, 3, 1, 4]]
+    boxp = (1, box[2], box[3], box[1], box[5], box[6], box[4])
+    b = _oracle(Up, nlev=2, boxes=[boxp], c=4.0, beta=0.8)
+    a.advance(4)
+    b.advance(4)
+    for l in range(2):
+        Sa = a.get_state(l)
+        Sb = b.get_state(l)
+        Sa_p = np.transpose(Sa, (0, 3, 1, 2))[[0, 2, 3, 1, 4]]
+        assert np.array_equal(np.isnan(Sa_p), np.isnan(Sb))
+        m = ~np.isnan(Sb)
+        assert np.allclose(Sa_p[m], Sb[m], rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_tangentially_linear_handoff_is_exact(axis):
+    """beta = 0 (pure transport), the populations along `axis` linear in the two
+    tangential coordinates and constant along `axis`, the others constant: the
+    fine level keeps the linear field exactly, so both tangential slopes of the
+    hand-off (eqs. 2d-recon-tanslope, 2d-recon, one per tangential axis) enter
+    with the right sign and offset on both faces normal to `axis`."""
+    n = 8
+    r = 2
+    co = (np.arange(n) + 0.5) / n
+    cf = (np.arange(n * r) + 0.5) / (n * r)
+    t = [a for a in range(3) if a != axis]
+    slope = {t[0]: 0.7, t[1]: -0.4}
+
+    def field(coords):  # coords: (z, y, x) meshes
+        val = 1.0
+        for a in t:
+            val = val + slope[a] * coords[2 - a]
+        return val
+
+    Zc, Yc, Xc = np.meshgrid(co, co, co, indexing="ij")
+    Zf, Yf, Xf = np.meshgrid(cf, cf, cf, indexing="ij")
+    F0 = np.full((30, n, n, n), 0.5)
+    F1 = np.full((30, n * r, n * r, n * r), 0.5)
+    for q in (2 * axis, 2 * axis + 1):
+        for k in range(5):
+            F0[q * 5 + k] = field((Zc, Yc, Xc)) * (1 + 0.1 * k)
+            F1[q * 5 + k] = field((Zf, Yf, Xf)) * (1 + 0.1 * k)
+    o = O3.Oracle3(n, n, n, 1.0 / n, r=r, nlev=2, c=2.0, beta=0.0, bc=(1,) * 6)
+    o.set_boxes([(1, 4, 4, 4, 8, 8, 8)])
+    o.set_pop(0, F0)
+    o.set_pop(1, F1)
+    o.advance(2)
+    G = o.get_pop(1)
+    m = o.active_mask(1)
+    for q in (2 * axis, 2 * axis + 1):
+        for k in range(5):
+            assert np.allclose(G[q * 5 + k][m], F1[q * 5 + k][m], rtol=0, atol=2e-15)
+
+
+def _sod_l1(n, axis):
+    """Sod along `axis` on n x 4 x 4 cells, c = 7.8125 (t = 0.2 after 0.2 c n
+    steps); returns the L1 density error and the profile."""
+    shape = [4, 4, 4]
+    shape[2 - axis] = n
+    coord = (np.arange(n) + 0.5) / n
+    x = coord.reshape([-1 if i == 2 - axis else 1 for i in range(3)]) * np.ones(shape)
+    z0 = np.zeros(shape)
+    U = _cons(np.where(x < 0.5, 1.0, 0.125), z0, z0, z0, np.where(x < 0.5, 1.0, 0.1))
+    bc = [0] * 6
+    bc[2 * axis] = bc[2 * axis + 1] = 1
+    c = 7.8125
+    o = O3.Oracle3(shape[2], shape[1], shape[0], 1.0 / n, nlev=1, c=c, beta=0.9, bc=tuple(bc))
+    o.set_state(0, U)
+    steps = int(round(0.2 * c * n))
+    o.advance(steps)
+    t = steps / (c * n)
+    line = np.moveaxis(o.get_state(0)[0], 2 - axis, 0).reshape(n, -1)
+    assert np.allclose(line, line[:, :1])  # uniform across the other two axes
+    rho_ex = exact.riemann_exact(np.array([1.0, 0.0, 1.0]), np.array([0.125, 0.0, 0.1]),
+                                 (coord - 0.5) / t)[0]
+    return float(np.mean(np.abs(line[:, 0] - rho_ex))), line[:, 0]
+
+
+def test_sod_along_each_axis_converges_and_agrees():
+    """The 1-D Sod problem carried along x, y or z: the L1 density error
+    against the exact Riemann solution falls with resolution, and the three
+    orientations give the same profile (to round-off)."""
+    e64, l64 = _sod_l1(64, 0)
+    e128, _ = _sod_l1(128, 0)
+    assert e128 < 0.75 * e64
+    for axis in (1, 2):
+        e, l = _sod_l1(64, axis)
+        assert np.allclose(l, l64, rtol=0, atol=1e-12)
