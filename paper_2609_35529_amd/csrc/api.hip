@@ -1966,6 +1966,14 @@ void cluster_hierarchy(vlbm_ctx *c, std::vector<TagMap> &tags, int buffer, int m
 extern "C" {
 
 const char *vlbm_last_error(void) { return g_err.c_str(); }
+}  // extern "C"
+
+// The three-dimensional path (api3.hip) reports through the same message.
+namespace vlbm {
+void set_error_message(const char *msg) { g_err = msg; }
+}  // namespace vlbm
+
+extern "C" {
 
 vlbm_status vlbm_create(const vlbm_params *params, void *stream, vlbm_ctx **out) {
   if (!params || !out) return fail(VLBM_EINVAL, "null argument");

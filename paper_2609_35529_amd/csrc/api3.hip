@@ -1,0 +1,981 @@
+// Host side of the three-dimensional (D3Q6) path of libvlbm: level frames,
+// tile and task lists, the recursive sub-cycle schedule and the C ABI declared
+// in include/vlbm3.h.
+//
+// Schedule (paper Sec. 3.2, Fig. 1): one coarse step of level l runs r steps
+// of level l+1, each recursively running level l+2, then advances level l.
+// Every level step is one launch of step3_kernel. Its workgroups fill the
+// ghost slots their own cells read: periodic images, boundary values, the
+// hand-off from the parent's two stored time levels (one tangential slope per
+// tangential axis) and the reflux average of the finer level's face values.
+// They also add this sub-step's outgoing face values into the parent's reflux
+// accumulators, then stream and relax their cells.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "../../include/vlbm3.h"
+#include "vlbm3_internal.hpp"
+
+namespace vlbm {
+void set_error_message(const char *msg);
+}
+
+using namespace vlbm3;
+
+namespace {
+
+vlbm_status fail3(vlbm_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  vlbm::set_error_message(buf);
+  return st;
+}
+
+#define HIPCHK3(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail3(VLBM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+  } while (0)
+
+constexpr int kL = VLBM3_MAX_LEVELS;
+const int E3[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+
+struct Level3 {
+  bool present = false;
+  int N[3] = {0, 0, 0};
+  double dx = 0.0;
+  int f0[3] = {0, 0, 0}, fn[3] = {0, 0, 0};  // frame origin and extent (bbox + ghost layer)
+  int pitch = 0, xoff = 0;
+  int64_t slab = 0, plane = 0;
+  void *buf[2] = {nullptr, nullptr};
+  std::vector<uint8_t> cov;     // per frame cell: covered at this level
+  std::vector<uint8_t> status;  // 0 none, 1 active, 2 hole
+  uint8_t *dstatus = nullptr;
+  std::vector<Tile3> tiles;
+  std::vector<Task3> tasks;
+  Tile3 *dtiles = nullptr;
+  Task3 *dtasks = nullptr;
+  double *dacc = nullptr;
+  int nacc = 0;
+  double *dledger = nullptr;
+  int nledger = 0;
+  double *dpartial = nullptr;
+  long steps = 0;
+
+  bool in_frame(const int p[3]) const {
+    for (int a = 0; a < 3; ++a)
+      if (p[a] < f0[a] || p[a] >= f0[a] + fn[a]) return false;
+    return true;
+  }
+  size_t fidx(const int p[3]) const {
+    return ((size_t)(p[2] - f0[2]) * fn[1] + (p[1] - f0[1])) * fn[0] + (p[0] - f0[0]);
+  }
+  int64_t off(const int p[3]) const {
+    return ((int64_t)(p[2] - f0[2]) * fn[1] + (p[1] - f0[1])) * pitch + (p[0] - f0[0]) + xoff;
+  }
+  int64_t stride(int a) const { return a == 0 ? 1 : a == 1 ? (int64_t)pitch : slab; }
+  int cur() const { return (int)(steps & 1); }
+};
+
+void dfree(void *&p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+template <class T>
+void dfree(T *&p) {
+  void *v = p;
+  dfree(v);
+  p = nullptr;
+}
+
+}  // namespace
+
+struct vlbm3_ctx {
+  vlbm3_params p{};
+  hipStream_t stream = nullptr;
+  Level3 lv[kL];
+  int nlev = 1;
+  bool have_hierarchy = false;
+  long coarse_steps = 0;
+  int tile_cells = 256;
+  int flags = 0;
+  double gm1 = 0, h = 0, tb = 0;
+  std::vector<vlbm3_box> boxes;
+  std::vector<std::pair<int, int>> phases;  // (level, k)
+  long flips[kL] = {};
+  Desc3 *ddesc = nullptr;
+  long table_base = 0;
+  bool prof = false;
+  std::vector<hipEvent_t> pev;
+  std::vector<std::pair<int, double>> pend;
+  double prof_ms[kL] = {}, prof_cells[kL] = {};
+  long prof_calls[kL] = {};
+
+  bool periodic(int a) const { return p.bc[2 * a] == VLBM_BC_PERIODIC; }
+  // wrap p (level l) by the periodic axes; false if outside a non-periodic side
+  bool wrap(int l, int q[3]) const {
+    for (int a = 0; a < 3; ++a) {
+      const int n = lv[l].N[a];
+      if (q[a] < 0 || q[a] >= n) {
+        if (!periodic(a)) return false;
+        q[a] = ((q[a] % n) + n) % n;
+      }
+    }
+    return true;
+  }
+  // q: in-domain coordinates of level l
+  bool covered(int l, const int q[3]) const {
+    if (l >= nlev || !lv[l].present) return false;
+    const Level3 &L = lv[l];
+    if (!L.in_frame(q)) return false;
+    return L.cov[L.fidx(q)] != 0;
+  }
+  bool active(int l, const int q[3]) const {
+    if (!covered(l, q)) return false;
+    const int r = p.r;
+    const int c[3] = {q[0] * r, q[1] * r, q[2] * r};
+    return !covered(l + 1, c);
+  }
+};
+
+namespace {
+
+void free_level3(Level3 &L) {
+  dfree(L.buf[0]);
+  dfree(L.buf[1]);
+  dfree(L.dstatus);
+  dfree(L.dtiles);
+  dfree(L.dtasks);
+  dfree(L.dacc);
+  dfree(L.dledger);
+  dfree(L.dpartial);
+  L = Level3();
+}
+
+void free_lists3(Level3 &L) {
+  dfree(L.dtiles);
+  dfree(L.dtasks);
+  dfree(L.dacc);
+  dfree(L.dledger);
+  dfree(L.dpartial);
+}
+
+vlbm_status check_params3(const vlbm3_params &p) {
+  if (p.nx0 < 1 || p.ny0 < 1 || p.nz0 < 1 || !(p.dx0 > 0) || p.r < 1 || p.r > 8 || p.max_levels < 1 ||
+      p.max_levels > kL || !(p.c > 0) || !(p.gamma > 1) || p.beta < 0 || p.beta > 1)
+    return fail3(VLBM_EINVAL, "bad parameters");
+  for (int a = 0; a < 3; ++a) {
+    const int b0 = p.bc[2 * a], b1 = p.bc[2 * a + 1];
+    if (b0 < 0 || b0 > 2 || b1 < 0 || b1 > 2) return fail3(VLBM_EINVAL, "bad boundary kind (3-D: periodic, outflow, reflect)");
+    if ((b0 == VLBM_BC_PERIODIC) != (b1 == VLBM_BC_PERIODIC))
+      return fail3(VLBM_EINVAL, "periodic sides must come in pairs");
+  }
+  return VLBM_OK;
+}
+
+struct Geom3 {
+  bool present[kL] = {};
+  int lo[kL][3], hi[kL][3];
+  int nlev = 1;
+};
+
+vlbm_status check_boxes3(const vlbm3_params &p, const vlbm3_box *boxes, int n, Geom3 &g) {
+  if (n < 0 || (n > 0 && !boxes)) return fail3(VLBM_EINVAL, "bad box list");
+  for (int l = 0; l < kL; ++l)
+    for (int a = 0; a < 3; ++a) {
+      g.lo[l][a] = 1 << 30;
+      g.hi[l][a] = -(1 << 30);
+    }
+  g.present[0] = true;
+  const int n0[3] = {p.nx0, p.ny0, p.nz0};
+  for (int a = 0; a < 3; ++a) {
+    g.lo[0][a] = 0;
+    g.hi[0][a] = n0[a];
+  }
+  g.nlev = 1;
+  for (int b = 0; b < n; ++b) {
+    const vlbm3_box &B = boxes[b];
+    if (B.level < 1 || B.level >= p.max_levels)
+      return fail3(VLBM_EINVAL, "box %d: level %d outside 1..%d", b, B.level, p.max_levels - 1);
+    long s = 1;
+    for (int i = 0; i < B.level; ++i) s *= p.r;
+    const int lo[3] = {B.i0, B.j0, B.k0}, ext[3] = {B.nx, B.ny, B.nz};
+    for (int a = 0; a < 3; ++a) {
+      if (ext[a] <= 0 || lo[a] < 0 || lo[a] + (long)ext[a] > n0[a] * s)
+        return fail3(VLBM_EINVAL, "box %d lies outside its level's domain", b);
+      if (lo[a] % p.r || ext[a] % p.r)
+        return fail3(VLBM_ENEST, "box %d is not made of whole parent cells (ratio %d)", b, p.r);
+    }
+    const int l = B.level;
+    g.present[l] = true;
+    g.nlev = std::max(g.nlev, l + 1);
+    for (int a = 0; a < 3; ++a) {
+      g.lo[l][a] = std::min(g.lo[l][a], lo[a]);
+      g.hi[l][a] = std::max(g.hi[l][a], lo[a] + ext[a]);
+    }
+  }
+  for (int l = 1; l < kL; ++l)
+    if (g.present[l] && !g.present[l - 1])
+      return fail3(VLBM_ENEST, "level %d has boxes but level %d has none", l, l - 1);
+  return VLBM_OK;
+}
+
+void frame3(const vlbm3_params &p, const Geom3 &g, int l, Level3 &L) {
+  long s = 1;
+  for (int i = 0; i < l; ++i) s *= p.r;
+  const int n0[3] = {p.nx0, p.ny0, p.nz0};
+  for (int a = 0; a < 3; ++a) L.N[a] = (int)(n0[a] * s);
+  L.dx = p.dx0 / (double)s;
+  L.present = g.present[l];
+  if (!L.present) return;
+  for (int a = 0; a < 3; ++a) {
+    L.f0[a] = g.lo[l][a] - 1;
+    L.fn[a] = g.hi[l][a] - g.lo[l][a] + 2;
+  }
+  // first interior column on a 128-byte line; rows padded to 64 elements;
+  // planes to a multiple of 4 KiB
+  L.xoff = 15;
+  L.pitch = (L.fn[0] + L.xoff + 63) / 64 * 64;
+  L.slab = (int64_t)L.pitch * L.fn[1];
+  L.plane = (L.slab * L.fn[2] + 511) / 512 * 512;
+}
+
+size_t level_bytes3(const Level3 &L) { return (size_t)L.plane * 30 * sizeof(double); }
+
+// What fills the slot from which active cell x of level l pulls population q
+// (returns false: an active cell of the same level, read in place).
+vlbm_status ghost_task3(const vlbm3_ctx *c, int l, const int x[3], int q, Task3 &t, bool &needed) {
+  const Level3 &L = c->lv[l];
+  const int r = c->p.r;
+  int s[3] = {x[0] - E3[q][0], x[1] - E3[q][1], x[2] - E3[q][2]};
+  int w[3] = {s[0], s[1], s[2]};
+  t = Task3{};
+  t.q = q;
+  t.n[0] = t.n[1] = t.n[2] = t.n[3] = -1;
+  if (!L.in_frame(s)) return fail3(VLBM_ENEST, "internal: ghost slot outside the frame");
+  t.dst = (int32_t)L.off(s);
+  needed = true;
+  if (!c->wrap(l, w)) {
+    const int side = q;  // +alpha enters through the -alpha side, -alpha through +alpha
+    t.kind = (c->p.bc[side] == VLBM_BC_OUTFLOW ? K3_OUTFLOW : K3_REFLECT) | K3_LEDGER;
+    t.src = (int32_t)L.off(x);
+    return VLBM_OK;
+  }
+  const int wc[3] = {w[0] * r, w[1] * r, w[2] * r};
+  if (c->covered(l + 1, wc)) {
+    t.kind = K3_REFLUX;
+    return VLBM_OK;
+  }
+  if (c->covered(l, w)) {
+    if (w[0] == s[0] && w[1] == s[1] && w[2] == s[2]) {
+      needed = false;
+      return VLBM_OK;
+    }
+    t.kind = K3_COPY;
+    t.src = (int32_t)L.off(w);
+    return VLBM_OK;
+  }
+  if (l == 0) return fail3(VLBM_ENEST, "internal: level-0 cell without a source");
+  const Level3 &PL = c->lv[l - 1];
+  int P[3] = {w[0] / r, w[1] / r, w[2] / r};
+  if (!c->active(l - 1, P)) return fail3(VLBM_ENEST, "level %d: parent ring cell inactive", l);
+  t.kind = K3_RECON;
+  t.src = (int32_t)PL.off(P);
+  const int n = q / 2;
+  int ti = 0;
+  for (int a = 0; a < 3; ++a) {
+    if (a == n) continue;
+    int m[3] = {P[0], P[1], P[2]}, pp[3] = {P[0], P[1], P[2]};
+    m[a] -= 1;
+    pp[a] += 1;
+    const bool have = c->wrap(l - 1, m) && c->wrap(l - 1, pp) && c->active(l - 1, m) && c->active(l - 1, pp);
+    if (have) {
+      t.n[2 * ti] = (int32_t)PL.off(m);
+      t.n[2 * ti + 1] = (int32_t)PL.off(pp);
+    }
+    const int j = x[a] - r * P[a];
+    if (ti == 0)
+      t.j1 = j;
+    else
+      t.j2 = j;
+    ++ti;
+  }
+  return VLBM_OK;
+}
+
+// Tiles of level l: per z-slab, runs of active cells along x (cut at
+// tile_cells), equal runs on consecutive rows stacked while the tile holds at
+// most tile_cells cells.
+void build_tiles3(vlbm3_ctx *c, int l, std::vector<int32_t> &owner) {
+  Level3 &L = c->lv[l];
+  L.tiles.clear();
+  owner.assign(L.status.size(), -1);
+  const int tc = c->tile_cells;
+  for (int z = L.f0[2] + 1; z < L.f0[2] + L.fn[2] - 1; ++z) {
+    std::map<std::pair<int, int>, int> open;  // (x0, w) -> tile growing on the previous row
+    for (int y = L.f0[1] + 1; y < L.f0[1] + L.fn[1] - 1; ++y) {
+      std::map<std::pair<int, int>, int> next;
+      int x = L.f0[0] + 1;
+      const int xe = L.f0[0] + L.fn[0] - 1;
+      while (x < xe) {
+        int p[3] = {x, y, z};
+        if (L.status[L.fidx(p)] != 1) {
+          ++x;
+          continue;
+        }
+        const int xa = x;
+        while (x < xe && x - xa < tc) {
+          int pp[3] = {x, y, z};
+          if (L.status[L.fidx(pp)] != 1) break;
+          ++x;
+        }
+        const int w = x - xa;
+        const std::pair<int, int> key{xa, w};
+        auto it = open.find(key);
+        int ti;
+        if (it != open.end() && (L.tiles[it->second].h + 1) * w <= tc) {
+          ti = it->second;
+          L.tiles[ti].h += 1;
+        } else {
+          Tile3 t{};
+          int q0[3] = {xa, y, z};
+          t.off0 = (int32_t)L.off(q0);
+          t.w = w;
+          t.h = 1;
+          L.tiles.push_back(t);
+          ti = (int)L.tiles.size() - 1;
+        }
+        next[key] = ti;
+        for (int xx = xa; xx < x; ++xx) {
+          int pp[3] = {xx, y, z};
+          owner[L.fidx(pp)] = ti;
+        }
+      }
+      open.swap(next);
+    }
+  }
+}
+
+struct RefluxKey3 {
+  int hole[3];  // hole cell H of level l (wrapped, in-domain)
+  int q;
+  int slot;
+};
+
+// Tiles, tasks, accumulator and ledger slots of every level (coarse to fine:
+// a level's reflux slots define the captures of the next finer level).
+vlbm_status build_lists3(vlbm3_ctx *c) {
+  std::vector<RefluxKey3> caps_from_parent;
+  const int r = c->p.r;
+  for (int l = 0; l < c->nlev; ++l) {
+    Level3 &L = c->lv[l];
+    std::vector<int32_t> owner;
+    build_tiles3(c, l, owner);
+    std::vector<std::vector<Task3>> per(L.tiles.size());
+    std::vector<RefluxKey3> refl;
+    L.nacc = 0;
+    L.nledger = 0;
+    for (size_t ti = 0; ti < L.tiles.size(); ++ti) {
+      const Tile3 &T = L.tiles[ti];
+      // tile cells: decode the first cell's coordinates once
+      const int64_t rel = T.off0 - L.xoff;
+      const int fz = (int)(rel / L.slab);
+      const int fy = (int)((rel - (int64_t)fz * L.slab) / L.pitch);
+      const int fx = (int)(rel - (int64_t)fz * L.slab - (int64_t)fy * L.pitch);
+      for (int cy = 0; cy < T.h; ++cy)
+        for (int cx = 0; cx < T.w; ++cx) {
+          const int x[3] = {L.f0[0] + fx + cx, L.f0[1] + fy + cy, L.f0[2] + fz};
+          bool interior = true;
+          for (int q = 0; q < 6 && interior; ++q) {
+            int s[3] = {x[0] - E3[q][0], x[1] - E3[q][1], x[2] - E3[q][2]};
+            if (!L.in_frame(s) || L.status[L.fidx(s)] != 1) interior = false;
+          }
+          if (interior) continue;
+          for (int q = 0; q < 6; ++q) {
+            Task3 t;
+            bool needed = false;
+            vlbm_status st = ghost_task3(c, l, x, q, t, needed);
+            if (st) return st;
+            if (!needed) continue;
+            const int kind = t.kind & 0xFF;
+            if (kind == K3_REFLUX) {
+              t.slot = L.nacc++;
+              int w[3] = {x[0] - E3[q][0], x[1] - E3[q][1], x[2] - E3[q][2]};
+              c->wrap(l, w);
+              refl.push_back({{w[0], w[1], w[2]}, q, t.slot});
+            } else if (kind == K3_OUTFLOW || kind == K3_REFLECT) {
+              t.slot = L.nledger++;
+            }
+            per[ti].push_back(t);
+          }
+        }
+    }
+    // captures of this level for the parent's reflux slots
+    if (l > 0) {
+      for (const RefluxKey3 &k : caps_from_parent) {
+        const int q = k.q, n = q / 2;
+        // the fine cells of hole H on its face towards the ring cell (which
+        // lies at H + e_q): normal index r-1 for a + population, 0 for -
+        int R0[3];
+        for (int a = 0; a < 3; ++a) R0[a] = k.hole[a] * r;
+        if (q % 2 == 0) R0[n] += r - 1;
+        int ta[2], nt = 0;
+        for (int a = 0; a < 3; ++a)
+          if (a != n) ta[nt++] = a;
+        if (!L.in_frame(R0)) return fail3(VLBM_ENEST, "internal: capture outside the fine frame");
+        Task3 t{};
+        t.kind = K3_CAPTURE;
+        t.q = q;
+        t.src = (int32_t)L.off(R0);
+        t.n[0] = (int32_t)L.stride(ta[1]);  // outer (raster order: the higher axis)
+        t.n[1] = (int32_t)L.stride(ta[0]);  // inner
+        t.n[2] = t.n[3] = -1;
+        t.slot = k.slot;
+        for (int a2 = 0; a2 < r; ++a2)
+          for (int b2 = 0; b2 < r; ++b2) {
+            int Rc[3] = {R0[0], R0[1], R0[2]};
+            Rc[ta[1]] += a2;
+            Rc[ta[0]] += b2;
+            if (!L.in_frame(Rc) || L.status[L.fidx(Rc)] != 1)
+              return fail3(VLBM_ENEST, "level %d: reflux face cell not active (nesting)", l);
+          }
+        const int32_t ti = owner[L.fidx(R0)];
+        if (ti < 0) return fail3(VLBM_ENEST, "internal: capture without a tile");
+        per[ti].push_back(t);
+      }
+    }
+    caps_from_parent.swap(refl);
+    L.tasks.clear();
+    for (size_t ti = 0; ti < L.tiles.size(); ++ti) {
+      L.tiles[ti].task0 = (int32_t)L.tasks.size();
+      L.tiles[ti].ntask = (int32_t)per[ti].size();
+      L.tasks.insert(L.tasks.end(), per[ti].begin(), per[ti].end());
+    }
+  }
+  if (!caps_from_parent.empty()) return fail3(VLBM_ENEST, "internal: reflux slots on the finest level");
+  return VLBM_OK;
+}
+
+template <class T>
+vlbm_status upload3(vlbm3_ctx *c, T *&dst, const std::vector<T> &v, size_t min_elems = 1) {
+  dfree(dst);
+  const size_t n = std::max(v.size(), min_elems);
+  HIPCHK3(hipMalloc((void **)&dst, sizeof(T) * n));
+  if (!v.empty()) HIPCHK3(hipMemcpyAsync(dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, c->stream));
+  return VLBM_OK;
+}
+
+vlbm_status upload_lists3(vlbm3_ctx *c) {
+  for (int l = 0; l < c->nlev; ++l) {
+    Level3 &L = c->lv[l];
+    vlbm_status st = upload3(c, L.dtiles, L.tiles);
+    if (!st) st = upload3(c, L.dtasks, L.tasks);
+    if (st) return st;
+    dfree(L.dacc);
+    dfree(L.dledger);
+    dfree(L.dpartial);
+    HIPCHK3(hipMalloc((void **)&L.dacc, sizeof(double) * 5 * std::max(1, L.nacc)));
+    HIPCHK3(hipMalloc((void **)&L.dledger, sizeof(double) * 5 * std::max(1, L.nledger)));
+    HIPCHK3(hipMalloc((void **)&L.dpartial, sizeof(double) * 5 * std::max<size_t>(1, L.tiles.size())));
+    HIPCHK3(hipMemsetAsync(L.dacc, 0, sizeof(double) * 5 * std::max(1, L.nacc), c->stream));
+    HIPCHK3(hipMemsetAsync(L.dledger, 0, sizeof(double) * 5 * std::max(1, L.nledger), c->stream));
+  }
+  HIPCHK3(hipStreamSynchronize(c->stream));
+  return VLBM_OK;
+}
+
+void schedule3(int l, int k, int nlev, int r, std::vector<std::pair<int, int>> &out) {
+  if (l + 1 < nlev)
+    for (int kk = 1; kk <= r; ++kk) schedule3(l + 1, kk, nlev, r, out);
+  out.push_back({l, k});
+}
+
+double ak3(int k, int r) { return (double)(2 * k - r - 1) / (double)(2 * r); }
+
+// Descriptors of every phase for the two parities of the coarse step count
+// relative to table_base (buffers alternate).
+vlbm_status build_tables3(vlbm3_ctx *c) {
+  c->phases.clear();
+  schedule3(0, 1, c->nlev, c->p.r, c->phases);
+  const size_t P = c->phases.size();
+  for (int l = 0; l < kL; ++l) c->flips[l] = 0;
+  for (const auto &ph : c->phases) c->flips[ph.first] += 1;
+  std::vector<Desc3> descs(2 * P);
+  for (int e = 0; e < 2; ++e) {
+    long st[kL];
+    for (int l = 0; l < kL; ++l) st[l] = c->lv[l].steps + e * c->flips[l];
+    for (size_t p = 0; p < P; ++p) {
+      const int l = c->phases[p].first;
+      const Level3 &L = c->lv[l];
+      Desc3 a{};
+      a.src = L.buf[st[l] & 1];
+      a.dst = L.buf[(st[l] + 1) & 1];
+      if (l > 0) {
+        const Level3 &PL = c->lv[l - 1];
+        a.pcur = PL.buf[st[l - 1] & 1];
+        a.pprev = PL.buf[(st[l - 1] + 1) & 1];
+        a.pplane = PL.plane;
+        a.acc_out = PL.dacc;
+      }
+      a.tiles = L.dtiles;
+      a.tasks = L.dtasks;
+      a.acc_in = L.dacc;
+      a.ledger = L.dledger;
+      a.plane = L.plane;
+      a.slab = L.slab;
+      a.pitch = L.pitch;
+      a.ntiles = (int32_t)L.tiles.size();
+      a.r = c->p.r;
+      a.rrr = (double)(c->p.r * c->p.r * c->p.r);
+      a.w3 = L.dx * L.dx * L.dx;
+      a.gm1 = c->gm1;
+      a.h = c->h;
+      a.tb = c->tb;
+      descs[e * P + p] = a;
+      st[l] += 1;
+    }
+  }
+  dfree(c->ddesc);
+  HIPCHK3(hipMalloc((void **)&c->ddesc, sizeof(Desc3) * descs.size()));
+  HIPCHK3(hipMemcpyAsync(c->ddesc, descs.data(), sizeof(Desc3) * descs.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK3(hipStreamSynchronize(c->stream));
+  c->table_base = c->coarse_steps;
+  return VLBM_OK;
+}
+
+vlbm_status prof_flush3(vlbm3_ctx *c) {
+  if (c->pend.empty()) return VLBM_OK;
+  HIPCHK3(hipEventSynchronize(c->pev[2 * c->pend.size() - 1]));
+  for (size_t i = 0; i < c->pend.size(); ++i) {
+    float ms = 0.f;
+    HIPCHK3(hipEventElapsedTime(&ms, c->pev[2 * i], c->pev[2 * i + 1]));
+    c->prof_ms[c->pend[i].first] += ms;
+    c->prof_calls[c->pend[i].first] += 1;
+    c->prof_cells[c->pend[i].first] += c->pend[i].second;
+  }
+  c->pend.clear();
+  return VLBM_OK;
+}
+
+vlbm_status coarse_step3(vlbm3_ctx *c) {
+  const int e = (int)((c->coarse_steps - c->table_base) & 1);
+  const size_t P = c->phases.size();
+  for (size_t p = 0; p < P; ++p) {
+    const int l = c->phases[p].first, k = c->phases[p].second;
+    Launch3 a{};
+    a.d = c->ddesc + e * P + p;
+    a.nblocks = (int32_t)c->lv[l].tiles.size();
+    a.first = k == 1;
+    a.flags = c->flags;
+    a.ak = ak3(k, c->p.r);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->prof) {
+      if (c->pend.size() >= 4096) {
+        vlbm_status st = prof_flush3(c);
+        if (st) return st;
+      }
+      const size_t i = 2 * c->pend.size();
+      while (c->pev.size() < i + 2) {
+        hipEvent_t ev;
+        HIPCHK3(hipEventCreate(&ev));
+        c->pev.push_back(ev);
+      }
+      e0 = c->pev[i];
+      e1 = c->pev[i + 1];
+      double cells = 0;
+      for (const Tile3 &t : c->lv[l].tiles) cells += (double)t.w * t.h;
+      c->pend.push_back({l, cells});
+    }
+    HIPCHK3(launch_step3(a, c->stream, e0, e1));
+  }
+  for (int l = 0; l < c->nlev; ++l) c->lv[l].steps += c->flips[l];
+  c->coarse_steps += 1;
+  return VLBM_OK;
+}
+
+vlbm_status check_rect3(vlbm3_ctx *c, int level, const int lo[3], const int ext[3]) {
+  if (!c || !c->have_hierarchy) return fail3(VLBM_ESTATE, "no hierarchy installed");
+  if (level < 0 || level >= c->p.max_levels) return fail3(VLBM_EINVAL, "bad level %d", level);
+  const Level3 &L = c->lv[level];
+  long s = 1;
+  for (int i = 0; i < level; ++i) s *= c->p.r;
+  const int n0[3] = {c->p.nx0, c->p.ny0, c->p.nz0};
+  for (int a = 0; a < 3; ++a)
+    if (lo[a] < 0 || ext[a] < 0 || lo[a] + (long)ext[a] > n0[a] * s)
+      return fail3(VLBM_EINVAL, "rectangle outside level %d", level);
+  (void)L;
+  return VLBM_OK;
+}
+
+vlbm_status rect_io3(vlbm3_ctx *c, int level, const int lo[3], const int ext[3], double *host, int ncomp,
+                     bool write, bool raw) {
+  vlbm_status st = check_rect3(c, level, lo, ext);
+  if (st) return st;
+  const size_t full = (size_t)ext[0] * ext[1] * ext[2];
+  if (!write)
+    for (size_t i = 0; i < full * ncomp; ++i) host[i] = NAN;
+  Level3 &L = c->lv[level];
+  if (!L.present || full == 0) return VLBM_OK;
+  // clip to the frame
+  int clo[3], cext[3], o[3];
+  for (int a = 0; a < 3; ++a) {
+    const int x0 = std::max(lo[a], L.f0[a]), x1 = std::min(lo[a] + ext[a], L.f0[a] + L.fn[a]);
+    if (x1 <= x0) return VLBM_OK;
+    clo[a] = x0;
+    cext[a] = x1 - x0;
+    o[a] = x0 - lo[a];
+  }
+  const size_t n = (size_t)cext[0] * cext[1] * cext[2];
+  double *stage = nullptr;
+  HIPCHK3(hipMalloc((void **)&stage, sizeof(double) * ncomp * n));
+  std::vector<double> tmp(ncomp * n);
+  Rect3 a{};
+  a.buf0 = write ? L.buf[0] : L.buf[L.cur()];
+  a.buf1 = L.buf[1];
+  a.status = L.dstatus;
+  a.stage = stage;
+  a.plane = L.plane;
+  a.slab = L.slab;
+  a.pitch = L.pitch;
+  a.xoff = L.xoff;
+  a.fx0 = L.f0[0];
+  a.fy0 = L.f0[1];
+  a.fz0 = L.f0[2];
+  a.fw = L.fn[0];
+  a.fh = L.fn[1];
+  a.x0 = clo[0];
+  a.y0 = clo[1];
+  a.z0 = clo[2];
+  a.nx = cext[0];
+  a.ny = cext[1];
+  a.nz = cext[2];
+  a.gm1 = c->gm1;
+  a.h = c->h;
+  auto hidx = [&](int k, int x, int y, int z) {
+    return (size_t)k * full + ((size_t)(z + o[2]) * ext[1] + (y + o[1])) * ext[0] + (x + o[0]);
+  };
+  hipError_t e = hipSuccess;
+  if (write) {
+    for (int k = 0; k < ncomp; ++k)
+      for (int z = 0; z < cext[2]; ++z)
+        for (int y = 0; y < cext[1]; ++y)
+          memcpy(&tmp[(size_t)k * n + ((size_t)z * cext[1] + y) * cext[0]], &host[hidx(k, 0, y, z)],
+                 sizeof(double) * cext[0]);
+    e = hipMemcpyAsync(stage, tmp.data(), sizeof(double) * ncomp * n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_set3(a, raw ? 1 : 0, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  } else {
+    e = launch_get3(a, ncomp == 30 ? 1 : 0, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(tmp.data(), stage, sizeof(double) * ncomp * n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess)
+      for (int k = 0; k < ncomp; ++k)
+        for (int z = 0; z < cext[2]; ++z)
+          for (int y = 0; y < cext[1]; ++y)
+            memcpy(&host[hidx(k, 0, y, z)], &tmp[(size_t)k * n + ((size_t)z * cext[1] + y) * cext[0]],
+                   sizeof(double) * cext[0]);
+  }
+  (void)hipFree(stage);
+  if (e != hipSuccess) return fail3(VLBM_EDEVICE, "state transfer: %s", hipGetErrorString(e));
+  return VLBM_OK;
+}
+
+vlbm_status restart_count3(vlbm3_ctx *c) {
+  c->table_base -= c->coarse_steps;  // keep the table parity while restarting the count
+  c->coarse_steps = 0;
+  for (int l = 0; l < c->nlev; ++l) {
+    Level3 &L = c->lv[l];
+    HIPCHK3(hipMemsetAsync(L.dledger, 0, sizeof(double) * 5 * std::max(1, L.nledger), c->stream));
+  }
+  return VLBM_OK;
+}
+
+void kadd3(double &s, double &cmp, double v) {
+  const double t = s + v;
+  if (std::fabs(s) >= std::fabs(v))
+    cmp += (s - t) + v;
+  else
+    cmp += (v - t) + s;
+  s = t;
+}
+
+}  // namespace
+
+extern "C" {
+
+vlbm_status vlbm3_create(const vlbm3_params *params, void *stream, vlbm3_ctx **out) {
+  if (!params || !out) return fail3(VLBM_EINVAL, "null argument");
+  vlbm_status st = check_params3(*params);
+  if (st) return st;
+  vlbm3_ctx *c = new vlbm3_ctx();
+  c->p = *params;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->gm1 = c->p.gamma - 1.0;
+  c->h = 1.0 / (2.0 * c->p.c);
+  c->tb = 2.0 * c->p.beta;
+  *out = c;
+  return VLBM_OK;
+}
+
+void vlbm3_destroy(vlbm3_ctx *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t ev : c->pev) (void)hipEventDestroy(ev);
+  for (int l = 0; l < kL; ++l) free_level3(c->lv[l]);
+  dfree(c->ddesc);
+  delete c;
+}
+
+size_t vlbm3_footprint_bytes(const vlbm3_params *params, const vlbm3_box *boxes, int nboxes) {
+  if (!params || check_params3(*params)) return 0;
+  Geom3 g;
+  if (check_boxes3(*params, boxes, nboxes, g)) return 0;
+  size_t total = 0;
+  for (int l = 0; l < g.nlev; ++l) {
+    Level3 L;
+    frame3(*params, g, l, L);
+    if (!L.present) continue;
+    const size_t cells = (size_t)L.fn[0] * L.fn[1] * L.fn[2];
+    total += 2 * level_bytes3(L) + cells;  // buffers and status
+    total += cells * 3;                    // tiles, tasks and slots (bounded estimate)
+  }
+  return total;
+}
+
+vlbm_status vlbm3_set_hierarchy(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
+  if (!c) return fail3(VLBM_EINVAL, "null context");
+  Geom3 g;
+  vlbm_status st = check_boxes3(c->p, boxes, nboxes, g);
+  if (st) return st;
+  HIPCHK3(hipStreamSynchronize(c->stream));
+  for (int l = 0; l < kL; ++l) free_level3(c->lv[l]);
+  c->have_hierarchy = false;
+  c->nlev = g.nlev;
+  for (int l = 0; l < kL; ++l) {
+    frame3(c->p, g, l, c->lv[l]);
+    if (c->lv[l].present && c->lv[l].plane >= (int64_t(1) << 31))
+      return fail3(VLBM_EINVAL, "level %d frame too large for 32-bit offsets", l);
+  }
+  // coverage (frame-indexed)
+  for (int l = 0; l < c->nlev; ++l) {
+    Level3 &L = c->lv[l];
+    L.cov.assign((size_t)L.fn[0] * L.fn[1] * L.fn[2], 0);
+    auto fill = [&](const int lo[3], const int ext[3]) {
+      for (int z = lo[2]; z < lo[2] + ext[2]; ++z)
+        for (int y = lo[1]; y < lo[1] + ext[1]; ++y) {
+          int p0[3] = {lo[0], y, z};
+          memset(&L.cov[L.fidx(p0)], 1, ext[0]);
+        }
+    };
+    if (l == 0) {
+      const int lo[3] = {0, 0, 0};
+      fill(lo, L.N);
+    } else {
+      for (int b = 0; b < nboxes; ++b)
+        if (boxes[b].level == l) {
+          const int lo[3] = {boxes[b].i0, boxes[b].j0, boxes[b].k0};
+          const int ext[3] = {boxes[b].nx, boxes[b].ny, boxes[b].nz};
+          fill(lo, ext);
+        }
+    }
+  }
+  // proper nesting: the parent of every covered cell and its face neighbours
+  const int r = c->p.r;
+  for (int b = 0; b < nboxes; ++b) {
+    const vlbm3_box &B = boxes[b];
+    const int l = B.level;
+    for (int pz = B.k0 / r; pz < (B.k0 + B.nz) / r; ++pz)
+      for (int py = B.j0 / r; py < (B.j0 + B.ny) / r; ++py)
+        for (int px = B.i0 / r; px < (B.i0 + B.nx) / r; ++px)
+          for (int d = -1; d < 6; ++d) {
+            int P[3] = {px + (d < 0 ? 0 : E3[d][0]), py + (d < 0 ? 0 : E3[d][1]), pz + (d < 0 ? 0 : E3[d][2])};
+            if (!c->wrap(l - 1, P)) continue;
+            if (!c->covered(l - 1, P)) {
+              for (int m = 0; m < kL; ++m) free_level3(c->lv[m]);
+              return fail3(VLBM_ENEST, "box %d: hierarchy not properly nested", b);
+            }
+          }
+  }
+  // status
+  for (int l = 0; l < c->nlev; ++l) {
+    Level3 &L = c->lv[l];
+    L.status.assign(L.cov.size(), 0);
+    for (int z = L.f0[2]; z < L.f0[2] + L.fn[2]; ++z)
+      for (int y = L.f0[1]; y < L.f0[1] + L.fn[1]; ++y)
+        for (int x = L.f0[0]; x < L.f0[0] + L.fn[0]; ++x) {
+          const int p[3] = {x, y, z};
+          const size_t i = L.fidx(p);
+          if (!L.cov[i]) continue;
+          const int ch[3] = {x * r, y * r, z * r};
+          L.status[i] = c->covered(l + 1, ch) ? 2 : 1;
+        }
+  }
+  st = build_lists3(c);
+  if (st) {
+    for (int m = 0; m < kL; ++m) free_level3(c->lv[m]);
+    return st;
+  }
+  for (int l = 0; l < c->nlev; ++l) {
+    Level3 &L = c->lv[l];
+    const size_t nb = level_bytes3(L);
+    HIPCHK3(hipMalloc(&L.buf[0], nb));
+    HIPCHK3(hipMalloc(&L.buf[1], nb));
+    HIPCHK3(hipMemsetAsync(L.buf[0], 0, nb, c->stream));
+    HIPCHK3(hipMemsetAsync(L.buf[1], 0, nb, c->stream));
+    HIPCHK3(hipMalloc((void **)&L.dstatus, L.status.size()));
+    HIPCHK3(hipMemcpyAsync(L.dstatus, L.status.data(), L.status.size(), hipMemcpyHostToDevice, c->stream));
+    L.steps = 0;
+  }
+  st = upload_lists3(c);
+  if (st) return st;
+  c->boxes.assign(boxes, boxes + nboxes);
+  c->have_hierarchy = true;
+  c->coarse_steps = 0;
+  return build_tables3(c);
+}
+
+vlbm_status vlbm3_set_state(vlbm3_ctx *c, int level, int i0, int j0, int k0, int nx, int ny, int nz,
+                            const double *U) {
+  if (!U) return fail3(VLBM_EINVAL, "null U");
+  const int lo[3] = {i0, j0, k0}, ext[3] = {nx, ny, nz};
+  vlbm_status st = rect_io3(c, level, lo, ext, const_cast<double *>(U), 5, true, false);
+  return st ? st : restart_count3(c);
+}
+
+vlbm_status vlbm3_set_populations(vlbm3_ctx *c, int level, int i0, int j0, int k0, int nx, int ny, int nz,
+                                  const double *F) {
+  if (!F) return fail3(VLBM_EINVAL, "null F");
+  const int lo[3] = {i0, j0, k0}, ext[3] = {nx, ny, nz};
+  vlbm_status st = rect_io3(c, level, lo, ext, const_cast<double *>(F), 30, true, true);
+  return st ? st : restart_count3(c);
+}
+
+vlbm_status vlbm3_get_state(vlbm3_ctx *c, int level, int i0, int j0, int k0, int nx, int ny, int nz,
+                            double *U) {
+  if (!U) return fail3(VLBM_EINVAL, "null U");
+  const int lo[3] = {i0, j0, k0}, ext[3] = {nx, ny, nz};
+  return rect_io3(c, level, lo, ext, U, 5, false, false);
+}
+
+vlbm_status vlbm3_get_populations(vlbm3_ctx *c, int level, int i0, int j0, int k0, int nx, int ny, int nz,
+                                  double *F) {
+  if (!F) return fail3(VLBM_EINVAL, "null F");
+  const int lo[3] = {i0, j0, k0}, ext[3] = {nx, ny, nz};
+  return rect_io3(c, level, lo, ext, F, 30, false, false);
+}
+
+vlbm_status vlbm3_advance(vlbm3_ctx *c, int n) {
+  if (!c || !c->have_hierarchy) return fail3(VLBM_ESTATE, "no hierarchy installed");
+  if (n < 0) return fail3(VLBM_EINVAL, "negative step count");
+  for (int i = 0; i < n; ++i) {
+    vlbm_status st = coarse_step3(c);
+    if (st) return st;
+  }
+  return VLBM_OK;
+}
+
+vlbm_status vlbm3_conserved_totals(vlbm3_ctx *c, double totals[5], double ledger[5]) {
+  if (!c || !c->have_hierarchy) return fail3(VLBM_ESTATE, "no hierarchy installed");
+  if (!totals) return fail3(VLBM_EINVAL, "null totals");
+  double s[5] = {}, cs[5] = {}, ls[5] = {}, lc[5] = {};
+  for (int l = 0; l < c->nlev; ++l) {
+    Level3 &L = c->lv[l];
+    const int nt = (int)L.tiles.size();
+    HIPCHK3(launch_audit3(L.buf[L.cur()], L.dtiles, nt, L.plane, L.pitch, L.dpartial, c->stream));
+    std::vector<double> part(5 * (size_t)std::max(nt, 1)), led(5 * (size_t)std::max(1, L.nledger));
+    if (nt) HIPCHK3(hipMemcpyAsync(part.data(), L.dpartial, sizeof(double) * 5 * nt, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK3(hipMemcpyAsync(led.data(), L.dledger, sizeof(double) * led.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK3(hipStreamSynchronize(c->stream));
+    const double w3 = L.dx * L.dx * L.dx;
+    for (int k = 0; k < 5; ++k) {
+      double sl = 0.0, cl = 0.0;
+      for (int t = 0; t < nt; ++t) kadd3(sl, cl, part[5 * (size_t)t + k]);
+      kadd3(s[k], cs[k], w3 * (sl + cl));
+      for (int t = 0; t < L.nledger; ++t) kadd3(ls[k], lc[k], led[5 * (size_t)t + k]);
+    }
+  }
+  for (int k = 0; k < 5; ++k) {
+    totals[k] = s[k] + cs[k];
+    if (ledger) ledger[k] = ls[k] + lc[k];
+  }
+  return VLBM_OK;
+}
+
+vlbm_status vlbm3_set_tuning(vlbm3_ctx *c, int tile_cells, int flags) {
+  if (!c) return fail3(VLBM_EINVAL, "null context");
+  if (tile_cells < 64 || tile_cells > 65536 || (flags & ~S3_NT_STORES))
+    return fail3(VLBM_EINVAL, "bad tuning (tile_cells %d, flags %d)", tile_cells, flags);
+  c->tile_cells = tile_cells;
+  c->flags = flags;
+  if (!c->have_hierarchy) return VLBM_OK;
+  HIPCHK3(hipStreamSynchronize(c->stream));
+  // the accumulators hold nothing between coarse steps and the ledger is
+  // carried through the rebuild
+  double led[5] = {}, tot[5];
+  vlbm_status st = vlbm3_conserved_totals(c, tot, led);
+  if (st) return st;
+  for (int l = 0; l < c->nlev; ++l) free_lists3(c->lv[l]);
+  st = build_lists3(c);
+  if (!st) st = upload_lists3(c);
+  if (st) return st;
+  // put the carried ledger into the first slot that exists
+  for (int l = 0; l < c->nlev; ++l)
+    if (c->lv[l].nledger > 0) {
+      HIPCHK3(hipMemcpy(c->lv[l].dledger, led, sizeof led, hipMemcpyHostToDevice));
+      break;
+    }
+  return build_tables3(c);  // descriptors for the current buffers
+}
+
+vlbm_status vlbm3_set_profiling(vlbm3_ctx *c, int enable) {
+  if (!c) return fail3(VLBM_EINVAL, "null context");
+  vlbm_status st = prof_flush3(c);
+  if (st) return st;
+  c->prof = enable != 0;
+  if (c->prof)
+    for (int i = 0; i < kL; ++i) {
+      c->prof_ms[i] = 0.0;
+      c->prof_calls[i] = 0;
+      c->prof_cells[i] = 0.0;
+    }
+  return VLBM_OK;
+}
+
+vlbm_status vlbm3_kernel_times(vlbm3_ctx *c, double *ms, long *calls, double *cells) {
+  if (!c || !ms || !calls || !cells) return fail3(VLBM_EINVAL, "null argument");
+  vlbm_status st = prof_flush3(c);
+  if (st) return st;
+  for (int i = 0; i < kL; ++i) {
+    ms[i] = c->prof_ms[i];
+    calls[i] = c->prof_calls[i];
+    cells[i] = c->prof_cells[i];
+  }
+  return VLBM_OK;
+}
+
+long vlbm3_active_cells(const vlbm3_ctx *c, int level) {
+  if (!c || !c->have_hierarchy || level < 0 || level >= kL || !c->lv[level].present) return 0;
+  long n = 0;
+  for (const Tile3 &t : c->lv[level].tiles) n += (long)t.w * t.h;
+  return n;
+}
+
+vlbm_status vlbm3_sync(vlbm3_ctx *c) {
+  if (!c) return fail3(VLBM_EINVAL, "null context");
+  HIPCHK3(hipStreamSynchronize(c->stream));
+  return VLBM_OK;
+}
+
+}  // extern "C"

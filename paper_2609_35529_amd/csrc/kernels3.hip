@@ -1,0 +1,316 @@
+// Device code of the three-dimensional (D3Q6) path of libvlbm, gfx950, FP64.
+//
+// `step3_kernel`: one workgroup per tile of active cells. It first executes the
+// tile's ghost and interface tasks (slots only its own cells read, reflux
+// captures), then, after one workgroup barrier, advances every cell: pull the
+// six inbound populations (exact shift, Sec. 2.2), relax them towards the
+// vectorial equilibrium (eqs. num-equilibrium with D = 3, num-relaxation) and
+// store the 30 post-collision values. Structure-of-arrays planes make every
+// load and store of a wavefront a contiguous run along x.
+//
+// Arithmetic contract (the oracle's order; built with -ffp-contract=off):
+//   W_k = ((((f_{0k} + f_{1k}) + f_{2k}) + f_{3k}) + f_{4k}) + f_{5k}
+//   u = m_x / rho, v = m_y / rho, w = m_z / rho
+//   p = (gamma - 1) (E - 0.5 ((m_x u + m_y v) + m_z w))
+//   Q_x = (m_x, m_x u + p, m_y u, m_z u, (E + p) u), Q_y, Q_z alike
+//   f^eq_{+-alpha,k} = W_k / 6 +- h Q_{alpha,k},  h = 1 / (2c)
+//   f*_{qk} = f_{qk} + 2 beta (f^eq_{qk} - f_{qk})
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include "vlbm3_internal.hpp"
+
+namespace vlbm3 {
+
+template <class S>
+using g1 = __attribute__((address_space(1))) S *;
+
+__device__ __forceinline__ void relax3(double g[30], double gm1, double h, double tb) {
+  double W[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k)
+    W[k] = ((((g[k] + g[5 + k]) + g[10 + k]) + g[15 + k]) + g[20 + k]) + g[25 + k];
+  const double rho = W[0], mx = W[1], my = W[2], mz = W[3], E = W[4];
+  const double u = mx / rho;
+  const double v = my / rho;
+  const double w = mz / rho;
+  const double p = gm1 * (E - 0.5 * ((mx * u + my * v) + mz * w));
+  const double Q[3][5] = {{mx, mx * u + p, my * u, mz * u, (E + p) * u},
+                          {my, mx * v, my * v + p, mz * v, (E + p) * v},
+                          {mz, mx * w, my * w, mz * w + p, (E + p) * w}};
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const double share = W[k] / 6.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double hq = h * Q[a][k];
+      double &fp = g[(2 * a) * 5 + k];
+      double &fm = g[(2 * a + 1) * 5 + k];
+      fp = fp + tb * ((share + hq) - fp);
+      fm = fm + tb * ((share - hq) - fm);
+    }
+  }
+}
+
+__device__ __forceinline__ double minmod3(double a, double b) {
+  if (a > 0.0 && b > 0.0) return a < b ? a : b;
+  if (a < 0.0 && b < 0.0) return a > b ? a : b;
+  return 0.0;
+}
+
+__device__ __forceinline__ void run_task3(const Desc3 &A, int first, double ak, const Task3 &t) {
+  double *S = static_cast<double *>(A.src);
+  const int64_t P = A.plane;
+  const int q = t.q;
+  switch (t.kind & 0xFF) {
+    case K3_COPY:
+#pragma unroll
+      for (int k = 0; k < 5; ++k) S[(q * 5 + k) * P + t.dst] = S[(q * 5 + k) * P + t.src];
+      break;
+    case K3_OUTFLOW:
+    case K3_REFLECT: {
+      const int qo = q ^ 1;
+      const int kn = 1 + (q >> 1);  // momentum component along the side's normal
+      const bool refl = (t.kind & 0xFF) == K3_REFLECT;
+      const bool book = (t.kind & K3_LEDGER) != 0;
+      double *L = A.ledger + 5 * (int64_t)t.slot;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        double vin;
+        if (refl) {
+          const double w = S[(qo * 5 + k) * P + t.src];
+          vin = (k == kn) ? -w : w;
+        } else {
+          vin = S[(q * 5 + k) * P + t.src];
+        }
+        S[(q * 5 + k) * P + t.dst] = vin;
+        if (book) {
+          const double out = S[(qo * 5 + k) * P + t.src];
+          const double l = L[k] + A.w3 * vin;
+          L[k] = l + (-1.0) * (A.w3 * out);
+        }
+      }
+      break;
+    }
+    case K3_RECON: {
+      const double *C = static_cast<const double *>(A.pcur);
+      const double *Pv = static_cast<const double *>(A.pprev);
+      const int64_t P2 = A.pplane;
+      const double b1 = (double)(2 * t.j1 - A.r + 1) / (double)(2 * A.r);
+      const double b2 = (double)(2 * t.j2 - A.r + 1) / (double)(2 * A.r);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const int64_t pl = (q * 5 + k) * P2;
+        const double out = C[pl + t.src];
+        const double prev = Pv[pl + t.src];
+        double v = out + (out - prev) * ak;
+        const double s1 = (t.n[0] >= 0) ? minmod3(out - C[pl + t.n[0]], C[pl + t.n[1]] - out) : 0.0;
+        v = v + s1 * b1;
+        const double s2 = (t.n[2] >= 0) ? minmod3(out - C[pl + t.n[2]], C[pl + t.n[3]] - out) : 0.0;
+        v = v + s2 * b2;
+        S[(q * 5 + k) * P + t.dst] = v;
+      }
+      break;
+    }
+    case K3_REFLUX:
+#pragma unroll
+      for (int k = 0; k < 5; ++k) S[(q * 5 + k) * P + t.dst] = A.acc_in[5 * (int64_t)t.slot + k] / A.rrr;
+      break;
+    case K3_CAPTURE: {
+      double *acc = A.acc_out + 5 * (int64_t)t.slot;
+      const int r = A.r;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        double s = first ? 0.0 : acc[k];
+        const int64_t base = (q * 5 + k) * P + t.src;
+        for (int a = 0; a < r; ++a)
+          for (int b = 0; b < r; ++b) s = s + S[base + (int64_t)a * t.n[0] + (int64_t)b * t.n[1]];
+        acc[k] = s;
+      }
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+template <bool NT>
+__global__ __launch_bounds__(256) void step3_kernel(Launch3 L) {
+  const Desc3 &A = *L.d;
+  const int tid = blockIdx.x;
+  // everything the cell loop needs is read before the first store
+  const int ntiles = A.ntiles;
+  if (tid >= ntiles) return;
+  const Tile3 tl = A.tiles[tid];
+  const auto s = (g1<const double>)A.src;
+  const auto d = (g1<double>)A.dst;
+  const int64_t P = A.plane, slab = A.slab;
+  const int pitch = A.pitch;
+  const double gm1 = A.gm1, h = A.h, tb = A.tb;
+  if (tl.ntask) {
+    for (int i = threadIdx.x; i < tl.ntask; i += blockDim.x) run_task3(A, L.first, L.ak, A.tasks[tl.task0 + i]);
+    __syncthreads();
+  }
+  const int n = tl.w * tl.h;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    const int cy = c / tl.w, cx = c - cy * tl.w;
+    const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
+    double g[30];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      g[k] = s[(0 * 5 + k) * P + o - 1];            // +x arrives from x - 1
+      g[5 + k] = s[(1 * 5 + k) * P + o + 1];        // -x from x + 1
+      g[10 + k] = s[(2 * 5 + k) * P + o - pitch];   // +y from y - 1
+      g[15 + k] = s[(3 * 5 + k) * P + o + pitch];   // -y from y + 1
+      g[20 + k] = s[(4 * 5 + k) * P + o - slab];    // +z from z - 1
+      g[25 + k] = s[(5 * 5 + k) * P + o + slab];    // -z from z + 1
+    }
+    relax3(g, gm1, h, tb);
+#pragma unroll
+    for (int i = 0; i < 30; ++i) {
+      if (NT)
+        __builtin_nontemporal_store(g[i], &d[i * P + o]);
+      else
+        d[i * P + o] = g[i];
+    }
+  }
+}
+
+hipError_t launch_step3(const Launch3 &a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  if (a.nblocks <= 0) return hipSuccess;
+  const dim3 grid(a.nblocks), block(256);
+  if (a.flags & S3_NT_STORES)
+    hipExtLaunchKernelGGL(step3_kernel<true>, grid, block, 0, s, ev0, ev1, 0, a);
+  else
+    hipExtLaunchKernelGGL(step3_kernel<false>, grid, block, 0, s, ev0, ev1, 0, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Conservation audit: per-tile compensated sums of sum_q f_{q,k}
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void neumaier3(double &s, double &c, double v) {
+  const double t = s + v;
+  if (fabs(s) >= fabs(v))
+    c += (s - t) + v;
+  else
+    c += (v - t) + s;
+  s = t;
+}
+
+__global__ __launch_bounds__(256) void audit3_kernel(const double *__restrict__ buf, const Tile3 *tiles,
+                                                     int64_t P, int pitch, double *partial) {
+  __shared__ double red[5][256];
+  const Tile3 tl = tiles[blockIdx.x];
+  double sm[5] = {0, 0, 0, 0, 0}, cc[5] = {0, 0, 0, 0, 0};
+  const int n = tl.w * tl.h;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    const int cy = c / tl.w, cx = c - cy * tl.w;
+    const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+#pragma unroll
+      for (int q = 0; q < 6; ++q) neumaier3(sm[k], cc[k], buf[(q * 5 + k) * P + o]);
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) red[k][threadIdx.x] = sm[k] + cc[k];
+  __syncthreads();
+  if (threadIdx.x < 5) {
+    const int k = threadIdx.x;
+    double s = 0.0, c = 0.0;
+    for (int i = 0; i < (int)blockDim.x; ++i) neumaier3(s, c, red[k][i]);
+    partial[5 * (int64_t)blockIdx.x + k] = s + c;
+  }
+}
+
+hipError_t launch_audit3(const void *buf, const Tile3 *tiles, int ntiles, int64_t plane, int pitch,
+                         double *partial, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(audit3_kernel, dim3(ntiles), dim3(256), 0, s, static_cast<const double *>(buf), tiles,
+                     plane, pitch, partial);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Rectangle copy-in (f^eq(U) or raw F into both buffers of covered cells) and
+// copy-out (W or F of active cells; NaN elsewhere)
+// ---------------------------------------------------------------------------
+__global__ void set3_kernel(Rect3 a, int raw) {
+  const int64_t n = (int64_t)a.nx * a.ny * a.nz;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int x = (int)(i % a.nx), y = (int)((i / a.nx) % a.ny), z = (int)(i / ((int64_t)a.nx * a.ny));
+  const int fx = a.x0 + x - a.fx0, fy = a.y0 + y - a.fy0, fz = a.z0 + z - a.fz0;
+  const uint8_t st = a.status[((int64_t)fz * a.fh + fy) * a.fw + fx];
+  if (st == 0) return;
+  const int64_t o = (int64_t)fz * a.slab + (int64_t)fy * a.pitch + fx + a.xoff;
+  double f[30];
+  if (raw) {
+#pragma unroll
+    for (int j = 0; j < 30; ++j) f[j] = a.stage[j * n + i];
+  } else {
+    double W[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) W[k] = a.stage[k * n + i];
+    const double rho = W[0], mx = W[1], my = W[2], mz = W[3], E = W[4];
+    const double u = mx / rho;
+    const double v = my / rho;
+    const double w = mz / rho;
+    const double p = a.gm1 * (E - 0.5 * ((mx * u + my * v) + mz * w));
+    const double Q[3][5] = {{mx, mx * u + p, my * u, mz * u, (E + p) * u},
+                            {my, mx * v, my * v + p, mz * v, (E + p) * v},
+                            {mz, mx * w, my * w, mz * w + p, (E + p) * w}};
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const double share = W[k] / 6.0;
+#pragma unroll
+      for (int al = 0; al < 3; ++al) {
+        f[(2 * al) * 5 + k] = share + a.h * Q[al][k];
+        f[(2 * al + 1) * 5 + k] = share - a.h * Q[al][k];
+      }
+    }
+  }
+  double *b0 = static_cast<double *>(a.buf0), *b1 = static_cast<double *>(a.buf1);
+#pragma unroll
+  for (int j = 0; j < 30; ++j) {
+    b0[j * a.plane + o] = f[j];
+    b1[j * a.plane + o] = f[j];
+  }
+}
+
+__global__ void get3_kernel(Rect3 a, int pops) {
+  const int64_t n = (int64_t)a.nx * a.ny * a.nz;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int x = (int)(i % a.nx), y = (int)((i / a.nx) % a.ny), z = (int)(i / ((int64_t)a.nx * a.ny));
+  const int fx = a.x0 + x - a.fx0, fy = a.y0 + y - a.fy0, fz = a.z0 + z - a.fz0;
+  const bool act = a.status[((int64_t)fz * a.fh + fy) * a.fw + fx] == 1;
+  const int64_t o = (int64_t)fz * a.slab + (int64_t)fy * a.pitch + fx + a.xoff;
+  const double *b = static_cast<const double *>(a.buf0);
+  if (pops) {
+    for (int j = 0; j < 30; ++j) a.stage[j * n + i] = act ? b[j * a.plane + o] : __builtin_nan("");
+  } else {
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+      a.stage[k * n + i] =
+          act ? ((((b[(0 * 5 + k) * a.plane + o] + b[(1 * 5 + k) * a.plane + o]) + b[(2 * 5 + k) * a.plane + o]) +
+                  b[(3 * 5 + k) * a.plane + o]) + b[(4 * 5 + k) * a.plane + o]) + b[(5 * 5 + k) * a.plane + o]
+              : __builtin_nan("");
+  }
+}
+
+hipError_t launch_set3(const Rect3 &a, int raw, hipStream_t s) {
+  const int64_t n = (int64_t)a.nx * a.ny * a.nz;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(set3_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, raw);
+  return hipGetLastError();
+}
+
+hipError_t launch_get3(const Rect3 &a, int pops, hipStream_t s) {
+  const int64_t n = (int64_t)a.nx * a.ny * a.nz;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(get3_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, pops);
+  return hipGetLastError();
+}
+
+}  // namespace vlbm3

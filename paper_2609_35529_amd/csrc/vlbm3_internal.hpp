@@ -1,0 +1,87 @@
+// Internal definitions of the three-dimensional (D3Q6) path of libvlbm: work
+// descriptors shared by api3.hip and kernels3.hip.
+//
+// Data layout, per level l: one dense frame = bounding box of the level's
+// coverage plus a one-cell ghost layer. Buffer b in {0, 1} holds 30 planes
+// (q * 5 + k) of `plane` doubles; cell (x, y, z) of the level sits at element
+//   ((z - fz0) * fh + (y - fy0)) * pitch + (x - fx0) + xoff
+// of a plane, with rows of `pitch` elements (a multiple of 64) and the first
+// interior column on a 128-byte line. The current time level of l lives in
+// buf[steps_l & 1]; stored values are post-collision populations f*.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace vlbm3 {
+
+// Ghost and interface work executed by a tile's workgroup before its cells.
+enum TaskKind3 : int32_t {
+  K3_COPY = 0,      // ghost slot <- same-level cell (periodic image)
+  K3_OUTFLOW = 1,   // ghost slot <- the edge cell's own population q; ledger
+  K3_REFLECT = 2,   // ghost slot <- the edge cell's population q^1, normal momentum negated; ledger
+  K3_RECON = 3,     // ghost slot <- coarse-to-fine hand-off from the parent ring cell
+  K3_REFLUX = 4,    // hole slot  <- reflux accumulator / r^3
+  K3_CAPTURE = 5,   // reflux accumulator (=, or += after the first sub-step) of r^2 face cells
+  K3_LEDGER = 0x100,
+};
+
+struct Task3 {    // 48 bytes
+  int32_t kind;   // TaskKind3 (| K3_LEDGER)
+  int32_t q;      // population written (ghost kinds) or captured
+  int32_t dst;    // element offset of the ghost / hole slot in this level's planes
+  int32_t src;    // source cell (own level; parent level for RECON; first face cell for CAPTURE)
+  int32_t n[4];   // RECON: parent cells -+ e_t1, -+ e_t2 (-1: no slope); CAPTURE: outer, inner stride
+  int32_t j1, j2; // RECON: tangential indices of the fine cell in its parent (t1 < t2)
+  int32_t slot;   // REFLUX / CAPTURE: accumulator slot; boundary kinds: ledger slot
+  int32_t pad;
+};
+
+struct Tile3 {    // 32 bytes: w x h cells, rows of one z-slab
+  int32_t off0;   // element offset of the first cell
+  int32_t w, h;
+  int32_t task0, ntask;
+  int32_t pad[3];
+};
+
+struct Desc3 {
+  void *src, *dst;            // current and next buffer of the level
+  const void *pcur, *pprev;   // parent: current and previous buffers (RECON)
+  const Tile3 *tiles;
+  const Task3 *tasks;
+  double *acc_in;             // accumulators the finer level filled (REFLUX)
+  double *acc_out;            // the parent's accumulators (CAPTURE)
+  double *ledger;             // boundary ledger slots [slot][5]
+  int64_t plane, pplane, slab;
+  int32_t pitch, ntiles, r, pad;
+  double rrr;                 // r^3
+  double w3;                  // dx_l^3
+  double gm1, h, tb;          // gamma - 1, 1/(2c), 2 beta
+};
+
+enum StepFlags3 : int32_t { S3_NT_STORES = 1 };
+
+struct Launch3 {
+  const Desc3 *d;
+  int32_t nblocks, first, flags, pad;
+  double ak;                  // (2k - r - 1) / (2r)
+};
+
+struct Rect3 {
+  void *buf0, *buf1;          // set: both written; get: buf0 read
+  const uint8_t *status;      // frame status: 0 none, 1 active, 2 hole
+  double *stage;              // device staging [ncomp][nz][ny][nx]
+  int64_t plane, slab;
+  int32_t pitch, xoff, fx0, fy0, fz0, fw, fh;
+  int32_t x0, y0, z0, nx, ny, nz;
+  double gm1, h;
+};
+
+hipError_t launch_step3(const Launch3 &a, hipStream_t s, hipEvent_t ev0 = nullptr,
+                        hipEvent_t ev1 = nullptr);
+hipError_t launch_audit3(const void *buf, const Tile3 *tiles, int ntiles, int64_t plane, int pitch,
+                         double *partial, hipStream_t s);
+hipError_t launch_set3(const Rect3 &a, int raw_populations, hipStream_t s);
+hipError_t launch_get3(const Rect3 &a, int populations, hipStream_t s);
+
+}  // namespace vlbm3

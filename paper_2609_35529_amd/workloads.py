@@ -511,3 +511,143 @@ def request_case(req, beta=0.6, kappa=1.5, r=2):
         X, Y = level_grid(n0, n0, 1.0 / n0, r, l)
         states.append(_quadrant_ic(quadrant_states(req["seed"]), 1.4)(X, Y))
     return dataclasses.replace(case, nlev=nlev, boxes=boxes, states=states, name="request")
+
+
+# ------------------------------------------------ three dimensions (D3Q6)
+Box3 = Tuple[int, int, int, int, int, int, int]  # (level, i0, j0, k0, nx, ny, nz)
+
+
+@dataclasses.dataclass
+class Case3:
+    """A 3-D problem: base grid, static hierarchy, parameters and per-level
+    initial state U[5][Nz][Ny][Nx] (rho, rho u, rho v, rho w, E)."""
+    name: str
+    nx0: int
+    ny0: int
+    nz0: int
+    dx0: float
+    r: int
+    nlev: int
+    gamma: float
+    c: float
+    beta: float
+    bc: Tuple[int, int, int, int, int, int]
+    boxes: List[Box3]
+    states: List[Optional[np.ndarray]]  # states[l]: U of a block of level-l cells (None: unset)
+    steps: int
+    origins: Optional[List[Tuple[int, int, int]]] = None  # (i0, j0, k0) of states[l]; None: 0
+
+    def level_shape(self, level):
+        s = self.r ** level
+        return self.nz0 * s, self.ny0 * s, self.nx0 * s
+
+    def origin(self, level):
+        return tuple(self.origins[level]) if self.origins else (0, 0, 0)
+
+    def full_state(self, level):
+        """states[level] placed in a zero array over the whole level."""
+        U = np.zeros((5,) + self.level_shape(level))
+        i0, j0, k0 = self.origin(level)
+        S = self.states[level]
+        U[:, k0:k0 + S.shape[1], j0:j0 + S.shape[2], i0:i0 + S.shape[3]] = S
+        return U
+
+    def fine_equivalent_per_coarse_step(self):
+        """Cells of the finest level's resolution over the whole domain, times
+        the finest level's sub-steps per coarse step."""
+        s = self.r ** (self.nlev - 1)
+        return self.nx0 * self.ny0 * self.nz0 * s ** 3 * s
+
+    def actual_updates_per_coarse_step(self):
+        """sum_l (active cells of level l) * r^l, from the box volumes (boxes of a
+        level do not overlap)."""
+        vol = [self.nx0 * self.ny0 * self.nz0] + [0] * (self.nlev - 1)
+        for (lv, i0, j0, k0, nx, ny, nz) in self.boxes:
+            vol[lv] += nx * ny * nz
+        total = 0
+        for l in range(self.nlev):
+            act = vol[l] - (vol[l + 1] // self.r ** 3 if l + 1 < self.nlev else 0)
+            total += act * self.r ** l
+        return total
+
+
+def conserved3(rho, u, v, w, p, gamma=1.4):
+    return np.stack([rho, rho * u, rho * v, rho * w,
+                     p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)])
+
+
+def level_grid3(nx0, ny0, nz0, dx0, r, level):
+    """Cell-centre coordinates (Z, Y, X) of the whole level-l domain."""
+    s = r ** level
+    dx = dx0 / s
+    z = (np.arange(nz0 * s) + 0.5) * dx
+    y = (np.arange(ny0 * s) + 0.5) * dx
+    x = (np.arange(nx0 * s) + 0.5) * dx
+    return np.meshgrid(z, y, x, indexing="ij")
+
+
+def link_speed3(U, gamma=1.4, kappa=1.5):
+    rho = U[0]
+    vel = [U[1] / rho, U[2] / rho, U[3] / rho]
+    p = (gamma - 1.0) * (U[4] - 0.5 * rho * (vel[0] ** 2 + vel[1] ** 2 + vel[2] ** 2))
+    cs = np.sqrt(gamma * np.maximum(p, 0.0) / rho)
+    return kappa * 3 * float(max(np.max(np.abs(a) + cs) for a in vel))
+
+
+def prolong3(U, r):
+    return U.repeat(r, axis=1).repeat(r, axis=2).repeat(r, axis=3)
+
+
+def random_state3(nx, ny, nz, seed, gamma=1.4, amp=0.25):
+    """Seeded smooth random 3-D state: a uniform base, three low Fourier modes
+    per field and small cellwise noise."""
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid(np.arange(nz) / nz, np.arange(ny) / ny, np.arange(nx) / nx, indexing="ij")
+
+    def field(base, a):
+        f = np.full(x.shape, base)
+        for _ in range(3):
+            kx, ky, kz = rng.integers(0, 3, 3)
+            f = f + a * rng.uniform(-1, 1) * np.sin(2 * np.pi * (kx * x + ky * y + kz * z)
+                                                   + rng.uniform(0, 6.3))
+        return f + 0.02 * a * rng.normal(size=x.shape)
+
+    rho = np.maximum(field(1.0, amp), 0.3)
+    p = np.maximum(field(1.0, amp), 0.3)
+    return conserved3(rho, field(0.0, 0.3), field(0.0, 0.3), field(0.0, 0.3), p, gamma)
+
+
+def blast3d(n0=256, steps=100, refine=True, r=2, beta=0.8, kappa=1.5, bc=REFLECT):
+    """Spherical blast in the unit cube with reflecting walls (the 3-D
+    counterpart of the explosion in a box, Sec. 4.2): rho = p = 5 inside a
+    sphere of radius 0.2 centred at (0.45, 0.45, 0.45), 1 outside, at rest;
+    one r = 2 patch over the central half of the domain along every axis."""
+    gamma = 1.4
+    dx0 = 1.0 / n0
+
+    def ic(Z, Y, X):
+        inside = (X - 0.45) ** 2 + (Y - 0.45) ** 2 + (Z - 0.45) ** 2 < 0.2 ** 2
+        rho = np.where(inside, 5.0, 1.0)
+        p = np.where(inside, 5.0, 1.0)
+        return conserved3(rho, 0 * X, 0 * X, 0 * X, p, gamma)
+
+    nlev = 2 if refine else 1
+    boxes = []
+    origins = [(0, 0, 0)]
+    if refine:
+        a, b = (n0 // 4) * r, (3 * n0 // 4) * r
+        boxes = [(1, a, a, a, b - a, b - a, b - a)]
+        origins.append((a, a, a))
+    states = [ic(*level_grid3(n0, n0, n0, dx0, r, 0))]
+    for l in range(1, nlev):
+        # the patch's own cells only (a level-l array over the whole domain
+        # would be r^3 times the level-0 array)
+        (_, i0, j0, k0, nx, ny, nz) = boxes[l - 1]
+        dx = dx0 / r ** l
+        zc = (k0 + np.arange(nz) + 0.5) * dx
+        yc = (j0 + np.arange(ny) + 0.5) * dx
+        xc = (i0 + np.arange(nx) + 0.5) * dx
+        states.append(ic(*np.meshgrid(zc, yc, xc, indexing="ij")))
+    c = link_speed3(states[0], gamma, kappa)
+    return Case3("blast3d", n0, n0, n0, dx0, r, nlev, gamma, c, beta, (bc,) * 6, boxes, states, steps,
+                 origins)
