@@ -30,6 +30,7 @@ def lib():
                                C.c_double, C.c_double, C.c_double, _I]
         L.orc3_free.argtypes = [C.c_void_p]
         L.orc3_set_boxes.argtypes = [C.c_void_p, _I, C.c_int]
+        L.orc3_regrid.argtypes = [C.c_void_p, _I, C.c_int]
         for name in ("orc3_set_state", "orc3_set_pop", "orc3_get_pop", "orc3_get_state"):
             getattr(L, name).argtypes = [C.c_void_p, C.c_int, _D]
         L.orc3_active_mask.argtypes = [C.c_void_p, C.c_int, _U8]
@@ -95,6 +96,12 @@ class Oracle3:
         flat = [int(v) for b in boxes for v in b]
         arr = (C.c_int * max(1, len(flat)))(*flat)
         if lib().orc3_set_boxes(self._h, arr, len(boxes)):
+            raise RuntimeError("oracle3: " + lib().orc3_error().decode())
+
+    def regrid(self, boxes):
+        flat = [int(v) for b in boxes for v in b]
+        arr = (C.c_int * max(1, len(flat)))(*flat)
+        if lib().orc3_regrid(self._h, arr, len(boxes)):
             raise RuntimeError("oracle3: " + lib().orc3_error().decode())
 
     def set_state(self, level, U):

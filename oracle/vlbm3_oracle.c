@@ -217,8 +217,10 @@ int orc3_shape(const orc3 *o, int level, int shape[3]) {
   return 0;
 }
 
-int orc3_set_boxes(orc3 *o, const int *boxes, int nboxes) {
-  for (int l = 0; l < o->nlev; ++l) memset(o->cov[l], l == 0 ? 1 : 0, ncell(o, l));
+/* Coverage of every level from a box list into cov[], with the checks of
+ * orc3_set_boxes; 0 on success. */
+static int build_cov3(orc3 *o, const int *boxes, int nboxes, unsigned char **cov) {
+  for (int l = 0; l < o->nlev; ++l) memset(cov[l], l == 0 ? 1 : 0, ncell(o, l));
   for (int b = 0; b < nboxes; ++b) {
     const int *B = boxes + 7 * b;
     int l = B[0];
@@ -238,7 +240,7 @@ int orc3_set_boxes(orc3 *o, const int *boxes, int nboxes) {
     }
     for (int z = B[3]; z < B[3] + B[6]; ++z)
       for (int y = B[2]; y < B[2] + B[5]; ++y)
-        for (int x = B[1]; x < B[1] + B[4]; ++x) o->cov[l][cid(o, l, x, y, z)] = 1;
+        for (int x = B[1]; x < B[1] + B[4]; ++x) cov[l][cid(o, l, x, y, z)] = 1;
   }
   /* proper nesting: the parent of every covered cell and its six face
    * neighbours are covered one level up */
@@ -246,18 +248,25 @@ int orc3_set_boxes(orc3 *o, const int *boxes, int nboxes) {
     for (int z = 0; z < o->N[l][2]; ++z)
       for (int y = 0; y < o->N[l][1]; ++y)
         for (int x = 0; x < o->N[l][0]; ++x) {
-          if (!o->cov[l][cid(o, l, x, y, z)]) continue;
+          if (!cov[l][cid(o, l, x, y, z)]) continue;
           for (int d = -1; d < 6; ++d) {
             int p[3] = {x / o->r + (d < 0 ? 0 : C3X[d]), y / o->r + (d < 0 ? 0 : C3Y[d]),
                         z / o->r + (d < 0 ? 0 : C3Z[d])};
             if (!wrap3(o, l - 1, p)) continue;
-            if (!o->cov[l - 1][cid(o, l - 1, p[0], p[1], p[2])]) {
+            if (!cov[l - 1][cid(o, l - 1, p[0], p[1], p[2])]) {
               set_err3("hierarchy not properly nested");
-              for (int m = 1; m < o->nlev; ++m) memset(o->cov[m], 0, ncell(o, m));
               return -1;
             }
           }
         }
+  return 0;
+}
+
+int orc3_set_boxes(orc3 *o, const int *boxes, int nboxes) {
+  if (build_cov3(o, boxes, nboxes, o->cov) != 0) {
+    for (int m = 1; m < o->nlev; ++m) memset(o->cov[m], 0, ncell(o, m));
+    return -1;
+  }
   for (int l = 0; l < o->nlev; ++l) memset(o->pok[l], 0, ncell(o, l));
   return 0;
 }
@@ -500,4 +509,106 @@ void orc3_totals(const orc3 *o, double T[5], double ledger[5]) {
     T[k] = s + cs;
     if (ledger) ledger[k] = o->led[k] + o->ledc[k];
   }
+}
+
+/* ------------------------------------------------------------------ */
+/* Regrid: merge exiting cells (finest level first), then split         */
+/* entering cells (coarsest level first) -- Sec. 3.4, eqs. (amr-merge),  */
+/* (amr-slope), (amr-split) with D = 3                                   */
+/* ------------------------------------------------------------------ */
+
+/* eq. (amr-split), D = 3: child (a, b, g) along (x, y, z) of a parent with
+ * value fi and minmod slopes s[3] gets fi + s_x xi_a + s_y xi_b + s_z xi_g,
+ * added in axis order. */
+static double split3_value(int r, double fi, const double s[3], int a, int b, int g) {
+  double xa = (double)(2 * a - r + 1) / (double)(2 * r);
+  double xb = (double)(2 * b - r + 1) / (double)(2 * r);
+  double xg = (double)(2 * g - r + 1) / (double)(2 * r);
+  double v = fi + s[0] * xa;
+  v = v + s[1] * xb;
+  return v + s[2] * xg;
+}
+
+int orc3_regrid(orc3 *o, const int *boxes, int nboxes) {
+  const int L = o->nlev, r = o->r;
+  unsigned char *ncov[O3MAXL];
+  for (int l = 0; l < L; ++l) ncov[l] = (unsigned char *)malloc(ncell(o, l));
+  if (build_cov3(o, boxes, nboxes, ncov) != 0) {
+    for (int l = 0; l < L; ++l) free(ncov[l]);
+    return -1;
+  }
+  unsigned char **ocov = o->cov;
+  /* 1. merges, finest level first (eq. amr-merge): a parent whose r^3
+   *    children leave level l gets their plain average, summed in raster
+   *    order (z, y, x); both time levels get it. */
+  for (int l = L - 1; l >= 1; --l) {
+    const int *Np = o->N[l - 1];
+    for (int pz = 0; pz < Np[2]; ++pz)
+      for (int py = 0; py < Np[1]; ++py)
+        for (int px = 0; px < Np[0]; ++px) {
+          size_t c0 = cid(o, l, px * r, py * r, pz * r);
+          if (!ocov[l][c0] || ncov[l][c0]) continue;
+          size_t pc = cid(o, l - 1, px, py, pz);
+          for (int i = 0; i < 30; ++i) {
+            double sum = 0.0;
+            for (int g = 0; g < r; ++g)
+              for (int b = 0; b < r; ++b)
+                for (int a = 0; a < r; ++a)
+                  sum += o->F[l][pid(o, l, i, px * r + a, py * r + b, pz * r + g)];
+            double m = sum / (double)(r * r * r);
+            o->F[l - 1][(size_t)i * ncell(o, l - 1) + pc] = m;
+            o->Fp[l - 1][(size_t)i * ncell(o, l - 1) + pc] = m;
+          }
+        }
+  }
+  /* 2. splits, coarsest level first (eqs. amr-slope, amr-split): a slope
+   *    neighbour must be covered at level l in the new hierarchy and hold
+   *    data (not a hole before and after). */
+  for (int l = 0; l + 1 < L; ++l) {
+    const int *Np = o->N[l];
+    for (int pz = 0; pz < Np[2]; ++pz)
+      for (int py = 0; py < Np[1]; ++py)
+        for (int px = 0; px < Np[0]; ++px) {
+          size_t c0 = cid(o, l + 1, px * r, py * r, pz * r);
+          if (!ncov[l + 1][c0] || ocov[l + 1][c0]) continue;
+          size_t nb[6];
+          int avail[6];
+          for (int d = 0; d < 6; ++d) {
+            int q[3] = {px + C3X[d], py + C3Y[d], pz + C3Z[d]};
+            avail[d] = wrap3(o, l, q);
+            if (avail[d]) {
+              nb[d] = cid(o, l, q[0], q[1], q[2]);
+              int persistent_hole = 0;
+              if (l + 1 < L) {
+                size_t cc = cid(o, l + 1, q[0] * r, q[1] * r, q[2] * r);
+                persistent_hole = ocov[l + 1][cc] && ncov[l + 1][cc];
+              }
+              avail[d] = ncov[l][nb[d]] && !persistent_hole;
+            }
+          }
+          size_t pc = cid(o, l, px, py, pz), ncl = ncell(o, l);
+          for (int i = 0; i < 30; ++i) {
+            const double *F = o->F[l] + (size_t)i * ncl;
+            double fi = F[pc], sl[3];
+            for (int a = 0; a < 3; ++a)
+              sl[a] = (avail[2 * a] && avail[2 * a + 1]) ? minmod3(fi - F[nb[2 * a + 1]], F[nb[2 * a]] - fi) : 0.0;
+            for (int g = 0; g < r; ++g)
+              for (int b = 0; b < r; ++b)
+                for (int a = 0; a < r; ++a) {
+                  size_t ci = pid(o, l + 1, i, px * r + a, py * r + b, pz * r + g);
+                  double v = split3_value(r, fi, sl, a, b, g);
+                  o->F[l + 1][ci] = v;
+                  o->Fp[l + 1][ci] = v;
+                }
+          }
+        }
+  }
+  /* 3. adopt the new coverage; every interface restarts its temporal
+   *    reconstruction (no previous-step samples). */
+  for (int l = 0; l < L; ++l) {
+    memcpy(o->cov[l], ncov[l], ncell(o, l));
+    memset(o->pok[l], 0, ncell(o, l));
+    free(ncov[l]);
+  }
+  return 0;
 }

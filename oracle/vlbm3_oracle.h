@@ -31,6 +31,11 @@ int orc3_get_pop(const orc3 *o, int level, double *F);     /* NaN where not acti
 int orc3_get_state(const orc3 *o, int level, double *U);   /* NaN where not active */
 int orc3_active_mask(const orc3 *o, int level, unsigned char *mask);
 int orc3_advance(orc3 *o, int ncoarse);
+/* Replace the hierarchy, moving the state conservatively (Sec. 3.4): merge
+ * exiting cells finest level first, split entering cells coarsest level first
+ * (minmod slope per axis); every interface restarts its temporal
+ * reconstruction. */
+int orc3_regrid(orc3 *o, const int *boxes, int nboxes);
 void orc3_totals(const orc3 *o, double T[5], double ledger[5]);
 int orc3_shape(const orc3 *o, int level, int shape[3]);     /* (Nx, Ny, Nz) */
 const char *orc3_error(void);

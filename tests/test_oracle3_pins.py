@@ -293,3 +293,79 @@ def test_sod_along_each_axis_converges_and_agrees():
     for axis in (1, 2):
         e, l = _sod_l1(64, axis)
         assert np.allclose(l, l64, rtol=0, atol=1e-12)
+
+
+# ----------------------------------------------------------- regrid (Sec. 3.4)
+def test_regrid_conserves_through_moves_and_removal():
+    """Merges (eq. amr-merge, r^3 children) and splits (eqs. amr-slope,
+    amr-split, one slope per axis) conserve the totals exactly, through a
+    moved level-1 box, a new level-2 box and its removal."""
+    U = _random_state(6, 8, 8, RNG, amp=0.3)
+    o = _oracle(U, nlev=3, boxes=[(1, 4, 4, 2, 8, 6, 8)], c=4.0, beta=0.8)
+    o.advance(2)
+    seq = [[(1, 6, 4, 4, 8, 8, 6)],
+           [(1, 4, 2, 2, 10, 10, 8), (2, 12, 8, 8, 8, 8, 8)],
+           [(1, 0, 0, 0, 6, 6, 6)]]
+    T, _ = o.totals()
+    for boxes in seq:
+        o.regrid(boxes)
+        T1, _ = o.totals()
+        assert np.allclose(T1, T, rtol=1e-14, atol=1e-14 * np.abs(T).max()), boxes
+        o.advance(2)
+        T, _ = o.totals()
+
+
+def test_merge_of_split_returns_the_parent():
+    """Splitting a block into r^3 children and merging them back returns the
+    parent to round-off (the offsets sum to zero along every axis)."""
+    U = _random_state(6, 8, 8, RNG, amp=0.3)
+    o = _oracle(U, nlev=2, boxes=[], c=4.0, beta=0.8)
+    F0 = o.get_pop(0)
+    o.regrid([(1, 4, 4, 2, 8, 6, 8)])
+    o.regrid([])
+    F1 = o.get_pop(0)
+    assert np.allclose(F1, F0, rtol=4e-16, atol=4e-16 * np.abs(F0).max())
+
+
+def test_regrid_to_same_boxes_is_a_restart():
+    """A regrid that changes no box restarts every interface's temporal
+    reconstruction: equal, bit for bit, to a new run from the current
+    populations, and different from running on without it."""
+    U = _random_state(6, 8, 8, RNG, amp=0.3)
+    boxes = [(1, 4, 4, 2, 8, 6, 8)]
+    a = _oracle(U, nlev=2, boxes=boxes, c=4.0, beta=0.8)
+    b = _oracle(U, nlev=2, boxes=boxes, c=4.0, beta=0.8)
+    a.advance(3)
+    b.advance(3)
+    F = [a.get_pop(l) for l in range(2)]
+    fresh = O3.Oracle3(8, 8, 6, 1.0 / 8, r=2, nlev=2, c=4.0, beta=0.8)
+    fresh.set_boxes(boxes)
+    for l in range(2):
+        fresh.set_pop(l, np.nan_to_num(F[l]))
+    a.regrid(boxes)
+    a.advance(3)
+    b.advance(3)
+    fresh.advance(3)
+    for l in range(2):
+        assert np.array_equal(a.get_pop(l), fresh.get_pop(l), equal_nan=True), l
+    assert not np.array_equal(a.get_pop(1), b.get_pop(1), equal_nan=True)
+
+
+def test_split_of_linear_populations_is_exact():
+    """Populations linear in x, y and z split into children that sample the
+    same linear function at their own centres (to round-off)."""
+    n, r = 8, 2
+    co = (np.arange(n) + 0.5) / n
+    cf = (np.arange(n * r) + 0.5) / (n * r)
+    lin = lambda Z, Y, X, i: 1.0 + 0.3 * X - 0.2 * Y + 0.1 * Z + 0.01 * i
+    Zc, Yc, Xc = np.meshgrid(co, co, co, indexing="ij")
+    Zf, Yf, Xf = np.meshgrid(cf, cf, cf, indexing="ij")
+    F0 = np.stack([lin(Zc, Yc, Xc, i) for i in range(30)])
+    o = O3.Oracle3(n, n, n, 1.0 / n, r=r, nlev=2, c=2.0, beta=0.0, bc=(1,) * 6)
+    o.set_boxes([])
+    o.set_pop(0, F0)
+    o.regrid([(1, 4, 4, 4, 8, 8, 8)])
+    G = o.get_pop(1)
+    m = o.active_mask(1)
+    want = np.stack([lin(Zf, Yf, Xf, i) for i in range(30)])
+    assert np.allclose(G[:, m], want[:, m], rtol=0, atol=2e-15)
