@@ -55,6 +55,14 @@ def lib():
         L.orc_minmod.argtypes = [C.c_double, C.c_double]
         L.orc_recon_value.restype = C.c_double
         L.orc_recon_value.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int]
+        L.orc_recon_value_scaled.restype = C.c_double
+        L.orc_recon_value_scaled.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
+                                             C.c_int, C.c_double]
+        L.orc_set_time_stepping.argtypes = [C.c_void_p, C.c_int, C.c_double]
+        L.orc_time.restype = C.c_double
+        L.orc_time.argtypes = [C.c_void_p]
+        L.orc_link_speed.restype = C.c_double
+        L.orc_link_speed.argtypes = [C.c_void_p]
         L.orc_split_block.argtypes = [C.c_int, _D, _D]
         L.orc_merge_block.restype = C.c_double
         L.orc_merge_block.argtypes = [C.c_int, _D]
@@ -132,6 +140,17 @@ class Oracle:
         """Space/time-adaptive relaxation (eq. sensor-B), from the next step on."""
         if lib().orc_set_sensor(self._h, int(bool(on)), c_sensor, beta_min, beta_max):
             raise RuntimeError("oracle: " + lib().orc_error().decode())
+
+    def set_time_stepping(self, on=True, kappa=1.5):
+        """Adaptive time step: c per coarse step from the current state."""
+        if lib().orc_set_time_stepping(self._h, int(bool(on)), kappa):
+            raise RuntimeError("oracle: " + lib().orc_error().decode())
+
+    def time(self):
+        return lib().orc_time(self._h)
+
+    def link_speed(self):
+        return lib().orc_link_speed(self._h)
 
     def get_beta(self, level):
         """beta of every cell of `level` at its last step, (Ny, Nx); 0 where inactive."""

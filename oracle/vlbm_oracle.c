@@ -64,6 +64,11 @@ struct orc {
   double c_sensor, beta_min, beta_max;
   double *beta_f[OMAXL];             /* per-cell beta of the level's last step */
   double qmax[4];                    /* max |Q_{alpha,k}| of the current coarse step */
+  int adt;                           /* adaptive time step: c per coarse step */
+  double kd;                         /* kappa * D */
+  double c0;                         /* the parameter c (initial equilibria) */
+  double c_last[OMAXL];              /* c of each level's last step */
+  double time;                       /* elapsed time */
   int mut;
   int bc[4];
   double win[4][4];
@@ -147,13 +152,20 @@ double orc_minmod(double a, double b) {
   return 0.0;
 }
 
-/* eq. (2d-recon): out + (out - prev)(2k - r - 1)/(2r) + sigma (2j - r + 1)/(2r). */
-double orc_recon_value(double out, double prev, double sigma, int r, int k, int j) {
+/* eq. (2d-recon): out + (out - prev)(2k - r - 1)/(2r) + sigma (2j - r + 1)/(2r);
+ * with a time step that changed since the parent's previous step, the
+ * temporal term takes the ratio dt_now / dt_prev = c_prev / c_now. */
+double orc_recon_value_scaled(double out, double prev, double sigma, int r, int k, int j, double ratio) {
   double ak = (double)(2 * k - r - 1) / (double)(2 * r);
+  ak = ak * ratio;
   double bj = (double)(2 * j - r + 1) / (double)(2 * r);
   double B = out - prev;
   double v = out + B * ak;
   return v + sigma * bj;
+}
+
+double orc_recon_value(double out, double prev, double sigma, int r, int k, int j) {
+  return orc_recon_value_scaled(out, prev, sigma, r, k, j, 1.0);
 }
 
 /* eq. (amr-slope) and (amr-split) for one population component. fc is the
@@ -231,6 +243,8 @@ orc *orc_new(int nx0, int ny0, double dx0, int r, int nlev, double gamma, double
   o->dx0 = dx0;
   o->gamma = gamma;
   o->c = c;
+  o->c0 = c;
+  for (int l = 0; l < OMAXL; ++l) o->c_last[l] = c;
   o->beta = beta;
   for (int s = 0; s < 4; ++s) {
     o->bc[s] = bc[s];
@@ -384,7 +398,7 @@ int orc_set_state(orc *o, int level, int i0, int j0, int nx, int ny, const doubl
       if (!covered(o, level, gx, gy)) continue;
       double W[4], feq[16];
       for (int k = 0; k < 4; ++k) W[k] = U[k * plane + (size_t)y * ld + x];
-      orc_feq(o->gamma, o->c, o->eos, o->eos_a, o->eos_b, W, feq);
+      orc_feq(o->gamma, o->c0, o->eos, o->eos_a, o->eos_b, W, feq);
       for (int i = 0; i < 16; ++i) {
         o->F[level][pidx(o, level, i, gx, gy)] = feq[i];
         o->Fp[level][pidx(o, level, i, gx, gy)] = feq[i];
@@ -392,6 +406,7 @@ int orc_set_state(orc *o, int level, int i0, int j0, int nx, int ny, const doubl
       o->pok[level][cidx(o, level, gx, gy)] = 0;
     }
   for (int k = 0; k < 4; ++k) o->led[k] = o->ledc[k] = 0.0;
+  o->time = 0.0;
   return 0;
 }
 
@@ -509,7 +524,7 @@ static void recon(const orc *o, int l, int q, int kstep, int x, int y, int sx, i
       sigma = orc_minmod(out - fm, fp - out);
       if (o->mut == ORC_MUT_RECON_SIGMA_SIGN) sigma = -sigma;
     }
-    v[k] = orc_recon_value(out, prev, sigma, r, kstep, j);
+    v[k] = orc_recon_value_scaled(out, prev, sigma, r, kstep, j, o->c_last[lp] / o->c);
   }
 }
 
@@ -709,6 +724,7 @@ static void advance_level(orc *o, int l, int kstep) {
       for (int i = 0; i < 16; ++i) G[pidx(o, l, i, x, y)] = fs[i];
     }
 
+  o->c_last[l] = o->c;
   /* Rotate: previous <- current <- new. */
   double *old = o->Fp[l];
   o->Fp[l] = o->F[l];
@@ -746,13 +762,62 @@ static void level_cycle(orc *o, int l, int kstep) {
   advance_level(o, l, kstep);
 }
 
+/* Adaptive time step (acoustic scaling with a CFL-type link speed, read
+ * from the step counts of Sec. 4 and the adaptive time stepping the paper
+ * builds on): at the start of every coarse step
+ *   c_n = (kappa D) max over the active cells of every level and both axes of
+ *         |u_alpha| + c_s,  c_s = sqrt(gamma p / rho)  (ideal gas),
+ * the same c on every level (dt_l = dx_l / c_n); the coarse step lasts
+ * dx_0 / c_n. */
+static double link_speed_now(const orc *o) {
+  double m = 0.0;
+  for (int l = 0; l < o->nlev; ++l) {
+    const double *F = o->F[l];
+    for (int y = 0; y < o->Ny[l]; ++y)
+      for (int x = 0; x < o->Nx[l]; ++x) {
+        if (!active(o, l, x, y)) continue;
+        double W[4];
+        for (int k = 0; k < 4; ++k)
+          W[k] = ((F[pidx(o, l, 0 * 4 + k, x, y)] + F[pidx(o, l, 1 * 4 + k, x, y)]) +
+                  F[pidx(o, l, 2 * 4 + k, x, y)]) + F[pidx(o, l, 3 * 4 + k, x, y)];
+        double u = W[1] / W[0];
+        double v = W[2] / W[0];
+        double p = pressure(o->eos, o->gamma, o->eos_a, o->eos_b, W[0], W[1], W[2], W[3]);
+        double cs = sqrt((o->gamma * p) / W[0]);
+        double a = fabs(u) + cs, b = fabs(v) + cs;
+        double s = a > b ? a : b;
+        if (s > m) m = s;
+      }
+  }
+  return o->kd * m;
+}
+
 int orc_advance(orc *o, int ncoarse) {
   for (int n = 0; n < ncoarse; ++n) {
     if (o->sensor) sensor_qmax(o);
+    if (o->adt) o->c = link_speed_now(o);
     level_cycle(o, 0, 1);
+    o->time += o->dx0 / o->c;
   }
   return 0;
 }
+
+int orc_set_time_stepping(orc *o, int on, double kappa) {
+  if (on && !(kappa > 0.0)) {
+    set_err("orc_set_time_stepping: kappa must be positive");
+    return -1;
+  }
+  if (on && o->eos != ORC_EOS_IDEAL) {
+    set_err("orc_set_time_stepping: ideal gas only");
+    return -1;
+  }
+  o->adt = on;
+  o->kd = kappa * 2.0;
+  return 0;
+}
+
+double orc_time(const orc *o) { return o->time; }
+double orc_link_speed(const orc *o) { return o->c; }
 
 /* T_k = sum_l dx_l^2 sum_{active} sum_q f_{q,k}  (Sec. 4.1.2, 2-D form). */
 void orc_totals(const orc *o, double T[4], double ledger[4]) {

@@ -47,6 +47,12 @@ int orc_get_pop(const orc *o, int level, int i0, int j0, int nx, int ny, double 
 int orc_set_pop(orc *o, int level, int i0, int j0, int nx, int ny, const double *F, long ld);
 int orc_active_mask(const orc *o, int level, unsigned char *mask);
 int orc_advance(orc *o, int ncoarse);
+/* Adaptive time step: with on != 0, c = kappa * D * max(|u_alpha| + c_s) over
+ * the active cells of every level at the start of every coarse step (ideal
+ * gas only); the hand-off's temporal slope takes dt_now / dt_prev. */
+int orc_set_time_stepping(orc *o, int on, double kappa);
+double orc_time(const orc *o);        /* elapsed time since set_state */
+double orc_link_speed(const orc *o);  /* c of the last coarse step */
 void orc_totals(const orc *o, double T[4], double ledger[4]);
 int orc_tag(const orc *o, int level, double thr, unsigned char *tags);
 const char *orc_error(void);
@@ -60,6 +66,7 @@ void orc_collide(double gamma, double c, double beta, int eos, double a, double 
                  const double g[16], double fstar[16]);
 double orc_minmod(double a, double b);
 double orc_recon_value(double out, double prev, double sigma, int r, int k, int j);
+double orc_recon_value_scaled(double out, double prev, double sigma, int r, int k, int j, double ratio);
 void orc_split_block(int r, const double fc[3][3], double *children);
 double orc_merge_block(int r, const double *children);
 

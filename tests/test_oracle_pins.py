@@ -729,3 +729,106 @@ def test_sensor_lowers_beta_at_the_sod_shock():
     assert abs(xs[np.argmin(b)] - shock) <= 3 * case.dx0, (xs[np.argmin(b)], shock)
     assert b.min() < 0.7
     assert np.all(b[xs < 0.5 - 1.3 * t] > 0.94)           # undisturbed left state
+
+
+# ----------------------------------------------------------- adaptive time step
+def test_scaled_handoff_keeps_its_mean_for_any_ratio():
+    """The temporal term scaled by dt_now / dt_prev keeps the mean over the
+    r sub-steps equal to the coarse sample (the a_k sum to zero), so the
+    coupling stays exactly conservative under a changing time step."""
+    for _ in range(30):
+        out, prev, sig = RNG.normal(size=3)
+        ratio = RNG.uniform(0.5, 2.0)
+        for r in (2, 3, 4):
+            vals = [O.lib().orc_recon_value_scaled(out, prev, sig, r, k, j, ratio)
+                    for k in range(1, r + 1) for j in range(r)]
+            assert abs(np.mean(vals) - out) <= 8e-16 * (abs(out) + abs(prev) + abs(sig))
+
+
+def _cfl_speed(U, kd, gamma=1.4):
+    rho = U[0]
+    u, v = U[1] / rho, U[2] / rho
+    p = (gamma - 1) * (U[3] - 0.5 * (U[1] * u + U[2] * v))
+    cs = np.sqrt(gamma * p / rho)
+    return kd * float(np.nanmax(np.maximum(np.abs(u) + cs, np.abs(v) + cs)))
+
+
+def test_link_speed_is_the_cfl_bound_of_the_current_state():
+    """c_n = kappa D max(|u_alpha| + c_s) over the active cells of every level at
+    the start of the coarse step, checked against numpy on the oracle's own
+    state; the elapsed time grows by dx0 / c_n per coarse step."""
+    n = 16
+    U = wl.random_state_U(n, n, seed=21)
+    case = wl.Case("t", n, n, 1.0 / n, 2, 2, 1.4, 4.0, 0.8, (0,) * 4, [(1, 8, 8, 16, 16)],
+                   [U, wl.prolong_piecewise(U, 2)], 0)
+    o = _run(case, 0)
+    o.set_time_stepping(True, 1.5)
+    t = 0.0
+    for _ in range(4):
+        S = [o.get_state(l) for l in range(2)]
+        want = max(_cfl_speed(S[0], 3.0), _cfl_speed(S[1], 3.0))
+        o.advance(1)
+        assert abs(o.link_speed() - want) <= 4e-16 * want
+        t += case.dx0 / o.link_speed()
+        assert abs(o.time() - t) <= 1e-15 * t
+
+
+def test_steady_link_speed_reproduces_the_fixed_run():
+    """Uniform flow keeps c_n constant; the adaptive run then equals the run
+    with that c fixed, bit for bit, through two interfaces."""
+    n = 16
+    U0 = wl.conserved(np.full((n, n), 1.2), np.full((n, n), 0.3), np.full((n, n), -0.2),
+                      np.full((n, n), 0.9))
+    c_fix = _cfl_speed(U0, 3.0)
+    mk = lambda c: wl.Case("t", n, n, 1.0 / n, 2, 3, 1.4, c, 0.8, (0,) * 4,
+                           [(1, 8, 8, 16, 16), (2, 24, 24, 8, 8)],
+                           [U0, wl.prolong_piecewise(U0, 2), wl.prolong_piecewise(U0, 4)], 0)
+    a = _run(mk(c_fix), 0)
+    b = _run(mk(c_fix), 0)
+    b.set_time_stepping(True, 1.5)
+    a.advance(5)
+    b.advance(5)
+    assert b.link_speed() == c_fix
+    for l in range(3):
+        assert np.array_equal(a.get_pop(l), b.get_pop(l), equal_nan=True), l
+
+
+def test_conservation_with_a_changing_time_step():
+    """Totals stay exact to round-off through three levels while c changes
+    every coarse step (the paper: conservation independent of the time step)."""
+    n = 16
+    U = wl.random_state_U(n, n, seed=23)
+    case = wl.Case("t", n, n, 1.0 / n, 2, 3, 1.4, 4.0, 0.8, (0,) * 4,
+                   [(1, 8, 4, 16, 20), (2, 20, 12, 24, 20)],
+                   [U, wl.prolong_piecewise(U, 2), wl.prolong_piecewise(U, 4)], 0)
+    o = _run(case, 0)
+    o.set_time_stepping(True, 1.5)
+    T0, _ = o.totals()
+    cs = []
+    for _ in range(10):
+        o.advance(1)
+        cs.append(o.link_speed())
+    assert len(set(cs)) > 5  # the time step does change
+    T1, _ = o.totals()
+    scale = np.abs(T0) + 1e-3 * np.abs(T0).max()
+    assert np.all(np.abs(T1 - T0) / scale < 1e-13)
+
+
+def _sod_adaptive_l1(n):
+    case = wl.sod_2d(nx0=n, ny0=4, steps=0, refine=False)
+    o = _run(case, 0)
+    o.set_time_stepping(True, 1.5)
+    while o.time() < 0.2:
+        o.advance(1)
+    xs = (np.arange(n) + 0.5) / n
+    rho = o.get_state(0)[0].mean(axis=0)
+    rho_ex = exact.riemann_exact(np.array([1.0, 0.0, 1.0]), np.array([0.125, 0.0, 0.1]),
+                                 (xs - 0.5) / o.time())[0]
+    return float(np.mean(np.abs(rho - rho_ex)))
+
+
+def test_sod_with_adaptive_time_step_converges():
+    """Sod with c chosen every coarse step: the L1 density error against the
+    exact solution at the reached time falls with resolution."""
+    e64, e128, e256 = (_sod_adaptive_l1(n) for n in (64, 128, 256))
+    assert e128 < 0.8 * e64 and e256 < 0.8 * e128, (e64, e128, e256)
