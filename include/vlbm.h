@@ -232,6 +232,24 @@ vlbm_status vlbm_autotune(vlbm_ctx *ctx, int steps_per_trial, int *tile_cells, i
 vlbm_status vlbm_set_sensor(vlbm_ctx *ctx, int on, double c_sensor, double beta_min,
                             double beta_max);
 
+/* Adaptive time step (the acoustic scaling dx/dt = c kept on every level,
+ * with c chosen per coarse step; the paper builds on an adaptive time
+ * stepping for the VLBM and states that the coupling conserves for any time
+ * step). With on != 0, every coarse step starts with
+ *   c_n = 2 kappa max(|u_alpha| + c_s), c_s = sqrt(gamma p / rho),
+ * over the active cells of every level (a device reduction; no host sync),
+ * relaxes and hands off with h = 1/(2 c_n), and a hand-off whose parent last
+ * stepped in the previous coarse step scales its temporal slope by
+ * dt_now / dt_prev = c_prev / c_n. kappa > 0; ideal gas only (VLBM_EINVAL
+ * otherwise). set_state keeps building equilibria with vlbm_params.c; on = 0
+ * returns to it. Not taken by vlbm_batch_advance. */
+vlbm_status vlbm_set_time_stepping(vlbm_ctx *ctx, int on, double kappa);
+
+/* Elapsed time since set_state and the link speed of the last coarse step
+ * (either pointer may be NULL). With a fixed c, time = steps * dx0 / c.
+ * Synchronises. */
+vlbm_status vlbm_time(vlbm_ctx *ctx, double *time, double *link_speed);
+
 /* beta[ny][ld] (host) of the active level-l cells in the rectangle, as used
  * by the level's latest step with the adaptive relaxation on; other cells, and
  * every cell while it is off, get NaN (0 before the level's first step with

@@ -1,6 +1,7 @@
 /*
  * libvlbm, three-dimensional path: the D3Q6 vectorial lattice Boltzmann method
- * with conservative static local grid refinement, on one GPU (gfx950).
+ * with conservative local grid refinement (static hierarchies and regrid), on
+ * one GPU (gfx950).
  *
  * The method (paper):
  *   - Six populations f_i = +-c e_alpha (alpha = x, y, z), each carrying the
@@ -77,6 +78,16 @@ size_t vlbm3_footprint_bytes(const vlbm3_params *params, const vlbm3_box *boxes,
  * nested: the parent of every covered cell and its six face neighbours are
  * covered one level up (VLBM_ENEST otherwise). Discards any previous state. */
 vlbm_status vlbm3_set_hierarchy(vlbm3_ctx *ctx, const vlbm3_box *boxes, int nboxes);
+
+/* Replace the hierarchy by boxes, moving the state conservatively (Sec. 3.4
+ * with D = 3): exiting cells are merged finest level first (eq. amr-merge, the
+ * plain average of r^3 children, summed z, y, x), entering cells split
+ * coarsest level first (eqs. amr-slope, amr-split, one minmod slope per axis
+ * from neighbours covered at that level in the new hierarchy that hold data).
+ * Merged and split cells get the same value in both time levels, and every
+ * interface restarts its temporal reconstruction. The boundary ledger is
+ * kept. Validation as vlbm3_set_hierarchy. Synchronises. */
+vlbm_status vlbm3_regrid(vlbm3_ctx *ctx, const vlbm3_box *boxes, int nboxes);
 
 /* f := f^eq(U) on the covered cells of the rectangle; clears the previous-step
  * samples of those cells and the boundary ledger. */

@@ -813,6 +813,10 @@ int orc_set_time_stepping(orc *o, int on, double kappa) {
   }
   o->adt = on;
   o->kd = kappa * 2.0;
+  if (!on) { /* back to the parameter c, with no time-step change to carry */
+    o->c = o->c0;
+    for (int l = 0; l < OMAXL; ++l) o->c_last[l] = o->c0;
+  }
   return 0;
 }
 

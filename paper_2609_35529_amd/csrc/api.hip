@@ -271,6 +271,10 @@ struct vlbm_ctx {
   double c_sensor = 1.0, beta_min = 1.0, beta_max = 1.0;
   unsigned long long *dqmax = nullptr;  // [2][4]: max |Q| per coarse-step parity, as bits
   bool sensor_stale = true;  // W planes and this coarse step's max |Q| need stage 0
+  // adaptive time step: DynState scalars and the CFL max slot (device)
+  bool adt = false;
+  double *ddyn = nullptr;
+  unsigned long long *dcmax = nullptr;
   int32_t s0_seg0 = 0, s0_nseg = 0, s0_nblocks = 0;  // stage 0: segments over every level
   double ledger_carry[4] = {0, 0, 0, 0}, ledger_carry_c[4] = {0, 0, 0, 0};
   // schedule tables: phases of one coarse step and their descriptors for the
@@ -1182,6 +1186,16 @@ vlbm_status build_tables(vlbm_ctx *c) {
       const int l = c->phases[p].first, k = c->phases[p].second;
       const bool fused = k == 0;
       descs[e * P + p] = make_desc(c, l, st, fused);
+      if (c->adt) {
+        // the hand-off scales its temporal slope when the parent's previous
+        // step belongs to the previous coarse step
+        LevelDesc &D = descs[e * P + p];
+        D.dyn = c->ddyn;
+        bool parent_stepped = false;
+        for (size_t q2 = 0; q2 < p; ++q2)
+          if (c->phases[q2].first == l - 1) parent_stepped = true;
+        D.use_ratio = (l > 0 && !parent_stepped) ? 1 : 0;
+      }
       if (descs[e * P + p].sen) {
         LevelDesc &D = descs[e * P + p];
         D.qmax = c->dqmax + 4 * e;
@@ -1214,14 +1228,17 @@ vlbm_status build_tables(vlbm_ctx *c) {
   c->s0_seg0 = (int32_t)seg_desc.size();
   c->s0_nseg = 0;
   c->s0_nblocks = 0;
-  if (c->sensor) {
-    // stage 0: one segment per level, the descriptor of the level's first
-    // phase (its buffers as at the coarse step's start)
+  if (c->sensor || c->adt) {
+    // one segment per level over every level's cells as at the coarse step's
+    // start (the sensor's stage 0, the adaptive time step's CFL bound): the
+    // descriptor of the level's first phase, fused or not (its tiles cover
+    // the level's active cells either way)
     for (int l = 0; l < c->nlev; ++l) {
       size_t p0 = 0;
       while (p0 < P && c->phases[p0].first != l) ++p0;
-      if (p0 == P || c->phases[p0].second == 0) return fail(VLBM_EINVAL, "internal: sensor schedule");
-      seg_desc.push_back({(int)p0, nb8(c->lv[l].tiles.size())});
+      if (p0 == P) return fail(VLBM_EINVAL, "internal: level without a phase");
+      const bool fz = c->phases[p0].second == 0;
+      seg_desc.push_back({(int)p0, nb8(fz ? c->lv[l].ftiles.size() : c->lv[l].tiles.size())});
       seg_desc1.push_back((int)(P + p0));
       c->s0_nseg += 1;
     }
@@ -1279,6 +1296,19 @@ vlbm_status prof_flush(vlbm_ctx *c) {
 
 // Launch every launch of one coarse step of table parity e.
 vlbm_status launch_coarse_step(vlbm_ctx *c, int e) {
+  if (c->adt) {  // this coarse step's link speed from the state at its start
+    StepLaunch a{};
+    const int s0 = e * c->nseg_table + c->s0_seg0;
+    if (c->s0_nseg == 1) {
+      a.d0 = c->hseg[s0].d;
+    } else {
+      a.segs = c->dseg + s0;
+      a.nseg = c->s0_nseg;
+    }
+    a.nblocks = c->s0_nblocks;
+    HIPCHK(launch_cfl(a, c->fp32, c->dcmax, c->ddyn, c->stream));
+    HIPCHK(launch_cfl_finalize(c->ddyn, c->dcmax, c->stream));
+  }
   for (const LaunchRec &r : c->launches) {
     if (r.nblocks <= 0) continue;
     StepLaunch a{};
@@ -1292,7 +1322,7 @@ vlbm_status launch_coarse_step(vlbm_ctx *c, int e) {
     }
     a.nblocks = r.nblocks;
     a.first = r.first;
-    a.flags = c->step_flags | (r.fused_kernel ? STEP_FUSED_PHASE : 0);
+    a.flags = c->step_flags | (r.fused_kernel ? STEP_FUSED_PHASE : 0) | (c->adt ? STEP_ADAPTIVE_DT : 0);
     a.ak = r.ak;
     if (c->sensor && !r.fused_kernel) {  // per-cell beta from the state at the start of the step
       HIPCHK(launch_sensor(a, 2, c->fp32, c->stream));
@@ -1479,6 +1509,14 @@ vlbm_status rect_io(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny, doub
   }
   c->mem.release(stage);
   if (e != hipSuccess) return fail(VLBM_EDEVICE, "state transfer: %s", hipGetErrorString(e));
+  return VLBM_OK;
+}
+
+vlbm_status reset_time(vlbm_ctx *c) {
+  if (!c->adt) return VLBM_OK;
+  const double zero = 0.0;
+  HIPCHK(hipMemcpyAsync(c->ddyn + DYN_TIME, &zero, sizeof zero, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
   return VLBM_OK;
 }
 
@@ -2022,6 +2060,8 @@ void vlbm_destroy(vlbm_ctx *c) {
   c->mem.release(c->dseg);
   c->mem.release(c->dflag);
   c->mem.release(c->dqmax);
+  c->mem.release(c->ddyn);
+  c->mem.release(c->dcmax);
   c->mem.release_all();
   delete c;
 }
@@ -2109,7 +2149,8 @@ vlbm_status vlbm_set_state(vlbm_ctx *c, int level, int i0, int j0, int nx, int n
   if (st) return st;
   c->table_base -= c->coarse_steps;  // keep the table parity while restarting the count
   c->coarse_steps = 0;
-  return reset_ledgers(c);
+  st = reset_time(c);
+  return st ? st : reset_ledgers(c);
 }
 
 vlbm_status vlbm_set_populations(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny,
@@ -2119,7 +2160,8 @@ vlbm_status vlbm_set_populations(vlbm_ctx *c, int level, int i0, int j0, int nx,
   if (st) return st;
   c->table_base -= c->coarse_steps;
   c->coarse_steps = 0;
-  return reset_ledgers(c);
+  st = reset_time(c);
+  return st ? st : reset_ledgers(c);
 }
 
 vlbm_status vlbm_get_state(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny, double *U,
@@ -2357,6 +2399,7 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
       return fail(VLBM_EINVAL, "context %d uses fused sub-steps, which batched launches do not take", i);
     if (c->sensor != c0->sensor)
       return fail(VLBM_EINVAL, "batched contexts must all use the adaptive relaxation, or none");
+    if (c->adt) return fail(VLBM_EINVAL, "context %d uses an adaptive time step, which batched launches do not take", i);
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == c) return fail(VLBM_EINVAL, "context %d listed twice", i);
   }
@@ -2473,7 +2516,7 @@ static std::map<std::string, std::pair<int, int>> g_tuned;
 static std::string tuning_key(const vlbm_ctx *c) {
   std::string k = std::to_string(c->p.nx0) + "x" + std::to_string(c->p.ny0) + "r" +
                   std::to_string(c->p.r) + "p" + std::to_string(c->p.precision) +
-                  (c->sensor ? "s" : "");
+                  (c->sensor ? "s" : "") + (c->adt ? "a" : "");
   for (const vlbm_box &b : c->boxes)
     k += ":" + std::to_string(b.level) + "," + std::to_string(b.i0) + "," + std::to_string(b.j0) +
          "," + std::to_string(b.nx) + "," + std::to_string(b.ny);
@@ -2547,6 +2590,48 @@ vlbm_status vlbm_set_sensor(vlbm_ctx *c, int on, double c_sensor, double beta_mi
   if (!c->have_hierarchy) return VLBM_OK;
   // same buffers and time history; descriptors, planes and fusion follow the setting
   return build_tables(c);
+}
+
+vlbm_status vlbm_set_time_stepping(vlbm_ctx *c, int on, double kappa) {
+  if (!c) return fail(VLBM_EINVAL, "null context");
+  if (on && !(kappa > 0.0)) return fail(VLBM_EINVAL, "adaptive time step needs kappa > 0");
+  if (on && c->eos.kind != VLBM_EOS_IDEAL) return fail(VLBM_EINVAL, "adaptive time step: ideal gas only");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->adt = on != 0;
+  if (c->adt) {
+    if (!c->ddyn) c->ddyn = static_cast<double *>(c->mem.alloc(sizeof(double) * DYN_SLOTS));
+    if (!c->dcmax) c->dcmax = static_cast<unsigned long long *>(c->mem.alloc(sizeof(unsigned long long)));
+    if (!c->ddyn || !c->dcmax) return fail(VLBM_ENOMEM, "adaptive time step scalars");
+    double dyn[DYN_SLOTS] = {};
+    dyn[DYN_C] = c->p.c;
+    dyn[DYN_H] = c->h;
+    dyn[DYN_C_PREV] = c->p.c;
+    dyn[DYN_TIME] = (double)c->coarse_steps * (c->p.dx0 / c->p.c);
+    dyn[DYN_GAMMA] = c->p.gamma;
+    dyn[DYN_KD] = kappa * 2.0;
+    dyn[DYN_DX0] = c->p.dx0;
+    const unsigned long long zero = 0;
+    HIPCHK(hipMemcpyAsync(c->ddyn, dyn, sizeof dyn, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->dcmax, &zero, sizeof zero, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  if (!c->have_hierarchy) return VLBM_OK;
+  return build_tables(c);
+}
+
+vlbm_status vlbm_time(vlbm_ctx *c, double *time, double *link_speed) {
+  if (!c) return fail(VLBM_EINVAL, "null context");
+  double t = (double)c->coarse_steps * (c->p.dx0 / c->p.c), cs = c->p.c;
+  if (c->adt) {
+    double dyn[DYN_SLOTS];
+    HIPCHK(hipMemcpyAsync(dyn, c->ddyn, sizeof dyn, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    t = dyn[DYN_TIME];
+    cs = dyn[DYN_C];
+  }
+  if (time) *time = t;
+  if (link_speed) *link_speed = cs;
+  return VLBM_OK;
 }
 
 vlbm_status vlbm_get_beta(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny, double *beta,

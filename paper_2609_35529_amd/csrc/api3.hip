@@ -711,6 +711,87 @@ void kadd3(double &s, double &cmp, double v) {
   s = t;
 }
 
+bool wrap_in(const vlbm3_params &p, const Level3 *lv, int l, int q[3]) {
+  for (int a = 0; a < 3; ++a) {
+    const int n = lv[l].N[a];
+    if (q[a] < 0 || q[a] >= n) {
+      if (p.bc[2 * a] != VLBM_BC_PERIODIC) return false;
+      q[a] = ((q[a] % n) + n) % n;
+    }
+  }
+  return true;
+}
+
+bool cov_in(const Level3 *lv, int nlev, int l, const int q[3]) {
+  if (l >= nlev || !lv[l].present || !lv[l].in_frame(q)) return false;
+  return lv[l].cov[lv[l].fidx(q)] != 0;
+}
+
+// Frames, coverage and status of the hierarchy `boxes` into lv[0..kL), with
+// every host-side check (alignment, range, proper nesting). No device work.
+vlbm_status build_geometry3(const vlbm3_params &p, const vlbm3_box *boxes, int nboxes, Level3 *lv, int &nlev) {
+  Geom3 g;
+  vlbm_status st = check_boxes3(p, boxes, nboxes, g);
+  if (st) return st;
+  nlev = g.nlev;
+  for (int l = 0; l < kL; ++l) {
+    lv[l] = Level3();
+    frame3(p, g, l, lv[l]);
+    if (lv[l].present && lv[l].plane >= (int64_t(1) << 31))
+      return fail3(VLBM_EINVAL, "level %d frame too large for 32-bit offsets", l);
+  }
+  for (int l = 0; l < nlev; ++l) {
+    Level3 &L = lv[l];
+    L.cov.assign((size_t)L.fn[0] * L.fn[1] * L.fn[2], 0);
+    auto fill = [&](const int lo[3], const int ext[3]) {
+      for (int z = lo[2]; z < lo[2] + ext[2]; ++z)
+        for (int y = lo[1]; y < lo[1] + ext[1]; ++y) {
+          int p0[3] = {lo[0], y, z};
+          memset(&L.cov[L.fidx(p0)], 1, ext[0]);
+        }
+    };
+    if (l == 0) {
+      const int lo[3] = {0, 0, 0};
+      fill(lo, L.N);
+    } else {
+      for (int b = 0; b < nboxes; ++b)
+        if (boxes[b].level == l) {
+          const int lo[3] = {boxes[b].i0, boxes[b].j0, boxes[b].k0};
+          const int ext[3] = {boxes[b].nx, boxes[b].ny, boxes[b].nz};
+          fill(lo, ext);
+        }
+    }
+  }
+  // proper nesting: the parent of every covered cell and its face neighbours
+  const int r = p.r;
+  for (int b = 0; b < nboxes; ++b) {
+    const vlbm3_box &B = boxes[b];
+    const int l = B.level;
+    for (int pz = B.k0 / r; pz < (B.k0 + B.nz) / r; ++pz)
+      for (int py = B.j0 / r; py < (B.j0 + B.ny) / r; ++py)
+        for (int px = B.i0 / r; px < (B.i0 + B.nx) / r; ++px)
+          for (int d = -1; d < 6; ++d) {
+            int P[3] = {px + (d < 0 ? 0 : E3[d][0]), py + (d < 0 ? 0 : E3[d][1]), pz + (d < 0 ? 0 : E3[d][2])};
+            if (!wrap_in(p, lv, l - 1, P)) continue;
+            if (!cov_in(lv, nlev, l - 1, P)) return fail3(VLBM_ENEST, "box %d: hierarchy not properly nested", b);
+          }
+  }
+  for (int l = 0; l < nlev; ++l) {
+    Level3 &L = lv[l];
+    L.status.assign(L.cov.size(), 0);
+    for (int z = L.f0[2]; z < L.f0[2] + L.fn[2]; ++z)
+      for (int y = L.f0[1]; y < L.f0[1] + L.fn[1]; ++y)
+        for (int x = L.f0[0]; x < L.f0[0] + L.fn[0]; ++x) {
+          const int q[3] = {x, y, z};
+          const size_t i = L.fidx(q);
+          if (!L.cov[i]) continue;
+          const int ch[3] = {x * r, y * r, z * r};
+          L.status[i] = cov_in(lv, nlev, l + 1, ch) ? 2 : 1;
+        }
+  }
+  return VLBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -756,72 +837,15 @@ size_t vlbm3_footprint_bytes(const vlbm3_params *params, const vlbm3_box *boxes,
 
 vlbm_status vlbm3_set_hierarchy(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
   if (!c) return fail3(VLBM_EINVAL, "null context");
-  Geom3 g;
-  vlbm_status st = check_boxes3(c->p, boxes, nboxes, g);
+  Level3 nl[kL];
+  int nnlev = 1;
+  vlbm_status st = build_geometry3(c->p, boxes, nboxes, nl, nnlev);
   if (st) return st;
   HIPCHK3(hipStreamSynchronize(c->stream));
   for (int l = 0; l < kL; ++l) free_level3(c->lv[l]);
   c->have_hierarchy = false;
-  c->nlev = g.nlev;
-  for (int l = 0; l < kL; ++l) {
-    frame3(c->p, g, l, c->lv[l]);
-    if (c->lv[l].present && c->lv[l].plane >= (int64_t(1) << 31))
-      return fail3(VLBM_EINVAL, "level %d frame too large for 32-bit offsets", l);
-  }
-  // coverage (frame-indexed)
-  for (int l = 0; l < c->nlev; ++l) {
-    Level3 &L = c->lv[l];
-    L.cov.assign((size_t)L.fn[0] * L.fn[1] * L.fn[2], 0);
-    auto fill = [&](const int lo[3], const int ext[3]) {
-      for (int z = lo[2]; z < lo[2] + ext[2]; ++z)
-        for (int y = lo[1]; y < lo[1] + ext[1]; ++y) {
-          int p0[3] = {lo[0], y, z};
-          memset(&L.cov[L.fidx(p0)], 1, ext[0]);
-        }
-    };
-    if (l == 0) {
-      const int lo[3] = {0, 0, 0};
-      fill(lo, L.N);
-    } else {
-      for (int b = 0; b < nboxes; ++b)
-        if (boxes[b].level == l) {
-          const int lo[3] = {boxes[b].i0, boxes[b].j0, boxes[b].k0};
-          const int ext[3] = {boxes[b].nx, boxes[b].ny, boxes[b].nz};
-          fill(lo, ext);
-        }
-    }
-  }
-  // proper nesting: the parent of every covered cell and its face neighbours
-  const int r = c->p.r;
-  for (int b = 0; b < nboxes; ++b) {
-    const vlbm3_box &B = boxes[b];
-    const int l = B.level;
-    for (int pz = B.k0 / r; pz < (B.k0 + B.nz) / r; ++pz)
-      for (int py = B.j0 / r; py < (B.j0 + B.ny) / r; ++py)
-        for (int px = B.i0 / r; px < (B.i0 + B.nx) / r; ++px)
-          for (int d = -1; d < 6; ++d) {
-            int P[3] = {px + (d < 0 ? 0 : E3[d][0]), py + (d < 0 ? 0 : E3[d][1]), pz + (d < 0 ? 0 : E3[d][2])};
-            if (!c->wrap(l - 1, P)) continue;
-            if (!c->covered(l - 1, P)) {
-              for (int m = 0; m < kL; ++m) free_level3(c->lv[m]);
-              return fail3(VLBM_ENEST, "box %d: hierarchy not properly nested", b);
-            }
-          }
-  }
-  // status
-  for (int l = 0; l < c->nlev; ++l) {
-    Level3 &L = c->lv[l];
-    L.status.assign(L.cov.size(), 0);
-    for (int z = L.f0[2]; z < L.f0[2] + L.fn[2]; ++z)
-      for (int y = L.f0[1]; y < L.f0[1] + L.fn[1]; ++y)
-        for (int x = L.f0[0]; x < L.f0[0] + L.fn[0]; ++x) {
-          const int p[3] = {x, y, z};
-          const size_t i = L.fidx(p);
-          if (!L.cov[i]) continue;
-          const int ch[3] = {x * r, y * r, z * r};
-          L.status[i] = c->covered(l + 1, ch) ? 2 : 1;
-        }
-  }
+  for (int l = 0; l < kL; ++l) c->lv[l] = std::move(nl[l]);
+  c->nlev = nnlev;
   st = build_lists3(c);
   if (st) {
     for (int m = 0; m < kL; ++m) free_level3(c->lv[m]);
@@ -843,6 +867,182 @@ vlbm_status vlbm3_set_hierarchy(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes
   c->boxes.assign(boxes, boxes + nboxes);
   c->have_hierarchy = true;
   c->coarse_steps = 0;
+  return build_tables3(c);
+}
+
+vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
+  if (!c || !c->have_hierarchy) return fail3(VLBM_ESTATE, "no hierarchy installed");
+  Level3 nl[kL];
+  int nnlev = 1;
+  vlbm_status st = build_geometry3(c->p, boxes, nboxes, nl, nnlev);
+  if (st) return st;
+  const int r = c->p.r, onlev = c->nlev;
+  // the boundary ledger survives the rebuild of its slots
+  double tot[5], led[5] = {};
+  st = vlbm3_conserved_totals(c, tot, led);
+  if (st) return st;
+  auto old_cov = [&](int l, const int q[3]) { return cov_in(c->lv, onlev, l, q); };
+  auto new_cov = [&](int l, const int q[3]) { return cov_in(nl, nnlev, l, q); };
+  std::vector<void *> scratch;  // device op lists, freed after the final sync
+  auto upload_ops = [&](const std::vector<RegridOp3> &ops, RegridOp3 *&d) -> vlbm_status {
+    HIPCHK3(hipMalloc((void **)&d, sizeof(RegridOp3) * std::max<size_t>(1, ops.size())));
+    scratch.push_back(d);
+    if (!ops.empty()) HIPCHK3(hipMemcpyAsync(d, ops.data(), sizeof(RegridOp3) * ops.size(), hipMemcpyHostToDevice, c->stream));
+    return VLBM_OK;
+  };
+  // 1. merges, finest level first, in the old frames (eq. amr-merge)
+  for (int l = onlev - 1; l >= 1; --l) {
+    const Level3 &F = c->lv[l];
+    Level3 &Cl = c->lv[l - 1];
+    std::vector<RegridOp3> ops;
+    for (int z = F.f0[2] + 1; z < F.f0[2] + F.fn[2] - 1; z += r)
+      for (int y = F.f0[1] + 1; y < F.f0[1] + F.fn[1] - 1; y += r)
+        for (int x = F.f0[0] + 1; x < F.f0[0] + F.fn[0] - 1; x += r) {
+          const int q[3] = {x, y, z};
+          if (!F.cov[F.fidx(q)] || new_cov(l, q)) continue;
+          const int P[3] = {x / r, y / r, z / r};
+          RegridOp3 o{};
+          o.dst = (int32_t)Cl.off(P);
+          o.src = (int32_t)F.off(q);
+          ops.push_back(o);
+        }
+    if (ops.empty()) continue;
+    RegridArgs3 a{};
+    a.fine_cur = F.buf[F.cur()];
+    a.coarse0 = Cl.buf[0];
+    a.coarse1 = Cl.buf[1];
+    a.fplane = F.plane;
+    a.fslab = F.slab;
+    a.fpitch = F.pitch;
+    a.cplane = Cl.plane;
+    a.r = r;
+    RegridOp3 *d = nullptr;
+    st = upload_ops(ops, d);
+    if (st) return st;
+    a.ops = d;
+    a.nops = (int32_t)ops.size();
+    HIPCHK3(launch_merge3(a, c->stream));
+  }
+  // 2. new frames: surviving cells move over (both time levels); a level
+  //    whose frame is unchanged keeps its buffers
+  for (int l = 0; l < nnlev; ++l) {
+    Level3 &N = nl[l];
+    Level3 *O = l < onlev ? &c->lv[l] : nullptr;
+    N.steps = O ? O->steps : 0;
+    if (O && O->present && O->plane == N.plane && O->pitch == N.pitch && O->slab == N.slab &&
+        O->f0[0] == N.f0[0] && O->f0[1] == N.f0[1] && O->f0[2] == N.f0[2] && O->fn[0] == N.fn[0] &&
+        O->fn[1] == N.fn[1] && O->fn[2] == N.fn[2]) {
+      N.buf[0] = O->buf[0];
+      N.buf[1] = O->buf[1];
+      O->buf[0] = O->buf[1] = nullptr;
+      continue;
+    }
+    const size_t nb = level_bytes3(N);
+    HIPCHK3(hipMalloc(&N.buf[0], nb));
+    HIPCHK3(hipMalloc(&N.buf[1], nb));
+    HIPCHK3(hipMemsetAsync(N.buf[0], 0, nb, c->stream));
+    HIPCHK3(hipMemsetAsync(N.buf[1], 0, nb, c->stream));
+    if (!O || !O->present) continue;
+    std::vector<int32_t> runs;
+    for (int z = N.f0[2] + 1; z < N.f0[2] + N.fn[2] - 1; ++z)
+      for (int y = N.f0[1] + 1; y < N.f0[1] + N.fn[1] - 1; ++y) {
+        int x = N.f0[0] + 1;
+        const int xe = N.f0[0] + N.fn[0] - 1;
+        while (x < xe) {
+          const int q[3] = {x, y, z};
+          if (!(N.cov[N.fidx(q)] && O->in_frame(q) && O->cov[O->fidx(q)])) {
+            ++x;
+            continue;
+          }
+          const int xa = x;
+          while (x < xe) {
+            const int qq[3] = {x, y, z};
+            if (!(N.cov[N.fidx(qq)] && O->in_frame(qq) && O->cov[O->fidx(qq)])) break;
+            ++x;
+          }
+          const int qa[3] = {xa, y, z};
+          runs.push_back((int32_t)O->off(qa));
+          runs.push_back((int32_t)N.off(qa));
+          runs.push_back(x - xa);
+        }
+      }
+    if (runs.empty()) continue;
+    int32_t *druns = nullptr;
+    HIPCHK3(hipMalloc((void **)&druns, sizeof(int32_t) * runs.size()));
+    scratch.push_back(druns);
+    HIPCHK3(hipMemcpyAsync(druns, runs.data(), sizeof(int32_t) * runs.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK3(launch_copy3_runs(O->buf[0], O->buf[1], N.buf[0], N.buf[1], druns, (int)(runs.size() / 3), O->plane,
+                              N.plane, c->stream));
+  }
+  // 3. splits, coarsest level first, in the new frames (eqs. amr-slope,
+  //    amr-split); a slope neighbour is covered at that level in the new
+  //    hierarchy and holds data (not a hole before and after)
+  for (int l = 0; l + 1 < nnlev; ++l) {
+    Level3 &Cl = nl[l], &F = nl[l + 1];
+    std::vector<RegridOp3> ops;
+    for (int z = F.f0[2] + 1; z < F.f0[2] + F.fn[2] - 1; z += r)
+      for (int y = F.f0[1] + 1; y < F.f0[1] + F.fn[1] - 1; y += r)
+        for (int x = F.f0[0] + 1; x < F.f0[0] + F.fn[0] - 1; x += r) {
+          const int q[3] = {x, y, z};
+          if (!F.cov[F.fidx(q)] || old_cov(l + 1, q)) continue;
+          const int P[3] = {x / r, y / r, z / r};
+          RegridOp3 o{};
+          o.dst = (int32_t)F.off(q);
+          o.src = (int32_t)Cl.off(P);
+          for (int d = 0; d < 6; ++d) {
+            int nbq[3] = {P[0] + E3[d][0], P[1] + E3[d][1], P[2] + E3[d][2]};
+            o.nb[d] = -1;
+            if (!wrap_in(c->p, nl, l, nbq) || !new_cov(l, nbq)) continue;
+            const int ch[3] = {nbq[0] * r, nbq[1] * r, nbq[2] * r};
+            if (old_cov(l + 1, ch) && new_cov(l + 1, ch)) continue;  // a hole before and after
+            o.nb[d] = (int32_t)Cl.off(nbq);
+          }
+          ops.push_back(o);
+        }
+    if (ops.empty()) continue;
+    RegridArgs3 a{};
+    a.coarse_cur = Cl.buf[Cl.cur()];
+    a.fine0 = F.buf[0];
+    a.fine1 = F.buf[1];
+    a.fplane = F.plane;
+    a.fslab = F.slab;
+    a.fpitch = F.pitch;
+    a.cplane = Cl.plane;
+    a.r = r;
+    RegridOp3 *d = nullptr;
+    st = upload_ops(ops, d);
+    if (st) return st;
+    a.ops = d;
+    a.nops = (int32_t)ops.size();
+    HIPCHK3(launch_split3(a, c->stream));
+  }
+  // 4. every interface restarts its temporal reconstruction: each level with
+  //    a finer level gets its current values in its other buffer too
+  for (int l = 0; l + 1 < nnlev; ++l) {
+    Level3 &N = nl[l];
+    HIPCHK3(hipMemcpyAsync(N.buf[N.cur() ^ 1], N.buf[N.cur()], level_bytes3(N), hipMemcpyDeviceToDevice, c->stream));
+  }
+  HIPCHK3(hipStreamSynchronize(c->stream));
+  for (void *p : scratch) (void)hipFree(p);
+  // 5. install the new hierarchy and rebuild its lists
+  for (int l = 0; l < kL; ++l) free_level3(c->lv[l]);
+  for (int l = 0; l < kL; ++l) c->lv[l] = std::move(nl[l]);
+  c->nlev = nnlev;
+  st = build_lists3(c);
+  if (st) return st;
+  for (int l = 0; l < c->nlev; ++l) {
+    Level3 &L = c->lv[l];
+    HIPCHK3(hipMalloc((void **)&L.dstatus, L.status.size()));
+    HIPCHK3(hipMemcpyAsync(L.dstatus, L.status.data(), L.status.size(), hipMemcpyHostToDevice, c->stream));
+  }
+  st = upload_lists3(c);
+  if (st) return st;
+  for (int l = 0; l < c->nlev; ++l)
+    if (c->lv[l].nledger > 0) {
+      HIPCHK3(hipMemcpy(c->lv[l].dledger, led, sizeof led, hipMemcpyHostToDevice));
+      break;
+    }
+  c->boxes.assign(boxes, boxes + nboxes);
   return build_tables3(c);
 }
 

@@ -93,7 +93,7 @@ __device__ __forceinline__ double minmod(double a, double b) {
 // Interface and boundary tasks (all arithmetic in FP64; stored in T)
 // ---------------------------------------------------------------------------
 template <class T>
-__device__ __forceinline__ void run_task(const LevelDesc &A, int first, double ak, const Task &t) {
+__device__ __forceinline__ void run_task(const LevelDesc &A, int first, double ak, double hd, const Task &t) {
   T *S = static_cast<T *>(A.src);
   const int64_t P = A.plane;
   const int q = t.q;
@@ -126,7 +126,7 @@ __device__ __forceinline__ void run_task(const LevelDesc &A, int first, double a
 #pragma unroll
         for (int k = 0; k < 4; ++k)
           W[k] = side == 0 ? A.win[0][k] : side == 1 ? A.win[1][k] : side == 2 ? A.win[2][k] : A.win[3][k];
-        equilibrium(W, eos_of<double>(A), A.h, f);
+        equilibrium(W, eos_of<double>(A), hd, f);
 #pragma unroll
         for (int k = 0; k < 4; ++k)
           in[k] = (double)(T)(q == 0 ? f[k] : q == 1 ? f[4 + k] : q == 2 ? f[8 + k] : f[12 + k]);
@@ -326,6 +326,9 @@ __device__ __forceinline__ double cell_beta(__attribute__((address_space(1))) co
 template <class T, class C, bool NT, bool TWO, bool SEN>
 __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks, int first,
                                          double ak, int flags) {
+  // adaptive time step: this coarse step's h, and the hand-off's dt ratio when
+  // the parent last stepped in the previous coarse step
+  const bool adt = (flags & STEP_ADAPTIVE_DT) != 0;
   // Tile order. Natural order keeps every workgroup of the chip inside one
   // narrow sweep front (few open DRAM pages); the XCD-contiguous order gives
   // each XCD's L2 a contiguous run of tiles instead.
@@ -340,7 +343,9 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
   const int64_t plane = A.plane;
   const int pitch = A.pitch;
   const EosT<C> eos = eos_of<C>(A);
-  const C h = (C)A.h, tb = (C)A.tb;
+  const double hd = adt ? A.dyn[DYN_H] : A.h;
+  if (adt && A.use_ratio) ak = ak * (A.dyn[DYN_C_PREV] / A.dyn[DYN_C]);
+  const C h = (C)hd, tb = (C)A.tb;
   // adaptive relaxation (eq. sensor-B): per-cell 2 beta in, W of the stored
   // result out, and on a level's last step of the coarse step the next max |Q|
   const auto Sp = (gptr<double>)(SEN ? A.sen : nullptr);
@@ -354,7 +359,7 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
   double m[4] = {0.0, 0.0, 0.0, 0.0};
   if (tl.ntask) {
     for (int i = threadIdx.x; i < tl.ntask; i += blockDim.x)
-      run_task<T>(A, first, ak, A.tasks[tl.task0 + i]);
+      run_task<T>(A, first, ak, hd, A.tasks[tl.task0 + i]);
     __syncthreads();
   }
   const int n = tl.w * tl.h;
@@ -452,7 +457,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepLaunch Lc) {
 // so results are bit-identical; the intermediate level never travels to HBM.
 // ---------------------------------------------------------------------------
 template <class T>
-__device__ __forceinline__ void run_task_k2(const LevelDesc &A, double ak2, const Task &t, T *F1) {
+__device__ __forceinline__ void run_task_k2(const LevelDesc &A, double ak2, double hd, const Task &t, T *F1) {
   constexpr int np = FUSE_POS;
   const int q = t.q;
   const int kind = t.kind & 0xFF;
@@ -494,7 +499,7 @@ __device__ __forceinline__ void run_task_k2(const LevelDesc &A, double ak2, cons
 #pragma unroll
     for (int k = 0; k < 4; ++k)
       W[k] = side == 0 ? A.win[0][k] : side == 1 ? A.win[1][k] : side == 2 ? A.win[2][k] : A.win[3][k];
-    equilibrium(W, eos_of<double>(A), A.h, f);
+    equilibrium(W, eos_of<double>(A), hd, f);
 #pragma unroll
     for (int k = 0; k < 4; ++k)
       in[k] = (double)(T)(q == 0 ? f[k] : q == 1 ? f[4 + k] : q == 2 ? f[8 + k] : f[12 + k]);
@@ -525,13 +530,20 @@ __device__ __forceinline__ void fused_tile(const LevelDesc &A, int lb, int nbloc
   const int64_t plane = A.plane;
   const int pitch = A.pitch;
   const EosT<C> eos = eos_of<C>(A);
-  const C h = (C)A.h, tb = (C)A.tb;
+  const bool adt = (flags & STEP_ADAPTIVE_DT) != 0;
+  const double hd = adt ? A.dyn[DYN_H] : A.h;
+  const C h = (C)hd, tb = (C)A.tb;
   const int w = tl.w, w1 = w + 1;
-  const double ak1 = (double)(1 - A.r) / (double)(2 * A.r);   // k = 1
-  const double ak2 = (double)(3 - A.r) / (double)(2 * A.r);   // k = 2
+  double ak1 = (double)(1 - A.r) / (double)(2 * A.r);   // k = 1
+  double ak2 = (double)(3 - A.r) / (double)(2 * A.r);   // k = 2
+  if (adt && A.use_ratio) {
+    const double ratio = A.dyn[DYN_C_PREV] / A.dyn[DYN_C];
+    ak1 = ak1 * ratio;
+    ak2 = ak2 * ratio;
+  }
   const Task *tk = A.tasks + tl.task0;
   // 1. sub-step-1 ghost values (global)
-  for (int i = threadIdx.x; i < tl.ntask; i += blockDim.x) run_task<T>(A, 1, ak1, tk[i]);
+  for (int i = threadIdx.x; i < tl.ntask; i += blockDim.x) run_task<T>(A, 1, ak1, hd, tk[i]);
   __syncthreads();
   // 2. sub-step 1 of tile and ring cells into LDS
   const int ncell = w * tl.h;
@@ -570,7 +582,7 @@ __device__ __forceinline__ void fused_tile(const LevelDesc &A, int lb, int nbloc
   const Task *cap = k2 + tl.nk2;
   for (int i = threadIdx.x; i < tl.nk2 + tl.ncap; i += blockDim.x) {
     if (i < tl.nk2) {
-      run_task_k2<T>(A, ak2, k2[i], F1);
+      run_task_k2<T>(A, ak2, hd, k2[i], F1);
     } else {
       const Task &t = cap[i - tl.nk2];
       double *acc = A.acc_out + 4 * (int64_t)t.slot;
@@ -828,6 +840,89 @@ hipError_t launch_sensor(const StepLaunch &a, int stage, int fp32, hipStream_t s
   } else {
     return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Adaptive time step: c_n = (kappa D) max over the active cells of every level
+// and both axes of |u_alpha| + c_s, c_s = sqrt(gamma p / rho), from the stored
+// state at the start of the coarse step; then c_prev := c, c := c_n,
+// h := 1 / (2 c_n), t := t + dx0 / c_n (the one-thread finalize), and the max
+// slot is cleared for the next coarse step.
+// ---------------------------------------------------------------------------
+// W of a cell from its stored populations (FP64 sums in the fixed order).
+template <class T>
+__device__ __forceinline__ void stored_W(const T *s0, int64_t P, int64_t o, double w[4]) {
+  const auto s = (__attribute__((address_space(1))) const T *)s0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    w[k] = (((double)s[(0 * 4 + k) * P + o] + (double)s[(1 * 4 + k) * P + o]) +
+            (double)s[(2 * 4 + k) * P + o]) + (double)s[(3 * 4 + k) * P + o];
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void cfl_kernel(StepLaunch Lc, unsigned long long *cmax, const double *dyn) {
+  VLBM_FIND_SEGMENT(Lc, (int)blockIdx.x, dp, fb, nb)
+  (void)nb;
+  const LevelDesc &A = *dp;
+  const int tid = blockIdx.x - fb;
+  if (tid >= A.ntiles) return;  // uniform over the workgroup
+  const Tile tl = A.tiles[tid];
+  const int64_t P = A.plane;
+  const int pitch = A.pitch;
+  const EosT<double> eos = eos_of<double>(A);
+  const double gamma = dyn[DYN_GAMMA];
+  double m = 0.0;
+  const int n = tl.w * tl.h;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    const int cy = c / tl.w, cx = c - cy * tl.w;
+    const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
+    double w[4];
+    stored_W<T>(static_cast<const T *>(A.src), P, o, w);
+    const double u = w[1] / w[0];
+    const double v = w[2] / w[0];
+    const double p = pressure<double>(eos, w[0], w[3] - 0.5 * (w[1] * u + w[2] * v));
+    const double cs = sqrt((gamma * p) / w[0]);
+    const double a = fabs(u) + cs, b = fabs(v) + cs;
+    m = fmax(m, a > b ? a : b);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double v = red[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) v = fmax(v, red[i]);
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+    if (bits > __hip_atomic_load(cmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(cmax, bits);
+  }
+}
+
+__global__ void cfl_finalize_kernel(double *dyn, unsigned long long *cmax) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double m = __longlong_as_double((long long)*cmax);
+  const double c = dyn[DYN_KD] * m;
+  dyn[DYN_C_PREV] = dyn[DYN_C];
+  dyn[DYN_C] = c;
+  dyn[DYN_H] = 1.0 / (2.0 * c);
+  dyn[DYN_TIME] = dyn[DYN_TIME] + dyn[DYN_DX0] / c;
+  *cmax = 0ull;
+}
+
+hipError_t launch_cfl(const StepLaunch &a, int fp32, unsigned long long *cmax, const double *dyn,
+                      hipStream_t s) {
+  if (a.nblocks <= 0 || a.nseg < 0) return hipSuccess;
+  const dim3 grid(a.nblocks), block(256);
+  if (fp32)
+    hipLaunchKernelGGL(cfl_kernel<float>, grid, block, 0, s, a, cmax, dyn);
+  else
+    hipLaunchKernelGGL(cfl_kernel<double>, grid, block, 0, s, a, cmax, dyn);
+  return hipGetLastError();
+}
+
+hipError_t launch_cfl_finalize(double *dyn, unsigned long long *cmax, hipStream_t s) {
+  hipLaunchKernelGGL(cfl_finalize_kernel, dim3(1), dim3(64), 0, s, dyn, cmax);
   return hipGetLastError();
 }
 

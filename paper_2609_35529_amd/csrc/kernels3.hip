@@ -314,3 +314,99 @@ hipError_t launch_get3(const Rect3 &a, int pops, hipStream_t s) {
 }
 
 }  // namespace vlbm3
+
+namespace vlbm3 {
+
+// ---------------------------------------------------------------------------
+// Regrid (Sec. 3.4 with D = 3): merge r^3 children into their parent (both
+// time levels), copy surviving cells into new frames, split a parent into r^3
+// children with one minmod slope per axis (both time levels).
+// ---------------------------------------------------------------------------
+__global__ void merge3_kernel(RegridArgs3 a) {
+  const int op = blockIdx.x;
+  if (op >= a.nops) return;
+  const RegridOp3 o = a.ops[op];
+  const double *F = static_cast<const double *>(a.fine_cur);
+  double *C0 = static_cast<double *>(a.coarse0), *C1 = static_cast<double *>(a.coarse1);
+  const int r = a.r;
+  const double rrr = (double)(r * r * r);
+  for (int i = threadIdx.x; i < 30; i += blockDim.x) {
+    const double *f = F + i * a.fplane + o.src;
+    double sum = 0.0;
+    for (int g = 0; g < r; ++g)
+      for (int b = 0; b < r; ++b)
+        for (int x = 0; x < r; ++x) sum += f[(int64_t)g * a.fslab + (int64_t)b * a.fpitch + x];
+    const double m = sum / rrr;
+    C0[i * a.cplane + o.dst] = m;
+    C1[i * a.cplane + o.dst] = m;
+  }
+}
+
+__global__ void split3_kernel(RegridArgs3 a) {
+  const int op = blockIdx.x;
+  if (op >= a.nops) return;
+  const RegridOp3 o = a.ops[op];
+  const double *C = static_cast<const double *>(a.coarse_cur);
+  double *F0 = static_cast<double *>(a.fine0), *F1 = static_cast<double *>(a.fine1);
+  const int r = a.r;
+  for (int i = threadIdx.x; i < 30; i += blockDim.x) {
+    const double *c = C + i * a.cplane;
+    const double fi = c[o.src];
+    double sl[3];
+    for (int ax = 0; ax < 3; ++ax)
+      sl[ax] = (o.nb[2 * ax] >= 0 && o.nb[2 * ax + 1] >= 0)
+                   ? minmod3(fi - c[o.nb[2 * ax + 1]], c[o.nb[2 * ax]] - fi)
+                   : 0.0;
+    for (int g = 0; g < r; ++g)
+      for (int b = 0; b < r; ++b)
+        for (int x = 0; x < r; ++x) {
+          const double xa = (double)(2 * x - r + 1) / (double)(2 * r);
+          const double xb = (double)(2 * b - r + 1) / (double)(2 * r);
+          const double xg = (double)(2 * g - r + 1) / (double)(2 * r);
+          double v = fi + sl[0] * xa;
+          v = v + sl[1] * xb;
+          v = v + sl[2] * xg;
+          const int64_t e = i * a.fplane + o.dst + (int64_t)g * a.fslab + (int64_t)b * a.fpitch + x;
+          F0[e] = v;
+          F1[e] = v;
+        }
+  }
+}
+
+// runs[k] = (src, dst, len): copy len consecutive elements of every plane of
+// both buffers from the old frame to the new one.
+__global__ void copy3_runs_kernel(const void *s0, const void *s1, void *d0, void *d1, const int32_t *runs,
+                                  int nruns, int64_t splane, int64_t dplane) {
+  const int k = blockIdx.x;
+  if (k >= nruns) return;
+  const int32_t src = runs[3 * k], dst = runs[3 * k + 1], len = runs[3 * k + 2];
+  const double *a0 = static_cast<const double *>(s0), *a1 = static_cast<const double *>(s1);
+  double *b0 = static_cast<double *>(d0), *b1 = static_cast<double *>(d1);
+  for (int64_t t = threadIdx.x; t < (int64_t)30 * len; t += blockDim.x) {
+    const int i = (int)(t / len), x = (int)(t - (int64_t)i * len);
+    b0[i * dplane + dst + x] = a0[i * splane + src + x];
+    b1[i * dplane + dst + x] = a1[i * splane + src + x];
+  }
+}
+
+hipError_t launch_merge3(const RegridArgs3 &a, hipStream_t s) {
+  if (a.nops <= 0) return hipSuccess;
+  hipLaunchKernelGGL(merge3_kernel, dim3(a.nops), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_split3(const RegridArgs3 &a, hipStream_t s) {
+  if (a.nops <= 0) return hipSuccess;
+  hipLaunchKernelGGL(split3_kernel, dim3(a.nops), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy3_runs(const void *s0, const void *s1, void *d0, void *d1, const int32_t *runs,
+                             int nruns, int64_t splane, int64_t dplane, hipStream_t s) {
+  if (nruns <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy3_runs_kernel, dim3(nruns), dim3(256), 0, s, s0, s1, d0, d1, runs, nruns, splane,
+                     dplane);
+  return hipGetLastError();
+}
+
+}  // namespace vlbm3

@@ -77,6 +77,28 @@ struct Rect3 {
   double gm1, h;
 };
 
+// Regrid: merge (dst: parent in the coarse frame, src: child (0,0,0) in the
+// fine frame) or split (dst: child (0,0,0) in the fine frame, src: parent in
+// the coarse frame, nb: parent's neighbours +x, -x, +y, -y, +z, -z or -1).
+struct RegridOp3 {
+  int32_t dst, src;
+  int32_t nb[6];
+};
+struct RegridArgs3 {
+  const void *fine_cur;           // merge: the fine level's current buffer (old frame)
+  void *fine0, *fine1;            // split: both fine buffers (new frame)
+  const void *coarse_cur;         // split: the coarse level's current buffer (new frame)
+  void *coarse0, *coarse1;        // merge: both coarse buffers (old frame)
+  int64_t fplane, fslab, cplane;
+  int32_t fpitch, r;
+  const RegridOp3 *ops;
+  int32_t nops;
+};
+hipError_t launch_merge3(const RegridArgs3 &a, hipStream_t s);
+hipError_t launch_split3(const RegridArgs3 &a, hipStream_t s);
+hipError_t launch_copy3_runs(const void *s0, const void *s1, void *d0, void *d1, const int32_t *runs,
+                             int nruns, int64_t splane, int64_t dplane, hipStream_t s);
+
 hipError_t launch_step3(const Launch3 &a, hipStream_t s, hipEvent_t ev0 = nullptr,
                         hipEvent_t ev1 = nullptr);
 hipError_t launch_audit3(const void *buf, const Tile3 *tiles, int ntiles, int64_t plane, int pitch,

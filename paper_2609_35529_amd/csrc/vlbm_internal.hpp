@@ -90,6 +90,20 @@ enum StepFlags : int32_t {
   STEP_FUSE2 = 16,           // tuning: the finest level takes both sub-steps per launch
   STEP_FUSED_PHASE = 32,     // launch-uniform: this phase is a fused two-sub-step launch
   STEP_SENSOR = 64,          // launch-uniform: relax with the per-cell beta of the sensor planes
+  STEP_ADAPTIVE_DT = 128,    // launch-uniform: h and the hand-off's time-step ratio from DynState
+};
+
+// Device scalars of the adaptive time step, updated once per coarse step by
+// launch_cfl_finalize (never by the host while steps are queued).
+enum DynSlot : int32_t {
+  DYN_C = 0,       // link speed of the current coarse step
+  DYN_H = 1,       // 1 / (2 c)
+  DYN_C_PREV = 2,  // link speed of the previous coarse step
+  DYN_TIME = 3,    // elapsed time
+  DYN_GAMMA = 4,   // gamma (sound speed)
+  DYN_KD = 5,      // kappa * D
+  DYN_DX0 = 6,     // level-0 cell size
+  DYN_SLOTS = 8
 };
 
 // Adaptive relaxation planes of a level (FP64, `plane` elements each, same
@@ -135,6 +149,10 @@ struct LevelDesc {
   int32_t fx0, fy0, xoff;    // frame origin (level cells)
   int32_t Nx, Ny;            // level domain
   double c_sensor, beta_min, beta_max;
+  // adaptive time step: the DynState scalars, and whether this phase's parent
+  // last stepped in the previous coarse step (hand-off takes c_prev / c)
+  const double *dyn;
+  int32_t use_ratio, pad_dyn;
 };
 
 // A run of workgroups of one launch that works on one LevelDesc. first_block
@@ -179,6 +197,12 @@ hipError_t launch_step(const StepLaunch &a, int fp32, hipStream_t s, hipEvent_t 
 // the tiles of the step launch `a` (same segments and descriptors), to run
 // just before it.
 hipError_t launch_sensor(const StepLaunch &a, int stage, int fp32, hipStream_t s);
+// Adaptive time step: the CFL bound max(|u_alpha| + c_s) over the step tiles of
+// the launch (every level at the coarse step's start) into *cmax (bits), then
+// the one-thread update of the DynState scalars, which also clears *cmax.
+hipError_t launch_cfl(const StepLaunch &a, int fp32, unsigned long long *cmax, const double *dyn,
+                      hipStream_t s);
+hipError_t launch_cfl_finalize(double *dyn, unsigned long long *cmax, hipStream_t s);
 // Neighbour masks of a level frame from its status (fw x fh bytes, 1 = active).
 hipError_t launch_sensor_mask(const uint8_t *status, uint8_t *mask, int fx0, int fy0, int fw, int fh,
                               int pitch, int xoff, int Nx, int Ny, int per, hipStream_t s);

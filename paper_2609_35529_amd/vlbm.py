@@ -98,6 +98,8 @@ vlbm_set_profiling = _sig("vlbm_set_profiling", _st, [_P, C.c_int])
 vlbm_kernel_times = _sig("vlbm_kernel_times", _st, [_P, _D, C.POINTER(C.c_long), _D])
 vlbm_set_sensor = _sig("vlbm_set_sensor", _st, [_P, C.c_int, C.c_double, C.c_double, C.c_double])
 vlbm_get_beta = _sig("vlbm_get_beta", _st, _rect)
+vlbm_set_time_stepping = _sig("vlbm_set_time_stepping", _st, [_P, C.c_int, C.c_double])
+vlbm_time = _sig("vlbm_time", _st, [_P, _D, _D])
 MAX_LEVELS = 8
 vlbm_last_error = _sig("vlbm_last_error", C.c_char_p, [])
 
@@ -107,7 +109,8 @@ EXPORTED = ["vlbm_create", "vlbm_destroy", "vlbm_bind_pool", "vlbm_footprint_byt
             "vlbm_tag", "vlbm_tag_and_regrid", "vlbm_get_boxes", "vlbm_check_health",
             "vlbm_save", "vlbm_load", "vlbm_batch_advance", "vlbm_set_tuning", "vlbm_autotune",
             "vlbm_steps", "vlbm_active_cells", "vlbm_sync", "vlbm_last_error",
-            "vlbm_set_profiling", "vlbm_kernel_times", "vlbm_set_sensor", "vlbm_get_beta"]
+            "vlbm_set_profiling", "vlbm_kernel_times", "vlbm_set_sensor", "vlbm_get_beta",
+            "vlbm_set_time_stepping", "vlbm_time"]
 
 
 class VLBMError(RuntimeError):
@@ -311,6 +314,16 @@ class Solver:
         b = np.empty((ny, nx))
         check(vlbm_get_beta(self._h, level, i0, j0, nx, ny, _dp(b), nx))
         return b
+
+    def set_time_stepping(self, on=True, kappa=1.5):
+        """Adaptive time step: c chosen every coarse step from the state."""
+        check(vlbm_set_time_stepping(self._h, int(bool(on)), float(kappa)))
+
+    def time(self):
+        """(elapsed time, link speed of the last coarse step)."""
+        t, c = C.c_double(), C.c_double()
+        check(vlbm_time(self._h, C.byref(t), C.byref(c)))
+        return t.value, c.value
 
     def set_tuning(self, tile_cells, flags=0):
         check(vlbm_set_tuning(self._h, int(tile_cells), int(flags)))

@@ -52,6 +52,7 @@ vlbm3_destroy = _sig("vlbm3_destroy", None, [_P])
 vlbm3_footprint_bytes = _sig("vlbm3_footprint_bytes", C.c_size_t,
                              [C.POINTER(vlbm3_params), C.POINTER(vlbm3_box), C.c_int])
 vlbm3_set_hierarchy = _sig("vlbm3_set_hierarchy", _st, [_P, C.POINTER(vlbm3_box), C.c_int])
+vlbm3_regrid = _sig("vlbm3_regrid", _st, [_P, C.POINTER(vlbm3_box), C.c_int])
 vlbm3_set_state = _sig("vlbm3_set_state", _st, _rect)
 vlbm3_set_populations = _sig("vlbm3_set_populations", _st, _rect)
 vlbm3_get_state = _sig("vlbm3_get_state", _st, _rect)
@@ -65,6 +66,7 @@ vlbm3_active_cells = _sig("vlbm3_active_cells", C.c_long, [_P, C.c_int])
 vlbm3_sync = _sig("vlbm3_sync", _st, [_P])
 
 EXPORTED = ["vlbm3_create", "vlbm3_destroy", "vlbm3_footprint_bytes", "vlbm3_set_hierarchy",
+            "vlbm3_regrid",
             "vlbm3_set_state", "vlbm3_set_populations", "vlbm3_get_state",
             "vlbm3_get_populations", "vlbm3_advance", "vlbm3_conserved_totals",
             "vlbm3_set_tuning", "vlbm3_set_profiling", "vlbm3_kernel_times",
@@ -132,6 +134,10 @@ class Solver3:
     def set_hierarchy(self, boxes):
         arr, n = make_boxes(boxes)
         check(vlbm3_set_hierarchy(self._h, arr, n))
+
+    def regrid(self, boxes):
+        arr, n = make_boxes(boxes)
+        check(vlbm3_regrid(self._h, arr, n))
 
     def _rect(self, level, lo, ext):
         NZ, NY, NX = self.shape(level)

@@ -171,6 +171,33 @@ def test_uniform_grid_full_size_parity():
         assert np.array_equal(Fg, Fo[:, z0:z0 + 32]), z0
 
 
+REGRID_SEQ = ([(1, 6, 4, 4, 12, 12, 12), (2, 16, 12, 12, 8, 8, 8)],
+              [(1, 0, 0, 0, 10, 8, 8), (1, 16, 12, 12, 12, 12, 10), (2, 36, 28, 28, 8, 8, 8)],
+              [(1, 8, 8, 8, 8, 8, 8)],
+              [])
+
+
+@pytest.mark.parametrize("bc", [(0,) * 6, (0, 0, 1, 1, 2, 2)])
+def test_regrid_sequence_bit_exact(bc):
+    """Moved, added and removed boxes on three levels (merges of r^3
+    children finest first, splits coarsest first, restarted interfaces): the
+    state matches the oracle bit for bit right after every regrid and after
+    the steps that follow, and the totals (with the wall ledger) are kept."""
+    case = _case(16, 14, 12, 3, [(1, 4, 4, 4, 12, 12, 10)], bc=bc)
+    o, g = _pair(case, 2)
+    T0, L0 = g.totals()
+    for boxes in REGRID_SEQ:
+        o.regrid(boxes)
+        g.regrid(boxes)
+        _bitwise(o, g, case)
+        o.advance(2)
+        g.advance(2)
+        _bitwise(o, g, case)
+        _totals_close(o, g)
+    T1, L1 = g.totals()
+    assert np.all(np.abs((T1 - T0) - (L1 - L0)) <= 1e-13 * np.abs(T0).max())
+
+
 def test_bad_hierarchies_are_rejected():
     from paper_2609_35529_amd import vlbm3
     s = vlbm3.Solver3(16, 16, 16, 1 / 16, c=3.0, r=2, max_levels=3, bc=(1,) * 6)

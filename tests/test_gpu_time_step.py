@@ -1,0 +1,130 @@
+"""Adaptive time step (c chosen every coarse step) on the HIP path vs the FP64
+oracle, through the C ABI: populations, elapsed time and link speed bit for
+bit in FP64 (the link speed is an order-free max, the rest follows the
+shared operation order); FP32 storage within its usual tolerance."""
+import numpy as np
+import pytest
+
+from paper_2609_35529_amd import workloads as wl
+from tests.parity import fp32_error, gpu_solver, run_pair
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu] {request.node.name}", flush=True)
+    yield
+
+
+def _pair(case, steps, kappa=1.5, precision=0, **kw):
+    o, g = run_pair(case, 0, precision, **kw)
+    o.set_time_stepping(True, kappa)
+    g.set_time_stepping(True, kappa)
+    if steps:
+        o.advance(steps)
+        g.advance(steps)
+    return o, g
+
+
+def _bitwise(o, g, case):
+    for l in range(case.nlev):
+        Fo, Fg = o.get_pop(l), g.get_populations(l)
+        assert np.array_equal(Fo, Fg, equal_nan=True), f"level {l}"
+
+
+def _same_clock(o, g):
+    t, c = g.time()
+    assert t == o.time() and c == o.link_speed(), (t, o.time(), c, o.link_speed())
+
+
+def _random_case(nx, ny, nlev, boxes, bc=(0, 0, 0, 0), seed=1, beta=0.8, c=4.0, w=None):
+    U = wl.random_state_U(nx, ny, seed=seed)
+    states = [U]
+    for l in range(1, nlev):
+        states.append(wl.prolong_piecewise(states[-1], 2) * (1 + 0.01 * l))
+    return wl.Case("rand", nx, ny, 1.0 / max(nx, ny), 2, nlev, 1.4, c, beta, bc, boxes, states, 0,
+                   w_inflow=w)
+
+
+@pytest.mark.parametrize("seed", [0, 2])
+def test_quadrant_three_levels(seed):
+    case = wl.request_case(dict(n0=48, nlev=3, seed=seed, steps=0))
+    o, g = _pair(case, 12)
+    _bitwise(o, g, case)
+    _same_clock(o, g)
+
+
+@pytest.mark.parametrize("bc", [(3, 1, 2, 2), (1, 1, 1, 1), (0, 0, 2, 3)])
+def test_three_levels_walls_and_inflow(bc):
+    """Inflow ghosts take this coarse step's h; every other boundary kind and
+    both interfaces follow the changing c."""
+    win = np.tile(wl.conserved(1.1, 0.4, -0.1, 1.2).reshape(4), (4, 1))
+    case = _random_case(40, 36, 3, [(1, 8, 8, 40, 32), (1, 48, 12, 16, 24), (2, 24, 24, 40, 32)],
+                        bc=bc, w=win)
+    o, g = _pair(case, 6)
+    _bitwise(o, g, case)
+    _same_clock(o, g)
+
+
+def test_fused_substeps_follow_the_time_step():
+    """The fused two-sub-step launch of the finest level reads the same h and
+    slope ratio as two separate launches."""
+    from paper_2609_35529_amd import vlbm
+    case = wl.request_case(dict(n0=64, nlev=3, seed=3, steps=0))
+    o, g = _pair(case, 0)
+    g.set_tuning(256, vlbm.TUNE_FUSE2 | vlbm.TUNE_XCD_ORDER)
+    o.advance(10)
+    g.advance(10)
+    _bitwise(o, g, case)
+    _same_clock(o, g)
+
+
+def test_with_the_adaptive_relaxation():
+    case = wl.request_case(dict(n0=48, nlev=3, seed=4, steps=0))
+    o, g = _pair(case, 0)
+    for s in (o, g):
+        s.set_sensor(True, 6.0, 0.4, 0.85)
+    o.advance(8)
+    g.advance(8)
+    _bitwise(o, g, case)
+    _same_clock(o, g)
+
+
+def test_graph_replays_and_toggling(monkeypatch):
+    """On a stream the coarse steps replay as graphs (the reduction and the
+    scalar update are kernels); switching the adaptive step off returns to the
+    parameter c, as in the oracle."""
+    import torch
+    monkeypatch.setenv("VLBM_GRAPHS", "1")
+    stream = torch.cuda.Stream()
+    case = wl.request_case(dict(n0=48, nlev=2, seed=5, steps=0))
+    o, g = _pair(case, 0, stream=stream)
+    o.advance(9)
+    g.advance(9)
+    _bitwise(o, g, case)
+    _same_clock(o, g)
+    for s in (o, g):
+        s.set_time_stepping(False)
+    o.advance(4)
+    g.advance(4)
+    _bitwise(o, g, case)
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+def test_fp32_storage_within_tolerance(precision):
+    case = wl.vortex(n0=64, t_end=0.05)
+    o, g = _pair(case, case.steps, precision=precision)
+    worst = fp32_error(o, g, case)
+    assert worst.max() <= 1e-5, worst
+    t, c = g.time()
+    assert abs(c - o.link_speed()) <= 1e-6 * c and abs(t - o.time()) <= 1e-6 * t
+
+
+def test_batch_refuses_adaptive_contexts():
+    from paper_2609_35529_amd import vlbm
+    a = gpu_solver(wl.request_case(dict(n0=32, nlev=1, seed=1, steps=0)))
+    b = gpu_solver(wl.request_case(dict(n0=32, nlev=1, seed=2, steps=0)))
+    a.set_time_stepping(True, 1.5)
+    with pytest.raises(vlbm.VLBMError):
+        vlbm.batch_advance([a, b], [1, 1])
