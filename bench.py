@@ -402,6 +402,11 @@ def main():
         traffic = m["bytes_per_launch"]
     scale = max(abs(x) for x in T0)
     drift = [float(abs((T1[k] - T0[k]) - (L1[k] - L0[k])) / scale) for k in range(4)]
+    # the whole path: algorithmic bytes of every step launch of a coarse step
+    # over the timed wall time per coarse step (launches of different levels
+    # may overlap on the chip, so this is not a sum of per-launch rates)
+    path_bytes = sum(v[2] for v in ktimes.values()) / prof_steps * bytes_per_update
+    path_gbs = path_bytes / (wall / args.steps) / 1e9
 
     out = {
         "metric": "fine-equiv cell updates/s",
@@ -430,7 +435,9 @@ def main():
                      "avg_launch_us": avg_launch_s * 1e6, "launches": dom_calls,
                      "kernel_share": dom_ms / sum(v[0] for v in ktimes.values()),
                      "timing": f"per-kernel events over {prof_steps} further coarse steps "
-                               f"({prof_wall * 1e3 / prof_steps:.4f} ms/step with events)"},
+                               f"({prof_wall * 1e3 / prof_steps:.4f} ms/step with events)",
+                     "path": {"bytes_per_step": path_bytes, "achieved": path_gbs,
+                              "frac": path_gbs / HBM_PEAK_GBS}},
         "actual_updates_per_s": upd * args.steps / wall,
         "amr": ({"regrid_every": regrid_every, "regrids": amr_timed["regrids"],
                  "boxes_min": min(amr_timed["boxes"]), "boxes_max": max(amr_timed["boxes"]),
