@@ -542,19 +542,47 @@ __device__ __forceinline__ void fused_tile(const LevelDesc &A, int lb, int nbloc
     ak2 = ak2 * ratio;
   }
   const Task *tk = A.tasks + tl.task0;
+  // Items of step 2: the tile cells, then the ring cells. A thread takes item
+  // t and item t + blockDim (there are at most FUSE_W x FUSE_H + 2 (FUSE_W +
+  // FUSE_H) items); the ring entries are read here, ahead of the first
+  // barrier, so the gathers of step 2 wait on nothing but themselves.
+  const int ncell = w * tl.h;
+  const Task *ring = tk + tl.ntask;
+  const int nitem = ncell + tl.nring;
+  const int i0 = threadIdx.x, i1 = threadIdx.x + blockDim.x;
+  // a thread without an item gathers around the tile's first cell (in bounds:
+  // every active cell has its four neighbour slots) and discards the values,
+  // so that the gathers are unconditional and the first relaxation waits only
+  // for its own sixteen loads
+  int64_t src0 = tl.off0, src1 = tl.off0;
+  int rq0 = -1, rq1 = -1, rd0 = 0, rd1 = 0;  // ring item: population and LDS position
+  if (i0 < ncell) {
+    const int cy = i0 / w, cx = i0 - cy * w;
+    src0 = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
+  } else if (i0 < nitem) {
+    const Task &t = ring[i0 - ncell];
+    src0 = t.src;
+    rq0 = t.q;
+    rd0 = t.dst;
+  }
+  if (i1 < ncell) {
+    const int cy = i1 / w, cx = i1 - cy * w;
+    src1 = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
+  } else if (i1 < nitem) {
+    const Task &t = ring[i1 - ncell];
+    src1 = t.src;
+    rq1 = t.q;
+    rd1 = t.dst;
+  }
   // 1. sub-step-1 ghost values (global)
   for (int i = threadIdx.x; i < tl.ntask; i += blockDim.x) run_task<T>(A, 1, ak1, hd, tk[i]);
   __syncthreads();
-  // 2. sub-step 1 of tile and ring cells into LDS
-  const int ncell = w * tl.h;
-  const Task *ring = tk + tl.ntask;
-  for (int i = threadIdx.x; i < ncell + tl.nring; i += blockDim.x) {
-    if (i < ncell) {
+  // 2. sub-step 1 of tile and ring cells into LDS: both gathers of a thread
+  // are issued before either relaxation, so the ring's round trip overlaps the
+  // tile's
+  auto item_store = [&](int i, int rq, int rd, const C g[16]) {
+    if (rq < 0) {
       const int cy = i / w, cx = i - cy * w;
-      const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
-      C g[16];
-      pull<T, C>(s, plane, pitch, o, g);
-      relax<C>(g, eos, h, tb);
       const int p0 = cy * w1 + cx + 1, p1 = cy * w1 + cx, p2 = (cy + 1) * w + cx, p3 = cy * w + cx;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -564,16 +592,25 @@ __device__ __forceinline__ void fused_tile(const LevelDesc &A, int lb, int nbloc
         F1[(12 + k) * np + p3] = (T)g[12 + k];
       }
     } else {
-      const Task &t = ring[i - ncell];
-      C g[16];
-      pull<T, C>(s, plane, pitch, (int64_t)t.src, g);
-      relax<C>(g, eos, h, tb);
-      const int q = t.q;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const C v = q == 0 ? g[k] : q == 1 ? g[4 + k] : q == 2 ? g[8 + k] : g[12 + k];
-        F1[(q * 4 + k) * np + t.dst] = (T)v;
+        const C v = rq == 0 ? g[k] : rq == 1 ? g[4 + k] : rq == 2 ? g[8 + k] : g[12 + k];
+        F1[(rq * 4 + k) * np + rd] = (T)v;
       }
+    }
+  };
+  {
+    const bool has0 = i0 < nitem, has1 = i1 < nitem;
+    C g0[16], g1[16];
+    pull<T, C>(s, plane, pitch, src0, g0);
+    pull<T, C>(s, plane, pitch, src1, g1);
+    if (has0) {
+      relax<C>(g0, eos, h, tb);
+      item_store(i0, rq0, rd0, g0);
+    }
+    if (has1) {
+      relax<C>(g1, eos, h, tb);
+      item_store(i1, rq1, rd1, g1);
     }
   }
   __syncthreads();

@@ -70,7 +70,9 @@ constexpr int FUSE_POS = (FUSE_W + 1) * FUSE_H > FUSE_W * (FUSE_H + 1) ? (FUSE_W
 #define VLBM_FUSE_THREADS 256
 #endif
 constexpr int FUSE_THREADS = VLBM_FUSE_THREADS;
-static_assert(FUSE_W % 2 == 0 && FUSE_H % 2 == 0 && FUSE_W * FUSE_H <= FUSE_THREADS, "fused tile shape");
+static_assert(FUSE_W % 2 == 0 && FUSE_H % 2 == 0 && FUSE_W * FUSE_H <= FUSE_THREADS &&
+                  2 * (FUSE_W + FUSE_H) <= FUSE_THREADS,
+              "fused tile shape: one tile cell and one ring cell per thread at most");
 
 // Equation of state p(rho, rho e) (Sec. 2.1 leaves it generic): kind 0 ideal
 // gas (gamma-1) rho e; 1 stiffened gas (gamma-1) rho e - gamma a; 2 van der
