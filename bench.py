@@ -73,7 +73,8 @@ WORKLOADS_3D = ("blast3d",)
 
 def bench_3d(args):
     """The three-dimensional (D3Q6) path: 3-D blast in a reflecting box, 256^3
-    coarse cells with one r = 2 patch of 256^3 fine cells, FP64."""
+    coarse cells with one r = 2 patch of 256^3 fine cells (FP64 unless
+    --precision says otherwise)."""
     import torch
     from paper_2609_35529_amd import vlbm3
     from paper_2609_35529_amd import workloads as wl
@@ -81,7 +82,8 @@ def bench_3d(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.Stream()
-    solver = vlbm3.Solver3.from_case(case, stream=stream)
+    prec = {"fp64": vlbm3.FP64, "fp32": vlbm3.FP32, "fp32s": vlbm3.FP32_STORAGE}[args.precision]
+    solver = vlbm3.Solver3.from_case(case, stream=stream, precision=prec)
     # the library's default (512-cell tiles, non-temporal stores) unless given
     tuning = {"tile_cells": args.tile_cells or 512, "flags": args.flags if args.tile_cells else 1}
     solver.set_tuning(tuning["tile_cells"], tuning["flags"])
@@ -105,7 +107,7 @@ def bench_3d(args):
     dom = max(kt, key=lambda k: kt[k][0])
     dom_ms, dom_calls, dom_cells = kt[dom]
     avg_s = dom_ms / 1e3 / dom_calls
-    bytes_per_launch = dom_cells / dom_calls * 2 * 30 * 8
+    bytes_per_launch = dom_cells / dom_calls * 2 * 30 * (8 if prec == vlbm3.FP64 else 4)
     achieved = bytes_per_launch / avg_s / 1e9
     scale = max(abs(x) for x in T0)
     out = {
@@ -119,13 +121,13 @@ def bench_3d(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp32s": "f64 math, f32 storage"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{case.name}: {case.nx0}^3 coarse, levels {case.nlev}, boxes {case.boxes}, "
                                f"r={case.r}, beta={case.beta}, c={case.c:.4f}, reflecting walls, D3Q6",
                    "fine_equiv_per_step": fe_step, "actual_updates_per_step": upd,
                    "launches_per_step": sum(v[1] for v in kt.values()) / prof_steps,
-                   "tuning": tuning, "precision": "fp64"},
+                   "tuning": tuning, "precision": args.precision},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "step3_kernel",
                      "level": dom, "bytes_per_launch": bytes_per_launch,

@@ -26,7 +26,7 @@
  * Host arrays: U[5][nz][ny][nx] (rho, rho u, rho v, rho w, E) and
  * F[30][nz][ny][nx] with plane index q * 5 + k, q in (+x, -x, +y, -y, +z, -z),
  * for the rectangle [i0, i0 + nx) x [j0, j0 + ny) x [k0, k0 + nz) of level-l
- * cells, FP64.
+ * cells, FP64 on the host in every precision.
  */
 #ifndef VLBM3_H
 #define VLBM3_H
@@ -47,7 +47,11 @@ typedef struct vlbm3_ctx vlbm3_ctx;
  * max_levels 1..VLBM3_MAX_LEVELS; bc per side (-x, +x, -y, +y, -z, +z):
  * VLBM_BC_PERIODIC (on both sides of an axis), VLBM_BC_OUTFLOW (the edge
  * cell's own post-collision inbound population) or VLBM_BC_REFLECT (the
- * outgoing population with the normal momentum negated); beta in [0, 1]. */
+ * outgoing population with the normal momentum negated); beta in [0, 1].
+ * precision as in include/vlbm.h: VLBM_FP64; VLBM_FP32_STORAGE (populations
+ * stored in FP32, the cell update evaluated in FP64); VLBM_FP32 (stored and
+ * updated in FP32). The hand-off, the reflux, the ledger, the audit and
+ * regrid evaluate in FP64 in every form and round to the storage type. */
 typedef struct {
   int nx0, ny0, nz0;
   double dx0;
@@ -55,6 +59,7 @@ typedef struct {
   double gamma, c, beta;
   int r;
   int max_levels;
+  int precision;
 } vlbm3_params;
 
 /* A box of level-l cells (level >= 1), made of whole parent cells. */

@@ -57,6 +57,7 @@ struct Level3 {
   double dx = 0.0;
   int f0[3] = {0, 0, 0}, fn[3] = {0, 0, 0};  // frame origin and extent (bbox + ghost layer)
   int pitch = 0, xoff = 0;
+  int esz = 8;  // bytes per stored element
   int64_t slab = 0, plane = 0;
   void *buf[2] = {nullptr, nullptr};
   std::vector<uint8_t> cov;     // per frame cell: covered at this level
@@ -112,6 +113,8 @@ struct vlbm3_ctx {
   // stores run the step at 0.57 of HBM peak, 256-cell tiles at 0.50, 64 at 0.23
   int tile_cells = 512;
   int flags = S3_NT_STORES;
+  int fp32 = 0;    // float storage
+  int sflags = 0;  // S3_FP32 | S3_F64_MATH of the precision
   double gm1 = 0, h = 0, tb = 0;
   std::vector<vlbm3_box> boxes;
   std::vector<std::pair<int, int>> phases;  // (level, k)
@@ -175,7 +178,8 @@ void free_lists3(Level3 &L) {
 
 vlbm_status check_params3(const vlbm3_params &p) {
   if (p.nx0 < 1 || p.ny0 < 1 || p.nz0 < 1 || !(p.dx0 > 0) || p.r < 1 || p.r > 8 || p.max_levels < 1 ||
-      p.max_levels > kL || !(p.c > 0) || !(p.gamma > 1) || p.beta < 0 || p.beta > 1)
+      p.max_levels > kL || !(p.c > 0) || !(p.gamma > 1) || p.beta < 0 || p.beta > 1 ||
+      (p.precision != VLBM_FP64 && p.precision != VLBM_FP32 && p.precision != VLBM_FP32_STORAGE))
     return fail3(VLBM_EINVAL, "bad parameters");
   for (int a = 0; a < 3; ++a) {
     const int b0 = p.bc[2 * a], b1 = p.bc[2 * a + 1];
@@ -247,13 +251,15 @@ void frame3(const vlbm3_params &p, const Geom3 &g, int l, Level3 &L) {
   }
   // first interior column on a 128-byte line; rows padded to 64 elements;
   // planes to a multiple of 4 KiB
-  L.xoff = 15;
+  L.esz = p.precision == VLBM_FP64 ? 8 : 4;
+  L.xoff = 128 / L.esz - 1;
   L.pitch = (L.fn[0] + L.xoff + 63) / 64 * 64;
   L.slab = (int64_t)L.pitch * L.fn[1];
-  L.plane = (L.slab * L.fn[2] + 511) / 512 * 512;
+  const int64_t pa = 4096 / L.esz;
+  L.plane = (L.slab * L.fn[2] + pa - 1) / pa * pa;
 }
 
-size_t level_bytes3(const Level3 &L) { return (size_t)L.plane * 30 * sizeof(double); }
+size_t level_bytes3(const Level3 &L) { return (size_t)L.plane * 30 * L.esz; }
 
 // What fills the slot from which active cell x of level l pulls population q
 // (returns false: an active cell of the same level, read in place).
@@ -579,7 +585,7 @@ vlbm_status coarse_step3(vlbm3_ctx *c) {
     a.d = c->ddesc + e * P + p;
     a.nblocks = (int32_t)c->lv[l].tiles.size();
     a.first = k == 1;
-    a.flags = c->flags;
+    a.flags = c->flags | c->sflags;
     a.ak = ak3(k, c->p.r);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->prof) {
@@ -675,10 +681,10 @@ vlbm_status rect_io3(vlbm3_ctx *c, int level, const int lo[3], const int ext[3],
           memcpy(&tmp[(size_t)k * n + ((size_t)z * cext[1] + y) * cext[0]], &host[hidx(k, 0, y, z)],
                  sizeof(double) * cext[0]);
     e = hipMemcpyAsync(stage, tmp.data(), sizeof(double) * ncomp * n, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = launch_set3(a, raw ? 1 : 0, c->stream);
+    if (e == hipSuccess) e = launch_set3(a, raw ? 1 : 0, c->fp32, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   } else {
-    e = launch_get3(a, ncomp == 30 ? 1 : 0, c->stream);
+    e = launch_get3(a, ncomp == 30 ? 1 : 0, c->fp32, c->stream);
     if (e == hipSuccess)
       e = hipMemcpyAsync(tmp.data(), stage, sizeof(double) * ncomp * n, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -808,6 +814,8 @@ vlbm_status vlbm3_create(const vlbm3_params *params, void *stream, vlbm3_ctx **o
   c->gm1 = c->p.gamma - 1.0;
   c->h = 1.0 / (2.0 * c->p.c);
   c->tb = 2.0 * c->p.beta;
+  c->fp32 = c->p.precision != VLBM_FP64;
+  c->sflags = !c->fp32 ? 0 : S3_FP32 | (c->p.precision == VLBM_FP32_STORAGE ? S3_F64_MATH : 0);
   *out = c;
   return VLBM_OK;
 }
@@ -923,7 +931,7 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
     if (st) return st;
     a.ops = d;
     a.nops = (int32_t)ops.size();
-    HIPCHK3(launch_merge3(a, c->stream));
+    HIPCHK3(launch_merge3(a, c->fp32, c->stream));
   }
   // 2. new frames: surviving cells move over (both time levels); a level
   //    whose frame is unchanged keeps its buffers
@@ -974,7 +982,7 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
     scratch.push_back(druns);
     HIPCHK3(hipMemcpyAsync(druns, runs.data(), sizeof(int32_t) * runs.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK3(launch_copy3_runs(O->buf[0], O->buf[1], N.buf[0], N.buf[1], druns, (int)(runs.size() / 3), O->plane,
-                              N.plane, c->stream));
+                              N.plane, c->fp32, c->stream));
   }
   // 3. splits, coarsest level first, in the new frames (eqs. amr-slope,
   //    amr-split); a slope neighbour is covered at that level in the new
@@ -1016,7 +1024,7 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
     if (st) return st;
     a.ops = d;
     a.nops = (int32_t)ops.size();
-    HIPCHK3(launch_split3(a, c->stream));
+    HIPCHK3(launch_split3(a, c->fp32, c->stream));
   }
   // 4. every interface restarts its temporal reconstruction: each level with
   //    a finer level gets its current values in its other buffer too
@@ -1095,7 +1103,7 @@ vlbm_status vlbm3_conserved_totals(vlbm3_ctx *c, double totals[5], double ledger
   for (int l = 0; l < c->nlev; ++l) {
     Level3 &L = c->lv[l];
     const int nt = (int)L.tiles.size();
-    HIPCHK3(launch_audit3(L.buf[L.cur()], L.dtiles, nt, L.plane, L.pitch, L.dpartial, c->stream));
+    HIPCHK3(launch_audit3(L.buf[L.cur()], L.dtiles, nt, L.plane, L.pitch, L.dpartial, c->fp32, c->stream));
     std::vector<double> part(5 * (size_t)std::max(nt, 1)), led(5 * (size_t)std::max(1, L.nledger));
     if (nt) HIPCHK3(hipMemcpyAsync(part.data(), L.dpartial, sizeof(double) * 5 * nt, hipMemcpyDeviceToHost, c->stream));
     HIPCHK3(hipMemcpyAsync(led.data(), L.dledger, sizeof(double) * led.size(), hipMemcpyDeviceToHost, c->stream));

@@ -1,4 +1,7 @@
-// Device code of the three-dimensional (D3Q6) path of libvlbm, gfx950, FP64.
+// Device code of the three-dimensional (D3Q6) path of libvlbm, gfx950.
+// Storage S (double, or float for the FP32 forms) and arithmetic type C of the
+// cell update (double, or float for plain FP32); hand-off, reflux, ledger,
+// audit and regrid arithmetic is FP64 in every form, rounded to S on store.
 //
 // `step3_kernel`: one workgroup per tile of active cells. It first executes the
 // tile's ghost and interface tasks (slots only its own cells read, reflux
@@ -25,27 +28,28 @@ namespace vlbm3 {
 template <class S>
 using g1 = __attribute__((address_space(1))) S *;
 
-__device__ __forceinline__ void relax3(double g[30], double gm1, double h, double tb) {
-  double W[5];
+template <class C>
+__device__ __forceinline__ void relax3(C g[30], C gm1, C h, C tb) {
+  C W[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k)
     W[k] = ((((g[k] + g[5 + k]) + g[10 + k]) + g[15 + k]) + g[20 + k]) + g[25 + k];
-  const double rho = W[0], mx = W[1], my = W[2], mz = W[3], E = W[4];
-  const double u = mx / rho;
-  const double v = my / rho;
-  const double w = mz / rho;
-  const double p = gm1 * (E - 0.5 * ((mx * u + my * v) + mz * w));
-  const double Q[3][5] = {{mx, mx * u + p, my * u, mz * u, (E + p) * u},
-                          {my, mx * v, my * v + p, mz * v, (E + p) * v},
-                          {mz, mx * w, my * w, mz * w + p, (E + p) * w}};
+  const C rho = W[0], mx = W[1], my = W[2], mz = W[3], E = W[4];
+  const C u = mx / rho;
+  const C v = my / rho;
+  const C w = mz / rho;
+  const C p = gm1 * (E - C(0.5) * ((mx * u + my * v) + mz * w));
+  const C Q[3][5] = {{mx, mx * u + p, my * u, mz * u, (E + p) * u},
+                     {my, mx * v, my * v + p, mz * v, (E + p) * v},
+                     {mz, mx * w, my * w, mz * w + p, (E + p) * w}};
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    const double share = W[k] / 6.0;
+    const C share = W[k] / C(6);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const double hq = h * Q[a][k];
-      double &fp = g[(2 * a) * 5 + k];
-      double &fm = g[(2 * a + 1) * 5 + k];
+      const C hq = h * Q[a][k];
+      C &fp = g[(2 * a) * 5 + k];
+      C &fm = g[(2 * a + 1) * 5 + k];
       fp = fp + tb * ((share + hq) - fp);
       fm = fm + tb * ((share - hq) - fm);
     }
@@ -58,8 +62,9 @@ __device__ __forceinline__ double minmod3(double a, double b) {
   return 0.0;
 }
 
+template <class T>
 __device__ __forceinline__ void run_task3(const Desc3 &A, int first, double ak, const Task3 &t) {
-  double *S = static_cast<double *>(A.src);
+  T *S = static_cast<T *>(A.src);
   const int64_t P = A.plane;
   const int q = t.q;
   switch (t.kind & 0xFF) {
@@ -78,14 +83,14 @@ __device__ __forceinline__ void run_task3(const Desc3 &A, int first, double ak, 
       for (int k = 0; k < 5; ++k) {
         double vin;
         if (refl) {
-          const double w = S[(qo * 5 + k) * P + t.src];
+          const double w = (double)S[(qo * 5 + k) * P + t.src];
           vin = (k == kn) ? -w : w;
         } else {
-          vin = S[(q * 5 + k) * P + t.src];
+          vin = (double)S[(q * 5 + k) * P + t.src];
         }
-        S[(q * 5 + k) * P + t.dst] = vin;
+        S[(q * 5 + k) * P + t.dst] = (T)vin;
         if (book) {
-          const double out = S[(qo * 5 + k) * P + t.src];
+          const double out = (double)S[(qo * 5 + k) * P + t.src];
           const double l = L[k] + A.w3 * vin;
           L[k] = l + (-1.0) * (A.w3 * out);
         }
@@ -93,28 +98,30 @@ __device__ __forceinline__ void run_task3(const Desc3 &A, int first, double ak, 
       break;
     }
     case K3_RECON: {
-      const double *C = static_cast<const double *>(A.pcur);
-      const double *Pv = static_cast<const double *>(A.pprev);
+      const T *C = static_cast<const T *>(A.pcur);
+      const T *Pv = static_cast<const T *>(A.pprev);
       const int64_t P2 = A.pplane;
       const double b1 = (double)(2 * t.j1 - A.r + 1) / (double)(2 * A.r);
       const double b2 = (double)(2 * t.j2 - A.r + 1) / (double)(2 * A.r);
 #pragma unroll
       for (int k = 0; k < 5; ++k) {
         const int64_t pl = (q * 5 + k) * P2;
-        const double out = C[pl + t.src];
-        const double prev = Pv[pl + t.src];
+        const double out = (double)C[pl + t.src];
+        const double prev = (double)Pv[pl + t.src];
         double v = out + (out - prev) * ak;
-        const double s1 = (t.n[0] >= 0) ? minmod3(out - C[pl + t.n[0]], C[pl + t.n[1]] - out) : 0.0;
+        const double s1 =
+            (t.n[0] >= 0) ? minmod3(out - (double)C[pl + t.n[0]], (double)C[pl + t.n[1]] - out) : 0.0;
         v = v + s1 * b1;
-        const double s2 = (t.n[2] >= 0) ? minmod3(out - C[pl + t.n[2]], C[pl + t.n[3]] - out) : 0.0;
+        const double s2 =
+            (t.n[2] >= 0) ? minmod3(out - (double)C[pl + t.n[2]], (double)C[pl + t.n[3]] - out) : 0.0;
         v = v + s2 * b2;
-        S[(q * 5 + k) * P + t.dst] = v;
+        S[(q * 5 + k) * P + t.dst] = (T)v;
       }
       break;
     }
     case K3_REFLUX:
 #pragma unroll
-      for (int k = 0; k < 5; ++k) S[(q * 5 + k) * P + t.dst] = A.acc_in[5 * (int64_t)t.slot + k] / A.rrr;
+      for (int k = 0; k < 5; ++k) S[(q * 5 + k) * P + t.dst] = (T)(A.acc_in[5 * (int64_t)t.slot + k] / A.rrr);
       break;
     case K3_CAPTURE: {
       double *acc = A.acc_out + 5 * (int64_t)t.slot;
@@ -124,7 +131,7 @@ __device__ __forceinline__ void run_task3(const Desc3 &A, int first, double ak, 
         double s = first ? 0.0 : acc[k];
         const int64_t base = (q * 5 + k) * P + t.src;
         for (int a = 0; a < r; ++a)
-          for (int b = 0; b < r; ++b) s = s + S[base + (int64_t)a * t.n[0] + (int64_t)b * t.n[1]];
+          for (int b = 0; b < r; ++b) s = s + (double)S[base + (int64_t)a * t.n[0] + (int64_t)b * t.n[1]];
         acc[k] = s;
       }
       break;
@@ -134,7 +141,7 @@ __device__ __forceinline__ void run_task3(const Desc3 &A, int first, double ak, 
   }
 }
 
-template <bool NT>
+template <class S, class C, bool NT>
 __global__ __launch_bounds__(256) void step3_kernel(Launch3 L) {
   const Desc3 &A = *L.d;
   const int tid = blockIdx.x;
@@ -142,36 +149,38 @@ __global__ __launch_bounds__(256) void step3_kernel(Launch3 L) {
   const int ntiles = A.ntiles;
   if (tid >= ntiles) return;
   const Tile3 tl = A.tiles[tid];
-  const auto s = (g1<const double>)A.src;
-  const auto d = (g1<double>)A.dst;
+  const auto s = (g1<const S>)A.src;
+  const auto d = (g1<S>)A.dst;
   const int64_t P = A.plane, slab = A.slab;
   const int pitch = A.pitch;
-  const double gm1 = A.gm1, h = A.h, tb = A.tb;
+  const C gm1 = (C)A.gm1, h = (C)A.h, tb = (C)A.tb;
   if (tl.ntask) {
-    for (int i = threadIdx.x; i < tl.ntask; i += blockDim.x) run_task3(A, L.first, L.ak, A.tasks[tl.task0 + i]);
+    for (int i = threadIdx.x; i < tl.ntask; i += blockDim.x)
+      run_task3<S>(A, L.first, L.ak, A.tasks[tl.task0 + i]);
     __syncthreads();
   }
   const int n = tl.w * tl.h;
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
     const int cy = c / tl.w, cx = c - cy * tl.w;
     const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
-    double g[30];
+    C g[30];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      g[k] = s[(0 * 5 + k) * P + o - 1];            // +x arrives from x - 1
-      g[5 + k] = s[(1 * 5 + k) * P + o + 1];        // -x from x + 1
-      g[10 + k] = s[(2 * 5 + k) * P + o - pitch];   // +y from y - 1
-      g[15 + k] = s[(3 * 5 + k) * P + o + pitch];   // -y from y + 1
-      g[20 + k] = s[(4 * 5 + k) * P + o - slab];    // +z from z - 1
-      g[25 + k] = s[(5 * 5 + k) * P + o + slab];    // -z from z + 1
+      g[k] = (C)s[(0 * 5 + k) * P + o - 1];            // +x arrives from x - 1
+      g[5 + k] = (C)s[(1 * 5 + k) * P + o + 1];        // -x from x + 1
+      g[10 + k] = (C)s[(2 * 5 + k) * P + o - pitch];   // +y from y - 1
+      g[15 + k] = (C)s[(3 * 5 + k) * P + o + pitch];   // -y from y + 1
+      g[20 + k] = (C)s[(4 * 5 + k) * P + o - slab];    // +z from z - 1
+      g[25 + k] = (C)s[(5 * 5 + k) * P + o + slab];    // -z from z + 1
     }
-    relax3(g, gm1, h, tb);
+    relax3<C>(g, gm1, h, tb);
 #pragma unroll
     for (int i = 0; i < 30; ++i) {
+      const S v = (S)g[i];
       if (NT)
-        __builtin_nontemporal_store(g[i], &d[i * P + o]);
+        __builtin_nontemporal_store(v, &d[i * P + o]);
       else
-        d[i * P + o] = g[i];
+        d[i * P + o] = v;
     }
   }
 }
@@ -179,10 +188,21 @@ __global__ __launch_bounds__(256) void step3_kernel(Launch3 L) {
 hipError_t launch_step3(const Launch3 &a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (a.nblocks <= 0) return hipSuccess;
   const dim3 grid(a.nblocks), block(256);
-  if (a.flags & S3_NT_STORES)
-    hipExtLaunchKernelGGL(step3_kernel<true>, grid, block, 0, s, ev0, ev1, 0, a);
+  const bool nt = (a.flags & S3_NT_STORES) != 0;
+#define VLBM3_STEP(S_, C_)                                                                        \
+  do {                                                                                            \
+    if (nt)                                                                                       \
+      hipExtLaunchKernelGGL((step3_kernel<S_, C_, true>), grid, block, 0, s, ev0, ev1, 0, a);      \
+    else                                                                                          \
+      hipExtLaunchKernelGGL((step3_kernel<S_, C_, false>), grid, block, 0, s, ev0, ev1, 0, a);     \
+  } while (0)
+  if (!(a.flags & S3_FP32))
+    VLBM3_STEP(double, double);
+  else if (a.flags & S3_F64_MATH)
+    VLBM3_STEP(float, double);
   else
-    hipExtLaunchKernelGGL(step3_kernel<false>, grid, block, 0, s, ev0, ev1, 0, a);
+    VLBM3_STEP(float, float);
+#undef VLBM3_STEP
   return hipGetLastError();
 }
 
@@ -198,7 +218,8 @@ __device__ __forceinline__ void neumaier3(double &s, double &c, double v) {
   s = t;
 }
 
-__global__ __launch_bounds__(256) void audit3_kernel(const double *__restrict__ buf, const Tile3 *tiles,
+template <class T>
+__global__ __launch_bounds__(256) void audit3_kernel(const T *__restrict__ buf, const Tile3 *tiles,
                                                      int64_t P, int pitch, double *partial) {
   __shared__ double red[5][256];
   const Tile3 tl = tiles[blockIdx.x];
@@ -210,7 +231,7 @@ __global__ __launch_bounds__(256) void audit3_kernel(const double *__restrict__ 
 #pragma unroll
     for (int k = 0; k < 5; ++k)
 #pragma unroll
-      for (int q = 0; q < 6; ++q) neumaier3(sm[k], cc[k], buf[(q * 5 + k) * P + o]);
+      for (int q = 0; q < 6; ++q) neumaier3(sm[k], cc[k], (double)buf[(q * 5 + k) * P + o]);
   }
 #pragma unroll
   for (int k = 0; k < 5; ++k) red[k][threadIdx.x] = sm[k] + cc[k];
@@ -224,10 +245,14 @@ __global__ __launch_bounds__(256) void audit3_kernel(const double *__restrict__ 
 }
 
 hipError_t launch_audit3(const void *buf, const Tile3 *tiles, int ntiles, int64_t plane, int pitch,
-                         double *partial, hipStream_t s) {
+                         double *partial, int fp32, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(audit3_kernel, dim3(ntiles), dim3(256), 0, s, static_cast<const double *>(buf), tiles,
-                     plane, pitch, partial);
+  if (fp32)
+    hipLaunchKernelGGL(audit3_kernel<float>, dim3(ntiles), dim3(256), 0, s, static_cast<const float *>(buf),
+                       tiles, plane, pitch, partial);
+  else
+    hipLaunchKernelGGL(audit3_kernel<double>, dim3(ntiles), dim3(256), 0, s, static_cast<const double *>(buf),
+                       tiles, plane, pitch, partial);
   return hipGetLastError();
 }
 
@@ -235,6 +260,7 @@ hipError_t launch_audit3(const void *buf, const Tile3 *tiles, int ntiles, int64_
 // Rectangle copy-in (f^eq(U) or raw F into both buffers of covered cells) and
 // copy-out (W or F of active cells; NaN elsewhere)
 // ---------------------------------------------------------------------------
+template <class T>
 __global__ void set3_kernel(Rect3 a, int raw) {
   const int64_t n = (int64_t)a.nx * a.ny * a.nz;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -270,14 +296,15 @@ __global__ void set3_kernel(Rect3 a, int raw) {
       }
     }
   }
-  double *b0 = static_cast<double *>(a.buf0), *b1 = static_cast<double *>(a.buf1);
+  T *b0 = static_cast<T *>(a.buf0), *b1 = static_cast<T *>(a.buf1);
 #pragma unroll
   for (int j = 0; j < 30; ++j) {
-    b0[j * a.plane + o] = f[j];
-    b1[j * a.plane + o] = f[j];
+    b0[j * a.plane + o] = (T)f[j];
+    b1[j * a.plane + o] = (T)f[j];
   }
 }
 
+template <class T>
 __global__ void get3_kernel(Rect3 a, int pops) {
   const int64_t n = (int64_t)a.nx * a.ny * a.nz;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -286,30 +313,37 @@ __global__ void get3_kernel(Rect3 a, int pops) {
   const int fx = a.x0 + x - a.fx0, fy = a.y0 + y - a.fy0, fz = a.z0 + z - a.fz0;
   const bool act = a.status[((int64_t)fz * a.fh + fy) * a.fw + fx] == 1;
   const int64_t o = (int64_t)fz * a.slab + (int64_t)fy * a.pitch + fx + a.xoff;
-  const double *b = static_cast<const double *>(a.buf0);
+  const T *b = static_cast<const T *>(a.buf0);
+  auto f = [&](int q, int k) { return (double)b[(q * 5 + k) * a.plane + o]; };
   if (pops) {
-    for (int j = 0; j < 30; ++j) a.stage[j * n + i] = act ? b[j * a.plane + o] : __builtin_nan("");
+    for (int j = 0; j < 30; ++j) a.stage[j * n + i] = act ? (double)b[j * a.plane + o] : __builtin_nan("");
   } else {
 #pragma unroll
     for (int k = 0; k < 5; ++k)
       a.stage[k * n + i] =
-          act ? ((((b[(0 * 5 + k) * a.plane + o] + b[(1 * 5 + k) * a.plane + o]) + b[(2 * 5 + k) * a.plane + o]) +
-                  b[(3 * 5 + k) * a.plane + o]) + b[(4 * 5 + k) * a.plane + o]) + b[(5 * 5 + k) * a.plane + o]
-              : __builtin_nan("");
+          act ? ((((f(0, k) + f(1, k)) + f(2, k)) + f(3, k)) + f(4, k)) + f(5, k) : __builtin_nan("");
   }
 }
 
-hipError_t launch_set3(const Rect3 &a, int raw, hipStream_t s) {
+hipError_t launch_set3(const Rect3 &a, int raw, int fp32, hipStream_t s) {
   const int64_t n = (int64_t)a.nx * a.ny * a.nz;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(set3_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, raw);
+  const dim3 grid((unsigned)((n + 255) / 256));
+  if (fp32)
+    hipLaunchKernelGGL(set3_kernel<float>, grid, dim3(256), 0, s, a, raw);
+  else
+    hipLaunchKernelGGL(set3_kernel<double>, grid, dim3(256), 0, s, a, raw);
   return hipGetLastError();
 }
 
-hipError_t launch_get3(const Rect3 &a, int pops, hipStream_t s) {
+hipError_t launch_get3(const Rect3 &a, int pops, int fp32, hipStream_t s) {
   const int64_t n = (int64_t)a.nx * a.ny * a.nz;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(get3_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, pops);
+  const dim3 grid((unsigned)((n + 255) / 256));
+  if (fp32)
+    hipLaunchKernelGGL(get3_kernel<float>, grid, dim3(256), 0, s, a, pops);
+  else
+    hipLaunchKernelGGL(get3_kernel<double>, grid, dim3(256), 0, s, a, pops);
   return hipGetLastError();
 }
 
@@ -322,40 +356,42 @@ namespace vlbm3 {
 // time levels), copy surviving cells into new frames, split a parent into r^3
 // children with one minmod slope per axis (both time levels).
 // ---------------------------------------------------------------------------
+template <class T>
 __global__ void merge3_kernel(RegridArgs3 a) {
   const int op = blockIdx.x;
   if (op >= a.nops) return;
   const RegridOp3 o = a.ops[op];
-  const double *F = static_cast<const double *>(a.fine_cur);
-  double *C0 = static_cast<double *>(a.coarse0), *C1 = static_cast<double *>(a.coarse1);
+  const T *F = static_cast<const T *>(a.fine_cur);
+  T *C0 = static_cast<T *>(a.coarse0), *C1 = static_cast<T *>(a.coarse1);
   const int r = a.r;
   const double rrr = (double)(r * r * r);
   for (int i = threadIdx.x; i < 30; i += blockDim.x) {
-    const double *f = F + i * a.fplane + o.src;
+    const T *f = F + i * a.fplane + o.src;
     double sum = 0.0;
     for (int g = 0; g < r; ++g)
       for (int b = 0; b < r; ++b)
-        for (int x = 0; x < r; ++x) sum += f[(int64_t)g * a.fslab + (int64_t)b * a.fpitch + x];
-    const double m = sum / rrr;
+        for (int x = 0; x < r; ++x) sum += (double)f[(int64_t)g * a.fslab + (int64_t)b * a.fpitch + x];
+    const T m = (T)(sum / rrr);
     C0[i * a.cplane + o.dst] = m;
     C1[i * a.cplane + o.dst] = m;
   }
 }
 
+template <class T>
 __global__ void split3_kernel(RegridArgs3 a) {
   const int op = blockIdx.x;
   if (op >= a.nops) return;
   const RegridOp3 o = a.ops[op];
-  const double *C = static_cast<const double *>(a.coarse_cur);
-  double *F0 = static_cast<double *>(a.fine0), *F1 = static_cast<double *>(a.fine1);
+  const T *C = static_cast<const T *>(a.coarse_cur);
+  T *F0 = static_cast<T *>(a.fine0), *F1 = static_cast<T *>(a.fine1);
   const int r = a.r;
   for (int i = threadIdx.x; i < 30; i += blockDim.x) {
-    const double *c = C + i * a.cplane;
-    const double fi = c[o.src];
+    const T *c = C + i * a.cplane;
+    const double fi = (double)c[o.src];
     double sl[3];
     for (int ax = 0; ax < 3; ++ax)
       sl[ax] = (o.nb[2 * ax] >= 0 && o.nb[2 * ax + 1] >= 0)
-                   ? minmod3(fi - c[o.nb[2 * ax + 1]], c[o.nb[2 * ax]] - fi)
+                   ? minmod3(fi - (double)c[o.nb[2 * ax + 1]], (double)c[o.nb[2 * ax]] - fi)
                    : 0.0;
     for (int g = 0; g < r; ++g)
       for (int b = 0; b < r; ++b)
@@ -367,21 +403,22 @@ __global__ void split3_kernel(RegridArgs3 a) {
           v = v + sl[1] * xb;
           v = v + sl[2] * xg;
           const int64_t e = i * a.fplane + o.dst + (int64_t)g * a.fslab + (int64_t)b * a.fpitch + x;
-          F0[e] = v;
-          F1[e] = v;
+          F0[e] = (T)v;
+          F1[e] = (T)v;
         }
   }
 }
 
 // runs[k] = (src, dst, len): copy len consecutive elements of every plane of
 // both buffers from the old frame to the new one.
+template <class T>
 __global__ void copy3_runs_kernel(const void *s0, const void *s1, void *d0, void *d1, const int32_t *runs,
                                   int nruns, int64_t splane, int64_t dplane) {
   const int k = blockIdx.x;
   if (k >= nruns) return;
   const int32_t src = runs[3 * k], dst = runs[3 * k + 1], len = runs[3 * k + 2];
-  const double *a0 = static_cast<const double *>(s0), *a1 = static_cast<const double *>(s1);
-  double *b0 = static_cast<double *>(d0), *b1 = static_cast<double *>(d1);
+  const T *a0 = static_cast<const T *>(s0), *a1 = static_cast<const T *>(s1);
+  T *b0 = static_cast<T *>(d0), *b1 = static_cast<T *>(d1);
   for (int64_t t = threadIdx.x; t < (int64_t)30 * len; t += blockDim.x) {
     const int i = (int)(t / len), x = (int)(t - (int64_t)i * len);
     b0[i * dplane + dst + x] = a0[i * splane + src + x];
@@ -389,23 +426,33 @@ __global__ void copy3_runs_kernel(const void *s0, const void *s1, void *d0, void
   }
 }
 
-hipError_t launch_merge3(const RegridArgs3 &a, hipStream_t s) {
+hipError_t launch_merge3(const RegridArgs3 &a, int fp32, hipStream_t s) {
   if (a.nops <= 0) return hipSuccess;
-  hipLaunchKernelGGL(merge3_kernel, dim3(a.nops), dim3(64), 0, s, a);
+  if (fp32)
+    hipLaunchKernelGGL(merge3_kernel<float>, dim3(a.nops), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL(merge3_kernel<double>, dim3(a.nops), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_split3(const RegridArgs3 &a, hipStream_t s) {
+hipError_t launch_split3(const RegridArgs3 &a, int fp32, hipStream_t s) {
   if (a.nops <= 0) return hipSuccess;
-  hipLaunchKernelGGL(split3_kernel, dim3(a.nops), dim3(64), 0, s, a);
+  if (fp32)
+    hipLaunchKernelGGL(split3_kernel<float>, dim3(a.nops), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL(split3_kernel<double>, dim3(a.nops), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_copy3_runs(const void *s0, const void *s1, void *d0, void *d1, const int32_t *runs,
-                             int nruns, int64_t splane, int64_t dplane, hipStream_t s) {
+                             int nruns, int64_t splane, int64_t dplane, int fp32, hipStream_t s) {
   if (nruns <= 0) return hipSuccess;
-  hipLaunchKernelGGL(copy3_runs_kernel, dim3(nruns), dim3(256), 0, s, s0, s1, d0, d1, runs, nruns, splane,
-                     dplane);
+  if (fp32)
+    hipLaunchKernelGGL(copy3_runs_kernel<float>, dim3(nruns), dim3(256), 0, s, s0, s1, d0, d1, runs, nruns,
+                       splane, dplane);
+  else
+    hipLaunchKernelGGL(copy3_runs_kernel<double>, dim3(nruns), dim3(256), 0, s, s0, s1, d0, d1, runs, nruns,
+                       splane, dplane);
   return hipGetLastError();
 }
 

@@ -3,7 +3,8 @@
 //
 // Data layout, per level l: one dense frame = bounding box of the level's
 // coverage plus a one-cell ghost layer. Buffer b in {0, 1} holds 30 planes
-// (q * 5 + k) of `plane` doubles; cell (x, y, z) of the level sits at element
+// (q * 5 + k) of `plane` elements (double, or float in the FP32 forms); cell
+// (x, y, z) of the level sits at element
 //   ((z - fz0) * fh + (y - fy0)) * pitch + (x - fx0) + xoff
 // of a plane, with rows of `pitch` elements (a multiple of 64) and the first
 // interior column on a 128-byte line. The current time level of l lives in
@@ -59,7 +60,11 @@ struct Desc3 {
   double gm1, h, tb;          // gamma - 1, 1/(2c), 2 beta
 };
 
-enum StepFlags3 : int32_t { S3_NT_STORES = 1 };
+enum StepFlags3 : int32_t {
+  S3_NT_STORES = 1,  // tuning: non-temporal stores of the new time level
+  S3_FP32 = 2,       // storage in float
+  S3_F64_MATH = 4,   // with S3_FP32: the cell update evaluated in double
+};
 
 struct Launch3 {
   const Desc3 *d;
@@ -94,16 +99,17 @@ struct RegridArgs3 {
   const RegridOp3 *ops;
   int32_t nops;
 };
-hipError_t launch_merge3(const RegridArgs3 &a, hipStream_t s);
-hipError_t launch_split3(const RegridArgs3 &a, hipStream_t s);
+// fp32: float storage. Every launcher below takes it; their arithmetic is FP64.
+hipError_t launch_merge3(const RegridArgs3 &a, int fp32, hipStream_t s);
+hipError_t launch_split3(const RegridArgs3 &a, int fp32, hipStream_t s);
 hipError_t launch_copy3_runs(const void *s0, const void *s1, void *d0, void *d1, const int32_t *runs,
-                             int nruns, int64_t splane, int64_t dplane, hipStream_t s);
+                             int nruns, int64_t splane, int64_t dplane, int fp32, hipStream_t s);
 
 hipError_t launch_step3(const Launch3 &a, hipStream_t s, hipEvent_t ev0 = nullptr,
                         hipEvent_t ev1 = nullptr);
 hipError_t launch_audit3(const void *buf, const Tile3 *tiles, int ntiles, int64_t plane, int pitch,
-                         double *partial, hipStream_t s);
-hipError_t launch_set3(const Rect3 &a, int raw_populations, hipStream_t s);
-hipError_t launch_get3(const Rect3 &a, int populations, hipStream_t s);
+                         double *partial, int fp32, hipStream_t s);
+hipError_t launch_set3(const Rect3 &a, int raw_populations, int fp32, hipStream_t s);
+hipError_t launch_get3(const Rect3 &a, int populations, int fp32, hipStream_t s);
 
 }  // namespace vlbm3

@@ -21,12 +21,14 @@ VLBMError = _v.VLBMError
 PERIODIC, OUTFLOW, REFLECT = _v.PERIODIC, _v.OUTFLOW, _v.REFLECT
 MAX_LEVELS = 6
 TUNE_NT_STORES = 1
+FP64, FP32, FP32_STORAGE = _v.FP64, _v.FP32, _v.FP32_STORAGE
 
 
 class vlbm3_params(C.Structure):
     _fields_ = [("nx0", C.c_int), ("ny0", C.c_int), ("nz0", C.c_int), ("dx0", C.c_double),
                 ("bc", C.c_int * 6), ("gamma", C.c_double), ("c", C.c_double),
-                ("beta", C.c_double), ("r", C.c_int), ("max_levels", C.c_int)]
+                ("beta", C.c_double), ("r", C.c_int), ("max_levels", C.c_int),
+                ("precision", C.c_int)]
 
 
 class vlbm3_box(C.Structure):
@@ -74,12 +76,13 @@ EXPORTED = ["vlbm3_create", "vlbm3_destroy", "vlbm3_footprint_bytes", "vlbm3_set
 
 
 def make_params(nx0, ny0, nz0, dx0, gamma=1.4, c=1.0, beta=0.9, r=2, max_levels=2,
-                bc=(PERIODIC,) * 6):
+                bc=(PERIODIC,) * 6, precision=FP64):
     p = vlbm3_params()
     p.nx0, p.ny0, p.nz0, p.dx0 = nx0, ny0, nz0, dx0
     for i in range(6):
         p.bc[i] = bc[i]
     p.gamma, p.c, p.beta, p.r, p.max_levels = gamma, c, beta, r, max_levels
+    p.precision = precision
     return p
 
 
@@ -100,16 +103,16 @@ class Solver3:
     """One 3-D hierarchy on one GPU. Arrays are (comp, z, y, x)."""
 
     def __init__(self, nx0, ny0, nz0, dx0, gamma=1.4, c=1.0, beta=0.9, r=2, max_levels=2,
-                 bc=(PERIODIC,) * 6, stream=None):
+                 bc=(PERIODIC,) * 6, stream=None, precision=FP64):
         self.r, self.n0 = r, (nx0, ny0, nz0)
-        self.p = make_params(nx0, ny0, nz0, dx0, gamma, c, beta, r, max_levels, bc)
+        self.p = make_params(nx0, ny0, nz0, dx0, gamma, c, beta, r, max_levels, bc, precision)
         self._h = C.c_void_p()
         check(vlbm3_create(C.byref(self.p), _v._stream_handle(stream), C.byref(self._h)))
 
     @classmethod
-    def from_case(cls, case, stream=None, max_levels=None):
+    def from_case(cls, case, stream=None, max_levels=None, precision=FP64):
         s = cls(case.nx0, case.ny0, case.nz0, case.dx0, case.gamma, case.c, case.beta, case.r,
-                max_levels or case.nlev, case.bc, stream)
+                max_levels or case.nlev, case.bc, stream, precision)
         s.set_hierarchy(case.boxes)
         for l, U in enumerate(case.states):
             if U is not None:
@@ -197,8 +200,8 @@ class Solver3:
         check(vlbm3_sync(self._h))
 
 
-def footprint_bytes(case):
+def footprint_bytes(case, precision=FP64):
     p = make_params(case.nx0, case.ny0, case.nz0, case.dx0, case.gamma, case.c, case.beta,
-                    case.r, case.nlev, case.bc)
+                    case.r, case.nlev, case.bc, precision)
     arr, n = make_boxes(case.boxes)
     return vlbm3_footprint_bytes(C.byref(p), arr, n)
