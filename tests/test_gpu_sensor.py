@@ -227,3 +227,33 @@ def test_bad_arguments_and_beta_while_off():
     g.advance(1)
     b = g.get_beta(0)
     assert np.all((b[~np.isnan(b)] >= 0.5) & (b[~np.isnan(b)] <= 0.9))
+
+
+@pytest.mark.parametrize("tile_cells", [64, 1024])
+def test_tile_shapes_and_periodic_seams(tile_cells):
+    """64-cell tiles (stacked rectangles) and 1024-cell single-row tiles, with
+    boxes across both periodic seams (neighbours found through the wrap), bit
+    for bit."""
+    case = _random_case(40, 36, 3, [(1, 0, 8, 12, 16), (1, 68, 8, 12, 16), (1, 24, 0, 16, 8),
+                                    (1, 24, 64, 16, 8), (2, 4, 20, 12, 20)])
+    o, g = _pair(case, 0, (6.0, 0.4, 0.85))
+    g.set_tuning(tile_cells, 0)
+    o.advance(6)
+    g.advance(6)
+    _bitwise(o, g, case)
+    assert _compare_beta(o, g, case) < 0.85
+
+
+def test_graph_replays_with_the_sensor(monkeypatch):
+    """Pairs of coarse steps replay as graphs (the next-Qmax clear is a kernel
+    store in them, no memset)."""
+    import torch
+    monkeypatch.setenv("VLBM_GRAPHS", "1")
+    stream = torch.cuda.Stream()
+    case = wl.request_case(dict(n0=48, nlev=3, seed=5, steps=0))
+    o, g = _pair(case, 0, (6.0, 0.4, 0.85), stream=stream)
+    for n in (8, 5, 6):
+        o.advance(n)
+        g.advance(n)
+        _bitwise(o, g, case)
+        _compare_beta(o, g, case)
