@@ -84,8 +84,10 @@ def bench_3d(args):
     stream = torch.cuda.Stream()
     prec = {"fp64": vlbm3.FP64, "fp32": vlbm3.FP32, "fp32s": vlbm3.FP32_STORAGE}[args.precision]
     solver = vlbm3.Solver3.from_case(case, stream=stream, precision=prec)
-    # the library's default (512-cell tiles, non-temporal stores) unless given
-    tuning = {"tile_cells": args.tile_cells or 512, "flags": args.flags if args.tile_cells else 1}
+    # the library's default (non-temporal stores; 512-cell tiles in FP64, 1024
+    # in the FP32 forms) unless given
+    tuning = {"tile_cells": args.tile_cells or (512 if prec == vlbm3.FP64 else 1024),
+              "flags": args.flags if args.tile_cells else 1}
     solver.set_tuning(tuning["tile_cells"], tuning["flags"])
     T0, L0 = solver.totals()
     print(f"[bench] {case.name} warmup {args.warmup}", file=sys.stderr, flush=True)

@@ -119,8 +119,9 @@ vlbm_status vlbm3_advance(vlbm3_ctx *ctx, int n_coarse_steps);
 vlbm_status vlbm3_conserved_totals(vlbm3_ctx *ctx, double totals[5], double ledger[5]);
 
 /* Launch tuning, no effect on results: tile_cells (64..65536) bounds the cells
- * one workgroup advances; flags: 1 non-temporal stores (default: 512 cells,
- * non-temporal stores). Rebuilds the lists; state and history are kept. */
+ * one workgroup advances; flags: 1 non-temporal stores (default: non-temporal
+ * stores, 512-cell tiles in FP64, 1024-cell tiles in the FP32 forms).
+ * Rebuilds the lists; state and history are kept. */
 vlbm_status vlbm3_set_tuning(vlbm3_ctx *ctx, int tile_cells, int flags);
 
 /* Per-level kernel timing of the step launches (launch-extension events),

@@ -109,8 +109,9 @@ struct vlbm3_ctx {
   int nlev = 1;
   bool have_hierarchy = false;
   long coarse_steps = 0;
-  // measured on MI355X (256^3 blast, FP64): 512-cell tiles with non-temporal
-  // stores run the step at 0.57 of HBM peak, 256-cell tiles at 0.50, 64 at 0.23
+  // measured on MI355X (256^3 blast): with non-temporal stores, FP64 runs the
+  // step at 0.57 of HBM peak with 512-cell tiles (0.50 at 256, 0.23 at 64),
+  // the FP32 forms at 0.58-0.62 with 1024-cell tiles (0.48-0.54 at 512)
   int tile_cells = 512;
   int flags = S3_NT_STORES;
   int fp32 = 0;    // float storage
@@ -816,6 +817,7 @@ vlbm_status vlbm3_create(const vlbm3_params *params, void *stream, vlbm3_ctx **o
   c->tb = 2.0 * c->p.beta;
   c->fp32 = c->p.precision != VLBM_FP64;
   c->sflags = !c->fp32 ? 0 : S3_FP32 | (c->p.precision == VLBM_FP32_STORAGE ? S3_F64_MATH : 0);
+  c->tile_cells = c->fp32 ? 1024 : 512;
   *out = c;
   return VLBM_OK;
 }
