@@ -385,8 +385,9 @@ def main():
     esz = 8 if prec == vlbm.FP64 else 4
     bytes_per_update = 2 * 16 * esz
     nl = sum(v[1] for v in ktimes.values()) / prof_steps
-    if sensor:  # stage 2 before every step launch
-        nl = 2 * nl
+    if sensor:  # the next-Qmax clear once per coarse step; the SEN step also
+        nl = nl + 1  # reads W (32 B), writes W (32 B) and beta (8 B), reads the mask (1 B)
+        bytes_per_update += 73
     # dominant kernel: the (level, launch form) with the largest kernel time;
     # algorithmic bytes of one launch: 16 populations read and 16 written per
     # active cell it advances (a fused launch keeps the finest level's

@@ -226,9 +226,12 @@ vlbm_status vlbm_autotune(vlbm_ctx *ctx, int steps_per_trial, int *tile_cells, i
  * itself in the differences and is left out of the mean. Arithmetic in FP64
  * for every precision. Needs 0 < beta_min <= beta_max <= 1 and c_sensor >= 0
  * (VLBM_EINVAL otherwise). While on, fused sub-steps (tuning flag 16) and two
- * cells per thread (flag 2) are not used, and each level holds 6 more FP64
- * planes of its frame (not counted by vlbm_footprint_bytes). on = 0 returns
- * to the constant beta. Keeps the state and the time history. */
+ * cells per thread (flag 2) are not used, the step tiles are at most 32 x 8
+ * cells whatever tile_cells says (each step workgroup computes its tile's
+ * sensor in LDS), and each level holds 9 more FP64 planes of its frame (two
+ * W sets and beta; not counted by vlbm_footprint_bytes). on = 0 returns to
+ * the constant beta. Switching rebuilds the tile lists; it keeps the state
+ * and the time history. */
 vlbm_status vlbm_set_sensor(vlbm_ctx *ctx, int on, double c_sensor, double beta_min,
                             double beta_max);
 

@@ -779,6 +779,7 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
     Work &w = W[l];
     // tiles: runs of active cells per row, stacked into rectangles of <= TC cells
     L.tiles.clear();
+    const bool sen_tiles = c->sensor;
     struct Open { int xa, xb, y0, h; };
     std::vector<Open> open, nopen;
     std::vector<std::pair<int, int>> rect_xy;  // (x0, y0) of each emitted tile
@@ -807,17 +808,24 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
         const int xa = x;
         for (uint64_t v; x + 8 <= L.fw && (memcpy(&v, row + x, 8), v == ones);) x += 8;
         while (x < L.fw && row[x] == 1) ++x;
-        const int a = L.fx0 + xa, b = L.fx0 + x, maxh = std::max(1, TC / (b - a));
-        while (j < open.size() && open[j].xa < a) emit(open[j++]);
-        if (j < open.size() && open[j].xa == a && open[j].xb == b) {
-          if (open[j].h < maxh) {
-            nopen.push_back({a, b, open[j].y0, open[j].h + 1});
-            ++j;
-            continue;
+        // with the adaptive relaxation, runs are cut on a SEN_TW grid from the
+        // frame's first interior column and stacked at most SEN_TH high
+        for (int ca = L.fx0 + xa; ca < L.fx0 + x;) {
+          const int cb = sen_tiles ? std::min(L.fx0 + x, L.fx0 + 1 + ((ca - L.fx0 - 1) / SEN_TW + 1) * SEN_TW)
+                                   : L.fx0 + x;
+          const int a = ca, b = cb, maxh = sen_tiles ? SEN_TH : std::max(1, TC / (b - a));
+          ca = cb;
+          while (j < open.size() && open[j].xa < a) emit(open[j++]);
+          if (j < open.size() && open[j].xa == a && open[j].xb == b) {
+            if (open[j].h < maxh) {
+              nopen.push_back({a, b, open[j].y0, open[j].h + 1});
+              ++j;
+              continue;
+            }
+            emit(open[j++]);
           }
-          emit(open[j++]);
+          nopen.push_back({a, b, y, 1});
         }
-        nopen.push_back({a, b, y, 1});
       }
       while (j < open.size()) emit(open[j++]);
       open.swap(nopen);
@@ -1170,6 +1178,10 @@ vlbm_status build_tables(vlbm_ctx *c) {
   c->phases.clear();
   schedule(0, 1, c->nlev, c->p.r, c->phases, fused_active(c));
   const size_t P = c->phases.size();
+  if (c->sensor)  // the SEN step keeps its tile's neighbourhood in LDS
+    for (int l = 0; l < c->nlev; ++l)
+      for (const Tile &t : c->lv[l].tiles)
+        if (t.w > SEN_TW || t.h > SEN_TH) return fail(VLBM_EINVAL, "internal: tile larger than the sensor's LDS");
   // buffer flips of each level per coarse step: one per phase
   for (int l = 0; l < kMaxLevels; ++l) c->flips[l] = 0;
   for (const auto &ph : c->phases) c->flips[ph.first] += 1;
@@ -1201,6 +1213,10 @@ vlbm_status build_tables(vlbm_ctx *c) {
         D.qmax = c->dqmax + 4 * e;
         D.qmax_next = c->dqmax + 4 * (e ^ 1);
         D.clear_next = p == 0;
+        const Level &L = c->lv[l];
+        const bool odd = (st[l] & 1) != 0;
+        D.wcur = L.dsen + (odd ? SEN_W1 : SEN_W0) * L.plane;
+        D.wnext = L.dsen + (odd ? SEN_W0 : SEN_W1) * L.plane;
         size_t last = p;
         for (size_t q = p + 1; q < P; ++q)
           if (c->phases[q].first == l) last = q;
@@ -1309,7 +1325,14 @@ vlbm_status launch_coarse_step(vlbm_ctx *c, int e) {
     HIPCHK(launch_cfl(a, c->fp32, c->dcmax, c->ddyn, c->stream));
     HIPCHK(launch_cfl_finalize(c->ddyn, c->dcmax, c->stream));
   }
-  for (const LaunchRec &r : c->launches) {
+  for (size_t ri = 0; ri < c->launches.size(); ++ri) {
+    const LaunchRec &r = c->launches[ri];
+    if (c->sensor && ri == 0) {  // clear the next coarse step's Qmax slot
+      StepLaunch a{};
+      a.d0 = c->hseg[e * c->nseg_table + r.seg0].d;
+      a.nblocks = 1;
+      HIPCHK(launch_sensor(a, 1, c->fp32, c->stream));
+    }
     if (r.nblocks <= 0) continue;
     StepLaunch a{};
     const int s0 = e * c->nseg_table + r.seg0;
@@ -1324,10 +1347,7 @@ vlbm_status launch_coarse_step(vlbm_ctx *c, int e) {
     a.first = r.first;
     a.flags = c->step_flags | (r.fused_kernel ? STEP_FUSED_PHASE : 0) | (c->adt ? STEP_ADAPTIVE_DT : 0);
     a.ak = r.ak;
-    if (c->sensor && !r.fused_kernel) {  // per-cell beta from the state at the start of the step
-      HIPCHK(launch_sensor(a, 2, c->fp32, c->stream));
-      a.flags |= STEP_SENSOR;
-    }
+    if (c->sensor && !r.fused_kernel) a.flags |= STEP_SENSOR;  // per-cell beta
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->prof) {
       if (c->pend.size() >= 4096) {
@@ -1590,6 +1610,7 @@ vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes, bool res
   t->esz = c->esz;
   t->tile_cells = c->tile_cells;
   t->step_flags = c->step_flags;
+  t->sensor = c->sensor;  // tile shapes follow it
   int nlev = 0;
   for (int l = 0; l < kMaxLevels; ++l) {
     frame_of(c->p, c->esz, g, l, t->lv[l]);
@@ -2104,6 +2125,7 @@ vlbm_status vlbm_set_hierarchy(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
   t->esz = c->esz;
   t->tile_cells = c->tile_cells;
   t->step_flags = c->step_flags;
+  t->sensor = c->sensor;  // tile shapes follow it
   int nlev = 0;
   for (int l = 0; l < kMaxLevels; ++l) {
     frame_of(c->p, c->esz, g, l, t->lv[l]);
@@ -2477,7 +2499,10 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
         L.ak = ak_of(ph[p].second, r);
         hipError_t err = hipSuccess;
         if (c0->sensor) {
-          err = launch_sensor(L, 2, c0->fp32, c0->stream);
+          // a context whose first phase this is clears its next Qmax slot first
+          bool first_of_some = false;
+          for (size_t a = 0; a < act.size(); ++a) first_of_some |= occ_index[a][p] == 0;
+          if (first_of_some) err = launch_sensor(L, 1, c0->fp32, c0->stream);
           L.flags |= STEP_SENSOR;
         }
         if (err == hipSuccess) err = launch_step(L, c0->fp32, c0->stream);
@@ -2581,6 +2606,7 @@ vlbm_status vlbm_set_sensor(vlbm_ctx *c, int on, double c_sensor, double beta_mi
   if (!c) return fail(VLBM_EINVAL, "null context");
   if (on && !(beta_min > 0.0 && beta_min <= beta_max && beta_max <= 1.0 && c_sensor >= 0.0))
     return fail(VLBM_EINVAL, "adaptive relaxation needs 0 < beta_min <= beta_max <= 1 and C >= 0");
+  const bool was = c->sensor;
   c->sensor = on != 0;
   if (c->sensor) {
     c->c_sensor = c_sensor;
@@ -2588,6 +2614,12 @@ vlbm_status vlbm_set_sensor(vlbm_ctx *c, int on, double c_sensor, double beta_mi
     c->beta_max = beta_max;
   }
   if (!c->have_hierarchy) return VLBM_OK;
+  if (was != c->sensor) {
+    // the step tiles change shape (SEN_TW x SEN_TH with the sensor): same
+    // hierarchy and time history, new lists
+    std::vector<vlbm_box> boxes = c->boxes;
+    return regrid_impl(c, boxes.data(), (int)boxes.size(), false);
+  }
   // same buffers and time history; descriptors, planes and fusion follow the setting
   return build_tables(c);
 }

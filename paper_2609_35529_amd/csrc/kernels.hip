@@ -296,29 +296,20 @@ __device__ __forceinline__ void tile_origin(const LevelDesc &A, const Tile &tl, 
   y0 = A.fy0 + fy;
 }
 
-// beta = beta_max - (beta_max - beta_min) clip(C sbar theta, 0, 1) of the cell
-// at offset o, level (x, y): sbar the mean of a over the active cells of its
-// 3 x 3 block (row by row from (x - 1, y - 1)), theta its own.
-__device__ __forceinline__ double cell_beta(__attribute__((address_space(1))) const double *Sp,
-                                            int mk, int64_t P, int64_t o, int x, int y, int pitch,
-                                            int Nx, int Ny, double cs, double bmax, double bspan) {
-  double sum = 0.0;
-  int cnt = 0;
-#pragma unroll
-  for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-    for (int dx = -1; dx <= 1; ++dx) {
-      if (dx == 0 && dy == 0) {
-        sum += Sp[SEN_A * P + o];
-        ++cnt;
-      } else if ((mk >> mask_bit(dx, dy)) & 1) {
-        sum += Sp[SEN_A * P + nb_offset(o, x, y, dx, dy, pitch, Nx, Ny)];
-        ++cnt;
-      }
-    }
-  double z = (cs * (sum / (double)cnt)) * Sp[SEN_BETA * P + o];
-  z = z < 0.0 ? 0.0 : z > 1.0 ? 1.0 : z;
-  return bmax - bspan * z;
+// Walk from the tile cell at offset o, level (x, y), by (dx, dy) with
+// |dx|, |dy| <= 1: the step is taken only where the cell's mask marks the
+// target as an active neighbour (then o, x, y become the target's, periodic
+// sides wrapped); returns whether it was.
+__device__ __forceinline__ bool mask_step(const __attribute__((address_space(1))) uint8_t *M, int64_t &o,
+                                          int &x, int &y, int dx, int dy, int pitch, int Nx, int Ny) {
+  if (dx == 0 && dy == 0) return true;
+  if (!((M[o] >> mask_bit(dx, dy)) & 1)) return false;
+  o = nb_offset(o, x, y, dx, dy, pitch, Nx, Ny);
+  x += dx;
+  y += dy;
+  x = x < 0 ? x + Nx : x >= Nx ? x - Nx : x;
+  y = y < 0 ? y + Ny : y >= Ny ? y - Ny : y;
+  return true;
 }
 
 // One workgroup's work on tile `lb` of descriptor A (inlined twice below, so
@@ -349,6 +340,7 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
   // adaptive relaxation (eq. sensor-B): per-cell 2 beta in, W of the stored
   // result out, and on a level's last step of the coarse step the next max |Q|
   const auto Sp = (gptr<double>)(SEN ? A.sen : nullptr);
+  const auto Wn = (gptr<double>)(SEN ? A.wnext : nullptr);
   const auto M = (__attribute__((address_space(1))) const uint8_t *)(SEN ? A.mask : nullptr);
   const bool emit = SEN && A.emit_qmax != 0;
   const EosT<double> eosd = eos_of<double>(A);
@@ -363,6 +355,83 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
     __syncthreads();
   }
   const int n = tl.w * tl.h;
+  // Adaptive relaxation (eq. sensor-B) from the W set of the input time level,
+  // in LDS: (A) flux and velocity of every active cell within two cells of
+  // the tile, each computed once; (B) activity a of the tile and of its
+  // one-cell ring and gate theta of the tile, from (A). A cell beyond the tile
+  // is reached by at most two mask-checked steps from the nearest tile cell
+  // (diagonal first), so only active cells are read and no read leaves the
+  // frame; a cell two steps out is used only by the ring cell it is reached
+  // through.
+  [[maybe_unused]] const int w2 = tl.w + 2;
+  double *a_l = nullptr, *th_l = nullptr;
+  if constexpr (SEN) {
+    __shared__ double qx_l[4][SEN_BLOCK], qy_l[4][SEN_BLOCK], u_l[SEN_BLOCK], v_l[SEN_BLOCK];
+    __shared__ double a_lds[SEN_RING], th_lds[SEN_TW * SEN_TH];
+    a_l = a_lds;
+    th_l = th_lds;
+    const auto Wc = (__attribute__((address_space(1))) const double *)A.wcur;
+    const int bw = tl.w + 4, nb = bw * (tl.h + 4);
+    for (int p = threadIdx.x; p < nb; p += blockDim.x) {
+      const int j = p / bw - 2, i = p - (j + 2) * bw - 2;
+      const int ci = i < 0 ? 0 : i >= tl.w ? tl.w - 1 : i, cj = j < 0 ? 0 : j >= tl.h ? tl.h - 1 : j;
+      const int di = i - ci, dj = j - cj;
+      if ((di == 2 || di == -2) && (dj == 2 || dj == -2)) continue;  // block corners: never used
+      int64_t o = (int64_t)tl.off0 + (int64_t)cj * pitch + ci;
+      int x = x0 + ci, y = y0 + cj;
+      const int sx = (di > 0) - (di < 0), sy = (dj > 0) - (dj < 0);
+      if (!mask_step(M, o, x, y, sx, sy, pitch, Nx, Ny)) continue;
+      if (!mask_step(M, o, x, y, di - sx, dj - sy, pitch, Nx, Ny)) continue;
+      double w[4], qx[4], qy[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) w[k] = Wc[k * plane + o];
+      euler_flux(eosd, w, qx, qy);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        qx_l[k][p] = qx[k];
+        qy_l[k][p] = qy[k];
+      }
+      u_l[p] = w[1] / w[0];
+      v_l[p] = w[2] / w[0];
+    }
+    __syncthreads();
+    double qm[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) qm[k] = __longlong_as_double((long long)A.qmax[k]);
+    const int nr = w2 * (tl.h + 2);
+    for (int p = threadIdx.x; p < nr; p += blockDim.x) {
+      const int j = p / w2 - 1, i = p - (j + 1) * w2 - 1;
+      const int ci = i < 0 ? 0 : i >= tl.w ? tl.w - 1 : i, cj = j < 0 ? 0 : j >= tl.h ? tl.h - 1 : j;
+      int64_t o = (int64_t)tl.off0 + (int64_t)cj * pitch + ci;
+      int x = x0 + ci, y = y0 + cj;
+      double a = 0.0, th = 0.0;
+      if (mask_step(M, o, x, y, i - ci, j - cj, pitch, Nx, Ny)) {
+        // s_k from the four neighbours' fluxes over this coarse step's Qmax,
+        // a their RMS; theta from dilatation and vorticity. A neighbour that
+        // is not an active cell stands in as the cell itself.
+        const int mk = M[o];
+        const int pb = (j + 2) * bw + i + 2;
+        constexpr int DX[4] = {1, -1, 0, 0}, DY[4] = {0, 0, 1, -1};
+        int e[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) e[d] = (mk >> mask_bit(DX[d], DY[d])) & 1 ? pb + DX[d] + DY[d] * bw : pb;
+        double sk[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double dq = (qx_l[k][e[0]] - qx_l[k][e[1]]) + (qy_l[k][e[2]] - qy_l[k][e[3]]);
+          sk[k] = qm[k] > 0.0 ? (0.5 * dq) / qm[k] : 0.0;
+        }
+        a = sqrt(0.25 * (((sk[0] * sk[0] + sk[1] * sk[1]) + sk[2] * sk[2]) + sk[3] * sk[3]));
+        const double dil = 0.5 * ((u_l[e[0]] - u_l[e[1]]) + (v_l[e[2]] - v_l[e[3]]));
+        const double vort = 0.5 * ((v_l[e[0]] - v_l[e[1]]) - (u_l[e[2]] - u_l[e[3]]));
+        const double den = dil * dil + vort * vort;
+        th = (dil < 0.0 && den > 0.0) ? (dil * dil) / den : 0.0;
+      }
+      a_l[p] = a;
+      if (i == ci && j == cj) th_l[j * tl.w + i] = th;
+    }
+    __syncthreads();
+  }
   if (TWO && !SEN) {
     // two cells per thread, both gathers issued before either relaxation
     for (int c = threadIdx.x; c < n; c += 2 * blockDim.x) {
@@ -393,7 +462,25 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
       pull<T, C>(s, plane, pitch, o, g);
       C tbc = tb;
       if (SEN) {
-        const double beta = cell_beta(Sp, M[o], plane, o, x0 + cx, y0 + cy, pitch, Nx, Ny, cs, bmax, bspan);
+        // beta = beta_max - (beta_max - beta_min) clip(C sbar theta, 0, 1),
+        // sbar the mean of a over the active cells of the 3 x 3 block, summed
+        // row by row from (x - 1, y - 1)
+        const int mk = M[o];
+        const int pc = (cy + 1) * w2 + cx + 1;
+        double sum = 0.0;
+        int cnt = 0;
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+          for (int dx = -1; dx <= 1; ++dx) {
+            if ((dx == 0 && dy == 0) || ((mk >> mask_bit(dx, dy)) & 1)) {
+              sum += a_l[pc + dy * w2 + dx];
+              ++cnt;
+            }
+          }
+        double z = (cs * (sum / (double)cnt)) * th_l[c];
+        z = z < 0.0 ? 0.0 : z > 1.0 ? 1.0 : z;
+        const double beta = bmax - bspan * z;
         Sp[SEN_BETA * plane + o] = beta;
         tbc = (C)(2.0 * beta);
       }
@@ -404,7 +491,7 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           w[k] = (((double)(T)g[k] + (double)(T)g[4 + k]) + (double)(T)g[8 + k]) + (double)(T)g[12 + k];
-          Sp[(SEN_W + k) * plane + o] = w[k];
+          Wn[k * plane + o] = w[k];
         }
         if (emit) flux_absmax(eosd, w, m);
       }
@@ -727,15 +814,18 @@ hipError_t launch_step(const StepLaunch &a, int fp32, hipStream_t s, hipEvent_t 
 // side, outside the frame, a hole, uncovered) stands in as the cell itself in
 // the differences and is left out of the mean.
 //
-// Pipeline. Before every step of a level, stage 2 puts a and theta into their
-// planes (the context's first phase of the coarse step also clears the next
-// Qmax slot). The step kernel (SEN variant) then takes beta from them
-// (cell_beta; beta overwrites theta in place, as a cell reads only its own
-// theta), writes W of every cell it advances into the W planes (the sums of
-// the values it stores), and on a level's last step of a coarse step
-// accumulates the next coarse step's Qmax from them. Stage 0 fills the W
-// planes of every level and this coarse step's Qmax from the stored
-// populations, once after any change of state.
+// Pipeline. The step kernel (SEN variant) computes, per tile and in LDS, the
+// fluxes of the cells within two cells of the tile, a of the tile and its
+// ring and theta of the tile, all from the W set of its input time level;
+// takes beta of every cell from them, writes beta to its plane, relaxes with
+// it, writes W of every cell it advances (the sums of the values it stores)
+// into the other W set, and on a level's last step of a coarse step
+// accumulates the next coarse step's Qmax from them. The two W sets alternate
+// with the level's step count, so no workgroup reads W that another one of
+// the same launch writes. Stage 1 clears the next Qmax slot before the
+// context's first launch of a coarse step; stage 0 fills the input W set of
+// every level and this coarse step's Qmax from the stored populations, once
+// after any change of state.
 // ---------------------------------------------------------------------------
 
 template <class T>
@@ -747,7 +837,8 @@ __global__ __launch_bounds__(256) void sensor0_kernel(StepLaunch Lc) {
   if (tid >= A.ntiles || !A.sen) return;  // uniform over the workgroup
   const Tile tl = A.tiles[tid];
   const auto s = (__attribute__((address_space(1))) const T *)A.src;
-  const auto Wp = (gptr<double>)A.sen;
+  // the W set this descriptor's step reads: the level's current time level
+  const auto Wp = (gptr<double>)const_cast<double *>(A.wcur);
   const int64_t P = A.plane;
   const int pitch = A.pitch;
   const EosT<double> eos = eos_of<double>(A);
@@ -761,65 +852,21 @@ __global__ __launch_bounds__(256) void sensor0_kernel(StepLaunch Lc) {
     for (int k = 0; k < 4; ++k) {
       w[k] = (((double)s[(0 * 4 + k) * P + o] + (double)s[(1 * 4 + k) * P + o]) +
               (double)s[(2 * 4 + k) * P + o]) + (double)s[(3 * 4 + k) * P + o];
-      Wp[(SEN_W + k) * P + o] = w[k];
+      Wp[k * P + o] = w[k];
     }
     flux_absmax(eos, w, m);
   }
   block_qmax(m, A.qmax);
 }
 
-__global__ __launch_bounds__(256) void sensor2_kernel(StepLaunch Lc) {
-  VLBM_FIND_SEGMENT(Lc, (int)blockIdx.x, dp, fb, nb)
-  (void)nb;
-  const LevelDesc &A = *dp;
-  const int tid = blockIdx.x - fb;
-  if (tid == 0 && A.clear_next && threadIdx.x < 4) A.qmax_next[threadIdx.x] = 0ull;
-  if (tid >= A.ntiles || !A.sen) return;
-  const Tile tl = A.tiles[tid];
-  const auto Sp = (gptr<double>)A.sen;
-  const auto M = (__attribute__((address_space(1))) const uint8_t *)A.mask;
-  const int64_t P = A.plane;
-  const int pitch = A.pitch;
-  const EosT<double> eos = eos_of<double>(A);
-  double qm[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) qm[k] = __longlong_as_double((long long)A.qmax[k]);
-  const int Nx = A.Nx, Ny = A.Ny;
-  int x0, y0;
-  tile_origin(A, tl, x0, y0);
-  const int n = tl.w * tl.h;
-  for (int c = threadIdx.x; c < n; c += blockDim.x) {
-    const int cy = c / tl.w, cx = c - cy * tl.w;
-    const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
-    const int x = x0 + cx, y = y0 + cy;
-    const int mk = M[o];
-    constexpr int DX[4] = {1, -1, 0, 0}, DY[4] = {0, 0, 1, -1};
-    double Qd[4][4], u[4], v[4];  // Qd: Qx of the x neighbours, Qy of the y neighbours
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      const int64_t e = (mk >> mask_bit(DX[d], DY[d])) & 1 ? nb_offset(o, x, y, DX[d], DY[d], pitch, Nx, Ny) : o;
-      double w[4], qx[4], qy[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) w[k] = Sp[(SEN_W + k) * P + e];
-      euler_flux(eos, w, qx, qy);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) Qd[d][k] = d < 2 ? qx[k] : qy[k];
-      u[d] = w[1] / w[0];
-      v[d] = w[2] / w[0];
-    }
-    double sk[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const double dq = (Qd[0][k] - Qd[1][k]) + (Qd[2][k] - Qd[3][k]);
-      sk[k] = qm[k] > 0.0 ? (0.5 * dq) / qm[k] : 0.0;
-    }
-    const double a = sqrt(0.25 * (((sk[0] * sk[0] + sk[1] * sk[1]) + sk[2] * sk[2]) + sk[3] * sk[3]));
-    const double dil = 0.5 * ((u[0] - u[1]) + (v[2] - v[3]));
-    const double vort = 0.5 * ((v[0] - v[1]) - (u[2] - u[3]));
-    const double den = dil * dil + vort * vort;
-    const double th = (dil < 0.0 && den > 0.0) ? (dil * dil) / den : 0.0;
-    Sp[SEN_A * P + o] = a;
-    Sp[SEN_BETA * P + o] = th;
+// Stage 1: clear the next coarse step's max |Q| slot of every descriptor of
+// the launch that is its context's first phase (the slot the previous coarse
+// step read as its Qmax; this coarse step's last steps accumulate into it).
+__global__ __launch_bounds__(64) void sensor_clear_kernel(StepLaunch Lc) {
+  const int ns = Lc.nseg > 0 ? Lc.nseg : 1;
+  for (int i = threadIdx.x; i < 4 * ns; i += blockDim.x) {
+    const LevelDesc *D = Lc.nseg > 0 ? Lc.segs[i >> 2].d : Lc.d0;
+    if (D->sen && D->clear_next) D->qmax_next[i & 3] = 0ull;
   }
 }
 
@@ -872,8 +919,8 @@ hipError_t launch_sensor(const StepLaunch &a, int stage, int fp32, hipStream_t s
       hipLaunchKernelGGL(sensor0_kernel<float>, grid, block, 0, s, a);
     else
       hipLaunchKernelGGL(sensor0_kernel<double>, grid, block, 0, s, a);
-  } else if (stage == 2) {
-    hipLaunchKernelGGL(sensor2_kernel, grid, block, 0, s, a);
+  } else if (stage == 1) {
+    hipLaunchKernelGGL(sensor_clear_kernel, dim3(1), dim3(64), 0, s, a);
   } else {
     return hipErrorInvalidValue;
   }

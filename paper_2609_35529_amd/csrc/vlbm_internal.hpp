@@ -109,10 +109,18 @@ enum DynSlot : int32_t {
 };
 
 // Adaptive relaxation planes of a level (FP64, `plane` elements each, same
-// element offsets as the populations): W_0..W_3 of the current time level
-// (written by the step that produced it), the activity a, and theta
-// (overwritten in place by beta).
-enum SensorPlane : int32_t { SEN_W = 0, SEN_A = 4, SEN_BETA = 5, SEN_PLANES = 6 };
+// element offsets as the populations): two sets of W_0..W_3, one per parity
+// of the level's step count (a step reads the set of its input time level
+// and writes the other one), and beta of the last step.
+enum SensorPlane : int32_t { SEN_W0 = 0, SEN_W1 = 4, SEN_BETA = 8, SEN_PLANES = 9 };
+
+// With the adaptive relaxation the step tiles are at most SEN_TW x SEN_TH
+// cells. A step workgroup keeps in LDS the fluxes and velocities of the
+// active cells within two cells of its tile (a (w + 4) x (h + 4) block) and
+// the activity of the tile and its one-cell ring ((w + 2) x (h + 2)).
+constexpr int SEN_TW = 32, SEN_TH = 8;
+constexpr int SEN_BLOCK = (SEN_TW + 4) * (SEN_TH + 4);
+constexpr int SEN_RING = (SEN_TW + 2) * (SEN_TH + 2);
 
 // Neighbour mask of an active cell (one byte per frame element): bit
 // (dy + 1) * 3 + (dx + 1), the centre bit 4 left out (bits 5..8 stored one
@@ -143,10 +151,13 @@ struct LevelDesc {
   double win[4][4];          // inflow conserved states per side
   // adaptive relaxation (eq. sensor-B); sen == nullptr when it is off
   double *sen;               // SEN_PLANES planes (SensorPlane)
+  const double *wcur;        // the W set of this step's input time level
+  double *wnext;             // the W set of its output
   const uint8_t *mask;       // neighbour masks (mask_bit), `plane` bytes
   unsigned long long *qmax;       // [4] max |Q_{alpha,k}| of this coarse step, as bits
   unsigned long long *qmax_next;  // [4] the next coarse step's, accumulated by its last steps
-  int32_t clear_next;        // this phase is the context's first of the coarse step: clear qmax_next
+  int32_t clear_next;        // this phase is the context's first of the coarse step: qmax_next is
+                             // cleared (stage 1) before it
   int32_t emit_qmax;         // this phase is the level's last of the coarse step: accumulate qmax_next
   int32_t fx0, fy0, xoff;    // frame origin (level cells)
   int32_t Nx, Ny;            // level domain
@@ -193,11 +204,11 @@ struct RectArgs {
 // Launchers (kernels.hip). All return hipError_t of the launch.
 hipError_t launch_step(const StepLaunch &a, int fp32, hipStream_t s, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr);
-// Adaptive relaxation: stage 0 (W planes of every level and the coarse step's
-// max |Q| from the stored populations, over the first-phase descriptors of
-// every level; after any change of state) or stage 2 (activity and gate) over
-// the tiles of the step launch `a` (same segments and descriptors), to run
-// just before it.
+// Adaptive relaxation: stage 0 (the input W set of every level and the coarse
+// step's max |Q| from the stored populations, over the first-phase
+// descriptors of every level; after any change of state) or stage 1 (one
+// workgroup: clear qmax_next of every descriptor of the launch `a` that has
+// clear_next, to run just before the step launch `a`).
 hipError_t launch_sensor(const StepLaunch &a, int stage, int fp32, hipStream_t s);
 // Adaptive time step: the CFL bound max(|u_alpha| + c_s) over the step tiles of
 // the launch (every level at the coarse step's start) into *cmax (bits), then
