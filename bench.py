@@ -32,9 +32,9 @@ HBM_PEAK_GBS = 8000.0
 # x 1.000 (scales measured on a plain 2 GiB copy); valid only for the kernel
 # source it was measured on. The fused tile shape does not depend on
 # tile_cells, so any tile_cells matches.
-MEASURED_TRAFFIC = {"kernel_sha256_16": "38f0ba9bfaa29201", "workload": "quadrant512",
+MEASURED_TRAFFIC = {"kernel_sha256_16": "c431598a23f890cd", "workload": "quadrant512",
                     "precision": "fp64", "tile_cells": None, "flags": 20, "kernel": "fused_kernel",
-                    "bytes_per_launch": 75366049.0}
+                    "bytes_per_launch": 75414748.0}
 
 
 # dynamic-refinement workloads: re-tag and regrid every few coarse steps
@@ -385,8 +385,11 @@ def main():
     esz = 8 if prec == vlbm.FP64 else 4
     bytes_per_update = 2 * 16 * esz
     nl = sum(v[1] for v in ktimes.values()) / prof_steps
-    if sensor:  # the next-Qmax clear once per coarse step; the SEN step also
-        nl = nl + 1  # reads W (32 B), writes W (32 B) and beta (8 B), reads the mask (1 B)
+    if sensor:
+        # a separate next-Qmax clear per coarse step only where the finest
+        # level takes one step per coarse step; the SEN step also reads W
+        # (32 B), writes W (32 B) and beta (8 B) and reads the mask (1 B)
+        nl = nl + (1 if case.nlev == 1 or case.r == 1 else 0)
         bytes_per_update += 73
     # dominant kernel: the (level, launch form) with the largest kernel time;
     # algorithmic bytes of one launch: 16 populations read and 16 written per

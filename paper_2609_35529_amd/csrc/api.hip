@@ -1327,7 +1327,8 @@ vlbm_status launch_coarse_step(vlbm_ctx *c, int e) {
   }
   for (size_t ri = 0; ri < c->launches.size(); ++ri) {
     const LaunchRec &r = c->launches[ri];
-    if (c->sensor && ri == 0) {  // clear the next coarse step's Qmax slot
+    if (c->sensor && ri == 0 && c->hdesc[e * c->phases.size()].emit_qmax) {
+      // the first phase also accumulates the next Qmax: clear its slot first
       StepLaunch a{};
       a.d0 = c->hseg[e * c->nseg_table + r.seg0].d;
       a.nblocks = 1;
@@ -2499,10 +2500,15 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
         L.ak = ak_of(ph[p].second, r);
         hipError_t err = hipSuccess;
         if (c0->sensor) {
-          // a context whose first phase this is clears its next Qmax slot first
-          bool first_of_some = false;
-          for (size_t a = 0; a < act.size(); ++a) first_of_some |= occ_index[a][p] == 0;
-          if (first_of_some) err = launch_sensor(L, 1, c0->fp32, c0->stream);
+          // a context whose first phase this is, and which also accumulates
+          // the next Qmax in it, has its slot cleared first
+          bool clear = false;
+          for (size_t a = 0; a < act.size(); ++a) {
+            const vlbm_ctx *ca = ctxs[act[a]];
+            const int ei = table_parity(ca) ^ e;
+            clear |= occ_index[a][p] == 0 && ca->hdesc[ei * ca->phases.size()].emit_qmax;
+          }
+          if (clear) err = launch_sensor(L, 1, c0->fp32, c0->stream);
           L.flags |= STEP_SENSOR;
         }
         if (err == hipSuccess) err = launch_step(L, c0->fp32, c0->stream);

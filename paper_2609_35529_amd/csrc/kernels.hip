@@ -355,6 +355,9 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
     __syncthreads();
   }
   const int n = tl.w * tl.h;
+  // the context's first phase clears the next coarse step's Qmax slot when it
+  // does not accumulate into it itself (else stage 1 cleared it before)
+  if (SEN && A.clear_next && !A.emit_qmax && lb == 0 && threadIdx.x < 4) A.qmax_next[threadIdx.x] = 0ull;
   // Adaptive relaxation (eq. sensor-B) from the W set of the input time level,
   // in LDS: (A) flux and velocity of every active cell within two cells of
   // the tile, each computed once; (B) activity a of the tile and of its
@@ -822,8 +825,9 @@ hipError_t launch_step(const StepLaunch &a, int fp32, hipStream_t s, hipEvent_t 
 // into the other W set, and on a level's last step of a coarse step
 // accumulates the next coarse step's Qmax from them. The two W sets alternate
 // with the level's step count, so no workgroup reads W that another one of
-// the same launch writes. Stage 1 clears the next Qmax slot before the
-// context's first launch of a coarse step; stage 0 fills the input W set of
+// the same launch writes. The context's first launch of a coarse step clears
+// the next Qmax slot (workgroup 0), or stage 1 does just before it when that
+// launch also accumulates into the slot; stage 0 fills the input W set of
 // every level and this coarse step's Qmax from the stored populations, once
 // after any change of state.
 // ---------------------------------------------------------------------------
@@ -860,13 +864,15 @@ __global__ __launch_bounds__(256) void sensor0_kernel(StepLaunch Lc) {
 }
 
 // Stage 1: clear the next coarse step's max |Q| slot of every descriptor of
-// the launch that is its context's first phase (the slot the previous coarse
-// step read as its Qmax; this coarse step's last steps accumulate into it).
+// the launch that is its context's first phase and also accumulates into
+// that slot (a level with one step per coarse step); the step kernel clears
+// it for every other first phase. The slot is the one the previous coarse
+// step read as its Qmax.
 __global__ __launch_bounds__(64) void sensor_clear_kernel(StepLaunch Lc) {
   const int ns = Lc.nseg > 0 ? Lc.nseg : 1;
   for (int i = threadIdx.x; i < 4 * ns; i += blockDim.x) {
     const LevelDesc *D = Lc.nseg > 0 ? Lc.segs[i >> 2].d : Lc.d0;
-    if (D->sen && D->clear_next) D->qmax_next[i & 3] = 0ull;
+    if (D->sen && D->clear_next && D->emit_qmax) D->qmax_next[i & 3] = 0ull;
   }
 }
 
