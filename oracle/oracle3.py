@@ -31,6 +31,7 @@ def lib():
         L.orc3_free.argtypes = [C.c_void_p]
         L.orc3_set_boxes.argtypes = [C.c_void_p, _I, C.c_int]
         L.orc3_regrid.argtypes = [C.c_void_p, _I, C.c_int]
+        L.orc3_tag.argtypes = [C.c_void_p, C.c_int, C.c_double, _U8]
         for name in ("orc3_set_state", "orc3_set_pop", "orc3_get_pop", "orc3_get_state"):
             getattr(L, name).argtypes = [C.c_void_p, C.c_int, _D]
         L.orc3_active_mask.argtypes = [C.c_void_p, C.c_int, _U8]
@@ -131,6 +132,13 @@ class Oracle3:
 
     def advance(self, n):
         lib().orc3_advance(self._h, int(n))
+
+    def tag(self, level, thr):
+        """Density-gradient refinement tags of the active cells (uint8, Nz x Ny x Nx)."""
+        t = np.zeros(self.shape(level), dtype=np.uint8)
+        if lib().orc3_tag(self._h, level, float(thr), t.ctypes.data_as(_U8)):
+            raise RuntimeError("oracle3: bad level")
+        return t
 
     def totals(self):
         T, L = np.zeros(5), np.zeros(5)

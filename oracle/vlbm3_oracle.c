@@ -612,3 +612,40 @@ int orc3_regrid(orc3 *o, const int *boxes, int nboxes) {
   }
   return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Refinement tags (Sec. 3.4, density-gradient variant)               */
+/* ------------------------------------------------------------------ */
+
+static double rho_at(const orc3 *o, int l, int x, int y, int z) {
+  const double *F = o->F[l];
+  const size_t nc = ncell(o, l), i = cid(o, l, x, y, z);
+  return ((((F[0 * nc + i] + F[5 * nc + i]) + F[10 * nc + i]) + F[15 * nc + i]) + F[20 * nc + i]) +
+         F[25 * nc + i];
+}
+
+int orc3_tag(const orc3 *o, int level, double thr, unsigned char *tags) {
+  const int l = level;
+  if (l < 0 || l >= o->nlev) return -1;
+  for (int z = 0; z < o->N[l][2]; ++z)
+    for (int y = 0; y < o->N[l][1]; ++y)
+      for (int x = 0; x < o->N[l][0]; ++x) {
+        const size_t i = cid(o, l, x, y, z);
+        tags[i] = 0;
+        if (!active3(o, l, x, y, z)) continue;
+        const double rc = rho_at(o, l, x, y, z);
+        double g = 0.0;
+        for (int a = 0; a < 3; ++a) {
+          double side[2];
+          for (int s = 0; s < 2; ++s) {
+            int p[3] = {x, y, z};
+            p[a] += s == 0 ? 1 : -1;
+            side[s] = (wrap3(o, l, p) && active3(o, l, p[0], p[1], p[2])) ? rho_at(o, l, p[0], p[1], p[2]) : rc;
+          }
+          const double ga = fabs(side[0] - side[1]) / (2.0 * rc);
+          if (ga > g) g = ga;
+        }
+        tags[i] = (unsigned char)(g > thr);
+      }
+  return 0;
+}

@@ -36,6 +36,11 @@ int orc3_advance(orc3 *o, int ncoarse);
  * (minmod slope per axis); every interface restarts its temporal
  * reconstruction. */
 int orc3_regrid(orc3 *o, const int *boxes, int nboxes);
+/* Refinement tags of the active level-l cells (Sec. 3.4, density-gradient
+ * variant): tag when max over the axes of |rho(+1) - rho(-1)| / (2 rho)
+ * exceeds thr, a neighbour that is not an active cell (periodic sides
+ * wrapped) replaced by the cell itself. tags[Nz][Ny][Nx], 0 elsewhere. */
+int orc3_tag(const orc3 *o, int level, double thr, unsigned char *tags);
 void orc3_totals(const orc3 *o, double T[5], double ledger[5]);
 int orc3_shape(const orc3 *o, int level, int shape[3]);     /* (Nx, Ny, Nz) */
 const char *orc3_error(void);

@@ -369,3 +369,71 @@ def test_split_of_linear_populations_is_exact():
     m = o.active_mask(1)
     want = np.stack([lin(Zf, Yf, Xf, i) for i in range(30)])
     assert np.allclose(G[:, m], want[:, m], rtol=0, atol=2e-15)
+
+
+# ------------------------------------------------ refinement tags (Sec. 3.4)
+def _tag_reference(rho, active, bc):
+    """Central density differences per axis with numpy: a neighbour across a
+    non-periodic side or inactive stands in as the cell itself."""
+    g = np.zeros_like(rho)
+    for ax, (a0, a1) in zip((2, 1, 0), ((bc[0], bc[1]), (bc[2], bc[3]), (bc[4], bc[5]))):
+        n = rho.shape[ax]
+        side = []
+        for s in (1, -1):
+            nb = np.roll(rho, -s, axis=ax)
+            ok = np.roll(active, -s, axis=ax)
+            if a0 != 0:  # non-periodic: the wrapped neighbour does not exist
+                idx = [slice(None)] * 3
+                idx[ax] = n - 1 if s == 1 else 0
+                ok = ok.copy()
+                ok[tuple(idx)] = False
+            side.append(np.where(ok, nb, rho))
+        g = np.maximum(g, np.abs(side[0] - side[1]) / (2 * rho))
+    return g
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("bc", [(0,) * 6, (1, 1, 2, 2, 1, 2)])
+def test_tags_match_central_differences(axis, bc):
+    """A density wave along one axis: the oracle's tags equal numpy's central
+    differences of the density it holds, thresholded; a uniform state has no
+    tag."""
+    nz, ny, nx = 10, 12, 14
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    coord, n = [(x, nx), (y, ny), (z, nz)][axis]
+    rho = 1.0 + 0.3 * np.sin(2 * np.pi * coord / n) ** 3
+    one = np.ones_like(rho)
+    o = _oracle(_cons(rho, 0.1 * one, -0.2 * one, 0.05 * one, one), bc=bc)
+    held = o.get_state(0)[0]
+    g = _tag_reference(held, np.ones(held.shape, bool), bc)
+    vals = np.unique(np.round(g, 12))
+    for q in (0.3, 0.6, 0.85):  # thresholds halfway between distinct values
+        k = int(q * (len(vals) - 1))
+        thr = 0.5 * (vals[k] + vals[k + 1])
+        assert np.min(np.abs(g - thr)) > 1e-9
+        t = o.tag(0, thr)
+        assert np.array_equal(t.astype(bool), g > thr), thr
+        assert t.any() and not t.all()
+    flat = _oracle(_cons(one, 0 * one, 0 * one, 0 * one, one), bc=bc)
+    assert not flat.tag(0, 1e-12).any()
+
+
+def test_tags_skip_holes_and_use_the_cell_for_inactive_neighbours():
+    """Two levels: cells under the patch carry no tag at level 0, and a level-0
+    cell next to the patch uses itself for the neighbour inside it; the fine
+    level is tagged from its own cells only."""
+    U0 = _random_state(8, 10, 12, RNG)
+    box = (1, 8, 6, 4, 8, 8, 8)
+    o = _oracle(U0, nlev=2, boxes=[box])
+    act0 = o.active_mask(0)
+    rho0 = o.get_state(0)[0]
+    g = _tag_reference(np.where(act0, rho0, 1.0), act0, (0,) * 6)
+    thr = np.quantile(g[act0], 0.6)
+    t = o.tag(0, thr)
+    assert not t[~act0].any()
+    assert np.array_equal(t.astype(bool), act0 & (g > thr))
+    act1 = o.active_mask(1)
+    rho1 = o.get_state(1)[0]
+    g1 = _tag_reference(np.where(act1, rho1, 1.0), act1, (0,) * 6)
+    thr1 = np.quantile(g1[act1], 0.5)
+    assert np.array_equal(o.tag(1, thr1).astype(bool), act1 & (g1 > thr1))
