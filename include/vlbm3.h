@@ -94,6 +94,25 @@ vlbm_status vlbm3_set_hierarchy(vlbm3_ctx *ctx, const vlbm3_box *boxes, int nbox
  * kept. Validation as vlbm3_set_hierarchy. Synchronises. */
 vlbm_status vlbm3_regrid(vlbm3_ctx *ctx, const vlbm3_box *boxes, int nboxes);
 
+/* Refinement tags of the active level-l cells (Sec. 3.4, density-gradient
+ * variant): max over the three axes of |rho(+1) - rho(-1)| / (2 rho) >
+ * threshold, a neighbour that is not an active cell of the level (periodic
+ * sides wrapped) replaced by the cell itself. tags[Nz_l][Ny_l][Nx_l] (host,
+ * caller-owned), 0 on cells that are not active. Synchronises. */
+vlbm_status vlbm3_tag(vlbm3_ctx *ctx, int level, double threshold, unsigned char *tags);
+
+/* Tag every present level below max_levels - 1, mark the parents of tagged
+ * finer cells, dilate by `buffer` cells and cluster, coarsest level first,
+ * into boxes of level l+1 on a grid of tiles of ceil(min_box / r) level-l
+ * cells per axis (boxes of at most max_box level-(l+1) cells per axis, tiles
+ * taken only where they and the cells beside their faces are covered, so the
+ * boxes nest), then vlbm3_regrid to them (Sec. 3.4, Fig. amr-flowchart).
+ * VLBM_EINVAL unless 0 <= buffer and 1 <= min_box <= max_box. Synchronises. */
+vlbm_status vlbm3_tag_and_regrid(vlbm3_ctx *ctx, double threshold, int buffer, int min_box, int max_box);
+
+/* The current boxes (up to cap of them) and their count. */
+vlbm_status vlbm3_get_boxes(vlbm3_ctx *ctx, vlbm3_box *boxes, int cap, int *nboxes);
+
 /* f := f^eq(U) on the covered cells of the rectangle; clears the previous-step
  * samples of those cells and the boundary ledger. */
 vlbm_status vlbm3_set_state(vlbm3_ctx *ctx, int level, int i0, int j0, int k0, int nx, int ny,

@@ -803,6 +803,270 @@ vlbm_status build_geometry3(const vlbm3_params &p, const vlbm3_box *boxes, int n
 
 }  // namespace
 
+namespace {
+
+// --------------------------------------------------------------------------
+// Tagging and clustering (Sec. 3.4, Fig. amr-flowchart, in 3-D)
+// --------------------------------------------------------------------------
+struct TagMap3 {  // one byte per frame cell of a level, frame order
+  int o[3] = {0, 0, 0}, n[3] = {0, 0, 0};
+  std::vector<uint8_t> t;
+  uint8_t &at(int x, int y, int z) { return t[((size_t)(z - o[2]) * n[1] + (y - o[1])) * n[0] + (x - o[0])]; }
+};
+
+struct CovMap3 {  // coverage of a level over a box of its cells (all: everything)
+  bool all = true;
+  int o[3] = {0, 0, 0}, n[3] = {0, 0, 0};
+  std::vector<uint8_t> m;
+  bool at(int x, int y, int z) const {
+    if (all) return true;
+    const int p[3] = {x - o[0], y - o[1], z - o[2]};
+    for (int a = 0; a < 3; ++a)
+      if (p[a] < 0 || p[a] >= n[a]) return false;
+    return m[((size_t)p[2] * n[1] + p[1]) * n[0] + p[0]] != 0;
+  }
+};
+
+// Tags of every active cell of level l's frame (device kernel, then to host).
+vlbm_status tag_frame3(vlbm3_ctx *c, int l, double thr, TagMap3 &T) {
+  const Level3 &L = c->lv[l];
+  const size_t n = (size_t)L.fn[0] * L.fn[1] * L.fn[2];
+  for (int a = 0; a < 3; ++a) {
+    T.o[a] = L.f0[a];
+    T.n[a] = L.fn[a];
+  }
+  T.t.assign(n, 0);
+  uint8_t *dt = nullptr;
+  HIPCHK3(hipMalloc((void **)&dt, n));
+  Tag3Args a{};
+  a.buf = L.buf[L.cur()];
+  a.status = L.dstatus;
+  a.tags = dt;
+  a.plane = L.plane;
+  a.slab = L.slab;
+  a.pitch = L.pitch;
+  a.xoff = L.xoff;
+  for (int k = 0; k < 3; ++k) {
+    a.f0[k] = L.f0[k];
+    a.fn[k] = L.fn[k];
+    a.N[k] = L.N[k];
+    a.periodic |= c->periodic(k) ? 1 << k : 0;
+  }
+  a.thr = thr;
+  hipError_t e = launch_tag3(a, c->fp32, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(T.t.data(), dt, n, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(dt);
+  if (e != hipSuccess) return fail3(VLBM_EDEVICE, "tags: %s", hipGetErrorString(e));
+  return VLBM_OK;
+}
+
+// Tiles of T cells (per axis) of level l reached by a range [a, b] of cells
+// along an axis of n cells (periodic: wrapped), appended to v.
+void tiles_in3(int a, int b, int n, int T, bool periodic, std::vector<int> &v) {
+  v.clear();
+  if (periodic && b - a + 1 >= n) a = 0, b = n - 1, periodic = false;
+  if (!periodic) {
+    a = std::max(a, 0);
+    b = std::min(b, n - 1);
+    for (int t = a / T; a <= b && t <= b / T; ++t) v.push_back(t);
+    return;
+  }
+  const int am = ((a % n) + n) % n, bm = ((b % n) + n) % n;
+  if (am <= bm) {
+    for (int t = am / T; t <= bm / T; ++t) v.push_back(t);
+  } else {  // wraps: [am, n) and [0, bm]
+    for (int t = 0; t <= bm / T; ++t) v.push_back(t);
+    for (int t = am / T; t <= (n - 1) / T; ++t)
+      if (v.empty() || t > v.back()) v.push_back(t);
+  }
+}
+
+// Boxes of level l+1 over the tagged cells of level l, dilated by `buffer`
+// cells: a grid of tiles of T = ceil(min_box / r) level-l cells per axis; a
+// tile is taken when the dilation reaches it and it, and the cells beside
+// its six faces, are covered at level l (so the boxes nest); taken tiles are
+// merged greedily into runs of at most maxT tiles along x, stacked along y
+// while identical, then along z while identical.
+void cluster_level3(const vlbm3_ctx *c, int l, const TagMap3 &tags, const CovMap3 &cov, int buffer,
+                    int min_box, int max_box, std::vector<vlbm3_box> &out) {
+  const int r = c->p.r;
+  const Level3 &L = c->lv[l];
+  const int T = std::max(1, (min_box + r - 1) / r);
+  const int maxT = std::max(1, max_box / (T * r));
+  int nt[3];
+  bool per[3];
+  for (int a = 0; a < 3; ++a) {
+    nt[a] = (L.N[a] + T - 1) / T;
+    per[a] = c->periodic(a);
+  }
+  auto tid = [&](int tx, int ty, int tz) { return ((size_t)tz * nt[1] + ty) * nt[0] + tx; };
+  std::vector<uint8_t> hit((size_t)nt[0] * nt[1] * nt[2], 0);
+  std::vector<int> xs, ys, zs;
+  for (int fz = 0; fz < tags.n[2]; ++fz)
+    for (int fy = 0; fy < tags.n[1]; ++fy) {
+      const uint8_t *row = &tags.t[((size_t)fz * tags.n[1] + fy) * tags.n[0]];
+      const int y = tags.o[1] + fy, z = tags.o[2] + fz;
+      bool any = false;
+      int fx = 0;
+      while (fx < tags.n[0]) {
+        if (!row[fx]) {
+          ++fx;
+          continue;
+        }
+        const int xa = fx;
+        while (fx < tags.n[0] && row[fx]) ++fx;
+        if (!any) {
+          tiles_in3(y - buffer, y + buffer, L.N[1], T, per[1], ys);
+          tiles_in3(z - buffer, z + buffer, L.N[2], T, per[2], zs);
+          any = true;
+        }
+        tiles_in3(tags.o[0] + xa - buffer, tags.o[0] + fx - 1 + buffer, L.N[0], T, per[0], xs);
+        for (int tz : zs)
+          for (int ty : ys)
+            for (int tx : xs) hit[tid(tx, ty, tz)] = 1;
+      }
+    }
+  // covered at level l; true outside a non-periodic side
+  auto covered_at = [&](int x, int y, int z) {
+    int p[3] = {x, y, z};
+    for (int a = 0; a < 3; ++a)
+      if (p[a] < 0 || p[a] >= L.N[a]) {
+        if (!per[a]) return true;
+        p[a] = (p[a] + L.N[a]) % L.N[a];
+      }
+    return cov.at(p[0], p[1], p[2]);
+  };
+  std::vector<uint8_t> mark(hit.size(), 0);
+  for (int tz = 0; tz < nt[2]; ++tz)
+    for (int ty = 0; ty < nt[1]; ++ty)
+      for (int tx = 0; tx < nt[0]; ++tx) {
+        if (!hit[tid(tx, ty, tz)]) continue;
+        bool ok = true;
+        if (!cov.all) {
+          const int lo[3] = {tx * T, ty * T, tz * T};
+          const int hi[3] = {std::min(L.N[0], lo[0] + T), std::min(L.N[1], lo[1] + T),
+                             std::min(L.N[2], lo[2] + T)};
+          for (int z = lo[2] - 1; ok && z <= hi[2]; ++z)
+            for (int y = lo[1] - 1; ok && y <= hi[1]; ++y)
+              for (int x = lo[0] - 1; ok && x <= hi[0]; ++x) {
+                const int outside = (x < lo[0] || x >= hi[0]) + (y < lo[1] || y >= hi[1]) + (z < lo[2] || z >= hi[2]);
+                if (outside <= 1) ok = covered_at(x, y, z);  // the tile and its face layers
+              }
+        }
+        mark[tid(tx, ty, tz)] = ok;
+      }
+  // greedy merge: x runs, stacked along y, then along z
+  struct Rect { int a, b, y0, h; };
+  struct Box { int a, b, y0, h, z0, d; };
+  std::vector<Box> open, next;
+  auto emit = [&](const Box &u) {
+    const int x0 = u.a * T, x1 = std::min(L.N[0], u.b * T);
+    const int y0 = u.y0 * T, y1 = std::min(L.N[1], (u.y0 + u.h) * T);
+    const int z0 = u.z0 * T, z1 = std::min(L.N[2], (u.z0 + u.d) * T);
+    out.push_back({l + 1, x0 * r, y0 * r, z0 * r, (x1 - x0) * r, (y1 - y0) * r, (z1 - z0) * r});
+  };
+  for (int tz = 0; tz <= nt[2]; ++tz) {
+    std::vector<Rect> rects;
+    if (tz < nt[2]) {  // the slab's rectangles
+      std::vector<Rect> ro, rn;
+      for (int ty = 0; ty <= nt[1]; ++ty) {
+        rn.clear();
+        if (ty < nt[1]) {
+          int tx = 0;
+          while (tx < nt[0]) {
+            if (!mark[tid(tx, ty, tz)]) {
+              ++tx;
+              continue;
+            }
+            const int a = tx;
+            while (tx < nt[0] && mark[tid(tx, ty, tz)] && tx - a < maxT) ++tx;
+            rn.push_back({a, tx, ty, 1});
+          }
+        }
+        for (const Rect &o : ro) {
+          bool cont = false;
+          for (Rect &q : rn)
+            if (q.a == o.a && q.b == o.b && q.h == 1 && o.h < maxT) {
+              q.y0 = o.y0;
+              q.h = o.h + 1;
+              cont = true;
+              break;
+            }
+          if (!cont) rects.push_back(o);
+        }
+        ro = rn;
+      }
+    }
+    next.clear();
+    for (const Box &o : open) {
+      bool cont = false;
+      for (Rect &q : rects)
+        if (q.a == o.a && q.b == o.b && q.y0 == o.y0 && q.h == o.h && o.d < maxT) {
+          next.push_back({o.a, o.b, o.y0, o.h, o.z0, o.d + 1});
+          q.h = -1;  // taken
+          cont = true;
+          break;
+        }
+      if (!cont) emit(o);
+    }
+    for (const Rect &q : rects)
+      if (q.h > 0) next.push_back({q.a, q.b, q.y0, q.h, tz, 1});
+    open.swap(next);
+  }
+}
+
+// Parents of tagged level-(l+1) cells are tagged at level l (so a refined
+// zone keeps its parent refined), then levels are clustered coarsest first,
+// each inside the coverage of the boxes just made one level up.
+void cluster_hierarchy3(const vlbm3_ctx *c, std::vector<TagMap3> &tags, int buffer, int min_box, int max_box,
+                        std::vector<vlbm3_box> &boxes) {
+  const int r = c->p.r, ML = c->p.max_levels;
+  for (int l = ML - 1; l >= 1; --l) {
+    TagMap3 &F = tags[l], &P = tags[l - 1];
+    if (F.t.empty() || P.t.empty()) continue;
+    for (int fz = 0; fz < F.n[2]; ++fz)
+      for (int fy = 0; fy < F.n[1]; ++fy)
+        for (int fx = 0; fx < F.n[0]; ++fx) {
+          if (!F.t[((size_t)fz * F.n[1] + fy) * F.n[0] + fx]) continue;
+          const int p[3] = {(F.o[0] + fx) / r, (F.o[1] + fy) / r, (F.o[2] + fz) / r};
+          bool in = true;
+          for (int a = 0; a < 3; ++a) in = in && p[a] >= P.o[a] && p[a] < P.o[a] + P.n[a];
+          if (in) P.at(p[0], p[1], p[2]) = 1;
+        }
+  }
+  CovMap3 cov;
+  for (int l = 0; l + 1 < ML; ++l) {
+    if (tags[l].t.empty()) break;
+    const size_t before = boxes.size();
+    cluster_level3(c, l, tags[l], cov, buffer, min_box, max_box, boxes);
+    if (boxes.size() == before || l + 2 >= ML) break;
+    CovMap3 nc;  // coverage of level l+1 over the bounding box of its new boxes
+    nc.all = false;
+    int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+    for (size_t b = before; b < boxes.size(); ++b) {
+      const int bl[3] = {boxes[b].i0, boxes[b].j0, boxes[b].k0}, bn[3] = {boxes[b].nx, boxes[b].ny, boxes[b].nz};
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], bl[a]);
+        hi[a] = std::max(hi[a], bl[a] + bn[a]);
+      }
+    }
+    for (int a = 0; a < 3; ++a) {
+      nc.o[a] = lo[a];
+      nc.n[a] = hi[a] - lo[a];
+    }
+    nc.m.assign((size_t)nc.n[0] * nc.n[1] * nc.n[2], 0);
+    for (size_t b = before; b < boxes.size(); ++b)
+      for (int z = boxes[b].k0; z < boxes[b].k0 + boxes[b].nz; ++z)
+        for (int y = boxes[b].j0; y < boxes[b].j0 + boxes[b].ny; ++y)
+          memset(&nc.m[((size_t)(z - lo[2]) * nc.n[1] + (y - lo[1])) * nc.n[0] + boxes[b].i0 - lo[0]], 1,
+                 boxes[b].nx);
+    cov = std::move(nc);
+  }
+}
+
+}  // namespace
+
 extern "C" {
 
 vlbm_status vlbm3_create(const vlbm3_params *params, void *stream, vlbm3_ctx **out) {
@@ -1174,6 +1438,55 @@ vlbm_status vlbm3_kernel_times(vlbm3_ctx *c, double *ms, long *calls, double *ce
     calls[i] = c->prof_calls[i];
     cells[i] = c->prof_cells[i];
   }
+  return VLBM_OK;
+}
+
+vlbm_status vlbm3_tag(vlbm3_ctx *c, int level, double threshold, unsigned char *tags) {
+  if (!c || !tags) return fail3(VLBM_EINVAL, "null argument");
+  if (!c->have_hierarchy) return fail3(VLBM_ESTATE, "no hierarchy installed");
+  if (level < 0 || level >= kL) return fail3(VLBM_EINVAL, "bad level");
+  const Level3 &L = c->lv[level];
+  const size_t nall = (size_t)L.N[0] * L.N[1] * L.N[2];
+  if (level < c->nlev && L.present) {
+    TagMap3 T;
+    vlbm_status st = tag_frame3(c, level, threshold, T);
+    if (st) return st;
+    memset(tags, 0, nall);
+    for (int z = 0; z < L.N[2]; ++z)
+      for (int y = 0; y < L.N[1]; ++y)
+        for (int x = 0; x < L.N[0]; ++x) {
+          const int p[3] = {x, y, z};
+          if (L.in_frame(p)) tags[((size_t)z * L.N[1] + y) * L.N[0] + x] = T.t[L.fidx(p)];
+        }
+  } else {
+    long s = 1;
+    for (int i = 0; i < level; ++i) s *= c->p.r;
+    memset(tags, 0, (size_t)c->p.nx0 * s * c->p.ny0 * s * c->p.nz0 * s);
+  }
+  return VLBM_OK;
+}
+
+vlbm_status vlbm3_tag_and_regrid(vlbm3_ctx *c, double threshold, int buffer, int min_box, int max_box) {
+  if (!c) return fail3(VLBM_EINVAL, "null context");
+  if (!c->have_hierarchy) return fail3(VLBM_ESTATE, "no hierarchy installed");
+  if (buffer < 0 || min_box < 1 || max_box < min_box) return fail3(VLBM_EINVAL, "bad clustering sizes");
+  const int ML = c->p.max_levels;
+  if (ML < 2) return VLBM_OK;
+  std::vector<TagMap3> tags(ML);
+  for (int l = 0; l < c->nlev; ++l) {
+    if (!c->lv[l].present) continue;
+    vlbm_status st = tag_frame3(c, l, threshold, tags[l]);
+    if (st) return st;
+  }
+  std::vector<vlbm3_box> boxes;
+  cluster_hierarchy3(c, tags, buffer, min_box, max_box, boxes);
+  return vlbm3_regrid(c, boxes.data(), (int)boxes.size());
+}
+
+vlbm_status vlbm3_get_boxes(vlbm3_ctx *c, vlbm3_box *boxes, int cap, int *nboxes) {
+  if (!c || !nboxes || cap < 0 || (cap > 0 && !boxes)) return fail3(VLBM_EINVAL, "bad argument");
+  *nboxes = (int)c->boxes.size();
+  for (int i = 0; i < std::min(cap, *nboxes); ++i) boxes[i] = c->boxes[i];
   return VLBM_OK;
 }
 

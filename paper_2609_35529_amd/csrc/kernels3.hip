@@ -207,6 +207,74 @@ hipError_t launch_step3(const Launch3 &a, hipStream_t s, hipEvent_t ev0, hipEven
 }
 
 // ---------------------------------------------------------------------------
+// Refinement tags (Sec. 3.4, density-gradient variant): an active cell is
+// tagged when max over the axes of |rho(+1) - rho(-1)| / (2 rho) exceeds the
+// threshold; a neighbour that is not an active cell of the level (across a
+// non-periodic side, outside the frame, a hole, uncovered) stands in as the
+// cell itself. rho = sum_q f_{q,rho} in the fixed order.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ double rho3(const T *b, int64_t P, int64_t o) {
+  return (((((double)b[0 * P + o] + (double)b[5 * P + o]) + (double)b[10 * P + o]) + (double)b[15 * P + o]) +
+          (double)b[20 * P + o]) +
+         (double)b[25 * P + o];
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void tag3_kernel(Tag3Args a) {
+  const int64_t n = (int64_t)a.fn[0] * a.fn[1] * a.fn[2];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int fx = (int)(i % a.fn[0]), fy = (int)((i / a.fn[0]) % a.fn[1]), fz = (int)(i / ((int64_t)a.fn[0] * a.fn[1]));
+  if (a.status[i] != 1) {
+    a.tags[i] = 0;
+    return;
+  }
+  const T *b = static_cast<const T *>(a.buf);
+  const int64_t o = (int64_t)fz * a.slab + (int64_t)fy * a.pitch + fx + a.xoff;
+  const double rc = rho3(b, a.plane, o);
+  const int fc[3] = {fx, fy, fz};
+  double g = 0.0;
+  for (int ax = 0; ax < 3; ++ax) {
+    double side[2];
+    for (int sd = 0; sd < 2; ++sd) {
+      int q[3] = {a.f0[0] + fx, a.f0[1] + fy, a.f0[2] + fz};
+      q[ax] += sd == 0 ? 1 : -1;
+      bool ok = true;
+      if (q[ax] < 0 || q[ax] >= a.N[ax]) {
+        if ((a.periodic >> ax) & 1)
+          q[ax] = q[ax] < 0 ? q[ax] + a.N[ax] : q[ax] - a.N[ax];
+        else
+          ok = false;
+      }
+      int gq[3] = {fc[0], fc[1], fc[2]};
+      if (ok) {
+        for (int k = 0; k < 3; ++k) {
+          gq[k] = q[k] - a.f0[k];
+          ok = ok && gq[k] >= 0 && gq[k] < a.fn[k];
+        }
+      }
+      if (ok) ok = a.status[((int64_t)gq[2] * a.fn[1] + gq[1]) * a.fn[0] + gq[0]] == 1;
+      side[sd] = ok ? rho3(b, a.plane, (int64_t)gq[2] * a.slab + (int64_t)gq[1] * a.pitch + gq[0] + a.xoff) : rc;
+    }
+    const double ga = fabs(side[0] - side[1]) / (2.0 * rc);
+    if (ga > g) g = ga;
+  }
+  a.tags[i] = (uint8_t)(g > a.thr);
+}
+
+hipError_t launch_tag3(const Tag3Args &a, int fp32, hipStream_t s) {
+  const int64_t n = (int64_t)a.fn[0] * a.fn[1] * a.fn[2];
+  if (n <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((n + 255) / 256));
+  if (fp32)
+    hipLaunchKernelGGL(tag3_kernel<float>, grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(tag3_kernel<double>, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Conservation audit: per-tile compensated sums of sum_q f_{q,k}
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void neumaier3(double &s, double &c, double v) {

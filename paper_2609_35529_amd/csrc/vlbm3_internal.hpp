@@ -105,6 +105,19 @@ hipError_t launch_split3(const RegridArgs3 &a, int fp32, hipStream_t s);
 hipError_t launch_copy3_runs(const void *s0, const void *s1, void *d0, void *d1, const int32_t *runs,
                              int nruns, int64_t splane, int64_t dplane, int fp32, hipStream_t s);
 
+// Refinement tags of one level frame (one byte per frame element).
+struct Tag3Args {
+  const void *buf;         // the level's current buffer
+  const uint8_t *status;   // frame status: 1 active
+  uint8_t *tags;           // out: fn0 x fn1 x fn2 bytes, frame order
+  int64_t plane, slab;
+  int32_t pitch, xoff;
+  int32_t f0[3], fn[3], N[3];
+  int32_t periodic;        // bit a: axis a is periodic
+  double thr;
+};
+hipError_t launch_tag3(const Tag3Args &a, int fp32, hipStream_t s);
+
 hipError_t launch_step3(const Launch3 &a, hipStream_t s, hipEvent_t ev0 = nullptr,
                         hipEvent_t ev1 = nullptr);
 hipError_t launch_audit3(const void *buf, const Tile3 *tiles, int ntiles, int64_t plane, int pitch,

@@ -66,13 +66,16 @@ vlbm3_set_profiling = _sig("vlbm3_set_profiling", _st, [_P, C.c_int])
 vlbm3_kernel_times = _sig("vlbm3_kernel_times", _st, [_P, _D, C.POINTER(C.c_long), _D])
 vlbm3_active_cells = _sig("vlbm3_active_cells", C.c_long, [_P, C.c_int])
 vlbm3_sync = _sig("vlbm3_sync", _st, [_P])
+vlbm3_tag = _sig("vlbm3_tag", _st, [_P, C.c_int, C.c_double, C.POINTER(C.c_uint8)])
+vlbm3_tag_and_regrid = _sig("vlbm3_tag_and_regrid", _st, [_P, C.c_double, C.c_int, C.c_int, C.c_int])
+vlbm3_get_boxes = _sig("vlbm3_get_boxes", _st, [_P, C.POINTER(vlbm3_box), C.c_int, C.POINTER(C.c_int)])
 
 EXPORTED = ["vlbm3_create", "vlbm3_destroy", "vlbm3_footprint_bytes", "vlbm3_set_hierarchy",
             "vlbm3_regrid",
             "vlbm3_set_state", "vlbm3_set_populations", "vlbm3_get_state",
             "vlbm3_get_populations", "vlbm3_advance", "vlbm3_conserved_totals",
             "vlbm3_set_tuning", "vlbm3_set_profiling", "vlbm3_kernel_times",
-            "vlbm3_active_cells", "vlbm3_sync"]
+            "vlbm3_active_cells", "vlbm3_sync", "vlbm3_tag", "vlbm3_tag_and_regrid", "vlbm3_get_boxes"]
 
 
 def make_params(nx0, ny0, nz0, dx0, gamma=1.4, c=1.0, beta=0.9, r=2, max_levels=2,
@@ -173,6 +176,22 @@ class Solver3:
 
     def advance(self, n):
         check(vlbm3_advance(self._h, int(n)))
+
+    def tag(self, level, threshold):
+        """Density-gradient refinement tags of level `level` (uint8, Nz x Ny x Nx)."""
+        t = np.zeros(self.shape(level), dtype=np.uint8)
+        check(vlbm3_tag(self._h, int(level), float(threshold), t.ctypes.data_as(C.POINTER(C.c_uint8))))
+        return t
+
+    def tag_and_regrid(self, threshold, buffer=2, min_box=8, max_box=64):
+        check(vlbm3_tag_and_regrid(self._h, float(threshold), int(buffer), int(min_box), int(max_box)))
+
+    def boxes(self):
+        n = C.c_int()
+        check(vlbm3_get_boxes(self._h, None, 0, C.byref(n)))
+        arr = (vlbm3_box * max(1, n.value))()
+        check(vlbm3_get_boxes(self._h, arr, n.value, C.byref(n)))
+        return [(b.level, b.i0, b.j0, b.k0, b.nx, b.ny, b.nz) for b in arr[:n.value]]
 
     def totals(self):
         T, L = np.empty(5), np.empty(5)
