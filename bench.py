@@ -90,14 +90,39 @@ def bench_3d(args):
               "flags": args.flags if args.tile_cells else 1}
     solver.set_tuning(tuning["tile_cells"], tuning["flags"])
     T0, L0 = solver.totals()
+    # dynamic refinement: tag and regrid every `regrid_every` coarse steps,
+    # inside the timed region
+    regrid_every = 5
+    amr = {"regrids": 0, "regrid_s": 0.0, "updates": 0, "boxes": []}
+
+    def run(n):
+        done = 0
+        while done < n:
+            k = n - done
+            if args.amr_threshold is not None:
+                k = min(k, regrid_every)
+            solver.advance(k)
+            if args.amr_threshold is not None:
+                act = [solver.active_cells(l) for l in range(case.nlev)]
+                amr["updates"] += k * sum(a * case.r ** l for l, a in enumerate(act))
+                t = time.perf_counter()
+                solver.tag_and_regrid(args.amr_threshold, buffer=args.amr_buffer,
+                                      min_box=args.amr_min_box, max_box=args.amr_max_box or 64)
+                amr["regrid_s"] += time.perf_counter() - t
+                amr["regrids"] += 1
+                amr["boxes"].append(len(solver.boxes()))
+            done += k
+
     print(f"[bench] {case.name} warmup {args.warmup}", file=sys.stderr, flush=True)
-    solver.advance(args.warmup)
+    run(args.warmup)
     torch.cuda.synchronize()
+    amr.update(regrids=0, regrid_s=0.0, updates=0, boxes=[])
     t0 = time.perf_counter()
-    solver.advance(args.steps)
+    run(args.steps)
     solver.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    amr_timed = dict(amr)
     prof_steps = min(args.steps, 20)
     solver.set_profiling(True)
     solver.advance(prof_steps)
@@ -105,7 +130,8 @@ def bench_3d(args):
     solver.set_profiling(False)
     T1, L1 = solver.totals()
     fe_step = case.fine_equivalent_per_coarse_step()
-    upd = case.actual_updates_per_coarse_step()
+    upd = (case.actual_updates_per_coarse_step() if args.amr_threshold is None
+           else amr_timed["updates"] / args.steps)
     dom = max(kt, key=lambda k: kt[k][0])
     dom_ms, dom_calls, dom_cells = kt[dom]
     avg_s = dom_ms / 1e3 / dom_calls
@@ -125,8 +151,10 @@ def bench_3d(args):
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "fp32s": "f64 math, f32 storage"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"{case.name}: {case.nx0}^3 coarse, levels {case.nlev}, boxes {case.boxes}, "
-                               f"r={case.r}, beta={case.beta}, c={case.c:.4f}, reflecting walls, D3Q6",
+        "config": {"workload": f"{case.name}: {case.nx0}^3 coarse, levels {case.nlev}, "
+                               + (f"initial boxes {case.boxes}, tag and regrid every {regrid_every} coarse steps, "
+                                  if args.amr_threshold is not None else f"boxes {case.boxes}, ")
+                               + f"r={case.r}, beta={case.beta}, c={case.c:.4f}, reflecting walls, D3Q6",
                    "fine_equiv_per_step": fe_step, "actual_updates_per_step": upd,
                    "launches_per_step": sum(v[1] for v in kt.values()) / prof_steps,
                    "tuning": tuning, "precision": args.precision},
@@ -136,6 +164,12 @@ def bench_3d(args):
                      "avg_launch_us": avg_s * 1e6, "launches": dom_calls,
                      "timing": f"per-kernel events over {prof_steps} further coarse steps"},
         "actual_updates_per_s": upd * args.steps / wall,
+        "amr": ({"regrid_every": regrid_every, "regrids": amr_timed["regrids"],
+                 "regrid_s": amr_timed["regrid_s"], "threshold": args.amr_threshold,
+                 "buffer": args.amr_buffer, "min_box": args.amr_min_box,
+                 "max_box": args.amr_max_box or 64,
+                 "boxes_min": min(amr_timed["boxes"]), "boxes_max": max(amr_timed["boxes"])}
+                if args.amr_threshold is not None and amr_timed["boxes"] else None),
         "conservation_drift_rel": [float(abs((T1[k] - T0[k]) - (L1[k] - L0[k])) / scale) for k in range(5)],
         "cpu_baseline": {"value": None, "unit": "fine-equiv cell updates/s", "cores": 1, "kind": "oracle",
                          "sample": "not run: the oracle keeps dense arrays over the whole domain at "

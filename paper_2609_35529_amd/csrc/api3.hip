@@ -18,6 +18,8 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/vlbm3.h"
@@ -98,6 +100,18 @@ void dfree(T *&p) {
   void *v = p;
   dfree(v);
   p = nullptr;
+}
+
+// f(lo, hi) over contiguous ranges of [0, n) on up to 16 threads (the calling
+// thread takes the first range); ranges hold at least `grain` items.
+template <class F>
+void par_ranges(size_t n, size_t grain, const F &f) {
+  const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+  const int nw = (int)std::max<size_t>(1, std::min<size_t>({16, hw, (n + grain - 1) / std::max<size_t>(1, grain)}));
+  std::vector<std::thread> th;
+  for (int w = 1; w < nw; ++w) th.emplace_back([&, w] { f(n * w / nw, n * (w + 1) / nw); });
+  f(0, n / nw);
+  for (std::thread &t : th) t.join();
 }
 
 }  // namespace
@@ -326,12 +340,52 @@ vlbm_status ghost_task3(const vlbm3_ctx *c, int l, const int x[3], int q, Task3 
 // Tiles of level l: per z-slab, runs of active cells along x (cut at
 // tile_cells), equal runs on consecutive rows stacked while the tile holds at
 // most tile_cells cells.
+void build_tile_slabs3(vlbm3_ctx *c, int l, int za, int zb, int tc, std::vector<Tile3> &tiles,
+                       std::vector<int32_t> &owner);
+
 void build_tiles3(vlbm3_ctx *c, int l, std::vector<int32_t> &owner) {
   Level3 &L = c->lv[l];
   L.tiles.clear();
   owner.assign(L.status.size(), -1);
   const int tc = c->tile_cells;
-  for (int z = L.f0[2] + 1; z < L.f0[2] + L.fn[2] - 1; ++z) {
+  // z-slabs are independent: ranges of them on worker threads, each with its
+  // own tile list (owner holds local indices), then concatenated in z order
+  const int nz = std::max(0, L.fn[2] - 2);
+  std::vector<std::vector<Tile3>> part;
+  std::vector<size_t> zr;  // range boundaries, in slabs
+  {
+    const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+    const int nw = (int)std::max<size_t>(1, std::min<size_t>({16, hw, (size_t)std::max(nz, 1)}));
+    part.resize(nw);
+    zr.resize(nw + 1);
+    for (int w = 0; w <= nw; ++w) zr[w] = (size_t)nz * w / nw;
+    std::vector<std::thread> th;
+    auto slabs = [&](int w) { build_tile_slabs3(c, l, L.f0[2] + 1 + (int)zr[w], L.f0[2] + 1 + (int)zr[w + 1], tc, part[w], owner); };
+    for (int w = 1; w < nw; ++w) th.emplace_back(slabs, w);
+    slabs(0);
+    for (std::thread &t : th) t.join();
+  }
+  std::vector<size_t> base(part.size(), 0);
+  for (size_t w = 0; w < part.size(); ++w) {
+    base[w] = L.tiles.size();
+    L.tiles.insert(L.tiles.end(), part[w].begin(), part[w].end());
+  }
+  par_ranges(part.size(), 1, [&](size_t w0, size_t w1) {
+    for (size_t w = w0; w < w1; ++w) {
+      if (!base[w]) continue;
+      const size_t i0 = (size_t)(zr[w] + 1) * L.fn[1] * L.fn[0], i1 = (size_t)(zr[w + 1] + 1) * L.fn[1] * L.fn[0];
+      for (size_t i = i0; i < i1; ++i)
+        if (owner[i] >= 0) owner[i] += (int32_t)base[w];
+    }
+  });
+}
+
+// Tiles of the z-slabs [za, zb) of level l into `tiles` (indices local to it,
+// written into owner).
+void build_tile_slabs3(vlbm3_ctx *c, int l, int za, int zb, int tc, std::vector<Tile3> &tiles,
+                       std::vector<int32_t> &owner) {
+  Level3 &L = c->lv[l];
+  for (int z = za; z < zb; ++z) {
     std::map<std::pair<int, int>, int> open;  // (x0, w) -> tile growing on the previous row
     for (int y = L.f0[1] + 1; y < L.f0[1] + L.fn[1] - 1; ++y) {
       std::map<std::pair<int, int>, int> next;
@@ -353,17 +407,17 @@ void build_tiles3(vlbm3_ctx *c, int l, std::vector<int32_t> &owner) {
         const std::pair<int, int> key{xa, w};
         auto it = open.find(key);
         int ti;
-        if (it != open.end() && (L.tiles[it->second].h + 1) * w <= tc) {
+        if (it != open.end() && (tiles[it->second].h + 1) * w <= tc) {
           ti = it->second;
-          L.tiles[ti].h += 1;
+          tiles[ti].h += 1;
         } else {
           Tile3 t{};
           int q0[3] = {xa, y, z};
           t.off0 = (int32_t)L.off(q0);
           t.w = w;
           t.h = 1;
-          L.tiles.push_back(t);
-          ti = (int)L.tiles.size() - 1;
+          tiles.push_back(t);
+          ti = (int)tiles.size() - 1;
         }
         next[key] = ti;
         for (int xx = xa; xx < x; ++xx) {
@@ -395,8 +449,15 @@ vlbm_status build_lists3(vlbm3_ctx *c) {
     std::vector<RefluxKey3> refl;
     L.nacc = 0;
     L.nledger = 0;
-    for (size_t ti = 0; ti < L.tiles.size(); ++ti) {
+    // Ghost tasks of the tiles, on worker threads over contiguous tile ranges:
+    // a tile's reflux and ledger slots are numbered locally first, then
+    // renumbered in tile order below, so the lists do not depend on the
+    // threading.
+    std::vector<std::vector<RefluxKey3>> trefl(L.tiles.size());
+    std::vector<int> tled(L.tiles.size(), 0);
+    auto tile_tasks = [&](size_t ti) -> vlbm_status {
       const Tile3 &T = L.tiles[ti];
+      int nacc = 0, nled = 0;
       // tile cells: decode the first cell's coordinates once
       const int64_t rel = T.off0 - L.xoff;
       const int fz = (int)(rel / L.slab);
@@ -419,16 +480,57 @@ vlbm_status build_lists3(vlbm3_ctx *c) {
             if (!needed) continue;
             const int kind = t.kind & 0xFF;
             if (kind == K3_REFLUX) {
-              t.slot = L.nacc++;
+              t.slot = nacc++;
               int w[3] = {x[0] - E3[q][0], x[1] - E3[q][1], x[2] - E3[q][2]};
               c->wrap(l, w);
-              refl.push_back({{w[0], w[1], w[2]}, q, t.slot});
+              trefl[ti].push_back({{w[0], w[1], w[2]}, q, t.slot});
             } else if (kind == K3_OUTFLOW || kind == K3_REFLECT) {
-              t.slot = L.nledger++;
+              t.slot = nled++;
             }
             per[ti].push_back(t);
           }
         }
+      tled[ti] = nled;
+      return VLBM_OK;
+    };
+    {
+      const size_t nt = L.tiles.size();
+      const int nw = (int)std::max<size_t>(1, std::min<size_t>({16, std::max(1u, std::thread::hardware_concurrency()),
+                                                                (nt + 255) / 256}));
+      std::vector<vlbm_status> wst(nw, VLBM_OK);
+      std::vector<std::string> wmsg(nw);
+      auto work = [&](int w) {
+        for (size_t ti = nt * w / nw; ti < nt * (w + 1) / nw; ++ti) {
+          vlbm_status st = tile_tasks(ti);
+          if (st) {
+            wst[w] = st;
+            wmsg[w] = vlbm_last_error();  // the message lives in the worker's thread
+            return;
+          }
+        }
+      };
+      std::vector<std::thread> th;
+      for (int w = 1; w < nw; ++w) th.emplace_back(work, w);
+      work(0);
+      for (std::thread &t : th) t.join();
+      for (int w = 0; w < nw; ++w)
+        if (wst[w]) return fail3(wst[w], "%s", wmsg[w].c_str());
+    }
+    for (size_t ti = 0; ti < L.tiles.size(); ++ti) {  // slots in tile order
+      const int acc0 = L.nacc, led0 = L.nledger;
+      for (Task3 &t : per[ti]) {
+        const int kind = t.kind & 0xFF;
+        if (kind == K3_REFLUX)
+          t.slot += acc0;
+        else if (kind == K3_OUTFLOW || kind == K3_REFLECT)
+          t.slot += led0;
+      }
+      for (RefluxKey3 k : trefl[ti]) {
+        k.slot += acc0;
+        refl.push_back(k);
+      }
+      L.nacc += (int)trefl[ti].size();
+      L.nledger += tled[ti];
     }
     // captures of this level for the parent's reflux slots
     if (l > 0) {
@@ -773,30 +875,40 @@ vlbm_status build_geometry3(const vlbm3_params &p, const vlbm3_box *boxes, int n
   }
   // proper nesting: the parent of every covered cell and its face neighbours
   const int r = p.r;
-  for (int b = 0; b < nboxes; ++b) {
-    const vlbm3_box &B = boxes[b];
-    const int l = B.level;
-    for (int pz = B.k0 / r; pz < (B.k0 + B.nz) / r; ++pz)
-      for (int py = B.j0 / r; py < (B.j0 + B.ny) / r; ++py)
-        for (int px = B.i0 / r; px < (B.i0 + B.nx) / r; ++px)
-          for (int d = -1; d < 6; ++d) {
-            int P[3] = {px + (d < 0 ? 0 : E3[d][0]), py + (d < 0 ? 0 : E3[d][1]), pz + (d < 0 ? 0 : E3[d][2])};
-            if (!wrap_in(p, lv, l - 1, P)) continue;
-            if (!cov_in(lv, nlev, l - 1, P)) return fail3(VLBM_ENEST, "box %d: hierarchy not properly nested", b);
-          }
-  }
+  std::vector<uint8_t> bad(nboxes > 0 ? nboxes : 1, 0);
+  par_ranges((size_t)std::max(nboxes, 0), 4, [&](size_t b0, size_t b1) {
+    for (size_t b = b0; b < b1; ++b) {
+      const vlbm3_box &B = boxes[b];
+      const int l = B.level;
+      for (int pz = B.k0 / r; pz < (B.k0 + B.nz) / r && !bad[b]; ++pz)
+        for (int py = B.j0 / r; py < (B.j0 + B.ny) / r && !bad[b]; ++py)
+          for (int px = B.i0 / r; px < (B.i0 + B.nx) / r && !bad[b]; ++px)
+            for (int d = -1; d < 6; ++d) {
+              int P[3] = {px + (d < 0 ? 0 : E3[d][0]), py + (d < 0 ? 0 : E3[d][1]), pz + (d < 0 ? 0 : E3[d][2])};
+              if (!wrap_in(p, lv, l - 1, P)) continue;
+              if (!cov_in(lv, nlev, l - 1, P)) {
+                bad[b] = 1;
+                break;
+              }
+            }
+    }
+  });
+  for (int b = 0; b < nboxes; ++b)
+    if (bad[b]) return fail3(VLBM_ENEST, "box %d: hierarchy not properly nested", b);
   for (int l = 0; l < nlev; ++l) {
     Level3 &L = lv[l];
     L.status.assign(L.cov.size(), 0);
-    for (int z = L.f0[2]; z < L.f0[2] + L.fn[2]; ++z)
-      for (int y = L.f0[1]; y < L.f0[1] + L.fn[1]; ++y)
-        for (int x = L.f0[0]; x < L.f0[0] + L.fn[0]; ++x) {
-          const int q[3] = {x, y, z};
-          const size_t i = L.fidx(q);
-          if (!L.cov[i]) continue;
-          const int ch[3] = {x * r, y * r, z * r};
-          L.status[i] = cov_in(lv, nlev, l + 1, ch) ? 2 : 1;
-        }
+    par_ranges((size_t)L.fn[2], 1, [&](size_t z0, size_t z1) {
+      for (int z = L.f0[2] + (int)z0; z < L.f0[2] + (int)z1; ++z)
+        for (int y = L.f0[1]; y < L.f0[1] + L.fn[1]; ++y)
+          for (int x = L.f0[0]; x < L.f0[0] + L.fn[0]; ++x) {
+            const int q[3] = {x, y, z};
+            const size_t i = L.fidx(q);
+            if (!L.cov[i]) continue;
+            const int ch[3] = {x * r, y * r, z * r};
+            L.status[i] = cov_in(lv, nlev, l + 1, ch) ? 2 : 1;
+          }
+    });
   }
   return VLBM_OK;
 }
