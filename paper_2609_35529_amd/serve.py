@@ -9,6 +9,11 @@ serves every solve at once. Solves that finish are read back (their level-0
 state) and freed; their slots and bytes go to the next arrivals. Latency is
 completion time minus arrival time.
 
+At admission, every `health_every` iterations and when a solve finishes,
+each resident solve is scanned (``vlbm_check_health``: rho <= 0, p <= 0 or
+NaN on any active cell). An unhealthy solve fails alone: it is reported with ``failed`` set and
+freed, and the others continue untouched (their states never share memory).
+
 ``run_sequential`` is the reference path: one solve at a time in arrival order,
 plain FP64, no batching.
 
@@ -36,6 +41,7 @@ class Result:
     steps: int
     fine_equiv: float
     state: Optional[np.ndarray] = None
+    failed: bool = False
 
     @property
     def latency(self):
@@ -47,9 +53,11 @@ def _percentile(x, q):
 
 
 def summarize(results: List[Result], wall: float) -> Dict:
-    lat = [r.latency for r in results]
-    fe = sum(r.fine_equiv for r in results)
-    return {"solves": len(results), "wall_s": wall, "solves_per_s": len(results) / wall,
+    ok = [r for r in results if not r.failed]
+    lat = [r.latency for r in ok]
+    fe = sum(r.fine_equiv for r in ok)
+    return {"solves": len(ok), "failed": len(results) - len(ok), "wall_s": wall,
+            "solves_per_s": len(ok) / wall,
             "fine_equiv_per_s": fe / wall, "p50_latency_s": _percentile(lat, 50),
             "p99_latency_s": _percentile(lat, 99), "mean_latency_s": float(np.mean(lat))}
 
@@ -68,7 +76,7 @@ class Server:
 
     def __init__(self, budget_bytes: int, precision=vlbm.FP32_STORAGE, quantum=25,
                  max_resident=64, stream=None, keep_states=False, slice_s=0.02,
-                 policy="share"):
+                 policy="share", health_every=8):
         """Per iteration, resident solves advance together in shared launches.
         policy "fixed": every solve takes `quantum` coarse steps.
         policy "share": every solve gets an equal share of a slice_s-second
@@ -84,6 +92,7 @@ class Server:
         self.keep_states = keep_states
         self.slice_s = slice_s
         self.policy = policy
+        self.health_every = int(health_every)
 
     def step_cost(self, case):
         esz = 4 if self.precision == vlbm.FP32 else 8
@@ -117,6 +126,7 @@ class Server:
         used = 0
         t0 = time.perf_counter()
         i = 0
+        it = 0
         while i < len(pending) or queue or resident:
             now = time.perf_counter() - t0
             while i < len(pending) and pending[i]["arrival"] * time_scale <= now:
@@ -133,6 +143,12 @@ class Server:
                     break
                 queue.pop(0)
                 s = vlbm.Solver.from_case(case, precision=self.precision, stream=self.stream)
+                if self.health_every > 0 and not s.check_health():  # a bad initial state
+                    now = time.perf_counter() - t0
+                    results.append(Result(req["id"], req["arrival"] * time_scale, now, now, 0, 0.0,
+                                          None, failed=True))
+                    s.close()
+                    continue
                 used += need
                 resident.append(dict(req=req, case=case, solver=s, need=need,
                                      left=req["steps"], cost=self.step_cost(case),
@@ -145,10 +161,20 @@ class Server:
                 continue
             n = self.plan(resident)
             vlbm.batch_advance([e["solver"] for e in resident], n)
+            it += 1
+            scan = self.health_every > 0 and it % self.health_every == 0
             for e, k in zip(resident, n):
                 e["left"] -= k
             still = []
             for e in resident:
+                if (scan or e["left"] <= 0) and not e["solver"].check_health():
+                    r = e["req"]
+                    results.append(Result(r["id"], r["arrival"] * time_scale, e["admitted"],
+                                          time.perf_counter() - t0, r["steps"] - e["left"], 0.0,
+                                          None, failed=True))
+                    e["solver"].close()
+                    used -= e["need"]
+                    continue
                 if e["left"] > 0:
                     still.append(e)
                     continue

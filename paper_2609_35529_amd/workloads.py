@@ -510,6 +510,10 @@ def request_case(req, beta=0.6, kappa=1.5, r=2):
     for l in range(1, nlev):
         X, Y = level_grid(n0, n0, 1.0 / n0, r, l)
         states.append(_quadrant_ic(quadrant_states(req["seed"]), 1.4)(X, Y))
+    if req.get("poison"):  # a faulty request: negative density in one level-0 cell
+        U = np.array(states[0], copy=True)
+        U[0, 1, 1] = -abs(U[0, 1, 1])
+        states[0] = U
     return dataclasses.replace(case, nlev=nlev, boxes=boxes, states=states, name="request")
 
 

@@ -48,3 +48,28 @@ def test_admission_respects_budget():
     assert sorted(r.rid for r in res) == sorted(r["id"] for r in reqs)
     with pytest.raises(RuntimeError):
         serve.Server(budget_bytes=biggest // 4, precision=vlbm.FP32, stream=stream).run(reqs, 0.0)
+
+
+def test_a_faulty_request_fails_alone():
+    """A request whose initial state has a negative density is detected by the
+    health scan, reported failed and freed; every other request's state is
+    bit-identical to solving it alone."""
+    import torch
+    from paper_2609_35529_amd import serve
+    stream = torch.cuda.Stream()
+    reqs = _requests()
+    bad = reqs[3]["id"]
+    reqs[3] = dict(reqs[3], poison=True)
+    srv = serve.Server(budget_bytes=2 << 30, precision=0, quantum=7, stream=stream, keep_states=True,
+                       health_every=1)
+    mixed, wall = srv.run(reqs, time_scale=0.0)
+    assert len(mixed) == len(reqs)
+    assert [r.rid for r in mixed if r.failed] == [bad]
+    good = [q for q in reqs if q["id"] != bad]
+    alone, _ = serve.run_sequential(good, precision=0, stream=stream, keep_states=True)
+    by_id = {r.rid: r for r in alone}
+    for r in mixed:
+        if not r.failed:
+            assert np.array_equal(r.state, by_id[r.rid].state, equal_nan=True), r.rid
+    stats = serve.summarize(mixed, wall)
+    assert stats["failed"] == 1 and stats["solves"] == len(reqs) - 1
