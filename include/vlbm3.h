@@ -149,6 +149,16 @@ vlbm_status vlbm3_set_tuning(vlbm3_ctx *ctx, int tile_cells, int flags);
 vlbm_status vlbm3_set_profiling(vlbm3_ctx *ctx, int enable);
 vlbm_status vlbm3_kernel_times(vlbm3_ctx *ctx, double *ms, long *calls, double *cells);
 
+/* Checkpoint of the state: the boxes, every level's two time levels of
+ * populations and step count, the coarse step count and the boundary
+ * ledger's totals, into buf (caller-owned, *bytes long; with buf NULL only
+ * the size needed is returned in *bytes). vlbm3_load restores it into a
+ * context created with equal parameters (VLBM_EINVAL otherwise), under any
+ * launch tuning; the run continues bit for bit as if never interrupted.
+ * Both synchronise. */
+vlbm_status vlbm3_save(vlbm3_ctx *ctx, void *buf, size_t *bytes);
+vlbm_status vlbm3_load(vlbm3_ctx *ctx, const void *buf, size_t bytes);
+
 /* Active cells of a level (0 if absent). */
 long vlbm3_active_cells(const vlbm3_ctx *ctx, int level);
 

@@ -1602,6 +1602,106 @@ vlbm_status vlbm3_get_boxes(vlbm3_ctx *c, vlbm3_box *boxes, int cap, int *nboxes
   return VLBM_OK;
 }
 
+// Checkpoint: header, boxes, per present level {step count, both buffers}.
+// The reflux accumulators hold nothing between coarse steps, and the
+// boundary ledger is kept as its five totals, so a checkpoint loads under any
+// launch tuning.
+struct Ckpt3Header {
+  char magic[8];
+  vlbm3_params p;
+  int32_t nboxes, nlev;
+  int64_t coarse_steps;
+  double ledger[5];
+};
+
+vlbm_status vlbm3_save(vlbm3_ctx *c, void *buf, size_t *bytes) {
+  if (!c || !bytes) return fail3(VLBM_EINVAL, "null argument");
+  if (!c->have_hierarchy) return fail3(VLBM_ESTATE, "nothing to save");
+  size_t need = sizeof(Ckpt3Header) + sizeof(vlbm3_box) * c->boxes.size();
+  for (int l = 0; l < c->nlev; ++l) need += sizeof(int64_t) + 2 * level_bytes3(c->lv[l]);
+  if (!buf) {
+    *bytes = need;
+    return VLBM_OK;
+  }
+  if (*bytes < need) return fail3(VLBM_EINVAL, "checkpoint buffer too small (%zu < %zu)", *bytes, need);
+  Ckpt3Header h{};
+  memcpy(h.magic, "VLBM3C1", 8);
+  h.p = c->p;
+  h.nboxes = (int32_t)c->boxes.size();
+  h.nlev = c->nlev;
+  h.coarse_steps = c->coarse_steps;
+  double tot[5];
+  vlbm_status st = vlbm3_conserved_totals(c, tot, h.ledger);
+  if (st) return st;
+  char *p = static_cast<char *>(buf);
+  memcpy(p, &h, sizeof h);
+  p += sizeof h;
+  memcpy(p, c->boxes.data(), sizeof(vlbm3_box) * c->boxes.size());
+  p += sizeof(vlbm3_box) * c->boxes.size();
+  for (int l = 0; l < c->nlev; ++l) {
+    const Level3 &L = c->lv[l];
+    const int64_t steps = L.steps;
+    memcpy(p, &steps, sizeof steps);
+    p += sizeof steps;
+    const size_t nb = level_bytes3(L);
+    for (int b = 0; b < 2; ++b) {
+      HIPCHK3(hipMemcpyAsync(p, L.buf[b], nb, hipMemcpyDeviceToHost, c->stream));
+      p += nb;
+    }
+  }
+  HIPCHK3(hipStreamSynchronize(c->stream));
+  *bytes = need;
+  return VLBM_OK;
+}
+
+vlbm_status vlbm3_load(vlbm3_ctx *c, const void *buf, size_t bytes) {
+  if (!c || !buf || bytes < sizeof(Ckpt3Header)) return fail3(VLBM_EINVAL, "bad checkpoint");
+  const char *p = static_cast<const char *>(buf);
+  Ckpt3Header h;
+  memcpy(&h, p, sizeof h);
+  p += sizeof h;
+  if (memcmp(h.magic, "VLBM3C1", 8) != 0) return fail3(VLBM_EINVAL, "not a 3-D checkpoint");
+  {
+    const vlbm3_params &a = h.p, &b = c->p;
+    bool same = a.nx0 == b.nx0 && a.ny0 == b.ny0 && a.nz0 == b.nz0 && a.dx0 == b.dx0 && a.gamma == b.gamma &&
+                a.c == b.c && a.beta == b.beta && a.r == b.r && a.max_levels == b.max_levels &&
+                a.precision == b.precision;
+    for (int s2 = 0; s2 < 6; ++s2) same = same && a.bc[s2] == b.bc[s2];
+    if (!same) return fail3(VLBM_EINVAL, "checkpoint parameters differ from the context's");
+  }
+  if (h.nboxes < 0 || sizeof h + sizeof(vlbm3_box) * (size_t)h.nboxes > bytes)
+    return fail3(VLBM_EINVAL, "truncated checkpoint");
+  std::vector<vlbm3_box> boxes(h.nboxes);
+  memcpy(boxes.data(), p, sizeof(vlbm3_box) * h.nboxes);
+  p += sizeof(vlbm3_box) * h.nboxes;
+  vlbm_status st = vlbm3_set_hierarchy(c, boxes.data(), h.nboxes);
+  if (st) return st;
+  if (c->nlev != h.nlev) return fail3(VLBM_EINVAL, "checkpoint level count mismatch");
+  for (int l = 0; l < c->nlev; ++l) {
+    Level3 &L = c->lv[l];
+    const size_t nb = level_bytes3(L);
+    if ((size_t)(p - static_cast<const char *>(buf)) + sizeof(int64_t) + 2 * nb > bytes)
+      return fail3(VLBM_EINVAL, "truncated checkpoint");
+    int64_t steps;
+    memcpy(&steps, p, sizeof steps);
+    p += sizeof steps;
+    L.steps = steps;
+    for (int b = 0; b < 2; ++b) {
+      HIPCHK3(hipMemcpyAsync(L.buf[b], p, nb, hipMemcpyHostToDevice, c->stream));
+      p += nb;
+    }
+  }
+  // the ledger totals into the first slot that exists (the others start at 0)
+  for (int l = 0; l < c->nlev; ++l)
+    if (c->lv[l].nledger > 0) {
+      HIPCHK3(hipMemcpyAsync(c->lv[l].dledger, h.ledger, sizeof h.ledger, hipMemcpyHostToDevice, c->stream));
+      break;
+    }
+  HIPCHK3(hipStreamSynchronize(c->stream));
+  c->coarse_steps = h.coarse_steps;
+  return build_tables3(c);
+}
+
 long vlbm3_active_cells(const vlbm3_ctx *c, int level) {
   if (!c || !c->have_hierarchy || level < 0 || level >= kL || !c->lv[level].present) return 0;
   long n = 0;

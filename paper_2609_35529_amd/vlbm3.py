@@ -69,13 +69,16 @@ vlbm3_sync = _sig("vlbm3_sync", _st, [_P])
 vlbm3_tag = _sig("vlbm3_tag", _st, [_P, C.c_int, C.c_double, C.POINTER(C.c_uint8)])
 vlbm3_tag_and_regrid = _sig("vlbm3_tag_and_regrid", _st, [_P, C.c_double, C.c_int, C.c_int, C.c_int])
 vlbm3_get_boxes = _sig("vlbm3_get_boxes", _st, [_P, C.POINTER(vlbm3_box), C.c_int, C.POINTER(C.c_int)])
+vlbm3_save = _sig("vlbm3_save", _st, [_P, C.c_void_p, C.POINTER(C.c_size_t)])
+vlbm3_load = _sig("vlbm3_load", _st, [_P, C.c_void_p, C.c_size_t])
 
 EXPORTED = ["vlbm3_create", "vlbm3_destroy", "vlbm3_footprint_bytes", "vlbm3_set_hierarchy",
             "vlbm3_regrid",
             "vlbm3_set_state", "vlbm3_set_populations", "vlbm3_get_state",
             "vlbm3_get_populations", "vlbm3_advance", "vlbm3_conserved_totals",
             "vlbm3_set_tuning", "vlbm3_set_profiling", "vlbm3_kernel_times",
-            "vlbm3_active_cells", "vlbm3_sync", "vlbm3_tag", "vlbm3_tag_and_regrid", "vlbm3_get_boxes"]
+            "vlbm3_active_cells", "vlbm3_sync", "vlbm3_tag", "vlbm3_tag_and_regrid", "vlbm3_get_boxes",
+            "vlbm3_save", "vlbm3_load"]
 
 
 def make_params(nx0, ny0, nz0, dx0, gamma=1.4, c=1.0, beta=0.9, r=2, max_levels=2,
@@ -185,6 +188,17 @@ class Solver3:
 
     def tag_and_regrid(self, threshold, buffer=2, min_box=8, max_box=64):
         check(vlbm3_tag_and_regrid(self._h, float(threshold), int(buffer), int(min_box), int(max_box)))
+
+    def save(self) -> bytes:
+        n = C.c_size_t(0)
+        check(vlbm3_save(self._h, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        check(vlbm3_save(self._h, buf, C.byref(n)))
+        return buf.raw[:n.value]
+
+    def load(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        check(vlbm3_load(self._h, buf, len(blob)))
 
     def boxes(self):
         n = C.c_int()
