@@ -182,7 +182,7 @@ def actual_updates_per_step(case):
     return case.actual_updates_per_coarse_step()
 
 
-def cpu_baseline(case, budget_s=15.0, boxes=None, mem_cap=8e9, sensor=None):
+def cpu_baseline(case, budget_s=15.0, boxes=None, mem_cap=8e9, sensor=None, adaptive_dt=None):
     """The oracle, single-threaded, on a bounded prefix of the same workload.
     A dynamic workload is sampled on the hierarchy the GPU run starts its timed
     region with (`boxes`), held fixed. The oracle keeps three dense arrays of
@@ -199,6 +199,8 @@ def cpu_baseline(case, budget_s=15.0, boxes=None, mem_cap=8e9, sensor=None):
     o = exact.run_oracle(case, steps=0)
     if sensor:
         o.set_sensor(True, *sensor)
+    if adaptive_dt is not None:
+        o.set_time_stepping(True, adaptive_dt)
     t0 = time.perf_counter()
     n = 0
     while time.perf_counter() - t0 < budget_s and n < case.steps:
@@ -209,6 +211,8 @@ def cpu_baseline(case, budget_s=15.0, boxes=None, mem_cap=8e9, sensor=None):
     held = f", hierarchy of the GPU run's timed region ({len(boxes)} boxes) held fixed" if boxes else ""
     if sensor:
         held += f", adaptive beta (C, beta_min, beta_max) = {tuple(sensor)}"
+    if adaptive_dt is not None:
+        held += f", adaptive time step (kappa = {adaptive_dt})"
     return {"value": fe, "unit": "fine-equiv cell updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{case.name} full size, first {n} coarse steps ({el:.1f} s){held}, FP64, "
                       f"one thread"}
@@ -301,6 +305,8 @@ def main():
     ap.add_argument("--serve-precision", default="fp32s", choices=["fp32", "fp32s", "fp64"])
     ap.add_argument("--serve-policy", default="share", choices=["share", "srpt", "fixed"])
     ap.add_argument("--n0-3d", type=int, default=256, help="coarse cells per axis of the 3-D workload")
+    ap.add_argument("--adaptive-dt", type=float, default=None, metavar="KAPPA",
+                    help="adaptive time step: c = 2 kappa max(|u| + c_s) every coarse step")
     ap.add_argument("--sensor", default=None, metavar="C,BMIN,BMAX",
                     help="space/time-adaptive beta (eq. sensor-B) with these constants")
     ap.add_argument("--copy-probe", action="store_true",
@@ -340,6 +346,8 @@ def main():
     if args.sensor:
         sensor = [float(x) for x in args.sensor.split(",")]
         solver.set_sensor(True, *sensor)
+    if args.adaptive_dt is not None:  # c chosen every coarse step from the state
+        solver.set_time_stepping(True, args.adaptive_dt)
     T0, L0 = solver.totals()
 
     tuning = None
@@ -419,6 +427,8 @@ def main():
     esz = 8 if prec == vlbm.FP64 else 4
     bytes_per_update = 2 * 16 * esz
     nl = sum(v[1] for v in ktimes.values()) / prof_steps
+    if args.adaptive_dt is not None:  # the CFL pass and its one-thread finalize, every coarse step
+        nl += 2
     if sensor:
         # a separate next-Qmax clear per coarse step only where the finest
         # level takes one step per coarse step; the SEN step also reads W
@@ -469,6 +479,7 @@ def main():
                    "fine_equiv_per_step": fe_step, "actual_updates_per_step": upd,
                    "launches_per_step": nl, "tuning": tuning,
                    "precision": args.precision,
+                   "adaptive_dt_kappa": args.adaptive_dt,
                    "adaptive_beta": (dict(zip(("C", "beta_min", "beta_max"), sensor))
                                      if sensor else None)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -498,7 +509,8 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(build_case(args.workload, 10 ** 6), args.cpu_budget,
-                                           boxes=timed_boxes if dynamic else None, sensor=sensor)
+                                           boxes=timed_boxes if dynamic else None, sensor=sensor,
+                                           adaptive_dt=args.adaptive_dt)
     print(json.dumps(out))
 
 
