@@ -32,9 +32,9 @@ HBM_PEAK_GBS = 8000.0
 # x 1.000 (scales measured on a plain 2 GiB copy); valid only for the kernel
 # source it was measured on. The fused tile shape does not depend on
 # tile_cells, so any tile_cells matches.
-MEASURED_TRAFFIC = {"kernel_sha256_16": "c431598a23f890cd", "workload": "quadrant512",
+MEASURED_TRAFFIC = {"kernel_sha256_16": "93baf27763ee153f", "workload": "quadrant512",
                     "precision": "fp64", "tile_cells": None, "flags": 20, "kernel": "fused_kernel",
-                    "bytes_per_launch": 75414748.0}
+                    "bytes_per_launch": 75445708.0}
 
 
 # dynamic-refinement workloads: re-tag and regrid every few coarse steps
@@ -423,8 +423,8 @@ def main():
     esz = 8 if prec == vlbm.FP64 else 4
     bytes_per_update = 2 * 16 * esz
     nl = sum(v[1] for v in ktimes.values()) / prof_steps
-    if args.adaptive_dt is not None:  # the CFL pass and its one-thread finalize, every coarse step
-        nl += 2
+    if args.adaptive_dt is not None:  # the one-thread update of the link speed, every coarse step
+        nl += 1
     if sensor:
         # a separate next-Qmax clear per coarse step only where the finest
         # level takes one step per coarse step; the SEN step also reads W

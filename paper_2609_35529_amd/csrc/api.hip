@@ -247,6 +247,7 @@ struct LaunchRec {
   int32_t fused_kernel = 0;  // launched as the fused kernel
   int32_t prof_key = 0;      // 2 * level + fused, for per-kernel timing
   double cells = 0.0;        // active cells the launch advances
+  int32_t emit_cfl = 0;      // adaptive time step: the level's last launch of the coarse step
 };
 }  // namespace
 
@@ -271,6 +272,8 @@ struct vlbm_ctx {
   double c_sensor = 1.0, beta_min = 1.0, beta_max = 1.0;
   unsigned long long *dqmax = nullptr;  // [2][4]: max |Q| per coarse-step parity, as bits
   bool sensor_stale = true;  // W planes and this coarse step's max |Q| need stage 0
+  bool cfl_stale = true;     // the state changed since the last step launches: the CFL bound needs
+                             // the full pass
   // adaptive time step: DynState scalars and the CFL max slot (device)
   bool adt = false;
   double *ddyn = nullptr;
@@ -1072,6 +1075,7 @@ bool fused_active(const vlbm_ctx *c) {
 // masks from the current status. The W planes and maxima then need stage 0.
 vlbm_status ensure_sensor(vlbm_ctx *c) {
   c->sensor_stale = true;
+  c->cfl_stale = true;
   for (int l = 0; l < kMaxLevels; ++l) {
     Level &L = c->lv[l];
     const bool want = c->sensor && L.present && l < c->nlev;
@@ -1207,6 +1211,11 @@ vlbm_status build_tables(vlbm_ctx *c) {
         for (size_t q2 = 0; q2 < p; ++q2)
           if (c->phases[q2].first == l - 1) parent_stepped = true;
         D.use_ratio = (l > 0 && !parent_stepped) ? 1 : 0;
+        bool later = false;
+        for (size_t q2 = p + 1; q2 < P; ++q2)
+          if (c->phases[q2].first == l) later = true;
+        D.emit_cfl = later ? 0 : 1;
+        D.cfl_next = c->dcmax;
       }
       if (descs[e * P + p].sen) {
         LevelDesc &D = descs[e * P + p];
@@ -1234,6 +1243,7 @@ vlbm_status build_tables(vlbm_ctx *c) {
         a.fused_kernel = fused;
         a.prof_key = 2 * l + (fused ? 1 : 0);
         a.cells = (double)tile_cells_sum(c->lv[l], fused, 0, SIZE_MAX);
+        a.emit_cfl = descs[e * P + p].emit_cfl;
         c->launches.push_back(a);
       } else {
         seg_desc1.push_back((int)(e * P + p));
@@ -1312,19 +1322,9 @@ vlbm_status prof_flush(vlbm_ctx *c) {
 
 // Launch every launch of one coarse step of table parity e.
 vlbm_status launch_coarse_step(vlbm_ctx *c, int e) {
-  if (c->adt) {  // this coarse step's link speed from the state at its start
-    StepLaunch a{};
-    const int s0 = e * c->nseg_table + c->s0_seg0;
-    if (c->s0_nseg == 1) {
-      a.d0 = c->hseg[s0].d;
-    } else {
-      a.segs = c->dseg + s0;
-      a.nseg = c->s0_nseg;
-    }
-    a.nblocks = c->s0_nblocks;
-    HIPCHK(launch_cfl(a, c->fp32, c->dcmax, c->ddyn, c->stream));
-    HIPCHK(launch_cfl_finalize(c->ddyn, c->dcmax, c->stream));
-  }
+  // this coarse step's link speed from the bound of the state at its start,
+  // which the previous coarse step's last launches (or cfl_init) left in dcmax
+  if (c->adt) HIPCHK(launch_cfl_finalize(c->ddyn, c->dcmax, c->stream));
   for (size_t ri = 0; ri < c->launches.size(); ++ri) {
     const LaunchRec &r = c->launches[ri];
     if (c->sensor && ri == 0 && c->hdesc[e * c->phases.size()].emit_qmax) {
@@ -1347,6 +1347,7 @@ vlbm_status launch_coarse_step(vlbm_ctx *c, int e) {
     a.nblocks = r.nblocks;
     a.first = r.first;
     a.flags = c->step_flags | (r.fused_kernel ? STEP_FUSED_PHASE : 0) | (c->adt ? STEP_ADAPTIVE_DT : 0);
+    if (c->adt && r.emit_cfl) a.flags |= STEP_CFL_EMIT;
     a.ak = r.ak;
     if (c->sensor && !r.fused_kernel) a.flags |= STEP_SENSOR;  // per-cell beta
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1390,6 +1391,26 @@ vlbm_status sensor_init(vlbm_ctx *c, int e) {
   return VLBM_OK;
 }
 
+// The CFL bound of the stored state, before a coarse step of table parity e,
+// after the host changed the state (eager, never inside a graph); the step
+// launches keep it current from then on.
+vlbm_status cfl_init(vlbm_ctx *c, int e) {
+  if (!c->adt || !c->cfl_stale) return VLBM_OK;
+  HIPCHK(hipMemsetAsync(c->dcmax, 0, sizeof(unsigned long long), c->stream));
+  StepLaunch a{};
+  const int s0 = e * c->nseg_table + c->s0_seg0;
+  if (c->s0_nseg == 1) {
+    a.d0 = c->hseg[s0].d;
+  } else {
+    a.segs = c->dseg + s0;
+    a.nseg = c->s0_nseg;
+  }
+  a.nblocks = c->s0_nblocks;
+  HIPCHK(launch_cfl(a, c->fp32, c->dcmax, c->ddyn, c->stream));
+  c->cfl_stale = false;
+  return VLBM_OK;
+}
+
 void count_steps(vlbm_ctx *c, long n) {
   for (int l = 0; l < c->nlev; ++l) c->lv[l].steps += n * c->flips[l];
   c->coarse_steps += n;
@@ -1422,6 +1443,7 @@ vlbm_status ensure_graph(vlbm_ctx *c) {
 vlbm_status advance_impl(vlbm_ctx *c, long n) {
   if (n > 0) {
     vlbm_status st = sensor_init(c, table_parity(c));
+    if (!st) st = cfl_init(c, table_parity(c));
     if (st) return st;
   }
   const bool graphs = c->use_graphs && !c->prof && c->stream != nullptr && n >= 4;
@@ -1516,6 +1538,7 @@ vlbm_status rect_io(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny, doub
     e = hipMemcpyAsync(stage, tmp.data(), sizeof(double) * ncomp * n, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_set_state(a, c->fp32, raw ? 1 : 0, c->stream);
     c->sensor_stale = true;
+    c->cfl_stale = true;
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   } else {
     e = launch_get(a, c->fp32, ncomp == 16 ? 1 : 0, c->stream);
@@ -2636,6 +2659,7 @@ vlbm_status vlbm_set_time_stepping(vlbm_ctx *c, int on, double kappa) {
   if (on && c->eos.kind != VLBM_EOS_IDEAL) return fail(VLBM_EINVAL, "adaptive time step: ideal gas only");
   HIPCHK(hipStreamSynchronize(c->stream));
   c->adt = on != 0;
+  c->cfl_stale = true;
   if (c->adt) {
     if (!c->ddyn) c->ddyn = static_cast<double *>(c->mem.alloc(sizeof(double) * DYN_SLOTS));
     if (!c->dcmax) c->dcmax = static_cast<unsigned long long *>(c->mem.alloc(sizeof(unsigned long long)));

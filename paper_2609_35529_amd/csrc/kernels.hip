@@ -275,6 +275,54 @@ __device__ __forceinline__ void block_qmax(double m[4], unsigned long long *qmax
   }
 }
 
+// Adaptive time step: the per-cell term of the CFL bound, max over both axes of
+// |u_alpha| + c_s, c_s = sqrt(gamma p / rho), from a cell's conserved state.
+__device__ __forceinline__ double cfl_term(const EosT<double> &eos, double gamma, const double w[4]) {
+  const double u = w[1] / w[0];
+  const double v = w[2] / w[0];
+  const double p = pressure<double>(eos, w[0], w[3] - 0.5 * (w[1] * u + w[2] * v));
+  const double cs = sqrt((gamma * p) / w[0]);
+  const double a = fabs(u) + cs, b = fabs(v) + cs;
+  return a > b ? a : b;
+}
+
+// W of a cell from its stored populations (FP64 sums in the fixed order).
+template <class T>
+__device__ __forceinline__ void stored_W(const T *s0, int64_t P, int64_t o, double w[4]) {
+  const auto s = (__attribute__((address_space(1))) const T *)s0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    w[k] = (((double)s[(0 * 4 + k) * P + o] + (double)s[(1 * 4 + k) * P + o]) +
+            (double)s[(2 * 4 + k) * P + o]) + (double)s[(3 * 4 + k) * P + o];
+}
+
+// W of a cell from the populations it is about to store: each rounded to the
+// storage type, then summed in FP64 in the fixed order of stored_W below, so
+// the value equals what stored_W gives for the stored cell.
+template <class T, class C>
+__device__ __forceinline__ void W_as_stored(const C g[16], double w[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    w[k] = (((double)(T)g[k] + (double)(T)g[4 + k]) + (double)(T)g[8 + k]) + (double)(T)g[12 + k];
+}
+
+// Fold a workgroup's maximum of non-negative doubles into *slot (as bits,
+// which order like the doubles); red: LDS scratch of one double per wave.
+// Every thread of the workgroup must call it.
+__device__ __forceinline__ void block_max_slot(double m, unsigned long long *slot, double *red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double v = red[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) v = fmax(v, red[i]);
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+    // the running maximum only grows: a stale read can only let an update through
+    if (bits > __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(slot, bits);
+  }
+}
+
 // Offset of level cell (x + dx, y + dy) (active, per its mask bit), periodic
 // wrap applied: a neighbour across the domain edge sits Nx columns (Ny rows)
 // back in the frame.
@@ -314,7 +362,7 @@ __device__ __forceinline__ bool mask_step(const __attribute__((address_space(1))
 
 // One workgroup's work on tile `lb` of descriptor A (inlined twice below, so
 // that A is either plain kernel-argument memory or plain global memory).
-template <class T, class C, bool NT, bool TWO, bool SEN>
+template <class T, class C, bool NT, bool TWO, bool SEN, bool CFL>
 __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks, int first,
                                          double ak, int flags) {
   // adaptive time step: this coarse step's h, and the hand-off's dt ratio when
@@ -337,6 +385,10 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
   const double hd = adt ? A.dyn[DYN_H] : A.h;
   if (adt && A.use_ratio) ak = ak * (A.dyn[DYN_C_PREV] / A.dyn[DYN_C]);
   const C h = (C)hd, tb = (C)A.tb;
+  // adaptive time step: the level's last step of the coarse step folds the
+  // CFL term of every cell it stores into the next coarse step's bound (a
+  // variant of its own, so that the other launches keep their registers)
+  const bool cfl = CFL && adt && A.emit_cfl != 0;
   // adaptive relaxation (eq. sensor-B): per-cell 2 beta in, W of the stored
   // result out, and on a level's last step of the coarse step the next max |Q|
   const auto Sp = (gptr<double>)(SEN ? A.sen : nullptr);
@@ -435,6 +487,15 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
     }
     __syncthreads();
   }
+  // with cfl, the CFL term of every stored cell (from the values as stored)
+  // joins the next coarse step's bound
+  double mc = 0.0;
+  double gam = 0.0;
+  EosT<double> eosc{};
+  if (cfl) {
+    eosc = eos_of<double>(A);
+    gam = A.dyn[DYN_GAMMA];
+  }
   if (TWO && !SEN) {
     // two cells per thread, both gathers issued before either relaxation
     for (int c = threadIdx.x; c < n; c += 2 * blockDim.x) {
@@ -451,9 +512,19 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
       }
       relax<C>(g, eos, h, tb);
       put<T, C, NT>(d, plane, o, g);
+      if (cfl) {
+        double w[4];
+        W_as_stored<T, C>(g, w);
+        mc = fmax(mc, cfl_term(eosc, gam, w));
+      }
       if (c2 < n) {
         relax<C>(g2, eos, h, tb);
         put<T, C, NT>(d, plane, o2, g2);
+        if (cfl) {
+          double w[4];
+          W_as_stored<T, C>(g2, w);
+          mc = fmax(mc, cfl_term(eosc, gam, w));
+        }
       }
     }
   } else {
@@ -489,18 +560,23 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
       }
       relax<C>(g, eos, h, tbc);
       put<T, C, NT>(d, plane, o, g);
-      if (SEN) {
+      if (SEN || cfl) {
         double w[4];
+        W_as_stored<T, C>(g, w);
+        if (SEN) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          w[k] = (((double)(T)g[k] + (double)(T)g[4 + k]) + (double)(T)g[8 + k]) + (double)(T)g[12 + k];
-          Wn[k * plane + o] = w[k];
+          for (int k = 0; k < 4; ++k) Wn[k * plane + o] = w[k];
+          if (emit) flux_absmax(eosd, w, m);
         }
-        if (emit) flux_absmax(eosd, w, m);
+        if (cfl) mc = fmax(mc, cfl_term(eosc, gam, w));
       }
     }
   }
   if (emit) block_qmax(m, A.qmax_next);
+  if (cfl) {
+    __shared__ double red[16];
+    block_max_slot(mc, A.cfl_next, red);
+  }
 }
 
 // DP_, FB_, NB_ := the descriptor of workgroup b of launch Lc, its
@@ -523,11 +599,11 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
   }
 
 
-template <class T, class C, bool NT, bool TWO, bool SEN>
+template <class T, class C, bool NT, bool TWO, bool SEN, bool CFL>
 __global__ __launch_bounds__(256) void step_kernel(StepLaunch Lc) {
   const int b = blockIdx.x;
   VLBM_FIND_SEGMENT(Lc, b, dp, first_block, nblocks)
-  run_tile<T, C, NT, TWO, SEN>(*dp, b - first_block, nblocks, Lc.first, Lc.ak, Lc.flags);
+  run_tile<T, C, NT, TWO, SEN, CFL>(*dp, b - first_block, nblocks, Lc.first, Lc.ak, Lc.flags);
 }
 
 // ---------------------------------------------------------------------------
@@ -608,7 +684,7 @@ __device__ __forceinline__ void run_task_k2(const LevelDesc &A, double ak2, doub
 template <class T, class C, bool NT>
 __device__ __forceinline__ void fused_tile(const LevelDesc &A, int lb, int nblocks, int flags) {
   constexpr int np = FUSE_POS;
-  __shared__ T F1[16 * FUSE_POS];
+  __shared__ __attribute__((aligned(16))) T F1[16 * FUSE_POS];
   // XCD-contiguous order: a tile's ring cells belong to its neighbours, whose
   // lines then sit in the same XCD's L2
   const int tid = (flags & STEP_XCD_CONTIGUOUS) ? (lb & 7) * (nblocks >> 3) + (lb >> 3) : lb;
@@ -631,6 +707,9 @@ __device__ __forceinline__ void fused_tile(const LevelDesc &A, int lb, int nbloc
     ak1 = ak1 * ratio;
     ak2 = ak2 * ratio;
   }
+  // adaptive time step: sub-step 2 folds the CFL term of every cell it stores
+  // into the next coarse step's bound when this is the level's last launch
+  const bool cfl = adt && A.emit_cfl != 0;
   const Task *tk = A.tasks + tl.task0;
   // Items of step 2: the tile cells, then the ring cells. A thread takes item
   // t and item t + blockDim (there are at most FUSE_W x FUSE_H + 2 (FUSE_W +
@@ -724,7 +803,15 @@ __device__ __forceinline__ void fused_tile(const LevelDesc &A, int lb, int nbloc
     }
   }
   __syncthreads();
-  // 4. sub-step 2 of the tile from LDS
+  // 4. sub-step 2 of the tile from LDS; with cfl, the CFL term of every
+  // stored cell (from the values as stored) joins the next coarse step's bound
+  double mc = 0.0;
+  double gam = 0.0;
+  EosT<double> eosd{};
+  if (cfl) {
+    eosd = eos_of<double>(A);
+    gam = A.dyn[DYN_GAMMA];
+  }
   for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
     const int cy = i / w, cx = i - cy * w;
     const int p0 = cy * w1 + cx, p1 = cy * w1 + cx + 1, p2 = cy * w + cx, p3 = (cy + 1) * w + cx;
@@ -739,6 +826,15 @@ __device__ __forceinline__ void fused_tile(const LevelDesc &A, int lb, int nbloc
     relax<C>(g, eos, h, tb);
     const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
     put<T, C, NT>(d, plane, o, g);
+    if (cfl) {
+      double wv[4];
+      W_as_stored<T, C>(g, wv);
+      mc = fmax(mc, cfl_term(eosd, gam, wv));
+    }
+  }
+  if (cfl) {
+    __syncthreads();  // every thread is done with F1: the reduction reuses it
+    block_max_slot(mc, A.cfl_next, reinterpret_cast<double *>(F1));
   }
 }
 
@@ -772,20 +868,28 @@ hipError_t launch_step(const StepLaunch &a, int fp32, hipStream_t s, hipEvent_t 
     return hipGetLastError();
   }
   const bool sen = (a.flags & STEP_SENSOR) != 0;  // per-cell beta: one cell per thread
-#define VLBM_STEP(S, C)                                                                                 \
-  do {                                                                                                  \
-    if (sen && nt)                                                                                      \
-      hipExtLaunchKernelGGL((step_kernel<S, C, true, false, true>), grid, block, 0, s, ev0, ev1, 0, a);   \
-    else if (sen)                                                                                       \
-      hipExtLaunchKernelGGL((step_kernel<S, C, false, false, true>), grid, block, 0, s, ev0, ev1, 0, a);  \
-    else if (nt && two)                                                                                 \
-      hipExtLaunchKernelGGL((step_kernel<S, C, true, true, false>), grid, block, 0, s, ev0, ev1, 0, a);   \
-    else if (nt)                                                                                        \
-      hipExtLaunchKernelGGL((step_kernel<S, C, true, false, false>), grid, block, 0, s, ev0, ev1, 0, a);  \
-    else if (two)                                                                                       \
-      hipExtLaunchKernelGGL((step_kernel<S, C, false, true, false>), grid, block, 0, s, ev0, ev1, 0, a);  \
-    else                                                                                                \
-      hipExtLaunchKernelGGL((step_kernel<S, C, false, false, false>), grid, block, 0, s, ev0, ev1, 0, a); \
+  const bool cfl = (a.flags & STEP_CFL_EMIT) != 0;
+#define VLBM_STEP1(S, C, CF)                                                                                \
+  do {                                                                                                      \
+    if (sen && nt)                                                                                          \
+      hipExtLaunchKernelGGL((step_kernel<S, C, true, false, true, CF>), grid, block, 0, s, ev0, ev1, 0, a);   \
+    else if (sen)                                                                                           \
+      hipExtLaunchKernelGGL((step_kernel<S, C, false, false, true, CF>), grid, block, 0, s, ev0, ev1, 0, a);  \
+    else if (nt && two)                                                                                     \
+      hipExtLaunchKernelGGL((step_kernel<S, C, true, true, false, CF>), grid, block, 0, s, ev0, ev1, 0, a);   \
+    else if (nt)                                                                                            \
+      hipExtLaunchKernelGGL((step_kernel<S, C, true, false, false, CF>), grid, block, 0, s, ev0, ev1, 0, a);  \
+    else if (two)                                                                                           \
+      hipExtLaunchKernelGGL((step_kernel<S, C, false, true, false, CF>), grid, block, 0, s, ev0, ev1, 0, a);  \
+    else                                                                                                    \
+      hipExtLaunchKernelGGL((step_kernel<S, C, false, false, false, CF>), grid, block, 0, s, ev0, ev1, 0, a); \
+  } while (0)
+#define VLBM_STEP(S, C)           \
+  do {                            \
+    if (cfl)                      \
+      VLBM_STEP1(S, C, true);     \
+    else                          \
+      VLBM_STEP1(S, C, false);    \
   } while (0)
   if (!fp32)
     VLBM_STEP(double, double);
@@ -793,6 +897,7 @@ hipError_t launch_step(const StepLaunch &a, int fp32, hipStream_t s, hipEvent_t 
     VLBM_STEP(float, double);
   else
     VLBM_STEP(float, float);
+#undef VLBM_STEP1
 #undef VLBM_STEP
   return hipGetLastError();
 }
@@ -938,18 +1043,10 @@ hipError_t launch_sensor(const StepLaunch &a, int stage, int fp32, hipStream_t s
 // and both axes of |u_alpha| + c_s, c_s = sqrt(gamma p / rho), from the stored
 // state at the start of the coarse step; then c_prev := c, c := c_n,
 // h := 1 / (2 c_n), t := t + dx0 / c_n (the one-thread finalize), and the max
-// slot is cleared for the next coarse step.
+// slot is cleared for the next coarse step. cfl_kernel takes the bound from
+// memory after the host changed the state; otherwise each level's last step
+// launch of the previous coarse step has already folded it in (emit_cfl).
 // ---------------------------------------------------------------------------
-// W of a cell from its stored populations (FP64 sums in the fixed order).
-template <class T>
-__device__ __forceinline__ void stored_W(const T *s0, int64_t P, int64_t o, double w[4]) {
-  const auto s = (__attribute__((address_space(1))) const T *)s0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-    w[k] = (((double)s[(0 * 4 + k) * P + o] + (double)s[(1 * 4 + k) * P + o]) +
-            (double)s[(2 * 4 + k) * P + o]) + (double)s[(3 * 4 + k) * P + o];
-}
-
 template <class T>
 __global__ __launch_bounds__(256) void cfl_kernel(StepLaunch Lc, unsigned long long *cmax, const double *dyn) {
   VLBM_FIND_SEGMENT(Lc, (int)blockIdx.x, dp, fb, nb)
@@ -969,24 +1066,10 @@ __global__ __launch_bounds__(256) void cfl_kernel(StepLaunch Lc, unsigned long l
     const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
     double w[4];
     stored_W<T>(static_cast<const T *>(A.src), P, o, w);
-    const double u = w[1] / w[0];
-    const double v = w[2] / w[0];
-    const double p = pressure<double>(eos, w[0], w[3] - 0.5 * (w[1] * u + w[2] * v));
-    const double cs = sqrt((gamma * p) / w[0]);
-    const double a = fabs(u) + cs, b = fabs(v) + cs;
-    m = fmax(m, a > b ? a : b);
+    m = fmax(m, cfl_term(eos, gamma, w));
   }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
-  __shared__ double red[4];
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double v = red[0];
-    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) v = fmax(v, red[i]);
-    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
-    if (bits > __hip_atomic_load(cmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(cmax, bits);
-  }
+  __shared__ double red[16];
+  block_max_slot(m, cmax, red);
 }
 
 __global__ void cfl_finalize_kernel(double *dyn, unsigned long long *cmax) {

@@ -93,6 +93,8 @@ enum StepFlags : int32_t {
   STEP_FUSED_PHASE = 32,     // launch-uniform: this phase is a fused two-sub-step launch
   STEP_SENSOR = 64,          // launch-uniform: relax with the per-cell beta of the sensor planes
   STEP_ADAPTIVE_DT = 128,    // launch-uniform: h and the hand-off's time-step ratio from DynState
+  STEP_CFL_EMIT = 256,       // launch-uniform: the level's last step launch of the coarse step folds
+                             // the CFL term of its stored cells into cfl_next (emit_cfl)
 };
 
 // Device scalars of the adaptive time step, updated once per coarse step by
@@ -165,7 +167,10 @@ struct LevelDesc {
   // adaptive time step: the DynState scalars, and whether this phase's parent
   // last stepped in the previous coarse step (hand-off takes c_prev / c)
   const double *dyn;
-  int32_t use_ratio, pad_dyn;
+  int32_t use_ratio;
+  int32_t emit_cfl;               // this phase is the level's last of the coarse step: fold the CFL
+                                  // term of every stored cell into *cfl_next
+  unsigned long long *cfl_next;   // the next coarse step's CFL bound (bits), cleared by the finalize
 };
 
 // A run of workgroups of one launch that works on one LevelDesc. first_block

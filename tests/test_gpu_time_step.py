@@ -111,6 +111,47 @@ def test_graph_replays_and_toggling(monkeypatch):
     _bitwise(o, g, case)
 
 
+@pytest.mark.parametrize("graphs", [False, True])
+def test_bound_after_host_changes(monkeypatch, graphs):
+    """Each coarse step's last launches carry the CFL bound to the next one.
+    A state written by the host (a fast block that raises the bound) and a
+    regrid replace it: the next link speed comes from the new state, bit for
+    bit as in the oracle, also where the steps replay as graphs."""
+    kw = {}
+    if graphs:
+        import torch
+        monkeypatch.setenv("VLBM_GRAPHS", "1")
+        kw["stream"] = torch.cuda.Stream()
+    case = wl.request_case(dict(n0=48, nlev=2, seed=3, steps=0))
+    o, g = _pair(case, 0, **kw)
+    o.advance(6)
+    g.advance(6)
+    _same_clock(o, g)
+    c_before = g.time()[1]
+    # level 0, 6 x 6 cells in the corner (the patch covers the central half)
+    rho, u, p = 1.0, 3.0, 1.0
+    U = np.zeros((4, 6, 6))
+    U[0], U[1], U[3] = rho, rho * u, p / 0.4 + 0.5 * rho * u * u
+    for s in (o, g):
+        s.set_state(0, U, 0, 0)
+    o.advance(1)
+    g.advance(1)
+    _same_clock(o, g)
+    assert g.time()[1] > c_before
+    _bitwise(o, g, case)
+    o.advance(5)
+    g.advance(5)
+    _same_clock(o, g)
+    (l, i0, j0, nx, ny), = case.boxes
+    for s in (o, g):
+        s.regrid([(l, i0 + 4, j0 - 2, nx, ny)])
+    for n in (1, 4):
+        o.advance(n)
+        g.advance(n)
+        _same_clock(o, g)
+        _bitwise(o, g, case)
+
+
 @pytest.mark.parametrize("precision", [1, 2])
 def test_fp32_storage_within_tolerance(precision):
     case = wl.vortex(n0=64, t_end=0.05)
