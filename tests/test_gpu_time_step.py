@@ -152,6 +152,20 @@ def test_bound_after_host_changes(monkeypatch, graphs):
         _bitwise(o, g, case)
 
 
+@pytest.mark.parametrize("tile,flags", [(256, 20), (1024, 0)])
+def test_full_size_quadrant(tile, flags):
+    """The 512^2 quadrant with its 512^2 fine patch, kappa = 1.5, in the launch
+    configurations the bench times (fused sub-steps in XCD order; unfused
+    natural order): 4 coarse steps bit for bit, clock included."""
+    case = wl.quadrant(n0=512, seed=0, steps=0)
+    o, g = _pair(case, 0)
+    g.set_tuning(tile, flags)
+    o.advance(4)
+    g.advance(4)
+    _same_clock(o, g)
+    _bitwise(o, g, case)
+
+
 @pytest.mark.parametrize("precision", [1, 2])
 def test_fp32_storage_within_tolerance(precision):
     case = wl.vortex(n0=64, t_end=0.05)
