@@ -182,6 +182,21 @@ def actual_updates_per_step(case):
     return case.actual_updates_per_coarse_step()
 
 
+def host_cpu():
+    """The host the oracle runs on: CPU model and the logical CPUs it offers."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "available_to_process": avail}
+
+
 def cpu_baseline(case, budget_s=15.0, boxes=None, mem_cap=8e9, sensor=None, adaptive_dt=None):
     """The oracle, single-threaded, on a bounded prefix of the same workload.
     A dynamic workload is sampled on the hierarchy the GPU run starts its timed
@@ -195,7 +210,8 @@ def cpu_baseline(case, budget_s=15.0, boxes=None, mem_cap=8e9, sensor=None, adap
                for l in range(case.nlev))
     if need > mem_cap:
         return {"value": None, "unit": "fine-equiv cell updates/s", "cores": 1, "kind": "oracle",
-                "sample": f"not run: the oracle's dense level arrays need {need / 1e9:.0f} GB"}
+                "sample": f"not run: the oracle's dense level arrays need {need / 1e9:.0f} GB",
+                "host": host_cpu()}
     o = exact.run_oracle(case, steps=0)
     if sensor:
         o.set_sensor(True, *sensor)
@@ -215,7 +231,7 @@ def cpu_baseline(case, budget_s=15.0, boxes=None, mem_cap=8e9, sensor=None, adap
         held += f", adaptive time step (kappa = {adaptive_dt})"
     return {"value": fe, "unit": "fine-equiv cell updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{case.name} full size, first {n} coarse steps ({el:.1f} s){held}, FP64, "
-                      f"one thread"}
+                      f"one thread", "host": host_cpu()}
 
 
 def copy_probe(gib=2.0, reps=20):

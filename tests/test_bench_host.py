@@ -39,3 +39,13 @@ def test_uniform_sizes():
 def test_unknown_workload():
     with pytest.raises(SystemExit):
         bench.build_case("no-such-workload", 1)
+
+
+def test_cpu_baseline_reports_its_host():
+    """The oracle leg on a tiny workload: a positive rate, one thread, and the
+    host CPU it ran on."""
+    from paper_2609_35529_amd import workloads as wl
+    r = bench.cpu_baseline(wl.sod_2d(steps=3), budget_s=5.0)
+    assert r["value"] > 0 and r["cores"] == 1 and r["kind"] == "oracle"
+    assert r["host"]["logical_cpus"] >= 1 and r["host"]["available_to_process"] >= 1
+    assert "first 3 coarse steps" in r["sample"]
