@@ -32,9 +32,9 @@ HBM_PEAK_GBS = 8000.0
 # x 1.000 (scales measured on a plain 2 GiB copy); valid only for the kernel
 # source it was measured on. The fused tile shape does not depend on
 # tile_cells, so any tile_cells matches.
-MEASURED_TRAFFIC = {"kernel_sha256_16": "93baf27763ee153f", "workload": "quadrant512",
+MEASURED_TRAFFIC = {"kernel_sha256_16": "6cf11abdac8d69f4", "workload": "quadrant512",
                     "precision": "fp64", "tile_cells": None, "flags": 20, "kernel": "fused_kernel",
-                    "bytes_per_launch": 75445708.0}
+                    "bytes_per_launch": 75366669.0}
 
 
 # dynamic-refinement workloads: re-tag and regrid every few coarse steps

@@ -1376,7 +1376,7 @@ vlbm_status launch_coarse_step(vlbm_ctx *c, int e) {
 // first; eager, never inside a graph).
 vlbm_status sensor_init(vlbm_ctx *c, int e) {
   if (!c->sensor || !c->sensor_stale) return VLBM_OK;
-  HIPCHK(hipMemsetAsync(c->dqmax, 0, 8 * sizeof(unsigned long long), c->stream));
+  HIPCHK(launch_clear_u64(c->dqmax, 8, c->stream));
   StepLaunch a{};
   const int s0 = e * c->nseg_table + c->s0_seg0;
   if (c->s0_nseg == 1) {
@@ -1396,7 +1396,7 @@ vlbm_status sensor_init(vlbm_ctx *c, int e) {
 // launches keep it current from then on.
 vlbm_status cfl_init(vlbm_ctx *c, int e) {
   if (!c->adt || !c->cfl_stale) return VLBM_OK;
-  HIPCHK(hipMemsetAsync(c->dcmax, 0, sizeof(unsigned long long), c->stream));
+  HIPCHK(launch_clear_u64(c->dcmax, 1, c->stream));
   StepLaunch a{};
   const int s0 = e * c->nseg_table + c->s0_seg0;
   if (c->s0_nseg == 1) {

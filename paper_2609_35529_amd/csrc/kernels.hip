@@ -1094,6 +1094,19 @@ hipError_t launch_cfl(const StepLaunch &a, int fp32, unsigned long long *cmax, c
   return hipGetLastError();
 }
 
+// Zero n 64-bit words: a kernel rather than a memset, because advance may run
+// under a caller's stream capture, and a captured memset node is avoided.
+__global__ void clear_u64_kernel(unsigned long long *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(clear_u64_kernel, dim3((n + 63) / 64), dim3(64), 0, s, p, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_cfl_finalize(double *dyn, unsigned long long *cmax, hipStream_t s) {
   hipLaunchKernelGGL(cfl_finalize_kernel, dim3(1), dim3(64), 0, s, dyn, cmax);
   return hipGetLastError();

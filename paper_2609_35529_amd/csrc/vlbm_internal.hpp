@@ -221,6 +221,8 @@ hipError_t launch_sensor(const StepLaunch &a, int stage, int fp32, hipStream_t s
 hipError_t launch_cfl(const StepLaunch &a, int fp32, unsigned long long *cmax, const double *dyn,
                       hipStream_t s);
 hipError_t launch_cfl_finalize(double *dyn, unsigned long long *cmax, hipStream_t s);
+// Zero n 64-bit words of device memory on stream s (no memset node under capture).
+hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t s);
 // Neighbour masks of a level frame from its status (fw x fh bytes, 1 = active).
 hipError_t launch_sensor_mask(const uint8_t *status, uint8_t *mask, int fx0, int fy0, int fw, int fh,
                               int pitch, int xoff, int Nx, int Ny, int per, hipStream_t s);
