@@ -245,7 +245,12 @@ vlbm_status vlbm_set_sensor(vlbm_ctx *ctx, int on, double c_sensor, double beta_
  * stepped in the previous coarse step scales its temporal slope by
  * dt_now / dt_prev = c_prev / c_n. kappa > 0; ideal gas only (VLBM_EINVAL
  * otherwise). set_state keeps building equilibria with vlbm_params.c; on = 0
- * returns to it. Not taken by vlbm_batch_advance. */
+ * returns to it. Not taken by vlbm_batch_advance. The maximum is accumulated
+ * by each level's last step launch of the previous coarse step from the
+ * values it stores; after a host-side change of the state (set_state,
+ * set_populations, regrid, tag_and_regrid, load, a new hierarchy or tuning)
+ * the next advance first reads every level once to take it from memory. Both
+ * give the same bits. */
 vlbm_status vlbm_set_time_stepping(vlbm_ctx *ctx, int on, double kappa);
 
 /* Elapsed time since set_state and the link speed of the last coarse step
