@@ -188,7 +188,10 @@ vlbm_status vlbm_load(vlbm_ctx *ctx, const void *buf, size_t bytes);
 /* Advance several contexts together, n_steps[i] coarse steps each, with the
  * phases of all contexts merged into shared launches. All contexts must use
  * the same stream, precision and refinement ratio, and none may have fused
- * sub-steps (tuning flag 16) in effect: VLBM_EINVAL otherwise. */
+ * sub-steps (tuning flag 16) in effect; either all or none use the adaptive
+ * relaxation, and either all or none the adaptive time step (each with its
+ * own constants and clock): VLBM_EINVAL otherwise. Each context's results are
+ * bit-identical to advancing it alone. */
 vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nctx);
 
 /* Launch tuning (no effect on results, which are identical for every
@@ -245,7 +248,8 @@ vlbm_status vlbm_set_sensor(vlbm_ctx *ctx, int on, double c_sensor, double beta_
  * stepped in the previous coarse step scales its temporal slope by
  * dt_now / dt_prev = c_prev / c_n. kappa > 0; ideal gas only (VLBM_EINVAL
  * otherwise). set_state keeps building equilibria with vlbm_params.c; on = 0
- * returns to it. Not taken by vlbm_batch_advance. The maximum is accumulated
+ * returns to it. vlbm_batch_advance takes it when every context of the batch
+ * uses it. The maximum is accumulated
  * by each level's last step launch of the previous coarse step from the
  * values it stores; after a host-side change of the state (set_state,
  * set_populations, regrid, tag_and_regrid, load, a new hierarchy or tuning)

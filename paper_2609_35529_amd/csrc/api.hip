@@ -2445,7 +2445,8 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
       return fail(VLBM_EINVAL, "context %d uses fused sub-steps, which batched launches do not take", i);
     if (c->sensor != c0->sensor)
       return fail(VLBM_EINVAL, "batched contexts must all use the adaptive relaxation, or none");
-    if (c->adt) return fail(VLBM_EINVAL, "context %d uses an adaptive time step, which batched launches do not take", i);
+    if (c->adt != c0->adt)
+      return fail(VLBM_EINVAL, "batched contexts must all use the adaptive time step, or none");
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == c) return fail(VLBM_EINVAL, "context %d listed twice", i);
   }
@@ -2503,8 +2504,9 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
         nseg[e * P + p] = (int32_t)segs.size() - seg0[e * P + p];
         nblk[e * P + p] = fb;
       }
-    for (int i : act) {  // adaptive relaxation stage 0 where the state changed
+    for (int i : act) {  // adaptive relaxation stage 0 and the CFL bound where the state changed
       vlbm_status st = sensor_init(ctxs[i], table_parity(ctxs[i]));
+      if (!st) st = cfl_init(ctxs[i], table_parity(ctxs[i]));
       if (st) return st;
     }
     Segment *dseg = static_cast<Segment *>(c0->mem.alloc(sizeof(Segment) * std::max<size_t>(1, segs.size())));
@@ -2512,6 +2514,16 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
     HIPCHK(hipMemcpyAsync(dseg, segs.data(), sizeof(Segment) * segs.size(), hipMemcpyHostToDevice, c0->stream));
     for (long s2 = 0; s2 < m; ++s2) {
       const int e = (int)(s2 & 1);
+      // adaptive time step: every context's link speed for this coarse step,
+      // from the bound its previous coarse step's last launches left
+      for (int i : act)
+        if (ctxs[i]->adt) {
+          const hipError_t err = launch_cfl_finalize(ctxs[i]->ddyn, ctxs[i]->dcmax, c0->stream);
+          if (err != hipSuccess) {
+            c0->mem.release(dseg);
+            return fail(VLBM_EDEVICE, "batched launch: %s", hipGetErrorString(err));
+          }
+        }
       for (size_t p = 0; p < P; ++p) {
         if (nseg[e * P + p] == 0) continue;
         StepLaunch L{};
@@ -2521,6 +2533,17 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
         L.first = ph[p].second == 1;
         L.flags = c0->step_flags;
         L.ak = ak_of(ph[p].second, r);
+        if (c0->adt) {
+          L.flags |= STEP_ADAPTIVE_DT;
+          // the variant that folds the CFL term, where some context's level
+          // takes its last step of the coarse step in this launch
+          for (size_t a = 0; a < act.size(); ++a) {
+            const vlbm_ctx *ca = ctxs[act[a]];
+            const int pi = occ_index[a][p];
+            if (pi >= 0 && ca->hdesc[(table_parity(ca) ^ e) * ca->phases.size() + pi].emit_cfl)
+              L.flags |= STEP_CFL_EMIT;
+          }
+        }
         hipError_t err = hipSuccess;
         if (c0->sensor) {
           // a context whose first phase this is, and which also accumulates

@@ -176,10 +176,61 @@ def test_fp32_storage_within_tolerance(precision):
     assert abs(c - o.link_speed()) <= 1e-6 * c and abs(t - o.time()) <= 1e-6 * t
 
 
-def test_batch_refuses_adaptive_contexts():
+def test_batch_refuses_mixing_fixed_and_adaptive():
     from paper_2609_35529_amd import vlbm
     a = gpu_solver(wl.request_case(dict(n0=32, nlev=1, seed=1, steps=0)))
     b = gpu_solver(wl.request_case(dict(n0=32, nlev=1, seed=2, steps=0)))
     a.set_time_stepping(True, 1.5)
     with pytest.raises(vlbm.VLBMError):
         vlbm.batch_advance([a, b], [1, 1])
+
+
+def test_batch_equals_alone():
+    """Contexts of different sizes, depths and kappas in batched launches:
+    each context's populations and clock are bit-identical to advancing it
+    alone, and to the oracle; a host-side state change in between is taken
+    into the next bound."""
+    import torch
+    from paper_2609_35529_amd import vlbm
+    stream = torch.cuda.Stream()
+    specs = ((32, 1, 1, 1.5), (64, 2, 2, 1.2), (48, 3, 3, 2.0))
+    steps = [5, 7, 4]
+    cases = [wl.request_case(dict(n0=n, nlev=l, seed=sd, steps=0)) for n, l, sd, _ in specs]
+
+    def make(case, kappa):
+        g = gpu_solver(case, stream=stream)
+        g.set_time_stepping(True, kappa)
+        return g
+
+    alone = [make(c, k) for c, (_, _, _, k) in zip(cases, specs)]
+    for g, n in zip(alone, steps):
+        g.advance(n)
+    batched = [make(c, k) for c, (_, _, _, k) in zip(cases, specs)]
+    vlbm.batch_advance(batched, steps)
+    for case, a, b, (_, _, _, k), n in zip(cases, alone, batched, specs, steps):
+        assert a.time() == b.time()
+        for l in range(case.nlev):
+            assert np.array_equal(a.get_populations(l), b.get_populations(l), equal_nan=True), l
+        o = exact_oracle(case, k, n)
+        _same_clock(o, b)
+        _bitwise(o, b, case)
+    # a faster block written into the first context, then one more batched round
+    U = np.zeros((4, 4, 4))
+    U[0], U[1], U[3] = 1.0, 3.0, 1.0 / 0.4 + 4.5
+    alone[0].set_state(0, U, 0, 0)
+    batched[0].set_state(0, U, 0, 0)
+    for g in alone:
+        g.advance(3)
+    vlbm.batch_advance(batched, [3, 3, 3])
+    for case, a, b in zip(cases, alone, batched):
+        assert a.time() == b.time()
+        for l in range(case.nlev):
+            assert np.array_equal(a.get_populations(l), b.get_populations(l), equal_nan=True), l
+
+
+def exact_oracle(case, kappa, n):
+    from tests import exact
+    o = exact.run_oracle(case, steps=0)
+    o.set_time_stepping(True, kappa)
+    o.advance(n)
+    return o
