@@ -18,6 +18,9 @@ _lib = None
 PERIODIC, OUTFLOW, REFLECT, INFLOW = 0, 1, 2, 3
 EOS_IDEAL, EOS_STIFFENED, EOS_VDW = 0, 1, 2
 MUT_NONE, MUT_REFLUX_END_LABEL, MUT_RECON_SIGMA_SIGN, MUT_REFLUX_LAST_ONLY = 0, 1, 2, 3
+MUT_REGRID_RESTART_ALL, MUT_REGRID_NEW_FACE_HISTORY, MUT_WALL_NO_FLIP = 4, 5, 6
+MUT_SENSOR_BOX_SUM, MUT_SENSOR_MAX_NORM, MUT_SLOPE_RATIO_INVERTED, MUT_TAG_ONE_SIDED = 7, 8, 9, 10
+FMUT_NONE, FMUT_VDW_SIGN = 0, 1
 
 _D = C.POINTER(C.c_double)
 _I = C.POINTER(C.c_int)
@@ -35,6 +38,7 @@ def lib():
         L.orc_free.argtypes = [C.c_void_p]
         L.orc_set_eos.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double]
         L.orc_set_mutation.argtypes = [C.c_void_p, C.c_int]
+        L.orc_set_function_mutation.argtypes = [C.c_int]
         L.orc_set_sensor.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_double]
         L.orc_get_beta.argtypes = [C.c_void_p, C.c_int, _D]
         L.orc_set_boxes.argtypes = [C.c_void_p, _I, C.c_int]
@@ -99,6 +103,11 @@ def collide(g, gamma, c, beta, eos=EOS_IDEAL, a=0.0, b=0.0):
     out = np.empty(16)
     lib().orc_collide(gamma, c, beta, eos, a, b, _dp(g), _dp(out))
     return out.reshape(4, 4)
+
+
+def set_function_mutation(mut):
+    """Plant (mut != 0) or remove a mistake in the single-operation functions."""
+    lib().orc_set_function_mutation(mut)
 
 
 def minmod(a, b):

@@ -21,6 +21,11 @@ _U8 = C.POINTER(C.c_uint8)
 _ready = False
 
 
+# planted mistakes (vlbm3_oracle.h)
+(MUT_NONE, MUT_TAN_SLOPE_SIGN, MUT_TAN_OFFSETS_SWAPPED, MUT_REFLUX_R2, MUT_WALL_NO_FLIP,
+ MUT_MERGE_R2, MUT_SPLIT_SLOPE_SIGN, MUT_REGRID_RESTART_ALL, MUT_REGRID_NEW_FACE_HISTORY) = range(9)
+
+
 def lib():
     global _ready
     L = _o2.lib()
@@ -29,6 +34,7 @@ def lib():
         L.orc3_new.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
                                C.c_double, C.c_double, C.c_double, _I]
         L.orc3_free.argtypes = [C.c_void_p]
+        L.orc3_set_mutation.argtypes = [C.c_void_p, C.c_int]
         L.orc3_set_boxes.argtypes = [C.c_void_p, _I, C.c_int]
         L.orc3_regrid.argtypes = [C.c_void_p, _I, C.c_int]
         L.orc3_tag.argtypes = [C.c_void_p, C.c_int, C.c_double, _U8]
@@ -87,6 +93,9 @@ class Oracle3:
         if getattr(self, "_h", None):
             lib().orc3_free(self._h)
             self._h = None
+
+    def set_mutation(self, mut):
+        lib().orc3_set_mutation(self._h, mut)
 
     def shape(self, level):
         s = (C.c_int * 3)()

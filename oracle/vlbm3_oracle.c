@@ -27,8 +27,10 @@
  * the reflux books the values at the start of each fine sub-step, the first
  * cycle of an interface has no older coarse sample (prev := out), a tangential
  * slope needs both tangential neighbours active at the parent's level (else
- * 0), relaxation is f + 2 beta (feq - f). Ideal gas; sides are periodic,
- * outflow (zero gradient) or reflecting.
+ * 0), relaxation is f + 2 beta (feq - f), and a regrid keeps the temporal
+ * reconstruction of every interface that exists before and after it (only
+ * the faces it creates start flat). Ideal gas; sides are periodic, outflow
+ * (zero gradient) or reflecting.
  */
 #include "vlbm3_oracle.h"
 
@@ -54,9 +56,18 @@ struct orc3 {
   int N[O3MAXL][3];
   double dx[O3MAXL];
   double *F[O3MAXL], *Fp[O3MAXL], *G[O3MAXL], *acc[O3MAXL];
-  unsigned char *cov[O3MAXL], *pok[O3MAXL];
+  unsigned char *cov[O3MAXL];
+  /* pok: per cell, bit q set when the cell's previous-step sample of
+   * population q may serve as the hand-off's older coarse sample */
+  unsigned char *pok[O3MAXL];
   double led[5], ledc[5];
+  int mut;
 };
+
+int orc3_set_mutation(orc3 *o, int mut) {
+  o->mut = mut;
+  return 0;
+}
 
 static void kadd3(double *s, double *cmp, double v) {
   double t = *s + v;
@@ -354,7 +365,7 @@ static void boundary3(const orc3 *o, int l, int side, int q, int x, int y, int z
     int qo = q ^ 1, kn = 1 + q / 2;
     for (int k = 0; k < 5; ++k) {
       double w = F[pid(o, l, qo * 5 + k, x, y, z)];
-      v[k] = (k == kn) ? -w : w;
+      v[k] = (k == kn && o->mut != ORC3_MUT_WALL_NO_FLIP) ? -w : w;
     }
   }
 }
@@ -367,7 +378,7 @@ static void recon3(const orc3 *o, int l, int q, int kstep, const int p[3], const
   int lp = l - 1, r = o->r, n = q / 2;
   int P[3] = {s[0] / r, s[1] / r, s[2] / r};
   const double *F = o->F[lp], *Fp = o->Fp[lp];
-  int has_prev = o->pok[lp][cid(o, lp, P[0], P[1], P[2])];
+  int has_prev = (o->pok[lp][cid(o, lp, P[0], P[1], P[2])] >> q) & 1;
   int ta[2], nt = 0;
   for (int a = 0; a < 3; ++a)
     if (a != n) ta[nt++] = a;
@@ -386,6 +397,11 @@ static void recon3(const orc3 *o, int l, int q, int kstep, const int p[3], const
     int j = p[a] - r * P[a];
     bj[t] = (double)(2 * j - r + 1) / (double)(2 * r);
   }
+  if (o->mut == ORC3_MUT_TAN_OFFSETS_SWAPPED) {
+    double b0 = bj[0];
+    bj[0] = bj[1];
+    bj[1] = b0;
+  }
   double ak = (double)(2 * kstep - r - 1) / (double)(2 * r);
   size_t nc = ncell(o, lp), ci = cid(o, lp, P[0], P[1], P[2]);
   for (int k = 0; k < 5; ++k) {
@@ -395,6 +411,7 @@ static void recon3(const orc3 *o, int l, int q, int kstep, const int p[3], const
     double val = out + (out - prev) * ak;
     for (int t = 0; t < 2; ++t) {
       double sigma = have[t] ? minmod3(out - F[pl + im[t]], F[pl + ip[t]] - out) : 0.0;
+      if (o->mut == ORC3_MUT_TAN_SLOPE_SIGN) sigma = -sigma;
       val = val + sigma * bj[t];
     }
     v[k] = val;
@@ -431,7 +448,7 @@ static void advance3(orc3 *o, int l, int kstep) {
       }
   /* transport (exact shift) into G with interface and boundary fills */
   double *G = o->G[l];
-  const double r3 = (double)(r * r * r);
+  const double r3 = o->mut == ORC3_MUT_REFLUX_R2 ? (double)(r * r) : (double)(r * r * r);
   for (int z = 0; z < N[2]; ++z)
     for (int y = 0; y < N[1]; ++y)
       for (int x = 0; x < N[0]; ++x) {
@@ -473,7 +490,7 @@ static void advance3(orc3 *o, int l, int kstep) {
   for (int z = 0; z < N[2]; ++z)
     for (int y = 0; y < N[1]; ++y)
       for (int x = 0; x < N[0]; ++x)
-        o->pok[l][cid(o, l, x, y, z)] = (unsigned char)active3(o, l, x, y, z);
+        o->pok[l][cid(o, l, x, y, z)] = active3(o, l, x, y, z) ? 0x3F : 0;
 }
 
 /* Level l+1 takes r steps inside each step of level l, then level l steps. */
@@ -555,10 +572,11 @@ int orc3_regrid(orc3 *o, const int *boxes, int nboxes) {
               for (int b = 0; b < r; ++b)
                 for (int a = 0; a < r; ++a)
                   sum += o->F[l][pid(o, l, i, px * r + a, py * r + b, pz * r + g)];
-            double m = sum / (double)(r * r * r);
+            double m = sum / (o->mut == ORC3_MUT_MERGE_R2 ? (double)(r * r) : (double)(r * r * r));
             o->F[l - 1][(size_t)i * ncell(o, l - 1) + pc] = m;
             o->Fp[l - 1][(size_t)i * ncell(o, l - 1) + pc] = m;
           }
+          o->pok[l - 1][pc] = 0;
         }
   }
   /* 2. splits, coarsest level first (eqs. amr-slope, amr-split): a slope
@@ -592,6 +610,8 @@ int orc3_regrid(orc3 *o, const int *boxes, int nboxes) {
             double fi = F[pc], sl[3];
             for (int a = 0; a < 3; ++a)
               sl[a] = (avail[2 * a] && avail[2 * a + 1]) ? minmod3(fi - F[nb[2 * a + 1]], F[nb[2 * a]] - fi) : 0.0;
+            if (o->mut == ORC3_MUT_SPLIT_SLOPE_SIGN)
+              for (int a = 0; a < 3; ++a) sl[a] = -sl[a];
             for (int g = 0; g < r; ++g)
               for (int b = 0; b < r; ++b)
                 for (int a = 0; a < r; ++a) {
@@ -601,13 +621,39 @@ int orc3_regrid(orc3 *o, const int *boxes, int nboxes) {
                   o->Fp[l + 1][ci] = v;
                 }
           }
+          for (int g = 0; g < r; ++g)
+            for (int b = 0; b < r; ++b)
+              for (int a = 0; a < r; ++a)
+                o->pok[l + 1][cid(o, l + 1, px * r + a, py * r + b, pz * r + g)] = 0;
         }
   }
-  /* 3. adopt the new coverage; every interface restarts its temporal
-   *    reconstruction (no previous-step samples). */
+  /* 3. interfaces: a face of level-l cell P towards a level-(l+1) hole P + c_q
+   *    that existed before the regrid keeps P's history of population q (the
+   *    reconstruction runs unmodified there, Sec. 3.4); a face the regrid
+   *    creates starts flat (no older sample on that face). */
+  for (int l = 0; l + 1 < L; ++l) {
+    const int *Np = o->N[l];
+    for (int pz = 0; pz < Np[2]; ++pz)
+      for (int py = 0; py < Np[1]; ++py)
+        for (int px = 0; px < Np[0]; ++px) {
+          size_t ci = cid(o, l, px, py, pz);
+          if (!o->pok[l][ci] || !ncov[l][ci]) continue;
+          size_t ch = cid(o, l + 1, px * r, py * r, pz * r);
+          if (ncov[l + 1][ch]) continue;
+          const int act_old = ocov[l][ci] && !ocov[l + 1][ch];
+          for (int q = 0; q < 6; ++q) {
+            int h[3] = {px + C3X[q], py + C3Y[q], pz + C3Z[q]};
+            if (!wrap3(o, l, h)) continue;
+            size_t hc = cid(o, l + 1, h[0] * r, h[1] * r, h[2] * r);
+            if (ncov[l + 1][hc] && !(act_old && ocov[l + 1][hc]) && o->mut != ORC3_MUT_REGRID_NEW_FACE_HISTORY)
+              o->pok[l][ci] &= (unsigned char)~(1u << q);
+          }
+        }
+  }
+  /* 4. adopt the new coverage */
   for (int l = 0; l < L; ++l) {
+    if (o->mut == ORC3_MUT_REGRID_RESTART_ALL) memset(o->pok[l], 0, ncell(o, l));
     memcpy(o->cov[l], ncov[l], ncell(o, l));
-    memset(o->pok[l], 0, ncell(o, l));
     free(ncov[l]);
   }
   return 0;

@@ -28,9 +28,11 @@
  * sub-step k, i.e. post-collision values at its start; the first cycle after an
  * interface appears has no older coarse sample, so prev := out (slope 0); the
  * tangential slope uses the cells at L0 -+ tau when they are active at the
- * same level, else sigma = 0; after a regrid every interface restarts its
- * temporal reconstruction (slope 0 on the first cycle); relaxation is
- * evaluated as f + 2 beta (feq - f);
+ * same level, else sigma = 0; a regrid leaves the reconstruction of every
+ * interface that exists both before and after it unmodified (Sec. 3.4: the
+ * operators run unchanged at whichever interfaces are active), so only the
+ * interfaces it creates start with slope 0; relaxation is evaluated as
+ * f + 2 beta (feq - f);
  * merges run finest level first and splits coarsest level first; split slopes
  * use neighbours covered at that level in the new hierarchy that hold data.
  *
@@ -76,7 +78,10 @@ struct orc {
   double dx[OMAXL];
   double *F[OMAXL], *Fp[OMAXL], *G[OMAXL], *acc[OMAXL];
   double *accl[OMAXL]; /* last-sub-step-only variant (planted mistake) */
-  unsigned char *cov[OMAXL], *pok[OMAXL];
+  unsigned char *cov[OMAXL];
+  /* pok: per cell, bit q set when the cell's previous-step sample of
+   * population q may serve as the hand-off's older coarse sample (eq. 1d-recon) */
+  unsigned char *pok[OMAXL];
   double led[4], ledc[4];
 };
 
@@ -95,12 +100,17 @@ static void kadd(double *s, double *cmp, double v) {
 /* ------------------------------------------------------------------ */
 /* Equation of state and Euler flux (Sec. 2.1: the EOS is generic)     */
 /* ------------------------------------------------------------------ */
+static int g_fmut = 0;
+void orc_set_function_mutation(int mut) { g_fmut = mut; }
+
 static double pressure(int eos, double gamma, double a, double b, double rho, double mx,
                        double my, double E) {
   double u = mx / rho;
   double v = my / rho;
   double eint = E - 0.5 * (mx * u + my * v); /* internal energy per volume */
   if (eos == ORC_EOS_STIFFENED) return (gamma - 1.0) * eint - gamma * a;
+  if (eos == ORC_EOS_VDW && g_fmut == 1) /* planted mistake */
+    return (gamma - 1.0) * (eint - a * rho * rho) / (1.0 - b * rho) - a * rho * rho;
   if (eos == ORC_EOS_VDW) return (gamma - 1.0) * (eint + a * rho * rho) / (1.0 - b * rho) - a * rho * rho;
   return (gamma - 1.0) * eint;
 }
@@ -479,7 +489,7 @@ static void boundary_value(const orc *o, int l, int side, int q, int x, int y, d
     int kn = (side < 2) ? 1 : 2;
     for (int k = 0; k < 4; ++k) {
       double w = F[pidx(o, l, qo * 4 + k, x, y)];
-      v[k] = (k == kn) ? -w : w;
+      v[k] = (k == kn && o->mut != ORC_MUT_WALL_NO_FLIP) ? -w : w;
     }
   } else {
     double feq[16];
@@ -513,7 +523,7 @@ static void recon(const orc *o, int l, int q, int kstep, int x, int y, int sx, i
   int mx_ = px - tx, my_ = py - ty, qx_ = px + tx, qy_ = py + ty;
   int have = wrap(o, lp, &mx_, &my_) && wrap(o, lp, &qx_, &qy_) && active(o, lp, mx_, my_) &&
              active(o, lp, qx_, qy_);
-  int has_prev = o->pok[lp][cidx(o, lp, px, py)];
+  int has_prev = (o->pok[lp][cidx(o, lp, px, py)] >> q) & 1;
   for (int k = 0; k < 4; ++k) {
     double out = F[pidx(o, lp, q * 4 + k, px, py)];
     double prev = has_prev ? Fp[pidx(o, lp, q * 4 + k, px, py)] : out;
@@ -524,7 +534,8 @@ static void recon(const orc *o, int l, int q, int kstep, int x, int y, int sx, i
       sigma = orc_minmod(out - fm, fp - out);
       if (o->mut == ORC_MUT_RECON_SIGMA_SIGN) sigma = -sigma;
     }
-    v[k] = orc_recon_value_scaled(out, prev, sigma, r, kstep, j, o->c_last[lp] / o->c);
+    const double ratio = o->mut == ORC_MUT_SLOPE_RATIO_INVERTED ? o->c / o->c_last[lp] : o->c_last[lp] / o->c;
+    v[k] = orc_recon_value_scaled(out, prev, sigma, r, kstep, j, ratio);
   }
 }
 
@@ -610,6 +621,10 @@ static void sensor_beta(orc *o, int l) {
         sk[k] = qmax[k] > 0.0 ? (0.5 * dq) / qmax[k] : 0.0;
       }
       a[c] = sqrt(0.25 * (((sk[0] * sk[0] + sk[1] * sk[1]) + sk[2] * sk[2]) + sk[3] * sk[3]));
+      if (o->mut == ORC_MUT_SENSOR_MAX_NORM) { /* planted mistake */
+        a[c] = 0.0;
+        for (int k = 0; k < 4; ++k) a[c] = fabs(sk[k]) > a[c] ? fabs(sk[k]) : a[c];
+      }
       double dil = 0.5 * ((u[0] - u[1]) + (v[2] - v[3]));
       double vort = 0.5 * ((v[0] - v[1]) - (u[2] - u[3]));
       const double den = dil * dil + vort * vort;
@@ -628,7 +643,7 @@ static void sensor_beta(orc *o, int l) {
           sum += a[cidx(o, l, xx, yy)];
           ++n;
         }
-      double z = (o->c_sensor * (sum / n)) * th[c];
+      double z = (o->c_sensor * (o->mut == ORC_MUT_SENSOR_BOX_SUM ? sum : sum / n)) * th[c];
       z = z < 0.0 ? 0.0 : z > 1.0 ? 1.0 : z;
       beta[c] = o->beta_max - (o->beta_max - o->beta_min) * z;
     }
@@ -731,7 +746,7 @@ static void advance_level(orc *o, int l, int kstep) {
   o->F[l] = o->G[l];
   o->G[l] = old;
   for (int y = 0; y < Ny; ++y)
-    for (int x = 0; x < Nx; ++x) o->pok[l][cidx(o, l, x, y)] = (unsigned char)active(o, l, x, y);
+    for (int x = 0; x < Nx; ++x) o->pok[l][cidx(o, l, x, y)] = active(o, l, x, y) ? 0xF : 0;
 
   if (o->mut == ORC_MUT_REFLUX_END_LABEL && l >= 1) {
     F = o->F[l];
@@ -922,13 +937,35 @@ int orc_regrid(orc *o, const int *boxes, int nboxes) {
           for (int a = 0; a < r; ++a) o->pok[l + 1][cidx(o, l + 1, px * r + a, py * r + b)] = 0;
       }
   }
-  /* 3. adopt the new coverage. A regrid rebuilds every interface, and each
-   *    interface starts its temporal reconstruction afresh: no cell keeps a
-   *    previous-step sample, so the first hand-off after a regrid has no
-   *    temporal slope. */
+  /* 3. interfaces. The hand-off across the face of level-l cell P towards a
+   *    level-(l+1) hole P + c_q reads population q of P at the last two
+   *    level-l steps. Where that face existed before the regrid (P active at
+   *    level l, P + c_q covered at level l+1) it is kept, with the history P
+   *    has (merged and split cells have none). A face the regrid creates has
+   *    no older sample on that face yet: its first hand-off has slope 0, as
+   *    for any interface that appears (Sec. 3.2 step 3). */
+  for (int l = 0; l + 1 < L; ++l)
+    for (int py = 0; py < o->Ny[l]; ++py)
+      for (int px = 0; px < o->Nx[l]; ++px) {
+        size_t ci = cidx(o, l, px, py);
+        if (!o->pok[l][ci]) continue;
+        const int act_new = ncov[l][ci] && !ncov[l + 1][cidx(o, l + 1, px * r, py * r)];
+        const int act_old = ocov[l][ci] && !ocov[l + 1][cidx(o, l + 1, px * r, py * r)];
+        if (!act_new) continue;
+        for (int q = 0; q < 4; ++q) {
+          int hx = px + CX[q], hy = py + CY[q];
+          if (!wrap(o, l, &hx, &hy)) continue;
+          const size_t hc = cidx(o, l + 1, hx * r, hy * r);
+          const int face_new = ncov[l + 1][hc];
+          const int face_old = act_old && ocov[l + 1][hc];
+          if (face_new && !face_old && o->mut != ORC_MUT_REGRID_NEW_FACE_HISTORY)
+            o->pok[l][ci] &= (unsigned char)~(1u << q);
+        }
+      }
+  /* 4. adopt the new coverage */
   for (int l = 0; l < L; ++l) {
+    if (o->mut == ORC_MUT_REGRID_RESTART_ALL) memset(o->pok[l], 0, (size_t)o->Nx[l] * o->Ny[l]);
     memcpy(o->cov[l], ncov[l], (size_t)o->Nx[l] * o->Ny[l]);
-    memset(o->pok[l], 0, (size_t)o->Nx[l] * o->Ny[l]);
     free(ncov[l]);
   }
   return 0;
@@ -958,6 +995,10 @@ int orc_tag(const orc *o, int level, double thr, unsigned char *tags) {
       }
       double gx = fabs(rho[0] - rho[1]) / (2.0 * rc);
       double gy = fabs(rho[2] - rho[3]) / (2.0 * rc);
+      if (o->mut == ORC_MUT_TAG_ONE_SIDED) { /* planted mistake */
+        gx = fabs(rho[0] - rc) / (2.0 * rc);
+        gy = fabs(rho[2] - rc) / (2.0 * rc);
+      }
       double g = gx > gy ? gx : gy;
       tags[cidx(o, l, x, y)] = (unsigned char)(g > thr);
     }

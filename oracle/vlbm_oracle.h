@@ -27,7 +27,17 @@ enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1, ORC_BC_REFLECT = 2, ORC_BC_INFLO
 enum { ORC_EOS_IDEAL = 0, ORC_EOS_STIFFENED = 1, ORC_EOS_VDW = 2 };
 /* Deliberate mistakes, planted only to show that the pins catch them. */
 enum { ORC_MUT_NONE = 0, ORC_MUT_REFLUX_END_LABEL = 1, ORC_MUT_RECON_SIGMA_SIGN = 2,
-       ORC_MUT_REFLUX_LAST_ONLY = 3 };
+       ORC_MUT_REFLUX_LAST_ONLY = 3,
+       ORC_MUT_REGRID_RESTART_ALL = 4,      /* a regrid clears every previous-step sample */
+       ORC_MUT_REGRID_NEW_FACE_HISTORY = 5, /* a new interface keeps its ring cell's history */
+       ORC_MUT_WALL_NO_FLIP = 6,            /* reflecting side without the normal-momentum flip */
+       ORC_MUT_SENSOR_BOX_SUM = 7,          /* box filter as a sum instead of a mean */
+       ORC_MUT_SENSOR_MAX_NORM = 8,         /* max over k of |s_k| instead of the RMS */
+       ORC_MUT_SLOPE_RATIO_INVERTED = 9,    /* hand-off slope scaled by c_now / c_prev */
+       ORC_MUT_TAG_ONE_SIDED = 10 };        /* tag from rho(+1) - rho(0) instead of the central difference */
+/* Planted mistake of the single-operation functions (EOS): 1 flips the sign
+ * of the a rho^2 term inside the van der Waals pressure. Process-wide. */
+void orc_set_function_mutation(int mut);
 
 orc *orc_new(int nx0, int ny0, double dx0, int r, int nlev, double gamma, double c,
              double beta, const int bc[4], const double win[16]);

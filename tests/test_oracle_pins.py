@@ -496,11 +496,12 @@ def test_periodic_translation_equivariance(shift):
         assert np.array_equal(Fa, Fb, equal_nan=True), l
 
 
-def test_regrid_restarts_temporal_reconstruction():
-    """Reading: a regrid rebuilds every interface and each starts its temporal
-    reconstruction afresh. Regridding to the same boxes and going on therefore
-    equals restarting from the current populations, and differs from going on
-    without the regrid (the temporal slope is not zero here)."""
+def test_regrid_to_the_same_boxes_changes_nothing():
+    """Sec. 3.4: reconstruction and reflux run unmodified at whichever
+    interfaces are active. A regrid to the boxes already in place merges and
+    splits nothing and keeps every interface, so going on after it equals going
+    on without it, bit for bit. The temporal slope matters in this case:
+    restarting every interface from the same populations gives another result."""
     n = 16
     U = wl.random_smooth_U(n, n, seed=5)
     case = wl.Case("t", n, n, 1.0 / n, 2, 3, 1.4, 4.0, 0.8, (1, 1, 2, 2),
@@ -510,17 +511,56 @@ def test_regrid_restarts_temporal_reconstruction():
     snap = [np.nan_to_num(a.get_pop(l)) for l in range(3)]
     a.regrid(case.boxes)
     a.advance(3)
+    c = _run(case, 7)
     b = _run(case, 0)
     for l in range(3):
         b.set_pop(l, snap[l])
     b.advance(3)
-    c = _run(case, 7)
-    differs = False
+    restart_differs = False
     for l in range(3):
         Fa, Fb, Fc = a.get_pop(l), b.get_pop(l), c.get_pop(l)
-        assert np.array_equal(Fa, Fb, equal_nan=True), l
-        differs |= not np.array_equal(Fa, Fc, equal_nan=True)
-    assert differs
+        assert np.array_equal(Fa, Fc, equal_nan=True), l
+        restart_differs |= not np.array_equal(Fb, Fc, equal_nan=True)
+    assert restart_differs
+
+
+def test_regrid_keeps_surviving_interfaces_and_starts_new_ones_flat():
+    """A regrid that adds a patch far from an existing one (periodic domain,
+    12 coarse cells apart). Within one coarse step nothing travels further
+    than one coarse cell, so:
+    - around the old patch, whose interfaces survive, the next coarse step is
+      bit for bit the step taken without the regrid (their temporal
+      reconstruction is unmodified, Sec. 3.4);
+    - around the new patch, it is bit for bit the step of a run restarted
+      from the regridded populations, in which every interface is new: a new
+      interface has no older coarse sample and hands off flat (slope 0)."""
+    n = 32
+    U = wl.random_smooth_U(n, n, seed=9)
+    B1, B2 = (1, 4, 4, 12, 12), (1, 40, 40, 12, 12)
+    case = wl.Case("t", n, n, 1.0 / n, 2, 2, 1.4, 4.0, 0.8, (0, 0, 0, 0), [B1],
+                   [U, wl.prolong_piecewise(U, 2)], 0)
+    a = _run(case, 4)
+    a.regrid([B1, B2])
+    post = [np.nan_to_num(a.get_pop(l)) for l in range(2)]
+    a.advance(1)
+    ref_old = _run(case, 5)
+    case2 = wl.Case("t", n, n, 1.0 / n, 2, 2, 1.4, 4.0, 0.8, (0, 0, 0, 0), [B1, B2],
+                    [U, wl.prolong_piecewise(U, 2)], 0)
+    ref_new = _run(case2, 0)
+    for l in range(2):
+        ref_new.set_pop(l, post[l])
+    ref_new.advance(1)
+    F1, F1_old, F1_new = a.get_pop(1), ref_old.get_pop(1), ref_new.get_pop(1)
+    F0, F0_old, F0_new = a.get_pop(0), ref_old.get_pop(0), ref_new.get_pop(0)
+    s1, s2 = np.s_[:, 4:16, 4:16], np.s_[:, 40:52, 40:52]        # the patches (fine cells)
+    c1, c2 = np.s_[:, 0:10, 0:10], np.s_[:, 18:28, 18:28]        # coarse neighbourhoods
+    assert np.array_equal(F1[s1], F1_old[s1])
+    assert np.array_equal(F0[c1], F0_old[c1], equal_nan=True)
+    assert np.array_equal(F1[s2], F1_new[s2])
+    assert np.array_equal(F0[c2], F0_new[c2], equal_nan=True)
+    # the surviving interfaces really use their history: the restarted run
+    # differs around the old patch
+    assert not np.array_equal(F1[s1], F1_new[s1])
 
 
 def test_regrid_rejects_bad_nesting():
