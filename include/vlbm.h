@@ -153,11 +153,13 @@ vlbm_status vlbm_get_populations(vlbm_ctx *ctx, int level, int i0, int j0, int n
  * set_state. T(t) - T(0) equals the ledger to round-off. Synchronises. */
 vlbm_status vlbm_conserved_totals(vlbm_ctx *ctx, double totals[4], double ledger[4]);
 
-/* Replace the hierarchy by boxes, moving the state conservatively: merge
- * exiting cells finest level first (eq. amr-merge), then split entering cells
- * coarsest level first (eqs. amr-slope, amr-split). Every interface of the
- * new hierarchy restarts its temporal reconstruction: the first coarse-to-fine
- * hand-off after a regrid has no temporal slope. Synchronises. */
+/* Replace the hierarchy by boxes, moving the state conservatively (Sec. 3.4):
+ * merge exiting cells finest level first (eq. amr-merge), then split entering
+ * cells coarsest level first (eqs. amr-slope, amr-split). An interface that
+ * exists before and after keeps its temporal reconstruction unmodified; a
+ * face the regrid creates (and every merged or split cell) has no older
+ * sample, so its first coarse-to-fine hand-off has no temporal slope.
+ * Synchronises. */
 vlbm_status vlbm_regrid(vlbm_ctx *ctx, const vlbm_box *boxes, int nboxes);
 
 /* Density-gradient tags of active level-l cells:

@@ -89,9 +89,10 @@ vlbm_status vlbm3_set_hierarchy(vlbm3_ctx *ctx, const vlbm3_box *boxes, int nbox
  * plain average of r^3 children, summed z, y, x), entering cells split
  * coarsest level first (eqs. amr-slope, amr-split, one minmod slope per axis
  * from neighbours covered at that level in the new hierarchy that hold data).
- * Merged and split cells get the same value in both time levels, and every
- * interface restarts its temporal reconstruction. The boundary ledger is
- * kept. Validation as vlbm3_set_hierarchy. Synchronises. */
+ * Merged and split cells get the same value in both time levels. An
+ * interface that exists before and after keeps its temporal reconstruction;
+ * a face the regrid creates starts with no temporal slope. The boundary
+ * ledger is kept. Validation as vlbm3_set_hierarchy. Synchronises. */
 vlbm_status vlbm3_regrid(vlbm3_ctx *ctx, const vlbm3_box *boxes, int nboxes);
 
 /* Refinement tags of the active level-l cells (Sec. 3.4, density-gradient

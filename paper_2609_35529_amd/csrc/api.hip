@@ -1610,10 +1610,14 @@ vlbm_status carry_ledgers(vlbm_ctx *c) {
 // neighbour only if it is covered at that level in the new hierarchy and holds
 // data (i.e. it is not a hole both before and after).
 //
-// With restart_history every level that has a finer level gets its current
-// values copied into its other buffer, so every interface of the new hierarchy
-// restarts its temporal reconstruction (no temporal slope on the first cycle).
-vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes, bool restart_history) {
+// Interfaces: the reconstruction of a face that exists before and after the
+// regrid runs unmodified (Sec. 3.4), with the ring cell's two stored time
+// levels. A face the regrid creates (ring cell P, population q towards the new
+// hole) has no older sample on that face: population q of P gets its current
+// value in the other buffer too, so its first hand-off is flat. A level that
+// ran fused before the regrid (the finest, whose other buffer is not its
+// previous sub-step) had no finer level, so all of its faces are new.
+vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
   PhaseTimer tm("regrid");
   Geometry g;
   vlbm_status st = check_boxes(c->p, boxes, nboxes, g);
@@ -1767,13 +1771,34 @@ vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes, bool res
     a.nops = (int32_t)ops.size();
     HIPCHK(launch_split(a, c->fp32, c->stream));
   }
-  if (restart_history)
-    for (int l = 0; l + 1 < nlev; ++l) {
-      Level &N = t->lv[l];
-      const int cur = (int)(N.steps & 1);
-      HIPCHK(hipMemcpyAsync(N.buf[cur ^ 1], N.buf[cur], level_bytes(N, c->esz), hipMemcpyDeviceToDevice, c->stream));
+  // 4. faces the regrid creates start flat (reflux keys name the faces:
+  //    ring cell P and the population P pulls from the hole, the opposite of
+  //    the one handed off into the hole)
+  std::vector<int32_t *> face_lists;
+  for (int l = 0; l + 1 < nlev; ++l) {
+    Level &N = t->lv[l];
+    const Level &O = c->lv[l];
+    std::vector<int64_t> old_keys(O.reflux_key);
+    std::sort(old_keys.begin(), old_keys.end());
+    std::vector<int32_t> items;
+    for (int64_t key : N.reflux_key) {
+      if (std::binary_search(old_keys.begin(), old_keys.end(), key)) continue;
+      const int q = (int)(key & 3);
+      const int64_t cell = key >> 2;
+      items.push_back((int32_t)N.off((int)(cell % N.Nx), (int)(cell / N.Nx)));
+      items.push_back(q ^ 1);
     }
+    if (items.empty()) continue;
+    int32_t *d = static_cast<int32_t *>(c->mem.alloc(sizeof(int32_t) * items.size()));
+    if (!d) return done(fail(VLBM_ENOMEM, "regrid face list"));
+    face_lists.push_back(d);
+    HIPCHK(hipMemcpyAsync(d, items.data(), sizeof(int32_t) * items.size(), hipMemcpyHostToDevice, c->stream));
+    const int cur = (int)(N.steps & 1);
+    HIPCHK(launch_restart_faces(N.buf[cur], N.buf[cur ^ 1], d, (int)(items.size() / 2), N.plane, c->fp32,
+                                c->stream));
+  }
   if (hipStreamSynchronize(c->stream) != hipSuccess) return done(fail(VLBM_EDEVICE, "regrid kernels failed"));
+  for (int32_t *d : face_lists) c->mem.release(d);
   tm.mark("merge/copy/split");
   c->mem.release(dops);
   // 4. install the new hierarchy
@@ -2295,7 +2320,7 @@ vlbm_status vlbm_get_boxes(vlbm_ctx *c, vlbm_box *boxes, int cap, int *nboxes) {
 
 vlbm_status vlbm_regrid(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
   if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "no hierarchy installed");
-  return regrid_impl(c, boxes, nboxes, true);
+  return regrid_impl(c, boxes, nboxes);
 }
 
 vlbm_status vlbm_tag_and_regrid(vlbm_ctx *c, double thr, int buffer, int min_box, int max_box) {
@@ -2584,7 +2609,7 @@ vlbm_status vlbm_set_tuning(vlbm_ctx *c, int tile_cells, int flags) {
   if (!c->have_hierarchy) return VLBM_OK;
   // same hierarchy and time history, new tile decomposition
   std::vector<vlbm_box> boxes = c->boxes;
-  return regrid_impl(c, boxes.data(), (int)boxes.size(), false);
+  return regrid_impl(c, boxes.data(), (int)boxes.size());
 }
 
 // Tuning cache: one entry per geometry (base grid, ratio, precision, boxes).
@@ -2670,7 +2695,7 @@ vlbm_status vlbm_set_sensor(vlbm_ctx *c, int on, double c_sensor, double beta_mi
     // the step tiles change shape (SEN_TW x SEN_TH with the sensor): same
     // hierarchy and time history, new lists
     std::vector<vlbm_box> boxes = c->boxes;
-    return regrid_impl(c, boxes.data(), (int)boxes.size(), false);
+    return regrid_impl(c, boxes.data(), (int)boxes.size());
   }
   // same buffers and time history; descriptors, planes and fusion follow the setting
   return build_tables(c);

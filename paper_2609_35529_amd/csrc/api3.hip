@@ -75,6 +75,9 @@ struct Level3 {
   int nledger = 0;
   double *dpartial = nullptr;
   long steps = 0;
+  // interfaces towards the finer level, sorted: (linear index of the ring
+  // cell in the level domain) * 6 + the population it hands into the hole
+  std::vector<int64_t> face_key;
 
   bool in_frame(const int p[3]) const {
     for (int a = 0; a < 3; ++a)
@@ -566,6 +569,14 @@ vlbm_status build_lists3(vlbm3_ctx *c) {
         per[ti].push_back(t);
       }
     }
+    L.face_key.clear();
+    L.face_key.reserve(refl.size());
+    for (const RefluxKey3 &k : refl) {
+      int ring[3] = {k.hole[0] + E3[k.q][0], k.hole[1] + E3[k.q][1], k.hole[2] + E3[k.q][2]};
+      c->wrap(l, ring);
+      L.face_key.push_back((((int64_t)ring[2] * L.N[1] + ring[1]) * L.N[0] + ring[0]) * 6 + (k.q ^ 1));
+    }
+    std::sort(L.face_key.begin(), L.face_key.end());
     caps_from_parent.swap(refl);
     L.tasks.clear();
     for (size_t ti = 0; ti < L.tiles.size(); ++ti) {
@@ -1404,20 +1415,41 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
     a.nops = (int32_t)ops.size();
     HIPCHK3(launch_split3(a, c->fp32, c->stream));
   }
-  // 4. every interface restarts its temporal reconstruction: each level with
-  //    a finer level gets its current values in its other buffer too
-  for (int l = 0; l + 1 < nnlev; ++l) {
-    Level3 &N = nl[l];
-    HIPCHK3(hipMemcpyAsync(N.buf[N.cur() ^ 1], N.buf[N.cur()], level_bytes3(N), hipMemcpyDeviceToDevice, c->stream));
-  }
   HIPCHK3(hipStreamSynchronize(c->stream));
   for (void *p : scratch) (void)hipFree(p);
-  // 5. install the new hierarchy and rebuild its lists
+  scratch.clear();
+  // 4. install the new hierarchy and rebuild its lists
+  std::vector<int64_t> old_faces[kL];
+  for (int l = 0; l < onlev; ++l) old_faces[l].swap(c->lv[l].face_key);
   for (int l = 0; l < kL; ++l) free_level3(c->lv[l]);
   for (int l = 0; l < kL; ++l) c->lv[l] = std::move(nl[l]);
   c->nlev = nnlev;
   st = build_lists3(c);
   if (st) return st;
+  // 5. an interface that exists before and after keeps its reconstruction
+  //    unmodified (Sec. 3.4); a face the regrid creates starts flat: the
+  //    population its ring cell hands into the new hole gets the current
+  //    value in the other buffer too
+  for (int l = 0; l + 1 < c->nlev; ++l) {
+    Level3 &N = c->lv[l];
+    std::vector<int32_t> items;
+    for (int64_t key : N.face_key) {
+      if (std::binary_search(old_faces[l].begin(), old_faces[l].end(), key)) continue;
+      const int64_t cell = key / 6;
+      const int p[3] = {(int)(cell % N.N[0]), (int)(cell / N.N[0] % N.N[1]), (int)(cell / ((int64_t)N.N[0] * N.N[1]))};
+      items.push_back((int32_t)N.off(p));
+      items.push_back((int32_t)(key % 6));
+    }
+    if (items.empty()) continue;
+    int32_t *d = nullptr;
+    HIPCHK3(hipMalloc((void **)&d, sizeof(int32_t) * items.size()));
+    scratch.push_back(d);
+    HIPCHK3(hipMemcpyAsync(d, items.data(), sizeof(int32_t) * items.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK3(launch_restart_faces3(N.buf[N.cur()], N.buf[N.cur() ^ 1], d, (int)(items.size() / 2), N.plane,
+                                  c->fp32, c->stream));
+  }
+  HIPCHK3(hipStreamSynchronize(c->stream));
+  for (void *p : scratch) (void)hipFree(p);
   for (int l = 0; l < c->nlev; ++l) {
     Level3 &L = c->lv[l];
     HIPCHK3(hipMalloc((void **)&L.dstatus, L.status.size()));

@@ -1457,4 +1457,33 @@ hipError_t launch_copy_frame(const void *src, void *dst, const int32_t *pairs, i
   return hipGetLastError();
 }
 
+// New interfaces after a regrid: population q of each listed ring cell gets
+// its current value in the level's other buffer too (items[2i] element
+// offset, items[2i+1] q), so the first hand-off across that face is flat.
+template <class T>
+__global__ void restart_faces_kernel(const T *__restrict__ cur, T *__restrict__ other,
+                                     const int32_t *items, int n, int64_t P) {
+  const int64_t total = (int64_t)n * 4;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = t >> 2;
+    const int k = (int)(t & 3);
+    const int64_t e = (int64_t)(items[2 * i + 1] * 4 + k) * P + items[2 * i];
+    other[e] = cur[e];
+  }
+}
+
+hipError_t launch_restart_faces(const void *cur, void *other, const int32_t *items, int n,
+                                int64_t plane, int fp32, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t total = (int64_t)n * 4;
+  if (fp32)
+    hipLaunchKernelGGL(restart_faces_kernel<float>, grid_for(total), dim3(256), 0, s,
+                       static_cast<const float *>(cur), static_cast<float *>(other), items, n, plane);
+  else
+    hipLaunchKernelGGL(restart_faces_kernel<double>, grid_for(total), dim3(256), 0, s,
+                       static_cast<const double *>(cur), static_cast<double *>(other), items, n, plane);
+  return hipGetLastError();
+}
+
 }  // namespace vlbm

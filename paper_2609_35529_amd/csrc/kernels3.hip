@@ -21,6 +21,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "vlbm3_internal.hpp"
 
 namespace vlbm3 {
@@ -521,6 +523,36 @@ hipError_t launch_copy3_runs(const void *s0, const void *s1, void *d0, void *d1,
   else
     hipLaunchKernelGGL(copy3_runs_kernel<double>, dim3(nruns), dim3(256), 0, s, s0, s1, d0, d1, runs, nruns,
                        splane, dplane);
+  return hipGetLastError();
+}
+
+// Interfaces a regrid creates: population q (5 planes) of each listed ring
+// cell gets its current value in the other buffer too (items[2i] element
+// offset, items[2i+1] q), so the first hand-off across that face is flat.
+template <class T>
+__global__ void restart_faces3_kernel(const T *__restrict__ cur, T *__restrict__ other,
+                                      const int32_t *items, int n, int64_t P) {
+  const int64_t total = (int64_t)n * 5;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = t / 5;
+    const int k = (int)(t - i * 5);
+    const int64_t e = (int64_t)(items[2 * i + 1] * 5 + k) * P + items[2 * i];
+    other[e] = cur[e];
+  }
+}
+
+hipError_t launch_restart_faces3(const void *cur, void *other, const int32_t *items, int n, int64_t plane,
+                                 int fp32, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t total = (int64_t)n * 5;
+  const dim3 grid((unsigned)std::min<int64_t>((total + 255) / 256, 65536));
+  if (fp32)
+    hipLaunchKernelGGL(restart_faces3_kernel<float>, grid, dim3(256), 0, s, static_cast<const float *>(cur),
+                       static_cast<float *>(other), items, n, plane);
+  else
+    hipLaunchKernelGGL(restart_faces3_kernel<double>, grid, dim3(256), 0, s, static_cast<const double *>(cur),
+                       static_cast<double *>(other), items, n, plane);
   return hipGetLastError();
 }
 

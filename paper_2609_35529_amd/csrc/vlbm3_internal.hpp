@@ -104,6 +104,11 @@ hipError_t launch_merge3(const RegridArgs3 &a, int fp32, hipStream_t s);
 hipError_t launch_split3(const RegridArgs3 &a, int fp32, hipStream_t s);
 hipError_t launch_copy3_runs(const void *s0, const void *s1, void *d0, void *d1, const int32_t *runs,
                              int nruns, int64_t splane, int64_t dplane, int fp32, hipStream_t s);
+// Interfaces a regrid creates: population q (5 planes) of each listed cell
+// copied from the current buffer into the other one; items[2i] element
+// offset, items[2i+1] q.
+hipError_t launch_restart_faces3(const void *cur, void *other, const int32_t *items, int n, int64_t plane,
+                                 int fp32, hipStream_t s);
 
 // Refinement tags of one level frame (one byte per frame element).
 struct Tag3Args {

@@ -258,5 +258,10 @@ hipError_t launch_merge(const RegridArgs &a, int fp32, hipStream_t s);
 hipError_t launch_split(const RegridArgs &a, int fp32, hipStream_t s);
 hipError_t launch_copy_frame(const void *src, void *dst, const int32_t *pairs, int npairs,
                              int64_t splane, int64_t dplane, int fp32, hipStream_t s);
+// Interfaces a regrid creates: population q (4 planes) of each listed cell
+// copied from the current buffer into the other one; items[2i] element offset,
+// items[2i+1] q.
+hipError_t launch_restart_faces(const void *cur, void *other, const int32_t *items, int n,
+                                int64_t plane, int fp32, hipStream_t s);
 
 }  // namespace vlbm

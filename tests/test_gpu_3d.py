@@ -180,7 +180,7 @@ REGRID_SEQ = ([(1, 6, 4, 4, 12, 12, 12), (2, 16, 12, 12, 8, 8, 8)],
 @pytest.mark.parametrize("bc", [(0,) * 6, (0, 0, 1, 1, 2, 2)])
 def test_regrid_sequence_bit_exact(bc):
     """Moved, added and removed boxes on three levels (merges of r^3
-    children finest first, splits coarsest first, restarted interfaces): the
+    children finest first, splits coarsest first, new interfaces flat): the
     state matches the oracle bit for bit right after every regrid and after
     the steps that follow, and the totals (with the wall ledger) are kept."""
     case = _case(16, 14, 12, 3, [(1, 4, 4, 4, 12, 12, 10)], bc=bc)
