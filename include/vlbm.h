@@ -142,6 +142,23 @@ vlbm_status vlbm_advance(vlbm_ctx *ctx, int n_coarse_steps);
 vlbm_status vlbm_get_state(vlbm_ctx *ctx, int level, int i0, int j0, int nx, int ny, double *U,
                            long ld);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as vlbm_get_state, staged through a static per-GPU device array of
+ * VLBM_NOALLOC_STAGE_BYTES (32 MiB) instead of a staging buffer allocated per
+ * call, and copied straight into U. Calls no hipMalloc, hipFree or other
+ * allocating routine. The part of the rectangle inside the level's frame may
+ * hold at most VLBM_NOALLOC_STAGE_BYTES / 32 cells (1 Mi cells, e.g. 1024 x
+ * 1024); a larger one returns VLBM_EINVAL before any device work (read it in
+ * pieces). The array's device address is looked up once per GPU, on the first
+ * call of a context whose stream is on it. Every call on one GPU shares that
+ * GPU's array, which keeps the last call's contents: calls that overlap
+ * in time on one GPU (two host threads, or two contexts on different streams)
+ * race and must be serialised by the caller. Synchronises. */
+#define VLBM_NOALLOC_STAGE_BYTES (32u << 20)
+vlbm_status vlbm_get_state_noalloc(vlbm_ctx *ctx, int level, int i0, int j0, int nx, int ny, double *U,
+                                   long ld);
+
 /* Read the stored post-collision populations F[16][ny][ld] (FP64 on the host,
  * widened in the FP32 form) of active cells; others NaN. Synchronises. */
 vlbm_status vlbm_get_populations(vlbm_ctx *ctx, int level, int i0, int j0, int nx, int ny,

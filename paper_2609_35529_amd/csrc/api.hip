@@ -22,6 +22,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <functional>
 #include <thread>
@@ -254,6 +255,7 @@ struct LaunchRec {
 struct vlbm_ctx {
   vlbm_params p{};
   hipStream_t stream = nullptr;
+  double *noalloc_stage = nullptr;  // its GPU's static staging array (vlbm_get_state_noalloc)
   bool fp32 = false;
   size_t esz = 8;
   DevMem mem;
@@ -1556,6 +1558,41 @@ vlbm_status rect_io(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny, doub
   return VLBM_OK;
 }
 
+}  // namespace
+
+// Static staging of vlbm_get_state_noalloc: every GPU the library runs on holds
+// its own copy of this array until the process ends. In host code `scratch`
+// only names the symbol; its device address on each GPU comes from
+// hipGetSymbolAddress (scratch_address) and is the only form passed to
+// kernels and copies.
+static __device__ __align__(256) double scratch[VLBM_NOALLOC_STAGE_BYTES / sizeof(double)];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, double *> g_scratch_addr;  // device -> address of its `scratch`
+
+// Address of `scratch` on device dev, looked up once per device with dev current.
+vlbm_status scratch_address(int dev, double **out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it != g_scratch_addr.end()) {
+    *out = it->second;
+    return VLBM_OK;
+  }
+  int cur = 0;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != dev) HIPCHK(hipSetDevice(dev));
+  double *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+  if (cur != dev) HIPCHK(hipSetDevice(cur));
+  if (e != hipSuccess || !ptr)
+    return fail(VLBM_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+  g_scratch_addr[dev] = ptr;
+  *out = ptr;
+  return VLBM_OK;
+}
+
 vlbm_status reset_time(vlbm_ctx *c) {
   if (!c->adt) return VLBM_OK;
   const double zero = 0.0;
@@ -2239,6 +2276,58 @@ vlbm_status vlbm_get_state(vlbm_ctx *c, int level, int i0, int j0, int nx, int n
                            long ld) {
   if (!U) return fail(VLBM_EINVAL, "null U");
   return rect_io(c, level, i0, j0, nx, ny, U, ld, 4, false, false);
+}
+
+vlbm_status vlbm_get_state_noalloc(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny, double *U,
+                                   long ld) {
+  if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "no hierarchy installed");
+  if (!U) return fail(VLBM_EINVAL, "null U");
+  vlbm_status st = check_rect(c, level, i0, j0, nx, ny);
+  if (st) return st;
+  if (ld < nx) return fail(VLBM_EINVAL, "ld < nx");
+  if (!c->noalloc_stage) {  // first call of this context: its GPU's array (looked up once per GPU)
+    hipDevice_t dev = 0;
+    HIPCHK(hipStreamGetDevice(c->stream, &dev));
+    st = scratch_address((int)dev, &c->noalloc_stage);
+    if (st) return st;
+  }
+  Level &L = c->lv[level];
+  int ci0 = i0, cj0 = j0, cnx = nx, cny = ny, ox = 0, oy = 0;
+  const bool any = L.present && clip_to_frame(L, ci0, cj0, cnx, cny, ox, oy);
+  const size_t n = any ? (size_t)cnx * cny : 0;
+  if (n * 4 * sizeof(double) > VLBM_NOALLOC_STAGE_BYTES)
+    return fail(VLBM_EINVAL, "rectangle part inside the frame has %zu cells; the static staging holds %zu",
+                n, (size_t)VLBM_NOALLOC_STAGE_BYTES / (4 * sizeof(double)));
+  const size_t full_plane = (size_t)ny * ld;
+  for (int k = 0; k < 4; ++k)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) U[k * full_plane + (size_t)y * ld + x] = NAN;
+  if (!any) return VLBM_OK;
+  RectArgs a{};
+  a.buf0 = L.buf[L.cur()];
+  a.buf1 = L.buf[1];
+  a.status = L.dstatus;
+  a.host_stage = c->noalloc_stage;
+  a.plane = L.plane;
+  a.pitch = L.pitch;
+  a.xoff = L.xoff;
+  a.fx0 = L.fx0;
+  a.fy0 = L.fy0;
+  a.fw = L.fw;
+  a.x0 = ci0;
+  a.y0 = cj0;
+  a.nx = cnx;
+  a.ny = cny;
+  a.gm1 = c->gm1;
+  a.h = c->h;
+  a.eos = c->eos;
+  HIPCHK(launch_get(a, c->fp32, 0, c->stream));
+  for (int k = 0; k < 4; ++k)
+    HIPCHK(hipMemcpy2DAsync(U + k * full_plane + (size_t)oy * ld + ox, sizeof(double) * ld,
+                            c->noalloc_stage + k * n, sizeof(double) * cnx, sizeof(double) * cnx, cny,
+                            hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return VLBM_OK;
 }
 
 vlbm_status vlbm_get_populations(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny,

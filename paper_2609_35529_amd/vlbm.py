@@ -76,6 +76,7 @@ _rect = [_P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _D, C.c_long]
 vlbm_set_state = _sig("vlbm_set_state", _st, _rect)
 vlbm_set_populations = _sig("vlbm_set_populations", _st, _rect)
 vlbm_get_state = _sig("vlbm_get_state", _st, _rect)
+vlbm_get_state_noalloc = _sig("vlbm_get_state_noalloc", _st, _rect)
 vlbm_get_populations = _sig("vlbm_get_populations", _st, _rect)
 vlbm_advance = _sig("vlbm_advance", _st, [_P, C.c_int])
 vlbm_conserved_totals = _sig("vlbm_conserved_totals", _st, [_P, _D, _D])
@@ -110,7 +111,7 @@ EXPORTED = ["vlbm_create", "vlbm_destroy", "vlbm_bind_pool", "vlbm_footprint_byt
             "vlbm_save", "vlbm_load", "vlbm_batch_advance", "vlbm_set_tuning", "vlbm_autotune",
             "vlbm_steps", "vlbm_active_cells", "vlbm_sync", "vlbm_last_error",
             "vlbm_set_profiling", "vlbm_kernel_times", "vlbm_set_sensor", "vlbm_get_beta",
-            "vlbm_set_time_stepping", "vlbm_time"]
+            "vlbm_set_time_stepping", "vlbm_time", "vlbm_get_state_noalloc"]
 
 
 class VLBMError(RuntimeError):
@@ -247,6 +248,14 @@ class Solver:
         nx, ny = self._rect(level, i0, j0, nx, ny)
         U = np.empty((4, ny, nx))
         check(vlbm_get_state(self._h, level, i0, j0, nx, ny, _dp(U), nx))
+        return U
+
+    def get_state_noalloc(self, level, i0=0, j0=0, nx=None, ny=None, out=None):
+        """As get_state, through the allocation-free entry point (static
+        per-GPU staging; at most 1 Mi cells of the rectangle inside the frame)."""
+        nx, ny = self._rect(level, i0, j0, nx, ny)
+        U = np.empty((4, ny, nx)) if out is None else out
+        check(vlbm_get_state_noalloc(self._h, level, i0, j0, nx, ny, _dp(U), U.shape[2]))
         return U
 
     def get_populations(self, level, i0=0, j0=0, nx=None, ny=None):
