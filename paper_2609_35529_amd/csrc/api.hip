@@ -192,11 +192,25 @@ struct DevMem {
   }
 };
 
+// Sorted, disjoint runs of level rows [y0, y1).
+using Runs = std::vector<std::pair<int, int>>;
+
 struct Level {
   bool present = false;
   int Nx = 0, Ny = 0;
   double dx = 0.0;
-  int fx0 = 0, fy0 = 0, fw = 0, fh = 0;  // frame = coverage bounding box + 1 ghost cell
+  // Frame: the columns of the coverage's bounding box plus one ghost column on
+  // each side, over row runs that hold every covered row and its neighbour rows
+  // (the ghost ring). Rows between runs are not stored: a level made of
+  // separate bands (two shear layers, say) stores only the bands. Stored rows
+  // follow each other in storage in increasing y, so the rows above and below
+  // an active cell are one pitch away.
+  int fx0 = 0, fy0 = 0, fw = 0, fh = 0;  // column and row range of the frame
+  Runs runs;                              // stored rows
+  std::vector<int32_t> srow;              // frame row (y - fy0) -> storage row, -1 if not stored
+  std::vector<int32_t> yrow;              // storage row -> frame row (y - fy0)
+  int nrows = 0;                          // stored rows
+  int32_t *dsrow = nullptr, *dyrow = nullptr;  // device copies of srow and yrow
   int pitch = 0, xoff = 0;
   int64_t plane = 0;
   void *buf[2] = {nullptr, nullptr};
@@ -226,13 +240,14 @@ struct Level {
   int64_t sen_plane = 0;
   std::vector<int64_t> reflux_key;  // per reflux slot: (y * Nx + x) * 4 + q of its ring cell
 
+  // (x, y) must lie in the frame (in_frame)
   int64_t off(int x, int y) const {
-    return (int64_t)(y - fy0) * pitch + (x - fx0) + xoff;
+    return (int64_t)srow[y - fy0] * pitch + (x - fx0) + xoff;
   }
-  bool in_frame(int x, int y) const {
-    return x >= fx0 && y >= fy0 && x < fx0 + fw && y < fy0 + fh;
-  }
-  size_t fidx(int x, int y) const { return (size_t)(y - fy0) * fw + (x - fx0); }
+  bool stored(int y) const { return y >= fy0 && y < fy0 + fh && srow[y - fy0] >= 0; }
+  bool in_frame(int x, int y) const { return x >= fx0 && x < fx0 + fw && stored(y); }
+  // index of frame cell (x, y) in the host arrays (cov, status: fw per stored row)
+  size_t fidx(int x, int y) const { return (size_t)srow[y - fy0] * fw + (x - fx0); }
   int cur() const { return (int)(steps & 1); }
 };
 
@@ -350,6 +365,8 @@ void free_level(vlbm_ctx *c, Level &L) {
   c->mem.release(L.dpartial);
   c->mem.release(L.dsen);
   c->mem.release(L.dmask);
+  c->mem.release(L.dsrow);
+  c->mem.release(L.dyrow);
   long steps = L.steps;
   L = Level();
   L.steps = steps;
@@ -361,7 +378,36 @@ void free_level(vlbm_ctx *c, Level &L) {
 struct Geometry {
   bool present[kMaxLevels] = {};
   int bx0[kMaxLevels], by0[kMaxLevels], bx1[kMaxLevels], by1[kMaxLevels];
+  Runs rows[kMaxLevels];  // rows each level's frame stores
 };
+
+// Runs closer than kRowGap rows are stored as one (fewer runs, little memory).
+constexpr int kRowGap = 16;
+// Rows a growing level adds beyond those it needs (a regrid that moves a band
+// by a few rows then reuses the frame).
+constexpr int kRowPad = 16;
+
+Runs merge_runs(Runs v) {
+  std::sort(v.begin(), v.end());
+  Runs out;
+  for (const auto &r : v) {
+    if (!out.empty() && r.first <= out.back().second + kRowGap)
+      out.back().second = std::max(out.back().second, r.second);
+    else
+      out.push_back(r);
+  }
+  return out;
+}
+
+// every run of `inner` lies inside a run of `outer`
+bool runs_cover(const Runs &outer, const Runs &inner) {
+  size_t j = 0;
+  for (const auto &r : inner) {
+    while (j < outer.size() && outer[j].second < r.second) ++j;
+    if (j == outer.size() || outer[j].first > r.first) return false;
+  }
+  return true;
+}
 
 vlbm_status check_boxes(const vlbm_params &p, const vlbm_box *boxes, int n, Geometry &g) {
   for (int l = 0; l < kMaxLevels; ++l) {
@@ -374,6 +420,8 @@ vlbm_status check_boxes(const vlbm_params &p, const vlbm_box *boxes, int n, Geom
   g.by0[0] = 0;
   g.bx1[0] = p.nx0;
   g.by1[0] = p.ny0;
+  for (int l = 0; l < kMaxLevels; ++l) g.rows[l].clear();
+  g.rows[0].push_back({-1, p.ny0 + 1});
   if (n < 0 || (n > 0 && !boxes)) return fail(VLBM_EINVAL, "bad box list");
   for (int b = 0; b < n; ++b) {
     const vlbm_box &B = boxes[b];
@@ -393,11 +441,32 @@ vlbm_status check_boxes(const vlbm_params &p, const vlbm_box *boxes, int n, Geom
     g.by0[l] = std::min(g.by0[l], B.j0);
     g.bx1[l] = std::max(g.bx1[l], B.i0 + B.nx);
     g.by1[l] = std::max(g.by1[l], B.j0 + B.ny);
+    g.rows[l].push_back({B.j0 - 1, B.j0 + B.ny + 1});
   }
   for (int l = 1; l < kMaxLevels; ++l)
     if (g.present[l] && !g.present[l - 1])
       return fail(VLBM_ENEST, "level %d has boxes but level %d has none", l, l - 1);
+  for (int l = 0; l < kMaxLevels; ++l) g.rows[l] = merge_runs(std::move(g.rows[l]));
   return VLBM_OK;
+}
+
+// A level that persists through a regrid keeps its frame when the new
+// coverage fits in it; otherwise its frame grows to hold old and new rows
+// (new rows padded by kRowPad), so a slowly moving band reallocates rarely.
+void grow_geometry(Geometry &g, int l, const Level &O, int Ny) {
+  if (!g.present[l] || !O.present) return;
+  g.bx0[l] = std::min(g.bx0[l], O.fx0 + 1);
+  g.bx1[l] = std::max(g.bx1[l], O.fx0 + O.fw - 1);
+  g.by0[l] = std::min(g.by0[l], O.fy0 + 1);
+  g.by1[l] = std::max(g.by1[l], O.fy0 + O.fh - 1);
+  if (runs_cover(O.runs, g.rows[l])) {
+    g.rows[l] = O.runs;
+    return;
+  }
+  Runs v = O.runs;
+  for (const auto &r : g.rows[l])
+    v.push_back({std::max(-1, r.first - kRowPad), std::min(Ny + 1, r.second + kRowPad)});
+  g.rows[l] = merge_runs(std::move(v));
 }
 
 void frame_of(const vlbm_params &p, size_t esz, const Geometry &g, int l, Level &L) {
@@ -407,15 +476,27 @@ void frame_of(const vlbm_params &p, size_t esz, const Geometry &g, int l, Level 
   L.Ny = (int)(p.ny0 * s);
   L.dx = p.dx0 / (double)s;
   L.present = g.present[l];
+  L.runs.clear();
+  L.srow.clear();
+  L.yrow.clear();
+  L.nrows = 0;
   if (!L.present) {
     L.fx0 = L.fy0 = L.fw = L.fh = L.pitch = L.xoff = 0;
     L.plane = 0;
     return;
   }
   L.fx0 = g.bx0[l] - 1;
-  L.fy0 = g.by0[l] - 1;
   L.fw = g.bx1[l] - g.bx0[l] + 2;
-  L.fh = g.by1[l] - g.by0[l] + 2;
+  L.runs = g.rows[l];
+  L.fy0 = L.runs.front().first;
+  L.fh = L.runs.back().second - L.fy0;
+  L.srow.assign(L.fh, -1);
+  for (const auto &r : L.runs)
+    for (int y = r.first; y < r.second; ++y) {
+      L.srow[y - L.fy0] = (int32_t)L.yrow.size();
+      L.yrow.push_back(y - L.fy0);
+    }
+  L.nrows = (int)L.yrow.size();
   // The first interior column starts on a 128-byte line; rows are padded to 64
   // elements and every population plane to a multiple of 4 KiB. Measured on
   // MI355X for a 4096^2 FP64 frame: a plane stride of 512 B mod 4 KiB runs the
@@ -424,10 +505,12 @@ void frame_of(const vlbm_params &p, size_t esz, const Geometry &g, int l, Level 
   L.xoff = align - 1;
   L.pitch = (L.fw + L.xoff + 63) / 64 * 64;
   const int64_t pa = 4096 / (int64_t)esz;
-  L.plane = ((int64_t)L.pitch * L.fh + pa - 1) / pa * pa;
+  L.plane = ((int64_t)L.pitch * L.nrows + pa - 1) / pa * pa;
 }
 
 size_t level_bytes(const Level &L, size_t esz) { return (size_t)L.plane * 16 * esz; }
+
+int align_up(int v, int a) { return (v + a - 1) / a * a; }  // v >= 0
 
 // Build coverage, check nesting, build status, tiles and tasks for all levels.
 // What fills the slot from which active cell (x, y) of level l pulls f_q
@@ -506,6 +589,7 @@ vlbm_status build_fused(vlbm_ctx *c, int l, const std::unordered_map<int64_t, in
   std::map<std::pair<int, int>, int> open;  // (x0, w) -> index in rects (current band)
   for (int y = L.fy0 + 1; y < L.fy0 + L.fh - 1; ++y) {
     if ((y - L.fy0 - 1) % FUSE_H == 0) open.clear();
+    if (!L.stored(y)) continue;  // no active cell (rectangles need consecutive rows)
     std::map<std::pair<int, int>, int> next;
     int x = L.fx0 + 1;
     const int xe = L.fx0 + L.fw - 1;
@@ -700,7 +784,7 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
     if (boxes[b].level >= 0 && boxes[b].level < nlev) of_level[boxes[b].level].push_back(b);
   vlbm_status cst = run_parallel(nlev, [&](int l) -> vlbm_status {
     Level &L = c->lv[l];
-    L.cov.assign((size_t)L.fw * L.fh, 0);
+    L.cov.assign((size_t)L.fw * L.nrows, 0);
     if (l == 0)
       for (int y = 0; y < L.Ny; ++y) memset(&L.cov[L.fidx(0, y)], 1, L.Nx);
     for (int b : of_level[l])
@@ -801,6 +885,11 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
     };
     for (int y = L.fy0; y < L.fy0 + L.fh; ++y) {
       nopen.clear();
+      if (!L.stored(y)) {  // no active cell: close every open rectangle
+        for (const Open &o : open) emit(o);
+        open.clear();
+        continue;
+      }
       const uint8_t *row = &L.status[L.fidx(L.fx0, y)];
       size_t j = 0;  // open rectangles are ordered by xa, like the runs of a row
       int x = 0;
@@ -878,6 +967,7 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
     std::vector<std::vector<int32_t>> edge(B);  // frame indices, row order
     st = run_parallel(B, [&](int b) -> vlbm_status {
       for (int y = ya + (int)((int64_t)(yb - ya) * b / B); y < ya + (int)((int64_t)(yb - ya) * (b + 1) / B); ++y) {
+        if (!L.stored(y)) continue;
         const size_t r0 = L.fidx(L.fx0, y);
         const uint8_t *sr = &L.status[r0];
         for (int xi = 1; xi < fw - 1; ++xi) {
@@ -904,7 +994,7 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
       Band &bd = bands[b];
       const size_t i0 = cells.size() * b / E, i1 = cells.size() * (b + 1) / E;
       for (size_t i = i0; i < i1; ++i) {
-        const int x = L.fx0 + cells[i] % fw, y = L.fy0 + cells[i] / fw;
+        const int x = L.fx0 + cells[i] % fw, y = L.fy0 + L.yrow[cells[i] / fw];
         const int tile = w.owner[cells[i]];
         for (int q = 0; q < 4; ++q) {
           Task t{};
@@ -1023,6 +1113,13 @@ vlbm_status upload_level(vlbm_ctx *c, Level &L, bool alloc_buffers) {
     HIPCHK(hipMemsetAsync(L.buf[1], 0, nb, c->stream));
   }
   L.dstatus = static_cast<uint8_t *>(M.alloc(L.status.size()));
+  L.dsrow = static_cast<int32_t *>(M.alloc(sizeof(int32_t) * std::max<size_t>(1, L.srow.size())));
+  L.dyrow = static_cast<int32_t *>(M.alloc(sizeof(int32_t) * std::max<size_t>(1, L.yrow.size())));
+  if (!L.dsrow || !L.dyrow) return fail(VLBM_ENOMEM, "level row tables");
+  if (!L.srow.empty())
+    HIPCHK(hipMemcpyAsync(L.dsrow, L.srow.data(), sizeof(int32_t) * L.srow.size(), hipMemcpyHostToDevice, c->stream));
+  if (!L.yrow.empty())
+    HIPCHK(hipMemcpyAsync(L.dyrow, L.yrow.data(), sizeof(int32_t) * L.yrow.size(), hipMemcpyHostToDevice, c->stream));
   L.dtiles = static_cast<Tile *>(M.alloc(sizeof(Tile) * std::max<size_t>(1, L.tiles.size())));
   L.dtasks = static_cast<Task *>(M.alloc(sizeof(Task) * std::max<size_t>(1, L.tasks.size())));
   L.dacc = static_cast<double *>(M.alloc(sizeof(double) * 4 * std::max(1, L.nacc)));
@@ -1098,8 +1195,9 @@ vlbm_status ensure_sensor(vlbm_ctx *c) {
       HIPCHK(hipMemsetAsync(L.dsen, 0, nb, c->stream));
     }
     HIPCHK(hipMemsetAsync(L.dmask, 0, (size_t)L.plane, c->stream));
-    HIPCHK(launch_sensor_mask(L.dstatus, L.dmask, L.fx0, L.fy0, L.fw, L.fh, L.pitch, L.xoff, L.Nx, L.Ny,
-                              (c->perx() ? 1 : 0) | (c->pery() ? 2 : 0), c->stream));
+    HIPCHK(launch_sensor_mask(L.dstatus, L.dmask, L.dsrow, L.dyrow, L.fx0, L.fy0, L.fw, L.fh, L.nrows,
+                              L.pitch, L.xoff, L.Nx, L.Ny, (c->perx() ? 1 : 0) | (c->pery() ? 2 : 0),
+                              c->stream));
   }
   if (!c->sensor) {
     c->mem.release(c->dqmax);
@@ -1150,6 +1248,8 @@ LevelDesc make_desc(const vlbm_ctx *c, int l, const long *st, bool fused = false
     a.fx0 = L.fx0;
     a.fy0 = L.fy0;
     a.xoff = L.xoff;
+    a.srow = L.dsrow;
+    a.yrow = L.dyrow;
     a.Nx = L.Nx;
     a.Ny = L.Ny;
     a.c_sensor = c->c_sensor;
@@ -1524,6 +1624,7 @@ vlbm_status rect_io(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny, doub
   a.fx0 = L.fx0;
   a.fy0 = L.fy0;
   a.fw = L.fw;
+  a.srow = L.dsrow;
   a.x0 = ci0;
   a.y0 = cj0;
   a.nx = cnx;
@@ -1621,7 +1722,7 @@ void kadd(double &s, double &cmp, double v) {
 
 bool same_frame(const Level &a, const Level &b) {
   return a.present && b.present && a.fx0 == b.fx0 && a.fy0 == b.fy0 && a.fw == b.fw &&
-         a.fh == b.fh && a.pitch == b.pitch && a.plane == b.plane && a.xoff == b.xoff;
+         a.fh == b.fh && a.pitch == b.pitch && a.plane == b.plane && a.xoff == b.xoff && a.runs == b.runs;
 }
 
 // Move the sum of every ledger slot into the host-side carry (before the slots
@@ -1662,14 +1763,7 @@ vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
   // Frames only grow while a level persists: when the new coverage fits in the
   // current frame the frame (and its buffers) is kept, so a moving refinement
   // zone does not reallocate every regrid.
-  for (int l = 1; l < kMaxLevels; ++l) {
-    const Level &O = c->lv[l];
-    if (!g.present[l] || !O.present) continue;
-    g.bx0[l] = std::min(g.bx0[l], O.fx0 + 1);
-    g.by0[l] = std::min(g.by0[l], O.fy0 + 1);
-    g.bx1[l] = std::max(g.bx1[l], O.fx0 + O.fw - 1);
-    g.by1[l] = std::max(g.by1[l], O.fy0 + O.fh - 1);
-  }
+  for (int l = 1; l < kMaxLevels; ++l) grow_geometry(g, l, c->lv[l], c->lv[l].Ny);
   vlbm_ctx *t = new vlbm_ctx();
   t->p = c->p;
   t->esz = c->esz;
@@ -1712,8 +1806,9 @@ vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
   for (int l = c->nlev - 1; l >= 1; --l) {
     Level &F = c->lv[l], &C = c->lv[l - 1];
     std::vector<RegridOp> ops;
-    for (int y = F.fy0 + 1; y < F.fy0 + F.fh - 1; y += r)
-      for (int x = F.fx0 + 1; x < F.fx0 + F.fw - 1; x += r) {
+    for (int y = align_up(F.fy0 + 1, r); y < F.fy0 + F.fh - 1; y += r) {
+      if (!F.stored(y)) continue;
+      for (int x = align_up(F.fx0 + 1, r); x < F.fx0 + F.fw - 1; x += r) {
         if (!F.cov[F.fidx(x, y)] || t->covered(l, x, y)) continue;
         RegridOp op{};
         op.dst = (int32_t)C.off(x / r, y / r);
@@ -1721,6 +1816,7 @@ vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
         op.nb[0] = op.nb[1] = op.nb[2] = op.nb[3] = -1;
         ops.push_back(op);
       }
+    }
     if (ops.empty()) continue;
     st = upload_ops(ops);
     if (st) return done(st);
@@ -1761,20 +1857,31 @@ vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
     int x0 = std::max(O.fx0, N.fx0), y0 = std::max(O.fy0, N.fy0);
     int x1 = std::min(O.fx0 + O.fw, N.fx0 + N.fw), y1 = std::min(O.fy0 + O.fh, N.fy0 + N.fh);
     if (x1 <= x0 || y1 <= y0) continue;
-    for (int b = 0; b < 2; ++b)
-      for (int i = 0; i < 16; ++i) {
-        char *dst = static_cast<char *>(N.buf[b]) + (i * N.plane + N.off(x0, y0)) * c->esz;
-        const char *src = static_cast<const char *>(O.buf[b]) + (i * O.plane + O.off(x0, y0)) * c->esz;
-        HIPCHK(hipMemcpy2DAsync(dst, N.pitch * c->esz, src, O.pitch * c->esz, (x1 - x0) * c->esz,
-                                y1 - y0, hipMemcpyDeviceToDevice, c->stream));
+    // rows stored by both frames, in runs that are contiguous in both
+    for (int ya = y0; ya < y1;) {
+      if (!O.stored(ya) || !N.stored(ya)) {
+        ++ya;
+        continue;
       }
+      int yb = ya + 1;
+      while (yb < y1 && O.stored(yb) && N.stored(yb)) ++yb;
+      for (int b = 0; b < 2; ++b)
+        for (int i = 0; i < 16; ++i) {
+          char *dst = static_cast<char *>(N.buf[b]) + (i * N.plane + N.off(x0, ya)) * c->esz;
+          const char *src = static_cast<const char *>(O.buf[b]) + (i * O.plane + O.off(x0, ya)) * c->esz;
+          HIPCHK(hipMemcpy2DAsync(dst, N.pitch * c->esz, src, O.pitch * c->esz, (x1 - x0) * c->esz,
+                                  yb - ya, hipMemcpyDeviceToDevice, c->stream));
+        }
+      ya = yb;
+    }
   }
   // 3. splits, coarsest level first, inside the new frames
   for (int l = 0; l + 1 < nlev; ++l) {
     Level &Cn = t->lv[l], &Fn = t->lv[l + 1];
     std::vector<RegridOp> ops;
-    for (int y = Fn.fy0 + 1; y < Fn.fy0 + Fn.fh - 1; y += r)
-      for (int x = Fn.fx0 + 1; x < Fn.fx0 + Fn.fw - 1; x += r) {
+    for (int y = align_up(Fn.fy0 + 1, r); y < Fn.fy0 + Fn.fh - 1; y += r) {
+      if (!Fn.stored(y)) continue;
+      for (int x = align_up(Fn.fx0 + 1, r); x < Fn.fx0 + Fn.fw - 1; x += r) {
         if (!Fn.cov[Fn.fidx(x, y)] || c->covered(l + 1, x, y)) continue;
         const int px = x / r, py = y / r;
         RegridOp op{};
@@ -1789,6 +1896,7 @@ vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
         }
         ops.push_back(op);
       }
+    }
     if (ops.empty()) continue;
     st = upload_ops(ops);
     if (st) return done(st);
@@ -1858,9 +1966,12 @@ vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
 int level_nx(const vlbm_ctx *c, int l);
 int level_ny(const vlbm_ctx *c, int l);
 
-// Tags of one level over a rectangle of its cells (a frame); outside it, none.
+// Tags of one level over its frame (outside it, none): w bytes per stored
+// frame row, srow mapping frame rows (y - y0) to stored rows (-1: not stored,
+// no tag there) and yrow back.
 struct TagMap {
   int x0 = 0, y0 = 0, w = 0, h = 0;
+  std::vector<int32_t> srow, yrow;
   std::vector<uint8_t> t;
 };
 // Coverage of one level over a rectangle of its cells (outside it: not
@@ -1918,9 +2029,9 @@ void cluster_level(vlbm_ctx *c, int l, const TagMap &tags, const CovMap &cov, in
   };
   // per row of the tag map, each run of tagged cells reaches one interval of
   // tile columns on the tile rows within `buffer` of the row
-  for (int fy = 0; fy < tags.h; ++fy) {
-    const uint8_t *row = &tags.t[(size_t)fy * tags.w];
-    const int y = tags.y0 + fy;
+  for (size_t sr = 0; sr < tags.yrow.size(); ++sr) {
+    const uint8_t *row = &tags.t[sr * tags.w];
+    const int y = tags.y0 + tags.yrow[sr];
     bool any = false;
     int fx = 0;
     while (fx < tags.w) {
@@ -2021,15 +2132,17 @@ int level_ny(const vlbm_ctx *c, int l) {
   return (int)(c->p.ny0 * s);
 }
 
-// Density-gradient tags of level l's active cells, frame-indexed (fw x fh).
+// Density-gradient tags of level l's active cells, indexed like its status
+// (fw bytes per stored row).
 vlbm_status tag_frame(vlbm_ctx *c, int l, double thr, std::vector<uint8_t> &ft) {
   const Level &L = c->lv[l];
-  const size_t n = (size_t)L.fw * L.fh;
+  const size_t n = (size_t)L.fw * L.nrows;
   ft.assign(n, 0);
   uint8_t *d = static_cast<uint8_t *>(c->mem.alloc(n));
   if (!d) return fail(VLBM_ENOMEM, "tag buffer");
-  hipError_t e = launch_tag(L.buf[L.cur()], L.dstatus, L.plane, L.pitch, L.xoff, L.fx0, L.fy0, L.fw,
-                            L.fh, L.Nx, L.Ny, c->perx(), c->pery(), c->fp32, thr, d, c->stream);
+  hipError_t e = launch_tag(L.buf[L.cur()], L.dstatus, L.dsrow, L.dyrow, L.plane, L.pitch, L.xoff, L.fx0,
+                            L.fy0, L.fw, L.fh, L.nrows, L.Nx, L.Ny, c->perx(), c->pery(), c->fp32, thr, d,
+                            c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(ft.data(), d, n, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   c->mem.release(d);
@@ -2049,10 +2162,13 @@ void cluster_hierarchy(vlbm_ctx *c, std::vector<TagMap> &tags, int buffer, int m
     TagMap &P = tags[l - 1];
     if (F.t.empty() || P.t.empty()) continue;
     // per row, each run of tagged fine cells tags the run of its parents
-    for (int fy = 0; fy < F.h; ++fy) {
-      const uint8_t *row = &F.t[(size_t)fy * F.w];
-      const int py = (F.y0 + fy) / r - P.y0;
-      if (py < 0 || py >= P.h) continue;
+    for (size_t sr = 0; sr < F.yrow.size(); ++sr) {
+      const uint8_t *row = &F.t[sr * F.w];
+      const int fyl = F.y0 + F.yrow[sr];
+      if (fyl < 0) continue;  // a ghost row below the domain holds no tag
+      const int py = fyl / r - P.y0;
+      if (py < 0 || py >= P.h || P.srow[py] < 0) continue;
+      const size_t prow = (size_t)P.srow[py] * P.w;
       int fx = 0;
       while (fx < F.w) {
         if (fx + 8 <= F.w) {  // skip untagged words
@@ -2071,7 +2187,7 @@ void cluster_hierarchy(vlbm_ctx *c, std::vector<TagMap> &tags, int buffer, int m
         while (fx < F.w && row[fx]) ++fx;
         const int pa = std::max((F.x0 + xa) / r - P.x0, 0);
         const int pb = std::min((F.x0 + fx - 1) / r - P.x0, P.w - 1);
-        if (pa <= pb) memset(&P.t[(size_t)py * P.w + pa], 1, pb - pa + 1);
+        if (pa <= pb) memset(&P.t[prow + pa], 1, pb - pa + 1);
       }
     }
   }
@@ -2188,22 +2304,44 @@ size_t vlbm_footprint_bytes(const vlbm_params *params, const vlbm_box *boxes, in
   for (int l = 0; l < kMaxLevels && g.present[l]; ++l) {
     Level L;
     frame_of(*params, esz, g, l, L);
-    size_t cells = (size_t)L.fw * L.fh;
+    size_t cells = (size_t)L.fw * L.nrows;
     total += DevMem::round(level_bytes(L, esz)) * 2;  // two time levels
     total += DevMem::round(cells);                    // status
     // tiles, tasks, accumulators, ledger, partials: bounded by the perimeter
-    size_t perim = 2 * (size_t)(L.fw + L.fh) * 4 + 64;
+    size_t perim = 2 * ((size_t)L.fw * L.runs.size() + L.nrows) * 4 + 64;
     total += DevMem::round(sizeof(Task) * perim * 2) + DevMem::round(sizeof(double) * 4 * perim * 2);
     total += DevMem::round((cells / 64 + 64) * (sizeof(Tile) + 4 * sizeof(double)));
   }
   return total + (1 << 20);
 }
 
-vlbm_status vlbm_set_hierarchy(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
+}  // extern "C"
+
+namespace {
+// A level's frame as a checkpoint records it: columns [bx0, bx1) of the
+// coverage's bounding box and the stored row runs.
+struct FrameSpec {
+  int bx0 = 0, bx1 = 0;
+  Runs rows;
+};
+
+// Install a hierarchy; with specs (one per level, a checkpoint's frames) every
+// level takes exactly that frame, which must hold its boxes.
+vlbm_status set_hierarchy_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes, const FrameSpec *specs) {
   if (!c) return fail(VLBM_EINVAL, "null context");
   Geometry g;
   vlbm_status st = check_boxes(c->p, boxes, nboxes, g);
   if (st) return st;
+  if (specs)
+    for (int l = 0; l < kMaxLevels; ++l) {
+      if (!g.present[l]) continue;
+      const FrameSpec &f = specs[l];
+      if (f.rows.empty() || f.bx0 > g.bx0[l] || f.bx1 < g.bx1[l] || !runs_cover(f.rows, g.rows[l]))
+        return fail(VLBM_EINVAL, "checkpoint frame of level %d does not hold its boxes", l);
+      g.bx0[l] = f.bx0;
+      g.bx1[l] = f.bx1;
+      g.rows[l] = f.rows;
+    }
   // Build every host table on a scratch context first: a rejected hierarchy
   // leaves the installed one untouched and touches no device state.
   vlbm_ctx *t = new vlbm_ctx();
@@ -2248,6 +2386,13 @@ vlbm_status vlbm_set_hierarchy(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
   c->have_hierarchy = true;
   c->coarse_steps = 0;
   return build_tables(c);
+}
+}  // namespace
+
+extern "C" {
+
+vlbm_status vlbm_set_hierarchy(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
+  return set_hierarchy_impl(c, boxes, nboxes, nullptr);
 }
 
 vlbm_status vlbm_set_state(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny,
@@ -2314,6 +2459,7 @@ vlbm_status vlbm_get_state_noalloc(vlbm_ctx *c, int level, int i0, int j0, int n
   a.fx0 = L.fx0;
   a.fy0 = L.fy0;
   a.fw = L.fw;
+  a.srow = L.dsrow;
   a.x0 = ci0;
   a.y0 = cj0;
   a.nx = cnx;
@@ -2395,8 +2541,10 @@ vlbm_status vlbm_tag(vlbm_ctx *c, int level, double thr, unsigned char *tags) {
   std::vector<uint8_t> ft;
   vlbm_status st = tag_frame(c, level, thr, ft);
   if (st) return st;
-  for (int fy = 1; fy < L.fh - 1; ++fy)  // the frame's interior lies inside the level
-    memcpy(&tags[(size_t)(L.fy0 + fy) * Nx + L.fx0 + 1], &ft[(size_t)fy * L.fw + 1], L.fw - 2);
+  for (int sr = 0; sr < L.nrows; ++sr) {  // stored rows inside the level; interior columns
+    const int y = L.fy0 + L.yrow[sr];
+    if (y >= 0 && y < Ny) memcpy(&tags[(size_t)y * Nx + L.fx0 + 1], &ft[(size_t)sr * L.fw + 1], L.fw - 2);
+  }
   return VLBM_OK;
 }
 
@@ -2426,6 +2574,8 @@ vlbm_status vlbm_tag_and_regrid(vlbm_ctx *c, double thr, int buffer, int min_box
     T.y0 = L.fy0;
     T.w = L.fw;
     T.h = L.fh;
+    T.srow = L.srow;
+    T.yrow = L.yrow;
     vlbm_status st = tag_frame(c, l, thr, T.t);
     if (st) return st;
   }
@@ -2436,14 +2586,19 @@ vlbm_status vlbm_tag_and_regrid(vlbm_ctx *c, double thr, int buffer, int min_box
   return vlbm_regrid(c, boxes.data(), (int)boxes.size());
 }
 
-// Checkpoint layout: header, boxes, per present level {steps, both buffers,
-// reflux accumulators, ledger slots}, ledger carry.
+// Checkpoint layout: header; boxes; per present level its frame {bx0, bx1,
+// number of row runs, the runs}; then per present level {steps, nacc,
+// nledger, both buffers, reflux accumulators, ledger slots}. The header
+// carries the ledger carry and, for the adaptive time step, the link speeds
+// of the current and previous coarse step and the elapsed time.
 struct CkptHeader {
   char magic[8];
   vlbm_params p;
   int32_t nboxes, nlev;
   int64_t coarse_steps;
   double carry[4], carry_c[4];
+  int32_t adt, pad;
+  double dyn_c, dyn_c_prev, dyn_time;
 };
 
 vlbm_status vlbm_save(vlbm_ctx *c, void *buf, size_t *bytes) {
@@ -2451,7 +2606,9 @@ vlbm_status vlbm_save(vlbm_ctx *c, void *buf, size_t *bytes) {
   size_t need = sizeof(CkptHeader) + sizeof(vlbm_box) * c->boxes.size();
   for (int l = 0; l < c->nlev; ++l) {
     const Level &L = c->lv[l];
-    need += sizeof(int64_t) + 2 * level_bytes(L, c->esz) + sizeof(double) * 4 * (L.nacc + L.nledger);
+    need += 3 * sizeof(int32_t) + 2 * sizeof(int32_t) * L.runs.size();
+    need += sizeof(int64_t) + 2 * sizeof(int32_t) + 2 * level_bytes(L, c->esz) +
+            sizeof(double) * 4 * ((size_t)L.nacc + L.nledger);
   }
   if (!buf) {
     *bytes = need;
@@ -2459,8 +2616,12 @@ vlbm_status vlbm_save(vlbm_ctx *c, void *buf, size_t *bytes) {
   }
   if (*bytes < need) return fail(VLBM_EINVAL, "checkpoint buffer too small (%zu < %zu)", *bytes, need);
   char *p = static_cast<char *>(buf);
+  auto put = [&](const void *v, size_t n) {
+    memcpy(p, v, n);
+    p += n;
+  };
   CkptHeader h{};
-  memcpy(h.magic, "VLBMCK1", 8);
+  memcpy(h.magic, "VLBMCK2", 8);
   h.p = c->p;
   h.nboxes = (int32_t)c->boxes.size();
   h.nlev = c->nlev;
@@ -2469,15 +2630,32 @@ vlbm_status vlbm_save(vlbm_ctx *c, void *buf, size_t *bytes) {
     h.carry[k] = c->ledger_carry[k];
     h.carry_c[k] = c->ledger_carry_c[k];
   }
-  memcpy(p, &h, sizeof h);
-  p += sizeof h;
-  memcpy(p, c->boxes.data(), sizeof(vlbm_box) * c->boxes.size());
-  p += sizeof(vlbm_box) * c->boxes.size();
+  h.adt = c->adt ? 1 : 0;
+  if (c->adt) {
+    double dyn[DYN_SLOTS];
+    HIPCHK(hipMemcpyAsync(dyn, c->ddyn, sizeof dyn, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    h.dyn_c = dyn[DYN_C];
+    h.dyn_c_prev = dyn[DYN_C_PREV];
+    h.dyn_time = dyn[DYN_TIME];
+  }
+  put(&h, sizeof h);
+  put(c->boxes.data(), sizeof(vlbm_box) * c->boxes.size());
   for (int l = 0; l < c->nlev; ++l) {
     const Level &L = c->lv[l];
-    int64_t steps = L.steps;
-    memcpy(p, &steps, sizeof steps);
-    p += sizeof steps;
+    const int32_t fr[3] = {L.fx0 + 1, L.fx0 + L.fw - 1, (int32_t)L.runs.size()};
+    put(fr, sizeof fr);
+    for (const auto &r : L.runs) {
+      const int32_t rr[2] = {r.first, r.second};
+      put(rr, sizeof rr);
+    }
+  }
+  for (int l = 0; l < c->nlev; ++l) {
+    const Level &L = c->lv[l];
+    const int64_t steps = L.steps;
+    const int32_t counts[2] = {L.nacc, L.nledger};
+    put(&steps, sizeof steps);
+    put(counts, sizeof counts);
     const size_t nb = level_bytes(L, c->esz);
     for (int b = 0; b < 2; ++b) {
       HIPCHK(hipMemcpyAsync(p, L.buf[b], nb, hipMemcpyDeviceToHost, c->stream));
@@ -2494,13 +2672,22 @@ vlbm_status vlbm_save(vlbm_ctx *c, void *buf, size_t *bytes) {
   return VLBM_OK;
 }
 
+// Every read is checked against the buffer's size before it is made; a
+// checkpoint that does not fit the context (parameters, time stepping mode,
+// levels, frames, slot counts) is refused with VLBM_EINVAL.
 vlbm_status vlbm_load(vlbm_ctx *c, const void *buf, size_t bytes) {
-  if (!c || !buf || bytes < sizeof(CkptHeader)) return fail(VLBM_EINVAL, "bad checkpoint");
-  const char *p = static_cast<const char *>(buf);
+  if (!c || !buf) return fail(VLBM_EINVAL, "bad checkpoint");
+  const char *const base = static_cast<const char *>(buf);
+  size_t at = 0;
+  auto take = [&](void *v, size_t n) -> bool {
+    if (n > bytes - at) return false;
+    memcpy(v, base + at, n);
+    at += n;
+    return true;
+  };
   CkptHeader h;
-  memcpy(&h, p, sizeof h);
-  p += sizeof h;
-  if (memcmp(h.magic, "VLBMCK1", 8) != 0) return fail(VLBM_EINVAL, "not a checkpoint");
+  if (bytes < sizeof h || !take(&h, sizeof h) || memcmp(h.magic, "VLBMCK2", 8) != 0)
+    return fail(VLBM_EINVAL, "not a checkpoint");
   {
     const vlbm_params &a = h.p, &b = c->p;
     bool same = a.nx0 == b.nx0 && a.ny0 == b.ny0 && a.dx0 == b.dx0 && a.gamma == b.gamma &&
@@ -2512,29 +2699,64 @@ vlbm_status vlbm_load(vlbm_ctx *c, const void *buf, size_t bytes) {
     }
     if (!same) return fail(VLBM_EINVAL, "checkpoint parameters differ from the context's");
   }
+  if ((h.adt != 0) != c->adt)
+    return fail(VLBM_EINVAL, "checkpoint taken with the adaptive time step %s, context has it %s",
+                h.adt ? "on" : "off", c->adt ? "on" : "off");
+  if (h.nboxes < 0 || h.nlev < 1 || h.nlev > kMaxLevels || h.coarse_steps < 0 ||
+      (size_t)h.nboxes > (bytes - at) / sizeof(vlbm_box))
+    return fail(VLBM_EINVAL, "corrupt checkpoint header");
   std::vector<vlbm_box> boxes(h.nboxes);
-  memcpy(boxes.data(), p, sizeof(vlbm_box) * h.nboxes);
-  p += sizeof(vlbm_box) * h.nboxes;
-  vlbm_status st = vlbm_set_hierarchy(c, boxes.data(), h.nboxes);
+  if (h.nboxes) take(boxes.data(), sizeof(vlbm_box) * h.nboxes);
+  FrameSpec specs[kMaxLevels];
+  for (int l = 0; l < h.nlev; ++l) {
+    int32_t fr[3];
+    if (!take(fr, sizeof fr)) return fail(VLBM_EINVAL, "truncated checkpoint");
+    if (fr[2] < 1 || fr[0] >= fr[1] || (size_t)fr[2] > (bytes - at) / (2 * sizeof(int32_t)))
+      return fail(VLBM_EINVAL, "corrupt checkpoint frame (level %d)", l);
+    specs[l].bx0 = fr[0];
+    specs[l].bx1 = fr[1];
+    for (int i = 0; i < fr[2]; ++i) {
+      int32_t rr[2];
+      take(rr, sizeof rr);
+      if (rr[0] >= rr[1] || (!specs[l].rows.empty() && rr[0] <= specs[l].rows.back().second))
+        return fail(VLBM_EINVAL, "corrupt checkpoint frame (level %d)", l);
+      specs[l].rows.push_back({rr[0], rr[1]});
+    }
+  }
+  vlbm_status st = set_hierarchy_impl(c, boxes.data(), h.nboxes, specs);
   if (st) return st;
   if (c->nlev != h.nlev) return fail(VLBM_EINVAL, "checkpoint level count mismatch");
   for (int l = 0; l < c->nlev; ++l) {
     Level &L = c->lv[l];
     int64_t steps;
-    memcpy(&steps, p, sizeof steps);
-    p += sizeof steps;
-    L.steps = steps;
+    int32_t counts[2];
+    if (!take(&steps, sizeof steps) || !take(counts, sizeof counts)) return fail(VLBM_EINVAL, "truncated checkpoint");
+    if (steps < 0 || counts[0] != L.nacc || counts[1] != L.nledger)
+      return fail(VLBM_EINVAL, "checkpoint level %d does not match its hierarchy", l);
     const size_t nb = level_bytes(L, c->esz);
-    if ((size_t)(p - static_cast<const char *>(buf)) + 2 * nb > bytes) return fail(VLBM_EINVAL, "truncated checkpoint");
+    const size_t slots = sizeof(double) * 4 * ((size_t)L.nacc + L.nledger);
+    if (bytes - at < 2 * nb || bytes - at - 2 * nb < slots) return fail(VLBM_EINVAL, "truncated checkpoint");
+    L.steps = steps;
     for (int b = 0; b < 2; ++b) {
-      HIPCHK(hipMemcpyAsync(L.buf[b], p, nb, hipMemcpyHostToDevice, c->stream));
-      p += nb;
+      HIPCHK(hipMemcpyAsync(L.buf[b], base + at, nb, hipMemcpyHostToDevice, c->stream));
+      at += nb;
     }
-    if (L.nacc) HIPCHK(hipMemcpyAsync(L.dacc, p, sizeof(double) * 4 * L.nacc, hipMemcpyHostToDevice, c->stream));
-    p += sizeof(double) * 4 * L.nacc;
+    if (L.nacc) HIPCHK(hipMemcpyAsync(L.dacc, base + at, sizeof(double) * 4 * L.nacc, hipMemcpyHostToDevice, c->stream));
+    at += sizeof(double) * 4 * L.nacc;
     if (L.nledger)
-      HIPCHK(hipMemcpyAsync(L.dledger, p, sizeof(double) * 4 * L.nledger, hipMemcpyHostToDevice, c->stream));
-    p += sizeof(double) * 4 * L.nledger;
+      HIPCHK(hipMemcpyAsync(L.dledger, base + at, sizeof(double) * 4 * L.nledger, hipMemcpyHostToDevice, c->stream));
+    at += sizeof(double) * 4 * L.nledger;
+  }
+  if (c->adt) {
+    double dyn[DYN_SLOTS];
+    HIPCHK(hipMemcpyAsync(dyn, c->ddyn, sizeof dyn, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    dyn[DYN_C] = h.dyn_c;
+    dyn[DYN_H] = 1.0 / (2.0 * h.dyn_c);
+    dyn[DYN_C_PREV] = h.dyn_c_prev;
+    dyn[DYN_TIME] = h.dyn_time;
+    HIPCHK(hipMemcpyAsync(c->ddyn, dyn, sizeof dyn, hipMemcpyHostToDevice, c->stream));
+    c->cfl_stale = true;
   }
   HIPCHK(hipStreamSynchronize(c->stream));
   c->coarse_steps = h.coarse_steps;
@@ -2846,13 +3068,22 @@ vlbm_status vlbm_get_beta(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny
   int ci0 = i0, cj0 = j0, cnx = nx, cny = ny, ox = 0, oy = 0;
   if (!clip_to_frame(L, ci0, cj0, cnx, cny, ox, oy)) return VLBM_OK;
   std::vector<double> rows((size_t)cnx * cny);
-  HIPCHK(hipMemcpy2DAsync(rows.data(), sizeof(double) * cnx, L.dsen + SEN_BETA * L.plane + L.off(ci0, cj0),
-                          sizeof(double) * L.pitch, sizeof(double) * cnx, cny, hipMemcpyDeviceToHost,
-                          c->stream));
+  for (int y = 0; y < cny;) {  // runs of stored rows
+    if (!L.stored(cj0 + y)) {
+      ++y;
+      continue;
+    }
+    int y1 = y + 1;
+    while (y1 < cny && L.stored(cj0 + y1)) ++y1;
+    HIPCHK(hipMemcpy2DAsync(rows.data() + (size_t)y * cnx, sizeof(double) * cnx,
+                            L.dsen + SEN_BETA * L.plane + L.off(ci0, cj0 + y), sizeof(double) * L.pitch,
+                            sizeof(double) * cnx, y1 - y, hipMemcpyDeviceToHost, c->stream));
+    y = y1;
+  }
   HIPCHK(hipStreamSynchronize(c->stream));
   for (int y = 0; y < cny; ++y)
     for (int x = 0; x < cnx; ++x)
-      if (L.status[L.fidx(ci0 + x, cj0 + y)] == 1)
+      if (L.stored(cj0 + y) && L.status[L.fidx(ci0 + x, cj0 + y)] == 1)
         beta[(size_t)(y + oy) * ld + x + ox] = rows[(size_t)y * cnx + x];
   return VLBM_OK;
 }

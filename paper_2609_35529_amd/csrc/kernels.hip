@@ -324,35 +324,39 @@ __device__ __forceinline__ void block_max_slot(double m, unsigned long long *slo
 }
 
 // Offset of level cell (x + dx, y + dy) (active, per its mask bit), periodic
-// wrap applied: a neighbour across the domain edge sits Nx columns (Ny rows)
-// back in the frame.
-__device__ __forceinline__ int64_t nb_offset(int64_t o, int x, int y, int dx, int dy, int pitch, int Nx,
-                                             int Ny) {
-  int64_t e = o + dx + (int64_t)dy * pitch;
-  if (x + dx < 0) e += Nx;
-  if (x + dx >= Nx) e -= Nx;
-  if (y + dy < 0) e += (int64_t)Ny * pitch;
-  if (y + dy >= Ny) e -= (int64_t)Ny * pitch;
-  return e;
+// wrap applied: a neighbour across a periodic x edge sits Nx columns back in
+// its row; across a periodic y edge it lies in another stored row, found from
+// the frame's row table (the rows next to an active cell are one pitch away).
+__device__ __forceinline__ int64_t nb_offset(const LevelDesc &A, int64_t o, int x, int y, int dx, int dy,
+                                             int pitch, int Nx, int Ny) {
+  int xx = x + dx, yy = y + dy;
+  int64_t e = o + dx;
+  if (xx < 0) e += Nx, xx += Nx;
+  if (xx >= Nx) e -= Nx, xx -= Nx;
+  if (yy < 0 || yy >= Ny) {
+    yy = yy < 0 ? yy + Ny : yy - Ny;
+    return (int64_t)A.srow[yy - A.fy0] * pitch + (xx - A.fx0) + A.xoff;
+  }
+  return e + (int64_t)dy * pitch;
 }
 
 // Level coordinates of a tile's first cell.
 __device__ __forceinline__ void tile_origin(const LevelDesc &A, const Tile &tl, int &x0, int &y0) {
   const int rel = tl.off0 - A.xoff;
-  const int fy = rel / A.pitch;
-  x0 = A.fx0 + (rel - fy * A.pitch);
-  y0 = A.fy0 + fy;
+  const int sr = rel / A.pitch;
+  x0 = A.fx0 + (rel - sr * A.pitch);
+  y0 = A.fy0 + A.yrow[sr];
 }
 
 // Walk from the tile cell at offset o, level (x, y), by (dx, dy) with
 // |dx|, |dy| <= 1: the step is taken only where the cell's mask marks the
 // target as an active neighbour (then o, x, y become the target's, periodic
 // sides wrapped); returns whether it was.
-__device__ __forceinline__ bool mask_step(const __attribute__((address_space(1))) uint8_t *M, int64_t &o,
-                                          int &x, int &y, int dx, int dy, int pitch, int Nx, int Ny) {
+__device__ __forceinline__ bool mask_step(const LevelDesc &A, const __attribute__((address_space(1))) uint8_t *M,
+                                          int64_t &o, int &x, int &y, int dx, int dy, int pitch, int Nx, int Ny) {
   if (dx == 0 && dy == 0) return true;
   if (!((M[o] >> mask_bit(dx, dy)) & 1)) return false;
-  o = nb_offset(o, x, y, dx, dy, pitch, Nx, Ny);
+  o = nb_offset(A, o, x, y, dx, dy, pitch, Nx, Ny);
   x += dx;
   y += dy;
   x = x < 0 ? x + Nx : x >= Nx ? x - Nx : x;
@@ -435,8 +439,8 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
       int64_t o = (int64_t)tl.off0 + (int64_t)cj * pitch + ci;
       int x = x0 + ci, y = y0 + cj;
       const int sx = (di > 0) - (di < 0), sy = (dj > 0) - (dj < 0);
-      if (!mask_step(M, o, x, y, sx, sy, pitch, Nx, Ny)) continue;
-      if (!mask_step(M, o, x, y, di - sx, dj - sy, pitch, Nx, Ny)) continue;
+      if (!mask_step(A, M, o, x, y, sx, sy, pitch, Nx, Ny)) continue;
+      if (!mask_step(A, M, o, x, y, di - sx, dj - sy, pitch, Nx, Ny)) continue;
       double w[4], qx[4], qy[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) w[k] = Wc[k * plane + o];
@@ -460,7 +464,7 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
       int64_t o = (int64_t)tl.off0 + (int64_t)cj * pitch + ci;
       int x = x0 + ci, y = y0 + cj;
       double a = 0.0, th = 0.0;
-      if (mask_step(M, o, x, y, i - ci, j - cj, pitch, Nx, Ny)) {
+      if (mask_step(A, M, o, x, y, i - ci, j - cj, pitch, Nx, Ny)) {
         // s_k from the four neighbours' fluxes over this coarse step's Qmax,
         // a their RMS; theta from dilatation and vorticity. A neighbour that
         // is not an active cell stands in as the cell itself.
@@ -981,18 +985,19 @@ __global__ __launch_bounds__(64) void sensor_clear_kernel(StepLaunch Lc) {
   }
 }
 
-// One thread per frame element; writes the mask of every active cell and 0
-// elsewhere.
-__global__ __launch_bounds__(256) void sensor_mask_kernel(const uint8_t *status, uint8_t *mask, int fx0,
-                                                          int fy0, int fw, int fh, int pitch, int xoff,
-                                                          int Nx, int Ny, int per) {
+// One thread per stored frame element; writes the mask of every active cell
+// and 0 elsewhere.
+__global__ __launch_bounds__(256) void sensor_mask_kernel(const uint8_t *status, uint8_t *mask,
+                                                          const int32_t *srow, const int32_t *yrow, int fx0,
+                                                          int fy0, int fw, int fh, int nrows, int pitch,
+                                                          int xoff, int Nx, int Ny, int per) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)fw * fh) return;
-  const int fy = (int)(i / fw), fx = (int)(i - (int64_t)fy * fw);
-  const int64_t o = (int64_t)fy * pitch + fx + xoff;
+  if (i >= (int64_t)fw * nrows) return;
+  const int sr = (int)(i / fw), fx = (int)(i - (int64_t)sr * fw);
+  const int64_t o = (int64_t)sr * pitch + fx + xoff;
   int mk = 0;
   if (status[i] == 1) {
-    const int x = fx0 + fx, y = fy0 + fy;
+    const int x = fx0 + fx, y = fy0 + yrow[sr];
     for (int dy = -1; dy <= 1; ++dy)
       for (int dx = -1; dx <= 1; ++dx) {
         if (dx == 0 && dy == 0) continue;
@@ -1006,19 +1011,20 @@ __global__ __launch_bounds__(256) void sensor_mask_kernel(const uint8_t *status,
           yy = yy < 0 ? yy + Ny : yy - Ny;
         }
         const int gx = xx - fx0, gy = yy - fy0;
-        if (gx < 0 || gy < 0 || gx >= fw || gy >= fh) continue;
-        if (status[(int64_t)gy * fw + gx] == 1) mk |= 1 << mask_bit(dx, dy);
+        if (gx < 0 || gy < 0 || gx >= fw || gy >= fh || srow[gy] < 0) continue;
+        if (status[(int64_t)srow[gy] * fw + gx] == 1) mk |= 1 << mask_bit(dx, dy);
       }
   }
   mask[o] = (uint8_t)mk;
 }
 
-hipError_t launch_sensor_mask(const uint8_t *status, uint8_t *mask, int fx0, int fy0, int fw, int fh,
-                              int pitch, int xoff, int Nx, int Ny, int per, hipStream_t s) {
-  const int64_t n = (int64_t)fw * fh;
+hipError_t launch_sensor_mask(const uint8_t *status, uint8_t *mask, const int32_t *srow, const int32_t *yrow,
+                              int fx0, int fy0, int fw, int fh, int nrows, int pitch, int xoff, int Nx,
+                              int Ny, int per, hipStream_t s) {
+  const int64_t n = (int64_t)fw * nrows;
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(sensor_mask_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, status, mask,
-                     fx0, fy0, fw, fh, pitch, xoff, Nx, Ny, per);
+                     srow, yrow, fx0, fy0, fw, fh, nrows, pitch, xoff, Nx, Ny, per);
   return hipGetLastError();
 }
 
@@ -1173,9 +1179,9 @@ __global__ void set_kernel(RectArgs a, int raw) {
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
        c += (int64_t)gridDim.x * blockDim.x) {
     const int y = (int)(c / a.nx), x = (int)(c - (int64_t)y * a.nx);
-    const int fx = a.x0 + x - a.fx0, fy = a.y0 + y - a.fy0;
-    if (a.status[(int64_t)fy * a.fw + fx] == 0) continue;
-    const int64_t o = (int64_t)fy * a.pitch + fx + a.xoff;
+    const int fx = a.x0 + x - a.fx0, sr = a.srow[a.y0 + y - a.fy0];
+    if (sr < 0 || a.status[(int64_t)sr * a.fw + fx] == 0) continue;
+    const int64_t o = (int64_t)sr * a.pitch + fx + a.xoff;
     double f[16];
     if (raw) {
 #pragma unroll
@@ -1202,9 +1208,9 @@ __global__ void get_kernel(RectArgs a, int pops) {
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
        c += (int64_t)gridDim.x * blockDim.x) {
     const int y = (int)(c / a.nx), x = (int)(c - (int64_t)y * a.nx);
-    const int fx = a.x0 + x - a.fx0, fy = a.y0 + y - a.fy0;
-    const bool act = a.status[(int64_t)fy * a.fw + fx] == 1;
-    const int64_t o = (int64_t)fy * a.pitch + fx + a.xoff;
+    const int fx = a.x0 + x - a.fx0, sr = a.srow[a.y0 + y - a.fy0];
+    const bool act = sr >= 0 && a.status[(int64_t)sr * a.fw + fx] == 1;
+    const int64_t o = (int64_t)(sr < 0 ? 0 : sr) * a.pitch + fx + a.xoff;
     const T *b0 = static_cast<const T *>(a.buf0);
     if (pops) {
 #pragma unroll
@@ -1298,19 +1304,19 @@ __device__ __forceinline__ double cell_rho(const T *b, int64_t P, int64_t o) {
 }
 
 template <class T>
-__global__ void tag_kernel(const T *__restrict__ buf, const uint8_t *status, int64_t P,
-                           int pitch, int xoff, int fx0, int fy0, int fw, int fh, int Nx,
-                           int Ny, int perx, int pery, double thr, uint8_t *tags) {
-  // one thread per frame cell; tags are frame-indexed (only active cells of
-  // the level, which all lie in its frame, can be tagged)
-  const int64_t n = (int64_t)fw * fh;
+__global__ void tag_kernel(const T *__restrict__ buf, const uint8_t *status, const int32_t *srow,
+                           const int32_t *yrow, int64_t P, int pitch, int xoff, int fx0, int fy0, int fw,
+                           int fh, int nrows, int Nx, int Ny, int perx, int pery, double thr, uint8_t *tags) {
+  // one thread per stored frame cell; tags are indexed like the status (only
+  // active cells of the level, which all lie in its frame, can be tagged)
+  const int64_t n = (int64_t)fw * nrows;
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
        c += (int64_t)gridDim.x * blockDim.x) {
-    const int fy = (int)(c / fw), fx = (int)(c - (int64_t)fy * fw);
-    const int x = fx + fx0, y = fy + fy0;
+    const int sr = (int)(c / fw), fx = (int)(c - (int64_t)sr * fw);
+    const int x = fx + fx0, y = yrow[sr] + fy0;
     uint8_t tag = 0;
     if (status[c] == 1) {
-      const int64_t o = (int64_t)fy * pitch + fx + xoff;
+      const int64_t o = (int64_t)sr * pitch + fx + xoff;
       const double rc = cell_rho<T>(buf, P, o);
       double rn[4];
       const int dx[4] = {1, -1, 0, 0}, dy[4] = {0, 0, 1, -1};
@@ -1327,8 +1333,9 @@ __global__ void tag_kernel(const T *__restrict__ buf, const uint8_t *status, int
         double v = rc;
         if (ok) {
           const int gx = xx - fx0, gy = yy - fy0;
-          if (gx >= 0 && gy >= 0 && gx < fw && gy < fh && status[(int64_t)gy * fw + gx] == 1)
-            v = cell_rho<T>(buf, P, (int64_t)gy * pitch + gx + xoff);
+          const int gs = (gy >= 0 && gy < fh) ? srow[gy] : -1;
+          if (gx >= 0 && gx < fw && gs >= 0 && status[(int64_t)gs * fw + gx] == 1)
+            v = cell_rho<T>(buf, P, (int64_t)gs * pitch + gx + xoff);
         }
         rn[d] = v;
       }
@@ -1341,18 +1348,20 @@ __global__ void tag_kernel(const T *__restrict__ buf, const uint8_t *status, int
   }
 }
 
-hipError_t launch_tag(const void *buf, const uint8_t *status, int64_t plane, int pitch, int xoff,
-                      int fx0, int fy0, int fw, int fh, int Nx, int Ny, int perx, int pery,
-                      int fp32, double thr, uint8_t *tags, hipStream_t s) {
-  const int64_t n = (int64_t)fw * fh;
+hipError_t launch_tag(const void *buf, const uint8_t *status, const int32_t *srow, const int32_t *yrow,
+                      int64_t plane, int pitch, int xoff, int fx0, int fy0, int fw, int fh, int nrows,
+                      int Nx, int Ny, int perx, int pery, int fp32, double thr, uint8_t *tags,
+                      hipStream_t s) {
+  const int64_t n = (int64_t)fw * nrows;
+  if (n <= 0) return hipSuccess;
   if (fp32)
-    hipLaunchKernelGGL(tag_kernel<float>, grid_for(n), dim3(256), 0, s,
-                       static_cast<const float *>(buf), status, plane, pitch, xoff, fx0, fy0, fw,
-                       fh, Nx, Ny, perx, pery, thr, tags);
+    hipLaunchKernelGGL(tag_kernel<float>, grid_for(n), dim3(256), 0, s, static_cast<const float *>(buf),
+                       status, srow, yrow, plane, pitch, xoff, fx0, fy0, fw, fh, nrows, Nx, Ny, perx, pery,
+                       thr, tags);
   else
-    hipLaunchKernelGGL(tag_kernel<double>, grid_for(n), dim3(256), 0, s,
-                       static_cast<const double *>(buf), status, plane, pitch, xoff, fx0, fy0,
-                       fw, fh, Nx, Ny, perx, pery, thr, tags);
+    hipLaunchKernelGGL(tag_kernel<double>, grid_for(n), dim3(256), 0, s, static_cast<const double *>(buf),
+                       status, srow, yrow, plane, pitch, xoff, fx0, fy0, fw, fh, nrows, Nx, Ny, perx, pery,
+                       thr, tags);
   return hipGetLastError();
 }
 

@@ -1,10 +1,13 @@
 // Internal definitions of libvlbm shared by its host and device translation
 // units: device work descriptors and the launch entry points.
 //
-// Data layout (per level l, one dense "frame" = bounding box of the level's
-// coverage plus a one-cell ghost ring):
+// Data layout (per level l, one "frame": the columns of the coverage's bounding
+// box plus a ghost column on each side, over the runs of rows that hold the
+// covered rows and their neighbour rows; rows between runs are not stored):
 //   buffer b in {0,1}: 16 planes (q*4+k) of `plane` elements each; the element
-//   of level cell (x,y) is  (y - fy0) * pitch + (x - fx0) + xoff  within a plane.
+//   of level cell (x,y) is  srow[y - fy0] * pitch + (x - fx0) + xoff  within a
+//   plane, where srow numbers the stored rows in increasing y (so the rows
+//   above and below an active cell are one pitch away).
 //   Stored values are post-collision populations f*; the current time level of
 //   level l lives in buf[steps_l & 1], the previous one in the other buffer.
 #pragma once
@@ -162,6 +165,8 @@ struct LevelDesc {
                              // cleared (stage 1) before it
   int32_t emit_qmax;         // this phase is the level's last of the coarse step: accumulate qmax_next
   int32_t fx0, fy0, xoff;    // frame origin (level cells)
+  const int32_t *srow;       // frame row -> storage row (-1: not stored)
+  const int32_t *yrow;       // storage row -> frame row
   int32_t Nx, Ny;            // level domain
   double c_sensor, beta_min, beta_max;
   // adaptive time step: the DynState scalars, and whether this phase's parent
@@ -197,7 +202,8 @@ struct StepLaunch {
 // Rectangle copy-in / copy-out and diagnostics.
 struct RectArgs {
   void *buf0, *buf1;         // both buffers of the level (set: both written; get: buf0 read)
-  const uint8_t *status;     // frame status: 0 none, 1 active, 2 hole
+  const uint8_t *status;     // frame status (fw per stored row): 0 none, 1 active, 2 hole
+  const int32_t *srow;       // frame row -> storage row (-1: not stored, no covered cell)
   double *host_stage;        // device staging [ncomp][ny][nx]
   int64_t plane;
   int32_t pitch, xoff, fx0, fy0, fw;
@@ -223,19 +229,23 @@ hipError_t launch_cfl(const StepLaunch &a, int fp32, unsigned long long *cmax, c
 hipError_t launch_cfl_finalize(double *dyn, unsigned long long *cmax, hipStream_t s);
 // Zero n 64-bit words of device memory on stream s (no memset node under capture).
 hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t s);
-// Neighbour masks of a level frame from its status (fw x fh bytes, 1 = active).
-hipError_t launch_sensor_mask(const uint8_t *status, uint8_t *mask, int fx0, int fy0, int fw, int fh,
-                              int pitch, int xoff, int Nx, int Ny, int per, hipStream_t s);
+// Neighbour masks of a level frame from its status (fw bytes per stored row,
+// 1 = active); srow / yrow map frame rows to storage rows and back.
+hipError_t launch_sensor_mask(const uint8_t *status, uint8_t *mask, const int32_t *srow, const int32_t *yrow,
+                              int fx0, int fy0, int fw, int fh, int nrows, int pitch, int xoff, int Nx,
+                              int Ny, int per, hipStream_t s);
 hipError_t launch_audit(const void *buf, const Tile *tiles, int ntiles, int64_t plane,
                         int pitch, int fp32, double *partial, hipStream_t s);
 hipError_t launch_set_state(const RectArgs &a, int fp32, int raw_populations, hipStream_t s);
 hipError_t launch_get(const RectArgs &a, int fp32, int populations, hipStream_t s);
 hipError_t launch_health(const void *buf, const Tile *tiles, int ntiles, int64_t plane,
                          int pitch, int fp32, const EosT<double> &eos, int *flag, hipStream_t s);
-// tags: frame-indexed (fw x fh bytes), 1 on tagged active cells, else 0
-hipError_t launch_tag(const void *buf, const uint8_t *status, int64_t plane, int pitch,
-                      int xoff, int fx0, int fy0, int fw, int fh, int Nx, int Ny, int perx,
-                      int pery, int fp32, double thr, uint8_t *tags, hipStream_t s);
+// tags: indexed like the status (fw bytes per stored row), 1 on tagged active
+// cells, else 0
+hipError_t launch_tag(const void *buf, const uint8_t *status, const int32_t *srow, const int32_t *yrow,
+                      int64_t plane, int pitch, int xoff, int fx0, int fy0, int fw, int fh, int nrows,
+                      int Nx, int Ny, int perx, int pery, int fp32, double thr, uint8_t *tags,
+                      hipStream_t s);
 
 // Regrid kernels: a list of cell operations on level frames.
 struct RegridOp {          // one coarse cell (merge) or one parent cell (split)

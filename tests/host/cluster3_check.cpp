@@ -26,6 +26,7 @@ hipError_t launch_get3(const Rect3 &, int, int, hipStream_t) { return hipErrorUn
 hipError_t launch_merge3(const RegridArgs3 &, int, hipStream_t) { return hipErrorUnknown; }
 hipError_t launch_split3(const RegridArgs3 &, int, hipStream_t) { return hipErrorUnknown; }
 hipError_t launch_copy3_runs(const void *, const void *, void *, void *, const int32_t *, int, int64_t, int64_t, int, hipStream_t) { return hipErrorUnknown; }
+hipError_t launch_restart_faces3(const void *, void *, const int32_t *, int, int64_t, int, hipStream_t) { return hipErrorUnknown; }
 hipError_t launch_tag3(const Tag3Args &, int, hipStream_t) { return hipErrorUnknown; }
 }  // namespace vlbm3
 
