@@ -41,7 +41,8 @@ MEASURED_TRAFFIC = {"kernel_sha256_16": "6cf11abdac8d69f4", "workload": "quadran
 # (the density-gradient indicator is per cell, so it halves with each level
 # on a smeared layer: the shear layer needs a lower threshold to keep level 3)
 DYNAMIC = {"shock_bubble": {"max_box": 64, "threshold": 0.05},
-           "kh_strip": {"max_box": 128, "threshold": 0.01}}
+           "kh_strip": {"max_box": 128, "threshold": 0.01},
+           "kh4096": {"max_box": 128, "threshold": 0.01, "tuning": (512, 17)}}
 
 
 def kernel_hash():
@@ -60,6 +61,8 @@ def build_case(name, steps):
         return wl.shock_bubble(steps=steps)
     if name == "kh_strip":
         return wl.kelvin_helmholtz_strip(steps=steps)
+    if name == "kh4096":
+        return wl.kelvin_helmholtz(n0=4096, seed=0, nlev=4, steps=steps, dynamic=True)
     if name == "uniform4096":
         import numpy as np
         n = 4096
@@ -105,6 +108,7 @@ def bench_3d(args):
             if args.amr_threshold is not None:
                 act = [solver.active_cells(l) for l in range(case.nlev)]
                 amr["updates"] += k * sum(a * case.r ** l for l, a in enumerate(act))
+                solver.sync()  # regrid_s: the regrid's own time, not the steps queued before it
                 t = time.perf_counter()
                 solver.tag_and_regrid(args.amr_threshold, buffer=args.amr_buffer,
                                       min_box=args.amr_min_box, max_box=args.amr_max_box or 64)
@@ -363,6 +367,8 @@ def main():
     T0, L0 = solver.totals()
 
     tuning = None
+    if not args.tile_cells and args.workload in DYNAMIC and "tuning" in DYNAMIC[args.workload]:
+        args.tile_cells, args.flags = DYNAMIC[args.workload]["tuning"]
     if args.tile_cells:
         solver.set_tuning(args.tile_cells, args.flags)
         tuning = {"tile_cells": args.tile_cells, "flags": args.flags}
@@ -370,11 +376,11 @@ def main():
         print(f"[bench] {case.name} autotune", file=sys.stderr, flush=True)
         tile, flags = solver.autotune(steps_per_trial=args.tune_steps)
         tuning = {"tile_cells": tile, "flags": flags}
-    dynamic = case.name in DYNAMIC
+    dynamic = args.workload in DYNAMIC
     if dynamic and args.amr_max_box == 0:
-        args.amr_max_box = DYNAMIC[case.name]["max_box"]
+        args.amr_max_box = DYNAMIC[args.workload]["max_box"]
     if dynamic and args.amr_threshold is None:
-        args.amr_threshold = DYNAMIC[case.name]["threshold"]
+        args.amr_threshold = DYNAMIC[args.workload]["threshold"]
     regrid_every = 5
     amr = {"regrids": 0, "boxes": [], "regrid_s": 0.0, "updates": 0}
 
@@ -387,6 +393,7 @@ def main():
         done = 0
         while done < n:
             if solver.steps() % regrid_every == 0:
+                solver.sync()  # regrid_s: the regrid's own time, not the steps queued before it
                 t = time.perf_counter()
                 solver.tag_and_regrid(args.amr_threshold, buffer=args.amr_buffer,
                                       min_box=args.amr_min_box, max_box=args.amr_max_box)

@@ -321,6 +321,19 @@ struct vlbm_ctx {
   std::vector<Segment> hseg;
   int nseg_table = 0;
   long graph_key = -1;
+  // device scratch of tag_and_regrid (tags per level, tile bits and lists,
+  // counts), kept between calls and grown on demand: slot -> (pointer, bytes)
+  std::vector<std::pair<void *, size_t>> tag_scratch;
+  void *scratch_slot(size_t slot, size_t bytes) {
+    if (tag_scratch.size() <= slot) tag_scratch.resize(slot + 1, {nullptr, 0});
+    auto &e = tag_scratch[slot];
+    if (e.second < bytes) {
+      mem.release(e.first);
+      e.first = mem.alloc(std::max<size_t>(bytes, 256));
+      e.second = e.first ? bytes : 0;
+    }
+    return e.first;
+  }
 
   bool perx() const { return p.bc[0] == VLBM_BC_PERIODIC; }
   bool pery() const { return p.bc[2] == VLBM_BC_PERIODIC; }
@@ -1966,39 +1979,59 @@ vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
 int level_nx(const vlbm_ctx *c, int l);
 int level_ny(const vlbm_ctx *c, int l);
 
-// Tags of one level over its frame (outside it, none): w bytes per stored
-// frame row, srow mapping frame rows (y - y0) to stored rows (-1: not stored,
-// no tag there) and yrow back.
-struct TagMap {
-  int x0 = 0, y0 = 0, w = 0, h = 0;
-  std::vector<int32_t> srow, yrow;
-  std::vector<uint8_t> t;
-};
-// Coverage of one level over a rectangle of its cells (outside it: not
-// covered), or of the whole level.
+// Coverage of one level (the boxes just made for it) as merged column
+// intervals [x0, x1) per row y0 + i; other rows hold none.
 struct CovMap {
   bool all = false;
-  int x0 = 0, y0 = 0, w = 0, h = 0;
-  std::vector<uint8_t> m;
-  bool at(int x, int y) const {
+  int y0 = 0;
+  std::vector<std::vector<std::pair<int, int>>> rows;
+  // [xa, xb) of in-domain row y covered
+  bool span(int y, int xa, int xb) const {
     if (all) return true;
-    x -= x0;
-    y -= y0;
-    return x >= 0 && y >= 0 && x < w && y < h && m[(size_t)y * w + x];
+    const int i = y - y0;
+    if (i < 0 || i >= (int)rows.size()) return false;
+    const auto &v = rows[i];
+    auto it = std::upper_bound(v.begin(), v.end(), std::make_pair(xa, INT32_MAX));
+    if (it == v.begin()) return false;
+    --it;
+    return it->first <= xa && it->second >= xb;
+  }
+  static CovMap of_boxes(const vlbm_box *b, size_t n) {
+    CovMap m;
+    int ya = INT32_MAX, yb = INT32_MIN;
+    for (size_t i = 0; i < n; ++i) {
+      ya = std::min(ya, b[i].j0);
+      yb = std::max(yb, b[i].j0 + b[i].ny);
+    }
+    if (!n) return m;
+    m.y0 = ya;
+    m.rows.resize(yb - ya);
+    for (size_t i = 0; i < n; ++i)
+      for (int y = b[i].j0; y < b[i].j0 + b[i].ny; ++y) m.rows[y - ya].push_back({b[i].i0, b[i].i0 + b[i].nx});
+    for (auto &v : m.rows) {
+      std::sort(v.begin(), v.end());
+      std::vector<std::pair<int, int>> out;
+      for (const auto &iv : v) {
+        if (!out.empty() && iv.first <= out.back().second)
+          out.back().second = std::max(out.back().second, iv.second);
+        else
+          out.push_back(iv);
+      }
+      v.swap(out);
+    }
+    return m;
   }
 };
 
-// Clustering for tag_and_regrid: level-l tags, dilated by a square of radius
-// `buffer` (periodic axes wrap, other axes clip), restricted to cells whose
-// four neighbours are covered at level l (neighbours outside a non-periodic
-// side exempt), covered by a tile grid of side ceil(min_box / r) level-l
-// cells; marked tiles merge greedily into rectangles, first along rows, then
-// stacking equal row runs, with sides of at most max_box level-(l+1) cells.
-// Work is per tagged cell and per reached tile, not per level cell: a tile
-// holds a dilated tag iff a tag lies within `buffer` of it, and it is free of
-// disallowed cells iff its rows widened by one column and its columns widened
-// by one row are covered.
-void cluster_level(vlbm_ctx *c, int l, const TagMap &tags, const CovMap &cov, int buffer, int min_box,
+// Clustering for tag_and_regrid, level l: `hits` (sorted) are the tiles of a
+// grid of side T = ceil(min_box / r) level-l cells that hold a cell within the
+// dilation buffer of a tag (computed on the device). A hit tile is kept when
+// it and the ring of cells around it are covered at level l (cells outside a
+// non-periodic side exempt, periodic axes wrapped), which keeps the new
+// level properly nested. Kept tiles merge greedily into rectangles: runs of
+// at most maxT tiles along a tile row, stacked while the run below is
+// identical, with sides of at most max_box level-(l+1) cells.
+void cluster_level(vlbm_ctx *c, int l, const std::vector<int32_t> &hits, const CovMap &cov, int min_box,
                    int max_box, std::vector<vlbm_box> &out) {
   const int r = c->p.r;
   const int Nx = level_nx(c, l), Ny = level_ny(c, l);
@@ -2006,105 +2039,37 @@ void cluster_level(vlbm_ctx *c, int l, const TagMap &tags, const CovMap &cov, in
   const int T = std::max(1, (min_box + r - 1) / r);
   const int maxT = std::max(1, max_box / (T * r));
   const int ntx = (Nx + T - 1) / T, nty = (Ny + T - 1) / T;
-  // tiles reached by the dilation of each tag
-  std::vector<uint8_t> hit((size_t)ntx * nty, 0);
-  std::vector<int> cols, rows;
-  auto tiles_in = [&](int a, int b, int n, bool periodic, std::vector<int> &v) {
-    v.clear();
-    if (periodic && b - a + 1 >= n) a = 0, b = n - 1, periodic = false;
-    if (!periodic) {
-      a = std::max(a, 0);
-      b = std::min(b, n - 1);
-      for (int t = a / T; a <= b && t <= b / T; ++t) v.push_back(t);
-      return;
-    }
-    const int am = ((a % n) + n) % n, bm = ((b % n) + n) % n;
-    if (am <= bm) {
-      for (int t = am / T; t <= bm / T; ++t) v.push_back(t);
-    } else {  // wraps: [am, n) and [0, bm]
-      for (int t = 0; t <= bm / T; ++t) v.push_back(t);
-      for (int t = am / T; t <= (n - 1) / T; ++t)
-        if (v.empty() || t > v.back()) v.push_back(t);
-    }
-  };
-  // per row of the tag map, each run of tagged cells reaches one interval of
-  // tile columns on the tile rows within `buffer` of the row
-  for (size_t sr = 0; sr < tags.yrow.size(); ++sr) {
-    const uint8_t *row = &tags.t[sr * tags.w];
-    const int y = tags.y0 + tags.yrow[sr];
-    bool any = false;
-    int fx = 0;
-    while (fx < tags.w) {
-      if (fx + 8 <= tags.w) {  // skip untagged words
-        uint64_t w;
-        memcpy(&w, row + fx, 8);
-        if (!w) {
-          fx += 8;
-          continue;
-        }
-      }
-      if (!row[fx]) {
-        ++fx;
-        continue;
-      }
-      const int xa = fx;
-      while (fx < tags.w && row[fx]) ++fx;
-      if (!any) {
-        tiles_in(y - buffer, y + buffer, Ny, py, rows);
-        any = true;
-      }
-      tiles_in(tags.x0 + xa - buffer, tags.x0 + fx - 1 + buffer, Nx, px, cols);
-      for (int ty : rows)
-        for (int tx : cols) hit[(size_t)ty * ntx + tx] = 1;
-    }
-  }
-  // reached tiles that hold no disallowed cell
-  auto covered_at = [&](int x, int y) {  // true outside a non-periodic side
-    if (x < 0 || x >= Nx) {
-      if (!px) return true;
-      x = (x + Nx) % Nx;
-    }
+  // [xa, xb) of row y covered, y possibly outside the domain (wrapped on a
+  // periodic axis, exempt on another)
+  auto row_ok = [&](int y, int xa, int xb) {
     if (y < 0 || y >= Ny) {
       if (!py) return true;
       y = (y + Ny) % Ny;
     }
-    return cov.at(x, y);
+    return cov.span(y, xa, xb);
   };
-  std::vector<uint8_t> mark((size_t)ntx * nty, 0);
-  for (int ty = 0; ty < nty; ++ty)
-    for (int tx = 0; tx < ntx; ++tx) {
-      if (!hit[(size_t)ty * ntx + tx]) continue;
-      const int x0 = tx * T, y0 = ty * T, x1 = std::min(Nx, x0 + T), y1 = std::min(Ny, y0 + T);
-      bool ok = true;
-      for (int y = y0; ok && y < y1; ++y) {
-        for (int x = x0; x < x1; ++x)
-          if (!cov.at(x, y)) {
-            ok = false;
-            break;
-          }
-        ok = ok && covered_at(x0 - 1, y) && covered_at(x1, y);
-      }
-      for (int x = x0; ok && x < x1; ++x) ok = covered_at(x, y0 - 1) && covered_at(x, y1);
-      mark[(size_t)ty * ntx + tx] = ok;
+  auto cell_ok = [&](int x, int y) {
+    if (x < 0 || x >= Nx) {
+      if (!px) return true;
+      x = (x + Nx) % Nx;
     }
-  // greedy merge: row runs of at most maxT tiles, stacked while identical
+    return row_ok(y, x, x + 1);
+  };
+  auto allowed = [&](int tx, int ty) {
+    const int x0 = tx * T, y0 = ty * T, x1 = std::min(Nx, x0 + T), y1 = std::min(Ny, y0 + T);
+    for (int y = y0; y < y1; ++y)
+      if (!row_ok(y, x0, x1) || !cell_ok(x0 - 1, y) || !cell_ok(x1, y)) return false;
+    return row_ok(y0 - 1, x0, x1) && row_ok(y1, x0, x1);
+  };
   struct Run { int a, b, y0, h; };
   std::vector<Run> open, next;
   auto emit = [&](const Run &u) {
     int x0 = u.a * T, x1 = std::min(Nx, u.b * T), y0 = u.y0 * T, y1 = std::min(Ny, (u.y0 + u.h) * T);
     out.push_back({l + 1, x0 * r, y0 * r, (x1 - x0) * r, (y1 - y0) * r});
   };
-  for (int ty = 0; ty <= nty; ++ty) {
-    next.clear();
-    if (ty < nty) {
-      int tx2 = 0;
-      while (tx2 < ntx) {
-        if (!mark[(size_t)ty * ntx + tx2]) { ++tx2; continue; }
-        int a = tx2;
-        while (tx2 < ntx && mark[(size_t)ty * ntx + tx2] && tx2 - a < maxT) ++tx2;
-        next.push_back({a, tx2, ty, 1});
-      }
-    }
+  // one tile row: its runs of kept tiles; then the open rectangles continue
+  // (identical run below, room to grow) or are emitted
+  auto close_row = [&](int ty) {
     for (auto &o : open) {
       bool cont = false;
       for (auto &nx2 : next)
@@ -2116,10 +2081,35 @@ void cluster_level(vlbm_ctx *c, int l, const TagMap &tags, const CovMap &cov, in
         }
       if (!cont) emit(o);
     }
-    open = next;
+    open.swap(next);
+    next.clear();
+    (void)ty;
+  };
+  size_t i = 0;
+  int last_ty = -2;
+  while (i < hits.size()) {
+    const int ty = (int)(hits[i] / ntx);
+    if (ty != last_ty + 1 && !open.empty()) close_row(last_ty + 1);  // an empty tile row between
+    // kept tiles of this row, in order, cut into runs of at most maxT
+    int run_a = -1, run_b = -1;
+    for (; i < hits.size() && hits[i] / ntx == ty; ++i) {
+      const int tx = (int)(hits[i] % ntx);
+      if (!allowed(tx, ty)) continue;
+      if (run_a >= 0 && tx == run_b && run_b - run_a < maxT) {
+        run_b = tx + 1;
+        continue;
+      }
+      if (run_a >= 0) next.push_back({run_a, run_b, ty, 1});
+      run_a = tx;
+      run_b = tx + 1;
+    }
+    if (run_a >= 0) next.push_back({run_a, run_b, ty, 1});
+    close_row(ty);
+    last_ty = ty;
   }
+  next.clear();
+  close_row(nty);  // emits whatever is still open
 }
-
 
 int level_nx(const vlbm_ctx *c, int l) {
   long s = 1;
@@ -2148,75 +2138,6 @@ vlbm_status tag_frame(vlbm_ctx *c, int l, double thr, std::vector<uint8_t> &ft) 
   c->mem.release(d);
   if (e != hipSuccess) return fail(VLBM_EDEVICE, "tag: %s", hipGetErrorString(e));
   return VLBM_OK;
-}
-
-// Boxes of a new hierarchy from per-level tags (levels 0..max_levels-1; a
-// level without tags has an empty map). A tagged finer cell tags its parent,
-// so refined features keep their levels; then each level is clustered inside
-// the coverage of the boxes just made for it.
-void cluster_hierarchy(vlbm_ctx *c, std::vector<TagMap> &tags, int buffer, int min_box, int max_box,
-                       std::vector<vlbm_box> &boxes) {
-  const int r = c->p.r, ML = c->p.max_levels;
-  for (int l = ML - 1; l >= 1; --l) {
-    const TagMap &F = tags[l];
-    TagMap &P = tags[l - 1];
-    if (F.t.empty() || P.t.empty()) continue;
-    // per row, each run of tagged fine cells tags the run of its parents
-    for (size_t sr = 0; sr < F.yrow.size(); ++sr) {
-      const uint8_t *row = &F.t[sr * F.w];
-      const int fyl = F.y0 + F.yrow[sr];
-      if (fyl < 0) continue;  // a ghost row below the domain holds no tag
-      const int py = fyl / r - P.y0;
-      if (py < 0 || py >= P.h || P.srow[py] < 0) continue;
-      const size_t prow = (size_t)P.srow[py] * P.w;
-      int fx = 0;
-      while (fx < F.w) {
-        if (fx + 8 <= F.w) {  // skip untagged words
-          uint64_t w;
-          memcpy(&w, row + fx, 8);
-          if (!w) {
-            fx += 8;
-            continue;
-          }
-        }
-        if (!row[fx]) {
-          ++fx;
-          continue;
-        }
-        const int xa = fx;
-        while (fx < F.w && row[fx]) ++fx;
-        const int pa = std::max((F.x0 + xa) / r - P.x0, 0);
-        const int pb = std::min((F.x0 + fx - 1) / r - P.x0, P.w - 1);
-        if (pa <= pb) memset(&P.t[prow + pa], 1, pb - pa + 1);
-      }
-    }
-  }
-  CovMap cov;
-  cov.all = true;
-  for (int l = 0; l + 1 < ML; ++l) {
-    if (tags[l].t.empty()) break;
-    size_t before = boxes.size();
-    cluster_level(c, l, tags[l], cov, buffer, min_box, max_box, boxes);
-    if (boxes.size() == before || l + 2 >= ML) break;
-    // coverage of level l+1 over the bounding box of its new boxes
-    CovMap nc;
-    int bx0 = INT32_MAX, by0 = INT32_MAX, bx1 = INT32_MIN, by1 = INT32_MIN;
-    for (size_t b = before; b < boxes.size(); ++b) {
-      bx0 = std::min(bx0, boxes[b].i0);
-      by0 = std::min(by0, boxes[b].j0);
-      bx1 = std::max(bx1, boxes[b].i0 + boxes[b].nx);
-      by1 = std::max(by1, boxes[b].j0 + boxes[b].ny);
-    }
-    nc.x0 = bx0;
-    nc.y0 = by0;
-    nc.w = bx1 - bx0;
-    nc.h = by1 - by0;
-    nc.m.assign((size_t)nc.w * nc.h, 0);
-    for (size_t b = before; b < boxes.size(); ++b)
-      for (int y = boxes[b].j0; y < boxes[b].j0 + boxes[b].ny; ++y)
-        memset(&nc.m[(size_t)(y - by0) * nc.w + boxes[b].i0 - bx0], 1, boxes[b].nx);
-    cov = std::move(nc);
-  }
 }
 
 }  // namespace
@@ -2285,6 +2206,7 @@ void vlbm_destroy(vlbm_ctx *c) {
   c->mem.release(c->dqmax);
   c->mem.release(c->ddyn);
   c->mem.release(c->dcmax);
+  for (auto &e : c->tag_scratch) c->mem.release(e.first);
   c->mem.release_all();
   delete c;
 }
@@ -2557,6 +2479,16 @@ vlbm_status vlbm_get_boxes(vlbm_ctx *c, vlbm_box *boxes, int cap, int *nboxes) {
 
 vlbm_status vlbm_regrid(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
   if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "no hierarchy installed");
+  // The same boxes again: nothing is merged or split and every interface is
+  // kept, so the hierarchy, its lists and both time levels stay as they are.
+  if (nboxes >= 0 && (size_t)nboxes == c->boxes.size() && (nboxes == 0 || boxes)) {
+    bool same = true;
+    for (int b = 0; b < nboxes && same; ++b) {
+      const vlbm_box &u = boxes[b], &v = c->boxes[b];
+      same = u.level == v.level && u.i0 == v.i0 && u.j0 == v.j0 && u.nx == v.nx && u.ny == v.ny;
+    }
+    if (same) return VLBM_OK;
+  }
   return regrid_impl(c, boxes, nboxes);
 }
 
@@ -2566,22 +2498,116 @@ vlbm_status vlbm_tag_and_regrid(vlbm_ctx *c, double thr, int buffer, int min_box
   PhaseTimer tm("tag_and_regrid");
   const int ML = c->p.max_levels;
   if (ML < 2) return VLBM_OK;
-  std::vector<TagMap> tags(ML);
-  for (int l = 0; l < c->nlev; ++l) {
-    const Level &L = c->lv[l];
-    TagMap &T = tags[l];
-    T.x0 = L.fx0;
-    T.y0 = L.fy0;
-    T.w = L.fw;
-    T.h = L.fh;
-    T.srow = L.srow;
-    T.yrow = L.yrow;
-    vlbm_status st = tag_frame(c, l, thr, T.t);
-    if (st) return st;
+  const int r = c->p.r;
+  const int nclu = std::min(c->nlev, ML - 1);  // levels whose tags make the next level's boxes
+  // 1. tags of every present level on the device (indexed like each level's
+  //    status); a tagged cell also tags its parent, finest level first, so
+  //    refined features keep their levels. Scratch: slots of the context's
+  //    tag scratch (kept between calls).
+  size_t next_slot = 0;
+  auto dalloc = [&](size_t n) -> void * { return c->scratch_slot(next_slot++, n); };
+  auto release = [&]() {};
+  if (getenv("VLBM_TIMING")) {  // separate the regrid's own time from the steps queued before it
+    HIPCHK(hipStreamSynchronize(c->stream));
+    tm.mark("queued steps");
   }
-  tm.mark("tags");
+  std::vector<uint8_t *> dtag(c->nlev, nullptr);
+  hipError_t e = hipSuccess;
+  for (int l = 0; l < c->nlev && e == hipSuccess; ++l) {
+    const Level &L = c->lv[l];
+    dtag[l] = static_cast<uint8_t *>(dalloc((size_t)L.fw * L.nrows));
+    if (!dtag[l]) {
+      release();
+      return fail(VLBM_ENOMEM, "tag buffer");
+    }
+    e = launch_tag(L.buf[L.cur()], L.dstatus, L.dsrow, L.dyrow, L.plane, L.pitch, L.xoff, L.fx0, L.fy0, L.fw,
+                   L.fh, L.nrows, L.Nx, L.Ny, c->perx(), c->pery(), c->fp32, thr, dtag[l], c->stream);
+  }
+  for (int l = c->nlev - 1; l >= 1 && e == hipSuccess; --l) {
+    const Level &F = c->lv[l], &P = c->lv[l - 1];
+    e = launch_tag_parents(dtag[l], F.dyrow, F.fx0, F.fy0, F.fw, F.nrows, dtag[l - 1], P.dsrow, P.fx0, P.fy0,
+                           P.fw, P.fh, r, c->stream);
+  }
+  // 2. per clustered level, the tiles within `buffer` of a tag, listed on the
+  //    device (few tiles of a large level are hit); only tile rows within
+  //    `buffer` of a stored frame row can hold one
+  const int T = std::max(1, (min_box + r - 1) / r);
+  std::vector<int32_t *> dlist(nclu, nullptr);
+  std::vector<int> cap(nclu, 0);
+  int *dcount = static_cast<int *>(dalloc(sizeof(int) * std::max(nclu, 1)));
+  if (!dcount) {
+    release();
+    return fail(VLBM_ENOMEM, "tile lists");
+  }
+  if (e == hipSuccess) e = hipMemsetAsync(dcount, 0, sizeof(int) * std::max(nclu, 1), c->stream);
+  std::vector<std::vector<int32_t>> trows(nclu);
+  for (int l = 0; l < nclu && e == hipSuccess; ++l) {
+    const Level &L = c->lv[l];
+    const int ntx = (L.Nx + T - 1) / T, nty = (L.Ny + T - 1) / T;
+    std::vector<uint8_t> want(nty, 0);
+    for (const auto &run : L.runs) {
+      const int ya = std::max(0, run.first) - buffer, yb = std::min(L.Ny, run.second) + buffer;
+      if (c->pery() && yb - ya >= L.Ny) {
+        std::fill(want.begin(), want.end(), 1);
+        break;
+      }
+      for (int y = ya; y < yb; ++y) {
+        int wy = y;
+        if (wy < 0 || wy >= L.Ny) {
+          if (!c->pery()) continue;
+          wy = (wy + L.Ny) % L.Ny;
+        }
+        want[wy / T] = 1;
+      }
+    }
+    for (int ty = 0; ty < nty; ++ty)
+      if (want[ty]) trows[l].push_back(ty);
+    const int64_t ntiles = (int64_t)ntx * (int64_t)trows[l].size();
+    if (ntiles >= (int64_t(1) << 31)) {
+      release();
+      return fail(VLBM_EINVAL, "clustering grid of level %d too large", l);
+    }
+    cap[l] = (int)ntiles;
+    dlist[l] = static_cast<int32_t *>(dalloc(sizeof(int32_t) * (size_t)std::max<int64_t>(ntiles, 1)));
+    int32_t *dtrows = static_cast<int32_t *>(dalloc(sizeof(int32_t) * std::max<size_t>(trows[l].size(), 1)));
+    if (!dlist[l] || !dtrows) {
+      release();
+      return fail(VLBM_ENOMEM, "tile lists");
+    }
+    if (!trows[l].empty())
+      e = hipMemcpyAsync(dtrows, trows[l].data(), sizeof(int32_t) * trows[l].size(), hipMemcpyHostToDevice,
+                         c->stream);
+    if (e == hipSuccess)
+      e = launch_tile_hits(dtag[l], L.dsrow, L.fx0, L.fy0, L.fw, L.fh, L.Nx, L.Ny, c->perx(), c->pery(), T,
+                           buffer, ntx, dtrows, (int)trows[l].size(), dlist[l], cap[l], dcount + l, c->stream);
+  }
+  std::vector<int> count(std::max(nclu, 1), 0);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(count.data(), dcount, sizeof(int) * std::max(nclu, 1), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  std::vector<std::vector<int32_t>> hits(nclu);
+  for (int l = 0; l < nclu && e == hipSuccess; ++l) {
+    hits[l].resize(std::min(count[l], cap[l]));
+    if (!hits[l].empty())
+      e = hipMemcpyAsync(hits[l].data(), dlist[l], sizeof(int32_t) * hits[l].size(), hipMemcpyDeviceToHost,
+                         c->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  release();
+  if (e != hipSuccess) return fail(VLBM_EDEVICE, "tag and cluster: %s", hipGetErrorString(e));
+  tm.mark("tags+tiles");
+  // 3. boxes, level by level: each level's kept tiles must lie in the
+  //    coverage of the boxes just made for it
   std::vector<vlbm_box> boxes;
-  cluster_hierarchy(c, tags, buffer, min_box, max_box, boxes);
+  CovMap cov;
+  cov.all = true;
+  for (int l = 0; l < nclu; ++l) {
+    const size_t before = boxes.size();
+    std::sort(hits[l].begin(), hits[l].end());
+    cluster_level(c, l, hits[l], cov, min_box, max_box, boxes);
+    if (boxes.size() == before || l + 2 >= ML) break;
+    cov = CovMap::of_boxes(boxes.data() + before, boxes.size() - before);
+  }
   tm.mark("cluster");
   return vlbm_regrid(c, boxes.data(), (int)boxes.size());
 }

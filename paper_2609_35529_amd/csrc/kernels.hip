@@ -1365,6 +1365,102 @@ hipError_t launch_tag(const void *buf, const uint8_t *status, const int32_t *sro
   return hipGetLastError();
 }
 
+// Refined features keep their levels: every tagged cell of a level-(l+1)
+// frame tags its parent in the level-l frame (one thread per stored fine frame
+// cell; several children write the same 1, which is benign).
+__global__ void tag_parents_kernel(const uint8_t *__restrict__ ftags, const int32_t *__restrict__ fyrow,
+                                   int ffx0, int ffy0, int ffw, int fnrows, uint8_t *__restrict__ ptags,
+                                   const int32_t *__restrict__ psrow, int pfx0, int pfy0, int pfw, int pfh,
+                                   int r) {
+  const int64_t n = (int64_t)ffw * fnrows;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    if (!ftags[c]) continue;
+    const int sr = (int)(c / ffw), fx = (int)(c - (int64_t)sr * ffw);
+    const int x = ffx0 + fx, y = ffy0 + fyrow[sr];  // a tagged cell is active, hence in the domain
+    const int px = x / r - pfx0, py = y / r - pfy0;
+    if (px < 0 || px >= pfw || py < 0 || py >= pfh) continue;
+    const int ps = psrow[py];
+    if (ps >= 0) ptags[(int64_t)ps * pfw + px] = 1;
+  }
+}
+
+hipError_t launch_tag_parents(const uint8_t *ftags, const int32_t *fyrow, int ffx0, int ffy0, int ffw,
+                              int fnrows, uint8_t *ptags, const int32_t *psrow, int pfx0, int pfy0, int pfw,
+                              int pfh, int r, hipStream_t s) {
+  const int64_t n = (int64_t)ffw * fnrows;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(tag_parents_kernel, grid_for(n), dim3(256), 0, s, ftags, fyrow, ffx0, ffy0, ffw, fnrows,
+                     ptags, psrow, pfx0, pfy0, pfw, pfh, r);
+  return hipGetLastError();
+}
+
+// Tiles of the clustering grid (side T level cells, ntx tiles per tile row)
+// that hold a cell within `buf` cells of a tag (square dilation, periodic axes
+// wrapped, other axes clipped). One thread per tile of the listed tile rows
+// scans the tile's window [x0 - buf, x1 + buf) x [y0 - buf, y1 + buf) of the
+// level's tags (fw bytes per stored frame row); the hits of a wavefront are
+// appended with one atomic add.
+__global__ void tile_hits_kernel(const uint8_t *__restrict__ tags, const int32_t *__restrict__ srow, int fx0,
+                                 int fy0, int fw, int fh, int Nx, int Ny, int perx, int pery, int T, int buf,
+                                 int ntx, const int32_t *__restrict__ trows, int ntrows, int32_t *list, int cap,
+                                 int *count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool hit = false;
+  int32_t t = 0;
+  if (i < (int64_t)ntrows * ntx) {
+    const int ty = trows[i / ntx], tx = (int)(i % ntx);
+    t = ty * ntx + tx;
+    const int xa = tx * T - buf, xb = min(Nx, tx * T + T) + buf;
+    const int ya = ty * T - buf, yb = min(Ny, ty * T + T) + buf;
+    for (int y = ya; y < yb && !hit; ++y) {
+      int wy = y;
+      if (wy < 0 || wy >= Ny) {
+        if (!pery) continue;
+        wy = wy < 0 ? wy + Ny : wy - Ny;
+      }
+      const int fr = wy - fy0;
+      if (fr < 0 || fr >= fh) continue;
+      const int sr = srow[fr];
+      if (sr < 0) continue;
+      const uint8_t *row = tags + (int64_t)sr * fw;
+      for (int x = xa; x < xb; ++x) {
+        int wx = x;
+        if (wx < 0 || wx >= Nx) {
+          if (!perx) continue;
+          wx = wx < 0 ? wx + Nx : wx - Nx;
+        }
+        const int fx = wx - fx0;
+        if (fx >= 0 && fx < fw && row[fx]) {
+          hit = true;
+          break;
+        }
+      }
+    }
+  }
+  const unsigned long long m = __ballot(hit);
+  if (!m) return;
+  const int lane = (int)(threadIdx.x & 63);
+  const int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(count, __popcll(m));
+  base = __shfl(base, leader);
+  if (hit) {
+    const int at = base + __popcll(m & ((1ull << lane) - 1ull));
+    if (at < cap) list[at] = t;
+  }
+}
+
+hipError_t launch_tile_hits(const uint8_t *tags, const int32_t *srow, int fx0, int fy0, int fw, int fh, int Nx,
+                            int Ny, int perx, int pery, int T, int buf, int ntx, const int32_t *trows, int ntrows,
+                            int32_t *list, int cap, int *count, hipStream_t s) {
+  const int64_t n = (int64_t)ntrows * ntx;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(tile_hits_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tags, srow, fx0, fy0,
+                     fw, fh, Nx, Ny, perx, pery, T, buf, ntx, trows, ntrows, list, cap, count);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Regrid: merge (eq. amr-merge) and minmod split (eqs. amr-slope, amr-split)
 // One thread per (operation, population plane).

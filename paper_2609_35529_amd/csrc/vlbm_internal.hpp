@@ -247,6 +247,18 @@ hipError_t launch_tag(const void *buf, const uint8_t *status, const int32_t *sro
                       int Nx, int Ny, int perx, int pery, int fp32, double thr, uint8_t *tags,
                       hipStream_t s);
 
+// Clustering on the device. tag_parents: every tagged cell of a level-(l+1)
+// frame (fw per stored row) tags its parent in the level-l tags. tile_hits:
+// of the tile rows listed in trows (tiles of side T, ntx per tile row), the
+// tiles within `buf` cells of a tag, appended to list[0 .. *count) in no
+// particular order (at most cap entries stored).
+hipError_t launch_tag_parents(const uint8_t *ftags, const int32_t *fyrow, int ffx0, int ffy0, int ffw,
+                              int fnrows, uint8_t *ptags, const int32_t *psrow, int pfx0, int pfy0, int pfw,
+                              int pfh, int r, hipStream_t s);
+hipError_t launch_tile_hits(const uint8_t *tags, const int32_t *srow, int fx0, int fy0, int fw, int fh, int Nx,
+                            int Ny, int perx, int pery, int T, int buf, int ntx, const int32_t *trows, int ntrows,
+                            int32_t *list, int cap, int *count, hipStream_t s);
+
 // Regrid kernels: a list of cell operations on level frames.
 struct RegridOp {          // one coarse cell (merge) or one parent cell (split)
   int32_t dst;             // element offset of the destination (merge: parent cell;

@@ -375,12 +375,15 @@ def prolong_piecewise(U, r):
 
 # --------------------------------------------------- Kelvin-Helmholtz shear layer
 def kelvin_helmholtz(n0=4096, seed=0, nlev=4, r=2, beta=0.8, kappa=1.5, steps=5000,
-                     band=0.25):
+                     band=0.25, dynamic=False):
     """Shear layer on [0,1]^2, periodic: |y - 0.5| < band has rho = 2, u = +0.5,
     outside rho = 1, u = -0.5; p = 2.5, gamma = 1.4. Perturbation drawn as two
     arrays in order: U1 for v (v = 0.01 sin(4 pi x) + 0.01 (U1 - 1/2)), then U2
     for u (u += 0.01 (U2 - 1/2)). Levels refine nested bands around the two
-    interfaces at y = 0.25 and 0.75."""
+    interfaces at y = 0.25 and 0.75; with dynamic=True there are no static
+    boxes and no finer-level states: the hierarchy comes from tagging and
+    clustering, and splitting fills the finer levels (the 4096^2 problem's
+    finest level alone would be a 32768^2 array on the host)."""
     gamma = 1.4
     dx0 = 1.0 / n0
     rng = np.random.default_rng(seed)
@@ -396,6 +399,9 @@ def kelvin_helmholtz(n0=4096, seed=0, nlev=4, r=2, beta=0.8, kappa=1.5, steps=50
 
     X, Y = level_grid(n0, n0, dx0, r, 0)
     U0 = ic0(X, Y)
+    if dynamic:
+        return Case("kelvin_helmholtz", n0, n0, dx0, r, nlev, gamma, link_speed(U0, gamma, kappa), beta,
+                    (PERIODIC,) * 4, [], [U0] + [None] * (nlev - 1), steps)
     states = [U0]
     for l in range(1, nlev):
         states.append(prolong_piecewise(states[-1], r))
