@@ -2,18 +2,22 @@
 """Throughput of the VLBM refinement hot path on one MI355X.
 
 One step = one coarse step of the whole hot path: the recursive sub-cycle of
-every level (fused ghost-fill / reflux-capture / stream / collide launches).
-Default workload: the four-quadrant Riemann problem, 512 x 512 coarse with a
-static r = 2 patch over the central 256 x 256 coarse cells (512 x 512 fine),
-FP64, seed 0, inputs resident in HBM before the timed region.
+every level (fused ghost-fill / reflux-capture / stream / collide launches),
+and for a dynamic workload a tag-and-regrid every 5 coarse steps (inside the
+timed region). Default workload: the Kelvin-Helmholtz shear layer, 4096 x 4096
+coarse, periodic, three refinement levels at r = 2 that track the two layers
+by tagging, clustering, merge and split; FP64, seed 0, inputs resident in HBM
+before the timed region.
 
 metric: fine-equivalent cell updates per second = (nx0 r^L)(ny0 r^L) r^L per
 coarse step (the updates a uniform finest-level grid would need), over the
 timed steps. The JSON line also carries the roofline of the dominant kernel
 (the level and launch form with the most kernel time; algorithmic bytes: 16
-populations in + 16 out per active cell per launch, over the launch's own
-duration from per-kernel events of the timed region) and the oracle timed on
-the host cores on a bounded sample of the same workload.
+populations in + 16 out per cell update, two updates per cell for a fused
+two-sub-step launch, over the launch's own duration from per-kernel events),
+the conservation defect per coarse step, and the oracle timed on the host
+cores on a bounded sample (for the 4096^2 problem: its largest down-scale
+whose dense oracle arrays fit in 8 GB).
 """
 import argparse
 import json
@@ -238,6 +242,62 @@ def cpu_baseline(case, budget_s=15.0, boxes=None, mem_cap=8e9, sensor=None, adap
                       f"one thread", "host": host_cpu()}
 
 
+def cpu_baseline_kh_downscale(args, prec, stream, n0=256):
+    """The oracle, single-threaded, on the Kelvin-Helmholtz problem down-scaled
+    to n0^2 coarse cells with the same three dynamic levels: the largest
+    down-scale whose dense oracle arrays (every level over the whole domain,
+    the finest one 2048^2 here) fit in 8 GB. The hierarchy comes from the GPU
+    solver's tag-and-regrid on the same down-scale (regrid every
+    args.regrid_every coarse steps), which the oracle follows box for box; the
+    oracle's own steps are timed. The same run gives the GPU's difference to
+    the oracle at the bench's precision (FP64: largest relative population
+    difference; FP32 forms: the smooth-cell error of the FP32 tolerance)."""
+    import numpy as np
+    from paper_2609_35529_amd import vlbm, workloads as wl
+    from tests import exact
+    from tests.parity import fp32_error
+    case = wl.kelvin_helmholtz(n0=n0, seed=0, nlev=4, steps=0, dynamic=True)
+    thr, buf = DYNAMIC["kh4096"]["threshold"], args.amr_buffer
+    mn, mx = args.amr_min_box, args.amr_max_box or DYNAMIC["kh4096"]["max_box"]
+    g = vlbm.Solver.from_case(case, precision=prec, stream=stream)
+    g.set_tuning(*DYNAMIC["kh4096"]["tuning"])
+    for _ in range(case.nlev - 1):
+        g.tag_and_regrid(thr, buffer=buf, min_box=mn, max_box=mx)
+    o = exact.run_oracle(case, steps=0)
+    o.regrid(g.boxes())
+    el, n = 0.0, 0
+    while el < args.cpu_budget or n < 2 * args.regrid_every:
+        k = args.regrid_every
+        g.advance(k)
+        t0 = time.perf_counter()
+        o.advance(k)
+        el += time.perf_counter() - t0
+        n += k
+        g.tag_and_regrid(thr, buffer=buf, min_box=mn, max_box=mx)
+        o.regrid(g.boxes())
+    upd = sum(o.active_mask(l).sum() * case.r ** l for l in range(case.nlev))
+    err = {}
+    if prec == vlbm.FP64:
+        worst = 0.0
+        for l in range(case.nlev):
+            Fo, Fg = o.get_pop(l), g.get_populations(l)
+            m = ~np.isnan(Fo)
+            if m.any():
+                worst = max(worst, float(np.max(np.abs(Fg[m] - Fo[m]) / np.maximum(np.abs(Fo[m]), 1e-3))))
+        err = {"gpu_vs_oracle_max_rel": worst, "gpu_vs_oracle_bitwise": bool(worst == 0.0)}
+    else:
+        e = fp32_error(o, g, case)
+        err = {"gpu_vs_oracle_smooth_rel_err": float(e.max()), "per_component": e.max(axis=0).tolist()}
+    g.close()
+    return {"value": case.fine_equivalent_per_coarse_step() * n / el, "unit": "fine-equiv cell updates/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"kelvin_helmholtz down-scaled to {n0}^2 coarse, 3 dynamic levels (finest {n0 * 8}^2), "
+                      f"the largest down-scale whose dense oracle arrays fit in 8 GB: {n} coarse steps "
+                      f"({el:.1f} s) with a regrid every {args.regrid_every} on the GPU run's boxes, FP64, "
+                      "one thread; the value is the down-scale's fine-equivalent rate",
+            "actual_updates_per_s": float(upd) * n / el, "host": host_cpu(), **err}
+
+
 def copy_probe(gib=2.0, reps=20):
     """Bandwidth of a plain device-to-device copy of known size (the practical
     HBM ceiling, and the reference for scaling hardware byte counters)."""
@@ -301,7 +361,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="quadrant512")
+    ap.add_argument("--workload", default="kh4096")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "fp32s"],
                     help="fp32s: FP32 storage, relaxation evaluated in FP64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -309,6 +369,7 @@ def main():
     ap.add_argument("--amr-threshold", type=float, default=None,
                     help="density-gradient tag threshold (default: the workload's)")
     ap.add_argument("--amr-buffer", type=int, default=4)
+    ap.add_argument("--regrid-every", type=int, default=5, help="coarse steps between tag-and-regrids")
     ap.add_argument("--amr-min-box", type=int, default=16)
     ap.add_argument("--amr-max-box", type=int, default=0,
                     help="largest box side in fine cells (0: the workload's default)")
@@ -381,7 +442,7 @@ def main():
         args.amr_max_box = DYNAMIC[args.workload]["max_box"]
     if dynamic and args.amr_threshold is None:
         args.amr_threshold = DYNAMIC[args.workload]["threshold"]
-    regrid_every = 5
+    regrid_every = args.regrid_every
     amr = {"regrids": 0, "boxes": [], "regrid_s": 0.0, "updates": 0}
 
     def run(n):
@@ -439,6 +500,17 @@ def main():
     solver.set_profiling(False)
     T1, L1 = solver.totals()
     healthy = solver.check_health()
+    # conservation defect coarse step by coarse step (regrids included):
+    # ((T - T0) - (L - L0)) / max|T0| per component
+    drift_steps = 10
+    Tp, Lp = solver.totals()
+    drift_series = []
+    for _ in range(drift_steps):
+        run(1)
+        Tn, Ln = solver.totals()
+        sc = max(abs(x) for x in Tp)
+        drift_series.append([float(((Tn[k] - Tp[k]) - (Ln[k] - Lp[k])) / sc) for k in range(4)])
+        Tp, Lp = Tn, Ln
 
     fe_step = case.fine_equivalent_per_coarse_step()
     value = fe_step * args.steps / wall
@@ -454,15 +526,17 @@ def main():
         # (32 B), writes W (32 B) and beta (8 B) and reads the mask (1 B)
         nl = nl + (1 if case.nlev == 1 or case.r == 1 else 0)
         bytes_per_update += 73
-    # dominant kernel: the (level, launch form) with the largest kernel time;
-    # algorithmic bytes of one launch: 16 populations read and 16 written per
-    # active cell it advances (a fused launch keeps the finest level's
-    # intermediate time level on chip, so it moves the same bytes for two
-    # sub-steps)
+    # dominant kernel: the (level, launch form) with the largest kernel time.
+    # Algorithmic bytes of one launch: 16 populations read and 16 written per
+    # cell update, and a fused launch makes two updates per cell (both
+    # sub-steps). What a fused launch must move is half of that (the
+    # intermediate time level stays on chip): reported as blocked_bytes.
     dom = max(ktimes, key=lambda k: ktimes[k][0])
     dom_ms, dom_calls, dom_cells = ktimes[dom]
     avg_launch_s = dom_ms / 1e3 / dom_calls
-    bytes_per_launch = dom_cells / dom_calls * bytes_per_update
+    updates_per_launch = dom_cells / dom_calls * (2 if dom[1] else 1)
+    bytes_per_launch = updates_per_launch * bytes_per_update
+    blocked_bytes = dom_cells / dom_calls * bytes_per_update
     achieved = bytes_per_launch / avg_launch_s / 1e9
     kernel_name = "fused_kernel" if dom[1] else "step_kernel"
     traffic = None
@@ -476,7 +550,7 @@ def main():
     # the whole path: algorithmic bytes of every step launch of a coarse step
     # over the timed wall time per coarse step (launches of different levels
     # may overlap on the chip, so this is not a sum of per-launch rates)
-    path_bytes = sum(v[2] for v in ktimes.values()) / prof_steps * bytes_per_update
+    path_bytes = sum(v[2] * (2 if k[1] else 1) for k, v in ktimes.items()) / prof_steps * bytes_per_update
     path_gbs = path_bytes / (wall / args.steps) / 1e9
 
     out = {
@@ -504,6 +578,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel_name, "level": dom[0], "bytes_per_launch": bytes_per_launch,
+                     "updates_per_launch": updates_per_launch, "bytes_per_update": bytes_per_update,
+                     "blocked_bytes_per_launch": blocked_bytes,
                      "avg_launch_us": avg_launch_s * 1e6, "launches": dom_calls,
                      "kernel_share": dom_ms / sum(v[0] for v in ktimes.values()),
                      "timing": f"per-kernel events over {prof_steps} further coarse steps "
@@ -519,6 +595,8 @@ def main():
                 if dynamic and amr_timed["boxes"] else None),
         "gpu_event_ms": gpu_ms,
         "conservation_drift_rel": drift,
+        "drift_per_step": {"steps": drift_steps, "max_abs": max(abs(x) for d in drift_series for x in d),
+                           "series": drift_series},
         "healthy": healthy,
     }
     if not args.no_serve:
@@ -527,9 +605,12 @@ def main():
                                         policy=args.serve_policy)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(build_case(args.workload, 10 ** 6), args.cpu_budget,
-                                           boxes=timed_boxes if dynamic else None, sensor=sensor,
-                                           adaptive_dt=args.adaptive_dt)
+        if args.workload == "kh4096":
+            out["cpu_baseline"] = cpu_baseline_kh_downscale(args, prec, stream)
+        else:
+            out["cpu_baseline"] = cpu_baseline(build_case(args.workload, 10 ** 6), args.cpu_budget,
+                                               boxes=timed_boxes if dynamic else None, sensor=sensor,
+                                               adaptive_dt=args.adaptive_dt)
     print(json.dumps(out))
 
 
