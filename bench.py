@@ -31,14 +31,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 # HBM traffic per launch of the dominant kernel of the default workload
-# (quadrant512, FP64, fused sub-steps with XCD-contiguous order: the fused
-# launch of the fine level), from rocprofv3 FETCH_SIZE x 2.000 and WRITE_SIZE
-# x 1.000 (scales measured on a plain 2 GiB copy); valid only for the kernel
-# source it was measured on. The fused tile shape does not depend on
-# tile_cells, so any tile_cells matches.
-MEASURED_TRAFFIC = {"kernel_sha256_16": "6cf11abdac8d69f4", "workload": "quadrant512",
-                    "precision": "fp64", "tile_cells": None, "flags": 20, "kernel": "fused_kernel",
-                    "bytes_per_launch": 75366669.0}
+# (kh4096, FP64, 512-cell tiles, flags 17: the level-0 step launch, 16,646,144
+# cells), from rocprofv3 FETCH_SIZE x 2.000 and WRITE_SIZE x 1.000 (the scales
+# a plain 2 GiB device copy reads on the same counters: 1,048,589 KiB fetched
+# and 2,097,152 KiB written per 2 GiB); valid only for the kernel source it
+# was measured on.
+MEASURED_TRAFFIC = {"kernel_sha256_16": "9e20e717e160179d", "workload": "kh4096",
+                    "precision": "fp64", "tile_cells": 512, "flags": 17, "kernel": "step_kernel",
+                    "level": 0, "bytes_per_launch": (2 * 1067123.625 + 2082642.869) * 1024}
 
 
 # dynamic-refinement workloads: re-tag and regrid every few coarse steps
@@ -543,7 +543,8 @@ def main():
     m = MEASURED_TRAFFIC
     if (kernel_hash() == m["kernel_sha256_16"] and args.workload == m["workload"]
             and args.precision == m["precision"] and tuning and m["kernel"] == kernel_name
-            and m["tile_cells"] in (None, tuning["tile_cells"]) and tuning["flags"] == m["flags"]):
+            and m["level"] == dom[0] and m["tile_cells"] in (None, tuning["tile_cells"])
+            and tuning["flags"] == m["flags"]):
         traffic = m["bytes_per_launch"]
     scale = max(abs(x) for x in T0)
     drift = [float(abs((T1[k] - T0[k]) - (L1[k] - L0[k])) / scale) for k in range(4)]
@@ -586,6 +587,11 @@ def main():
                                f"({prof_wall * 1e3 / prof_steps:.4f} ms/step with events)",
                      "path": {"bytes_per_step": path_bytes, "achieved": path_gbs,
                               "frac": path_gbs / HBM_PEAK_GBS}},
+        "kernels": [{"level": k[0], "fused": bool(k[1]), "launches_per_step": v[1] / prof_steps,
+                     "avg_launch_us": v[0] * 1e3 / v[1],
+                     "frac": v[2] / v[1] * (2 if k[1] else 1) * bytes_per_update / (v[0] / 1e3 / v[1]) / 1e9
+                     / HBM_PEAK_GBS}
+                    for k, v in sorted(ktimes.items()) if v[1]],
         "actual_updates_per_s": upd * args.steps / wall,
         "amr": ({"regrid_every": regrid_every, "regrids": amr_timed["regrids"],
                  "boxes_min": min(amr_timed["boxes"]), "boxes_max": max(amr_timed["boxes"]),

@@ -219,7 +219,8 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
  * 4 XCD-contiguous workgroup order, 16 fused sub-steps: with r = 2 and at
  * least two levels, one launch advances the finest level by both sub-steps of
  * its parent's step, the intermediate time level kept in LDS (temporal
- * blocking of the sub-cycling of Sec. 3). Rebuilds the launch tables; the
+ * blocking of the sub-cycling of Sec. 3), 512 XCD-contiguous order for the
+ * fused launches only. Rebuilds the launch tables; the
  * hierarchy and the time history are kept. VLBM_EINVAL for other values. */
 vlbm_status vlbm_set_tuning(vlbm_ctx *ctx, int tile_cells, int flags);
 

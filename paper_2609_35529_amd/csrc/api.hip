@@ -1462,6 +1462,7 @@ vlbm_status launch_coarse_step(vlbm_ctx *c, int e) {
     a.nblocks = r.nblocks;
     a.first = r.first;
     a.flags = c->step_flags | (r.fused_kernel ? STEP_FUSED_PHASE : 0) | (c->adt ? STEP_ADAPTIVE_DT : 0);
+    if (r.fused_kernel && (c->step_flags & STEP_XCD_FUSED)) a.flags |= STEP_XCD_CONTIGUOUS;
     if (c->adt && r.emit_cfl) a.flags |= STEP_CFL_EMIT;
     a.ak = r.ak;
     if (c->sensor && !r.fused_kernel) a.flags |= STEP_SENSOR;  // per-cell beta
@@ -2939,7 +2940,7 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
 vlbm_status vlbm_set_tuning(vlbm_ctx *c, int tile_cells, int flags) {
   if (!c) return fail(VLBM_EINVAL, "null context");
   if (tile_cells < 64 || tile_cells > (1 << 20) ||
-      (flags & ~(STEP_NT_STORES | STEP_TWO_CELLS | STEP_XCD_CONTIGUOUS | STEP_FUSE2)))
+      (flags & ~(STEP_NT_STORES | STEP_TWO_CELLS | STEP_XCD_CONTIGUOUS | STEP_FUSE2 | STEP_XCD_FUSED)))
     return fail(VLBM_EINVAL, "bad tuning (tile_cells %d, flags %d)", tile_cells, flags);
   c->tile_cells = tile_cells;
   c->step_flags = flags | (c->step_flags & STEP_F64_MATH);

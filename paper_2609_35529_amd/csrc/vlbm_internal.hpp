@@ -98,6 +98,7 @@ enum StepFlags : int32_t {
   STEP_ADAPTIVE_DT = 128,    // launch-uniform: h and the hand-off's time-step ratio from DynState
   STEP_CFL_EMIT = 256,       // launch-uniform: the level's last step launch of the coarse step folds
                              // the CFL term of its stored cells into cfl_next (emit_cfl)
+  STEP_XCD_FUSED = 512,      // tuning: XCD-contiguous order for the fused launches only
 };
 
 // Device scalars of the adaptive time step, updated once per coarse step by
