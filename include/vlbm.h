@@ -113,8 +113,28 @@ void vlbm_destroy(vlbm_ctx *ctx);
  * the context. Must precede vlbm_set_hierarchy. */
 vlbm_status vlbm_bind_pool(vlbm_ctx *ctx, void *dev, size_t bytes);
 
+/* A caller's device allocator: alloc returns a block of at least `bytes`
+ * bytes, 256-byte aligned, usable on the context's stream (NULL when it cannot:
+ * the call that needed it returns VLBM_ENOMEM); release returns a block the
+ * library has finished with (the context's stream has completed all work on
+ * it). Both are called on the thread that made the library call. */
+typedef void *(*vlbm_alloc_fn)(size_t bytes, void *user);
+typedef void (*vlbm_free_fn)(void *ptr, void *user);
+
+/* Take every later device allocation of ctx from the caller's allocator
+ * (e.g. PyTorch's caching allocator on the context's stream), so that the
+ * caller is the only allocator and a hierarchy can grow through regrids
+ * without a preset pool size. Must precede vlbm_set_hierarchy and cannot be
+ * combined with vlbm_bind_pool (VLBM_ESTATE). vlbm_destroy releases every
+ * block still held. */
+vlbm_status vlbm_bind_allocator(vlbm_ctx *ctx, vlbm_alloc_fn alloc, vlbm_free_fn release, void *user);
+
 /* Device bytes a context with these parameters and boxes needs (admission
- * control). Pure host computation. */
+ * control, and the size of a pool that holds it): both time levels of every
+ * frame, status and row tables, list and slot estimates, and the staging of
+ * a whole-level read. Not included: the adaptive relaxation's planes
+ * (vlbm_set_sensor) and frames that later regrids grow. Pure host
+ * computation. */
 size_t vlbm_footprint_bytes(const vlbm_params *params, const vlbm_box *boxes, int nboxes);
 
 /* Install a static hierarchy (level-0 always covers the domain). Discards any
@@ -138,7 +158,9 @@ vlbm_status vlbm_set_populations(vlbm_ctx *ctx, int level, int i0, int j0, int n
 vlbm_status vlbm_advance(vlbm_ctx *ctx, int n_coarse_steps);
 
 /* Read W = sum_q f_q (U[4][ny][ld], host, FP64) of active level-l cells in the
- * rectangle; other cells get NaN. Synchronises. */
+ * rectangle (Sec. 2.2: the conserved state is the sum of the populations;
+ * Sec. 4.1.2 reads it on the active cells of each grid); other cells get NaN.
+ * Synchronises. */
 vlbm_status vlbm_get_state(vlbm_ctx *ctx, int level, int i0, int j0, int nx, int ny, double *U,
                            long ld);
 
@@ -164,7 +186,9 @@ vlbm_status vlbm_get_state_noalloc(vlbm_ctx *ctx, int level, int i0, int j0, int
 vlbm_status vlbm_get_populations(vlbm_ctx *ctx, int level, int i0, int j0, int nx, int ny,
                                  double *F, long ld);
 
-/* Conserved totals T_k = sum_l dx_l^2 sum_active sum_q f_{q,k} (FP64,
+/* Conserved totals (Sec. 4.1.2: the mass summed over the active cells of both
+ * grids, each weighted by its cell size; here every component, in 2-D)
+ * T_k = sum_l dx_l^2 sum_active sum_q f_{q,k} (FP64,
  * compensated, fixed summation order) and the boundary ledger: the net amount
  * of each component that entered through non-periodic sides since the last
  * set_state. T(t) - T(0) equals the ledger to round-off. Synchronises. */

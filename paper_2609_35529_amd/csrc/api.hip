@@ -89,6 +89,10 @@ struct DevMem {
   char *base = nullptr;
   size_t size = 0;
   bool bound = false;
+  // caller's allocator (vlbm_bind_allocator): every block comes from it
+  vlbm_alloc_fn ext_alloc = nullptr;
+  vlbm_free_fn ext_free = nullptr;
+  void *ext_user = nullptr;
   std::map<size_t, size_t> free_;     // offset -> length
   std::map<void *, size_t> live_;     // pointer -> length (bound region)
   std::unordered_map<void *, size_t> owned_;  // hipMalloc'ed blocks in use -> length
@@ -114,6 +118,16 @@ struct DevMem {
 
   void *alloc(size_t n) {
     n = round(std::max<size_t>(n, 256));
+    if (ext_alloc) {
+      void *p = ext_alloc(n, ext_user);
+      if (!p) return nullptr;
+      if (reinterpret_cast<uintptr_t>(p) & 255) {  // the layout needs 256-byte alignment
+        ext_free(p, ext_user);
+        return nullptr;
+      }
+      owned_[p] = n;
+      return p;
+    }
     if (!bound) {
       auto c = cache_.lower_bound(n);
       if (c != cache_.end() && c->first <= 2 * n) {
@@ -146,6 +160,13 @@ struct DevMem {
 
   void release(void *p) {
     if (!p) return;
+    if (ext_alloc) {
+      auto it = owned_.find(p);
+      if (it == owned_.end()) return;
+      owned_.erase(it);
+      ext_free(p, ext_user);
+      return;
+    }
     if (!bound) {
       auto it = owned_.find(p);
       if (it == owned_.end()) return;
@@ -185,7 +206,12 @@ struct DevMem {
   }
 
   void release_all() {
-    for (auto &kv : owned_) (void)hipFree(kv.first);
+    for (auto &kv : owned_) {
+      if (ext_alloc)
+        ext_free(kv.first, ext_user);
+      else
+        (void)hipFree(kv.first);
+    }
     owned_.clear();
     drop_cache();
     if (bound) bind(base, size);
@@ -2214,8 +2240,19 @@ void vlbm_destroy(vlbm_ctx *c) {
 
 vlbm_status vlbm_bind_pool(vlbm_ctx *c, void *dev, size_t bytes) {
   if (!c || !dev || bytes < 4096) return fail(VLBM_EINVAL, "bad pool");
-  if (c->have_hierarchy) return fail(VLBM_ESTATE, "bind the pool before set_hierarchy");
+  if (c->have_hierarchy || c->mem.ext_alloc) return fail(VLBM_ESTATE, "bind the pool before set_hierarchy");
   c->mem.bind(dev, bytes);
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_bind_allocator(vlbm_ctx *c, vlbm_alloc_fn alloc, vlbm_free_fn release, void *user) {
+  if (!c || !alloc || !release) return fail(VLBM_EINVAL, "null allocator");
+  if (c->have_hierarchy || c->mem.bound || !c->mem.owned_.empty())
+    return fail(VLBM_ESTATE, "bind the allocator before set_hierarchy");
+  c->mem.drop_cache();
+  c->mem.ext_alloc = alloc;
+  c->mem.ext_free = release;
+  c->mem.ext_user = user;
   return VLBM_OK;
 }
 
@@ -2223,19 +2260,21 @@ size_t vlbm_footprint_bytes(const vlbm_params *params, const vlbm_box *boxes, in
   if (!params) return 0;
   Geometry g;
   if (check_boxes(*params, boxes, nboxes, g) != VLBM_OK) return 0;
-  size_t esz = params->precision == VLBM_FP32 ? 4 : 8, total = 0;
+  size_t esz = params->precision == VLBM_FP32 ? 4 : 8, total = 0, stage = 0;
   for (int l = 0; l < kMaxLevels && g.present[l]; ++l) {
     Level L;
     frame_of(*params, esz, g, l, L);
     size_t cells = (size_t)L.fw * L.nrows;
     total += DevMem::round(level_bytes(L, esz)) * 2;  // two time levels
     total += DevMem::round(cells);                    // status
+    total += DevMem::round(sizeof(int32_t) * ((size_t)L.fh + L.nrows));  // row tables
+    stage = std::max(stage, DevMem::round(sizeof(double) * 16 * cells));  // a whole-level read
     // tiles, tasks, accumulators, ledger, partials: bounded by the perimeter
     size_t perim = 2 * ((size_t)L.fw * L.runs.size() + L.nrows) * 4 + 64;
     total += DevMem::round(sizeof(Task) * perim * 2) + DevMem::round(sizeof(double) * 4 * perim * 2);
     total += DevMem::round((cells / 64 + 64) * (sizeof(Tile) + 4 * sizeof(double)));
   }
-  return total + (1 << 20);
+  return total + stage + (1 << 20);
 }
 
 }  // extern "C"

@@ -69,6 +69,9 @@ def _sig(name, res, args):
 vlbm_create = _sig("vlbm_create", _st, [C.POINTER(vlbm_params), _P, C.POINTER(_P)])
 vlbm_destroy = _sig("vlbm_destroy", None, [_P])
 vlbm_bind_pool = _sig("vlbm_bind_pool", _st, [_P, _P, C.c_size_t])
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+vlbm_bind_allocator = _sig("vlbm_bind_allocator", _st, [_P, ALLOC_FN, FREE_FN, _P])
 vlbm_footprint_bytes = _sig("vlbm_footprint_bytes", C.c_size_t,
                             [C.POINTER(vlbm_params), C.POINTER(vlbm_box), C.c_int])
 vlbm_set_hierarchy = _sig("vlbm_set_hierarchy", _st, [_P, C.POINTER(vlbm_box), C.c_int])
@@ -111,7 +114,7 @@ EXPORTED = ["vlbm_create", "vlbm_destroy", "vlbm_bind_pool", "vlbm_footprint_byt
             "vlbm_save", "vlbm_load", "vlbm_batch_advance", "vlbm_set_tuning", "vlbm_autotune",
             "vlbm_steps", "vlbm_active_cells", "vlbm_sync", "vlbm_last_error",
             "vlbm_set_profiling", "vlbm_kernel_times", "vlbm_set_sensor", "vlbm_get_beta",
-            "vlbm_set_time_stepping", "vlbm_time", "vlbm_get_state_noalloc"]
+            "vlbm_set_time_stepping", "vlbm_time", "vlbm_get_state_noalloc", "vlbm_bind_allocator"]
 
 
 class VLBMError(RuntimeError):
@@ -165,28 +168,91 @@ def _stream_handle(stream):
     return C.c_void_p(int(stream.cuda_stream))
 
 
+class TorchAllocator:
+    """Device blocks for the library from PyTorch's caching allocator, on the
+    library's stream (blocks freed there are reused in that stream's order).
+    Holds each block's tensor until the library releases it."""
+
+    def __init__(self, stream=None):
+        if torch is None:
+            raise ImportError("torch is needed for the PyTorch allocator")
+        self.stream = stream
+        self.live = {}
+        self.bytes_in_use = 0
+        self.alloc_cb = ALLOC_FN(self._alloc)
+        self.free_cb = FREE_FN(self._free)
+
+    def _alloc(self, nbytes, user):
+        try:
+            ctx = torch.cuda.stream(self.stream) if self.stream is not None else None
+            if ctx is not None:
+                with ctx:
+                    t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+            else:
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+        except Exception:  # out of memory: the library reports VLBM_ENOMEM
+            return None
+        p = t.data_ptr()
+        self.live[p] = t
+        self.bytes_in_use += int(nbytes)
+        return p
+
+    def _free(self, ptr, user):
+        t = self.live.pop(ptr, None)
+        if t is not None:
+            self.bytes_in_use -= t.numel()
+
+
+def torch_pool(nbytes, device="cuda"):
+    """A device tensor of nbytes bytes from PyTorch's allocator, to bind as a
+    context's memory pool (vlbm_bind_pool)."""
+    if torch is None:
+        raise ImportError("torch is needed to allocate a device pool")
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
 class Solver:
-    """One VLBM hierarchy living on the GPU (a ``vlbm_ctx``)."""
+    """One VLBM hierarchy living on the GPU (a ``vlbm_ctx``).
+
+    Device memory (PyTorch is the allocator unless memory="library"):
+    memory="torch" (default when torch is importable) takes every block from
+    PyTorch's caching allocator on the solver's stream (vlbm_bind_allocator);
+    `pool` is one device tensor the library suballocates (vlbm_bind_pool), and
+    `pool_bytes` asks for such a tensor of that size."""
 
     def __init__(self, nx0, ny0, dx0, gamma=1.4, c=1.0, beta=0.9, r=2, max_levels=2,
                  bc=(PERIODIC,) * 4, w_inflow=None, precision=FP64, stream=None, pool=None,
-                 eos=None):
+                 eos=None, pool_bytes=None, memory="torch"):
         self.params = make_params(nx0, ny0, dx0, gamma, c, beta, r, max_levels, bc, w_inflow,
                                   precision, eos)
         self.nx0, self.ny0, self.r = nx0, ny0, r
         self.max_levels = max_levels
         self._h = C.c_void_p()
+        self._pool = None
+        self._alloc = None
         check(vlbm_create(C.byref(self.params), _stream_handle(stream), C.byref(self._h)))
-        self._pool = pool  # keeps a caller-provided device tensor alive
+        if pool is None and pool_bytes:
+            pool = torch_pool(pool_bytes)
         if pool is not None:
+            self._pool = pool  # keeps the device tensor alive as long as the context
             check(vlbm_bind_pool(self._h, C.c_void_p(pool.data_ptr()),
                                  pool.numel() * pool.element_size()))
+        elif memory == "torch" and torch is not None:
+            self._alloc = TorchAllocator(stream)
+            check(vlbm_bind_allocator(self._h, self._alloc.alloc_cb, self._alloc.free_cb, None))
+        elif memory not in ("torch", "library"):
+            raise ValueError(f"memory={memory!r}")
+
+    @property
+    def memory(self):
+        return "pool" if self._pool is not None else "torch" if self._alloc is not None else "library"
 
     @classmethod
-    def from_case(cls, case, precision=FP64, stream=None, pool=None, max_levels=None):
+    def from_case(cls, case, precision=FP64, stream=None, pool=None, max_levels=None, pool_bytes=None,
+                  memory="torch"):
         s = cls(case.nx0, case.ny0, case.dx0, case.gamma, case.c, case.beta, case.r,
                 max_levels or case.nlev, case.bc, case.w_inflow, precision, stream, pool,
-                eos=getattr(case, "eos", None))
+                eos=getattr(case, "eos", None), pool_bytes=pool_bytes, memory=memory)
         s.set_hierarchy(case.boxes)
         for l in range(case.nlev):
             if case.states[l] is not None:
@@ -201,6 +267,8 @@ class Solver:
         if self._h:
             vlbm_destroy(self._h)
             self._h = C.c_void_p()
+        self._pool = None
+        self._alloc = None
 
     def __del__(self):
         try:
