@@ -20,6 +20,7 @@ EOS_IDEAL, EOS_STIFFENED, EOS_VDW = 0, 1, 2
 MUT_NONE, MUT_REFLUX_END_LABEL, MUT_RECON_SIGMA_SIGN, MUT_REFLUX_LAST_ONLY = 0, 1, 2, 3
 MUT_REGRID_RESTART_ALL, MUT_REGRID_NEW_FACE_HISTORY, MUT_WALL_NO_FLIP = 4, 5, 6
 MUT_SENSOR_BOX_SUM, MUT_SENSOR_MAX_NORM, MUT_SLOPE_RATIO_INVERTED, MUT_TAG_ONE_SIDED = 7, 8, 9, 10
+MUT_FLUX_SENSOR_RMS = 11
 FMUT_NONE, FMUT_VDW_SIGN = 0, 1
 
 _D = C.POINTER(C.c_double)
@@ -50,6 +51,8 @@ def lib():
         L.orc_advance.argtypes = [C.c_void_p, C.c_int]
         L.orc_totals.argtypes = [C.c_void_p, _D, _D]
         L.orc_tag.argtypes = [C.c_void_p, C.c_int, C.c_double, _U8]
+        L.orc_flux_sensor.argtypes = [C.c_void_p, C.c_int, _D]
+        L.orc_tag_flux.argtypes = [C.c_void_p, C.c_int, C.c_double, _U8]
         L.orc_error.restype = C.c_char_p
         L.orc_feq.argtypes = [C.c_double, C.c_double, C.c_int, C.c_double, C.c_double, _D, _D]
         L.orc_flux.argtypes = [C.c_double, C.c_int, C.c_double, C.c_double, _D, _D, _D]
@@ -236,4 +239,16 @@ class Oracle:
         NY, NX = self.shape(level)
         t = np.empty((NY, NX), dtype=np.uint8)
         _check(lib().orc_tag(self._h, level, thr, t.ctypes.data_as(_U8)))
+        return t
+
+    def flux_sensor(self, level):
+        """eq. amr-sigma: s = max_k |s_k| per active cell, (Ny, Nx), 0 elsewhere."""
+        out = np.zeros(self.shape(level))
+        _check(lib().orc_flux_sensor(self._h, level, _dp(out)))
+        return out
+
+    def tag_flux(self, level, thr):
+        NY, NX = self.shape(level)
+        t = np.empty((NY, NX), dtype=np.uint8)
+        _check(lib().orc_tag_flux(self._h, level, thr, t.ctypes.data_as(_U8)))
         return t

@@ -971,6 +971,64 @@ int orc_regrid(orc *o, const int *boxes, int nboxes) {
   return 0;
 }
 
+/* The refinement sensor of eq. (amr-sigma) (Sec. 3.4) on the active cells of
+ * level l: s_k = dx (div Q)_k / max_{x,alpha} |Q_{alpha,k}| as for eq.
+ * (sensor-B) -- central differences 0.5 ((Qx_k(x+1) - Qx_k(x-1)) +
+ * (Qy_k(y+1) - Qy_k(y-1))), a neighbour that is not an active cell of the
+ * level replaced by the cell itself, the max over the active cells of every
+ * level and both directions (s_k = 0 where it is 0) -- combined with the
+ * max norm s = max_k |s_k|. out[Ny][Nx], 0 on inactive cells. */
+int orc_flux_sensor(orc *o, int level, double *out) {
+  int l = level;
+  if (l < 0 || l >= o->nlev) return -1;
+  sensor_qmax(o);
+  const double *F = o->F[l];
+  for (int y = 0; y < o->Ny[l]; ++y)
+    for (int x = 0; x < o->Nx[l]; ++x) {
+      out[cidx(o, l, x, y)] = 0.0;
+      if (!active(o, l, x, y)) continue;
+      double Qx[4][4], Qy[4][4];
+      for (int d = 0; d < 4; ++d) {
+        int xx = x + CX[d], yy = y + CY[d];
+        if (!wrap(o, l, &xx, &yy) || !active(o, l, xx, yy)) {
+          xx = x;
+          yy = y;
+        }
+        double Wn[4];
+        for (int k = 0; k < 4; ++k)
+          Wn[k] = ((F[pidx(o, l, 0 * 4 + k, xx, yy)] + F[pidx(o, l, 1 * 4 + k, xx, yy)]) +
+                   F[pidx(o, l, 2 * 4 + k, xx, yy)]) + F[pidx(o, l, 3 * 4 + k, xx, yy)];
+        orc_flux(o->gamma, o->eos, o->eos_a, o->eos_b, Wn, Qx[d], Qy[d]);
+      }
+      double smax = 0.0;
+      for (int k = 0; k < 4; ++k) {
+        double dq = (Qx[0][k] - Qx[1][k]) + (Qy[2][k] - Qy[3][k]);
+        double sk = o->qmax[k] > 0.0 ? (0.5 * dq) / o->qmax[k] : 0.0;
+        if (o->mut == ORC_MUT_FLUX_SENSOR_RMS) { /* planted mistake: accumulate squares */
+          smax += 0.25 * sk * sk;
+          continue;
+        }
+        if (fabs(sk) > smax) smax = fabs(sk);
+      }
+      if (o->mut == ORC_MUT_FLUX_SENSOR_RMS) smax = sqrt(smax);
+      out[cidx(o, l, x, y)] = smax;
+    }
+  return 0;
+}
+
+/* Refinement tags from eq. (amr-sigma): s > thr on active level-l cells. */
+int orc_tag_flux(orc *o, int level, double thr, unsigned char *tags) {
+  int l = level;
+  if (l < 0 || l >= o->nlev) return -1;
+  size_t nc = (size_t)o->Nx[l] * o->Ny[l];
+  double *s = (double *)malloc(sizeof(double) * nc);
+  if (!s) return -1;
+  orc_flux_sensor(o, l, s);
+  for (size_t i = 0; i < nc; ++i) tags[i] = (unsigned char)(s[i] > thr);
+  free(s);
+  return 0;
+}
+
 /* Density-gradient tag on active level-l cells: max over axes of
  * |rho(+) - rho(-)| / (2 rho) > thr; a neighbour that is not active at level
  * l (or lies outside a non-periodic domain) is replaced by the cell itself. */

@@ -34,7 +34,8 @@ enum { ORC_MUT_NONE = 0, ORC_MUT_REFLUX_END_LABEL = 1, ORC_MUT_RECON_SIGMA_SIGN 
        ORC_MUT_SENSOR_BOX_SUM = 7,          /* box filter as a sum instead of a mean */
        ORC_MUT_SENSOR_MAX_NORM = 8,         /* max over k of |s_k| instead of the RMS */
        ORC_MUT_SLOPE_RATIO_INVERTED = 9,    /* hand-off slope scaled by c_now / c_prev */
-       ORC_MUT_TAG_ONE_SIDED = 10 };        /* tag from rho(+1) - rho(0) instead of the central difference */
+       ORC_MUT_TAG_ONE_SIDED = 10,          /* tag from rho(+1) - rho(0) instead of the central difference */
+       ORC_MUT_FLUX_SENSOR_RMS = 11 };      /* eq. amr-sigma with the RMS over k instead of the max norm */
 /* Planted mistake of the single-operation functions (EOS): 1 flips the sign
  * of the a rho^2 term inside the van der Waals pressure. Process-wide. */
 void orc_set_function_mutation(int mut);
@@ -65,6 +66,10 @@ double orc_time(const orc *o);        /* elapsed time since set_state */
 double orc_link_speed(const orc *o);  /* c of the last coarse step */
 void orc_totals(const orc *o, double T[4], double ledger[4]);
 int orc_tag(const orc *o, int level, double thr, unsigned char *tags);
+/* Refinement sensor of eq. (amr-sigma), s = max_k |s_k| per active cell of
+ * `level` (out[Ny][Nx], 0 elsewhere), and its tags s > thr. */
+int orc_flux_sensor(orc *o, int level, double *out);
+int orc_tag_flux(orc *o, int level, double thr, unsigned char *tags);
 const char *orc_error(void);
 
 /* Single-operation entry points used by the unit pins. */

@@ -345,3 +345,83 @@ def test_planted_history_on_new_interfaces_fails_the_new_patch_pin():
     coarse step (the unmutated rule matches a restart there, bit for bit)."""
     assert _new_patch_matches_restart()
     assert not _new_patch_matches_restart(O.MUT_REGRID_NEW_FACE_HISTORY)
+
+
+# ------------------------------------------------ refinement sensor (eq. amr-sigma)
+def _analytic_flux_sensor(n):
+    """max_k |dx (div Q)_k / max|Q_k|| with exact derivatives (complex step)."""
+    dx = 1.0 / n
+    xc = (np.arange(n) + 0.5) * dx
+    X, Y = np.meshgrid(xc, xc)
+    Qx, Qy, _, _ = _flux_of(X, Y)
+    s = []
+    for k in range(4):
+        qmax = max(np.abs(Qx[k]).max(), np.abs(Qy[k]).max())
+        div = _d(lambda a, b: _flux_of(a, b)[0][k], X, Y, 0) + _d(lambda a, b: _flux_of(a, b)[1][k], X, Y, 1)
+        s.append(np.abs(dx * div / qmax))
+    return np.max(s, axis=0)
+
+
+def _oracle_flux_sensor(n, mut=O.MUT_NONE):
+    dx = 1.0 / n
+    xc = (np.arange(n) + 0.5) * dx
+    X, Y = np.meshgrid(xc, xc)
+    o = O.Oracle(n, n, dx, 2, 1, GAMMA, 5.0, 0.8, (O.PERIODIC,) * 4)
+    o.set_mutation(mut)
+    o.set_boxes([])
+    o.set_state(0, wl.conserved(*_field(X, Y), GAMMA))
+    return o.flux_sensor(0)
+
+
+def test_flux_sensor_matches_analytic_derivatives():
+    """eq. amr-sigma on a smooth analytic field: the oracle's s (central
+    differences, the domain-wide max of |Q_k|, the max norm over k) matches s
+    from exact derivatives to the differences' O(dx^2) truncation."""
+    s_ref = _analytic_flux_sensor(128)
+    s = _oracle_flux_sensor(128)
+    assert np.max(np.abs(s - s_ref)) < 3e-3 * s_ref.max()
+
+
+def test_planted_rms_flux_sensor_fails_the_analytic_pin():
+    s_ref = _analytic_flux_sensor(128)
+    s = _oracle_flux_sensor(128, O.MUT_FLUX_SENSOR_RMS)
+    assert np.max(np.abs(s - s_ref)) > 5e-2 * s_ref.max()
+
+
+def test_flux_sensor_and_tags_match_numpy_on_two_levels():
+    """Two levels with a wall and an outflow side: s on each level equals numpy's
+    central differences of the Euler flux of the held state, with the max of
+    |Q_k| over the active cells of both levels, inactive neighbours replaced by
+    the cell; tags are s above the threshold on active cells only."""
+    nx0, ny0 = 24, 18
+    bc = (O.REFLECT, O.OUTFLOW, O.PERIODIC, O.PERIODIC)
+    o = O.Oracle(nx0, ny0, 1.0 / 24, 2, 2, GAMMA, 4.0, 0.8, bc)
+    o.set_boxes([(1, 12, 8, 16, 20)])
+    o.set_state(0, wl.random_smooth_U(nx0, ny0, seed=13, amp=0.3))
+    o.set_state(1, wl.random_smooth_U(2 * nx0, 2 * ny0, seed=14, amp=0.3))
+    o.advance(2)
+    acts = [o.active_mask(l) for l in range(2)]
+    Us = [o.get_state(l) for l in range(2)]
+    qmax = np.zeros(4)
+    for U, act in zip(Us, acts):
+        Fx, Fy = exact.euler_flux(np.where(act, U, 1.0), GAMMA)
+        qmax = np.maximum(qmax, np.max(np.where(act, np.maximum(np.abs(Fx), np.abs(Fy)), 0.0), axis=(1, 2)))
+    for l in range(2):
+        act, U = acts[l], np.where(acts[l], Us[l], 1.0)
+        Fx, Fy = exact.euler_flux(U, GAMMA)
+
+        def nb(F, axis, shift, per):
+            G = np.roll(F, shift, axis=axis + 1)
+            a = np.roll(act, shift, axis=axis)
+            if not per:
+                idx = [slice(None)] * 2
+                idx[axis] = 0 if shift == 1 else -1
+                a[tuple(idx)] = False
+            return np.where(a, G, F)
+
+        div = (nb(Fx, 1, -1, False) - nb(Fx, 1, 1, False)) + (nb(Fy, 0, -1, True) - nb(Fy, 0, 1, True))
+        s_np = np.where(act, np.max(np.abs(0.5 * div / qmax[:, None, None]), axis=0), 0.0)
+        s = o.flux_sensor(l)
+        assert np.allclose(s, s_np, rtol=1e-11, atol=1e-14), l
+        thr = np.quantile(s[act], 0.7)
+        assert np.array_equal(o.tag_flux(l, thr).astype(bool), act & (s > thr))
