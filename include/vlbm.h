@@ -203,10 +203,21 @@ vlbm_status vlbm_conserved_totals(vlbm_ctx *ctx, double totals[4], double ledger
  * Synchronises. */
 vlbm_status vlbm_regrid(vlbm_ctx *ctx, const vlbm_box *boxes, int nboxes);
 
-/* Density-gradient tags of active level-l cells:
- * max over axes |rho(+1) - rho(-1)| / (2 rho) > threshold, a missing or
- * inactive neighbour replaced by the cell itself. tags[Ny_l][Nx_l] (host).
- * Synchronises. */
+/* Refinement indicator of vlbm_tag and vlbm_tag_and_regrid (default
+ * VLBM_TAG_DENSITY):
+ *   VLBM_TAG_DENSITY  max over axes |rho(+1) - rho(-1)| / (2 rho) > threshold;
+ *   VLBM_TAG_FLUX     the sensor of eq. amr-sigma (Sec. 3.4),
+ *                     max_k |s_k| > threshold with s_k = dx (div Q)_k /
+ *                     max_{x,alpha} |Q_{alpha,k}| (central differences; the
+ *                     max over the active cells of every level).
+ * Either way a missing or inactive neighbour is replaced by the cell itself.
+ * VLBM_EINVAL for another kind. */
+#define VLBM_TAG_DENSITY 0
+#define VLBM_TAG_FLUX 1
+vlbm_status vlbm_set_tag_indicator(vlbm_ctx *ctx, int kind);
+
+/* Tags of active level-l cells by the context's indicator
+ * (vlbm_set_tag_indicator). tags[Ny_l][Nx_l] (host). Synchronises. */
 vlbm_status vlbm_tag(vlbm_ctx *ctx, int level, double threshold, unsigned char *tags);
 
 /* Tag every level below the finest, dilate by `buffer` cells, cluster into

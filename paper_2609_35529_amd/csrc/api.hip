@@ -350,6 +350,8 @@ struct vlbm_ctx {
   // device scratch of tag_and_regrid (tags per level, tile bits and lists,
   // counts), kept between calls and grown on demand: slot -> (pointer, bytes)
   std::vector<std::pair<void *, size_t>> tag_scratch;
+  int tag_kind = VLBM_TAG_DENSITY;              // refinement indicator (vlbm_set_tag_indicator)
+  unsigned long long *dflux_qmax = nullptr;     // [4] its domain-wide flux maxima (bits)
   void *scratch_slot(size_t slot, size_t bytes) {
     if (tag_scratch.size() <= slot) tag_scratch.resize(slot + 1, {nullptr, 0});
     auto &e = tag_scratch[slot];
@@ -2149,17 +2151,46 @@ int level_ny(const vlbm_ctx *c, int l) {
   return (int)(c->p.ny0 * s);
 }
 
-// Density-gradient tags of level l's active cells, indexed like its status
-// (fw bytes per stored row).
+// Refinement tags of the present levels l with dtag[l] set, into dtag[l]
+// (device, indexed like each level's status): the density-gradient indicator,
+// or the sensor of eq. amr-sigma, whose flux maxima run over every level.
+hipError_t launch_level_tags(vlbm_ctx *c, double thr, const std::vector<uint8_t *> &dtag) {
+  hipError_t e = hipSuccess;
+  if (c->tag_kind == VLBM_TAG_FLUX) {
+    if (!c->dflux_qmax) c->dflux_qmax = static_cast<unsigned long long *>(c->mem.alloc(4 * sizeof(unsigned long long)));
+    if (!c->dflux_qmax) return hipErrorOutOfMemory;
+    e = launch_clear_u64(c->dflux_qmax, 4, c->stream);
+    for (int l = 0; l < c->nlev && e == hipSuccess; ++l) {
+      const Level &L = c->lv[l];
+      e = launch_flux_max(L.buf[L.cur()], L.dtiles, (int)L.tiles.size(), L.plane, L.pitch, c->fp32, c->eos,
+                          c->dflux_qmax, c->stream);
+    }
+  }
+  for (int l = 0; l < (int)dtag.size() && l < c->nlev && e == hipSuccess; ++l) {
+    if (!dtag[l]) continue;
+    const Level &L = c->lv[l];
+    if (c->tag_kind == VLBM_TAG_FLUX)
+      e = launch_tag_flux(L.buf[L.cur()], L.dstatus, L.dsrow, L.dyrow, L.plane, L.pitch, L.xoff, L.fx0, L.fy0,
+                          L.fw, L.fh, L.nrows, L.Nx, L.Ny, c->perx(), c->pery(), c->fp32, c->eos, c->dflux_qmax,
+                          thr, dtag[l], c->stream);
+    else
+      e = launch_tag(L.buf[L.cur()], L.dstatus, L.dsrow, L.dyrow, L.plane, L.pitch, L.xoff, L.fx0, L.fy0, L.fw,
+                     L.fh, L.nrows, L.Nx, L.Ny, c->perx(), c->pery(), c->fp32, thr, dtag[l], c->stream);
+  }
+  return e;
+}
+
+// Refinement tags of level l's active cells, indexed like its status (fw
+// bytes per stored row).
 vlbm_status tag_frame(vlbm_ctx *c, int l, double thr, std::vector<uint8_t> &ft) {
   const Level &L = c->lv[l];
   const size_t n = (size_t)L.fw * L.nrows;
   ft.assign(n, 0);
   uint8_t *d = static_cast<uint8_t *>(c->mem.alloc(n));
   if (!d) return fail(VLBM_ENOMEM, "tag buffer");
-  hipError_t e = launch_tag(L.buf[L.cur()], L.dstatus, L.dsrow, L.dyrow, L.plane, L.pitch, L.xoff, L.fx0,
-                            L.fy0, L.fw, L.fh, L.nrows, L.Nx, L.Ny, c->perx(), c->pery(), c->fp32, thr, d,
-                            c->stream);
+  std::vector<uint8_t *> dtag(l + 1, nullptr);
+  dtag[l] = d;
+  hipError_t e = launch_level_tags(c, thr, dtag);
   if (e == hipSuccess) e = hipMemcpyAsync(ft.data(), d, n, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   c->mem.release(d);
@@ -2234,6 +2265,7 @@ void vlbm_destroy(vlbm_ctx *c) {
   c->mem.release(c->ddyn);
   c->mem.release(c->dcmax);
   for (auto &e : c->tag_scratch) c->mem.release(e.first);
+  c->mem.release(c->dflux_qmax);
   c->mem.release_all();
   delete c;
 }
@@ -2510,6 +2542,13 @@ vlbm_status vlbm_tag(vlbm_ctx *c, int level, double thr, unsigned char *tags) {
   return VLBM_OK;
 }
 
+vlbm_status vlbm_set_tag_indicator(vlbm_ctx *c, int kind) {
+  if (!c) return fail(VLBM_EINVAL, "null context");
+  if (kind != VLBM_TAG_DENSITY && kind != VLBM_TAG_FLUX) return fail(VLBM_EINVAL, "unknown tag indicator %d", kind);
+  c->tag_kind = kind;
+  return VLBM_OK;
+}
+
 vlbm_status vlbm_get_boxes(vlbm_ctx *c, vlbm_box *boxes, int cap, int *nboxes) {
   if (!c || !nboxes) return fail(VLBM_EINVAL, "null argument");
   *nboxes = (int)c->boxes.size();
@@ -2552,17 +2591,15 @@ vlbm_status vlbm_tag_and_regrid(vlbm_ctx *c, double thr, int buffer, int min_box
     tm.mark("queued steps");
   }
   std::vector<uint8_t *> dtag(c->nlev, nullptr);
-  hipError_t e = hipSuccess;
-  for (int l = 0; l < c->nlev && e == hipSuccess; ++l) {
+  for (int l = 0; l < c->nlev; ++l) {
     const Level &L = c->lv[l];
     dtag[l] = static_cast<uint8_t *>(dalloc((size_t)L.fw * L.nrows));
     if (!dtag[l]) {
       release();
       return fail(VLBM_ENOMEM, "tag buffer");
     }
-    e = launch_tag(L.buf[L.cur()], L.dstatus, L.dsrow, L.dyrow, L.plane, L.pitch, L.xoff, L.fx0, L.fy0, L.fw,
-                   L.fh, L.nrows, L.Nx, L.Ny, c->perx(), c->pery(), c->fp32, thr, dtag[l], c->stream);
   }
+  hipError_t e = launch_level_tags(c, thr, dtag);
   for (int l = c->nlev - 1; l >= 1 && e == hipSuccess; --l) {
     const Level &F = c->lv[l], &P = c->lv[l - 1];
     e = launch_tag_parents(dtag[l], F.dyrow, F.fx0, F.fy0, F.fw, F.nrows, dtag[l - 1], P.dsrow, P.fx0, P.fy0,

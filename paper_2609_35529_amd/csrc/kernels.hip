@@ -1365,6 +1365,109 @@ hipError_t launch_tag(const void *buf, const uint8_t *status, const int32_t *sro
   return hipGetLastError();
 }
 
+// Refinement sensor of eq. amr-sigma (Sec. 3.4). First the domain-wide
+// max_{x,alpha} |Q_{alpha,k}| over the active cells of every level (one
+// launch per level over its step tiles, into qmax as bits), then per active
+// cell s_k = (0.5 ((Qx_k(x+1) - Qx_k(x-1)) + (Qy_k(y+1) - Qy_k(y-1)))) / qmax_k
+// (0 where qmax_k is 0), a neighbour that is not an active cell replaced by
+// the cell itself, and the tag max_k |s_k| > thr. The arithmetic follows the
+// order of the FP64 contract above.
+template <class T>
+__global__ __launch_bounds__(256) void flux_max_kernel(const T *__restrict__ buf, const Tile *tiles, int64_t P,
+                                                       int pitch, EosT<double> eos, unsigned long long *qmax) {
+  const Tile tl = tiles[blockIdx.x];
+  double m[4] = {0.0, 0.0, 0.0, 0.0};
+  const int n = tl.w * tl.h;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int cy = i / tl.w, cx = i - cy * tl.w;
+    double w[4];
+    stored_W<T>(buf, P, (int64_t)tl.off0 + (int64_t)cy * pitch + cx, w);
+    flux_absmax(eos, w, m);
+  }
+  block_qmax(m, qmax);
+}
+
+hipError_t launch_flux_max(const void *buf, const Tile *tiles, int ntiles, int64_t plane, int pitch, int fp32,
+                           const EosT<double> &eos, unsigned long long *qmax, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(flux_max_kernel<float>, dim3(ntiles), dim3(256), 0, s, static_cast<const float *>(buf),
+                       tiles, plane, pitch, eos, qmax);
+  else
+    hipLaunchKernelGGL(flux_max_kernel<double>, dim3(ntiles), dim3(256), 0, s, static_cast<const double *>(buf),
+                       tiles, plane, pitch, eos, qmax);
+  return hipGetLastError();
+}
+
+template <class T>
+__global__ void tag_flux_kernel(const T *__restrict__ buf, const uint8_t *status, const int32_t *srow,
+                                const int32_t *yrow, int64_t P, int pitch, int xoff, int fx0, int fy0, int fw,
+                                int fh, int nrows, int Nx, int Ny, int perx, int pery, EosT<double> eos,
+                                const unsigned long long *qmax_bits, double thr, uint8_t *tags) {
+  const int64_t n = (int64_t)fw * nrows;
+  double qm[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) qm[k] = __longlong_as_double((long long)qmax_bits[k]);
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const int sr = (int)(c / fw), fx = (int)(c - (int64_t)sr * fw);
+    const int x = fx + fx0, y = yrow[sr] + fy0;
+    uint8_t tag = 0;
+    if (status[c] == 1) {
+      const int64_t o = (int64_t)sr * pitch + fx + xoff;
+      const int dx[4] = {1, -1, 0, 0}, dy[4] = {0, 0, 1, -1};
+      double Qx[4][4], Qy[4][4];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        int xx = x + dx[d], yy = y + dy[d];
+        bool ok = true;
+        if (xx < 0 || xx >= Nx) {
+          if (perx) xx = (xx + Nx) % Nx; else ok = false;
+        }
+        if (yy < 0 || yy >= Ny) {
+          if (pery) yy = (yy + Ny) % Ny; else ok = false;
+        }
+        int64_t on = o;
+        if (ok) {
+          const int gx = xx - fx0, gy = yy - fy0;
+          const int gs = (gy >= 0 && gy < fh) ? srow[gy] : -1;
+          if (gx >= 0 && gx < fw && gs >= 0 && status[(int64_t)gs * fw + gx] == 1)
+            on = (int64_t)gs * pitch + gx + xoff;
+        }
+        double w[4];
+        stored_W<T>(buf, P, on, w);
+        euler_flux(eos, w, Qx[d], Qy[d]);
+      }
+      double smax = 0.0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double dq = (Qx[0][k] - Qx[1][k]) + (Qy[2][k] - Qy[3][k]);
+        const double sk = qm[k] > 0.0 ? (0.5 * dq) / qm[k] : 0.0;
+        smax = fabs(sk) > smax ? fabs(sk) : smax;
+      }
+      tag = (uint8_t)(smax > thr);
+    }
+    tags[c] = tag;
+  }
+}
+
+hipError_t launch_tag_flux(const void *buf, const uint8_t *status, const int32_t *srow, const int32_t *yrow,
+                           int64_t plane, int pitch, int xoff, int fx0, int fy0, int fw, int fh, int nrows, int Nx,
+                           int Ny, int perx, int pery, int fp32, const EosT<double> &eos,
+                           const unsigned long long *qmax, double thr, uint8_t *tags, hipStream_t s) {
+  const int64_t n = (int64_t)fw * nrows;
+  if (n <= 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(tag_flux_kernel<float>, grid_for(n), dim3(256), 0, s, static_cast<const float *>(buf),
+                       status, srow, yrow, plane, pitch, xoff, fx0, fy0, fw, fh, nrows, Nx, Ny, perx, pery, eos,
+                       qmax, thr, tags);
+  else
+    hipLaunchKernelGGL(tag_flux_kernel<double>, grid_for(n), dim3(256), 0, s, static_cast<const double *>(buf),
+                       status, srow, yrow, plane, pitch, xoff, fx0, fy0, fw, fh, nrows, Nx, Ny, perx, pery, eos,
+                       qmax, thr, tags);
+  return hipGetLastError();
+}
+
 // Refined features keep their levels: every tagged cell of a level-(l+1)
 // frame tags its parent in the level-l frame (one thread per stored fine frame
 // cell; several children write the same 1, which is benign).

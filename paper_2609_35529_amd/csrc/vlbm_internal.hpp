@@ -248,6 +248,17 @@ hipError_t launch_tag(const void *buf, const uint8_t *status, const int32_t *sro
                       int Nx, int Ny, int perx, int pery, int fp32, double thr, uint8_t *tags,
                       hipStream_t s);
 
+// Refinement sensor of eq. amr-sigma: flux_max folds max |Q_{alpha,k}| of a
+// level's active cells (its step tiles) into qmax[4] (bits, zeroed by the
+// caller before the first level); tag_flux tags, like launch_tag, the active
+// cells whose max_k |s_k| exceeds thr.
+hipError_t launch_flux_max(const void *buf, const Tile *tiles, int ntiles, int64_t plane, int pitch, int fp32,
+                           const EosT<double> &eos, unsigned long long *qmax, hipStream_t s);
+hipError_t launch_tag_flux(const void *buf, const uint8_t *status, const int32_t *srow, const int32_t *yrow,
+                           int64_t plane, int pitch, int xoff, int fx0, int fy0, int fw, int fh, int nrows, int Nx,
+                           int Ny, int perx, int pery, int fp32, const EosT<double> &eos,
+                           const unsigned long long *qmax, double thr, uint8_t *tags, hipStream_t s);
+
 // Clustering on the device. tag_parents: every tagged cell of a level-(l+1)
 // frame (fw per stored row) tags its parent in the level-l tags. tile_hits:
 // of the tile rows listed in trows (tiles of side T, ntx per tile row), the

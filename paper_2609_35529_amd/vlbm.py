@@ -85,6 +85,8 @@ vlbm_advance = _sig("vlbm_advance", _st, [_P, C.c_int])
 vlbm_conserved_totals = _sig("vlbm_conserved_totals", _st, [_P, _D, _D])
 vlbm_regrid = _sig("vlbm_regrid", _st, [_P, C.POINTER(vlbm_box), C.c_int])
 vlbm_tag = _sig("vlbm_tag", _st, [_P, C.c_int, C.c_double, C.POINTER(C.c_uint8)])
+vlbm_set_tag_indicator = _sig("vlbm_set_tag_indicator", _st, [_P, C.c_int])
+TAG_DENSITY, TAG_FLUX = 0, 1
 vlbm_tag_and_regrid = _sig("vlbm_tag_and_regrid", _st,
                            [_P, C.c_double, C.c_int, C.c_int, C.c_int])
 vlbm_get_boxes = _sig("vlbm_get_boxes", _st, [_P, C.POINTER(vlbm_box), C.c_int,
@@ -114,7 +116,7 @@ EXPORTED = ["vlbm_create", "vlbm_destroy", "vlbm_bind_pool", "vlbm_footprint_byt
             "vlbm_save", "vlbm_load", "vlbm_batch_advance", "vlbm_set_tuning", "vlbm_autotune",
             "vlbm_steps", "vlbm_active_cells", "vlbm_sync", "vlbm_last_error",
             "vlbm_set_profiling", "vlbm_kernel_times", "vlbm_set_sensor", "vlbm_get_beta",
-            "vlbm_set_time_stepping", "vlbm_time", "vlbm_get_state_noalloc", "vlbm_bind_allocator"]
+            "vlbm_set_time_stepping", "vlbm_time", "vlbm_get_state_noalloc", "vlbm_bind_allocator", "vlbm_set_tag_indicator"]
 
 
 class VLBMError(RuntimeError):
@@ -287,6 +289,10 @@ class Solver:
     def regrid(self, boxes):
         arr, n = make_boxes(boxes)
         check(vlbm_regrid(self._h, arr, n))
+
+    def set_tag_indicator(self, kind):
+        """TAG_DENSITY (density gradient) or TAG_FLUX (eq. amr-sigma)."""
+        check(vlbm_set_tag_indicator(self._h, int(kind)))
 
     def tag_and_regrid(self, threshold, buffer=4, min_box=16, max_box=128):
         check(vlbm_tag_and_regrid(self._h, threshold, buffer, min_box, max_box))
