@@ -240,12 +240,19 @@ vlbm_status vlbm_save(vlbm_ctx *ctx, void *buf, size_t *bytes);
 vlbm_status vlbm_load(vlbm_ctx *ctx, const void *buf, size_t bytes);
 
 /* Advance several contexts together, n_steps[i] coarse steps each, with the
- * phases of all contexts merged into shared launches. All contexts must use
- * the same stream, precision and refinement ratio, and none may have fused
- * sub-steps (tuning flag 16) in effect; either all or none use the adaptive
+ * phases of all contexts merged into shared launches (Sec. 3.2, Fig. 1: the
+ * sub-cycle of the deepest context; a shallower one joins the phases of the
+ * levels it has, and a fused finest level takes its two sub-steps in one
+ * launch at its parent's second sub-step, shared with the other fused
+ * levels there). All contexts must use the same stream, precision,
+ * refinement ratio and launch tuning; either all or none use the adaptive
  * relaxation, and either all or none the adaptive time step (each with its
- * own constants and clock): VLBM_EINVAL otherwise. Each context's results are
- * bit-identical to advancing it alone. */
+ * own constants and clock): VLBM_EINVAL otherwise. With the graph tuning flag
+ * (1024), two coarse steps of the merged launches are captured once per
+ * membership (the contexts, their launch tables and parities) as a hipGraph
+ * of kernel nodes and replayed; up to 16 captures are cached, and destroying
+ * a context drops those that hold it. Each context's results are
+ * bit-identical to advancing it alone. Synchronises. */
 vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nctx);
 
 /* Launch tuning (no effect on results, which are identical for every
@@ -255,7 +262,10 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
  * least two levels, one launch advances the finest level by both sub-steps of
  * its parent's step, the intermediate time level kept in LDS (temporal
  * blocking of the sub-cycling of Sec. 3), 512 XCD-contiguous order for the
- * fused launches only. Rebuilds the launch tables; the
+ * fused launches only, 1024 replay captured hipGraphs of two coarse steps
+ * (vlbm_advance of four or more steps, and vlbm_batch_advance; the
+ * environment variable VLBM_GRAPHS=1 sets it at creation). Rebuilds the
+ * launch tables; the
  * hierarchy and the time history are kept. VLBM_EINVAL for other values. */
 vlbm_status vlbm_set_tuning(vlbm_ctx *ctx, int tile_cells, int flags);
 

@@ -331,6 +331,7 @@ struct vlbm_ctx {
   LevelDesc *ddesc = nullptr;
   Segment *dseg = nullptr;
   long table_base = 0;
+  long tables_version = 0;  // bumped by every rebuild of the launch tables
   long flips[kMaxLevels] = {};  // buffer flips of each level per coarse step
   bool use_graphs = false;
   hipGraphExec_t graph = nullptr;  // two coarse steps from an even table parity
@@ -392,6 +393,8 @@ struct vlbm_ctx {
 };
 
 namespace {
+
+void drop_batch_graphs(vlbm_ctx *c);  // captured batches that hold c (vlbm_batch_advance)
 
 void free_level(vlbm_ctx *c, Level &L) {
   c->mem.release(L.buf[0]);
@@ -1320,6 +1323,7 @@ long tile_cells_sum(const Level &L, bool fused, size_t t0, size_t t1) {
 // per phase, each a run of segments of the segment table.
 vlbm_status build_tables(vlbm_ctx *c) {
   drop_graph(c);
+  c->tables_version += 1;
   vlbm_status sst = ensure_sensor(c);
   if (sst) return sst;
   c->phases.clear();
@@ -2243,7 +2247,8 @@ vlbm_status vlbm_create(const vlbm_params *params, void *stream, vlbm_ctx **out)
   if (const char *e = getenv("VLBM_NT_STORES")) c->step_flags |= atoi(e) ? STEP_NT_STORES : 0;
   if (const char *e = getenv("VLBM_TWO_CELLS")) c->step_flags |= atoi(e) ? STEP_TWO_CELLS : 0;
   if (const char *e = getenv("VLBM_XCD_CONTIGUOUS")) c->step_flags |= atoi(e) ? STEP_XCD_CONTIGUOUS : 0;
-  if (const char *e = getenv("VLBM_GRAPHS")) c->use_graphs = atoi(e) != 0;
+  if (const char *e = getenv("VLBM_GRAPHS")) c->step_flags |= atoi(e) ? STEP_GRAPHS : 0;
+  c->use_graphs = (c->step_flags & STEP_GRAPHS) != 0;
   c->gm1 = p.gamma - 1.0;
   c->eos = EosT<double>{p.eos, p.gamma - 1.0, p.eos_a, p.eos_b, p.gamma * p.eos_a};
   c->h = 1.0 / (2.0 * p.c);
@@ -2256,6 +2261,7 @@ void vlbm_destroy(vlbm_ctx *c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   drop_graph(c);
+  drop_batch_graphs(c);
   for (hipEvent_t ev : c->pev) (void)hipEventDestroy(ev);
   for (int l = 0; l < kMaxLevels; ++l) free_level(c, c->lv[l]);
   c->mem.release(c->ddesc);
@@ -2870,6 +2876,172 @@ vlbm_status vlbm_load(vlbm_ctx *c, const void *buf, size_t bytes) {
   return build_tables(c);
 }
 
+}  // extern "C"
+
+namespace {
+
+// A merged batch of contexts: the launches of one coarse step for both table
+// parities e (relative to the batch's start). A phase of the merged schedule
+// (the deepest context's, unfused) is one step-kernel launch over the
+// segments of every context that steps that level there, plus one fused-
+// kernel launch over the fused finest levels placed at its second sub-step.
+struct BatchLaunch {
+  int32_t seg0 = 0, nseg = 0, nblocks = 0, flags = 0, first = 0;
+  double ak = 0.0;
+  bool sensor_clear = false;
+};
+struct BatchPlan {
+  std::vector<Segment> segs;
+  std::vector<BatchLaunch> launches[2];
+  std::vector<vlbm_ctx *> adt_ctx;  // contexts whose link speed is updated every coarse step
+  Segment *dseg = nullptr;
+};
+
+vlbm_status plan_batch(vlbm_ctx *const *ctxs, const std::vector<int> &act, BatchPlan &bp) {
+  vlbm_ctx *c0 = ctxs[act[0]];
+  const int r = c0->p.r;
+  int D = 0;
+  for (int i : act) D = std::max(D, ctxs[i]->nlev);
+  std::vector<std::pair<int, int>> ph;
+  schedule(0, 1, D, r, ph);
+  const size_t P = ph.size();
+  // per context and merged phase: its own phase index there (-1: none), and
+  // whether that is its fused finest level (taken at the second sub-step)
+  std::vector<std::vector<int>> occ(act.size());
+  for (size_t a = 0; a < act.size(); ++a) {
+    vlbm_ctx *c = ctxs[act[a]];
+    std::vector<std::vector<int>> idx(kMaxLevels);
+    for (size_t p = 0; p < c->phases.size(); ++p) idx[c->phases[p].first].push_back((int)p);
+    std::vector<int> seen(kMaxLevels, 0);
+    const bool fz = fused_active(c);
+    for (size_t p = 0; p < P; ++p) {
+      const int l = ph[p].first;
+      int pi = -1;
+      if (l < c->nlev) {
+        if (fz && l == c->nlev - 1) {
+          // the fused launch replaces this level's sub-steps k = 1, 2
+          if (ph[p].second == r) pi = idx[l][seen[l]++];
+        } else {
+          pi = idx[l][seen[l]++];
+        }
+      }
+      occ[a].push_back(pi);
+    }
+    for (int l = 0; l < c->nlev; ++l)
+      if (seen[l] != (int)idx[l].size())
+        return fail(VLBM_EINVAL, "internal: batched schedule does not cover context %d", act[a]);
+  }
+  for (int i : act)
+    if (ctxs[i]->adt) bp.adt_ctx.push_back(ctxs[i]);
+  for (int e = 0; e < 2; ++e)
+    for (size_t p = 0; p < P; ++p)
+      for (int fused = 0; fused < 2; ++fused) {
+        BatchLaunch L;
+        L.seg0 = (int32_t)bp.segs.size();
+        int32_t fb = 0;
+        bool cfl_emit = false, clear = false;
+        for (size_t a = 0; a < act.size(); ++a) {
+          vlbm_ctx *c = ctxs[act[a]];
+          const int pi = occ[a][p];
+          if (pi < 0 || c->phase_blocks[pi] == 0) continue;
+          if ((c->phases[pi].second == 0) != (fused == 1)) continue;
+          const int ei = table_parity(c) ^ e;
+          const size_t Pi = c->phases.size();
+          bp.segs.push_back({c->ddesc + ei * Pi + pi, fb, c->phase_blocks[pi]});
+          fb += c->phase_blocks[pi];
+          const LevelDesc &D0 = c->hdesc[ei * Pi + pi];
+          cfl_emit |= c->adt && D0.emit_cfl;
+          // a context whose first phase this is, and which also accumulates
+          // the next Qmax in it, has its slot cleared first
+          clear |= c->sensor && pi == 0 && c->hdesc[ei * Pi].emit_qmax;
+        }
+        L.nseg = (int32_t)bp.segs.size() - L.seg0;
+        if (L.nseg == 0) continue;
+        L.nblocks = fb;
+        L.first = fused ? 0 : ph[p].second == 1;
+        L.ak = ak_of(fused ? 0 : ph[p].second, r);
+        L.flags = c0->step_flags | (fused ? STEP_FUSED_PHASE : 0);
+        if (fused && (c0->step_flags & STEP_XCD_FUSED)) L.flags |= STEP_XCD_CONTIGUOUS;
+        if (c0->adt) L.flags |= STEP_ADAPTIVE_DT | (cfl_emit ? STEP_CFL_EMIT : 0);
+        if (c0->sensor && !fused) L.flags |= STEP_SENSOR;
+        L.sensor_clear = clear;
+        bp.launches[e].push_back(L);
+      }
+  return VLBM_OK;
+}
+
+// The launches of one coarse step of relative parity e.
+hipError_t launch_batch_step(const BatchPlan &bp, int e, int fp32, hipStream_t s) {
+  hipError_t err = hipSuccess;
+  // adaptive time step: every context's link speed for this coarse step, from
+  // the bound its previous coarse step's last launches left
+  for (vlbm_ctx *c : bp.adt_ctx)
+    if (err == hipSuccess) err = launch_cfl_finalize(c->ddyn, c->dcmax, s);
+  for (const BatchLaunch &L : bp.launches[e]) {
+    if (err != hipSuccess) break;
+    StepLaunch a{};
+    a.segs = bp.dseg + L.seg0;
+    a.nseg = L.nseg;
+    a.nblocks = L.nblocks;
+    a.first = L.first;
+    a.flags = L.flags;
+    a.ak = L.ak;
+    if (L.sensor_clear) err = launch_sensor(a, 1, fp32, s);
+    if (err == hipSuccess) err = launch_step(a, fp32, s);
+  }
+  return err;
+}
+
+// Captured batches: two coarse steps (relative parities 0 and 1) of a fixed
+// list of contexts, each at the table version and parity it had at capture.
+struct BatchGraph {
+  std::vector<long> key;  // per context: pointer, tables_version, table parity
+  std::vector<vlbm_ctx *> ctxs;
+  vlbm_ctx *owner = nullptr;  // whose memory holds the segment table
+  BatchPlan plan;
+  hipGraphExec_t exec = nullptr;
+  long last_use = 0;
+};
+std::mutex g_batch_mu;
+std::vector<BatchGraph> g_batch_graphs;
+long g_batch_clock = 0;
+constexpr size_t kBatchGraphs = 16;
+
+void release_batch_graph(BatchGraph &g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  g.exec = nullptr;
+  if (g.owner) g.owner->mem.release(g.plan.dseg);
+  g.plan.dseg = nullptr;
+}
+
+// Forget every captured batch that holds c (called before c goes away).
+void drop_batch_graphs(vlbm_ctx *c) {
+  std::lock_guard<std::mutex> lock(g_batch_mu);
+  for (size_t i = 0; i < g_batch_graphs.size();) {
+    BatchGraph &g = g_batch_graphs[i];
+    if (std::find(g.ctxs.begin(), g.ctxs.end(), c) != g.ctxs.end()) {
+      release_batch_graph(g);
+      g_batch_graphs.erase(g_batch_graphs.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+}
+
+std::vector<long> batch_key(vlbm_ctx *const *ctxs, const std::vector<int> &act) {
+  std::vector<long> key;
+  for (int i : act) {
+    key.push_back((long)reinterpret_cast<uintptr_t>(ctxs[i]));
+    key.push_back(ctxs[i]->tables_version);
+    key.push_back(table_parity(ctxs[i]));
+  }
+  return key;
+}
+
+}  // namespace
+
+extern "C" {
+
 vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nctx) {
   if (nctx <= 0) return VLBM_OK;
   if (!ctxs || !n_steps) return fail(VLBM_EINVAL, "null argument");
@@ -2880,8 +3052,8 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
     if (n_steps[i] < 0) return fail(VLBM_EINVAL, "negative step count");
     if (c->stream != c0->stream || c->p.precision != c0->p.precision || c->p.r != c0->p.r)
       return fail(VLBM_EINVAL, "batched contexts must share stream, precision and ratio");
-    if (fused_active(c))
-      return fail(VLBM_EINVAL, "context %d uses fused sub-steps, which batched launches do not take", i);
+    if ((c->step_flags & ~STEP_F64_MATH) != (c0->step_flags & ~STEP_F64_MATH))
+      return fail(VLBM_EINVAL, "batched contexts must share their launch tuning");
     if (c->sensor != c0->sensor)
       return fail(VLBM_EINVAL, "batched contexts must all use the adaptive relaxation, or none");
     if (c->adt != c0->adt)
@@ -2890,7 +3062,6 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
       if (ctxs[j] == c) return fail(VLBM_EINVAL, "context %d listed twice", i);
   }
   std::vector<long> rem(n_steps, n_steps + nctx);
-  const int r = c0->p.r;
   for (;;) {
     std::vector<int> act;
     long m = 0;
@@ -2906,105 +3077,74 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
       rem[act[0]] -= m;
       continue;
     }
-    // merged schedule of the deepest context; shallower ones join the
-    // phases of the levels they have, occurrence by occurrence
-    int D = 0;
-    for (int i : act) D = std::max(D, ctxs[i]->nlev);
-    std::vector<std::pair<int, int>> ph;
-    schedule(0, 1, D, r, ph);
-    const size_t P = ph.size();
-    std::vector<std::vector<int>> occ_index(act.size());  // per context: phase index of the j-th phase of level l
-    for (size_t a = 0; a < act.size(); ++a) {
-      vlbm_ctx *c = ctxs[act[a]];
-      std::vector<int> seen(kMaxLevels, 0);
-      std::vector<std::vector<int>> idx(kMaxLevels);
-      for (size_t p = 0; p < c->phases.size(); ++p) idx[c->phases[p].first].push_back((int)p);
-      std::vector<int> &oi = occ_index[a];
-      for (size_t p = 0; p < P; ++p) {
-        const int l = ph[p].first;
-        oi.push_back(l < c->nlev ? idx[l][seen[l]++] : -1);
-      }
-    }
-    std::vector<Segment> segs;
-    std::vector<int32_t> seg0(2 * P), nseg(2 * P), nblk(2 * P);
-    for (int e = 0; e < 2; ++e)
-      for (size_t p = 0; p < P; ++p) {
-        seg0[e * P + p] = (int32_t)segs.size();
-        int32_t fb = 0;
-        for (size_t a = 0; a < act.size(); ++a) {
-          vlbm_ctx *c = ctxs[act[a]];
-          const int pi = occ_index[a][p];
-          if (pi < 0 || c->phase_blocks[pi] == 0) continue;
-          const int ei = table_parity(c) ^ e;
-          const size_t Pi = c->phases.size();
-          segs.push_back({c->ddesc + ei * Pi + pi, fb, c->phase_blocks[pi]});
-          fb += c->phase_blocks[pi];
-        }
-        nseg[e * P + p] = (int32_t)segs.size() - seg0[e * P + p];
-        nblk[e * P + p] = fb;
-      }
     for (int i : act) {  // adaptive relaxation stage 0 and the CFL bound where the state changed
       vlbm_status st = sensor_init(ctxs[i], table_parity(ctxs[i]));
       if (!st) st = cfl_init(ctxs[i], table_parity(ctxs[i]));
       if (st) return st;
     }
-    Segment *dseg = static_cast<Segment *>(c0->mem.alloc(sizeof(Segment) * std::max<size_t>(1, segs.size())));
-    if (!dseg) return fail(VLBM_ENOMEM, "batch segment table");
-    HIPCHK(hipMemcpyAsync(dseg, segs.data(), sizeof(Segment) * segs.size(), hipMemcpyHostToDevice, c0->stream));
-    for (long s2 = 0; s2 < m; ++s2) {
-      const int e = (int)(s2 & 1);
-      // adaptive time step: every context's link speed for this coarse step,
-      // from the bound its previous coarse step's last launches left
-      for (int i : act)
-        if (ctxs[i]->adt) {
-          const hipError_t err = launch_cfl_finalize(ctxs[i]->ddyn, ctxs[i]->dcmax, c0->stream);
-          if (err != hipSuccess) {
-            c0->mem.release(dseg);
-            return fail(VLBM_EDEVICE, "batched launch: %s", hipGetErrorString(err));
-          }
+    vlbm_ctx *lead = ctxs[act[0]];
+    const bool graphs = lead->use_graphs && lead->stream != nullptr && m >= 4;
+    long done = 0;
+    if (graphs) {
+      // replay a captured pair of coarse steps (capturing it the first time)
+      std::lock_guard<std::mutex> lock(g_batch_mu);
+      const std::vector<long> key = batch_key(ctxs, act);
+      BatchGraph *g = nullptr;
+      for (BatchGraph &b : g_batch_graphs)
+        if (b.key == key) g = &b;
+      if (!g) {
+        if (g_batch_graphs.size() >= kBatchGraphs) {  // evict the least recently used
+          auto it = std::min_element(g_batch_graphs.begin(), g_batch_graphs.end(),
+                                     [](const BatchGraph &x, const BatchGraph &y) { return x.last_use < y.last_use; });
+          release_batch_graph(*it);
+          g_batch_graphs.erase(it);
         }
-      for (size_t p = 0; p < P; ++p) {
-        if (nseg[e * P + p] == 0) continue;
-        StepLaunch L{};
-        L.segs = dseg + seg0[e * P + p];
-        L.nseg = nseg[e * P + p];
-        L.nblocks = nblk[e * P + p];
-        L.first = ph[p].second == 1;
-        L.flags = c0->step_flags;
-        L.ak = ak_of(ph[p].second, r);
-        if (c0->adt) {
-          L.flags |= STEP_ADAPTIVE_DT;
-          // the variant that folds the CFL term, where some context's level
-          // takes its last step of the coarse step in this launch
-          for (size_t a = 0; a < act.size(); ++a) {
-            const vlbm_ctx *ca = ctxs[act[a]];
-            const int pi = occ_index[a][p];
-            if (pi >= 0 && ca->hdesc[(table_parity(ca) ^ e) * ca->phases.size() + pi].emit_cfl)
-              L.flags |= STEP_CFL_EMIT;
-          }
-        }
-        hipError_t err = hipSuccess;
-        if (c0->sensor) {
-          // a context whose first phase this is, and which also accumulates
-          // the next Qmax in it, has its slot cleared first
-          bool clear = false;
-          for (size_t a = 0; a < act.size(); ++a) {
-            const vlbm_ctx *ca = ctxs[act[a]];
-            const int ei = table_parity(ca) ^ e;
-            clear |= occ_index[a][p] == 0 && ca->hdesc[ei * ca->phases.size()].emit_qmax;
-          }
-          if (clear) err = launch_sensor(L, 1, c0->fp32, c0->stream);
-          L.flags |= STEP_SENSOR;
-        }
-        if (err == hipSuccess) err = launch_step(L, c0->fp32, c0->stream);
+        BatchGraph nb;
+        nb.key = key;
+        for (int i : act) nb.ctxs.push_back(ctxs[i]);
+        nb.owner = lead;
+        vlbm_status st = plan_batch(ctxs, act, nb.plan);
+        if (st) return st;
+        nb.plan.dseg = static_cast<Segment *>(lead->mem.alloc(sizeof(Segment) * std::max<size_t>(1, nb.plan.segs.size())));
+        if (!nb.plan.dseg) return fail(VLBM_ENOMEM, "batch segment table");
+        HIPCHK(hipMemcpyAsync(nb.plan.dseg, nb.plan.segs.data(), sizeof(Segment) * nb.plan.segs.size(),
+                              hipMemcpyHostToDevice, lead->stream));
+        HIPCHK(hipStreamSynchronize(lead->stream));
+        hipGraph_t graph = nullptr;
+        HIPCHK(hipStreamBeginCapture(lead->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t err = launch_batch_step(nb.plan, 0, lead->fp32, lead->stream);
+        if (err == hipSuccess) err = launch_batch_step(nb.plan, 1, lead->fp32, lead->stream);
+        const hipError_t ec = hipStreamEndCapture(lead->stream, &graph);
+        if (err == hipSuccess) err = ec;
+        if (err == hipSuccess) err = hipGraphInstantiate(&nb.exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
         if (err != hipSuccess) {
-          c0->mem.release(dseg);
-          return fail(VLBM_EDEVICE, "batched launch: %s", hipGetErrorString(err));
+          release_batch_graph(nb);
+          return fail(VLBM_EDEVICE, "batched graph: %s", hipGetErrorString(err));
         }
+        g_batch_graphs.push_back(std::move(nb));
+        g = &g_batch_graphs.back();
       }
+      g->last_use = ++g_batch_clock;
+      for (; done + 2 <= m; done += 2) HIPCHK(hipGraphLaunch(g->exec, lead->stream));
+      if (done < m) {  // an odd last coarse step, relative parity 0, eagerly
+        HIPCHK(launch_batch_step(g->plan, 0, lead->fp32, lead->stream));
+        done += 1;
+      }
+    } else {
+      BatchPlan bp;
+      vlbm_status st = plan_batch(ctxs, act, bp);
+      if (st) return st;
+      bp.dseg = static_cast<Segment *>(lead->mem.alloc(sizeof(Segment) * std::max<size_t>(1, bp.segs.size())));
+      if (!bp.dseg) return fail(VLBM_ENOMEM, "batch segment table");
+      HIPCHK(hipMemcpyAsync(bp.dseg, bp.segs.data(), sizeof(Segment) * bp.segs.size(), hipMemcpyHostToDevice,
+                            lead->stream));
+      hipError_t err = hipSuccess;
+      for (; done < m && err == hipSuccess; ++done) err = launch_batch_step(bp, (int)(done & 1), lead->fp32, lead->stream);
+      if (err == hipSuccess) err = hipStreamSynchronize(lead->stream);
+      lead->mem.release(bp.dseg);
+      if (err != hipSuccess) return fail(VLBM_EDEVICE, "batched launch: %s", hipGetErrorString(err));
     }
-    HIPCHK(hipStreamSynchronize(c0->stream));
-    c0->mem.release(dseg);
     for (int i : act) {
       count_steps(ctxs[i], m);
       rem[i] -= m;
@@ -3016,10 +3156,11 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
 vlbm_status vlbm_set_tuning(vlbm_ctx *c, int tile_cells, int flags) {
   if (!c) return fail(VLBM_EINVAL, "null context");
   if (tile_cells < 64 || tile_cells > (1 << 20) ||
-      (flags & ~(STEP_NT_STORES | STEP_TWO_CELLS | STEP_XCD_CONTIGUOUS | STEP_FUSE2 | STEP_XCD_FUSED)))
+      (flags & ~(STEP_NT_STORES | STEP_TWO_CELLS | STEP_XCD_CONTIGUOUS | STEP_FUSE2 | STEP_XCD_FUSED | STEP_GRAPHS)))
     return fail(VLBM_EINVAL, "bad tuning (tile_cells %d, flags %d)", tile_cells, flags);
   c->tile_cells = tile_cells;
   c->step_flags = flags | (c->step_flags & STEP_F64_MATH);
+  c->use_graphs = (flags & STEP_GRAPHS) != 0;
   if (!c->have_hierarchy) return VLBM_OK;
   // same hierarchy and time history, new tile decomposition
   std::vector<vlbm_box> boxes = c->boxes;

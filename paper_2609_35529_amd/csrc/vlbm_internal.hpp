@@ -99,6 +99,7 @@ enum StepFlags : int32_t {
   STEP_CFL_EMIT = 256,       // launch-uniform: the level's last step launch of the coarse step folds
                              // the CFL term of its stored cells into cfl_next (emit_cfl)
   STEP_XCD_FUSED = 512,      // tuning: XCD-contiguous order for the fused launches only
+  STEP_GRAPHS = 1024,        // tuning: replay captured graphs of two coarse steps (kernels unaffected)
 };
 
 // Device scalars of the adaptive time step, updated once per coarse step by

@@ -87,3 +87,44 @@ def test_set_state_after_steps_keeps_parity():
     a.advance(5)
     b.advance(5)
     assert _same(_pops(a, 2), _pops(b, 2))
+
+
+def _mix_fused():
+    reqs = [dict(n0=32, nlev=1, seed=11), dict(n0=64, nlev=2, seed=12), dict(n0=48, nlev=3, seed=13),
+            dict(n0=16, nlev=2, seed=14), dict(n0=64, nlev=3, seed=15), dict(n0=40, nlev=2, seed=16)]
+    return [wl.request_case(dict(r, steps=0)) for r in reqs]
+
+
+@pytest.mark.parametrize("flags", [16, 16 | 1024, 17 | 1024])
+@pytest.mark.parametrize("precision", [0, 2])
+def test_fused_and_graph_batches_equal_alone(precision, flags):
+    """Contexts of one, two and three levels with fused finest levels (tuning
+    flag 16), advanced in batches whose membership changes (all six, then four,
+    then two, then all six again), eagerly or as replayed graphs (flag 1024,
+    interleaved with unrelated eager work): every context equals the same
+    context advanced alone, bit for bit, after every batch."""
+    import torch
+    from paper_2609_35529_amd import vlbm
+    stream = torch.cuda.Stream()
+    cases = _mix_fused()
+    rounds = [([0, 1, 2, 3, 4, 5], [6, 9, 4, 8, 10, 7]), ([1, 2, 4, 5], [5, 6, 5, 9]),
+              ([2, 4], [8, 4]), ([0, 1, 2, 3, 4, 5], [6, 6, 6, 6, 6, 6])]
+    alone = []
+    for case in cases:
+        g = gpu_solver(case, precision, stream=stream)
+        g.set_tuning(256, flags & ~1024)
+        alone.append(g)
+    sol = []
+    for case in cases:
+        g = gpu_solver(case, precision, stream=stream)
+        g.set_tuning(256, flags)
+        sol.append(g)
+    for ids, steps in rounds:
+        for i, n in zip(ids, steps):
+            alone[i].advance(n)
+        vlbm.batch_advance([sol[i] for i in ids], steps)
+        torch.cuda.synchronize()
+        assert torch.ones(777, device="cuda").sum().item() == 777.0
+        for i in range(len(cases)):
+            assert sol[i].steps() == alone[i].steps()
+            assert _same(_pops(sol[i], cases[i].nlev), _pops(alone[i], cases[i].nlev)), (ids, i)
