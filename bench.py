@@ -324,9 +324,10 @@ def copy_probe(gib=2.0, reps=20):
 
 
 def serve_benchmark(n_requests=48, rate=64.0, seed=0, budget_gib=64.0, quantum=25,
-                    check_accuracy=True, precision="fp32s", policy="share"):
+                    check_accuracy=True, precision="fp32s", policy="share", tuning=None, seq_tuning=None):
     """Served stream: continuous batching (FP32 bulk, FP64 interfaces) against
-    sequential plain FP64, same requests, same arrival times."""
+    sequential plain FP64, same requests, same arrival times. tuning /
+    seq_tuning: (tile_cells, flags) of the served and the sequential solves."""
     import numpy as np
     import torch
     from paper_2609_35529_amd import serve, vlbm, workloads as wl
@@ -335,28 +336,47 @@ def serve_benchmark(n_requests=48, rate=64.0, seed=0, budget_gib=64.0, quantum=2
     reqs = wl.request_stream(n_requests, rate, seed=seed)
     prec = {"fp32": vlbm.FP32, "fp32s": vlbm.FP32_STORAGE, "fp64": vlbm.FP64}[precision]
     srv = serve.Server(int(budget_gib * 2 ** 30), precision=prec, quantum=quantum,
-                       stream=stream, keep_states=check_accuracy, policy=policy)
+                       stream=stream, keep_states=check_accuracy, policy=policy, tuning=tuning)
     print(f"[bench] served stream (batched {precision})", file=sys.stderr, flush=True)
     served, wall_s = srv.run(reqs)
     print("[bench] sequential FP64", file=sys.stderr, flush=True)
     seq, wall_q = serve.run_sequential(reqs, precision=vlbm.FP64, stream=stream,
-                                       keep_states=check_accuracy)
+                                       keep_states=check_accuracy, tuning=seq_tuning)
     out = {"requests": n_requests, "rate_per_s": rate, "seed": seed,
-           "served_precision": precision, "policy": policy,
+           "served_precision": precision, "policy": policy, "tuning": tuning, "seq_tuning": seq_tuning,
            "batched": serve.summarize(served, wall_s),
            "sequential_fp64": serve.summarize(seq, wall_q)}
     if check_accuracy:
         ref = {r.rid: r.state for r in seq}
-        worst = 0.0
+        worst, nan_mismatch, compared = 0.0, 0, 0
         for r in served:
             Uo = ref[r.rid]
-            m = smooth_mask(Uo)
+            nan_mismatch += int(np.count_nonzero(np.isnan(Uo) != np.isnan(r.state)))
+            m = smooth_mask(Uo) & np.isfinite(r.state).all(axis=0)
+            if not m.any():
+                continue
+            compared += 1
             for k in range(4):
                 scale = np.nanmax(np.abs(Uo[k]))
-                if m.any():
-                    worst = max(worst, float(np.max(np.abs(r.state[k][m] - Uo[k][m])) / scale))
+                worst = max(worst, float(np.max(np.abs(r.state[k][m] - Uo[k][m])) / scale))
         out["served_vs_fp64_smooth_rel_err"] = worst
+        out["served_vs_fp64_compared_solves"] = compared
+        out["served_vs_fp64_nan_mismatch_cells"] = nan_mismatch
     return out
+
+
+def _tuning_arg(s):
+    return tuple(int(x) for x in s.split(",")) if s else None
+
+
+def serve_sweep(args):
+    """The served benchmark at every arrival rate of --rates (else --rate); a
+    single rate gives one record, several a list under "rates"."""
+    rates = [float(x) for x in args.rates.split(",")] if args.rates else [args.rate]
+    recs = [serve_benchmark(args.requests, r, precision=args.serve_precision, policy=args.serve_policy,
+                            tuning=_tuning_arg(args.serve_tuning), seq_tuning=_tuning_arg(args.seq_tuning))
+            for r in rates]
+    return recs[0] if len(recs) == 1 else {"rates": recs}
 
 
 def main():
@@ -388,6 +408,12 @@ def main():
     ap.add_argument("--rate", type=float, default=64.0)
     ap.add_argument("--serve-precision", default="fp32s", choices=["fp32", "fp32s", "fp64"])
     ap.add_argument("--serve-policy", default="share", choices=["share", "srpt", "fixed"])
+    ap.add_argument("--serve-tuning", default=None, metavar="TILE,FLAGS",
+                    help="launch tuning of the served solves (vlbm_set_tuning)")
+    ap.add_argument("--seq-tuning", default=None, metavar="TILE,FLAGS",
+                    help="launch tuning of the sequential FP64 solves")
+    ap.add_argument("--rates", default=None, metavar="R1,R2,...",
+                    help="arrival rates (requests/s) of the served stream; default: --rate")
     ap.add_argument("--n0-3d", type=int, default=256, help="coarse cells per axis of the 3-D workload")
     ap.add_argument("--adaptive-dt", type=float, default=None, metavar="KAPPA",
                     help="adaptive time step: c = 2 kappa max(|u| + c_s) every coarse step")
@@ -409,9 +435,7 @@ def main():
     if args.workload in DYNAMIC:
         args.no_tune = True  # the hierarchy changes every few steps
     if args.serve_only:
-        print(json.dumps(serve_benchmark(args.requests, args.rate,
-                                         precision=args.serve_precision,
-                                         policy=args.serve_policy)))
+        print(json.dumps(serve_sweep(args)))
         return
     import torch
     from paper_2609_35529_amd import vlbm
@@ -609,9 +633,7 @@ def main():
         "healthy": healthy,
     }
     if not args.no_serve:
-        out["served"] = serve_benchmark(args.requests, args.rate,
-                                        precision=args.serve_precision,
-                                        policy=args.serve_policy)
+        out["served"] = serve_sweep(args)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         if args.workload == "kh4096":

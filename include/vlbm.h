@@ -272,7 +272,11 @@ vlbm_status vlbm_set_tuning(vlbm_ctx *ctx, int tile_cells, int flags);
 /* Autotuner: time tile sizes {128, 256, 512, 1024} x workgroup orders x store
  * kinds (x fused sub-steps on or off, where they apply) on real
  * coarse steps of this context (every trial advances the solution by
- * 1 + steps_per_trial coarse steps) and keep the fastest. The choice is cached
+ * 1 + steps_per_trial coarse steps) and keep the fastest. A context created
+ * with a stream of its own then times the fastest with and without graph
+ * replay (flag 1024; 2 + m and 4 + m more coarse steps, m = steps_per_trial
+ * rounded up to an even number of at least 4) and keeps replay if it saves
+ * more than 2%. The choice is cached
  * per geometry (base grid, ratio, precision, boxes) for the process, so a
  * repeated call advances nothing. Reports the choice in tile_cells/flags
  * (either may be NULL). */

@@ -3180,6 +3180,22 @@ static std::string tuning_key(const vlbm_ctx *c) {
   return k;
 }
 
+namespace {
+// One timed autotuning trial: install (tile_cells, flags), advance `warm`
+// untimed coarse steps, then time `steps` of them between two events.
+vlbm_status time_trial(vlbm_ctx *c, int tile_cells, int flags, int warm, int steps, hipEvent_t e0,
+                       hipEvent_t e1, float *ms) {
+  vlbm_status st = vlbm_set_tuning(c, tile_cells, flags);
+  if (!st) st = advance_impl(c, warm);
+  if (!st && hipEventRecord(e0, c->stream) != hipSuccess) st = fail(VLBM_EDEVICE, "event");
+  if (!st) st = advance_impl(c, steps);
+  if (!st && hipEventRecord(e1, c->stream) != hipSuccess) st = fail(VLBM_EDEVICE, "event");
+  if (!st && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(ms, e0, e1) != hipSuccess))
+    st = fail(VLBM_EDEVICE, "event timing");
+  return st;
+}
+}  // namespace
+
 vlbm_status vlbm_autotune(vlbm_ctx *c, int steps_per_trial, int *tile_cells, int *flags) {
   if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "no hierarchy installed");
   if (steps_per_trial < 1) return fail(VLBM_EINVAL, "steps_per_trial < 1");
@@ -3204,15 +3220,10 @@ vlbm_status vlbm_autotune(vlbm_ctx *c, int steps_per_trial, int *tile_cells, int
     for (int tcell : tiles)
       for (int oi = 0; oi < norders; ++oi) {
         const int ord = orders[oi];
-        const int fl = (c->step_flags & ~(STEP_XCD_CONTIGUOUS | STEP_FUSE2 | STEP_NT_STORES | STEP_F64_MATH)) | ord;
-        st = vlbm_set_tuning(c, tcell, fl);
-        if (!st) st = advance_impl(c, 1);  // warm
-        if (!st && hipEventRecord(e0, c->stream) != hipSuccess) st = fail(VLBM_EDEVICE, "event");
-        if (!st) st = advance_impl(c, steps_per_trial);
-        if (!st && hipEventRecord(e1, c->stream) != hipSuccess) st = fail(VLBM_EDEVICE, "event");
+        const int fl = (c->step_flags & ~(STEP_XCD_CONTIGUOUS | STEP_FUSE2 | STEP_NT_STORES | STEP_F64_MATH |
+                                          STEP_GRAPHS)) | ord;
         float ms = 0.f;
-        if (!st && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-          st = fail(VLBM_EDEVICE, "event timing");
+        st = time_trial(c, tcell, fl, 1, steps_per_trial, e0, e1, &ms);
         if (st) {
           (void)hipEventDestroy(e0);
           (void)hipEventDestroy(e1);
@@ -3223,6 +3234,21 @@ vlbm_status vlbm_autotune(vlbm_ctx *c, int steps_per_trial, int *tile_cells, int
           choice = {tcell, fl};
         }
       }
+    // graph replay of the chosen launches (an even number of steps, at least
+    // four, so that every step of the trial is replayed) where the context has
+    // a stream of its own; kept only if it saves more than 2%
+    if (c->stream != nullptr && !c->prof) {
+      const int gsteps = std::max(4, (steps_per_trial + 1) & ~1);
+      float plain = 0.f, graphed = 0.f;
+      st = time_trial(c, choice.first, choice.second, 2, gsteps, e0, e1, &plain);
+      if (!st) st = time_trial(c, choice.first, choice.second | STEP_GRAPHS, 4, gsteps, e0, e1, &graphed);
+      if (st) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return st;
+      }
+      if (graphed < 0.98f * plain) choice.second |= STEP_GRAPHS;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     hit = g_tuned.emplace(key, choice).first;

@@ -76,7 +76,7 @@ class Server:
 
     def __init__(self, budget_bytes: int, precision=vlbm.FP32_STORAGE, quantum=25,
                  max_resident=64, stream=None, keep_states=False, slice_s=0.02,
-                 policy="share", health_every=8):
+                 policy="share", health_every=8, tuning=None):
         """Per iteration, resident solves advance together in shared launches.
         policy "fixed": every solve takes `quantum` coarse steps.
         policy "share": every solve gets an equal share of a slice_s-second
@@ -93,6 +93,7 @@ class Server:
         self.slice_s = slice_s
         self.policy = policy
         self.health_every = int(health_every)
+        self.tuning = tuning  # (tile_cells, flags) of every solve (vlbm_set_tuning), or None
 
     def step_cost(self, case):
         esz = 4 if self.precision == vlbm.FP32 else 8
@@ -143,6 +144,8 @@ class Server:
                     break
                 queue.pop(0)
                 s = vlbm.Solver.from_case(case, precision=self.precision, stream=self.stream)
+                if self.tuning:
+                    s.set_tuning(*self.tuning)
                 if self.health_every > 0 and not s.check_health():  # a bad initial state
                     now = time.perf_counter() - t0
                     results.append(Result(req["id"], req["arrival"] * time_scale, now, now, 0, 0.0,
@@ -193,8 +196,9 @@ class Server:
 
 
 def run_sequential(requests: List[dict], precision=vlbm.FP64, stream=None, time_scale=1.0,
-                   keep_states=False):
-    """One solve at a time in arrival order, no batching."""
+                   keep_states=False, tuning=None):
+    """One solve at a time in arrival order, no batching (tuning: the
+    single-solve launch settings, vlbm_set_tuning)."""
     results: List[Result] = []
     t0 = time.perf_counter()
     for req in sorted(requests, key=lambda r: r["arrival"]):
@@ -204,6 +208,8 @@ def run_sequential(requests: List[dict], precision=vlbm.FP64, stream=None, time_
         case = wl.request_case(req)
         adm = time.perf_counter() - t0
         s = vlbm.Solver.from_case(case, precision=precision, stream=stream)
+        if tuning:
+            s.set_tuning(*tuning)
         s.advance(req["steps"])
         state = s.get_state(0) if keep_states else None
         s.sync()

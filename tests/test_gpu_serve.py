@@ -73,3 +73,33 @@ def test_a_faulty_request_fails_alone():
             assert np.array_equal(r.state, by_id[r.rid].state, equal_nan=True), r.rid
     stats = serve.summarize(mixed, wall)
     assert stats["failed"] == 1 and stats["solves"] == len(reqs) - 1
+
+
+@pytest.mark.parametrize("tuning", [None, (256, 16 | 1024)])
+def test_served_fp64_mix_matches_oracle_per_request(tuning):
+    """Every request of a served FP64 mix (one to three levels, different
+    sizes, arrival while others run; plain launches, or fused finest levels
+    with replayed graphs) ends in the level-0 state the oracle computes for
+    that request alone: NaN holes in the same cells, values within 1e-14
+    relative (the populations are bit-identical; the moment sums may round
+    in another order)."""
+    import torch
+    from paper_2609_35529_amd import serve, workloads as wl
+    from tests import exact
+    stream = torch.cuda.Stream()
+    reqs = wl.request_stream(8, rate=400.0, seed=23, sizes=(32, 48, 64), steps_range=(10, 40))
+    assert {r["nlev"] for r in reqs} == {1, 2, 3}
+    srv = serve.Server(budget_bytes=2 << 30, precision=0, quantum=5, stream=stream,
+                       keep_states=True, tuning=tuning)
+    mixed, _ = srv.run(reqs, time_scale=0.0)
+    by_req = {q["id"]: q for q in reqs}
+    assert sorted(r.rid for r in mixed) == sorted(by_req)
+    for r in mixed:
+        q = by_req[r.rid]
+        assert r.steps == q["steps"] and not r.failed
+        o = exact.run_oracle(wl.request_case(q), steps=q["steps"])
+        Uo = o.get_state(0)
+        assert np.array_equal(np.isnan(Uo), np.isnan(r.state)), r.rid
+        m = ~np.isnan(Uo)
+        err = np.abs(r.state[m] - Uo[m]) / np.maximum(np.abs(Uo[m]), 1e-12)
+        assert err.max() <= 1e-14, (r.rid, float(err.max()))
