@@ -364,6 +364,39 @@ __device__ __forceinline__ bool mask_step(const LevelDesc &A, const __attribute_
   return true;
 }
 
+// The W sets of the adaptive relaxation hold the four components of a cell
+// next to each other (element o at 4 o .. 4 o + 3): two 16-byte accesses per
+// cell.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void load_W4(const __attribute__((address_space(1))) double *W, int64_t o,
+                                        double w[4]) {
+  const auto v = (const __attribute__((address_space(1))) dvec2 *)(W + 4 * o);
+  const dvec2 a = v[0], b = v[1];
+  w[0] = a.x;
+  w[1] = a.y;
+  w[2] = b.x;
+  w[3] = b.y;
+}
+__device__ __forceinline__ void store_W4(__attribute__((address_space(1))) double *W, int64_t o,
+                                         const double w[4]) {
+  const auto v = (__attribute__((address_space(1))) dvec2 *)(W + 4 * o);
+  v[0] = dvec2{w[0], w[1]};
+  v[1] = dvec2{w[2], w[3]};
+}
+
+// mask_step with the mask byte of the cell at o already in hand.
+__device__ __forceinline__ bool mask_step_known(const LevelDesc &A, int mk, int64_t &o, int &x, int &y, int dx,
+                                                int dy, int pitch, int Nx, int Ny) {
+  if (dx == 0 && dy == 0) return true;
+  if (!((mk >> mask_bit(dx, dy)) & 1)) return false;
+  o = nb_offset(A, o, x, y, dx, dy, pitch, Nx, Ny);
+  x += dx;
+  y += dy;
+  x = x < 0 ? x + Nx : x >= Nx ? x - Nx : x;
+  y = y < 0 ? y + Ny : y >= Ny ? y - Ny : y;
+  return true;
+}
+
 // One workgroup's work on tile `lb` of descriptor A (inlined twice below, so
 // that A is either plain kernel-argument memory or plain global memory).
 template <class T, class C, bool NT, bool TWO, bool SEN, bool CFL>
@@ -393,7 +426,7 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
   // CFL term of every cell it stores into the next coarse step's bound (a
   // variant of its own, so that the other launches keep their registers)
   const bool cfl = CFL && adt && A.emit_cfl != 0;
-  // adaptive relaxation (eq. sensor-B): per-cell 2 beta in, W of the stored
+  // adaptive relaxation (eq. sensor-B): per-cell beta out, W of the stored
   // result out, and on a level's last step of the coarse step the next max |Q|
   const auto Sp = (gptr<double>)(SEN ? A.sen : nullptr);
   const auto Wn = (gptr<double>)(SEN ? A.wnext : nullptr);
@@ -422,28 +455,92 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
   // (diagonal first), so only active cells are read and no read leaves the
   // frame; a cell two steps out is used only by the ring cell it is reached
   // through.
-  [[maybe_unused]] const int w2 = tl.w + 2;
+  //
+  // A tile has at most SEN_TW x SEN_TH <= blockDim.x cells, one per thread.
+  // Passes, each ended by a barrier:
+  //   0. each thread issues the pull of its cell (kept in registers through
+  //      the sensor passes, so that the population loads are in flight while
+  //      the sensor runs) and stores its cell's mask byte in LDS;
+  //   1. the mask bytes of the active ring cells (reached by one mask-checked
+  //      step from the nearest tile cell);
+  //   2. (A), every walk checked against the masks in LDS;
+  //   3. (B), from LDS only.
+  // The LDS arrays have constant strides: ring-sized arrays (tile plus
+  // one-cell ring) SEN_TW + 2, block-sized arrays (tile plus two cells)
+  // SEN_TW + 4, whatever the tile's width.
+  constexpr int RW = SEN_TW + 2, BW = SEN_TW + 4;
+  const uint16_t *mk_l = nullptr;  // ring-sized: 0x100 | mask byte of an active cell, else 0
   double *a_l = nullptr, *th_l = nullptr;
+  [[maybe_unused]] C gpre[16];
   if constexpr (SEN) {
     __shared__ double qx_l[4][SEN_BLOCK], qy_l[4][SEN_BLOCK], u_l[SEN_BLOCK], v_l[SEN_BLOCK];
     __shared__ double a_lds[SEN_RING], th_lds[SEN_TW * SEN_TH];
+    __shared__ uint16_t mk_lds[SEN_RING];
     a_l = a_lds;
     th_l = th_lds;
+    mk_l = mk_lds;
+    const int tw = tl.w, th_ = tl.h;
+    // pass 0
+    if ((int)threadIdx.x < n) {
+      const int cy = threadIdx.x / tw, cx = threadIdx.x - cy * tw;
+      const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
+      pull<T, C>(s, plane, pitch, o, gpre);
+      mk_lds[(cy + 1) * RW + cx + 1] = (uint16_t)(0x100 | M[o]);
+    }
+    __syncthreads();
+    // pass 1: ring cell t of 2 (w + 2) + 2 h, top row, bottom row, left
+    // column, right column
+    {
+      const int t = threadIdx.x;
+      const int nring = 2 * (tw + 2) + 2 * th_;
+      if (t < nring) {
+        int i, j;
+        if (t < tw + 2) {
+          i = t - 1, j = -1;
+        } else if (t < 2 * (tw + 2)) {
+          i = t - (tw + 2) - 1, j = th_;
+        } else if (t < 2 * (tw + 2) + th_) {
+          i = -1, j = t - 2 * (tw + 2);
+        } else {
+          i = tw, j = t - 2 * (tw + 2) - th_;
+        }
+        const int ci = i < 0 ? 0 : i >= tw ? tw - 1 : i, cj = j < 0 ? 0 : j >= th_ ? th_ - 1 : j;
+        int64_t o = (int64_t)tl.off0 + (int64_t)cj * pitch + ci;
+        int x = x0 + ci, y = y0 + cj;
+        uint16_t v = 0;
+        if (mask_step_known(A, mk_lds[(cj + 1) * RW + ci + 1] & 0xff, o, x, y, i - ci, j - cj, pitch, Nx, Ny))
+          v = (uint16_t)(0x100 | M[o]);
+        mk_lds[(j + 1) * RW + i + 1] = v;
+      }
+    }
+    __syncthreads();
+    // pass 2 (A)
     const auto Wc = (__attribute__((address_space(1))) const double *)A.wcur;
-    const int bw = tl.w + 4, nb = bw * (tl.h + 4);
-    for (int p = threadIdx.x; p < nb; p += blockDim.x) {
-      const int j = p / bw - 2, i = p - (j + 2) * bw - 2;
-      const int ci = i < 0 ? 0 : i >= tl.w ? tl.w - 1 : i, cj = j < 0 ? 0 : j >= tl.h ? tl.h - 1 : j;
+    for (int p = threadIdx.x; p < SEN_BLOCK; p += blockDim.x) {
+      const int bj = p / BW, bi = p - bj * BW;
+      const int j = bj - 2, i = bi - 2;
+      if (i >= tw + 2 || j >= th_ + 2) continue;
+      const int ci = i < 0 ? 0 : i >= tw ? tw - 1 : i, cj = j < 0 ? 0 : j >= th_ ? th_ - 1 : j;
       const int di = i - ci, dj = j - cj;
       if ((di == 2 || di == -2) && (dj == 2 || dj == -2)) continue;  // block corners: never used
+      const int sx = (di > 0) - (di < 0), sy = (dj > 0) - (dj < 0);
+      // first step: to the tile or ring cell (ci + sx, cj + sy)
+      const int m1 = mk_lds[(cj + sy + 1) * RW + ci + sx + 1];
+      if (!(m1 & 0x100)) continue;
       int64_t o = (int64_t)tl.off0 + (int64_t)cj * pitch + ci;
       int x = x0 + ci, y = y0 + cj;
-      const int sx = (di > 0) - (di < 0), sy = (dj > 0) - (dj < 0);
-      if (!mask_step(A, M, o, x, y, sx, sy, pitch, Nx, Ny)) continue;
-      if (!mask_step(A, M, o, x, y, di - sx, dj - sy, pitch, Nx, Ny)) continue;
+      if (sx != 0 || sy != 0) {
+        const int64_t o1 = nb_offset(A, o, x, y, sx, sy, pitch, Nx, Ny);
+        o = o1;
+        x += sx;
+        y += sy;
+        x = x < 0 ? x + Nx : x >= Nx ? x - Nx : x;
+        y = y < 0 ? y + Ny : y >= Ny ? y - Ny : y;
+      }
+      // second step, from that cell's mask
+      if (!mask_step_known(A, m1 & 0xff, o, x, y, di - sx, dj - sy, pitch, Nx, Ny)) continue;
       double w[4], qx[4], qy[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) w[k] = Wc[k * plane + o];
+      load_W4(Wc, o, w);
       euler_flux(eosd, w, qx, qy);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -454,26 +551,26 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
       v_l[p] = w[2] / w[0];
     }
     __syncthreads();
+    // pass 3 (B)
     double qm[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) qm[k] = __longlong_as_double((long long)A.qmax[k]);
-    const int nr = w2 * (tl.h + 2);
-    for (int p = threadIdx.x; p < nr; p += blockDim.x) {
-      const int j = p / w2 - 1, i = p - (j + 1) * w2 - 1;
-      const int ci = i < 0 ? 0 : i >= tl.w ? tl.w - 1 : i, cj = j < 0 ? 0 : j >= tl.h ? tl.h - 1 : j;
-      int64_t o = (int64_t)tl.off0 + (int64_t)cj * pitch + ci;
-      int x = x0 + ci, y = y0 + cj;
+    for (int p = threadIdx.x; p < SEN_RING; p += blockDim.x) {
+      const int rj = p / RW, ri = p - rj * RW;
+      if (ri >= tw + 2 || rj >= th_ + 2) continue;
+      const int i = ri - 1, j = rj - 1;
+      const int mv = mk_lds[p];
       double a = 0.0, th = 0.0;
-      if (mask_step(A, M, o, x, y, i - ci, j - cj, pitch, Nx, Ny)) {
+      if (mv & 0x100) {
         // s_k from the four neighbours' fluxes over this coarse step's Qmax,
         // a their RMS; theta from dilatation and vorticity. A neighbour that
         // is not an active cell stands in as the cell itself.
-        const int mk = M[o];
-        const int pb = (j + 2) * bw + i + 2;
+        const int mk = mv & 0xff;
+        const int pb = (j + 2) * BW + i + 2;
         constexpr int DX[4] = {1, -1, 0, 0}, DY[4] = {0, 0, 1, -1};
         int e[4];
 #pragma unroll
-        for (int d = 0; d < 4; ++d) e[d] = (mk >> mask_bit(DX[d], DY[d])) & 1 ? pb + DX[d] + DY[d] * bw : pb;
+        for (int d = 0; d < 4; ++d) e[d] = (mk >> mask_bit(DX[d], DY[d])) & 1 ? pb + DX[d] + DY[d] * BW : pb;
         double sk[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -487,7 +584,7 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
         th = (dil < 0.0 && den > 0.0) ? (dil * dil) / den : 0.0;
       }
       a_l[p] = a;
-      if (i == ci && j == cj) th_l[j * tl.w + i] = th;
+      if (i >= 0 && i < tw && j >= 0 && j < th_) th_l[j * SEN_TW + i] = th;
     }
     __syncthreads();
   }
@@ -537,14 +634,19 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
       const int cx = c - cy * tl.w;
       const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
       C g[16];
-      pull<T, C>(s, plane, pitch, o, g);
+      if (SEN && c == (int)threadIdx.x) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) g[q] = gpre[q];
+      } else {
+        pull<T, C>(s, plane, pitch, o, g);
+      }
       C tbc = tb;
       if (SEN) {
         // beta = beta_max - (beta_max - beta_min) clip(C sbar theta, 0, 1),
         // sbar the mean of a over the active cells of the 3 x 3 block, summed
         // row by row from (x - 1, y - 1)
-        const int mk = M[o];
-        const int pc = (cy + 1) * w2 + cx + 1;
+        const int pc = (cy + 1) * RW + cx + 1;
+        const int mk = mk_l[pc] & 0xff;
         double sum = 0.0;
         int cnt = 0;
 #pragma unroll
@@ -552,14 +654,14 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
 #pragma unroll
           for (int dx = -1; dx <= 1; ++dx) {
             if ((dx == 0 && dy == 0) || ((mk >> mask_bit(dx, dy)) & 1)) {
-              sum += a_l[pc + dy * w2 + dx];
+              sum += a_l[pc + dy * RW + dx];
               ++cnt;
             }
           }
-        double z = (cs * (sum / (double)cnt)) * th_l[c];
+        double z = (cs * (sum / (double)cnt)) * th_l[cy * SEN_TW + cx];
         z = z < 0.0 ? 0.0 : z > 1.0 ? 1.0 : z;
         const double beta = bmax - bspan * z;
-        Sp[SEN_BETA * plane + o] = beta;
+        if (emit) Sp[SEN_BETA * plane + o] = beta;  // beta of the level's last step of the coarse step
         tbc = (C)(2.0 * beta);
       }
       relax<C>(g, eos, h, tbc);
@@ -568,8 +670,7 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
         double w[4];
         W_as_stored<T, C>(g, w);
         if (SEN) {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) Wn[k * plane + o] = w[k];
+          store_W4(Wn, o, w);
           if (emit) flux_absmax(eosd, w, m);
         }
         if (cfl) mc = fmax(mc, cfl_term(eosc, gam, w));
@@ -934,11 +1035,13 @@ hipError_t launch_step(const StepLaunch &a, int fp32, hipStream_t s, hipEvent_t 
 // into the other W set, and on a level's last step of a coarse step
 // accumulates the next coarse step's Qmax from them. The two W sets alternate
 // with the level's step count, so no workgroup reads W that another one of
-// the same launch writes. The context's first launch of a coarse step clears
-// the next Qmax slot (workgroup 0), or stage 1 does just before it when that
-// launch also accumulates into the slot; stage 0 fills the input W set of
-// every level and this coarse step's Qmax from the stored populations, once
-// after any change of state.
+// the same launch writes. (Summing W from the stored populations of the
+// block instead, which saves the two W sets' traffic, was measured slower:
+// four times the loads per block cell.) The context's first launch of a
+// coarse step clears the next Qmax slot (workgroup 0), or stage 1 does just
+// before it when that launch also accumulates into the slot; stage 0 fills
+// the input W set of every level and this coarse step's Qmax from the stored
+// populations, once after any change of state.
 // ---------------------------------------------------------------------------
 
 template <class T>
@@ -949,7 +1052,7 @@ __global__ __launch_bounds__(256) void sensor0_kernel(StepLaunch Lc) {
   const int tid = blockIdx.x - fb;
   if (tid >= A.ntiles || !A.sen) return;  // uniform over the workgroup
   const Tile tl = A.tiles[tid];
-  const auto s = (__attribute__((address_space(1))) const T *)A.src;
+  const T *s = static_cast<const T *>(A.src);
   // the W set this descriptor's step reads: the level's current time level
   const auto Wp = (gptr<double>)const_cast<double *>(A.wcur);
   const int64_t P = A.plane;
@@ -961,12 +1064,8 @@ __global__ __launch_bounds__(256) void sensor0_kernel(StepLaunch Lc) {
     const int cy = c / tl.w, cx = c - cy * tl.w;
     const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
     double w[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      w[k] = (((double)s[(0 * 4 + k) * P + o] + (double)s[(1 * 4 + k) * P + o]) +
-              (double)s[(2 * 4 + k) * P + o]) + (double)s[(3 * 4 + k) * P + o];
-      Wp[k * P + o] = w[k];
-    }
+    stored_W<T>(s, P, o, w);
+    store_W4(Wp, o, w);
     flux_absmax(eos, w, m);
   }
   block_qmax(m, A.qmax);
