@@ -118,7 +118,8 @@ enum DynSlot : int32_t {
 // Adaptive relaxation planes of a level (FP64, `plane` elements each, same
 // element offsets as the populations): two sets of W_0..W_3, one per parity
 // of the level's step count (a step reads the set of its input time level
-// and writes the other one), and beta of the last step.
+// and writes the other one), and beta of the last step. A W set spans four
+// planes with the components of element o at 4 o .. 4 o + 3.
 enum SensorPlane : int32_t { SEN_W0 = 0, SEN_W1 = 4, SEN_BETA = 8, SEN_PLANES = 9 };
 
 // With the adaptive relaxation the step tiles are at most SEN_TW x SEN_TH
