@@ -262,7 +262,7 @@ struct Level {
   // adaptive relaxation planes (SensorPlane, SEN_PLANES x sen_plane doubles)
   // and neighbour masks (sen_plane bytes), allocated while the sensor is on
   double *dsen = nullptr;
-  uint8_t *dmask = nullptr;
+  uint32_t *dmask = nullptr;
   int64_t sen_plane = 0;
   std::vector<int64_t> reflux_key;  // per reflux slot: (y * Nx + x) * 4 + q of its ring cell
 
@@ -1233,12 +1233,12 @@ vlbm_status ensure_sensor(vlbm_ctx *c) {
     if (!L.dsen) {
       const size_t nb = sizeof(double) * SEN_PLANES * (size_t)L.plane;
       L.dsen = static_cast<double *>(c->mem.alloc(nb));
-      L.dmask = static_cast<uint8_t *>(c->mem.alloc((size_t)L.plane));
+      L.dmask = static_cast<uint32_t *>(c->mem.alloc(sizeof(uint32_t) * (size_t)L.plane));
       if (!L.dsen || !L.dmask) return fail(VLBM_ENOMEM, "adaptive relaxation planes (%zu bytes)", nb);
       L.sen_plane = L.plane;
       HIPCHK(hipMemsetAsync(L.dsen, 0, nb, c->stream));
     }
-    HIPCHK(hipMemsetAsync(L.dmask, 0, (size_t)L.plane, c->stream));
+    HIPCHK(hipMemsetAsync(L.dmask, 0, sizeof(uint32_t) * (size_t)L.plane, c->stream));
     HIPCHK(launch_sensor_mask(L.dstatus, L.dmask, L.dsrow, L.dyrow, L.fx0, L.fy0, L.fw, L.fh, L.nrows,
                               L.pitch, L.xoff, L.Nx, L.Ny, (c->perx() ? 1 : 0) | (c->pery() ? 2 : 0),
                               c->stream));

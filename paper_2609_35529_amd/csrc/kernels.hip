@@ -348,22 +348,6 @@ __device__ __forceinline__ void tile_origin(const LevelDesc &A, const Tile &tl, 
   y0 = A.fy0 + A.yrow[sr];
 }
 
-// Walk from the tile cell at offset o, level (x, y), by (dx, dy) with
-// |dx|, |dy| <= 1: the step is taken only where the cell's mask marks the
-// target as an active neighbour (then o, x, y become the target's, periodic
-// sides wrapped); returns whether it was.
-__device__ __forceinline__ bool mask_step(const LevelDesc &A, const __attribute__((address_space(1))) uint8_t *M,
-                                          int64_t &o, int &x, int &y, int dx, int dy, int pitch, int Nx, int Ny) {
-  if (dx == 0 && dy == 0) return true;
-  if (!((M[o] >> mask_bit(dx, dy)) & 1)) return false;
-  o = nb_offset(A, o, x, y, dx, dy, pitch, Nx, Ny);
-  x += dx;
-  y += dy;
-  x = x < 0 ? x + Nx : x >= Nx ? x - Nx : x;
-  y = y < 0 ? y + Ny : y >= Ny ? y - Ny : y;
-  return true;
-}
-
 // The W sets of the adaptive relaxation hold the four components of a cell
 // next to each other (element o at 4 o .. 4 o + 3): two 16-byte accesses per
 // cell.
@@ -382,19 +366,6 @@ __device__ __forceinline__ void store_W4(__attribute__((address_space(1))) doubl
   const auto v = (__attribute__((address_space(1))) dvec2 *)(W + 4 * o);
   v[0] = dvec2{w[0], w[1]};
   v[1] = dvec2{w[2], w[3]};
-}
-
-// mask_step with the mask byte of the cell at o already in hand.
-__device__ __forceinline__ bool mask_step_known(const LevelDesc &A, int mk, int64_t &o, int &x, int &y, int dx,
-                                                int dy, int pitch, int Nx, int Ny) {
-  if (dx == 0 && dy == 0) return true;
-  if (!((mk >> mask_bit(dx, dy)) & 1)) return false;
-  o = nb_offset(A, o, x, y, dx, dy, pitch, Nx, Ny);
-  x += dx;
-  y += dy;
-  x = x < 0 ? x + Nx : x >= Nx ? x - Nx : x;
-  y = y < 0 ? y + Ny : y >= Ny ? y - Ny : y;
-  return true;
 }
 
 // One workgroup's work on tile `lb` of descriptor A (inlined twice below, so
@@ -430,7 +401,7 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
   // result out, and on a level's last step of the coarse step the next max |Q|
   const auto Sp = (gptr<double>)(SEN ? A.sen : nullptr);
   const auto Wn = (gptr<double>)(SEN ? A.wnext : nullptr);
-  const auto M = (__attribute__((address_space(1))) const uint8_t *)(SEN ? A.mask : nullptr);
+  const auto M = (__attribute__((address_space(1))) const uint32_t *)(SEN ? A.mask : nullptr);
   const bool emit = SEN && A.emit_qmax != 0;
   const EosT<double> eosd = eos_of<double>(A);
   const double cs = A.c_sensor, bmax = A.beta_max, bspan = A.beta_max - A.beta_min;
@@ -460,62 +431,41 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
   // Passes, each ended by a barrier:
   //   0. each thread issues the pull of its cell (kept in registers through
   //      the sensor passes, so that the population loads are in flight while
-  //      the sensor runs) and stores its cell's mask byte in LDS;
-  //   1. the mask bytes of the active ring cells (reached by one mask-checked
-  //      step from the nearest tile cell);
-  //   2. (A), every walk checked against the masks in LDS;
-  //   3. (B), from LDS only.
-  // The LDS arrays have constant strides: ring-sized arrays (tile plus
-  // one-cell ring) SEN_TW + 2, block-sized arrays (tile plus two cells)
-  // SEN_TW + 4, whatever the tile's width.
+  //      the sensor runs) and stores its cell's neighbourhood mask in LDS;
+  //   1. (A); whether a cell within two of the tile is reached, and through
+  //      which ring cell, follows from the nearest tile cell's mask alone
+  //      (its bits cover every cell of the walk);
+  //   2. (B), from LDS only; the ring cells' neighbours are active or not
+  //      per the nearest tile cell's mask as well.
+  // Block-sized LDS arrays (tile plus two cells) have the constant stride
+  // SEN_TW + 4, ring-sized ones (tile plus one cell) SEN_TW + 2.
   constexpr int RW = SEN_TW + 2, BW = SEN_TW + 4;
-  const uint16_t *mk_l = nullptr;  // ring-sized: 0x100 | mask byte of an active cell, else 0
+  const uint32_t *mt_l = nullptr;  // the tile cells' masks, stride SEN_TW
   double *a_l = nullptr, *th_l = nullptr;
   [[maybe_unused]] C gpre[16];
   if constexpr (SEN) {
     __shared__ double qx_l[4][SEN_BLOCK], qy_l[4][SEN_BLOCK], u_l[SEN_BLOCK], v_l[SEN_BLOCK];
     __shared__ double a_lds[SEN_RING], th_lds[SEN_TW * SEN_TH];
-    __shared__ uint16_t mk_lds[SEN_RING];
+    __shared__ uint32_t mt_lds[SEN_TW * SEN_TH];
     a_l = a_lds;
     th_l = th_lds;
-    mk_l = mk_lds;
+    mt_l = mt_lds;
     const int tw = tl.w, th_ = tl.h;
+    // is the cell (dx, dy) away from the tile cell with mask m active?
+    auto act = [](uint32_t m, int dx, int dy) -> bool { return (m >> nb_bit(dx, dy)) & 1u; };
     // pass 0
     if ((int)threadIdx.x < n) {
       const int cy = threadIdx.x / tw, cx = threadIdx.x - cy * tw;
       const int64_t o = (int64_t)tl.off0 + (int64_t)cy * pitch + cx;
       pull<T, C>(s, plane, pitch, o, gpre);
-      mk_lds[(cy + 1) * RW + cx + 1] = (uint16_t)(0x100 | M[o]);
+      mt_lds[cy * SEN_TW + cx] = M[o];
     }
     __syncthreads();
-    // pass 1: ring cell t of 2 (w + 2) + 2 h, top row, bottom row, left
-    // column, right column
-    {
-      const int t = threadIdx.x;
-      const int nring = 2 * (tw + 2) + 2 * th_;
-      if (t < nring) {
-        int i, j;
-        if (t < tw + 2) {
-          i = t - 1, j = -1;
-        } else if (t < 2 * (tw + 2)) {
-          i = t - (tw + 2) - 1, j = th_;
-        } else if (t < 2 * (tw + 2) + th_) {
-          i = -1, j = t - 2 * (tw + 2);
-        } else {
-          i = tw, j = t - 2 * (tw + 2) - th_;
-        }
-        const int ci = i < 0 ? 0 : i >= tw ? tw - 1 : i, cj = j < 0 ? 0 : j >= th_ ? th_ - 1 : j;
-        int64_t o = (int64_t)tl.off0 + (int64_t)cj * pitch + ci;
-        int x = x0 + ci, y = y0 + cj;
-        uint16_t v = 0;
-        if (mask_step_known(A, mk_lds[(cj + 1) * RW + ci + 1] & 0xff, o, x, y, i - ci, j - cj, pitch, Nx, Ny))
-          v = (uint16_t)(0x100 | M[o]);
-        mk_lds[(j + 1) * RW + i + 1] = v;
-      }
-    }
-    __syncthreads();
-    // pass 2 (A)
+    // pass 1 (A). Where the tile's block (two cells around it) stays inside
+    // the level, no walk wraps and cell (i, j) of the block sits at
+    // off0 + j pitch + i (the rows next to an active cell are one pitch away).
     const auto Wc = (__attribute__((address_space(1))) const double *)A.wcur;
+    const bool inner = x0 >= 2 && y0 >= 2 && x0 + tw + 2 <= Nx && y0 + th_ + 2 <= Ny;
     for (int p = threadIdx.x; p < SEN_BLOCK; p += blockDim.x) {
       const int bj = p / BW, bi = p - bj * BW;
       const int j = bj - 2, i = bi - 2;
@@ -524,21 +474,25 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
       const int di = i - ci, dj = j - cj;
       if ((di == 2 || di == -2) && (dj == 2 || dj == -2)) continue;  // block corners: never used
       const int sx = (di > 0) - (di < 0), sy = (dj > 0) - (dj < 0);
-      // first step: to the tile or ring cell (ci + sx, cj + sy)
-      const int m1 = mk_lds[(cj + sy + 1) * RW + ci + sx + 1];
-      if (!(m1 & 0x100)) continue;
-      int64_t o = (int64_t)tl.off0 + (int64_t)cj * pitch + ci;
-      int x = x0 + ci, y = y0 + cj;
-      if (sx != 0 || sy != 0) {
-        const int64_t o1 = nb_offset(A, o, x, y, sx, sy, pitch, Nx, Ny);
-        o = o1;
-        x += sx;
-        y += sy;
-        x = x < 0 ? x + Nx : x >= Nx ? x - Nx : x;
-        y = y < 0 ? y + Ny : y >= Ny ? y - Ny : y;
+      // first step to the tile or ring cell (ci + sx, cj + sy), then on to
+      // (ci + di, cj + dj): both cells active
+      const uint32_t mt = mt_lds[cj * SEN_TW + ci];
+      if (!act(mt, sx, sy) || !act(mt, di, dj)) continue;
+      int64_t o;
+      if (inner) {
+        o = (int64_t)tl.off0 + (int64_t)j * pitch + i;
+      } else {
+        o = (int64_t)tl.off0 + (int64_t)cj * pitch + ci;
+        int x = x0 + ci, y = y0 + cj;
+        if (sx != 0 || sy != 0) {
+          o = nb_offset(A, o, x, y, sx, sy, pitch, Nx, Ny);
+          x += sx;
+          y += sy;
+          x = x < 0 ? x + Nx : x >= Nx ? x - Nx : x;
+          y = y < 0 ? y + Ny : y >= Ny ? y - Ny : y;
+        }
+        if (di != sx || dj != sy) o = nb_offset(A, o, x, y, di - sx, dj - sy, pitch, Nx, Ny);
       }
-      // second step, from that cell's mask
-      if (!mask_step_known(A, m1 & 0xff, o, x, y, di - sx, dj - sy, pitch, Nx, Ny)) continue;
       double w[4], qx[4], qy[4];
       load_W4(Wc, o, w);
       euler_flux(eosd, w, qx, qy);
@@ -551,7 +505,7 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
       v_l[p] = w[2] / w[0];
     }
     __syncthreads();
-    // pass 3 (B)
+    // pass 2 (B)
     double qm[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) qm[k] = __longlong_as_double((long long)A.qmax[k]);
@@ -559,18 +513,19 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
       const int rj = p / RW, ri = p - rj * RW;
       if (ri >= tw + 2 || rj >= th_ + 2) continue;
       const int i = ri - 1, j = rj - 1;
-      const int mv = mk_lds[p];
+      const int ci = i < 0 ? 0 : i >= tw ? tw - 1 : i, cj = j < 0 ? 0 : j >= th_ ? th_ - 1 : j;
+      const int ai = i - ci, aj = j - cj;  // this cell relative to the nearest tile cell
+      const uint32_t mt = mt_lds[cj * SEN_TW + ci];
       double a = 0.0, th = 0.0;
-      if (mv & 0x100) {
+      if (act(mt, ai, aj)) {
         // s_k from the four neighbours' fluxes over this coarse step's Qmax,
         // a their RMS; theta from dilatation and vorticity. A neighbour that
         // is not an active cell stands in as the cell itself.
-        const int mk = mv & 0xff;
         const int pb = (j + 2) * BW + i + 2;
         constexpr int DX[4] = {1, -1, 0, 0}, DY[4] = {0, 0, 1, -1};
         int e[4];
 #pragma unroll
-        for (int d = 0; d < 4; ++d) e[d] = (mk >> mask_bit(DX[d], DY[d])) & 1 ? pb + DX[d] + DY[d] * BW : pb;
+        for (int d = 0; d < 4; ++d) e[d] = act(mt, ai + DX[d], aj + DY[d]) ? pb + DX[d] + DY[d] * BW : pb;
         double sk[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -646,14 +601,14 @@ __device__ __forceinline__ void run_tile(const LevelDesc &A, int lb, int nblocks
         // sbar the mean of a over the active cells of the 3 x 3 block, summed
         // row by row from (x - 1, y - 1)
         const int pc = (cy + 1) * RW + cx + 1;
-        const int mk = mk_l[pc] & 0xff;
+        const uint32_t mk = mt_l[cy * SEN_TW + cx];
         double sum = 0.0;
         int cnt = 0;
 #pragma unroll
         for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
           for (int dx = -1; dx <= 1; ++dx) {
-            if ((dx == 0 && dy == 0) || ((mk >> mask_bit(dx, dy)) & 1)) {
+            if ((mk >> nb_bit(dx, dy)) & 1) {
               sum += a_l[pc + dy * RW + dx];
               ++cnt;
             }
@@ -1086,7 +1041,7 @@ __global__ __launch_bounds__(64) void sensor_clear_kernel(StepLaunch Lc) {
 
 // One thread per stored frame element; writes the mask of every active cell
 // and 0 elsewhere.
-__global__ __launch_bounds__(256) void sensor_mask_kernel(const uint8_t *status, uint8_t *mask,
+__global__ __launch_bounds__(256) void sensor_mask_kernel(const uint8_t *status, uint32_t *mask,
                                                           const int32_t *srow, const int32_t *yrow, int fx0,
                                                           int fy0, int fw, int fh, int nrows, int pitch,
                                                           int xoff, int Nx, int Ny, int per) {
@@ -1094,30 +1049,31 @@ __global__ __launch_bounds__(256) void sensor_mask_kernel(const uint8_t *status,
   if (i >= (int64_t)fw * nrows) return;
   const int sr = (int)(i / fw), fx = (int)(i - (int64_t)sr * fw);
   const int64_t o = (int64_t)sr * pitch + fx + xoff;
-  int mk = 0;
+  uint32_t mk = 0;
   if (status[i] == 1) {
     const int x = fx0 + fx, y = fy0 + yrow[sr];
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        if (dx == 0 && dy == 0) continue;
+    for (int dy = -2; dy <= 2; ++dy)
+      for (int dx = -2; dx <= 2; ++dx) {
+        if ((dx == 2 || dx == -2) && (dy == 2 || dy == -2)) continue;  // corners: unused
+        const int bit = nb_bit(dx, dy);
         int xx = x + dx, yy = y + dy;
         if (xx < 0 || xx >= Nx) {
           if (!(per & 1)) continue;
-          xx = xx < 0 ? xx + Nx : xx - Nx;
+          xx = ((xx % Nx) + Nx) % Nx;
         }
         if (yy < 0 || yy >= Ny) {
           if (!(per & 2)) continue;
-          yy = yy < 0 ? yy + Ny : yy - Ny;
+          yy = ((yy % Ny) + Ny) % Ny;
         }
         const int gx = xx - fx0, gy = yy - fy0;
         if (gx < 0 || gy < 0 || gx >= fw || gy >= fh || srow[gy] < 0) continue;
-        if (status[(int64_t)srow[gy] * fw + gx] == 1) mk |= 1 << mask_bit(dx, dy);
+        if (status[(int64_t)srow[gy] * fw + gx] == 1) mk |= 1u << bit;
       }
   }
-  mask[o] = (uint8_t)mk;
+  mask[o] = mk;
 }
 
-hipError_t launch_sensor_mask(const uint8_t *status, uint8_t *mask, const int32_t *srow, const int32_t *yrow,
+hipError_t launch_sensor_mask(const uint8_t *status, uint32_t *mask, const int32_t *srow, const int32_t *yrow,
                               int fx0, int fy0, int fw, int fh, int nrows, int pitch, int xoff, int Nx,
                               int Ny, int per, hipStream_t s) {
   const int64_t n = (int64_t)fw * nrows;

@@ -130,13 +130,12 @@ constexpr int SEN_TW = 32, SEN_TH = 8;
 constexpr int SEN_BLOCK = (SEN_TW + 4) * (SEN_TH + 4);
 constexpr int SEN_RING = (SEN_TW + 2) * (SEN_TH + 2);
 
-// Neighbour mask of an active cell (one byte per frame element): bit
-// (dy + 1) * 3 + (dx + 1), the centre bit 4 left out (bits 5..8 stored one
-// lower), set when level cell (x + dx, y + dy), periodic sides wrapped, is an
-// active cell of the level.
-__host__ __device__ constexpr int mask_bit(int dx, int dy) {
-  return (dy + 1) * 3 + (dx + 1) - ((dy + 1) * 3 + (dx + 1) > 4 ? 1 : 0);
-}
+// Neighbourhood mask of an active cell (32 bits per frame element): bit
+// nb_bit(dx, dy) = (dy + 2) * 5 + (dx + 2), |dx|, |dy| <= 2, is set when
+// level cell (x + dx, y + dy), periodic sides wrapped, is an active cell of
+// the level (the centre bit always, the four corner bits never). Inactive
+// cells hold 0.
+__host__ __device__ constexpr int nb_bit(int dx, int dy) { return (dy + 2) * 5 + (dx + 2); }
 
 // Everything the step kernel needs about one (context, level) at one phase of
 // the schedule. Lives in device memory; a launch covers one or more of them.
@@ -161,7 +160,7 @@ struct LevelDesc {
   double *sen;               // SEN_PLANES planes (SensorPlane)
   const double *wcur;        // the W set of this step's input time level
   double *wnext;             // the W set of its output
-  const uint8_t *mask;       // neighbour masks (mask_bit), `plane` bytes
+  const uint32_t *mask;      // neighbourhood masks (nb_bit), `plane` words
   unsigned long long *qmax;       // [4] max |Q_{alpha,k}| of this coarse step, as bits
   unsigned long long *qmax_next;  // [4] the next coarse step's, accumulated by its last steps
   int32_t clear_next;        // this phase is the context's first of the coarse step: qmax_next is
@@ -232,9 +231,9 @@ hipError_t launch_cfl(const StepLaunch &a, int fp32, unsigned long long *cmax, c
 hipError_t launch_cfl_finalize(double *dyn, unsigned long long *cmax, hipStream_t s);
 // Zero n 64-bit words of device memory on stream s (no memset node under capture).
 hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t s);
-// Neighbour masks of a level frame from its status (fw bytes per stored row,
-// 1 = active); srow / yrow map frame rows to storage rows and back.
-hipError_t launch_sensor_mask(const uint8_t *status, uint8_t *mask, const int32_t *srow, const int32_t *yrow,
+// Neighbourhood masks of a level frame from its status (fw bytes per stored
+// row, 1 = active); srow / yrow map frame rows to storage rows and back.
+hipError_t launch_sensor_mask(const uint8_t *status, uint32_t *mask, const int32_t *srow, const int32_t *yrow,
                               int fx0, int fy0, int fw, int fh, int nrows, int pitch, int xoff, int Nx,
                               int Ny, int per, hipStream_t s);
 hipError_t launch_audit(const void *buf, const Tile *tiles, int ntiles, int64_t plane,
