@@ -44,7 +44,11 @@ MEASURED_TRAFFIC = {"kernel_sha256_16": "9e20e717e160179d", "workload": "kh4096"
 # dynamic-refinement workloads: re-tag and regrid every few coarse steps
 # (the density-gradient indicator is per cell, so it halves with each level
 # on a smeared layer: the shear layer needs a lower threshold to keep level 3)
-DYNAMIC = {"shock_bubble": {"max_box": 64, "threshold": 0.05},
+# shock_bubble: the fused finest level (the autotuner's pick from timing steps
+# alone) makes every regrid build fused tile lists too, which costs more host
+# time per regrid than the fused launches save over five coarse steps: plain
+# 256-cell tiles measure fastest over the timed region, regrids included
+DYNAMIC = {"shock_bubble": {"max_box": 64, "threshold": 0.05, "tuning": (256, 0)},
            "kh_strip": {"max_box": 128, "threshold": 0.01},
            "kh4096": {"max_box": 128, "threshold": 0.01, "tuning": (512, 17)}}
 
