@@ -33,12 +33,12 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic per launch of the dominant kernel of the default workload
 # (kh4096, FP64, 512-cell tiles, flags 17: the level-0 step launch, 16,646,144
 # cells), from rocprofv3 FETCH_SIZE x 2.000 and WRITE_SIZE x 1.000 (the scales
-# a plain 2 GiB device copy reads on the same counters: 1,048,589 KiB fetched
+# a plain 2 GiB device copy reads on the same counters: 1,048,588 KiB fetched
 # and 2,097,152 KiB written per 2 GiB); valid only for the kernel source it
 # was measured on.
-MEASURED_TRAFFIC = {"kernel_sha256_16": "9e20e717e160179d", "workload": "kh4096",
+MEASURED_TRAFFIC = {"kernel_sha256_16": "89fd30e6fc02339b", "workload": "kh4096",
                     "precision": "fp64", "tile_cells": 512, "flags": 17, "kernel": "step_kernel",
-                    "level": 0, "bytes_per_launch": (2 * 1067123.625 + 2082642.869) * 1024}
+                    "level": 0, "bytes_per_launch": (2 * 1067135.6 + 2082632.7) * 1024}
 
 
 # dynamic-refinement workloads: re-tag and regrid every few coarse steps
