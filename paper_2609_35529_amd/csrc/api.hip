@@ -2088,11 +2088,66 @@ void cluster_level(vlbm_ctx *c, int l, const std::vector<int32_t> &hits, const C
     }
     return row_ok(y, x, x + 1);
   };
-  auto allowed = [&](int tx, int ty) {
+  auto allowed_slow = [&](int tx, int ty) {
     const int x0 = tx * T, y0 = ty * T, x1 = std::min(Nx, x0 + T), y1 = std::min(Ny, y0 + T);
     for (int y = y0; y < y1; ++y)
       if (!row_ok(y, x0, x1) || !cell_ok(x0 - 1, y) || !cell_ok(x1, y)) return false;
     return row_ok(y0 - 1, x0, x1) && row_ok(y1, x0, x1);
+  };
+  // Per tile row, the columns covered on every row of the tile (mid) and on
+  // the rows just above and below (edge), as merged intervals; a tile away
+  // from the x sides is allowed iff [x0 - 1, x1 + 1) lies in mid and
+  // [x0, x1) in both edges, the same test as allowed_slow.
+  using Iv = std::vector<std::pair<int, int>>;
+  auto row_iv = [&](int y, Iv &out) {  // coverage of row y, wrapped or exempt outside
+    out.clear();
+    if (y < 0 || y >= Ny) {
+      if (!py) {
+        out.push_back({INT32_MIN, INT32_MAX});
+        return;
+      }
+      y = (y + Ny) % Ny;
+    }
+    if (cov.all) {
+      out.push_back({INT32_MIN, INT32_MAX});
+      return;
+    }
+    const int i = y - cov.y0;
+    if (i >= 0 && i < (int)cov.rows.size()) out = cov.rows[i];
+  };
+  auto intersect = [](const Iv &a, const Iv &b, Iv &out) {
+    out.clear();
+    size_t i = 0, j = 0;
+    while (i < a.size() && j < b.size()) {
+      const int lo = std::max(a[i].first, b[j].first), hi = std::min(a[i].second, b[j].second);
+      if (lo < hi) out.push_back({lo, hi});
+      if (a[i].second < b[j].second) ++i; else ++j;
+    }
+  };
+  auto inside = [](const Iv &v, int xa, int xb) {  // [xa, xb) within one interval of v
+    auto it = std::upper_bound(v.begin(), v.end(), std::make_pair(xa, INT32_MAX));
+    if (it == v.begin()) return false;
+    --it;
+    return it->first <= xa && it->second >= xb;
+  };
+  Iv mid, top, bot, tmp, cur;
+  int row_ty = -1;
+  auto allowed = [&](int tx, int ty) {
+    const int x0 = tx * T, x1 = std::min(Nx, x0 + T);
+    if (x0 == 0 || x1 >= Nx) return allowed_slow(tx, ty);
+    if (ty != row_ty) {
+      row_ty = ty;
+      const int y0 = ty * T, y1 = std::min(Ny, y0 + T);
+      row_iv(y0, mid);
+      for (int y = y0 + 1; y < y1 && !mid.empty(); ++y) {
+        row_iv(y, cur);
+        intersect(mid, cur, tmp);
+        mid.swap(tmp);
+      }
+      row_iv(y0 - 1, top);
+      row_iv(y1, bot);
+    }
+    return inside(mid, x0 - 1, x1 + 1) && inside(top, x0, x1) && inside(bot, x0, x1);
   };
   struct Run { int a, b, y0, h; };
   std::vector<Run> open, next;
@@ -2686,7 +2741,28 @@ vlbm_status vlbm_tag_and_regrid(vlbm_ctx *c, double thr, int buffer, int min_box
   cov.all = true;
   for (int l = 0; l < nclu; ++l) {
     const size_t before = boxes.size();
-    std::sort(hits[l].begin(), hits[l].end());
+    // the hits in tile order: a bit per tile of the scanned tile rows (the
+    // device appends them a wavefront at a time, in any order)
+    {
+      const Level &L = c->lv[l];
+      const int ntx = (L.Nx + T - 1) / T, nty = (L.Ny + T - 1) / T;
+      std::vector<int32_t> row_of(nty, -1);
+      for (size_t k = 0; k < trows[l].size(); ++k) row_of[trows[l][k]] = (int32_t)k;
+      const int64_t nbit = (int64_t)ntx * (int64_t)trows[l].size();
+      std::vector<uint64_t> bits((size_t)((nbit + 63) / 64), 0);
+      for (int32_t h : hits[l]) {
+        if (h < 0 || h / ntx >= nty || row_of[h / ntx] < 0) continue;  // only scanned tiles are listed
+        const int64_t k = (int64_t)row_of[h / ntx] * ntx + h % ntx;
+        bits[(size_t)(k >> 6)] |= 1ull << (k & 63);
+      }
+      size_t n = 0;
+      for (size_t wi = 0; wi < bits.size(); ++wi)
+        for (uint64_t w = bits[wi]; w; w &= w - 1) {
+          const int64_t k = (int64_t)wi * 64 + __builtin_ctzll(w);
+          hits[l][n++] = trows[l][(size_t)(k / ntx)] * ntx + (int32_t)(k % ntx);
+        }
+      hits[l].resize(n);
+    }
     cluster_level(c, l, hits[l], cov, min_box, max_box, boxes);
     if (boxes.size() == before || l + 2 >= ML) break;
     cov = CovMap::of_boxes(boxes.data() + before, boxes.size() - before);
