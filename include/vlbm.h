@@ -264,7 +264,10 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
  * blocking of the sub-cycling of Sec. 3), 512 XCD-contiguous order for the
  * fused launches only, 1024 replay captured hipGraphs of two coarse steps
  * (vlbm_advance of four or more steps, and vlbm_batch_advance; the
- * environment variable VLBM_GRAPHS=1 sets it at creation). Rebuilds the
+ * environment variable VLBM_GRAPHS=1 sets it at creation), 2048 a level with
+ * fewer than 4096 step tiles of tile_cells cells gets tiles of half the size
+ * until it has that many or they reach 64 cells (levels too small to fill
+ * the chip). Rebuilds the
  * launch tables; the
  * hierarchy and the time history are kept. VLBM_EINVAL for other values. */
 vlbm_status vlbm_set_tuning(vlbm_ctx *ctx, int tile_cells, int flags);
@@ -276,7 +279,9 @@ vlbm_status vlbm_set_tuning(vlbm_ctx *ctx, int tile_cells, int flags);
  * with a stream of its own then times the fastest with and without graph
  * replay (flag 1024; 2 + m and 4 + m more coarse steps, m = steps_per_trial
  * rounded up to an even number of at least 4) and keeps replay if it saves
- * more than 2%. The choice is cached
+ * more than 2%. Before that it times the fastest with and without flag 2048
+ * (2 + 2 m coarse steps, m = steps_per_trial; not with the adaptive
+ * relaxation) and keeps the flag if it saves more than 1%. The choice is cached
  * per geometry (base grid, ratio, precision, boxes) for the process, so a
  * repeated call advances nothing. Reports the choice in tile_cells/flags
  * (either may be NULL). */

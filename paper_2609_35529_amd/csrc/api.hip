@@ -905,17 +905,24 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
     std::string err;
   };
   std::vector<Work> W(nlev);
-  const int TC = c->tile_cells;
+  const int TCfull = c->tile_cells;
   auto passA = [&](int l) -> vlbm_status {
     PhaseTimer lt(l == 0 ? "passA l0" : l == 1 ? "passA l1" : l == 2 ? "passA l2" : "passA l3+");
     Level &L = c->lv[l];
     Work &w = W[l];
     // tiles: runs of active cells per row, stacked into rectangles of <= TC cells
-    L.tiles.clear();
     const bool sen_tiles = c->sensor;
     struct Open { int xa, xb, y0, h; };
     std::vector<Open> open, nopen;
     std::vector<std::pair<int, int>> rect_xy;  // (x0, y0) of each emitted tile
+    // With STEP_SMALL_TILES, a level too small to fill the chip with tiles of
+    // TCfull cells (fewer than 4096 of them) gets tiles of half the size,
+    // down to 64 cells.
+    const int kMinTiles = (c->step_flags & STEP_SMALL_TILES) ? 4096 : 0;
+    for (int TC = TCfull;; TC /= 2) {
+    L.tiles.clear();
+    rect_xy.clear();
+    open.clear();
     auto emit = [&](const Open &o) {
       // split wide rectangles (h == 1) into chunks of at most TC cells
       for (int x = o.xa; x < o.xb; x += TC) {
@@ -969,6 +976,8 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
       open.swap(nopen);
     }
     for (const Open &o : open) emit(o);
+    if (sen_tiles || TC <= 64 || (int64_t)L.tiles.size() >= kMinTiles) break;
+    }
     // order tiles by (y0, x0) for locality
     std::vector<int> order(L.tiles.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
@@ -3232,7 +3241,8 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
 vlbm_status vlbm_set_tuning(vlbm_ctx *c, int tile_cells, int flags) {
   if (!c) return fail(VLBM_EINVAL, "null context");
   if (tile_cells < 64 || tile_cells > (1 << 20) ||
-      (flags & ~(STEP_NT_STORES | STEP_TWO_CELLS | STEP_XCD_CONTIGUOUS | STEP_FUSE2 | STEP_XCD_FUSED | STEP_GRAPHS)))
+      (flags & ~(STEP_NT_STORES | STEP_TWO_CELLS | STEP_XCD_CONTIGUOUS | STEP_FUSE2 | STEP_XCD_FUSED | STEP_GRAPHS |
+                 STEP_SMALL_TILES)))
     return fail(VLBM_EINVAL, "bad tuning (tile_cells %d, flags %d)", tile_cells, flags);
   c->tile_cells = tile_cells;
   c->step_flags = flags | (c->step_flags & STEP_F64_MATH);
@@ -3297,7 +3307,7 @@ vlbm_status vlbm_autotune(vlbm_ctx *c, int steps_per_trial, int *tile_cells, int
       for (int oi = 0; oi < norders; ++oi) {
         const int ord = orders[oi];
         const int fl = (c->step_flags & ~(STEP_XCD_CONTIGUOUS | STEP_FUSE2 | STEP_NT_STORES | STEP_F64_MATH |
-                                          STEP_GRAPHS)) | ord;
+                                          STEP_GRAPHS | STEP_SMALL_TILES)) | ord;
         float ms = 0.f;
         st = time_trial(c, tcell, fl, 1, steps_per_trial, e0, e1, &ms);
         if (st) {
@@ -3310,6 +3320,19 @@ vlbm_status vlbm_autotune(vlbm_ctx *c, int steps_per_trial, int *tile_cells, int
           choice = {tcell, fl};
         }
       }
+    // smaller tiles on levels with few tiles (STEP_SMALL_TILES), kept only
+    // if it saves more than 1%
+    if (!c->sensor) {
+      float base = 0.f, small = 0.f;
+      st = time_trial(c, choice.first, choice.second, 1, steps_per_trial, e0, e1, &base);
+      if (!st) st = time_trial(c, choice.first, choice.second | STEP_SMALL_TILES, 1, steps_per_trial, e0, e1, &small);
+      if (st) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return st;
+      }
+      if (small < 0.99f * base) choice.second |= STEP_SMALL_TILES;
+    }
     // graph replay of the chosen launches (an even number of steps, at least
     // four, so that every step of the trial is replayed) where the context has
     // a stream of its own; kept only if it saves more than 2%

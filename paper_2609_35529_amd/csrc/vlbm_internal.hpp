@@ -100,6 +100,7 @@ enum StepFlags : int32_t {
                              // the CFL term of its stored cells into cfl_next (emit_cfl)
   STEP_XCD_FUSED = 512,      // tuning: XCD-contiguous order for the fused launches only
   STEP_GRAPHS = 1024,        // tuning: replay captured graphs of two coarse steps (kernels unaffected)
+  STEP_SMALL_TILES = 2048,   // tuning: a level with fewer than 4096 step tiles gets smaller tiles
 };
 
 // Device scalars of the adaptive time step, updated once per coarse step by

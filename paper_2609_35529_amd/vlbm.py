@@ -39,7 +39,7 @@ FP64, FP32, FP32_STORAGE = 0, 1, 2
 EOS_IDEAL, EOS_STIFFENED, EOS_VDW = 0, 1, 2
 # vlbm_set_tuning flags
 TUNE_NT_STORES, TUNE_TWO_CELLS, TUNE_XCD_ORDER, TUNE_FUSE2 = 1, 2, 4, 16
-TUNE_XCD_FUSED, TUNE_GRAPHS = 512, 1024
+TUNE_XCD_FUSED, TUNE_GRAPHS, TUNE_SMALL_TILES = 512, 1024, 2048
 
 
 class vlbm_params(C.Structure):

@@ -80,11 +80,12 @@ def test_kh_downscaled_bench_settings_match_oracle():
     """The 4096^2 problem down-scaled to 128^2 coarse (finest level 1024^2),
     with the bench's refinement settings (threshold 0.01, buffer 4, boxes
     16..128, a regrid every 5 coarse steps) and launch tuning (512-cell tiles,
-    non-temporal stores, fused sub-steps of the finest level): bit for bit
-    with the oracle after every regrid and the steps that follow."""
+    non-temporal stores, fused sub-steps of the finest level, smaller tiles on
+    levels with few of them): bit for bit with the oracle after every regrid
+    and the steps that follow."""
     case = _kh_dynamic(128)
     g = gpu_solver(case)
-    g.set_tuning(512, 17)
+    g.set_tuning(512, 17 | 2048)
     for _ in range(case.nlev - 1):
         g.tag_and_regrid(0.01, buffer=4, min_box=16, max_box=128)
     o = exact.run_oracle(case, steps=0)
@@ -109,7 +110,7 @@ def test_kh4096_full_size_prefix():
     for bit (the FP64 contract makes every launch configuration identical)."""
     case = _kh_dynamic(4096)
     runs = []
-    for tile, flags in ((512, 17), (256, 0)):
+    for tile, flags in ((512, 17 | 2048), (256, 0)):
         g = gpu_solver(case)
         g.set_tuning(tile, flags)
         for _ in range(case.nlev - 1):

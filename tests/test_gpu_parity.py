@@ -201,7 +201,7 @@ def test_fp32_drift_per_step_is_reported(precision):
 
 
 @pytest.mark.parametrize("eos", [(1, 0.4, 0.0), (2, 0.1, 0.05)])
-@pytest.mark.parametrize("flags", [0, 16])
+@pytest.mark.parametrize("flags", [0, 16, 16 | 2048])
 def test_non_ideal_eos(eos, flags):
     """Stiffened gas and van der Waals: the bulk relaxation, inflow equilibria
     and set_state use the EOS; FP64 parity with the oracle through three levels
