@@ -222,7 +222,10 @@ vlbm_status vlbm_tag(vlbm_ctx *ctx, int level, double threshold, unsigned char *
 
 /* Tag every level below the finest, dilate by `buffer` cells, cluster into
  * boxes with sides in [min_box, max_box] level-(l+1) cells and regrid
- * (Sec. 3.4, Fig. amr-flowchart). Synchronises. */
+ * (Sec. 3.4, Fig. amr-flowchart). Synchronises. The tags, the tile lists and,
+ * for VLBM_TAG_DENSITY, one FP64 density per frame element of the largest
+ * level live in device scratch that the context keeps between calls (and
+ * vlbm_tag shares); vlbm_destroy frees it. */
 vlbm_status vlbm_tag_and_regrid(vlbm_ctx *ctx, double threshold, int buffer, int min_box,
                                 int max_box);
 

@@ -2222,6 +2222,10 @@ int level_ny(const vlbm_ctx *c, int l) {
 // Refinement tags of the present levels l with dtag[l] set, into dtag[l]
 // (device, indexed like each level's status): the density-gradient indicator,
 // or the sensor of eq. amr-sigma, whose flux maxima run over every level.
+// Scratch slot of the density plane (tag_and_regrid numbers its own slots
+// from 0, a few per level).
+constexpr size_t kRhoSlot = 64;
+
 hipError_t launch_level_tags(vlbm_ctx *c, double thr, const std::vector<uint8_t *> &dtag) {
   hipError_t e = hipSuccess;
   if (c->tag_kind == VLBM_TAG_FLUX) {
@@ -2241,9 +2245,14 @@ hipError_t launch_level_tags(vlbm_ctx *c, double thr, const std::vector<uint8_t 
       e = launch_tag_flux(L.buf[L.cur()], L.dstatus, L.dsrow, L.dyrow, L.plane, L.pitch, L.xoff, L.fx0, L.fy0,
                           L.fw, L.fh, L.nrows, L.Nx, L.Ny, c->perx(), c->pery(), c->fp32, c->eos, c->dflux_qmax,
                           thr, dtag[l], c->stream);
-    else
+    else {
+      // the density plane: one scratch slot of its own, shared by the levels
+      // (their launches follow each other on the stream)
+      double *rho = static_cast<double *>(c->scratch_slot(kRhoSlot, sizeof(double) * (size_t)L.fw * L.nrows));
+      if (!rho) return hipErrorOutOfMemory;
       e = launch_tag(L.buf[L.cur()], L.dstatus, L.dsrow, L.dyrow, L.plane, L.pitch, L.xoff, L.fx0, L.fy0, L.fw,
-                     L.fh, L.nrows, L.Nx, L.Ny, c->perx(), c->pery(), c->fp32, thr, dtag[l], c->stream);
+                     L.fh, L.nrows, L.Nx, L.Ny, c->perx(), c->pery(), c->fp32, thr, rho, dtag[l], c->stream);
+    }
   }
   return e;
 }
@@ -2717,7 +2726,9 @@ vlbm_status vlbm_tag_and_regrid(vlbm_ctx *c, double thr, int buffer, int min_box
     cap[l] = (int)ntiles;
     dlist[l] = static_cast<int32_t *>(dalloc(sizeof(int32_t) * (size_t)std::max<int64_t>(ntiles, 1)));
     int32_t *dtrows = static_cast<int32_t *>(dalloc(sizeof(int32_t) * std::max<size_t>(trows[l].size(), 1)));
-    if (!dlist[l] || !dtrows) {
+    auto *dmasks = static_cast<unsigned long long *>(
+        dalloc(sizeof(unsigned long long) * (size_t)std::max(L.nrows, 1) * (size_t)((L.Nx + 63) / 64)));
+    if (!dlist[l] || !dtrows || !dmasks) {
       release();
       return fail(VLBM_ENOMEM, "tile lists");
     }
@@ -2725,8 +2736,9 @@ vlbm_status vlbm_tag_and_regrid(vlbm_ctx *c, double thr, int buffer, int min_box
       e = hipMemcpyAsync(dtrows, trows[l].data(), sizeof(int32_t) * trows[l].size(), hipMemcpyHostToDevice,
                          c->stream);
     if (e == hipSuccess)
-      e = launch_tile_hits(dtag[l], L.dsrow, L.fx0, L.fy0, L.fw, L.fh, L.Nx, L.Ny, c->perx(), c->pery(), T,
-                           buffer, ntx, dtrows, (int)trows[l].size(), dlist[l], cap[l], dcount + l, c->stream);
+      e = launch_tile_hits(dtag[l], L.dsrow, L.fx0, L.fy0, L.fw, L.fh, L.nrows, L.Nx, L.Ny, c->perx(), c->pery(),
+                           T, buffer, ntx, dtrows, (int)trows[l].size(), dmasks, dlist[l], cap[l], dcount + l,
+                           c->stream);
   }
   std::vector<int> count(std::max(nclu, 1), 0);
   if (e == hipSuccess)

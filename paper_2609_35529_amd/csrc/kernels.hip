@@ -1358,42 +1358,69 @@ __device__ __forceinline__ double cell_rho(const T *b, int64_t P, int64_t o) {
          (double)b[12 * P + o];
 }
 
+// Density of every stored frame cell (0 where it is not an active cell), in
+// FP64 from the stored populations, indexed like the status.
 template <class T>
-__global__ void tag_kernel(const T *__restrict__ buf, const uint8_t *status, const int32_t *srow,
-                           const int32_t *yrow, int64_t P, int pitch, int xoff, int fx0, int fy0, int fw,
-                           int fh, int nrows, int Nx, int Ny, int perx, int pery, double thr, uint8_t *tags) {
-  // one thread per stored frame cell; tags are indexed like the status (only
-  // active cells of the level, which all lie in its frame, can be tagged)
-  const int64_t n = (int64_t)fw * nrows;
-  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
-       c += (int64_t)gridDim.x * blockDim.x) {
-    const int sr = (int)(c / fw), fx = (int)(c - (int64_t)sr * fw);
+__global__ void rho_kernel(const T *__restrict__ buf, const uint8_t *__restrict__ status, int64_t P, int pitch,
+                           int xoff, int fw, int nrows, double *__restrict__ rho) {
+  // x: frame column, y: stored rows (strided when there are more than the grid)
+  const int fx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (fx >= fw) return;
+  for (int sr = blockIdx.y; sr < nrows; sr += gridDim.y) {
+    const int64_t c = (int64_t)sr * fw + fx;
+    rho[c] = status[c] == 1 ? cell_rho<T>(buf, P, (int64_t)sr * pitch + fx + xoff) : 0.0;
+  }
+}
+
+// Density-gradient tags from the density plane (rho_kernel): each density is
+// summed once, and a cell's four neighbours read theirs from the plane.
+__global__ void tag_kernel(const double *__restrict__ rho, const uint8_t *__restrict__ status,
+                           const int32_t *__restrict__ srow, const int32_t *__restrict__ yrow, int fx0, int fy0,
+                           int fw, int fh, int nrows, int Nx, int Ny, int perx, int pery, double thr,
+                           uint8_t *__restrict__ tags) {
+  // one thread per stored frame cell (x: frame column, y: stored rows); tags
+  // are indexed like the status (only active cells of the level, which all
+  // lie in its frame, can be tagged)
+  const int fx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (fx >= fw) return;
+  for (int sr = blockIdx.y; sr < nrows; sr += gridDim.y) {
+    const int64_t c = (int64_t)sr * fw + fx;
     const int x = fx + fx0, y = yrow[sr] + fy0;
-    uint8_t tag = 0;
-    if (status[c] == 1) {
-      const int64_t o = (int64_t)sr * pitch + fx + xoff;
-      const double rc = cell_rho<T>(buf, P, o);
-      double rn[4];
-      const int dx[4] = {1, -1, 0, 0}, dy[4] = {0, 0, 1, -1};
+    // every load issued up front: a neighbour's status and density are read
+    // at once (the density of an inactive neighbour is read and not used)
+    const uint8_t sc = status[c];
+    const double rc = rho[c];
+    const int dx[4] = {1, -1, 0, 0}, dy[4] = {0, 0, 1, -1};
+    int64_t ni[4];
+    bool valid[4];
 #pragma unroll
-      for (int d = 0; d < 4; ++d) {
-        int xx = x + dx[d], yy = y + dy[d];
-        bool ok = true;
-        if (xx < 0 || xx >= Nx) {
-          if (perx) xx = (xx + Nx) % Nx; else ok = false;
-        }
-        if (yy < 0 || yy >= Ny) {
-          if (pery) yy = (yy + Ny) % Ny; else ok = false;
-        }
-        double v = rc;
-        if (ok) {
-          const int gx = xx - fx0, gy = yy - fy0;
-          const int gs = (gy >= 0 && gy < fh) ? srow[gy] : -1;
-          if (gx >= 0 && gx < fw && gs >= 0 && status[(int64_t)gs * fw + gx] == 1)
-            v = cell_rho<T>(buf, P, (int64_t)gs * pitch + gx + xoff);
-        }
-        rn[d] = v;
+    for (int d = 0; d < 4; ++d) {
+      int xx = x + dx[d], yy = y + dy[d];
+      bool ok = true;
+      if (xx < 0 || xx >= Nx) {
+        if (perx) xx = (xx + Nx) % Nx; else ok = false;
       }
+      if (yy < 0 || yy >= Ny) {
+        if (pery) yy = (yy + Ny) % Ny; else ok = false;
+      }
+      const int gx = xx - fx0, gy = yy - fy0;
+      // the same stored row for a neighbour along x
+      const int gs = !ok ? -1 : dy[d] == 0 ? sr : (gy >= 0 && gy < fh) ? srow[gy] : -1;
+      valid[d] = gs >= 0 && gx >= 0 && gx < fw;
+      ni[d] = valid[d] ? (int64_t)gs * fw + gx : c;
+    }
+    uint8_t sn[4];
+    double rv[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      sn[d] = status[ni[d]];
+      rv[d] = rho[ni[d]];
+    }
+    uint8_t tag = 0;
+    if (sc == 1) {
+      double rn[4];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) rn[d] = (valid[d] && sn[d] == 1) ? rv[d] : rc;
       const double gx = fabs(rn[0] - rn[1]) / (2.0 * rc);
       const double gy = fabs(rn[2] - rn[3]) / (2.0 * rc);
       const double g = gx > gy ? gx : gy;
@@ -1405,18 +1432,19 @@ __global__ void tag_kernel(const T *__restrict__ buf, const uint8_t *status, con
 
 hipError_t launch_tag(const void *buf, const uint8_t *status, const int32_t *srow, const int32_t *yrow,
                       int64_t plane, int pitch, int xoff, int fx0, int fy0, int fw, int fh, int nrows,
-                      int Nx, int Ny, int perx, int pery, int fp32, double thr, uint8_t *tags,
+                      int Nx, int Ny, int perx, int pery, int fp32, double thr, double *rho, uint8_t *tags,
                       hipStream_t s) {
   const int64_t n = (int64_t)fw * nrows;
   if (n <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((fw + 255) / 256), (unsigned)std::min(nrows, 65535));
   if (fp32)
-    hipLaunchKernelGGL(tag_kernel<float>, grid_for(n), dim3(256), 0, s, static_cast<const float *>(buf),
-                       status, srow, yrow, plane, pitch, xoff, fx0, fy0, fw, fh, nrows, Nx, Ny, perx, pery,
-                       thr, tags);
+    hipLaunchKernelGGL(rho_kernel<float>, grid, dim3(256), 0, s, static_cast<const float *>(buf), status, plane,
+                       pitch, xoff, fw, nrows, rho);
   else
-    hipLaunchKernelGGL(tag_kernel<double>, grid_for(n), dim3(256), 0, s, static_cast<const double *>(buf),
-                       status, srow, yrow, plane, pitch, xoff, fx0, fy0, fw, fh, nrows, Nx, Ny, perx, pery,
-                       thr, tags);
+    hipLaunchKernelGGL(rho_kernel<double>, grid, dim3(256), 0, s, static_cast<const double *>(buf), status, plane,
+                       pitch, xoff, fw, nrows, rho);
+  hipLaunchKernelGGL(tag_kernel, grid, dim3(256), 0, s, rho, status, srow, yrow, fx0, fy0, fw, fh, nrows, Nx, Ny,
+                     perx, pery, thr, tags);
   return hipGetLastError();
 }
 
@@ -1555,23 +1583,58 @@ hipError_t launch_tag_parents(const uint8_t *ftags, const int32_t *fyrow, int ff
 
 // Tiles of the clustering grid (side T level cells, ntx tiles per tile row)
 // that hold a cell within `buf` cells of a tag (square dilation, periodic axes
-// wrapped, other axes clipped). One thread per tile of the listed tile rows
-// scans the tile's window [x0 - buf, x1 + buf) x [y0 - buf, y1 + buf) of the
-// level's tags (fw bytes per stored frame row); the hits of a wavefront are
-// appended with one atomic add.
-__global__ void tile_hits_kernel(const uint8_t *__restrict__ tags, const int32_t *__restrict__ srow, int fx0,
-                                 int fy0, int fw, int fh, int Nx, int Ny, int perx, int pery, int T, int buf,
-                                 int ntx, const int32_t *__restrict__ trows, int ntrows, int32_t *list, int cap,
-                                 int *count) {
+// wrapped, other axes clipped), in two passes: the rows' tag masks, then per
+// tile a range test of each of its window rows.
+//
+// Row masks of the tags: bit j of word w of stored frame row sr is the tag of
+// level column 64 w + j (0 outside the frame). One thread per level column,
+// 64 columns per wavefront (one word each).
+__global__ void row_mask_kernel(const uint8_t *__restrict__ tags, int fx0, int fw, int nrows, int Nx, int nw,
+                                unsigned long long *__restrict__ masks) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per_row = (int64_t)nw * 64;
+  bool bit = false;
+  int64_t word = -1;
+  if (t < (int64_t)nrows * per_row) {
+    const int sr = (int)(t / per_row), x = (int)(t - (int64_t)sr * per_row);
+    word = (int64_t)sr * nw + (x >> 6);
+    const int fx = x - fx0;
+    bit = x < Nx && fx >= 0 && fx < fw && tags[(int64_t)sr * fw + fx] != 0;
+  }
+  const unsigned long long m = __ballot(bit);
+  if ((threadIdx.x & 63) == 0 && word >= 0) masks[word] = m;
+}
+
+// Any set bit of row mask mr in columns [xa, xb), 0 <= xa < xb.
+__device__ __forceinline__ bool any_bits(const unsigned long long *mr, int xa, int xb) {
+  unsigned long long acc = 0;
+  for (int w = xa >> 6; w <= (xb - 1) >> 6; ++w) {
+    const int lo = w == (xa >> 6) ? (xa & 63) : 0, hi = w == ((xb - 1) >> 6) ? ((xb - 1) & 63) : 63;
+    const unsigned long long sel = (hi == 63 ? ~0ull : ((1ull << (hi + 1)) - 1ull)) & ~((1ull << lo) - 1ull);
+    acc |= mr[w] & sel;
+  }
+  return acc != 0;
+}
+
+// Tiles of side T (level cells) that hold a cell within `buf` of a tag: one
+// thread per tile of the listed tile rows tests its window
+// [x0 - buf, x1 + buf) x [y0 - buf, y1 + buf) row by row on the row masks
+// (periodic axes wrapped, other axes clipped); the hits of a wavefront are
+// appended with one atomic, the list in no particular order (at most cap
+// entries stored).
+__global__ void tile_hits_kernel(const unsigned long long *__restrict__ masks, int nw, const int32_t *__restrict__ srow,
+                                 int fy0, int fh, int Nx, int Ny, int perx, int pery, int T, int buf, int ntx,
+                                 const int32_t *__restrict__ trows, int ntrows, int32_t *list, int cap, int *count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool hit = false;
   int32_t t = 0;
   if (i < (int64_t)ntrows * ntx) {
     const int ty = trows[i / ntx], tx = (int)(i % ntx);
     t = ty * ntx + tx;
-    const int xa = tx * T - buf, xb = min(Nx, tx * T + T) + buf;
+    const int x0 = tx * T, x1 = min(Nx, x0 + T);
+    const int xa = x0 - buf, xb = x1 + buf;
     const int ya = ty * T - buf, yb = min(Ny, ty * T + T) + buf;
-    for (int y = ya; y < yb && !hit; ++y) {
+    for (int y = ya; y < yb; ++y) {
       int wy = y;
       if (wy < 0 || wy >= Ny) {
         if (!pery) continue;
@@ -1581,19 +1644,20 @@ __global__ void tile_hits_kernel(const uint8_t *__restrict__ tags, const int32_t
       if (fr < 0 || fr >= fh) continue;
       const int sr = srow[fr];
       if (sr < 0) continue;
-      const uint8_t *row = tags + (int64_t)sr * fw;
-      for (int x = xa; x < xb; ++x) {
-        int wx = x;
-        if (wx < 0 || wx >= Nx) {
-          if (!perx) continue;
-          wx = wx < 0 ? wx + Nx : wx - Nx;
-        }
-        const int fx = wx - fx0;
-        if (fx >= 0 && fx < fw && row[fx]) {
-          hit = true;
-          break;
-        }
+      const unsigned long long *mr = masks + (int64_t)sr * nw;
+      bool h;
+      if (!perx) {
+        h = any_bits(mr, max(0, xa), min(Nx, xb));
+      } else if (xb - xa >= Nx) {
+        h = any_bits(mr, 0, Nx);
+      } else if (xa < 0) {
+        h = any_bits(mr, xa + Nx, Nx) || any_bits(mr, 0, xb);
+      } else if (xb > Nx) {
+        h = any_bits(mr, xa, Nx) || any_bits(mr, 0, xb - Nx);
+      } else {
+        h = any_bits(mr, xa, xb);
       }
+      hit = hit || h;
     }
   }
   const unsigned long long m = __ballot(hit);
@@ -1609,13 +1673,18 @@ __global__ void tile_hits_kernel(const uint8_t *__restrict__ tags, const int32_t
   }
 }
 
-hipError_t launch_tile_hits(const uint8_t *tags, const int32_t *srow, int fx0, int fy0, int fw, int fh, int Nx,
-                            int Ny, int perx, int pery, int T, int buf, int ntx, const int32_t *trows, int ntrows,
-                            int32_t *list, int cap, int *count, hipStream_t s) {
+hipError_t launch_tile_hits(const uint8_t *tags, const int32_t *srow, int fx0, int fy0, int fw, int fh, int nrows,
+                            int Nx, int Ny, int perx, int pery, int T, int buf, int ntx, const int32_t *trows,
+                            int ntrows, unsigned long long *masks, int32_t *list, int cap, int *count, hipStream_t s) {
+  const int nw = (Nx + 63) / 64;
+  const int64_t nm = (int64_t)nrows * nw * 64;
+  if (nm > 0)
+    hipLaunchKernelGGL(row_mask_kernel, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, s, tags, fx0, fw, nrows,
+                       Nx, nw, masks);
   const int64_t n = (int64_t)ntrows * ntx;
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(tile_hits_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tags, srow, fx0, fy0,
-                     fw, fh, Nx, Ny, perx, pery, T, buf, ntx, trows, ntrows, list, cap, count);
+  if (n <= 0) return hipGetLastError();
+  hipLaunchKernelGGL(tile_hits_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, masks, nw, srow, fy0, fh,
+                     Nx, Ny, perx, pery, T, buf, ntx, trows, ntrows, list, cap, count);
   return hipGetLastError();
 }
 

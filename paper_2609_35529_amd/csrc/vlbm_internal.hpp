@@ -244,10 +244,10 @@ hipError_t launch_get(const RectArgs &a, int fp32, int populations, hipStream_t 
 hipError_t launch_health(const void *buf, const Tile *tiles, int ntiles, int64_t plane,
                          int pitch, int fp32, const EosT<double> &eos, int *flag, hipStream_t s);
 // tags: indexed like the status (fw bytes per stored row), 1 on tagged active
-// cells, else 0
+// cells, else 0; rho: device scratch of fw * nrows doubles (the densities)
 hipError_t launch_tag(const void *buf, const uint8_t *status, const int32_t *srow, const int32_t *yrow,
                       int64_t plane, int pitch, int xoff, int fx0, int fy0, int fw, int fh, int nrows,
-                      int Nx, int Ny, int perx, int pery, int fp32, double thr, uint8_t *tags,
+                      int Nx, int Ny, int perx, int pery, int fp32, double thr, double *rho, uint8_t *tags,
                       hipStream_t s);
 
 // Refinement sensor of eq. amr-sigma: flux_max folds max |Q_{alpha,k}| of a
@@ -269,9 +269,10 @@ hipError_t launch_tag_flux(const void *buf, const uint8_t *status, const int32_t
 hipError_t launch_tag_parents(const uint8_t *ftags, const int32_t *fyrow, int ffx0, int ffy0, int ffw,
                               int fnrows, uint8_t *ptags, const int32_t *psrow, int pfx0, int pfy0, int pfw,
                               int pfh, int r, hipStream_t s);
-hipError_t launch_tile_hits(const uint8_t *tags, const int32_t *srow, int fx0, int fy0, int fw, int fh, int Nx,
-                            int Ny, int perx, int pery, int T, int buf, int ntx, const int32_t *trows, int ntrows,
-                            int32_t *list, int cap, int *count, hipStream_t s);
+// masks: device scratch of nrows * ceil(Nx / 64) words (the rows' tags as bits).
+hipError_t launch_tile_hits(const uint8_t *tags, const int32_t *srow, int fx0, int fy0, int fw, int fh, int nrows,
+                            int Nx, int Ny, int perx, int pery, int T, int buf, int ntx, const int32_t *trows,
+                            int ntrows, unsigned long long *masks, int32_t *list, int cap, int *count, hipStream_t s);
 
 // Regrid kernels: a list of cell operations on level frames.
 struct RegridOp {          // one coarse cell (merge) or one parent cell (split)
