@@ -37,9 +37,9 @@ HBM_PEAK_GBS = 8000.0
 # a plain 2 GiB device copy reads on the same counters: 1,048,588 KiB fetched
 # and 2,097,152 KiB written per 2 GiB); valid only for the kernel source it
 # was measured on.
-MEASURED_TRAFFIC = {"kernel_sha256_16": "89fd30e6fc02339b", "workload": "kh4096",
+MEASURED_TRAFFIC = {"kernel_sha256_16": "f9a98e712236bc2e", "workload": "kh4096",
                     "precision": "fp64", "tile_cells": 512, "flags": (17, 17 | 2048), "kernel": "step_kernel",
-                    "level": 0, "bytes_per_launch": (2 * 1067135.6 + 2082632.7) * 1024}
+                    "level": 0, "bytes_per_launch": (2 * 1067192.9 + 2082632.1) * 1024}
 
 
 # dynamic-refinement workloads: re-tag and regrid every few coarse steps
