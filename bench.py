@@ -637,6 +637,12 @@ def main():
                            "series": drift_series},
         "healthy": healthy,
     }
+    # the timed solve is done: its device memory goes back before the served
+    # stream and the baseline legs run
+    solver.close()
+    del solver, case
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     if not args.no_serve:
         out["served"] = serve_sweep(args)
     if not args.no_cpu_baseline:
