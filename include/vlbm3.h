@@ -71,6 +71,16 @@ typedef struct {
  * VLBM_EINVAL for bad parameters. */
 vlbm_status vlbm3_create(const vlbm3_params *params, void *stream, vlbm3_ctx **out);
 
+/* Take every later device allocation of ctx from the caller's allocator
+ * (vlbm_alloc_fn / vlbm_free_fn of include/vlbm.h; e.g. PyTorch's caching
+ * allocator on the context's stream), so that the caller is the only
+ * allocator; blocks must be 256-byte aligned (others are handed back and
+ * count as a failure). Must precede vlbm3_set_hierarchy (VLBM_ESTATE after
+ * it); VLBM_EINVAL for a null function. Without it the library allocates
+ * with hipMalloc. A failed allocation makes the call that needed it return
+ * VLBM_ENOMEM. vlbm3_destroy releases every block through `release`. */
+vlbm_status vlbm3_bind_allocator(vlbm3_ctx *ctx, vlbm_alloc_fn alloc, vlbm_free_fn release, void *user);
+
 /* Release all device memory of ctx and free it. NULL is a no-op. */
 void vlbm3_destroy(vlbm3_ctx *ctx);
 

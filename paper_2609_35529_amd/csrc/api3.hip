@@ -16,10 +16,12 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/vlbm3.h"
@@ -48,6 +50,14 @@ vlbm_status fail3(vlbm_status st, const char *fmt, ...) {
     hipError_t e_ = (expr);                                                              \
     if (e_ != hipSuccess)                                                                \
       return fail3(VLBM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+  } while (0)
+
+// ptr := n bytes of the context's device memory, or VLBM_ENOMEM.
+#define ALLOC3(ptr, n)                                                                       \
+  do {                                                                                       \
+    const size_t n_ = (n);                                                                   \
+    (ptr) = static_cast<std::remove_reference_t<decltype(ptr)>>(c->mem.alloc(n_));           \
+    if (!(ptr)) return fail3(VLBM_ENOMEM, "device memory (%zu bytes)", n_);                  \
   } while (0)
 
 constexpr int kL = VLBM3_MAX_LEVELS;
@@ -94,14 +104,42 @@ struct Level3 {
   int cur() const { return (int)(steps & 1); }
 };
 
-void dfree(void *&p) {
-  if (p) (void)hipFree(p);
+// Device memory of a context: from the caller's allocator after
+// vlbm3_bind_allocator, else hipMalloc. Blocks are 256-byte aligned.
+struct Alloc3 {
+  vlbm_alloc_fn a = nullptr;
+  vlbm_free_fn f = nullptr;
+  void *user = nullptr;
+  void *alloc(size_t n) {
+    n = (std::max<size_t>(n, 256) + 255) & ~size_t(255);
+    if (a) {
+      void *q = a(n, user);
+      if (q && (reinterpret_cast<uintptr_t>(q) & 255)) {
+        f(q, user);
+        return nullptr;
+      }
+      return q;
+    }
+    void *q = nullptr;
+    return hipMalloc(&q, n) == hipSuccess ? q : nullptr;
+  }
+  void release(void *q) {
+    if (!q) return;
+    if (f)
+      f(q, user);
+    else
+      (void)hipFree(q);
+  }
+};
+
+void dfree(Alloc3 &m, void *&p) {
+  m.release(p);
   p = nullptr;
 }
 template <class T>
-void dfree(T *&p) {
+void dfree(Alloc3 &m, T *&p) {
   void *v = p;
-  dfree(v);
+  dfree(m, v);
   p = nullptr;
 }
 
@@ -139,6 +177,7 @@ struct vlbm3_ctx {
   long flips[kL] = {};
   Desc3 *ddesc = nullptr;
   long table_base = 0;
+  Alloc3 mem;
   bool prof = false;
   std::vector<hipEvent_t> pev;
   std::vector<std::pair<int, double>> pend;
@@ -174,24 +213,24 @@ struct vlbm3_ctx {
 
 namespace {
 
-void free_level3(Level3 &L) {
-  dfree(L.buf[0]);
-  dfree(L.buf[1]);
-  dfree(L.dstatus);
-  dfree(L.dtiles);
-  dfree(L.dtasks);
-  dfree(L.dacc);
-  dfree(L.dledger);
-  dfree(L.dpartial);
+void free_level3(Alloc3 &m, Level3 &L) {
+  dfree(m, L.buf[0]);
+  dfree(m, L.buf[1]);
+  dfree(m, L.dstatus);
+  dfree(m, L.dtiles);
+  dfree(m, L.dtasks);
+  dfree(m, L.dacc);
+  dfree(m, L.dledger);
+  dfree(m, L.dpartial);
   L = Level3();
 }
 
-void free_lists3(Level3 &L) {
-  dfree(L.dtiles);
-  dfree(L.dtasks);
-  dfree(L.dacc);
-  dfree(L.dledger);
-  dfree(L.dpartial);
+void free_lists3(Alloc3 &m, Level3 &L) {
+  dfree(m, L.dtiles);
+  dfree(m, L.dtasks);
+  dfree(m, L.dacc);
+  dfree(m, L.dledger);
+  dfree(m, L.dpartial);
 }
 
 vlbm_status check_params3(const vlbm3_params &p) {
@@ -591,9 +630,9 @@ vlbm_status build_lists3(vlbm3_ctx *c) {
 
 template <class T>
 vlbm_status upload3(vlbm3_ctx *c, T *&dst, const std::vector<T> &v, size_t min_elems = 1) {
-  dfree(dst);
+  dfree(c->mem, dst);
   const size_t n = std::max(v.size(), min_elems);
-  HIPCHK3(hipMalloc((void **)&dst, sizeof(T) * n));
+  ALLOC3(dst, sizeof(T) * n);
   if (!v.empty()) HIPCHK3(hipMemcpyAsync(dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, c->stream));
   return VLBM_OK;
 }
@@ -604,12 +643,12 @@ vlbm_status upload_lists3(vlbm3_ctx *c) {
     vlbm_status st = upload3(c, L.dtiles, L.tiles);
     if (!st) st = upload3(c, L.dtasks, L.tasks);
     if (st) return st;
-    dfree(L.dacc);
-    dfree(L.dledger);
-    dfree(L.dpartial);
-    HIPCHK3(hipMalloc((void **)&L.dacc, sizeof(double) * 5 * std::max(1, L.nacc)));
-    HIPCHK3(hipMalloc((void **)&L.dledger, sizeof(double) * 5 * std::max(1, L.nledger)));
-    HIPCHK3(hipMalloc((void **)&L.dpartial, sizeof(double) * 5 * std::max<size_t>(1, L.tiles.size())));
+    dfree(c->mem, L.dacc);
+    dfree(c->mem, L.dledger);
+    dfree(c->mem, L.dpartial);
+    ALLOC3(L.dacc, sizeof(double) * 5 * std::max(1, L.nacc));
+    ALLOC3(L.dledger, sizeof(double) * 5 * std::max(1, L.nledger));
+    ALLOC3(L.dpartial, sizeof(double) * 5 * std::max<size_t>(1, L.tiles.size()));
     HIPCHK3(hipMemsetAsync(L.dacc, 0, sizeof(double) * 5 * std::max(1, L.nacc), c->stream));
     HIPCHK3(hipMemsetAsync(L.dledger, 0, sizeof(double) * 5 * std::max(1, L.nledger), c->stream));
   }
@@ -668,8 +707,8 @@ vlbm_status build_tables3(vlbm3_ctx *c) {
       st[l] += 1;
     }
   }
-  dfree(c->ddesc);
-  HIPCHK3(hipMalloc((void **)&c->ddesc, sizeof(Desc3) * descs.size()));
+  dfree(c->mem, c->ddesc);
+  ALLOC3(c->ddesc, sizeof(Desc3) * descs.size());
   HIPCHK3(hipMemcpyAsync(c->ddesc, descs.data(), sizeof(Desc3) * descs.size(), hipMemcpyHostToDevice, c->stream));
   HIPCHK3(hipStreamSynchronize(c->stream));
   c->table_base = c->coarse_steps;
@@ -760,7 +799,7 @@ vlbm_status rect_io3(vlbm3_ctx *c, int level, const int lo[3], const int ext[3],
   }
   const size_t n = (size_t)cext[0] * cext[1] * cext[2];
   double *stage = nullptr;
-  HIPCHK3(hipMalloc((void **)&stage, sizeof(double) * ncomp * n));
+  ALLOC3(stage, sizeof(double) * ncomp * n);
   std::vector<double> tmp(ncomp * n);
   Rect3 a{};
   a.buf0 = write ? L.buf[0] : L.buf[L.cur()];
@@ -809,7 +848,7 @@ vlbm_status rect_io3(vlbm3_ctx *c, int level, const int lo[3], const int ext[3],
             memcpy(&host[hidx(k, 0, y, z)], &tmp[(size_t)k * n + ((size_t)z * cext[1] + y) * cext[0]],
                    sizeof(double) * cext[0]);
   }
-  (void)hipFree(stage);
+  c->mem.release(stage);
   if (e != hipSuccess) return fail3(VLBM_EDEVICE, "state transfer: %s", hipGetErrorString(e));
   return VLBM_OK;
 }
@@ -960,7 +999,7 @@ vlbm_status tag_frame3(vlbm3_ctx *c, int l, double thr, TagMap3 &T) {
   }
   T.t.assign(n, 0);
   uint8_t *dt = nullptr;
-  HIPCHK3(hipMalloc((void **)&dt, n));
+  ALLOC3(dt, n);
   Tag3Args a{};
   a.buf = L.buf[L.cur()];
   a.status = L.dstatus;
@@ -979,7 +1018,7 @@ vlbm_status tag_frame3(vlbm3_ctx *c, int l, double thr, TagMap3 &T) {
   hipError_t e = launch_tag3(a, c->fp32, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(T.t.data(), dt, n, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  (void)hipFree(dt);
+  c->mem.release(dt);
   if (e != hipSuccess) return fail3(VLBM_EDEVICE, "tags: %s", hipGetErrorString(e));
   return VLBM_OK;
 }
@@ -1209,12 +1248,21 @@ vlbm_status vlbm3_create(const vlbm3_params *params, void *stream, vlbm3_ctx **o
   return VLBM_OK;
 }
 
+vlbm_status vlbm3_bind_allocator(vlbm3_ctx *c, vlbm_alloc_fn alloc, vlbm_free_fn release, void *user) {
+  if (!c || !alloc || !release) return fail3(VLBM_EINVAL, "null argument");
+  if (c->have_hierarchy) return fail3(VLBM_ESTATE, "bind the allocator before installing a hierarchy");
+  c->mem.a = alloc;
+  c->mem.f = release;
+  c->mem.user = user;
+  return VLBM_OK;
+}
+
 void vlbm3_destroy(vlbm3_ctx *c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t ev : c->pev) (void)hipEventDestroy(ev);
-  for (int l = 0; l < kL; ++l) free_level3(c->lv[l]);
-  dfree(c->ddesc);
+  for (int l = 0; l < kL; ++l) free_level3(c->mem, c->lv[l]);
+  dfree(c->mem, c->ddesc);
   delete c;
 }
 
@@ -1241,23 +1289,23 @@ vlbm_status vlbm3_set_hierarchy(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes
   vlbm_status st = build_geometry3(c->p, boxes, nboxes, nl, nnlev);
   if (st) return st;
   HIPCHK3(hipStreamSynchronize(c->stream));
-  for (int l = 0; l < kL; ++l) free_level3(c->lv[l]);
+  for (int l = 0; l < kL; ++l) free_level3(c->mem, c->lv[l]);
   c->have_hierarchy = false;
   for (int l = 0; l < kL; ++l) c->lv[l] = std::move(nl[l]);
   c->nlev = nnlev;
   st = build_lists3(c);
   if (st) {
-    for (int m = 0; m < kL; ++m) free_level3(c->lv[m]);
+    for (int m = 0; m < kL; ++m) free_level3(c->mem, c->lv[m]);
     return st;
   }
   for (int l = 0; l < c->nlev; ++l) {
     Level3 &L = c->lv[l];
     const size_t nb = level_bytes3(L);
-    HIPCHK3(hipMalloc(&L.buf[0], nb));
-    HIPCHK3(hipMalloc(&L.buf[1], nb));
+    ALLOC3(L.buf[0], nb);
+    ALLOC3(L.buf[1], nb);
     HIPCHK3(hipMemsetAsync(L.buf[0], 0, nb, c->stream));
     HIPCHK3(hipMemsetAsync(L.buf[1], 0, nb, c->stream));
-    HIPCHK3(hipMalloc((void **)&L.dstatus, L.status.size()));
+    ALLOC3(L.dstatus, L.status.size());
     HIPCHK3(hipMemcpyAsync(L.dstatus, L.status.data(), L.status.size(), hipMemcpyHostToDevice, c->stream));
     L.steps = 0;
   }
@@ -1284,7 +1332,7 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
   auto new_cov = [&](int l, const int q[3]) { return cov_in(nl, nnlev, l, q); };
   std::vector<void *> scratch;  // device op lists, freed after the final sync
   auto upload_ops = [&](const std::vector<RegridOp3> &ops, RegridOp3 *&d) -> vlbm_status {
-    HIPCHK3(hipMalloc((void **)&d, sizeof(RegridOp3) * std::max<size_t>(1, ops.size())));
+    ALLOC3(d, sizeof(RegridOp3) * std::max<size_t>(1, ops.size()));
     scratch.push_back(d);
     if (!ops.empty()) HIPCHK3(hipMemcpyAsync(d, ops.data(), sizeof(RegridOp3) * ops.size(), hipMemcpyHostToDevice, c->stream));
     return VLBM_OK;
@@ -1337,8 +1385,8 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
       continue;
     }
     const size_t nb = level_bytes3(N);
-    HIPCHK3(hipMalloc(&N.buf[0], nb));
-    HIPCHK3(hipMalloc(&N.buf[1], nb));
+    ALLOC3(N.buf[0], nb);
+    ALLOC3(N.buf[1], nb);
     HIPCHK3(hipMemsetAsync(N.buf[0], 0, nb, c->stream));
     HIPCHK3(hipMemsetAsync(N.buf[1], 0, nb, c->stream));
     if (!O || !O->present) continue;
@@ -1367,7 +1415,7 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
       }
     if (runs.empty()) continue;
     int32_t *druns = nullptr;
-    HIPCHK3(hipMalloc((void **)&druns, sizeof(int32_t) * runs.size()));
+    ALLOC3(druns, sizeof(int32_t) * runs.size());
     scratch.push_back(druns);
     HIPCHK3(hipMemcpyAsync(druns, runs.data(), sizeof(int32_t) * runs.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK3(launch_copy3_runs(O->buf[0], O->buf[1], N.buf[0], N.buf[1], druns, (int)(runs.size() / 3), O->plane,
@@ -1416,12 +1464,12 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
     HIPCHK3(launch_split3(a, c->fp32, c->stream));
   }
   HIPCHK3(hipStreamSynchronize(c->stream));
-  for (void *p : scratch) (void)hipFree(p);
+  for (void *p : scratch) c->mem.release(p);
   scratch.clear();
   // 4. install the new hierarchy and rebuild its lists
   std::vector<int64_t> old_faces[kL];
   for (int l = 0; l < onlev; ++l) old_faces[l].swap(c->lv[l].face_key);
-  for (int l = 0; l < kL; ++l) free_level3(c->lv[l]);
+  for (int l = 0; l < kL; ++l) free_level3(c->mem, c->lv[l]);
   for (int l = 0; l < kL; ++l) c->lv[l] = std::move(nl[l]);
   c->nlev = nnlev;
   st = build_lists3(c);
@@ -1442,17 +1490,17 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
     }
     if (items.empty()) continue;
     int32_t *d = nullptr;
-    HIPCHK3(hipMalloc((void **)&d, sizeof(int32_t) * items.size()));
+    ALLOC3(d, sizeof(int32_t) * items.size());
     scratch.push_back(d);
     HIPCHK3(hipMemcpyAsync(d, items.data(), sizeof(int32_t) * items.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK3(launch_restart_faces3(N.buf[N.cur()], N.buf[N.cur() ^ 1], d, (int)(items.size() / 2), N.plane,
                                   c->fp32, c->stream));
   }
   HIPCHK3(hipStreamSynchronize(c->stream));
-  for (void *p : scratch) (void)hipFree(p);
+  for (void *p : scratch) c->mem.release(p);
   for (int l = 0; l < c->nlev; ++l) {
     Level3 &L = c->lv[l];
-    HIPCHK3(hipMalloc((void **)&L.dstatus, L.status.size()));
+    ALLOC3(L.dstatus, L.status.size());
     HIPCHK3(hipMemcpyAsync(L.dstatus, L.status.data(), L.status.size(), hipMemcpyHostToDevice, c->stream));
   }
   st = upload_lists3(c);
@@ -1546,7 +1594,7 @@ vlbm_status vlbm3_set_tuning(vlbm3_ctx *c, int tile_cells, int flags) {
   double led[5] = {}, tot[5];
   vlbm_status st = vlbm3_conserved_totals(c, tot, led);
   if (st) return st;
-  for (int l = 0; l < c->nlev; ++l) free_lists3(c->lv[l]);
+  for (int l = 0; l < c->nlev; ++l) free_lists3(c->mem, c->lv[l]);
   st = build_lists3(c);
   if (!st) st = upload_lists3(c);
   if (st) return st;

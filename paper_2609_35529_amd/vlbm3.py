@@ -71,6 +71,7 @@ vlbm3_tag_and_regrid = _sig("vlbm3_tag_and_regrid", _st, [_P, C.c_double, C.c_in
 vlbm3_get_boxes = _sig("vlbm3_get_boxes", _st, [_P, C.POINTER(vlbm3_box), C.c_int, C.POINTER(C.c_int)])
 vlbm3_save = _sig("vlbm3_save", _st, [_P, C.c_void_p, C.POINTER(C.c_size_t)])
 vlbm3_load = _sig("vlbm3_load", _st, [_P, C.c_void_p, C.c_size_t])
+vlbm3_bind_allocator = _sig("vlbm3_bind_allocator", _st, [_P, _v.ALLOC_FN, _v.FREE_FN, C.c_void_p])
 
 EXPORTED = ["vlbm3_create", "vlbm3_destroy", "vlbm3_footprint_bytes", "vlbm3_set_hierarchy",
             "vlbm3_regrid",
@@ -78,7 +79,7 @@ EXPORTED = ["vlbm3_create", "vlbm3_destroy", "vlbm3_footprint_bytes", "vlbm3_set
             "vlbm3_get_populations", "vlbm3_advance", "vlbm3_conserved_totals",
             "vlbm3_set_tuning", "vlbm3_set_profiling", "vlbm3_kernel_times",
             "vlbm3_active_cells", "vlbm3_sync", "vlbm3_tag", "vlbm3_tag_and_regrid", "vlbm3_get_boxes",
-            "vlbm3_save", "vlbm3_load"]
+            "vlbm3_save", "vlbm3_load", "vlbm3_bind_allocator"]
 
 
 def make_params(nx0, ny0, nz0, dx0, gamma=1.4, c=1.0, beta=0.9, r=2, max_levels=2,
@@ -106,19 +107,33 @@ def _dp(a):
 
 
 class Solver3:
-    """One 3-D hierarchy on one GPU. Arrays are (comp, z, y, x)."""
+    """One 3-D hierarchy on one GPU. Arrays are (comp, z, y, x).
+
+    memory="torch" (default when torch is importable) takes every device block
+    from PyTorch's caching allocator on the solver's stream
+    (vlbm3_bind_allocator); memory="library" lets the library hipMalloc."""
 
     def __init__(self, nx0, ny0, nz0, dx0, gamma=1.4, c=1.0, beta=0.9, r=2, max_levels=2,
-                 bc=(PERIODIC,) * 6, stream=None, precision=FP64):
+                 bc=(PERIODIC,) * 6, stream=None, precision=FP64, memory="torch"):
         self.r, self.n0 = r, (nx0, ny0, nz0)
         self.p = make_params(nx0, ny0, nz0, dx0, gamma, c, beta, r, max_levels, bc, precision)
         self._h = C.c_void_p()
+        self._alloc = None
         check(vlbm3_create(C.byref(self.p), _v._stream_handle(stream), C.byref(self._h)))
+        if memory == "torch" and _v.torch is not None:
+            self._alloc = _v.TorchAllocator(stream)
+            check(vlbm3_bind_allocator(self._h, self._alloc.alloc_cb, self._alloc.free_cb, None))
+        elif memory not in ("torch", "library"):
+            raise ValueError(f"memory={memory!r}")
+
+    @property
+    def memory(self):
+        return "torch" if self._alloc is not None else "library"
 
     @classmethod
-    def from_case(cls, case, stream=None, max_levels=None, precision=FP64):
+    def from_case(cls, case, stream=None, max_levels=None, precision=FP64, memory="torch"):
         s = cls(case.nx0, case.ny0, case.nz0, case.dx0, case.gamma, case.c, case.beta, case.r,
-                max_levels or case.nlev, case.bc, stream, precision)
+                max_levels or case.nlev, case.bc, stream, precision, memory)
         s.set_hierarchy(case.boxes)
         for l, U in enumerate(case.states):
             if U is not None:
@@ -129,6 +144,7 @@ class Solver3:
         if getattr(self, "_h", None) and self._h.value:
             vlbm3_destroy(self._h)
             self._h = C.c_void_p()
+        self._alloc = None
 
     def __del__(self):
         try:
