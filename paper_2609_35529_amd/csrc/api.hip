@@ -2271,6 +2271,7 @@ vlbm_status tag_frame(vlbm_ctx *c, int l, double thr, std::vector<uint8_t> &ft) 
   if (e == hipSuccess) e = hipMemcpyAsync(ft.data(), d, n, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   c->mem.release(d);
+  if (e == hipErrorOutOfMemory) return fail(VLBM_ENOMEM, "tag scratch");
   if (e != hipSuccess) return fail(VLBM_EDEVICE, "tag: %s", hipGetErrorString(e));
   return VLBM_OK;
 }
@@ -2753,6 +2754,7 @@ vlbm_status vlbm_tag_and_regrid(vlbm_ctx *c, double thr, int buffer, int min_box
   }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   release();
+  if (e == hipErrorOutOfMemory) return fail(VLBM_ENOMEM, "tag scratch");
   if (e != hipSuccess) return fail(VLBM_EDEVICE, "tag and cluster: %s", hipGetErrorString(e));
   tm.mark("tags+tiles");
   // 3. boxes, level by level: each level's kept tiles must lie in the
