@@ -68,6 +68,8 @@ def build_case(name, steps):
         return wl.sod_2d(steps=steps)
     if name == "shock_bubble":
         return wl.shock_bubble(steps=steps)
+    if name == "patches":
+        return wl.patch_set(seed=0, steps=steps)
     if name == "kh_strip":
         return wl.kelvin_helmholtz_strip(steps=steps)
     if name == "kh4096":

@@ -486,6 +486,61 @@ def shock_bubble(nx0=1024, ny0=256, steps=500, nlev=3, r=2, beta=0.8, kappa=1.5)
                 (INFLOW, OUTFLOW, REFLECT, REFLECT), [], states, steps, w_inflow=win)
 
 
+def patch_set(seed=0, nx0=1024, ny0=256, np_range=(100, 400), size_range=(16, 128), steps=100,
+              beta=0.8, kappa=1.5, max_tries=200):
+    """Batched uneven patches on the shock-bubble problem (its base grid,
+    state and sides): a seeded, static set of N_p ~ U{np_range} boxes, levels
+    1 and 2 in a 3:1 ratio (N_p // 4 on level 2), sides ~ U{size_range}
+    level-l cells made even (whole parent cells). Draws in order: N_p; per
+    level-1 box its width, height and position until it overlaps no earlier
+    level-1 box (at most max_tries draws per box); per level-2 box its width,
+    height, host level-1 box and position, its parent footprint one level-1
+    cell inside the host on every side and overlapping no earlier level-2
+    box. Boxes whose draws all fail are left out (the Case name states the
+    counts placed)."""
+    base = shock_bubble(nx0=nx0, ny0=ny0, steps=steps, nlev=3, beta=beta, kappa=kappa)
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(np_range[0], np_range[1] + 1))
+    n2 = n // 4
+    n1 = n - n2
+    lo, hi = size_range
+
+    def side():
+        v = int(rng.integers(lo, hi + 1))
+        return v + (v % 2)
+
+    W1, H1 = 2 * nx0, 2 * ny0
+    occ1 = np.zeros((H1, W1), dtype=bool)
+    b1 = []
+    for _ in range(n1):
+        for _ in range(max_tries):
+            w, h = min(side(), W1), min(side(), H1)
+            x = 2 * int(rng.integers(0, (W1 - w) // 2 + 1))
+            y = 2 * int(rng.integers(0, (H1 - h) // 2 + 1))
+            if not occ1[y:y + h, x:x + w].any():
+                occ1[y:y + h, x:x + w] = True
+                b1.append((1, x, y, w, h))
+                break
+    occ2 = np.zeros((2 * H1, 2 * W1), dtype=bool)
+    b2 = []
+    for _ in range(n2):
+        for _ in range(max_tries):
+            w, h = side(), side()
+            _, hx, hy, hw, hh = b1[int(rng.integers(0, len(b1)))]
+            fw, fh = w // 2, h // 2  # parent footprint in level-1 cells
+            if fw > hw - 2 or fh > hh - 2:
+                continue
+            fx = hx + 1 + int(rng.integers(0, hw - 2 - fw + 1))
+            fy = hy + 1 + int(rng.integers(0, hh - 2 - fh + 1))
+            x, y = 2 * fx, 2 * fy
+            if not occ2[y:y + h, x:x + w].any():
+                occ2[y:y + h, x:x + w] = True
+                b2.append((2, x, y, w, h))
+                break
+    name = f"patch_set(seed {seed}: {len(b1)} level-1 and {len(b2)} level-2 boxes of {n} drawn)"
+    return dataclasses.replace(base, name=name, boxes=b1 + b2)
+
+
 def request_stream(n_requests, rate, seed=0, sizes=(64, 128, 256, 512, 1024),
                    steps_range=(200, 2000)):
     """Poisson arrivals of quadrant Riemann solves: per request draw in order
