@@ -35,7 +35,9 @@
  *   Every call returns a vlbm_status and never throws across the ABI. Host
  *   pointers are owned by the caller and used only during the call. Device
  *   memory is suballocated from a caller-bound pool (vlbm_bind_pool) or, when
- *   none is bound, allocated by the library; vlbm_destroy releases it. Work is
+ *   none is bound, allocated by the library; vlbm_destroy releases it. Table
+ *   uploads go through a pinned host staging area of the context (4-64 MB,
+ *   grown on demand, freed by vlbm_destroy). Work is
  *   issued on the HIP stream given at creation (NULL: the default stream);
  *   vlbm_advance returns before the GPU finishes, every call that returns data
  *   to the host synchronises the stream first. A context must not be used from

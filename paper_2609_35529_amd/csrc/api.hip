@@ -30,6 +30,7 @@
 #include <vector>
 
 #include "../../include/vlbm.h"
+#include "host_pool.hpp"
 #include "vlbm_internal.hpp"
 
 using namespace vlbm;
@@ -241,6 +242,7 @@ struct Level {
   int64_t plane = 0;
   void *buf[2] = {nullptr, nullptr};
   uint8_t *dstatus = nullptr;
+  void *dtables = nullptr;  // one block: dstatus, dsrow, dyrow and the tile, task and slot tables
   std::vector<uint8_t> cov;     // per frame cell: covered at this level
   std::vector<uint8_t> status;  // 0 none, 1 active, 2 hole
   std::vector<Tile> tiles;
@@ -364,6 +366,10 @@ struct vlbm_ctx {
     return e.first;
   }
 
+  // pinned host staging of table uploads (stage_h2d)
+  char *stage = nullptr;
+  size_t stage_cap = 0, stage_used = 0;
+
   bool perx() const { return p.bc[0] == VLBM_BC_PERIODIC; }
   bool pery() const { return p.bc[2] == VLBM_BC_PERIODIC; }
   bool wrap(int l, int &x, int &y) const {
@@ -399,18 +405,9 @@ void drop_batch_graphs(vlbm_ctx *c);  // captured batches that hold c (vlbm_batc
 void free_level(vlbm_ctx *c, Level &L) {
   c->mem.release(L.buf[0]);
   c->mem.release(L.buf[1]);
-  c->mem.release(L.dstatus);
-  c->mem.release(L.dtiles);
-  c->mem.release(L.dtasks);
-  c->mem.release(L.dftiles);
-  c->mem.release(L.dftasks);
-  c->mem.release(L.dacc);
-  c->mem.release(L.dledger);
-  c->mem.release(L.dpartial);
+  c->mem.release(L.dtables);  // status, row maps, tiles, tasks, slots (upload_level)
   c->mem.release(L.dsen);
   c->mem.release(L.dmask);
-  c->mem.release(L.dsrow);
-  c->mem.release(L.dyrow);
   long steps = L.steps;
   L = Level();
   L.steps = steps;
@@ -792,22 +789,17 @@ vlbm_status build_fused(vlbm_ctx *c, int l, const std::unordered_map<int64_t, in
   return VLBM_OK;
 }
 
-// Run f(i) for i in [0, n), each on its own thread (i = 0 on this one). The
-// status of the lowest failing index is returned, with its message (messages
-// are per thread).
+// Run f(i) for i in [0, n) on the process's worker pool and this thread
+// (independent items, in any order and concurrency). The status of the lowest
+// failing index is returned, with its message (messages are per thread).
 vlbm_status run_parallel(int n, const std::function<vlbm_status(int)> &f) {
   if (n <= 1) return n == 1 ? f(0) : VLBM_OK;
   std::vector<vlbm_status> st(n, VLBM_OK);
   std::vector<std::string> err(n);
-  std::vector<std::thread> th;
-  for (int i = 1; i < n; ++i)
-    th.emplace_back([&, i] {
-      st[i] = f(i);
-      if (st[i]) err[i] = g_err;
-    });
-  st[0] = f(0);
-  if (st[0]) err[0] = g_err;
-  for (auto &t : th) t.join();
+  vlbm_host::Pool::get().run(n, [&](int i) {
+    st[i] = f(i);
+    if (st[i]) err[i] = g_err;
+  });
   for (int i = 0; i < n; ++i)
     if (st[i]) {
       g_err = err[i];
@@ -816,8 +808,10 @@ vlbm_status run_parallel(int n, const std::function<vlbm_status(int)> &f) {
   return VLBM_OK;
 }
 
-vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
-  PhaseTimer tm("build_lists");
+// Coverage, proper nesting and cell status of every present level of c, from
+// the boxes.
+vlbm_status build_coverage(vlbm_ctx *c, const vlbm_box *boxes, int n) {
+  PhaseTimer tm("build_coverage");
   const vlbm_params &p = c->p;
   const int r = p.r;
   int nlev = 0;
@@ -892,6 +886,17 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
   });
   if (cst) return cst;
   tm.mark("status");
+  return VLBM_OK;
+}
+
+// Tiles, ghost tasks, reflux and ledger slots, captures and fused lists of
+// every present level of c (after build_coverage). Reads the levels' frames,
+// coverage and status; writes only their lists.
+vlbm_status build_task_lists(vlbm_ctx *c) {
+  PhaseTimer tm("build_task_lists");
+  const int r = c->p.r;
+  int nlev = 0;
+  while (nlev < kMaxLevels && c->lv[nlev].present) ++nlev;
   // Per level, two passes; the levels of a pass run on threads of their own.
   // Pass A: tiles, cell -> tile map, ghost tasks, reflux and ledger slots.
   // Pass B (needs the parent's reflux slots): captures, task order, fused lists.
@@ -1155,6 +1160,62 @@ vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
   return st;
 }
 
+vlbm_status build_lists(vlbm_ctx *c, const vlbm_box *boxes, int n) {
+  vlbm_status st = build_coverage(c, boxes, n);
+  return st ? st : build_task_lists(c);
+}
+
+// Pinned host staging of uploads: n bytes of the context's staging area that
+// no copy in flight reads (the caller fills them and copies from them on the
+// context's stream), or nullptr when n exceeds kStageMax or no pinned memory
+// can be had. The area is used front to back and restarts after a
+// synchronisation of the stream when a request does not fit; it grows to the
+// largest request up to kStageMax.
+constexpr size_t kStageMin = size_t(4) << 20, kStageMax = size_t(64) << 20;
+char *stage_reserve(vlbm_ctx *c, size_t n, hipError_t &e) {
+  e = hipSuccess;
+  const size_t need = (std::max<size_t>(n, 1) + 255) & ~size_t(255);
+  if (need > kStageMax) return nullptr;
+  if (c->stage_used + need > c->stage_cap) {
+    e = hipStreamSynchronize(c->stream);  // the stream has read the area
+    if (e != hipSuccess) return nullptr;
+    c->stage_used = 0;
+    if (need > c->stage_cap) {
+      const size_t cap = std::min(kStageMax, std::max({need, kStageMin, 2 * c->stage_cap}));
+      if (c->stage) (void)hipHostFree(c->stage);
+      c->stage = nullptr;
+      c->stage_cap = 0;
+      void *h = nullptr;
+      if (hipHostMalloc(&h, cap, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+      c->stage = static_cast<char *>(h);
+      c->stage_cap = cap;
+    }
+  }
+  char *h = c->stage + c->stage_used;
+  c->stage_used += need;
+  return h;
+}
+
+// Host-to-device copy of n bytes, asynchronous on the context's stream: the
+// source may change as soon as this returns. Through the staging area (a DMA
+// enqueue instead of a staged pageable copy); beyond it, from the pageable
+// source, followed by a synchronisation.
+hipError_t stage_h2d(vlbm_ctx *c, void *dst, const void *src, size_t n) {
+  if (n == 0) return hipSuccess;
+  hipError_t e;
+  char *h = stage_reserve(c, n, e);
+  if (e != hipSuccess) return e;
+  if (!h) {
+    e = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, c->stream);
+    return e == hipSuccess ? hipStreamSynchronize(c->stream) : e;
+  }
+  memcpy(h, src, n);
+  return hipMemcpyAsync(dst, h, n, hipMemcpyHostToDevice, c->stream);
+}
+
 vlbm_status upload_level(vlbm_ctx *c, Level &L, bool alloc_buffers) {
   auto &M = c->mem;
   if (alloc_buffers) {
@@ -1165,38 +1226,52 @@ vlbm_status upload_level(vlbm_ctx *c, Level &L, bool alloc_buffers) {
     HIPCHK(hipMemsetAsync(L.buf[0], 0, nb, c->stream));
     HIPCHK(hipMemsetAsync(L.buf[1], 0, nb, c->stream));
   }
-  L.dstatus = static_cast<uint8_t *>(M.alloc(L.status.size()));
-  L.dsrow = static_cast<int32_t *>(M.alloc(sizeof(int32_t) * std::max<size_t>(1, L.srow.size())));
-  L.dyrow = static_cast<int32_t *>(M.alloc(sizeof(int32_t) * std::max<size_t>(1, L.yrow.size())));
-  if (!L.dsrow || !L.dyrow) return fail(VLBM_ENOMEM, "level row tables");
-  if (!L.srow.empty())
-    HIPCHK(hipMemcpyAsync(L.dsrow, L.srow.data(), sizeof(int32_t) * L.srow.size(), hipMemcpyHostToDevice, c->stream));
-  if (!L.yrow.empty())
-    HIPCHK(hipMemcpyAsync(L.dyrow, L.yrow.data(), sizeof(int32_t) * L.yrow.size(), hipMemcpyHostToDevice, c->stream));
-  L.dtiles = static_cast<Tile *>(M.alloc(sizeof(Tile) * std::max<size_t>(1, L.tiles.size())));
-  L.dtasks = static_cast<Task *>(M.alloc(sizeof(Task) * std::max<size_t>(1, L.tasks.size())));
-  L.dacc = static_cast<double *>(M.alloc(sizeof(double) * 4 * std::max(1, L.nacc)));
-  L.dledger = static_cast<double *>(M.alloc(sizeof(double) * 4 * std::max(1, L.nledger)));
-  L.dpartial = static_cast<double *>(M.alloc(sizeof(double) * 4 * std::max<size_t>(1, L.tiles.size())));
-  if (!L.dstatus || !L.dtiles || !L.dtasks || !L.dacc || !L.dledger || !L.dpartial)
-    return fail(VLBM_ENOMEM, "level tables");
-  if (!L.ftiles.empty()) {
-    L.dftiles = static_cast<Tile *>(M.alloc(sizeof(Tile) * L.ftiles.size()));
-    L.dftasks = static_cast<Task *>(M.alloc(sizeof(Task) * std::max<size_t>(1, L.ftasks.size())));
-    if (!L.dftiles || !L.dftasks) return fail(VLBM_ENOMEM, "fused level tables");
-    HIPCHK(hipMemcpyAsync(L.dftiles, L.ftiles.data(), sizeof(Tile) * L.ftiles.size(), hipMemcpyHostToDevice, c->stream));
-    if (!L.ftasks.empty())
-      HIPCHK(hipMemcpyAsync(L.dftasks, L.ftasks.data(), sizeof(Task) * L.ftasks.size(), hipMemcpyHostToDevice, c->stream));
+  // Every table of the level lives in one device block, written by one copy
+  // of its host image (reflux accumulators and ledger slots zeroed by it).
+  struct Part {
+    void **dst;
+    const void *src;  // bytes copied; the rest of the part is zeroed
+    size_t nsrc, n;
+  };
+  const bool fused = !L.ftiles.empty();
+  const Part parts[] = {
+      {(void **)&L.dstatus, L.status.data(), L.status.size(), L.status.size()},
+      {(void **)&L.dsrow, L.srow.data(), sizeof(int32_t) * L.srow.size(), sizeof(int32_t) * std::max<size_t>(1, L.srow.size())},
+      {(void **)&L.dyrow, L.yrow.data(), sizeof(int32_t) * L.yrow.size(), sizeof(int32_t) * std::max<size_t>(1, L.yrow.size())},
+      {(void **)&L.dtiles, L.tiles.data(), sizeof(Tile) * L.tiles.size(), sizeof(Tile) * std::max<size_t>(1, L.tiles.size())},
+      {(void **)&L.dtasks, L.tasks.data(), sizeof(Task) * L.tasks.size(), sizeof(Task) * std::max<size_t>(1, L.tasks.size())},
+      {(void **)&L.dacc, nullptr, 0, sizeof(double) * 4 * std::max(1, L.nacc)},
+      {(void **)&L.dledger, nullptr, 0, sizeof(double) * 4 * std::max(1, L.nledger)},
+      {(void **)&L.dpartial, nullptr, 0, sizeof(double) * 4 * std::max<size_t>(1, L.tiles.size())},
+      {fused ? (void **)&L.dftiles : nullptr, L.ftiles.data(), sizeof(Tile) * L.ftiles.size(), sizeof(Tile) * L.ftiles.size()},
+      {fused ? (void **)&L.dftasks : nullptr, L.ftasks.data(), sizeof(Task) * L.ftasks.size(),
+       sizeof(Task) * std::max<size_t>(1, L.ftasks.size())},
+  };
+  size_t at[sizeof parts / sizeof parts[0]], total = 0;
+  for (size_t i = 0; i < sizeof parts / sizeof parts[0]; ++i) {
+    at[i] = total;
+    if (parts[i].dst) total += (std::max<size_t>(parts[i].n, 1) + 255) & ~size_t(255);
   }
-  HIPCHK(hipMemcpyAsync(L.dstatus, L.status.data(), L.status.size(), hipMemcpyHostToDevice, c->stream));
-  if (!L.tiles.empty())
-    HIPCHK(hipMemcpyAsync(L.dtiles, L.tiles.data(), sizeof(Tile) * L.tiles.size(), hipMemcpyHostToDevice, c->stream));
-  if (!L.tasks.empty())
-    HIPCHK(hipMemcpyAsync(L.dtasks, L.tasks.data(), sizeof(Task) * L.tasks.size(), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(hipMemsetAsync(L.dacc, 0, sizeof(double) * 4 * std::max(1, L.nacc), c->stream));
-  HIPCHK(hipMemsetAsync(L.dledger, 0, sizeof(double) * 4 * std::max(1, L.nledger), c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  return VLBM_OK;
+  L.dtables = M.alloc(total);
+  if (!L.dtables) return fail(VLBM_ENOMEM, "level tables (%zu bytes)", total);
+  hipError_t e;
+  char *img = stage_reserve(c, total, e);
+  if (e != hipSuccess) return fail(VLBM_EDEVICE, "%s", hipGetErrorString(e));
+  std::vector<char> pageable;
+  if (!img) {
+    pageable.resize(total);
+    img = pageable.data();
+  }
+  for (size_t i = 0; i < sizeof parts / sizeof parts[0]; ++i) {
+    const Part &q = parts[i];
+    if (!q.dst) continue;
+    *q.dst = static_cast<char *>(L.dtables) + at[i];
+    if (q.nsrc) memcpy(img + at[i], q.src, q.nsrc);
+    if (q.n > q.nsrc) memset(img + at[i] + q.nsrc, 0, q.n - q.nsrc);
+  }
+  HIPCHK(hipMemcpyAsync(L.dtables, img, total, hipMemcpyHostToDevice, c->stream));
+  if (!pageable.empty()) HIPCHK(hipStreamSynchronize(c->stream));
+  return VLBM_OK;  // the caller's build_tables synchronises
 }
 
 // Phases of one coarse step in execution order: level l+1 takes r steps
@@ -1452,8 +1527,8 @@ vlbm_status build_tables(vlbm_ctx *c) {
   c->nseg_table = (int)NS;
   c->hseg = segs;
   c->hdesc = descs;
-  HIPCHK(hipMemcpyAsync(c->ddesc, descs.data(), sizeof(LevelDesc) * descs.size(), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(hipMemcpyAsync(c->dseg, segs.data(), sizeof(Segment) * segs.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(stage_h2d(c, c->ddesc, descs.data(), sizeof(LevelDesc) * descs.size()));
+  HIPCHK(stage_h2d(c, c->dseg, segs.data(), sizeof(Segment) * segs.size()));
   HIPCHK(hipStreamSynchronize(c->stream));
   c->table_base = c->coarse_steps;
   return VLBM_OK;
@@ -1834,13 +1909,71 @@ vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
       return fail(VLBM_EINVAL, "level %d frame too large for 32-bit offsets", l);
     }
   }
-  st = build_lists(t, boxes, nboxes);
+  st = build_coverage(t, boxes, nboxes);
   if (st) {
     delete t;
     return st;
   }
-  tm.mark("lists");
   const int r = c->p.r;
+  // The new levels' task lists depend on their coverage alone: they are built
+  // while another thread plans the merges and splits, and the device is
+  // touched only after both are done (a failure leaves the installed
+  // hierarchy as it was).
+  std::vector<std::vector<RegridOp>> merge_ops(kMaxLevels), split_ops(kMaxLevels);
+  auto plan = [&] {
+    // merges, finest level first, inside the old frames: a covered cell of level
+    // l >= 1 on the r-grid whose coverage the new hierarchy drops
+    for (int l = c->nlev - 1; l >= 1; --l) {
+      const Level &F = c->lv[l], &C = c->lv[l - 1];
+      std::vector<RegridOp> &ops = merge_ops[l];
+      for (int y = align_up(F.fy0 + 1, r); y < F.fy0 + F.fh - 1; y += r) {
+        if (!F.stored(y)) continue;
+        for (int x = align_up(F.fx0 + 1, r); x < F.fx0 + F.fw - 1; x += r) {
+          if (!F.cov[F.fidx(x, y)] || t->covered(l, x, y)) continue;
+          RegridOp op{};
+          op.dst = (int32_t)C.off(x / r, y / r);
+          op.src = (int32_t)F.off(x, y);
+          op.nb[0] = op.nb[1] = op.nb[2] = op.nb[3] = -1;
+          ops.push_back(op);
+        }
+      }
+    }
+    // splits, coarsest level first, inside the new frames: a newly covered cell
+    // of level l + 1 on the r-grid, from its parent and the parent's slope
+    // neighbours
+    for (int l = 0; l + 1 < nlev; ++l) {
+      const Level &Cn = t->lv[l], &Fn = t->lv[l + 1];
+      std::vector<RegridOp> &ops = split_ops[l];
+      for (int y = align_up(Fn.fy0 + 1, r); y < Fn.fy0 + Fn.fh - 1; y += r) {
+        if (!Fn.stored(y)) continue;
+        for (int x = align_up(Fn.fx0 + 1, r); x < Fn.fx0 + Fn.fw - 1; x += r) {
+          if (!Fn.cov[Fn.fidx(x, y)] || c->covered(l + 1, x, y)) continue;
+          const int px = x / r, py = y / r;
+          RegridOp op{};
+          op.src = (int32_t)Cn.off(px, py);
+          op.dst = (int32_t)Fn.off(x, y);
+          for (int d = 0; d < 4; ++d) {
+            int nx = px + CX[d], ny = py + CY[d];
+            op.nb[d] = -1;
+            if (!t->wrap(l, nx, ny)) continue;
+            const bool persistent_hole = c->covered(l + 1, nx * r, ny * r) && t->covered(l + 1, nx * r, ny * r);
+            if (t->covered(l, nx, ny) && !persistent_hole) op.nb[d] = (int32_t)Cn.off(nx, ny);
+          }
+          ops.push_back(op);
+        }
+      }
+    }
+  };
+  vlbm_status lst = run_parallel(2, [&](int i) -> vlbm_status {
+    if (i == 0) return build_task_lists(t);
+    plan();
+    return VLBM_OK;
+  });
+  if (lst) {
+    delete t;
+    return lst;
+  }
+  tm.mark("lists+plans");
   auto done = [&](vlbm_status s2) {
     delete t;
     return s2;
@@ -1854,24 +1987,13 @@ vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
     dops = static_cast<RegridOp *>(c->mem.alloc(sizeof(RegridOp) * std::max<size_t>(1, ops.size())));
     if (!dops) return fail(VLBM_ENOMEM, "regrid op list");
     if (!ops.empty())
-      HIPCHK(hipMemcpyAsync(dops, ops.data(), sizeof(RegridOp) * ops.size(), hipMemcpyHostToDevice, c->stream));
+      HIPCHK(stage_h2d(c, dops, ops.data(), sizeof(RegridOp) * ops.size()));
     return VLBM_OK;
   };
   // 1. merges, finest level first, inside the old frames
   for (int l = c->nlev - 1; l >= 1; --l) {
     Level &F = c->lv[l], &C = c->lv[l - 1];
-    std::vector<RegridOp> ops;
-    for (int y = align_up(F.fy0 + 1, r); y < F.fy0 + F.fh - 1; y += r) {
-      if (!F.stored(y)) continue;
-      for (int x = align_up(F.fx0 + 1, r); x < F.fx0 + F.fw - 1; x += r) {
-        if (!F.cov[F.fidx(x, y)] || t->covered(l, x, y)) continue;
-        RegridOp op{};
-        op.dst = (int32_t)C.off(x / r, y / r);
-        op.src = (int32_t)F.off(x, y);
-        op.nb[0] = op.nb[1] = op.nb[2] = op.nb[3] = -1;
-        ops.push_back(op);
-      }
-    }
+    const std::vector<RegridOp> &ops = merge_ops[l];
     if (ops.empty()) continue;
     st = upload_ops(ops);
     if (st) return done(st);
@@ -1933,25 +2055,7 @@ vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
   // 3. splits, coarsest level first, inside the new frames
   for (int l = 0; l + 1 < nlev; ++l) {
     Level &Cn = t->lv[l], &Fn = t->lv[l + 1];
-    std::vector<RegridOp> ops;
-    for (int y = align_up(Fn.fy0 + 1, r); y < Fn.fy0 + Fn.fh - 1; y += r) {
-      if (!Fn.stored(y)) continue;
-      for (int x = align_up(Fn.fx0 + 1, r); x < Fn.fx0 + Fn.fw - 1; x += r) {
-        if (!Fn.cov[Fn.fidx(x, y)] || c->covered(l + 1, x, y)) continue;
-        const int px = x / r, py = y / r;
-        RegridOp op{};
-        op.src = (int32_t)Cn.off(px, py);
-        op.dst = (int32_t)Fn.off(x, y);
-        for (int d = 0; d < 4; ++d) {
-          int nx = px + CX[d], ny = py + CY[d];
-          op.nb[d] = -1;
-          if (!t->wrap(l, nx, ny)) continue;
-          const bool persistent_hole = c->covered(l + 1, nx * r, ny * r) && t->covered(l + 1, nx * r, ny * r);
-          if (t->covered(l, nx, ny) && !persistent_hole) op.nb[d] = (int32_t)Cn.off(nx, ny);
-        }
-        ops.push_back(op);
-      }
-    }
+    const std::vector<RegridOp> &ops = split_ops[l];
     if (ops.empty()) continue;
     st = upload_ops(ops);
     if (st) return done(st);
@@ -1992,7 +2096,7 @@ vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
     int32_t *d = static_cast<int32_t *>(c->mem.alloc(sizeof(int32_t) * items.size()));
     if (!d) return done(fail(VLBM_ENOMEM, "regrid face list"));
     face_lists.push_back(d);
-    HIPCHK(hipMemcpyAsync(d, items.data(), sizeof(int32_t) * items.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(stage_h2d(c, d, items.data(), sizeof(int32_t) * items.size()));
     const int cur = (int)(N.steps & 1);
     HIPCHK(launch_restart_faces(N.buf[cur], N.buf[cur ^ 1], d, (int)(items.size() / 2), N.plane, c->fp32,
                                 c->stream));
@@ -2347,6 +2451,7 @@ void vlbm_destroy(vlbm_ctx *c) {
   for (auto &e : c->tag_scratch) c->mem.release(e.first);
   c->mem.release(c->dflux_qmax);
   c->mem.release_all();
+  if (c->stage) (void)hipHostFree(c->stage);
   delete c;
 }
 
@@ -2734,8 +2839,7 @@ vlbm_status vlbm_tag_and_regrid(vlbm_ctx *c, double thr, int buffer, int min_box
       return fail(VLBM_ENOMEM, "tile lists");
     }
     if (!trows[l].empty())
-      e = hipMemcpyAsync(dtrows, trows[l].data(), sizeof(int32_t) * trows[l].size(), hipMemcpyHostToDevice,
-                         c->stream);
+      e = stage_h2d(c, dtrows, trows[l].data(), sizeof(int32_t) * trows[l].size());
     if (e == hipSuccess)
       e = launch_tile_hits(dtag[l], L.dsrow, L.fx0, L.fy0, L.fw, L.fh, L.nrows, L.Nx, L.Ny, c->perx(), c->pery(),
                            T, buffer, ntx, dtrows, (int)trows[l].size(), dmasks, dlist[l], cap[l], dcount + l,

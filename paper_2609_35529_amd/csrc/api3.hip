@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "../../include/vlbm3.h"
+#include "host_pool.hpp"
 #include "vlbm3_internal.hpp"
 
 namespace vlbm {
@@ -143,16 +144,13 @@ void dfree(Alloc3 &m, T *&p) {
   p = nullptr;
 }
 
-// f(lo, hi) over contiguous ranges of [0, n) on up to 16 threads (the calling
-// thread takes the first range); ranges hold at least `grain` items.
+// f(lo, hi) over up to 16 contiguous ranges of [0, n), on the process's
+// worker pool and the calling thread; ranges hold at least `grain` items.
 template <class F>
 void par_ranges(size_t n, size_t grain, const F &f) {
   const size_t hw = std::max(1u, std::thread::hardware_concurrency());
   const int nw = (int)std::max<size_t>(1, std::min<size_t>({16, hw, (n + grain - 1) / std::max<size_t>(1, grain)}));
-  std::vector<std::thread> th;
-  for (int w = 1; w < nw; ++w) th.emplace_back([&, w] { f(n * w / nw, n * (w + 1) / nw); });
-  f(0, n / nw);
-  for (std::thread &t : th) t.join();
+  vlbm_host::Pool::get().run(nw, [&](int w) { f(n * w / nw, n * (w + 1) / nw); });
 }
 
 }  // namespace
@@ -401,11 +399,9 @@ void build_tiles3(vlbm3_ctx *c, int l, std::vector<int32_t> &owner) {
     part.resize(nw);
     zr.resize(nw + 1);
     for (int w = 0; w <= nw; ++w) zr[w] = (size_t)nz * w / nw;
-    std::vector<std::thread> th;
-    auto slabs = [&](int w) { build_tile_slabs3(c, l, L.f0[2] + 1 + (int)zr[w], L.f0[2] + 1 + (int)zr[w + 1], tc, part[w], owner); };
-    for (int w = 1; w < nw; ++w) th.emplace_back(slabs, w);
-    slabs(0);
-    for (std::thread &t : th) t.join();
+    vlbm_host::Pool::get().run(nw, [&](int w) {
+      build_tile_slabs3(c, l, L.f0[2] + 1 + (int)zr[w], L.f0[2] + 1 + (int)zr[w + 1], tc, part[w], owner);
+    });
   }
   std::vector<size_t> base(part.size(), 0);
   for (size_t w = 0; w < part.size(); ++w) {
@@ -551,10 +547,7 @@ vlbm_status build_lists3(vlbm3_ctx *c) {
           }
         }
       };
-      std::vector<std::thread> th;
-      for (int w = 1; w < nw; ++w) th.emplace_back(work, w);
-      work(0);
-      for (std::thread &t : th) t.join();
+      vlbm_host::Pool::get().run(nw, work);
       for (int w = 0; w < nw; ++w)
         if (wst[w]) return fail3(wst[w], "%s", wmsg[w].c_str());
     }
