@@ -951,9 +951,10 @@ vlbm_status build_task_lists(vlbm_ctx *c) {
       int x = 0;
       constexpr uint64_t ones = 0x0101010101010101ull;
       while (x < L.fw) {
-        if (row[x] != 1) {
-          ++x;
-          continue;
+        if (row[x] != 1) {  // to the next active cell
+          const void *nx = memchr(row + x, 1, L.fw - x);
+          if (!nx) break;
+          x = (int)(static_cast<const uint8_t *>(nx) - row);
         }
         const int xa = x;
         for (uint64_t v; x + 8 <= L.fw && (memcpy(&v, row + x, 8), v == ones);) x += 8;
@@ -1002,7 +1003,8 @@ vlbm_status build_task_lists(vlbm_ctx *c) {
     // cell -> tile map over the frame; only active cells are ever looked up
     w.owner.reset(new int32_t[L.cov.size()]);
     const int nt = (int)L.tiles.size();
-    const int TB = std::max(1, std::min(8, nt / 256));
+    // (inner phases split work only where a share outweighs a dispatch to the pool)
+    const int TB = std::max(1, std::min(8, nt / 1024));
     vlbm_status st = run_parallel(TB, [&](int b) -> vlbm_status {
       for (int t = (int)((int64_t)nt * b / TB); t < (int)((int64_t)nt * (b + 1) / TB); ++t)
         for (int yy = 0; yy < L.tiles[t].h; ++yy) {
@@ -1021,19 +1023,37 @@ vlbm_status build_task_lists(vlbm_ctx *c) {
     w.fuse = (c->step_flags & STEP_FUSE2) && l >= 1 && l == nlev - 1 && r == 2;
     const int fw = L.fw, ya = L.fy0 + 1, yb = L.fy0 + L.fh - 1;
     // 1. active cells with a non-active upwind neighbour, per band of rows
-    const int B = std::max(1, std::min(8, (yb - ya) / 16));
+    const int B = std::max(1, std::min({8, (yb - ya) / 16, (int)(L.cov.size() >> 18)}));
     std::vector<std::vector<int32_t>> edge(B);  // frame indices, row order
     st = run_parallel(B, [&](int b) -> vlbm_status {
+      constexpr uint64_t ones = 0x0101010101010101ull;
+      auto all8 = [&](const uint8_t *p) {
+        uint64_t v;
+        memcpy(&v, p, 8);
+        return v == ones;
+      };
       for (int y = ya + (int)((int64_t)(yb - ya) * b / B); y < ya + (int)((int64_t)(yb - ya) * (b + 1) / B); ++y) {
         if (!L.stored(y)) continue;
         const size_t r0 = L.fidx(L.fx0, y);
         const uint8_t *sr = &L.status[r0];
-        for (int xi = 1; xi < fw - 1; ++xi) {
-          if (sr[xi] != 1) continue;
+        for (int xi = 1; xi < fw - 1;) {
+          if (sr[xi] != 1) {  // to the next active cell
+            const void *nx = memchr(sr + xi, 1, fw - 1 - xi);
+            if (!nx) break;
+            xi = (int)(static_cast<const uint8_t *>(nx) - sr);
+          }
+          // (the rows of an active cell's neighbours are stored next to its row)
+          // eight interior cells at once: cells xi - 1 .. xi + 8 of the row and
+          // xi .. xi + 7 of the rows below and above active
+          if (xi + 8 < fw && all8(sr + xi - 1) && all8(sr + xi + 1) && all8(sr + xi - fw) && all8(sr + xi + fw)) {
+            xi += 8;
+            continue;
+          }
           // interior cell: all four upwind neighbours active at this level (hence
           // inside the domain) -> plain pulls, no task
-          if (sr[xi - 1] == 1 && sr[xi + 1] == 1 && sr[xi - fw] == 1 && sr[xi + fw] == 1) continue;
-          edge[b].push_back((int32_t)(r0 + xi));
+          if (!(sr[xi - 1] == 1 && sr[xi + 1] == 1 && sr[xi - fw] == 1 && sr[xi + fw] == 1))
+            edge[b].push_back((int32_t)(r0 + xi));
+          ++xi;
         }
       }
       return VLBM_OK;
@@ -1041,8 +1061,9 @@ vlbm_status build_task_lists(vlbm_ctx *c) {
     if (st) return st;
     std::vector<int32_t> cells;
     for (auto &e : edge) cells.insert(cells.end(), e.begin(), e.end());
+    lt.mark("edges");
     // 2. their ghost tasks, in equal shares of the cell list
-    const int E = std::max(1, std::min(8, (int)(cells.size() / 1024)));
+    const int E = std::max(1, std::min(8, (int)(cells.size() / 4096)));
     struct Band {
       std::vector<std::pair<int, Task>> tk;
       std::vector<int64_t> key;  // (cell, q) of each task
@@ -1055,6 +1076,9 @@ vlbm_status build_task_lists(vlbm_ctx *c) {
         const int x = L.fx0 + cells[i] % fw, y = L.fy0 + L.yrow[cells[i] / fw];
         const int tile = w.owner[cells[i]];
         for (int q = 0; q < 4; ++q) {
+          // an active upwind cell of this level is read in place (no task);
+          // the rows next to an active cell are stored next to its row
+          if (L.status[cells[i] - CX[q] - (int64_t)CY[q] * fw] == 1) continue;
           Task t{};
           vlbm_status gs = ghost_task(c, l, x, y, q, t);
           if (gs) return gs;
