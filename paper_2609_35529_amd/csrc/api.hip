@@ -30,7 +30,7 @@
 #include <vector>
 
 #include "../../include/vlbm.h"
-#include "host_pool.hpp"
+#include "host_util.hpp"
 #include "vlbm_internal.hpp"
 
 using namespace vlbm;
@@ -58,20 +58,7 @@ vlbm_status fail(vlbm_status st, const char *fmt, ...) {
 
 constexpr int kMaxLevels = VLBM_MAX_LEVELS;
 
-// VLBM_TIMING=1 prints host-side phase timings of hierarchy changes to stderr.
-struct PhaseTimer {
-  bool on;
-  std::chrono::steady_clock::time_point t;
-  const char *what;
-  explicit PhaseTimer(const char *w) : on(getenv("VLBM_TIMING") != nullptr), t(std::chrono::steady_clock::now()), what(w) {}
-  void mark(const char *phase) {
-    if (!on) return;
-    auto now = std::chrono::steady_clock::now();
-    fprintf(stderr, "[vlbm] %s %s %.3f ms\n", what, phase,
-            std::chrono::duration<double, std::milli>(now - t).count());
-    t = now;
-  }
-};
+using vlbm_host::PhaseTimer;
 const int CX[4] = {1, -1, 0, 0};
 const int CY[4] = {0, 0, 1, -1};
 
@@ -569,15 +556,23 @@ vlbm_status ghost_task(const vlbm_ctx *c, int l, int x, int y, int q, Task &t) {
   t.q = q;
   t.dst = (int32_t)L.off(sx, sy);
   t.n0 = t.n1 = -1;
+  // A level's status holds its coverage and that of the next finer level
+  // (proper nesting): 1 active, 2 under a finer box (covered at l + 1), 0 not
+  // covered; cells outside the frame are not covered.
+  auto status = [&](int lv, int ax, int ay) -> int {
+    const Level &A = c->lv[lv];
+    return A.in_frame(ax, ay) ? A.status[A.fidx(ax, ay)] : 0;
+  };
+  int s;
   if (!c->wrap(l, wx, wy)) {
     const int side = q;  // +x enters through west (0), -x east (1), +y south (2), -y north (3)
     const int bc = p.bc[side];
     t.kind = (bc == VLBM_BC_OUTFLOW ? T_OUTFLOW : bc == VLBM_BC_REFLECT ? T_REFLECT : T_INFLOW) | TASK_LEDGER;
     t.src = (int32_t)L.off(x, y);
     t.n0 = side;
-  } else if (c->covered(l + 1, wx * r, wy * r)) {
+  } else if ((s = status(l, wx, wy)) == 2) {
     t.kind = T_REFLUX;
-  } else if (c->covered(l, wx, wy)) {
+  } else if (s == 1) {
     if (wx != sx || wy != sy) {
       t.kind = T_COPY;
       t.src = (int32_t)L.off(wx, wy);
@@ -586,15 +581,15 @@ vlbm_status ghost_task(const vlbm_ctx *c, int l, int x, int y, int q, Task &t) {
     if (l == 0) return fail(VLBM_ENEST, "internal: level-0 cell without source");
     const Level &PL = c->lv[l - 1];
     int px = wx / r, py = wy / r;
-    if (!c->active(l - 1, px, py))
+    if (status(l - 1, px, py) != 1)
       return fail(VLBM_ENEST, "level %d cell (%d,%d): parent ring cell inactive", l, x, y);
     t.kind = T_RECON;
     t.src = (int32_t)PL.off(px, py);
     int tx = q < 2 ? 0 : 1, ty = q < 2 ? 1 : 0;
     t.j = q < 2 ? (y - r * py) : (x - r * px);
     int mx = px - tx, my = py - ty, qx = px + tx, qy = py + ty;
-    bool have = c->wrap(l - 1, mx, my) && c->wrap(l - 1, qx, qy) && c->active(l - 1, mx, my) &&
-                c->active(l - 1, qx, qy);
+    bool have = c->wrap(l - 1, mx, my) && c->wrap(l - 1, qx, qy) && status(l - 1, mx, my) == 1 &&
+                status(l - 1, qx, qy) == 1;
     if (have) {
       t.n0 = (int32_t)PL.off(mx, my);
       t.n1 = (int32_t)PL.off(qx, qy);
@@ -901,7 +896,19 @@ vlbm_status build_task_lists(vlbm_ctx *c) {
   // Pass A: tiles, cell -> tile map, ghost tasks, reflux and ledger slots.
   // Pass B (needs the parent's reflux slots): captures, task order, fused lists.
   struct Work {
-    std::unique_ptr<int32_t[]> owner;           // frame cell -> tile (active cells only)
+    // cell -> tile: per stored row, the tiles crossing it as frame-column
+    // ranges [x0, x1), ordered by x0 (rows row0[s] .. row0[s + 1] of own)
+    struct Own {
+      int32_t x0, x1, tile;
+    };
+    std::vector<int32_t> row0;
+    std::vector<Own> own;
+    int32_t owner(const Level &L, int64_t fi) const {  // fi: frame index of an active cell
+      const int s = (int)(fi / L.fw), fx = (int)(fi % L.fw);
+      const Own *b = own.data() + row0[s], *e = own.data() + row0[s + 1];
+      const Own *it = std::upper_bound(b, e, fx, [](int v, const Own &o) { return v < o.x0; });
+      return (it != b && fx < (it - 1)->x1) ? (it - 1)->tile : -1;
+    }
     std::vector<std::pair<int, Task>> tk;       // (tile, task)
     std::unordered_map<int64_t, int> bc_slot;   // (cell, q) -> ledger slot (fused level)
     std::vector<std::pair<int64_t, Task>> caps; // (cell R_0 as y * Nx + x, capture) (fused level)
@@ -1000,20 +1007,25 @@ vlbm_status build_task_lists(vlbm_ctx *c) {
     L.tiles.swap(sorted);
     rect_xy.swap(sxy);
     lt.mark("tiles");
-    // cell -> tile map over the frame; only active cells are ever looked up
-    w.owner.reset(new int32_t[L.cov.size()]);
-    const int nt = (int)L.tiles.size();
-    // (inner phases split work only where a share outweighs a dispatch to the pool)
-    const int TB = std::max(1, std::min(8, nt / 1024));
-    vlbm_status st = run_parallel(TB, [&](int b) -> vlbm_status {
-      for (int t = (int)((int64_t)nt * b / TB); t < (int)((int64_t)nt * (b + 1) / TB); ++t)
-        for (int yy = 0; yy < L.tiles[t].h; ++yy) {
-          int32_t *o = &w.owner[L.fidx(rect_xy[t].first, rect_xy[t].second + yy)];
-          std::fill(o, o + L.tiles[t].w, (int32_t)t);
-        }
-      return VLBM_OK;
-    });
-    if (st) return st;
+    // cell -> tile: the tiles crossing each stored row
+    {
+      const int nt = (int)L.tiles.size();
+      w.row0.assign((size_t)L.nrows + 1, 0);
+      for (int t = 0; t < nt; ++t)
+        for (int yy = 0; yy < L.tiles[t].h; ++yy) w.row0[L.srow[rect_xy[t].second + yy - L.fy0] + 1] += 1;
+      for (int s2 = 0; s2 < L.nrows; ++s2) w.row0[s2 + 1] += w.row0[s2];
+      w.own.resize(w.row0[L.nrows]);
+      std::vector<int32_t> at(w.row0.begin(), w.row0.end() - 1);
+      for (int t = 0; t < nt; ++t) {
+        const int x0 = rect_xy[t].first - L.fx0;
+        for (int yy = 0; yy < L.tiles[t].h; ++yy)
+          w.own[at[L.srow[rect_xy[t].second + yy - L.fy0]]++] = {x0, x0 + L.tiles[t].w, t};
+      }
+      for (int s2 = 0; s2 < L.nrows; ++s2)
+        std::sort(w.own.begin() + w.row0[s2], w.own.begin() + w.row0[s2 + 1],
+                  [](const Work::Own &a, const Work::Own &b) { return a.x0 < b.x0; });
+    }
+    vlbm_status st = VLBM_OK;
     lt.mark("owner");
     // ghost tasks, found per band of rows in parallel, then numbered in row order
     L.reflux_key.clear();
@@ -1063,7 +1075,7 @@ vlbm_status build_task_lists(vlbm_ctx *c) {
     for (auto &e : edge) cells.insert(cells.end(), e.begin(), e.end());
     lt.mark("edges");
     // 2. their ghost tasks, in equal shares of the cell list
-    const int E = std::max(1, std::min(8, (int)(cells.size() / 4096)));
+    const int E = std::max(1, std::min(8, (int)(cells.size() / 512)));
     struct Band {
       std::vector<std::pair<int, Task>> tk;
       std::vector<int64_t> key;  // (cell, q) of each task
@@ -1074,7 +1086,7 @@ vlbm_status build_task_lists(vlbm_ctx *c) {
       const size_t i0 = cells.size() * b / E, i1 = cells.size() * (b + 1) / E;
       for (size_t i = i0; i < i1; ++i) {
         const int x = L.fx0 + cells[i] % fw, y = L.fy0 + L.yrow[cells[i] / fw];
-        const int tile = w.owner[cells[i]];
+        const int tile = w.owner(L, cells[i]);
         for (int q = 0; q < 4; ++q) {
           // an active upwind cell of this level is read in place (no task);
           // the rows next to an active cell are stored next to its row
@@ -1154,7 +1166,7 @@ vlbm_status build_task_lists(vlbm_ctx *c) {
         t.n1 = -1;
         t.j = r - 1;  // captured cells beyond the first (the device reads r)
         t.slot = cd.slot;
-        tk.push_back({w.owner[L.fidx(cd.x, cd.y)], t});
+        tk.push_back({w.owner(L, L.fidx(cd.x, cd.y)), t});
         if (w.fuse) w.caps.push_back({(int64_t)cd.y * L.Nx + cd.x, t});
       }
     }
@@ -1940,59 +1952,90 @@ vlbm_status regrid_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
   }
   const int r = c->p.r;
   // The new levels' task lists depend on their coverage alone: they are built
-  // while another thread plans the merges and splits, and the device is
-  // touched only after both are done (a failure leaves the installed
-  // hierarchy as it was).
-  std::vector<std::vector<RegridOp>> merge_ops(kMaxLevels), split_ops(kMaxLevels);
-  auto plan = [&] {
-    // merges, finest level first, inside the old frames: a covered cell of level
-    // l >= 1 on the r-grid whose coverage the new hierarchy drops
-    for (int l = c->nlev - 1; l >= 1; --l) {
+  // while other threads plan the merges and splits (per level and kind, in
+  // bands of the r-aligned rows of the frame the ops live in; a level's ops
+  // in row order), and the device is touched only after both are done (a
+  // failure leaves the installed hierarchy as it was).
+  struct PlanItem {
+    bool split;
+    int l, y0, y1;  // rows [y0, y1), y0 r-aligned
+    std::vector<RegridOp> ops;
+  };
+  std::vector<PlanItem> items;
+  auto bands = [&](bool split, int l, const Level &L) {
+    const int ya = align_up(L.fy0 + 1, r), yb = L.fy0 + L.fh - 1;
+    if (ya >= yb) return;
+    const int k = (yb - ya + r - 1) / r;  // r-aligned rows
+    const int nb = std::max(1, std::min(8, (int)(((int64_t)k * L.fw) >> 15)));
+    for (int i = 0; i < nb; ++i)
+      items.push_back({split, l, ya + (int)((int64_t)k * i / nb) * r, std::min(yb, ya + (int)((int64_t)k * (i + 1) / nb) * r), {}});
+  };
+  for (int l = c->nlev - 1; l >= 1; --l) bands(false, l, c->lv[l]);
+  for (int l = 0; l + 1 < nlev; ++l) bands(true, l, t->lv[l + 1]);
+  // coverage row y of level l of context x (null: none stored), indexed by
+  // x - fx0 over [fx0, fx0 + fw)
+  auto cov_row = [](const vlbm_ctx *x, int l, int y) -> const uint8_t * {
+    if (l >= kMaxLevels || !x->lv[l].present || !x->lv[l].stored(y)) return nullptr;
+    const Level &L = x->lv[l];
+    return &L.cov[L.fidx(L.fx0, y)];
+  };
+  auto in_row = [](const vlbm_ctx *x, int l, const uint8_t *row, int xx) {
+    const Level &L = x->lv[l];
+    return row && xx >= L.fx0 && xx < L.fx0 + L.fw && row[xx - L.fx0];
+  };
+  auto plan = [&](PlanItem &it) {
+    const int l = it.l;
+    if (!it.split) {
+      // merges, inside the old frames: a covered cell of level l >= 1 on the
+      // r-grid whose coverage the new hierarchy drops
       const Level &F = c->lv[l], &C = c->lv[l - 1];
-      std::vector<RegridOp> &ops = merge_ops[l];
-      for (int y = align_up(F.fy0 + 1, r); y < F.fy0 + F.fh - 1; y += r) {
-        if (!F.stored(y)) continue;
+      for (int y = it.y0; y < it.y1; y += r) {
+        const uint8_t *fo = cov_row(c, l, y), *fn = cov_row(t, l, y);
+        if (!fo) continue;
         for (int x = align_up(F.fx0 + 1, r); x < F.fx0 + F.fw - 1; x += r) {
-          if (!F.cov[F.fidx(x, y)] || t->covered(l, x, y)) continue;
+          if (!fo[x - F.fx0] || in_row(t, l, fn, x)) continue;
           RegridOp op{};
           op.dst = (int32_t)C.off(x / r, y / r);
           op.src = (int32_t)F.off(x, y);
           op.nb[0] = op.nb[1] = op.nb[2] = op.nb[3] = -1;
-          ops.push_back(op);
+          it.ops.push_back(op);
         }
       }
+      return;
     }
-    // splits, coarsest level first, inside the new frames: a newly covered cell
-    // of level l + 1 on the r-grid, from its parent and the parent's slope
-    // neighbours
-    for (int l = 0; l + 1 < nlev; ++l) {
-      const Level &Cn = t->lv[l], &Fn = t->lv[l + 1];
-      std::vector<RegridOp> &ops = split_ops[l];
-      for (int y = align_up(Fn.fy0 + 1, r); y < Fn.fy0 + Fn.fh - 1; y += r) {
-        if (!Fn.stored(y)) continue;
-        for (int x = align_up(Fn.fx0 + 1, r); x < Fn.fx0 + Fn.fw - 1; x += r) {
-          if (!Fn.cov[Fn.fidx(x, y)] || c->covered(l + 1, x, y)) continue;
-          const int px = x / r, py = y / r;
-          RegridOp op{};
-          op.src = (int32_t)Cn.off(px, py);
-          op.dst = (int32_t)Fn.off(x, y);
-          for (int d = 0; d < 4; ++d) {
-            int nx = px + CX[d], ny = py + CY[d];
-            op.nb[d] = -1;
-            if (!t->wrap(l, nx, ny)) continue;
-            const bool persistent_hole = c->covered(l + 1, nx * r, ny * r) && t->covered(l + 1, nx * r, ny * r);
-            if (t->covered(l, nx, ny) && !persistent_hole) op.nb[d] = (int32_t)Cn.off(nx, ny);
-          }
-          ops.push_back(op);
+    // splits, inside the new frames: a newly covered cell of level l + 1 on
+    // the r-grid, from its parent and the parent's slope neighbours
+    const Level &Cn = t->lv[l], &Fn = t->lv[l + 1];
+    for (int y = it.y0; y < it.y1; y += r) {
+      const uint8_t *fn = cov_row(t, l + 1, y), *fo = cov_row(c, l + 1, y);
+      if (!fn) continue;
+      for (int x = align_up(Fn.fx0 + 1, r); x < Fn.fx0 + Fn.fw - 1; x += r) {
+        if (!fn[x - Fn.fx0] || in_row(c, l + 1, fo, x)) continue;
+        const int px = x / r, py = y / r;
+        RegridOp op{};
+        op.src = (int32_t)Cn.off(px, py);
+        op.dst = (int32_t)Fn.off(x, y);
+        for (int d = 0; d < 4; ++d) {
+          int nx = px + CX[d], ny = py + CY[d];
+          op.nb[d] = -1;
+          if (!t->wrap(l, nx, ny)) continue;
+          const bool persistent_hole = c->covered(l + 1, nx * r, ny * r) && t->covered(l + 1, nx * r, ny * r);
+          if (t->covered(l, nx, ny) && !persistent_hole) op.nb[d] = (int32_t)Cn.off(nx, ny);
         }
+        it.ops.push_back(op);
       }
     }
   };
-  vlbm_status lst = run_parallel(2, [&](int i) -> vlbm_status {
+  vlbm_status lst = run_parallel(1 + (int)items.size(), [&](int i) -> vlbm_status {
     if (i == 0) return build_task_lists(t);
-    plan();
+    plan(items[i - 1]);
     return VLBM_OK;
   });
+  std::vector<std::vector<RegridOp>> merge_ops(kMaxLevels), split_ops(kMaxLevels);
+  for (PlanItem &it : items) {
+    std::vector<RegridOp> &v = it.split ? split_ops[it.l] : merge_ops[it.l];
+    v.insert(v.end(), it.ops.begin(), it.ops.end());
+  }
   if (lst) {
     delete t;
     return lst;
@@ -2294,17 +2337,19 @@ void cluster_level(vlbm_ctx *c, int l, const std::vector<int32_t> &hits, const C
   };
   // one tile row: its runs of kept tiles; then the open rectangles continue
   // (identical run below, room to grow) or are emitted
+  // (the runs of a row are disjoint and both lists are ordered by a, so the
+  // run of the new row that starts where an open rectangle does is found by
+  // one merged pass)
   auto close_row = [&](int ty) {
+    size_t j = 0;
     for (auto &o : open) {
-      bool cont = false;
-      for (auto &nx2 : next)
-        if (nx2.a == o.a && nx2.b == o.b && nx2.h == 1 && o.h < maxT) {
-          nx2.y0 = o.y0;
-          nx2.h = o.h + 1;
-          cont = true;
-          break;
-        }
-      if (!cont) emit(o);
+      while (j < next.size() && next[j].a < o.a) ++j;
+      if (j < next.size() && next[j].a == o.a && next[j].b == o.b && next[j].h == 1 && o.h < maxT) {
+        next[j].y0 = o.y0;
+        next[j].h = o.h + 1;
+      } else {
+        emit(o);
+      }
     }
     open.swap(next);
     next.clear();
@@ -2915,6 +2960,8 @@ vlbm_status vlbm_tag_and_regrid(vlbm_ctx *c, double thr, int buffer, int min_box
       hits[l].resize(n);
     }
     cluster_level(c, l, hits[l], cov, min_box, max_box, boxes);
+    static const char *const kClu[] = {"cluster l0", "cluster l1", "cluster l2", "cluster l3+"};
+    tm.mark(kClu[std::min(l, 3)]);
     if (boxes.size() == before || l + 2 >= ML) break;
     cov = CovMap::of_boxes(boxes.data() + before, boxes.size() - before);
   }

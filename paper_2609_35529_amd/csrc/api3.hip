@@ -25,7 +25,7 @@
 #include <vector>
 
 #include "../../include/vlbm3.h"
-#include "host_pool.hpp"
+#include "host_util.hpp"
 #include "vlbm3_internal.hpp"
 
 namespace vlbm {
@@ -33,6 +33,7 @@ void set_error_message(const char *msg);
 }
 
 using namespace vlbm3;
+using vlbm_host::PhaseTimer;
 
 namespace {
 
@@ -1312,10 +1313,12 @@ vlbm_status vlbm3_set_hierarchy(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes
 
 vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
   if (!c || !c->have_hierarchy) return fail3(VLBM_ESTATE, "no hierarchy installed");
+  PhaseTimer tm("regrid3");
   Level3 nl[kL];
   int nnlev = 1;
   vlbm_status st = build_geometry3(c->p, boxes, nboxes, nl, nnlev);
   if (st) return st;
+  tm.mark("geometry");
   const int r = c->p.r, onlev = c->nlev;
   // the boundary ledger survives the rebuild of its slots
   double tot[5], led[5] = {};
@@ -1363,6 +1366,7 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
     a.nops = (int32_t)ops.size();
     HIPCHK3(launch_merge3(a, c->fp32, c->stream));
   }
+  tm.mark("merges");
   // 2. new frames: surviving cells move over (both time levels); a level
   //    whose frame is unchanged keeps its buffers
   for (int l = 0; l < nnlev; ++l) {
@@ -1414,6 +1418,7 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
     HIPCHK3(launch_copy3_runs(O->buf[0], O->buf[1], N.buf[0], N.buf[1], druns, (int)(runs.size() / 3), O->plane,
                               N.plane, c->fp32, c->stream));
   }
+  tm.mark("frames");
   // 3. splits, coarsest level first, in the new frames (eqs. amr-slope,
   //    amr-split); a slope neighbour is covered at that level in the new
   //    hierarchy and holds data (not a hole before and after)
@@ -1459,6 +1464,7 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
   HIPCHK3(hipStreamSynchronize(c->stream));
   for (void *p : scratch) c->mem.release(p);
   scratch.clear();
+  tm.mark("splits+sync");
   // 4. install the new hierarchy and rebuild its lists
   std::vector<int64_t> old_faces[kL];
   for (int l = 0; l < onlev; ++l) old_faces[l].swap(c->lv[l].face_key);
@@ -1467,6 +1473,7 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
   c->nlev = nnlev;
   st = build_lists3(c);
   if (st) return st;
+  tm.mark("lists");
   // 5. an interface that exists before and after keeps its reconstruction
   //    unmodified (Sec. 3.4); a face the regrid creates starts flat: the
   //    population its ring cell hands into the new hole gets the current
@@ -1504,7 +1511,9 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
       break;
     }
   c->boxes.assign(boxes, boxes + nboxes);
-  return build_tables3(c);
+  st = build_tables3(c);
+  tm.mark("faces+upload");
+  return st;
 }
 
 vlbm_status vlbm3_set_state(vlbm3_ctx *c, int level, int i0, int j0, int k0, int nx, int ny, int nz,
@@ -1657,14 +1666,17 @@ vlbm_status vlbm3_tag_and_regrid(vlbm3_ctx *c, double threshold, int buffer, int
   if (buffer < 0 || min_box < 1 || max_box < min_box) return fail3(VLBM_EINVAL, "bad clustering sizes");
   const int ML = c->p.max_levels;
   if (ML < 2) return VLBM_OK;
+  PhaseTimer tm("tag_and_regrid3");
   std::vector<TagMap3> tags(ML);
   for (int l = 0; l < c->nlev; ++l) {
     if (!c->lv[l].present) continue;
     vlbm_status st = tag_frame3(c, l, threshold, tags[l]);
     if (st) return st;
   }
+  tm.mark("tags");
   std::vector<vlbm3_box> boxes;
   cluster_hierarchy3(c, tags, buffer, min_box, max_box, boxes);
+  tm.mark("cluster");
   return vlbm3_regrid(c, boxes.data(), (int)boxes.size());
 }
 

@@ -1,13 +1,16 @@
-// Worker threads kept for the life of the process, shared by every context:
-// hierarchy changes run many short parallel sections (per level, per band of
-// rows), and creating threads for each costs more than the work on a virtual
-// machine.
+// Host-side utilities of the 2-D and 3-D libraries: a worker pool kept for the
+// life of the process, shared by every context (hierarchy changes run many
+// short parallel sections, per level and per band of rows, and creating
+// threads for each costs more than the work on a virtual machine), and a
+// phase timer for hierarchy changes.
 #pragma once
 
 #include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
 #include <deque>
 #include <functional>
 #include <mutex>
@@ -109,6 +112,21 @@ class Pool {
   std::condition_variable cv_;
   std::deque<Batch *> q_;
   std::atomic<int> queued_{0};
+};
+
+// VLBM_TIMING=1 prints host-side phase timings of hierarchy changes to stderr.
+struct PhaseTimer {
+  bool on;
+  std::chrono::steady_clock::time_point t;
+  const char *what;
+  explicit PhaseTimer(const char *w)
+      : on(getenv("VLBM_TIMING") != nullptr), t(std::chrono::steady_clock::now()), what(w) {}
+  void mark(const char *phase) {
+    if (!on) return;
+    auto now = std::chrono::steady_clock::now();
+    fprintf(stderr, "[vlbm] %s %s %.3f ms\n", what, phase, std::chrono::duration<double, std::milli>(now - t).count());
+    t = now;
+  }
 };
 
 }  // namespace vlbm_host
