@@ -154,6 +154,24 @@ void par_ranges(size_t n, size_t grain, const F &f) {
   vlbm_host::Pool::get().run(nw, [&](int w) { f(n * w / nw, n * (w + 1) / nw); });
 }
 
+// Items of f(i, out) for i in [0, n), each appending to `out`, computed on
+// the worker pool in contiguous ranges and concatenated in order of i.
+template <class T, class F>
+std::vector<T> par_collect(size_t n, const F &f) {
+  const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+  const int nw = (int)std::max<size_t>(1, std::min<size_t>({16, hw, n}));
+  std::vector<std::vector<T>> part(nw);
+  vlbm_host::Pool::get().run(nw, [&](int w) {
+    for (size_t i = n * w / nw; i < n * (w + 1) / nw; ++i) f(i, part[w]);
+  });
+  std::vector<T> out;
+  size_t total = 0;
+  for (const auto &v : part) total += v.size();
+  out.reserve(total);
+  for (const auto &v : part) out.insert(out.end(), v.begin(), v.end());
+  return out;
+}
+
 }  // namespace
 
 struct vlbm3_ctx {
@@ -378,95 +396,119 @@ vlbm_status ghost_task3(const vlbm3_ctx *c, int l, const int x[3], int q, Task3 
   return VLBM_OK;
 }
 
-// Tiles of level l: per z-slab, runs of active cells along x (cut at
-// tile_cells), equal runs on consecutive rows stacked while the tile holds at
-// most tile_cells cells.
-void build_tile_slabs3(vlbm3_ctx *c, int l, int za, int zb, int tc, std::vector<Tile3> &tiles,
-                       std::vector<int32_t> &owner);
+// Cell -> tile of one level: per frame row (z, y), the tiles crossing it as
+// frame-column ranges [x0, x1), ordered by x0.
+struct TileRows3 {
+  struct Ent {
+    int32_t x0, x1, tile;
+  };
+  std::vector<int32_t> row0;  // row i holds ent[row0[i] .. row0[i + 1])
+  std::vector<Ent> ent;
+  int32_t tile_of(const Level3 &L, const int p[3]) const {  // p: an active cell
+    const size_t row = (size_t)(p[2] - L.f0[2]) * L.fn[1] + (p[1] - L.f0[1]);
+    const int fx = p[0] - L.f0[0];
+    const Ent *b = ent.data() + row0[row], *e = ent.data() + row0[row + 1];
+    const Ent *it = std::upper_bound(b, e, fx, [](int v, const Ent &o) { return v < o.x0; });
+    return (it != b && fx < (it - 1)->x1) ? (it - 1)->tile : -1;
+  }
+};
 
-void build_tiles3(vlbm3_ctx *c, int l, std::vector<int32_t> &owner) {
-  Level3 &L = c->lv[l];
-  L.tiles.clear();
-  owner.assign(L.status.size(), -1);
-  const int tc = c->tile_cells;
-  // z-slabs are independent: ranges of them on worker threads, each with its
-  // own tile list (owner holds local indices), then concatenated in z order
-  const int nz = std::max(0, L.fn[2] - 2);
-  std::vector<std::vector<Tile3>> part;
-  std::vector<size_t> zr;  // range boundaries, in slabs
-  {
-    const size_t hw = std::max(1u, std::thread::hardware_concurrency());
-    const int nw = (int)std::max<size_t>(1, std::min<size_t>({16, hw, (size_t)std::max(nz, 1)}));
-    part.resize(nw);
-    zr.resize(nw + 1);
-    for (int w = 0; w <= nw; ++w) zr[w] = (size_t)nz * w / nw;
-    vlbm_host::Pool::get().run(nw, [&](int w) {
-      build_tile_slabs3(c, l, L.f0[2] + 1 + (int)zr[w], L.f0[2] + 1 + (int)zr[w + 1], tc, part[w], owner);
-    });
-  }
-  std::vector<size_t> base(part.size(), 0);
-  for (size_t w = 0; w < part.size(); ++w) {
-    base[w] = L.tiles.size();
-    L.tiles.insert(L.tiles.end(), part[w].begin(), part[w].end());
-  }
-  par_ranges(part.size(), 1, [&](size_t w0, size_t w1) {
-    for (size_t w = w0; w < w1; ++w) {
-      if (!base[w]) continue;
-      const size_t i0 = (size_t)(zr[w] + 1) * L.fn[1] * L.fn[0], i1 = (size_t)(zr[w + 1] + 1) * L.fn[1] * L.fn[0];
-      for (size_t i = i0; i < i1; ++i)
-        if (owner[i] >= 0) owner[i] += (int32_t)base[w];
-    }
-  });
+// Frame position (fx, fy, fz) of a tile's first cell.
+void tile_origin3(const Level3 &L, const Tile3 &T, int f[3]) {
+  const int64_t rel = T.off0 - L.xoff;
+  f[2] = (int)(rel / L.slab);
+  f[1] = (int)((rel - (int64_t)f[2] * L.slab) / L.pitch);
+  f[0] = (int)(rel - (int64_t)f[2] * L.slab - (int64_t)f[1] * L.pitch);
 }
 
-// Tiles of the z-slabs [za, zb) of level l into `tiles` (indices local to it,
-// written into owner).
-void build_tile_slabs3(vlbm3_ctx *c, int l, int za, int zb, int tc, std::vector<Tile3> &tiles,
-                       std::vector<int32_t> &owner) {
+// Tiles of the z-slabs [za, zb) of level l into `tiles`: runs of active cells
+// along x (cut at tc cells), equal runs on consecutive rows stacked while the
+// tile holds at most tc cells.
+void build_tile_slabs3(vlbm3_ctx *c, int l, int za, int zb, int tc, std::vector<Tile3> &tiles) {
   Level3 &L = c->lv[l];
+  struct Open {
+    int xa, w, ti;  // run start (frame column), width, tile growing on the previous row
+  };
+  std::vector<Open> open, next;  // ordered by xa (the runs of a row are disjoint)
+  const int xe = L.fn[0] - 1;
   for (int z = za; z < zb; ++z) {
-    std::map<std::pair<int, int>, int> open;  // (x0, w) -> tile growing on the previous row
+    open.clear();
     for (int y = L.f0[1] + 1; y < L.f0[1] + L.fn[1] - 1; ++y) {
-      std::map<std::pair<int, int>, int> next;
-      int x = L.f0[0] + 1;
-      const int xe = L.f0[0] + L.fn[0] - 1;
-      while (x < xe) {
-        int p[3] = {x, y, z};
-        if (L.status[L.fidx(p)] != 1) {
-          ++x;
-          continue;
+      next.clear();
+      const int p0[3] = {L.f0[0], y, z};
+      const uint8_t *row = &L.status[L.fidx(p0)];
+      size_t j = 0;
+      for (int x = 1; x < xe;) {
+        if (row[x] != 1) {  // to the next active cell
+          const void *nx = memchr(row + x, 1, xe - x);
+          if (!nx) break;
+          x = (int)(static_cast<const uint8_t *>(nx) - row);
         }
         const int xa = x;
-        while (x < xe && x - xa < tc) {
-          int pp[3] = {x, y, z};
-          if (L.status[L.fidx(pp)] != 1) break;
-          ++x;
-        }
+        while (x < xe && x - xa < tc && row[x] == 1) ++x;
         const int w = x - xa;
-        const std::pair<int, int> key{xa, w};
-        auto it = open.find(key);
+        while (j < open.size() && open[j].xa < xa) ++j;
         int ti;
-        if (it != open.end() && (tiles[it->second].h + 1) * w <= tc) {
-          ti = it->second;
+        if (j < open.size() && open[j].xa == xa && open[j].w == w && (tiles[open[j].ti].h + 1) * w <= tc) {
+          ti = open[j].ti;
           tiles[ti].h += 1;
         } else {
           Tile3 t{};
-          int q0[3] = {xa, y, z};
+          const int q0[3] = {L.f0[0] + xa, y, z};
           t.off0 = (int32_t)L.off(q0);
           t.w = w;
           t.h = 1;
           tiles.push_back(t);
           ti = (int)tiles.size() - 1;
         }
-        next[key] = ti;
-        for (int xx = xa; xx < x; ++xx) {
-          int pp[3] = {xx, y, z};
-          owner[L.fidx(pp)] = ti;
-        }
+        next.push_back({xa, w, ti});
       }
       open.swap(next);
     }
   }
+}
+
+void build_tiles3(vlbm3_ctx *c, int l, TileRows3 &own) {
+  Level3 &L = c->lv[l];
+  L.tiles.clear();
+  const int tc = c->tile_cells;
+  // z-slabs are independent: ranges of them on worker threads, each with its
+  // own tile list, then concatenated in z order
+  const int nz = std::max(0, L.fn[2] - 2);
+  const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+  const int nw = (int)std::max<size_t>(1, std::min<size_t>({16, hw, (size_t)std::max(nz, 1)}));
+  std::vector<std::vector<Tile3>> part(nw);
+  vlbm_host::Pool::get().run(nw, [&](int w) {
+    build_tile_slabs3(c, l, L.f0[2] + 1 + (int)((size_t)nz * w / nw), L.f0[2] + 1 + (int)((size_t)nz * (w + 1) / nw),
+                      tc, part[w]);
+  });
+  for (const auto &v : part) L.tiles.insert(L.tiles.end(), v.begin(), v.end());
+  // the tiles crossing each frame row
+  const size_t nrows = (size_t)L.fn[1] * L.fn[2];
+  own.row0.assign(nrows + 1, 0);
+  for (const Tile3 &T : L.tiles) {
+    int f[3];
+    tile_origin3(L, T, f);
+    for (int cy = 0; cy < T.h; ++cy) own.row0[(size_t)f[2] * L.fn[1] + f[1] + cy + 1] += 1;
+  }
+  for (size_t i = 0; i < nrows; ++i) own.row0[i + 1] += own.row0[i];
+  own.ent.resize(own.row0[nrows]);
+  std::vector<int32_t> at(own.row0.begin(), own.row0.end() - 1);
+  for (size_t ti = 0; ti < L.tiles.size(); ++ti) {
+    const Tile3 &T = L.tiles[ti];
+    int f[3];
+    tile_origin3(L, T, f);
+    for (int cy = 0; cy < T.h; ++cy)
+      own.ent[at[(size_t)f[2] * L.fn[1] + f[1] + cy]++] = {f[0], f[0] + T.w, (int32_t)ti};
+  }
+  // a row's entries come in tile order (tiles that started on earlier rows
+  // first): ordered by x0 row by row
+  par_ranges(nrows, 4096, [&](size_t i0, size_t i1) {
+    for (size_t i = i0; i < i1; ++i)
+      if (own.row0[i + 1] - own.row0[i] > 1)
+        std::sort(own.ent.begin() + own.row0[i], own.ent.begin() + own.row0[i + 1],
+                  [](const TileRows3::Ent &a, const TileRows3::Ent &b) { return a.x0 < b.x0; });
+  });
 }
 
 struct RefluxKey3 {
@@ -481,9 +523,11 @@ vlbm_status build_lists3(vlbm3_ctx *c) {
   std::vector<RefluxKey3> caps_from_parent;
   const int r = c->p.r;
   for (int l = 0; l < c->nlev; ++l) {
+    PhaseTimer lt(l == 0 ? "lists3 l0" : l == 1 ? "lists3 l1" : l == 2 ? "lists3 l2" : "lists3 l3+");
     Level3 &L = c->lv[l];
-    std::vector<int32_t> owner;
-    build_tiles3(c, l, owner);
+    TileRows3 own;
+    build_tiles3(c, l, own);
+    lt.mark("tiles");
     std::vector<std::vector<Task3>> per(L.tiles.size());
     std::vector<RefluxKey3> refl;
     L.nacc = 0;
@@ -502,16 +546,32 @@ vlbm_status build_lists3(vlbm3_ctx *c) {
       const int fz = (int)(rel / L.slab);
       const int fy = (int)((rel - (int64_t)fz * L.slab) / L.pitch);
       const int fx = (int)(rel - (int64_t)fz * L.slab - (int64_t)fy * L.pitch);
-      for (int cy = 0; cy < T.h; ++cy)
-        for (int cx = 0; cx < T.w; ++cx) {
-          const int x[3] = {L.f0[0] + fx + cx, L.f0[1] + fy + cy, L.f0[2] + fz};
-          bool interior = true;
-          for (int q = 0; q < 6 && interior; ++q) {
-            int s[3] = {x[0] - E3[q][0], x[1] - E3[q][1], x[2] - E3[q][2]};
-            if (!L.in_frame(s) || L.status[L.fidx(s)] != 1) interior = false;
+      // Status offsets of the six upwind neighbours (an active cell's
+      // neighbours all lie in the frame, whose ghost layer surrounds them).
+      const int64_t sy = L.fn[0], sz = (int64_t)L.fn[0] * L.fn[1];
+      const int64_t up[6] = {-1, 1, -sy, sy, -sz, sz};  // cell - e_q
+      constexpr uint64_t ones = 0x0101010101010101ull;
+      auto all8 = [](const uint8_t *p) {
+        uint64_t v;
+        memcpy(&v, p, 8);
+        return v == ones;
+      };
+      for (int cy = 0; cy < T.h; ++cy) {
+        const uint8_t *st = &L.status[((size_t)fz * L.fn[1] + fy + cy) * L.fn[0] + fx];
+        for (int cx = 0; cx < T.w;) {
+          // eight interior cells at once: cells cx - 1 .. cx + 8 of the row and
+          // cx .. cx + 7 of the four rows around it active
+          if (cx + 8 <= T.w && fx + cx + 8 < L.fn[0] && all8(st + cx - 1) && all8(st + cx + 1) &&
+              all8(st + cx - sy) && all8(st + cx + sy) && all8(st + cx - sz) && all8(st + cx + sz)) {
+            cx += 8;
+            continue;
           }
-          if (interior) continue;
+          const uint8_t *sc = st + cx;
+          ++cx;
+          if (sc[-1] == 1 && sc[1] == 1 && sc[-sy] == 1 && sc[sy] == 1 && sc[-sz] == 1 && sc[sz] == 1) continue;
+          const int x[3] = {L.f0[0] + fx + cx - 1, L.f0[1] + fy + cy, L.f0[2] + fz};
           for (int q = 0; q < 6; ++q) {
+            if (sc[up[q]] == 1) continue;  // an active cell of this level, read in place
             Task3 t;
             bool needed = false;
             vlbm_status st = ghost_task3(c, l, x, q, t, needed);
@@ -529,6 +589,7 @@ vlbm_status build_lists3(vlbm3_ctx *c) {
             per[ti].push_back(t);
           }
         }
+      }
       tled[ti] = nled;
       return VLBM_OK;
     };
@@ -552,6 +613,7 @@ vlbm_status build_lists3(vlbm3_ctx *c) {
       for (int w = 0; w < nw; ++w)
         if (wst[w]) return fail3(wst[w], "%s", wmsg[w].c_str());
     }
+    lt.mark("tasks");
     for (size_t ti = 0; ti < L.tiles.size(); ++ti) {  // slots in tile order
       const int acc0 = L.nacc, led0 = L.nledger;
       for (Task3 &t : per[ti]) {
@@ -568,9 +630,17 @@ vlbm_status build_lists3(vlbm3_ctx *c) {
       L.nacc += (int)trefl[ti].size();
       L.nledger += tled[ti];
     }
+    lt.mark("slots");
     // captures of this level for the parent's reflux slots
     if (l > 0) {
-      for (const RefluxKey3 &k : caps_from_parent) {
+      // found on the pool in order of the parent's slots (a failure is
+      // reported as its tile -1 - code), then appended to their tiles
+      struct Cap {
+        int32_t ti;
+        Task3 t;
+      };
+      const std::vector<Cap> caps = par_collect<Cap>(caps_from_parent.size(), [&](size_t i, std::vector<Cap> &out) {
+        const RefluxKey3 &k = caps_from_parent[i];
         const int q = k.q, n = q / 2;
         // the fine cells of hole H on its face towards the ring cell (which
         // lies at H + e_q): normal index r-1 for a + population, 0 for -
@@ -580,8 +650,11 @@ vlbm_status build_lists3(vlbm3_ctx *c) {
         int ta[2], nt = 0;
         for (int a = 0; a < 3; ++a)
           if (a != n) ta[nt++] = a;
-        if (!L.in_frame(R0)) return fail3(VLBM_ENEST, "internal: capture outside the fine frame");
         Task3 t{};
+        if (!L.in_frame(R0)) {
+          out.push_back({-1, t});
+          return;
+        }
         t.kind = K3_CAPTURE;
         t.q = q;
         t.src = (int32_t)L.off(R0);
@@ -594,14 +667,22 @@ vlbm_status build_lists3(vlbm3_ctx *c) {
             int Rc[3] = {R0[0], R0[1], R0[2]};
             Rc[ta[1]] += a2;
             Rc[ta[0]] += b2;
-            if (!L.in_frame(Rc) || L.status[L.fidx(Rc)] != 1)
-              return fail3(VLBM_ENEST, "level %d: reflux face cell not active (nesting)", l);
+            if (!L.in_frame(Rc) || L.status[L.fidx(Rc)] != 1) {
+              out.push_back({-2, t});
+              return;
+            }
           }
-        const int32_t ti = owner[L.fidx(R0)];
-        if (ti < 0) return fail3(VLBM_ENEST, "internal: capture without a tile");
-        per[ti].push_back(t);
+        const int32_t ti = own.tile_of(L, R0);
+        out.push_back({ti < 0 ? -3 : ti, t});
+      });
+      for (const Cap &cp : caps) {
+        if (cp.ti == -1) return fail3(VLBM_ENEST, "internal: capture outside the fine frame");
+        if (cp.ti == -2) return fail3(VLBM_ENEST, "level %d: reflux face cell not active (nesting)", l);
+        if (cp.ti == -3) return fail3(VLBM_ENEST, "internal: capture without a tile");
+        per[cp.ti].push_back(cp.t);
       }
     }
+    lt.mark("captures");
     L.face_key.clear();
     L.face_key.reserve(refl.size());
     for (const RefluxKey3 &k : refl) {
@@ -609,14 +690,20 @@ vlbm_status build_lists3(vlbm3_ctx *c) {
       c->wrap(l, ring);
       L.face_key.push_back((((int64_t)ring[2] * L.N[1] + ring[1]) * L.N[0] + ring[0]) * 6 + (k.q ^ 1));
     }
+    lt.mark("face keys");
     std::sort(L.face_key.begin(), L.face_key.end());
+    lt.mark("face sort");
     caps_from_parent.swap(refl);
     L.tasks.clear();
+    size_t ntask = 0;
+    for (const auto &v : per) ntask += v.size();
+    L.tasks.reserve(ntask);
     for (size_t ti = 0; ti < L.tiles.size(); ++ti) {
       L.tiles[ti].task0 = (int32_t)L.tasks.size();
       L.tiles[ti].ntask = (int32_t)per[ti].size();
       L.tasks.insert(L.tasks.end(), per[ti].begin(), per[ti].end());
     }
+    lt.mark("faces+order");
   }
   if (!caps_from_parent.empty()) return fail3(VLBM_ENEST, "internal: reflux slots on the finest level");
   return VLBM_OK;
@@ -939,20 +1026,20 @@ vlbm_status build_geometry3(const vlbm3_params &p, const vlbm3_box *boxes, int n
   });
   for (int b = 0; b < nboxes; ++b)
     if (bad[b]) return fail3(VLBM_ENEST, "box %d: hierarchy not properly nested", b);
+  // status: covered cells are active (1); those under a level-(l+1) box,
+  // whose parent cells form a block of whole level-l cells, are holes (2)
   for (int l = 0; l < nlev; ++l) {
     Level3 &L = lv[l];
-    L.status.assign(L.cov.size(), 0);
-    par_ranges((size_t)L.fn[2], 1, [&](size_t z0, size_t z1) {
-      for (int z = L.f0[2] + (int)z0; z < L.f0[2] + (int)z1; ++z)
-        for (int y = L.f0[1]; y < L.f0[1] + L.fn[1]; ++y)
-          for (int x = L.f0[0]; x < L.f0[0] + L.fn[0]; ++x) {
-            const int q[3] = {x, y, z};
-            const size_t i = L.fidx(q);
-            if (!L.cov[i]) continue;
-            const int ch[3] = {x * r, y * r, z * r};
-            L.status[i] = cov_in(lv, nlev, l + 1, ch) ? 2 : 1;
-          }
-    });
+    L.status = L.cov;
+    for (int b = 0; b < nboxes; ++b) {
+      const vlbm3_box &B = boxes[b];
+      if (B.level != l + 1) continue;
+      for (int z = B.k0 / r; z < (B.k0 + B.nz) / r; ++z)
+        for (int y = B.j0 / r; y < (B.j0 + B.ny) / r; ++y) {
+          const int p0[3] = {B.i0 / r, y, z};
+          memset(&L.status[L.fidx(p0)], 2, B.nx / r);
+        }
+    }
   }
   return VLBM_OK;
 }
@@ -1066,9 +1153,10 @@ void cluster_level3(const vlbm3_ctx *c, int l, const TagMap3 &tags, const CovMap
       bool any = false;
       int fx = 0;
       while (fx < tags.n[0]) {
-        if (!row[fx]) {
-          ++fx;
-          continue;
+        if (!row[fx]) {  // to the next tagged cell (tags are 0 or 1)
+          const void *nx = memchr(row + fx, 1, tags.n[0] - fx);
+          if (!nx) break;
+          fx = (int)(static_cast<const uint8_t *>(nx) - row);
         }
         const int xa = fx;
         while (fx < tags.n[0] && row[fx]) ++fx;
@@ -1182,20 +1270,29 @@ void cluster_hierarchy3(const vlbm3_ctx *c, std::vector<TagMap3> &tags, int buff
     TagMap3 &F = tags[l], &P = tags[l - 1];
     if (F.t.empty() || P.t.empty()) continue;
     for (int fz = 0; fz < F.n[2]; ++fz)
-      for (int fy = 0; fy < F.n[1]; ++fy)
+      for (int fy = 0; fy < F.n[1]; ++fy) {
+        const uint8_t *row = &F.t[((size_t)fz * F.n[1] + fy) * F.n[0]];
         for (int fx = 0; fx < F.n[0]; ++fx) {
-          if (!F.t[((size_t)fz * F.n[1] + fy) * F.n[0] + fx]) continue;
+          if (!row[fx]) {  // to the next tagged cell (tags are 0 or 1)
+            const void *nx = memchr(row + fx, 1, F.n[0] - fx);
+            if (!nx) break;
+            fx = (int)(static_cast<const uint8_t *>(nx) - row);
+          }
           const int p[3] = {(F.o[0] + fx) / r, (F.o[1] + fy) / r, (F.o[2] + fz) / r};
           bool in = true;
           for (int a = 0; a < 3; ++a) in = in && p[a] >= P.o[a] && p[a] < P.o[a] + P.n[a];
           if (in) P.at(p[0], p[1], p[2]) = 1;
         }
+      }
   }
+  PhaseTimer tm("cluster3");
+  tm.mark("parents");
   CovMap3 cov;
   for (int l = 0; l + 1 < ML; ++l) {
     if (tags[l].t.empty()) break;
     const size_t before = boxes.size();
     cluster_level3(c, l, tags[l], cov, buffer, min_box, max_box, boxes);
+    tm.mark(l == 0 ? "level 0" : l == 1 ? "level 1" : "level 2+");
     if (boxes.size() == before || l + 2 >= ML) break;
     CovMap3 nc;  // coverage of level l+1 over the bounding box of its new boxes
     nc.all = false;
@@ -1337,8 +1434,9 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
   for (int l = onlev - 1; l >= 1; --l) {
     const Level3 &F = c->lv[l];
     Level3 &Cl = c->lv[l - 1];
-    std::vector<RegridOp3> ops;
-    for (int z = F.f0[2] + 1; z < F.f0[2] + F.fn[2] - 1; z += r)
+    const int nzs = (F.fn[2] - 2 + r - 1) / r;  // r-grid planes (the frame's first interior cell is aligned)
+    const std::vector<RegridOp3> ops = par_collect<RegridOp3>((size_t)std::max(nzs, 0), [&](size_t iz, std::vector<RegridOp3> &out) {
+      const int z = F.f0[2] + 1 + (int)iz * r;
       for (int y = F.f0[1] + 1; y < F.f0[1] + F.fn[1] - 1; y += r)
         for (int x = F.f0[0] + 1; x < F.f0[0] + F.fn[0] - 1; x += r) {
           const int q[3] = {x, y, z};
@@ -1347,8 +1445,9 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
           RegridOp3 o{};
           o.dst = (int32_t)Cl.off(P);
           o.src = (int32_t)F.off(q);
-          ops.push_back(o);
+          out.push_back(o);
         }
+    });
     if (ops.empty()) continue;
     RegridArgs3 a{};
     a.fine_cur = F.buf[F.cur()];
@@ -1387,8 +1486,8 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
     HIPCHK3(hipMemsetAsync(N.buf[0], 0, nb, c->stream));
     HIPCHK3(hipMemsetAsync(N.buf[1], 0, nb, c->stream));
     if (!O || !O->present) continue;
-    std::vector<int32_t> runs;
-    for (int z = N.f0[2] + 1; z < N.f0[2] + N.fn[2] - 1; ++z)
+    const std::vector<int32_t> runs = par_collect<int32_t>((size_t)std::max(N.fn[2] - 2, 0), [&](size_t iz, std::vector<int32_t> &out) {
+      const int z = N.f0[2] + 1 + (int)iz;
       for (int y = N.f0[1] + 1; y < N.f0[1] + N.fn[1] - 1; ++y) {
         int x = N.f0[0] + 1;
         const int xe = N.f0[0] + N.fn[0] - 1;
@@ -1405,11 +1504,12 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
             ++x;
           }
           const int qa[3] = {xa, y, z};
-          runs.push_back((int32_t)O->off(qa));
-          runs.push_back((int32_t)N.off(qa));
-          runs.push_back(x - xa);
+          out.push_back((int32_t)O->off(qa));
+          out.push_back((int32_t)N.off(qa));
+          out.push_back(x - xa);
         }
       }
+    });
     if (runs.empty()) continue;
     int32_t *druns = nullptr;
     ALLOC3(druns, sizeof(int32_t) * runs.size());
@@ -1424,8 +1524,9 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
   //    hierarchy and holds data (not a hole before and after)
   for (int l = 0; l + 1 < nnlev; ++l) {
     Level3 &Cl = nl[l], &F = nl[l + 1];
-    std::vector<RegridOp3> ops;
-    for (int z = F.f0[2] + 1; z < F.f0[2] + F.fn[2] - 1; z += r)
+    const int nzs = (F.fn[2] - 2 + r - 1) / r;
+    const std::vector<RegridOp3> ops = par_collect<RegridOp3>((size_t)std::max(nzs, 0), [&](size_t iz, std::vector<RegridOp3> &out) {
+      const int z = F.f0[2] + 1 + (int)iz * r;
       for (int y = F.f0[1] + 1; y < F.f0[1] + F.fn[1] - 1; y += r)
         for (int x = F.f0[0] + 1; x < F.f0[0] + F.fn[0] - 1; x += r) {
           const int q[3] = {x, y, z};
@@ -1442,8 +1543,9 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
             if (old_cov(l + 1, ch) && new_cov(l + 1, ch)) continue;  // a hole before and after
             o.nb[d] = (int32_t)Cl.off(nbq);
           }
-          ops.push_back(o);
+          out.push_back(o);
         }
+    });
     if (ops.empty()) continue;
     RegridArgs3 a{};
     a.coarse_cur = Cl.buf[Cl.cur()];
