@@ -1266,10 +1266,16 @@ void cluster_level3(const vlbm3_ctx *c, int l, const TagMap3 &tags, const CovMap
 void cluster_hierarchy3(const vlbm3_ctx *c, std::vector<TagMap3> &tags, int buffer, int min_box, int max_box,
                         std::vector<vlbm3_box> &boxes) {
   const int r = c->p.r, ML = c->p.max_levels;
+  PhaseTimer tm("cluster3");
   for (int l = ML - 1; l >= 1; --l) {
     TagMap3 &F = tags[l], &P = tags[l - 1];
     if (F.t.empty() || P.t.empty()) continue;
-    for (int fz = 0; fz < F.n[2]; ++fz)
+    // on the pool by parent planes: the fine planes of a parent plane are its
+    // r children planes, so no two threads mark the same parent cell
+    auto fdiv = [r](int a) { return a >= 0 ? a / r : -((-a + r - 1) / r); };  // floor(a / r)
+    const int pz0 = fdiv(F.o[2]), pz1 = fdiv(F.o[2] + F.n[2] - 1) + 1;
+    par_ranges((size_t)(pz1 - pz0), 1, [&](size_t i0, size_t i1) {
+    for (int fz = std::max(0, (pz0 + (int)i0) * r - F.o[2]); fz < std::min(F.n[2], (pz0 + (int)i1) * r - F.o[2]); ++fz)
       for (int fy = 0; fy < F.n[1]; ++fy) {
         const uint8_t *row = &F.t[((size_t)fz * F.n[1] + fy) * F.n[0]];
         for (int fx = 0; fx < F.n[0]; ++fx) {
@@ -1284,8 +1290,8 @@ void cluster_hierarchy3(const vlbm3_ctx *c, std::vector<TagMap3> &tags, int buff
           if (in) P.at(p[0], p[1], p[2]) = 1;
         }
       }
+    });
   }
-  PhaseTimer tm("cluster3");
   tm.mark("parents");
   CovMap3 cov;
   for (int l = 0; l + 1 < ML; ++l) {
