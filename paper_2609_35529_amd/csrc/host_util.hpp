@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <deque>
+#include <exception>
 #include <functional>
 #include <mutex>
 #include <thread>
@@ -31,7 +32,8 @@ class Pool {
   // Calls f(i) for every i in [0, n) on the workers and the calling thread,
   // and returns when all have returned. The caller takes items of its own
   // call until none is left, so a call made from inside f (nested) always
-  // progresses, whatever the workers are doing. f must not throw.
+  // progresses, whatever the workers are doing. If items throw, every item
+  // still runs and the first exception caught is rethrown to the caller.
   void run(int n, const std::function<void(int)> &f) {
     if (n <= 0) return;
     if (n == 1) {
@@ -47,10 +49,7 @@ class Pool {
       queued_.fetch_add(1, std::memory_order_release);
     }
     cv_.notify_all();
-    for (int i; (i = b.next.fetch_add(1)) < n;) {
-      f(i);
-      b.done.fetch_add(1, std::memory_order_release);
-    }
+    for (int i; (i = b.next.fetch_add(1)) < n;) b.item(i);
     {  // no worker can claim an item of b once it has left the queue
       std::lock_guard<std::mutex> g(m_);
       auto it = std::find(q_.begin(), q_.end(), &b);
@@ -60,6 +59,7 @@ class Pool {
       }
     }
     while (b.done.load(std::memory_order_acquire) < n) std::this_thread::yield();
+    if (b.err) std::rethrow_exception(b.err);
   }
 
  private:
@@ -67,6 +67,17 @@ class Pool {
     const std::function<void(int)> *f = nullptr;
     int n = 0;
     std::atomic<int> next{0}, done{0};
+    std::mutex em;
+    std::exception_ptr err;  // the first exception an item threw
+    void item(int i) {
+      try {
+        (*f)(i);
+      } catch (...) {
+        std::lock_guard<std::mutex> g(em);
+        if (!err) err = std::current_exception();
+      }
+      done.fetch_add(1, std::memory_order_release);  // the batch may end right after this
+    }
   };
 
   explicit Pool(int nworkers) {
@@ -103,8 +114,7 @@ class Pool {
           cv_.wait(l, [&] { return claim(b, i); });
         }
       }
-      (*b->f)(i);
-      b->done.fetch_add(1, std::memory_order_release);  // b may end right after this
+      b->item(i);
     }
   }
 

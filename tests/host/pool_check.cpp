@@ -2,12 +2,14 @@
 // (paper_2609_35529_amd/csrc/host_util.hpp), built with ThreadSanitizer by
 // tests/test_host_pool.py: every item of a section runs exactly once, nested
 // sections (a section started from inside an item, as the list builders do
-// per level and per band of rows) complete, and sections started by several
-// host threads at once (several contexts) do not mix their items.
+// per level and per band of rows) complete, sections started by several host
+// threads at once (several contexts) do not mix their items, and an item that
+// throws leaves the others running and reaches the caller.
 #include "../../paper_2609_35529_amd/csrc/host_util.hpp"
 
 #include <atomic>
 #include <cstdio>
+#include <stdexcept>
 #include <thread>
 #include <vector>
 
@@ -59,6 +61,25 @@ int main() {
           printf("threads: section %d item %d sum %ld\n", t, i, sums[t][i]);
           bad = 1;
         }
+  }
+  // items that throw: the section still runs every item, and the caller
+  // gets the exception
+  {
+    std::vector<std::atomic<int>> c(32);
+    bool caught = false;
+    try {
+      pool.run(32, [&](int i) {
+        c[i].fetch_add(1);
+        if (i % 7 == 3) throw std::runtime_error("item");
+      });
+    } catch (const std::runtime_error &) {
+      caught = true;
+    }
+    bad |= check_counts(c, 1, "throwing");
+    if (!caught) {
+      printf("throwing: no exception reached the caller\n");
+      bad = 1;
+    }
   }
   printf(bad ? "FAIL\n" : "ok\n");
   return bad;
