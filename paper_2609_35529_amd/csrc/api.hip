@@ -23,6 +23,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <new>
 #include <string>
 #include <functional>
 #include <thread>
@@ -792,7 +793,13 @@ vlbm_status run_parallel(int n, const std::function<vlbm_status(int)> &f) {
   std::vector<vlbm_status> st(n, VLBM_OK);
   std::vector<std::string> err(n);
   vlbm_host::Pool::get().run(n, [&](int i) {
-    st[i] = f(i);
+    try {  // no exception leaves a section (nor the C ABI above it)
+      st[i] = f(i);
+    } catch (const std::bad_alloc &) {
+      st[i] = fail(VLBM_ENOMEM, "host memory exhausted");
+    } catch (...) {
+      st[i] = fail(VLBM_EINVAL, "internal error in a host section");
+    }
     if (st[i]) err[i] = g_err;
   });
   for (int i = 0; i < n; ++i)

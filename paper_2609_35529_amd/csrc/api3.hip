@@ -19,6 +19,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <new>
 #include <string>
 #include <thread>
 #include <type_traits>
@@ -45,6 +46,20 @@ vlbm_status fail3(vlbm_status st, const char *fmt, ...) {
   va_end(ap);
   vlbm::set_error_message(buf);
   return st;
+}
+
+// An entry point's body that runs host sections on the worker pool: an
+// exception (host memory exhausted) becomes a status, not a throw across the
+// C ABI.
+template <class F>
+vlbm_status guard3(F &&f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc &) {
+    return fail3(VLBM_ENOMEM, "host memory exhausted");
+  } catch (...) {
+    return fail3(VLBM_EINVAL, "internal error in a host section");
+  }
 }
 
 #define HIPCHK3(expr)                                                                    \
@@ -1380,248 +1395,252 @@ size_t vlbm3_footprint_bytes(const vlbm3_params *params, const vlbm3_box *boxes,
 }
 
 vlbm_status vlbm3_set_hierarchy(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
-  if (!c) return fail3(VLBM_EINVAL, "null context");
-  Level3 nl[kL];
-  int nnlev = 1;
-  vlbm_status st = build_geometry3(c->p, boxes, nboxes, nl, nnlev);
-  if (st) return st;
-  HIPCHK3(hipStreamSynchronize(c->stream));
-  for (int l = 0; l < kL; ++l) free_level3(c->mem, c->lv[l]);
-  c->have_hierarchy = false;
-  for (int l = 0; l < kL; ++l) c->lv[l] = std::move(nl[l]);
-  c->nlev = nnlev;
-  st = build_lists3(c);
-  if (st) {
-    for (int m = 0; m < kL; ++m) free_level3(c->mem, c->lv[m]);
-    return st;
-  }
-  for (int l = 0; l < c->nlev; ++l) {
-    Level3 &L = c->lv[l];
-    const size_t nb = level_bytes3(L);
-    ALLOC3(L.buf[0], nb);
-    ALLOC3(L.buf[1], nb);
-    HIPCHK3(hipMemsetAsync(L.buf[0], 0, nb, c->stream));
-    HIPCHK3(hipMemsetAsync(L.buf[1], 0, nb, c->stream));
-    ALLOC3(L.dstatus, L.status.size());
-    HIPCHK3(hipMemcpyAsync(L.dstatus, L.status.data(), L.status.size(), hipMemcpyHostToDevice, c->stream));
-    L.steps = 0;
-  }
-  st = upload_lists3(c);
-  if (st) return st;
-  c->boxes.assign(boxes, boxes + nboxes);
-  c->have_hierarchy = true;
-  c->coarse_steps = 0;
-  return build_tables3(c);
+  return guard3([&]() -> vlbm_status {
+    if (!c) return fail3(VLBM_EINVAL, "null context");
+    Level3 nl[kL];
+    int nnlev = 1;
+    vlbm_status st = build_geometry3(c->p, boxes, nboxes, nl, nnlev);
+    if (st) return st;
+    HIPCHK3(hipStreamSynchronize(c->stream));
+    for (int l = 0; l < kL; ++l) free_level3(c->mem, c->lv[l]);
+    c->have_hierarchy = false;
+    for (int l = 0; l < kL; ++l) c->lv[l] = std::move(nl[l]);
+    c->nlev = nnlev;
+    st = build_lists3(c);
+    if (st) {
+      for (int m = 0; m < kL; ++m) free_level3(c->mem, c->lv[m]);
+      return st;
+    }
+    for (int l = 0; l < c->nlev; ++l) {
+      Level3 &L = c->lv[l];
+      const size_t nb = level_bytes3(L);
+      ALLOC3(L.buf[0], nb);
+      ALLOC3(L.buf[1], nb);
+      HIPCHK3(hipMemsetAsync(L.buf[0], 0, nb, c->stream));
+      HIPCHK3(hipMemsetAsync(L.buf[1], 0, nb, c->stream));
+      ALLOC3(L.dstatus, L.status.size());
+      HIPCHK3(hipMemcpyAsync(L.dstatus, L.status.data(), L.status.size(), hipMemcpyHostToDevice, c->stream));
+      L.steps = 0;
+    }
+    st = upload_lists3(c);
+    if (st) return st;
+    c->boxes.assign(boxes, boxes + nboxes);
+    c->have_hierarchy = true;
+    c->coarse_steps = 0;
+    return build_tables3(c);
+  });
 }
 
 vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
-  if (!c || !c->have_hierarchy) return fail3(VLBM_ESTATE, "no hierarchy installed");
-  PhaseTimer tm("regrid3");
-  Level3 nl[kL];
-  int nnlev = 1;
-  vlbm_status st = build_geometry3(c->p, boxes, nboxes, nl, nnlev);
-  if (st) return st;
-  tm.mark("geometry");
-  const int r = c->p.r, onlev = c->nlev;
-  // the boundary ledger survives the rebuild of its slots
-  double tot[5], led[5] = {};
-  st = vlbm3_conserved_totals(c, tot, led);
-  if (st) return st;
-  auto old_cov = [&](int l, const int q[3]) { return cov_in(c->lv, onlev, l, q); };
-  auto new_cov = [&](int l, const int q[3]) { return cov_in(nl, nnlev, l, q); };
-  std::vector<void *> scratch;  // device op lists, freed after the final sync
-  auto upload_ops = [&](const std::vector<RegridOp3> &ops, RegridOp3 *&d) -> vlbm_status {
-    ALLOC3(d, sizeof(RegridOp3) * std::max<size_t>(1, ops.size()));
-    scratch.push_back(d);
-    if (!ops.empty()) HIPCHK3(hipMemcpyAsync(d, ops.data(), sizeof(RegridOp3) * ops.size(), hipMemcpyHostToDevice, c->stream));
-    return VLBM_OK;
-  };
-  // 1. merges, finest level first, in the old frames (eq. amr-merge)
-  for (int l = onlev - 1; l >= 1; --l) {
-    const Level3 &F = c->lv[l];
-    Level3 &Cl = c->lv[l - 1];
-    const int nzs = (F.fn[2] - 2 + r - 1) / r;  // r-grid planes (the frame's first interior cell is aligned)
-    const std::vector<RegridOp3> ops = par_collect<RegridOp3>((size_t)std::max(nzs, 0), [&](size_t iz, std::vector<RegridOp3> &out) {
-      const int z = F.f0[2] + 1 + (int)iz * r;
-      for (int y = F.f0[1] + 1; y < F.f0[1] + F.fn[1] - 1; y += r)
-        for (int x = F.f0[0] + 1; x < F.f0[0] + F.fn[0] - 1; x += r) {
-          const int q[3] = {x, y, z};
-          if (!F.cov[F.fidx(q)] || new_cov(l, q)) continue;
-          const int P[3] = {x / r, y / r, z / r};
-          RegridOp3 o{};
-          o.dst = (int32_t)Cl.off(P);
-          o.src = (int32_t)F.off(q);
-          out.push_back(o);
-        }
-    });
-    if (ops.empty()) continue;
-    RegridArgs3 a{};
-    a.fine_cur = F.buf[F.cur()];
-    a.coarse0 = Cl.buf[0];
-    a.coarse1 = Cl.buf[1];
-    a.fplane = F.plane;
-    a.fslab = F.slab;
-    a.fpitch = F.pitch;
-    a.cplane = Cl.plane;
-    a.r = r;
-    RegridOp3 *d = nullptr;
-    st = upload_ops(ops, d);
+  return guard3([&]() -> vlbm_status {
+    if (!c || !c->have_hierarchy) return fail3(VLBM_ESTATE, "no hierarchy installed");
+    PhaseTimer tm("regrid3");
+    Level3 nl[kL];
+    int nnlev = 1;
+    vlbm_status st = build_geometry3(c->p, boxes, nboxes, nl, nnlev);
     if (st) return st;
-    a.ops = d;
-    a.nops = (int32_t)ops.size();
-    HIPCHK3(launch_merge3(a, c->fp32, c->stream));
-  }
-  tm.mark("merges");
-  // 2. new frames: surviving cells move over (both time levels); a level
-  //    whose frame is unchanged keeps its buffers
-  for (int l = 0; l < nnlev; ++l) {
-    Level3 &N = nl[l];
-    Level3 *O = l < onlev ? &c->lv[l] : nullptr;
-    N.steps = O ? O->steps : 0;
-    if (O && O->present && O->plane == N.plane && O->pitch == N.pitch && O->slab == N.slab &&
-        O->f0[0] == N.f0[0] && O->f0[1] == N.f0[1] && O->f0[2] == N.f0[2] && O->fn[0] == N.fn[0] &&
-        O->fn[1] == N.fn[1] && O->fn[2] == N.fn[2]) {
-      N.buf[0] = O->buf[0];
-      N.buf[1] = O->buf[1];
-      O->buf[0] = O->buf[1] = nullptr;
-      continue;
+    tm.mark("geometry");
+    const int r = c->p.r, onlev = c->nlev;
+    // the boundary ledger survives the rebuild of its slots
+    double tot[5], led[5] = {};
+    st = vlbm3_conserved_totals(c, tot, led);
+    if (st) return st;
+    auto old_cov = [&](int l, const int q[3]) { return cov_in(c->lv, onlev, l, q); };
+    auto new_cov = [&](int l, const int q[3]) { return cov_in(nl, nnlev, l, q); };
+    std::vector<void *> scratch;  // device op lists, freed after the final sync
+    auto upload_ops = [&](const std::vector<RegridOp3> &ops, RegridOp3 *&d) -> vlbm_status {
+      ALLOC3(d, sizeof(RegridOp3) * std::max<size_t>(1, ops.size()));
+      scratch.push_back(d);
+      if (!ops.empty()) HIPCHK3(hipMemcpyAsync(d, ops.data(), sizeof(RegridOp3) * ops.size(), hipMemcpyHostToDevice, c->stream));
+      return VLBM_OK;
+    };
+    // 1. merges, finest level first, in the old frames (eq. amr-merge)
+    for (int l = onlev - 1; l >= 1; --l) {
+      const Level3 &F = c->lv[l];
+      Level3 &Cl = c->lv[l - 1];
+      const int nzs = (F.fn[2] - 2 + r - 1) / r;  // r-grid planes (the frame's first interior cell is aligned)
+      const std::vector<RegridOp3> ops = par_collect<RegridOp3>((size_t)std::max(nzs, 0), [&](size_t iz, std::vector<RegridOp3> &out) {
+        const int z = F.f0[2] + 1 + (int)iz * r;
+        for (int y = F.f0[1] + 1; y < F.f0[1] + F.fn[1] - 1; y += r)
+          for (int x = F.f0[0] + 1; x < F.f0[0] + F.fn[0] - 1; x += r) {
+            const int q[3] = {x, y, z};
+            if (!F.cov[F.fidx(q)] || new_cov(l, q)) continue;
+            const int P[3] = {x / r, y / r, z / r};
+            RegridOp3 o{};
+            o.dst = (int32_t)Cl.off(P);
+            o.src = (int32_t)F.off(q);
+            out.push_back(o);
+          }
+      });
+      if (ops.empty()) continue;
+      RegridArgs3 a{};
+      a.fine_cur = F.buf[F.cur()];
+      a.coarse0 = Cl.buf[0];
+      a.coarse1 = Cl.buf[1];
+      a.fplane = F.plane;
+      a.fslab = F.slab;
+      a.fpitch = F.pitch;
+      a.cplane = Cl.plane;
+      a.r = r;
+      RegridOp3 *d = nullptr;
+      st = upload_ops(ops, d);
+      if (st) return st;
+      a.ops = d;
+      a.nops = (int32_t)ops.size();
+      HIPCHK3(launch_merge3(a, c->fp32, c->stream));
     }
-    const size_t nb = level_bytes3(N);
-    ALLOC3(N.buf[0], nb);
-    ALLOC3(N.buf[1], nb);
-    HIPCHK3(hipMemsetAsync(N.buf[0], 0, nb, c->stream));
-    HIPCHK3(hipMemsetAsync(N.buf[1], 0, nb, c->stream));
-    if (!O || !O->present) continue;
-    const std::vector<int32_t> runs = par_collect<int32_t>((size_t)std::max(N.fn[2] - 2, 0), [&](size_t iz, std::vector<int32_t> &out) {
-      const int z = N.f0[2] + 1 + (int)iz;
-      for (int y = N.f0[1] + 1; y < N.f0[1] + N.fn[1] - 1; ++y) {
-        int x = N.f0[0] + 1;
-        const int xe = N.f0[0] + N.fn[0] - 1;
-        while (x < xe) {
-          const int q[3] = {x, y, z};
-          if (!(N.cov[N.fidx(q)] && O->in_frame(q) && O->cov[O->fidx(q)])) {
-            ++x;
-            continue;
-          }
-          const int xa = x;
-          while (x < xe) {
-            const int qq[3] = {x, y, z};
-            if (!(N.cov[N.fidx(qq)] && O->in_frame(qq) && O->cov[O->fidx(qq)])) break;
-            ++x;
-          }
-          const int qa[3] = {xa, y, z};
-          out.push_back((int32_t)O->off(qa));
-          out.push_back((int32_t)N.off(qa));
-          out.push_back(x - xa);
-        }
+    tm.mark("merges");
+    // 2. new frames: surviving cells move over (both time levels); a level
+    //    whose frame is unchanged keeps its buffers
+    for (int l = 0; l < nnlev; ++l) {
+      Level3 &N = nl[l];
+      Level3 *O = l < onlev ? &c->lv[l] : nullptr;
+      N.steps = O ? O->steps : 0;
+      if (O && O->present && O->plane == N.plane && O->pitch == N.pitch && O->slab == N.slab &&
+          O->f0[0] == N.f0[0] && O->f0[1] == N.f0[1] && O->f0[2] == N.f0[2] && O->fn[0] == N.fn[0] &&
+          O->fn[1] == N.fn[1] && O->fn[2] == N.fn[2]) {
+        N.buf[0] = O->buf[0];
+        N.buf[1] = O->buf[1];
+        O->buf[0] = O->buf[1] = nullptr;
+        continue;
       }
-    });
-    if (runs.empty()) continue;
-    int32_t *druns = nullptr;
-    ALLOC3(druns, sizeof(int32_t) * runs.size());
-    scratch.push_back(druns);
-    HIPCHK3(hipMemcpyAsync(druns, runs.data(), sizeof(int32_t) * runs.size(), hipMemcpyHostToDevice, c->stream));
-    HIPCHK3(launch_copy3_runs(O->buf[0], O->buf[1], N.buf[0], N.buf[1], druns, (int)(runs.size() / 3), O->plane,
-                              N.plane, c->fp32, c->stream));
-  }
-  tm.mark("frames");
-  // 3. splits, coarsest level first, in the new frames (eqs. amr-slope,
-  //    amr-split); a slope neighbour is covered at that level in the new
-  //    hierarchy and holds data (not a hole before and after)
-  for (int l = 0; l + 1 < nnlev; ++l) {
-    Level3 &Cl = nl[l], &F = nl[l + 1];
-    const int nzs = (F.fn[2] - 2 + r - 1) / r;
-    const std::vector<RegridOp3> ops = par_collect<RegridOp3>((size_t)std::max(nzs, 0), [&](size_t iz, std::vector<RegridOp3> &out) {
-      const int z = F.f0[2] + 1 + (int)iz * r;
-      for (int y = F.f0[1] + 1; y < F.f0[1] + F.fn[1] - 1; y += r)
-        for (int x = F.f0[0] + 1; x < F.f0[0] + F.fn[0] - 1; x += r) {
-          const int q[3] = {x, y, z};
-          if (!F.cov[F.fidx(q)] || old_cov(l + 1, q)) continue;
-          const int P[3] = {x / r, y / r, z / r};
-          RegridOp3 o{};
-          o.dst = (int32_t)F.off(q);
-          o.src = (int32_t)Cl.off(P);
-          for (int d = 0; d < 6; ++d) {
-            int nbq[3] = {P[0] + E3[d][0], P[1] + E3[d][1], P[2] + E3[d][2]};
-            o.nb[d] = -1;
-            if (!wrap_in(c->p, nl, l, nbq) || !new_cov(l, nbq)) continue;
-            const int ch[3] = {nbq[0] * r, nbq[1] * r, nbq[2] * r};
-            if (old_cov(l + 1, ch) && new_cov(l + 1, ch)) continue;  // a hole before and after
-            o.nb[d] = (int32_t)Cl.off(nbq);
+      const size_t nb = level_bytes3(N);
+      ALLOC3(N.buf[0], nb);
+      ALLOC3(N.buf[1], nb);
+      HIPCHK3(hipMemsetAsync(N.buf[0], 0, nb, c->stream));
+      HIPCHK3(hipMemsetAsync(N.buf[1], 0, nb, c->stream));
+      if (!O || !O->present) continue;
+      const std::vector<int32_t> runs = par_collect<int32_t>((size_t)std::max(N.fn[2] - 2, 0), [&](size_t iz, std::vector<int32_t> &out) {
+        const int z = N.f0[2] + 1 + (int)iz;
+        for (int y = N.f0[1] + 1; y < N.f0[1] + N.fn[1] - 1; ++y) {
+          int x = N.f0[0] + 1;
+          const int xe = N.f0[0] + N.fn[0] - 1;
+          while (x < xe) {
+            const int q[3] = {x, y, z};
+            if (!(N.cov[N.fidx(q)] && O->in_frame(q) && O->cov[O->fidx(q)])) {
+              ++x;
+              continue;
+            }
+            const int xa = x;
+            while (x < xe) {
+              const int qq[3] = {x, y, z};
+              if (!(N.cov[N.fidx(qq)] && O->in_frame(qq) && O->cov[O->fidx(qq)])) break;
+              ++x;
+            }
+            const int qa[3] = {xa, y, z};
+            out.push_back((int32_t)O->off(qa));
+            out.push_back((int32_t)N.off(qa));
+            out.push_back(x - xa);
           }
-          out.push_back(o);
         }
-    });
-    if (ops.empty()) continue;
-    RegridArgs3 a{};
-    a.coarse_cur = Cl.buf[Cl.cur()];
-    a.fine0 = F.buf[0];
-    a.fine1 = F.buf[1];
-    a.fplane = F.plane;
-    a.fslab = F.slab;
-    a.fpitch = F.pitch;
-    a.cplane = Cl.plane;
-    a.r = r;
-    RegridOp3 *d = nullptr;
-    st = upload_ops(ops, d);
+      });
+      if (runs.empty()) continue;
+      int32_t *druns = nullptr;
+      ALLOC3(druns, sizeof(int32_t) * runs.size());
+      scratch.push_back(druns);
+      HIPCHK3(hipMemcpyAsync(druns, runs.data(), sizeof(int32_t) * runs.size(), hipMemcpyHostToDevice, c->stream));
+      HIPCHK3(launch_copy3_runs(O->buf[0], O->buf[1], N.buf[0], N.buf[1], druns, (int)(runs.size() / 3), O->plane,
+                                N.plane, c->fp32, c->stream));
+    }
+    tm.mark("frames");
+    // 3. splits, coarsest level first, in the new frames (eqs. amr-slope,
+    //    amr-split); a slope neighbour is covered at that level in the new
+    //    hierarchy and holds data (not a hole before and after)
+    for (int l = 0; l + 1 < nnlev; ++l) {
+      Level3 &Cl = nl[l], &F = nl[l + 1];
+      const int nzs = (F.fn[2] - 2 + r - 1) / r;
+      const std::vector<RegridOp3> ops = par_collect<RegridOp3>((size_t)std::max(nzs, 0), [&](size_t iz, std::vector<RegridOp3> &out) {
+        const int z = F.f0[2] + 1 + (int)iz * r;
+        for (int y = F.f0[1] + 1; y < F.f0[1] + F.fn[1] - 1; y += r)
+          for (int x = F.f0[0] + 1; x < F.f0[0] + F.fn[0] - 1; x += r) {
+            const int q[3] = {x, y, z};
+            if (!F.cov[F.fidx(q)] || old_cov(l + 1, q)) continue;
+            const int P[3] = {x / r, y / r, z / r};
+            RegridOp3 o{};
+            o.dst = (int32_t)F.off(q);
+            o.src = (int32_t)Cl.off(P);
+            for (int d = 0; d < 6; ++d) {
+              int nbq[3] = {P[0] + E3[d][0], P[1] + E3[d][1], P[2] + E3[d][2]};
+              o.nb[d] = -1;
+              if (!wrap_in(c->p, nl, l, nbq) || !new_cov(l, nbq)) continue;
+              const int ch[3] = {nbq[0] * r, nbq[1] * r, nbq[2] * r};
+              if (old_cov(l + 1, ch) && new_cov(l + 1, ch)) continue;  // a hole before and after
+              o.nb[d] = (int32_t)Cl.off(nbq);
+            }
+            out.push_back(o);
+          }
+      });
+      if (ops.empty()) continue;
+      RegridArgs3 a{};
+      a.coarse_cur = Cl.buf[Cl.cur()];
+      a.fine0 = F.buf[0];
+      a.fine1 = F.buf[1];
+      a.fplane = F.plane;
+      a.fslab = F.slab;
+      a.fpitch = F.pitch;
+      a.cplane = Cl.plane;
+      a.r = r;
+      RegridOp3 *d = nullptr;
+      st = upload_ops(ops, d);
+      if (st) return st;
+      a.ops = d;
+      a.nops = (int32_t)ops.size();
+      HIPCHK3(launch_split3(a, c->fp32, c->stream));
+    }
+    HIPCHK3(hipStreamSynchronize(c->stream));
+    for (void *p : scratch) c->mem.release(p);
+    scratch.clear();
+    tm.mark("splits+sync");
+    // 4. install the new hierarchy and rebuild its lists
+    std::vector<int64_t> old_faces[kL];
+    for (int l = 0; l < onlev; ++l) old_faces[l].swap(c->lv[l].face_key);
+    for (int l = 0; l < kL; ++l) free_level3(c->mem, c->lv[l]);
+    for (int l = 0; l < kL; ++l) c->lv[l] = std::move(nl[l]);
+    c->nlev = nnlev;
+    st = build_lists3(c);
     if (st) return st;
-    a.ops = d;
-    a.nops = (int32_t)ops.size();
-    HIPCHK3(launch_split3(a, c->fp32, c->stream));
-  }
-  HIPCHK3(hipStreamSynchronize(c->stream));
-  for (void *p : scratch) c->mem.release(p);
-  scratch.clear();
-  tm.mark("splits+sync");
-  // 4. install the new hierarchy and rebuild its lists
-  std::vector<int64_t> old_faces[kL];
-  for (int l = 0; l < onlev; ++l) old_faces[l].swap(c->lv[l].face_key);
-  for (int l = 0; l < kL; ++l) free_level3(c->mem, c->lv[l]);
-  for (int l = 0; l < kL; ++l) c->lv[l] = std::move(nl[l]);
-  c->nlev = nnlev;
-  st = build_lists3(c);
-  if (st) return st;
-  tm.mark("lists");
-  // 5. an interface that exists before and after keeps its reconstruction
-  //    unmodified (Sec. 3.4); a face the regrid creates starts flat: the
-  //    population its ring cell hands into the new hole gets the current
-  //    value in the other buffer too
-  for (int l = 0; l + 1 < c->nlev; ++l) {
-    Level3 &N = c->lv[l];
-    std::vector<int32_t> items;
-    for (int64_t key : N.face_key) {
-      if (std::binary_search(old_faces[l].begin(), old_faces[l].end(), key)) continue;
-      const int64_t cell = key / 6;
-      const int p[3] = {(int)(cell % N.N[0]), (int)(cell / N.N[0] % N.N[1]), (int)(cell / ((int64_t)N.N[0] * N.N[1]))};
-      items.push_back((int32_t)N.off(p));
-      items.push_back((int32_t)(key % 6));
+    tm.mark("lists");
+    // 5. an interface that exists before and after keeps its reconstruction
+    //    unmodified (Sec. 3.4); a face the regrid creates starts flat: the
+    //    population its ring cell hands into the new hole gets the current
+    //    value in the other buffer too
+    for (int l = 0; l + 1 < c->nlev; ++l) {
+      Level3 &N = c->lv[l];
+      std::vector<int32_t> items;
+      for (int64_t key : N.face_key) {
+        if (std::binary_search(old_faces[l].begin(), old_faces[l].end(), key)) continue;
+        const int64_t cell = key / 6;
+        const int p[3] = {(int)(cell % N.N[0]), (int)(cell / N.N[0] % N.N[1]), (int)(cell / ((int64_t)N.N[0] * N.N[1]))};
+        items.push_back((int32_t)N.off(p));
+        items.push_back((int32_t)(key % 6));
+      }
+      if (items.empty()) continue;
+      int32_t *d = nullptr;
+      ALLOC3(d, sizeof(int32_t) * items.size());
+      scratch.push_back(d);
+      HIPCHK3(hipMemcpyAsync(d, items.data(), sizeof(int32_t) * items.size(), hipMemcpyHostToDevice, c->stream));
+      HIPCHK3(launch_restart_faces3(N.buf[N.cur()], N.buf[N.cur() ^ 1], d, (int)(items.size() / 2), N.plane,
+                                    c->fp32, c->stream));
     }
-    if (items.empty()) continue;
-    int32_t *d = nullptr;
-    ALLOC3(d, sizeof(int32_t) * items.size());
-    scratch.push_back(d);
-    HIPCHK3(hipMemcpyAsync(d, items.data(), sizeof(int32_t) * items.size(), hipMemcpyHostToDevice, c->stream));
-    HIPCHK3(launch_restart_faces3(N.buf[N.cur()], N.buf[N.cur() ^ 1], d, (int)(items.size() / 2), N.plane,
-                                  c->fp32, c->stream));
-  }
-  HIPCHK3(hipStreamSynchronize(c->stream));
-  for (void *p : scratch) c->mem.release(p);
-  for (int l = 0; l < c->nlev; ++l) {
-    Level3 &L = c->lv[l];
-    ALLOC3(L.dstatus, L.status.size());
-    HIPCHK3(hipMemcpyAsync(L.dstatus, L.status.data(), L.status.size(), hipMemcpyHostToDevice, c->stream));
-  }
-  st = upload_lists3(c);
-  if (st) return st;
-  for (int l = 0; l < c->nlev; ++l)
-    if (c->lv[l].nledger > 0) {
-      HIPCHK3(hipMemcpy(c->lv[l].dledger, led, sizeof led, hipMemcpyHostToDevice));
-      break;
+    HIPCHK3(hipStreamSynchronize(c->stream));
+    for (void *p : scratch) c->mem.release(p);
+    for (int l = 0; l < c->nlev; ++l) {
+      Level3 &L = c->lv[l];
+      ALLOC3(L.dstatus, L.status.size());
+      HIPCHK3(hipMemcpyAsync(L.dstatus, L.status.data(), L.status.size(), hipMemcpyHostToDevice, c->stream));
     }
-  c->boxes.assign(boxes, boxes + nboxes);
-  st = build_tables3(c);
-  tm.mark("faces+upload");
-  return st;
+    st = upload_lists3(c);
+    if (st) return st;
+    for (int l = 0; l < c->nlev; ++l)
+      if (c->lv[l].nledger > 0) {
+        HIPCHK3(hipMemcpy(c->lv[l].dledger, led, sizeof led, hipMemcpyHostToDevice));
+        break;
+      }
+    c->boxes.assign(boxes, boxes + nboxes);
+    st = build_tables3(c);
+    tm.mark("faces+upload");
+    return st;
+  });
 }
 
 vlbm_status vlbm3_set_state(vlbm3_ctx *c, int level, int i0, int j0, int k0, int nx, int ny, int nz,
@@ -1705,7 +1724,7 @@ vlbm_status vlbm3_set_tuning(vlbm3_ctx *c, int tile_cells, int flags) {
   vlbm_status st = vlbm3_conserved_totals(c, tot, led);
   if (st) return st;
   for (int l = 0; l < c->nlev; ++l) free_lists3(c->mem, c->lv[l]);
-  st = build_lists3(c);
+  st = guard3([&] { return build_lists3(c); });
   if (!st) st = upload_lists3(c);
   if (st) return st;
   // put the carried ledger into the first slot that exists
@@ -1769,23 +1788,25 @@ vlbm_status vlbm3_tag(vlbm3_ctx *c, int level, double threshold, unsigned char *
 }
 
 vlbm_status vlbm3_tag_and_regrid(vlbm3_ctx *c, double threshold, int buffer, int min_box, int max_box) {
-  if (!c) return fail3(VLBM_EINVAL, "null context");
-  if (!c->have_hierarchy) return fail3(VLBM_ESTATE, "no hierarchy installed");
-  if (buffer < 0 || min_box < 1 || max_box < min_box) return fail3(VLBM_EINVAL, "bad clustering sizes");
-  const int ML = c->p.max_levels;
-  if (ML < 2) return VLBM_OK;
-  PhaseTimer tm("tag_and_regrid3");
-  std::vector<TagMap3> tags(ML);
-  for (int l = 0; l < c->nlev; ++l) {
-    if (!c->lv[l].present) continue;
-    vlbm_status st = tag_frame3(c, l, threshold, tags[l]);
-    if (st) return st;
-  }
-  tm.mark("tags");
-  std::vector<vlbm3_box> boxes;
-  cluster_hierarchy3(c, tags, buffer, min_box, max_box, boxes);
-  tm.mark("cluster");
-  return vlbm3_regrid(c, boxes.data(), (int)boxes.size());
+  return guard3([&]() -> vlbm_status {
+    if (!c) return fail3(VLBM_EINVAL, "null context");
+    if (!c->have_hierarchy) return fail3(VLBM_ESTATE, "no hierarchy installed");
+    if (buffer < 0 || min_box < 1 || max_box < min_box) return fail3(VLBM_EINVAL, "bad clustering sizes");
+    const int ML = c->p.max_levels;
+    if (ML < 2) return VLBM_OK;
+    PhaseTimer tm("tag_and_regrid3");
+    std::vector<TagMap3> tags(ML);
+    for (int l = 0; l < c->nlev; ++l) {
+      if (!c->lv[l].present) continue;
+      vlbm_status st = tag_frame3(c, l, threshold, tags[l]);
+      if (st) return st;
+    }
+    tm.mark("tags");
+    std::vector<vlbm3_box> boxes;
+    cluster_hierarchy3(c, tags, buffer, min_box, max_box, boxes);
+    tm.mark("cluster");
+    return vlbm3_regrid(c, boxes.data(), (int)boxes.size());
+  });
 }
 
 vlbm_status vlbm3_get_boxes(vlbm3_ctx *c, vlbm3_box *boxes, int cap, int *nboxes) {
