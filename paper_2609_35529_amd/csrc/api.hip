@@ -785,6 +785,19 @@ vlbm_status build_fused(vlbm_ctx *c, int l, const std::unordered_map<int64_t, in
   return VLBM_OK;
 }
 
+// An entry point's body that builds host tables: an exception (host memory
+// exhausted) becomes a status, not a throw across the C ABI.
+template <class F>
+vlbm_status guarded(F &&f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc &) {
+    return fail(VLBM_ENOMEM, "host memory exhausted");
+  } catch (...) {
+    return fail(VLBM_EINVAL, "internal error in a host section");
+  }
+}
+
 // Run f(i) for i in [0, n) on the process's worker pool and this thread
 // (independent items, in any order and concurrency). The status of the lowest
 // failing index is returned, with its message (messages are per thread).
@@ -2647,7 +2660,9 @@ vlbm_status set_hierarchy_impl(vlbm_ctx *c, const vlbm_box *boxes, int nboxes, c
 extern "C" {
 
 vlbm_status vlbm_set_hierarchy(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
-  return set_hierarchy_impl(c, boxes, nboxes, nullptr);
+  return guarded([&]() -> vlbm_status {
+    return set_hierarchy_impl(c, boxes, nboxes, nullptr);
+  });
 }
 
 vlbm_status vlbm_set_state(vlbm_ctx *c, int level, int i0, int j0, int nx, int ny,
@@ -2818,162 +2833,166 @@ vlbm_status vlbm_get_boxes(vlbm_ctx *c, vlbm_box *boxes, int cap, int *nboxes) {
 }
 
 vlbm_status vlbm_regrid(vlbm_ctx *c, const vlbm_box *boxes, int nboxes) {
-  if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "no hierarchy installed");
-  // The same boxes again: nothing is merged or split and every interface is
-  // kept, so the hierarchy, its lists and both time levels stay as they are.
-  if (nboxes >= 0 && (size_t)nboxes == c->boxes.size() && (nboxes == 0 || boxes)) {
-    bool same = true;
-    for (int b = 0; b < nboxes && same; ++b) {
-      const vlbm_box &u = boxes[b], &v = c->boxes[b];
-      same = u.level == v.level && u.i0 == v.i0 && u.j0 == v.j0 && u.nx == v.nx && u.ny == v.ny;
+  return guarded([&]() -> vlbm_status {
+    if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "no hierarchy installed");
+    // The same boxes again: nothing is merged or split and every interface is
+    // kept, so the hierarchy, its lists and both time levels stay as they are.
+    if (nboxes >= 0 && (size_t)nboxes == c->boxes.size() && (nboxes == 0 || boxes)) {
+      bool same = true;
+      for (int b = 0; b < nboxes && same; ++b) {
+        const vlbm_box &u = boxes[b], &v = c->boxes[b];
+        same = u.level == v.level && u.i0 == v.i0 && u.j0 == v.j0 && u.nx == v.nx && u.ny == v.ny;
+      }
+      if (same) return VLBM_OK;
     }
-    if (same) return VLBM_OK;
-  }
-  return regrid_impl(c, boxes, nboxes);
+    return regrid_impl(c, boxes, nboxes);
+  });
 }
 
 vlbm_status vlbm_tag_and_regrid(vlbm_ctx *c, double thr, int buffer, int min_box, int max_box) {
-  if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "no hierarchy installed");
-  if (buffer < 0 || min_box < 1 || max_box < min_box) return fail(VLBM_EINVAL, "bad clustering sizes");
-  PhaseTimer tm("tag_and_regrid");
-  const int ML = c->p.max_levels;
-  if (ML < 2) return VLBM_OK;
-  const int r = c->p.r;
-  const int nclu = std::min(c->nlev, ML - 1);  // levels whose tags make the next level's boxes
-  // 1. tags of every present level on the device (indexed like each level's
-  //    status); a tagged cell also tags its parent, finest level first, so
-  //    refined features keep their levels. Scratch: slots of the context's
-  //    tag scratch (kept between calls).
-  size_t next_slot = 0;
-  auto dalloc = [&](size_t n) -> void * { return c->scratch_slot(next_slot++, n); };
-  auto release = [&]() {};
-  if (getenv("VLBM_TIMING")) {  // separate the regrid's own time from the steps queued before it
-    HIPCHK(hipStreamSynchronize(c->stream));
-    tm.mark("queued steps");
-  }
-  std::vector<uint8_t *> dtag(c->nlev, nullptr);
-  for (int l = 0; l < c->nlev; ++l) {
-    const Level &L = c->lv[l];
-    dtag[l] = static_cast<uint8_t *>(dalloc((size_t)L.fw * L.nrows));
-    if (!dtag[l]) {
-      release();
-      return fail(VLBM_ENOMEM, "tag buffer");
+  return guarded([&]() -> vlbm_status {
+    if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "no hierarchy installed");
+    if (buffer < 0 || min_box < 1 || max_box < min_box) return fail(VLBM_EINVAL, "bad clustering sizes");
+    PhaseTimer tm("tag_and_regrid");
+    const int ML = c->p.max_levels;
+    if (ML < 2) return VLBM_OK;
+    const int r = c->p.r;
+    const int nclu = std::min(c->nlev, ML - 1);  // levels whose tags make the next level's boxes
+    // 1. tags of every present level on the device (indexed like each level's
+    //    status); a tagged cell also tags its parent, finest level first, so
+    //    refined features keep their levels. Scratch: slots of the context's
+    //    tag scratch (kept between calls).
+    size_t next_slot = 0;
+    auto dalloc = [&](size_t n) -> void * { return c->scratch_slot(next_slot++, n); };
+    auto release = [&]() {};
+    if (getenv("VLBM_TIMING")) {  // separate the regrid's own time from the steps queued before it
+      HIPCHK(hipStreamSynchronize(c->stream));
+      tm.mark("queued steps");
     }
-  }
-  hipError_t e = launch_level_tags(c, thr, dtag);
-  for (int l = c->nlev - 1; l >= 1 && e == hipSuccess; --l) {
-    const Level &F = c->lv[l], &P = c->lv[l - 1];
-    e = launch_tag_parents(dtag[l], F.dyrow, F.fx0, F.fy0, F.fw, F.nrows, dtag[l - 1], P.dsrow, P.fx0, P.fy0,
-                           P.fw, P.fh, r, c->stream);
-  }
-  // 2. per clustered level, the tiles within `buffer` of a tag, listed on the
-  //    device (few tiles of a large level are hit); only tile rows within
-  //    `buffer` of a stored frame row can hold one
-  const int T = std::max(1, (min_box + r - 1) / r);
-  std::vector<int32_t *> dlist(nclu, nullptr);
-  std::vector<int> cap(nclu, 0);
-  int *dcount = static_cast<int *>(dalloc(sizeof(int) * std::max(nclu, 1)));
-  if (!dcount) {
-    release();
-    return fail(VLBM_ENOMEM, "tile lists");
-  }
-  if (e == hipSuccess) e = hipMemsetAsync(dcount, 0, sizeof(int) * std::max(nclu, 1), c->stream);
-  std::vector<std::vector<int32_t>> trows(nclu);
-  for (int l = 0; l < nclu && e == hipSuccess; ++l) {
-    const Level &L = c->lv[l];
-    const int ntx = (L.Nx + T - 1) / T, nty = (L.Ny + T - 1) / T;
-    std::vector<uint8_t> want(nty, 0);
-    for (const auto &run : L.runs) {
-      const int ya = std::max(0, run.first) - buffer, yb = std::min(L.Ny, run.second) + buffer;
-      if (c->pery() && yb - ya >= L.Ny) {
-        std::fill(want.begin(), want.end(), 1);
-        break;
-      }
-      for (int y = ya; y < yb; ++y) {
-        int wy = y;
-        if (wy < 0 || wy >= L.Ny) {
-          if (!c->pery()) continue;
-          wy = (wy + L.Ny) % L.Ny;
-        }
-        want[wy / T] = 1;
+    std::vector<uint8_t *> dtag(c->nlev, nullptr);
+    for (int l = 0; l < c->nlev; ++l) {
+      const Level &L = c->lv[l];
+      dtag[l] = static_cast<uint8_t *>(dalloc((size_t)L.fw * L.nrows));
+      if (!dtag[l]) {
+        release();
+        return fail(VLBM_ENOMEM, "tag buffer");
       }
     }
-    for (int ty = 0; ty < nty; ++ty)
-      if (want[ty]) trows[l].push_back(ty);
-    const int64_t ntiles = (int64_t)ntx * (int64_t)trows[l].size();
-    if (ntiles >= (int64_t(1) << 31)) {
-      release();
-      return fail(VLBM_EINVAL, "clustering grid of level %d too large", l);
+    hipError_t e = launch_level_tags(c, thr, dtag);
+    for (int l = c->nlev - 1; l >= 1 && e == hipSuccess; --l) {
+      const Level &F = c->lv[l], &P = c->lv[l - 1];
+      e = launch_tag_parents(dtag[l], F.dyrow, F.fx0, F.fy0, F.fw, F.nrows, dtag[l - 1], P.dsrow, P.fx0, P.fy0,
+                             P.fw, P.fh, r, c->stream);
     }
-    cap[l] = (int)ntiles;
-    dlist[l] = static_cast<int32_t *>(dalloc(sizeof(int32_t) * (size_t)std::max<int64_t>(ntiles, 1)));
-    int32_t *dtrows = static_cast<int32_t *>(dalloc(sizeof(int32_t) * std::max<size_t>(trows[l].size(), 1)));
-    auto *dmasks = static_cast<unsigned long long *>(
-        dalloc(sizeof(unsigned long long) * (size_t)std::max(L.nrows, 1) * (size_t)((L.Nx + 63) / 64)));
-    if (!dlist[l] || !dtrows || !dmasks) {
+    // 2. per clustered level, the tiles within `buffer` of a tag, listed on the
+    //    device (few tiles of a large level are hit); only tile rows within
+    //    `buffer` of a stored frame row can hold one
+    const int T = std::max(1, (min_box + r - 1) / r);
+    std::vector<int32_t *> dlist(nclu, nullptr);
+    std::vector<int> cap(nclu, 0);
+    int *dcount = static_cast<int *>(dalloc(sizeof(int) * std::max(nclu, 1)));
+    if (!dcount) {
       release();
       return fail(VLBM_ENOMEM, "tile lists");
     }
-    if (!trows[l].empty())
-      e = stage_h2d(c, dtrows, trows[l].data(), sizeof(int32_t) * trows[l].size());
-    if (e == hipSuccess)
-      e = launch_tile_hits(dtag[l], L.dsrow, L.fx0, L.fy0, L.fw, L.fh, L.nrows, L.Nx, L.Ny, c->perx(), c->pery(),
-                           T, buffer, ntx, dtrows, (int)trows[l].size(), dmasks, dlist[l], cap[l], dcount + l,
-                           c->stream);
-  }
-  std::vector<int> count(std::max(nclu, 1), 0);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(count.data(), dcount, sizeof(int) * std::max(nclu, 1), hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  std::vector<std::vector<int32_t>> hits(nclu);
-  for (int l = 0; l < nclu && e == hipSuccess; ++l) {
-    hits[l].resize(std::min(count[l], cap[l]));
-    if (!hits[l].empty())
-      e = hipMemcpyAsync(hits[l].data(), dlist[l], sizeof(int32_t) * hits[l].size(), hipMemcpyDeviceToHost,
-                         c->stream);
-  }
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  release();
-  if (e == hipErrorOutOfMemory) return fail(VLBM_ENOMEM, "tag scratch");
-  if (e != hipSuccess) return fail(VLBM_EDEVICE, "tag and cluster: %s", hipGetErrorString(e));
-  tm.mark("tags+tiles");
-  // 3. boxes, level by level: each level's kept tiles must lie in the
-  //    coverage of the boxes just made for it
-  std::vector<vlbm_box> boxes;
-  CovMap cov;
-  cov.all = true;
-  for (int l = 0; l < nclu; ++l) {
-    const size_t before = boxes.size();
-    // the hits in tile order: a bit per tile of the scanned tile rows (the
-    // device appends them a wavefront at a time, in any order)
-    {
+    if (e == hipSuccess) e = hipMemsetAsync(dcount, 0, sizeof(int) * std::max(nclu, 1), c->stream);
+    std::vector<std::vector<int32_t>> trows(nclu);
+    for (int l = 0; l < nclu && e == hipSuccess; ++l) {
       const Level &L = c->lv[l];
       const int ntx = (L.Nx + T - 1) / T, nty = (L.Ny + T - 1) / T;
-      std::vector<int32_t> row_of(nty, -1);
-      for (size_t k = 0; k < trows[l].size(); ++k) row_of[trows[l][k]] = (int32_t)k;
-      const int64_t nbit = (int64_t)ntx * (int64_t)trows[l].size();
-      std::vector<uint64_t> bits((size_t)((nbit + 63) / 64), 0);
-      for (int32_t h : hits[l]) {
-        if (h < 0 || h / ntx >= nty || row_of[h / ntx] < 0) continue;  // only scanned tiles are listed
-        const int64_t k = (int64_t)row_of[h / ntx] * ntx + h % ntx;
-        bits[(size_t)(k >> 6)] |= 1ull << (k & 63);
-      }
-      size_t n = 0;
-      for (size_t wi = 0; wi < bits.size(); ++wi)
-        for (uint64_t w = bits[wi]; w; w &= w - 1) {
-          const int64_t k = (int64_t)wi * 64 + __builtin_ctzll(w);
-          hits[l][n++] = trows[l][(size_t)(k / ntx)] * ntx + (int32_t)(k % ntx);
+      std::vector<uint8_t> want(nty, 0);
+      for (const auto &run : L.runs) {
+        const int ya = std::max(0, run.first) - buffer, yb = std::min(L.Ny, run.second) + buffer;
+        if (c->pery() && yb - ya >= L.Ny) {
+          std::fill(want.begin(), want.end(), 1);
+          break;
         }
-      hits[l].resize(n);
+        for (int y = ya; y < yb; ++y) {
+          int wy = y;
+          if (wy < 0 || wy >= L.Ny) {
+            if (!c->pery()) continue;
+            wy = (wy + L.Ny) % L.Ny;
+          }
+          want[wy / T] = 1;
+        }
+      }
+      for (int ty = 0; ty < nty; ++ty)
+        if (want[ty]) trows[l].push_back(ty);
+      const int64_t ntiles = (int64_t)ntx * (int64_t)trows[l].size();
+      if (ntiles >= (int64_t(1) << 31)) {
+        release();
+        return fail(VLBM_EINVAL, "clustering grid of level %d too large", l);
+      }
+      cap[l] = (int)ntiles;
+      dlist[l] = static_cast<int32_t *>(dalloc(sizeof(int32_t) * (size_t)std::max<int64_t>(ntiles, 1)));
+      int32_t *dtrows = static_cast<int32_t *>(dalloc(sizeof(int32_t) * std::max<size_t>(trows[l].size(), 1)));
+      auto *dmasks = static_cast<unsigned long long *>(
+          dalloc(sizeof(unsigned long long) * (size_t)std::max(L.nrows, 1) * (size_t)((L.Nx + 63) / 64)));
+      if (!dlist[l] || !dtrows || !dmasks) {
+        release();
+        return fail(VLBM_ENOMEM, "tile lists");
+      }
+      if (!trows[l].empty())
+        e = stage_h2d(c, dtrows, trows[l].data(), sizeof(int32_t) * trows[l].size());
+      if (e == hipSuccess)
+        e = launch_tile_hits(dtag[l], L.dsrow, L.fx0, L.fy0, L.fw, L.fh, L.nrows, L.Nx, L.Ny, c->perx(), c->pery(),
+                             T, buffer, ntx, dtrows, (int)trows[l].size(), dmasks, dlist[l], cap[l], dcount + l,
+                             c->stream);
     }
-    cluster_level(c, l, hits[l], cov, min_box, max_box, boxes);
-    static const char *const kClu[] = {"cluster l0", "cluster l1", "cluster l2", "cluster l3+"};
-    tm.mark(kClu[std::min(l, 3)]);
-    if (boxes.size() == before || l + 2 >= ML) break;
-    cov = CovMap::of_boxes(boxes.data() + before, boxes.size() - before);
-  }
-  tm.mark("cluster");
-  return vlbm_regrid(c, boxes.data(), (int)boxes.size());
+    std::vector<int> count(std::max(nclu, 1), 0);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(count.data(), dcount, sizeof(int) * std::max(nclu, 1), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    std::vector<std::vector<int32_t>> hits(nclu);
+    for (int l = 0; l < nclu && e == hipSuccess; ++l) {
+      hits[l].resize(std::min(count[l], cap[l]));
+      if (!hits[l].empty())
+        e = hipMemcpyAsync(hits[l].data(), dlist[l], sizeof(int32_t) * hits[l].size(), hipMemcpyDeviceToHost,
+                           c->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    release();
+    if (e == hipErrorOutOfMemory) return fail(VLBM_ENOMEM, "tag scratch");
+    if (e != hipSuccess) return fail(VLBM_EDEVICE, "tag and cluster: %s", hipGetErrorString(e));
+    tm.mark("tags+tiles");
+    // 3. boxes, level by level: each level's kept tiles must lie in the
+    //    coverage of the boxes just made for it
+    std::vector<vlbm_box> boxes;
+    CovMap cov;
+    cov.all = true;
+    for (int l = 0; l < nclu; ++l) {
+      const size_t before = boxes.size();
+      // the hits in tile order: a bit per tile of the scanned tile rows (the
+      // device appends them a wavefront at a time, in any order)
+      {
+        const Level &L = c->lv[l];
+        const int ntx = (L.Nx + T - 1) / T, nty = (L.Ny + T - 1) / T;
+        std::vector<int32_t> row_of(nty, -1);
+        for (size_t k = 0; k < trows[l].size(); ++k) row_of[trows[l][k]] = (int32_t)k;
+        const int64_t nbit = (int64_t)ntx * (int64_t)trows[l].size();
+        std::vector<uint64_t> bits((size_t)((nbit + 63) / 64), 0);
+        for (int32_t h : hits[l]) {
+          if (h < 0 || h / ntx >= nty || row_of[h / ntx] < 0) continue;  // only scanned tiles are listed
+          const int64_t k = (int64_t)row_of[h / ntx] * ntx + h % ntx;
+          bits[(size_t)(k >> 6)] |= 1ull << (k & 63);
+        }
+        size_t n = 0;
+        for (size_t wi = 0; wi < bits.size(); ++wi)
+          for (uint64_t w = bits[wi]; w; w &= w - 1) {
+            const int64_t k = (int64_t)wi * 64 + __builtin_ctzll(w);
+            hits[l][n++] = trows[l][(size_t)(k / ntx)] * ntx + (int32_t)(k % ntx);
+          }
+        hits[l].resize(n);
+      }
+      cluster_level(c, l, hits[l], cov, min_box, max_box, boxes);
+      static const char *const kClu[] = {"cluster l0", "cluster l1", "cluster l2", "cluster l3+"};
+      tm.mark(kClu[std::min(l, 3)]);
+      if (boxes.size() == before || l + 2 >= ML) break;
+      cov = CovMap::of_boxes(boxes.data() + before, boxes.size() - before);
+    }
+    tm.mark("cluster");
+    return vlbm_regrid(c, boxes.data(), (int)boxes.size());
+  });
 }
 
 // Checkpoint layout: header; boxes; per present level its frame {bx0, bx1,
@@ -3066,95 +3085,97 @@ vlbm_status vlbm_save(vlbm_ctx *c, void *buf, size_t *bytes) {
 // checkpoint that does not fit the context (parameters, time stepping mode,
 // levels, frames, slot counts) is refused with VLBM_EINVAL.
 vlbm_status vlbm_load(vlbm_ctx *c, const void *buf, size_t bytes) {
-  if (!c || !buf) return fail(VLBM_EINVAL, "bad checkpoint");
-  const char *const base = static_cast<const char *>(buf);
-  size_t at = 0;
-  auto take = [&](void *v, size_t n) -> bool {
-    if (n > bytes - at) return false;
-    memcpy(v, base + at, n);
-    at += n;
-    return true;
-  };
-  CkptHeader h;
-  if (bytes < sizeof h || !take(&h, sizeof h) || memcmp(h.magic, "VLBMCK2", 8) != 0)
-    return fail(VLBM_EINVAL, "not a checkpoint");
-  {
-    const vlbm_params &a = h.p, &b = c->p;
-    bool same = a.nx0 == b.nx0 && a.ny0 == b.ny0 && a.dx0 == b.dx0 && a.gamma == b.gamma &&
-                a.c == b.c && a.beta == b.beta && a.r == b.r && a.max_levels == b.max_levels &&
-                a.precision == b.precision && a.eos == b.eos && a.eos_a == b.eos_a && a.eos_b == b.eos_b;
-    for (int s = 0; s < 4; ++s) {
-      same = same && a.bc[s] == b.bc[s];
-      for (int k = 0; k < 4; ++k) same = same && a.w_inflow[s][k] == b.w_inflow[s][k];
+  return guarded([&]() -> vlbm_status {
+    if (!c || !buf) return fail(VLBM_EINVAL, "bad checkpoint");
+    const char *const base = static_cast<const char *>(buf);
+    size_t at = 0;
+    auto take = [&](void *v, size_t n) -> bool {
+      if (n > bytes - at) return false;
+      memcpy(v, base + at, n);
+      at += n;
+      return true;
+    };
+    CkptHeader h;
+    if (bytes < sizeof h || !take(&h, sizeof h) || memcmp(h.magic, "VLBMCK2", 8) != 0)
+      return fail(VLBM_EINVAL, "not a checkpoint");
+    {
+      const vlbm_params &a = h.p, &b = c->p;
+      bool same = a.nx0 == b.nx0 && a.ny0 == b.ny0 && a.dx0 == b.dx0 && a.gamma == b.gamma &&
+                  a.c == b.c && a.beta == b.beta && a.r == b.r && a.max_levels == b.max_levels &&
+                  a.precision == b.precision && a.eos == b.eos && a.eos_a == b.eos_a && a.eos_b == b.eos_b;
+      for (int s = 0; s < 4; ++s) {
+        same = same && a.bc[s] == b.bc[s];
+        for (int k = 0; k < 4; ++k) same = same && a.w_inflow[s][k] == b.w_inflow[s][k];
+      }
+      if (!same) return fail(VLBM_EINVAL, "checkpoint parameters differ from the context's");
     }
-    if (!same) return fail(VLBM_EINVAL, "checkpoint parameters differ from the context's");
-  }
-  if ((h.adt != 0) != c->adt)
-    return fail(VLBM_EINVAL, "checkpoint taken with the adaptive time step %s, context has it %s",
-                h.adt ? "on" : "off", c->adt ? "on" : "off");
-  if (h.nboxes < 0 || h.nlev < 1 || h.nlev > kMaxLevels || h.coarse_steps < 0 ||
-      (size_t)h.nboxes > (bytes - at) / sizeof(vlbm_box))
-    return fail(VLBM_EINVAL, "corrupt checkpoint header");
-  std::vector<vlbm_box> boxes(h.nboxes);
-  if (h.nboxes) take(boxes.data(), sizeof(vlbm_box) * h.nboxes);
-  FrameSpec specs[kMaxLevels];
-  for (int l = 0; l < h.nlev; ++l) {
-    int32_t fr[3];
-    if (!take(fr, sizeof fr)) return fail(VLBM_EINVAL, "truncated checkpoint");
-    if (fr[2] < 1 || fr[0] >= fr[1] || (size_t)fr[2] > (bytes - at) / (2 * sizeof(int32_t)))
-      return fail(VLBM_EINVAL, "corrupt checkpoint frame (level %d)", l);
-    specs[l].bx0 = fr[0];
-    specs[l].bx1 = fr[1];
-    for (int i = 0; i < fr[2]; ++i) {
-      int32_t rr[2];
-      take(rr, sizeof rr);
-      if (rr[0] >= rr[1] || (!specs[l].rows.empty() && rr[0] <= specs[l].rows.back().second))
+    if ((h.adt != 0) != c->adt)
+      return fail(VLBM_EINVAL, "checkpoint taken with the adaptive time step %s, context has it %s",
+                  h.adt ? "on" : "off", c->adt ? "on" : "off");
+    if (h.nboxes < 0 || h.nlev < 1 || h.nlev > kMaxLevels || h.coarse_steps < 0 ||
+        (size_t)h.nboxes > (bytes - at) / sizeof(vlbm_box))
+      return fail(VLBM_EINVAL, "corrupt checkpoint header");
+    std::vector<vlbm_box> boxes(h.nboxes);
+    if (h.nboxes) take(boxes.data(), sizeof(vlbm_box) * h.nboxes);
+    FrameSpec specs[kMaxLevels];
+    for (int l = 0; l < h.nlev; ++l) {
+      int32_t fr[3];
+      if (!take(fr, sizeof fr)) return fail(VLBM_EINVAL, "truncated checkpoint");
+      if (fr[2] < 1 || fr[0] >= fr[1] || (size_t)fr[2] > (bytes - at) / (2 * sizeof(int32_t)))
         return fail(VLBM_EINVAL, "corrupt checkpoint frame (level %d)", l);
-      specs[l].rows.push_back({rr[0], rr[1]});
+      specs[l].bx0 = fr[0];
+      specs[l].bx1 = fr[1];
+      for (int i = 0; i < fr[2]; ++i) {
+        int32_t rr[2];
+        take(rr, sizeof rr);
+        if (rr[0] >= rr[1] || (!specs[l].rows.empty() && rr[0] <= specs[l].rows.back().second))
+          return fail(VLBM_EINVAL, "corrupt checkpoint frame (level %d)", l);
+        specs[l].rows.push_back({rr[0], rr[1]});
+      }
     }
-  }
-  vlbm_status st = set_hierarchy_impl(c, boxes.data(), h.nboxes, specs);
-  if (st) return st;
-  if (c->nlev != h.nlev) return fail(VLBM_EINVAL, "checkpoint level count mismatch");
-  for (int l = 0; l < c->nlev; ++l) {
-    Level &L = c->lv[l];
-    int64_t steps;
-    int32_t counts[2];
-    if (!take(&steps, sizeof steps) || !take(counts, sizeof counts)) return fail(VLBM_EINVAL, "truncated checkpoint");
-    if (steps < 0 || counts[0] != L.nacc || counts[1] != L.nledger)
-      return fail(VLBM_EINVAL, "checkpoint level %d does not match its hierarchy", l);
-    const size_t nb = level_bytes(L, c->esz);
-    const size_t slots = sizeof(double) * 4 * ((size_t)L.nacc + L.nledger);
-    if (bytes - at < 2 * nb || bytes - at - 2 * nb < slots) return fail(VLBM_EINVAL, "truncated checkpoint");
-    L.steps = steps;
-    for (int b = 0; b < 2; ++b) {
-      HIPCHK(hipMemcpyAsync(L.buf[b], base + at, nb, hipMemcpyHostToDevice, c->stream));
-      at += nb;
+    vlbm_status st = set_hierarchy_impl(c, boxes.data(), h.nboxes, specs);
+    if (st) return st;
+    if (c->nlev != h.nlev) return fail(VLBM_EINVAL, "checkpoint level count mismatch");
+    for (int l = 0; l < c->nlev; ++l) {
+      Level &L = c->lv[l];
+      int64_t steps;
+      int32_t counts[2];
+      if (!take(&steps, sizeof steps) || !take(counts, sizeof counts)) return fail(VLBM_EINVAL, "truncated checkpoint");
+      if (steps < 0 || counts[0] != L.nacc || counts[1] != L.nledger)
+        return fail(VLBM_EINVAL, "checkpoint level %d does not match its hierarchy", l);
+      const size_t nb = level_bytes(L, c->esz);
+      const size_t slots = sizeof(double) * 4 * ((size_t)L.nacc + L.nledger);
+      if (bytes - at < 2 * nb || bytes - at - 2 * nb < slots) return fail(VLBM_EINVAL, "truncated checkpoint");
+      L.steps = steps;
+      for (int b = 0; b < 2; ++b) {
+        HIPCHK(hipMemcpyAsync(L.buf[b], base + at, nb, hipMemcpyHostToDevice, c->stream));
+        at += nb;
+      }
+      if (L.nacc) HIPCHK(hipMemcpyAsync(L.dacc, base + at, sizeof(double) * 4 * L.nacc, hipMemcpyHostToDevice, c->stream));
+      at += sizeof(double) * 4 * L.nacc;
+      if (L.nledger)
+        HIPCHK(hipMemcpyAsync(L.dledger, base + at, sizeof(double) * 4 * L.nledger, hipMemcpyHostToDevice, c->stream));
+      at += sizeof(double) * 4 * L.nledger;
     }
-    if (L.nacc) HIPCHK(hipMemcpyAsync(L.dacc, base + at, sizeof(double) * 4 * L.nacc, hipMemcpyHostToDevice, c->stream));
-    at += sizeof(double) * 4 * L.nacc;
-    if (L.nledger)
-      HIPCHK(hipMemcpyAsync(L.dledger, base + at, sizeof(double) * 4 * L.nledger, hipMemcpyHostToDevice, c->stream));
-    at += sizeof(double) * 4 * L.nledger;
-  }
-  if (c->adt) {
-    double dyn[DYN_SLOTS];
-    HIPCHK(hipMemcpyAsync(dyn, c->ddyn, sizeof dyn, hipMemcpyDeviceToHost, c->stream));
+    if (c->adt) {
+      double dyn[DYN_SLOTS];
+      HIPCHK(hipMemcpyAsync(dyn, c->ddyn, sizeof dyn, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      dyn[DYN_C] = h.dyn_c;
+      dyn[DYN_H] = 1.0 / (2.0 * h.dyn_c);
+      dyn[DYN_C_PREV] = h.dyn_c_prev;
+      dyn[DYN_TIME] = h.dyn_time;
+      HIPCHK(hipMemcpyAsync(c->ddyn, dyn, sizeof dyn, hipMemcpyHostToDevice, c->stream));
+      c->cfl_stale = true;
+    }
     HIPCHK(hipStreamSynchronize(c->stream));
-    dyn[DYN_C] = h.dyn_c;
-    dyn[DYN_H] = 1.0 / (2.0 * h.dyn_c);
-    dyn[DYN_C_PREV] = h.dyn_c_prev;
-    dyn[DYN_TIME] = h.dyn_time;
-    HIPCHK(hipMemcpyAsync(c->ddyn, dyn, sizeof dyn, hipMemcpyHostToDevice, c->stream));
-    c->cfl_stale = true;
-  }
-  HIPCHK(hipStreamSynchronize(c->stream));
-  c->coarse_steps = h.coarse_steps;
-  for (int k = 0; k < 4; ++k) {
-    c->ledger_carry[k] = h.carry[k];
-    c->ledger_carry_c[k] = h.carry_c[k];
-  }
-  return build_tables(c);
+    c->coarse_steps = h.coarse_steps;
+    for (int k = 0; k < 4; ++k) {
+      c->ledger_carry[k] = h.carry[k];
+      c->ledger_carry_c[k] = h.carry_c[k];
+    }
+    return build_tables(c);
+  });
 }
 
 }  // extern "C"
@@ -3435,18 +3456,20 @@ vlbm_status vlbm_batch_advance(vlbm_ctx *const *ctxs, const int *n_steps, int nc
 }
 
 vlbm_status vlbm_set_tuning(vlbm_ctx *c, int tile_cells, int flags) {
-  if (!c) return fail(VLBM_EINVAL, "null context");
-  if (tile_cells < 64 || tile_cells > (1 << 20) ||
-      (flags & ~(STEP_NT_STORES | STEP_TWO_CELLS | STEP_XCD_CONTIGUOUS | STEP_FUSE2 | STEP_XCD_FUSED | STEP_GRAPHS |
-                 STEP_SMALL_TILES)))
-    return fail(VLBM_EINVAL, "bad tuning (tile_cells %d, flags %d)", tile_cells, flags);
-  c->tile_cells = tile_cells;
-  c->step_flags = flags | (c->step_flags & STEP_F64_MATH);
-  c->use_graphs = (flags & STEP_GRAPHS) != 0;
-  if (!c->have_hierarchy) return VLBM_OK;
-  // same hierarchy and time history, new tile decomposition
-  std::vector<vlbm_box> boxes = c->boxes;
-  return regrid_impl(c, boxes.data(), (int)boxes.size());
+  return guarded([&]() -> vlbm_status {
+    if (!c) return fail(VLBM_EINVAL, "null context");
+    if (tile_cells < 64 || tile_cells > (1 << 20) ||
+        (flags & ~(STEP_NT_STORES | STEP_TWO_CELLS | STEP_XCD_CONTIGUOUS | STEP_FUSE2 | STEP_XCD_FUSED | STEP_GRAPHS |
+                   STEP_SMALL_TILES)))
+      return fail(VLBM_EINVAL, "bad tuning (tile_cells %d, flags %d)", tile_cells, flags);
+    c->tile_cells = tile_cells;
+    c->step_flags = flags | (c->step_flags & STEP_F64_MATH);
+    c->use_graphs = (flags & STEP_GRAPHS) != 0;
+    if (!c->have_hierarchy) return VLBM_OK;
+    // same hierarchy and time history, new tile decomposition
+    std::vector<vlbm_box> boxes = c->boxes;
+    return regrid_impl(c, boxes.data(), (int)boxes.size());
+  });
 }
 
 // Tuning cache: one entry per geometry (base grid, ratio, precision, boxes).
@@ -3479,80 +3502,82 @@ vlbm_status time_trial(vlbm_ctx *c, int tile_cells, int flags, int warm, int ste
 }  // namespace
 
 vlbm_status vlbm_autotune(vlbm_ctx *c, int steps_per_trial, int *tile_cells, int *flags) {
-  if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "no hierarchy installed");
-  if (steps_per_trial < 1) return fail(VLBM_EINVAL, "steps_per_trial < 1");
-  const std::string key = tuning_key(c);
-  auto hit = g_tuned.find(key);
-  vlbm_status st;
-  if (hit == g_tuned.end()) {
-    const int tiles[] = {128, 256, 512, 1024};
-    const bool can_fuse = c->p.r == 2 && c->nlev >= 2 && !c->sensor;
-    // workgroup order x store kind (x fused sub-steps where they apply)
-    std::vector<int> orders;
-    for (int fuse : {0, (int)STEP_FUSE2})
-      for (int nt : {0, (int)STEP_NT_STORES})
-        for (int xcd : {0, (int)STEP_XCD_CONTIGUOUS})
-          if (!fuse || can_fuse) orders.push_back(fuse | nt | xcd);
-    const int norders = (int)orders.size();
-    float best = 1e30f;
-    std::pair<int, int> choice{c->tile_cells, c->step_flags};
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    for (int tcell : tiles)
-      for (int oi = 0; oi < norders; ++oi) {
-        const int ord = orders[oi];
-        const int fl = (c->step_flags & ~(STEP_XCD_CONTIGUOUS | STEP_FUSE2 | STEP_NT_STORES | STEP_F64_MATH |
-                                          STEP_GRAPHS | STEP_SMALL_TILES)) | ord;
-        float ms = 0.f;
-        st = time_trial(c, tcell, fl, 1, steps_per_trial, e0, e1, &ms);
+  return guarded([&]() -> vlbm_status {
+    if (!c || !c->have_hierarchy) return fail(VLBM_ESTATE, "no hierarchy installed");
+    if (steps_per_trial < 1) return fail(VLBM_EINVAL, "steps_per_trial < 1");
+    const std::string key = tuning_key(c);
+    auto hit = g_tuned.find(key);
+    vlbm_status st;
+    if (hit == g_tuned.end()) {
+      const int tiles[] = {128, 256, 512, 1024};
+      const bool can_fuse = c->p.r == 2 && c->nlev >= 2 && !c->sensor;
+      // workgroup order x store kind (x fused sub-steps where they apply)
+      std::vector<int> orders;
+      for (int fuse : {0, (int)STEP_FUSE2})
+        for (int nt : {0, (int)STEP_NT_STORES})
+          for (int xcd : {0, (int)STEP_XCD_CONTIGUOUS})
+            if (!fuse || can_fuse) orders.push_back(fuse | nt | xcd);
+      const int norders = (int)orders.size();
+      float best = 1e30f;
+      std::pair<int, int> choice{c->tile_cells, c->step_flags};
+      hipEvent_t e0, e1;
+      HIPCHK(hipEventCreate(&e0));
+      HIPCHK(hipEventCreate(&e1));
+      for (int tcell : tiles)
+        for (int oi = 0; oi < norders; ++oi) {
+          const int ord = orders[oi];
+          const int fl = (c->step_flags & ~(STEP_XCD_CONTIGUOUS | STEP_FUSE2 | STEP_NT_STORES | STEP_F64_MATH |
+                                            STEP_GRAPHS | STEP_SMALL_TILES)) | ord;
+          float ms = 0.f;
+          st = time_trial(c, tcell, fl, 1, steps_per_trial, e0, e1, &ms);
+          if (st) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return st;
+          }
+          if (ms < best) {
+            best = ms;
+            choice = {tcell, fl};
+          }
+        }
+      // smaller tiles on levels with few tiles (STEP_SMALL_TILES), kept only
+      // if it saves more than 1%
+      if (!c->sensor) {
+        float base = 0.f, small = 0.f;
+        st = time_trial(c, choice.first, choice.second, 1, steps_per_trial, e0, e1, &base);
+        if (!st) st = time_trial(c, choice.first, choice.second | STEP_SMALL_TILES, 1, steps_per_trial, e0, e1, &small);
         if (st) {
           (void)hipEventDestroy(e0);
           (void)hipEventDestroy(e1);
           return st;
         }
-        if (ms < best) {
-          best = ms;
-          choice = {tcell, fl};
+        if (small < 0.99f * base) choice.second |= STEP_SMALL_TILES;
+      }
+      // graph replay of the chosen launches (an even number of steps, at least
+      // four, so that every step of the trial is replayed) where the context has
+      // a stream of its own; kept only if it saves more than 2%
+      if (c->stream != nullptr && !c->prof) {
+        const int gsteps = std::max(4, (steps_per_trial + 1) & ~1);
+        float plain = 0.f, graphed = 0.f;
+        st = time_trial(c, choice.first, choice.second, 2, gsteps, e0, e1, &plain);
+        if (!st) st = time_trial(c, choice.first, choice.second | STEP_GRAPHS, 4, gsteps, e0, e1, &graphed);
+        if (st) {
+          (void)hipEventDestroy(e0);
+          (void)hipEventDestroy(e1);
+          return st;
         }
+        if (graphed < 0.98f * plain) choice.second |= STEP_GRAPHS;
       }
-    // smaller tiles on levels with few tiles (STEP_SMALL_TILES), kept only
-    // if it saves more than 1%
-    if (!c->sensor) {
-      float base = 0.f, small = 0.f;
-      st = time_trial(c, choice.first, choice.second, 1, steps_per_trial, e0, e1, &base);
-      if (!st) st = time_trial(c, choice.first, choice.second | STEP_SMALL_TILES, 1, steps_per_trial, e0, e1, &small);
-      if (st) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        return st;
-      }
-      if (small < 0.99f * base) choice.second |= STEP_SMALL_TILES;
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      hit = g_tuned.emplace(key, choice).first;
     }
-    // graph replay of the chosen launches (an even number of steps, at least
-    // four, so that every step of the trial is replayed) where the context has
-    // a stream of its own; kept only if it saves more than 2%
-    if (c->stream != nullptr && !c->prof) {
-      const int gsteps = std::max(4, (steps_per_trial + 1) & ~1);
-      float plain = 0.f, graphed = 0.f;
-      st = time_trial(c, choice.first, choice.second, 2, gsteps, e0, e1, &plain);
-      if (!st) st = time_trial(c, choice.first, choice.second | STEP_GRAPHS, 4, gsteps, e0, e1, &graphed);
-      if (st) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        return st;
-      }
-      if (graphed < 0.98f * plain) choice.second |= STEP_GRAPHS;
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    hit = g_tuned.emplace(key, choice).first;
-  }
-  st = vlbm_set_tuning(c, hit->second.first, hit->second.second);
-  if (st) return st;
-  if (tile_cells) *tile_cells = c->tile_cells;
-  if (flags) *flags = c->step_flags & ~STEP_F64_MATH;
-  return VLBM_OK;
+    st = vlbm_set_tuning(c, hit->second.first, hit->second.second);
+    if (st) return st;
+    if (tile_cells) *tile_cells = c->tile_cells;
+    if (flags) *flags = c->step_flags & ~STEP_F64_MATH;
+    return VLBM_OK;
+  });
 }
 
 vlbm_status vlbm_set_sensor(vlbm_ctx *c, int on, double c_sensor, double beta_min, double beta_max) {
