@@ -186,11 +186,67 @@ def bench_3d(args):
                  "boxes_min": min(amr_timed["boxes"]), "boxes_max": max(amr_timed["boxes"])}
                 if args.amr_threshold is not None and amr_timed["boxes"] else None),
         "conservation_drift_rel": [float(abs((T1[k] - T0[k]) - (L1[k] - L0[k])) / scale) for k in range(5)],
-        "cpu_baseline": {"value": None, "unit": "fine-equiv cell updates/s", "cores": 1, "kind": "oracle",
-                         "sample": "not run: the oracle keeps dense arrays over the whole domain at "
-                                   "every level's resolution (the 512^3 fine level alone needs 129 GB)"},
+        "cpu_baseline": None,
     }
+    solver.close()
+    del solver
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if args.no_cpu_baseline:
+        out["cpu_baseline"] = {"value": None, "unit": "fine-equiv cell updates/s", "cores": 1, "kind": "oracle",
+                               "sample": "not run (--no-cpu-baseline)"}
+    else:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline_blast3d_downscale(args, prec, stream)
     print(json.dumps(out))
+
+
+def cpu_baseline_blast3d_downscale(args, prec, stream, mem_cap=8e9):
+    """The 3-D oracle, single-threaded, on the blast down-scaled to the
+    largest n0^3 (a multiple of 32) whose dense oracle arrays fit in mem_cap:
+    every level over the whole domain at its own resolution, 4 x 30 doubles
+    and 2 bytes per cell (96^3 coarse and its 192^3 fine level: 7.7 GB). The
+    hierarchy is the line's initial one (the central half refined), held
+    fixed; the oracle's steps are timed for about args.cpu_budget seconds. The
+    GPU advances the same down-scale as many steps, and the line reports their
+    largest relative population difference."""
+    import numpy as np
+    from oracle import oracle3 as O3
+    from paper_2609_35529_amd import vlbm3, workloads as wl
+    per_cell = 4 * 30 * 8 + 2
+    n0 = 32
+    while per_cell * ((n0 + 32) ** 3) * sum(8 ** l for l in range(2)) <= mem_cap:
+        n0 += 32
+    case = wl.blast3d(n0=n0, steps=0)
+    o = O3.Oracle3(case.nx0, case.ny0, case.nz0, case.dx0, r=case.r, nlev=case.nlev, gamma=case.gamma,
+                   c=case.c, beta=case.beta, bc=case.bc)
+    o.set_boxes(case.boxes)
+    for l in range(case.nlev):
+        o.set_state(l, case.full_state(l) if case.origins else case.states[l])
+    el, n = 0.0, 0
+    while el < args.cpu_budget or n < 2:
+        t0 = time.perf_counter()
+        o.advance(1)
+        el += time.perf_counter() - t0
+        n += 1
+    g = vlbm3.Solver3.from_case(case, stream=stream, precision=prec)
+    g.advance(n)
+    worst = 0.0
+    for l in range(case.nlev):
+        Fo, Fg = o.get_pop(l), g.get_populations(l)
+        m = ~np.isnan(Fo)
+        if m.any():
+            worst = max(worst, float(np.max(np.abs(Fg[m] - Fo[m]) / np.maximum(np.abs(Fo[m]), 1e-3))))
+    g.close()
+    upd = case.actual_updates_per_coarse_step()
+    return {"value": case.fine_equivalent_per_coarse_step() * n / el, "unit": "fine-equiv cell updates/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"blast3d down-scaled to {n0}^3 coarse with its central-half patch ({2 * n0}^3 fine "
+                      f"cells), the largest multiple of 32 whose dense oracle arrays fit in {mem_cap / 1e9:.0f} GB: "
+                      f"{n} coarse steps ({el:.1f} s), static hierarchy, FP64, one thread; the value is the "
+                      "down-scale's fine-equivalent rate",
+            "actual_updates_per_s": upd * n / el, "host": host_cpu(),
+            "gpu_vs_oracle_max_rel": worst, "gpu_vs_oracle_bitwise": bool(worst == 0.0 and prec == vlbm3.FP64)}
 
 
 def actual_updates_per_step(case):
