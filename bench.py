@@ -305,11 +305,13 @@ def cpu_baseline(case, budget_s=15.0, boxes=None, mem_cap=8e9, sensor=None, adap
                       f"one thread", "host": host_cpu()}
 
 
-def cpu_baseline_kh_downscale(args, prec, stream, n0=256):
+def cpu_baseline_kh_downscale(args, prec, stream, n0=256, strip=False):
     """The oracle, single-threaded, on the Kelvin-Helmholtz problem down-scaled
     to n0^2 coarse cells with the same three dynamic levels: the largest
     down-scale whose dense oracle arrays (every level over the whole domain,
-    the finest one 2048^2 here) fit in 8 GB. The hierarchy comes from the GPU
+    the finest one 2048^2 here) fit in 8 GB. With strip, the 4096 x 512 strip
+    down-scaled to n0 x n0 / 8 coarse cells (n0 = 1024: the finest level
+    8192 x 1024, 7.2 GB of dense arrays). The hierarchy comes from the GPU
     solver's tag-and-regrid on the same down-scale (regrid every
     args.regrid_every coarse steps), which the oracle follows box for box; the
     oracle's own steps are timed. The same run gives the GPU's difference to
@@ -319,9 +321,13 @@ def cpu_baseline_kh_downscale(args, prec, stream, n0=256):
     from paper_2609_35529_amd import vlbm, workloads as wl
     from tests import exact
     from tests.parity import fp32_error
-    case = wl.kelvin_helmholtz(n0=n0, seed=0, nlev=4, steps=0, dynamic=True)
-    thr, buf = DYNAMIC["kh4096"]["threshold"], args.amr_buffer
-    mn, mx = args.amr_min_box, args.amr_max_box or DYNAMIC["kh4096"]["max_box"]
+    key = "kh_strip" if strip else "kh4096"
+    if strip:
+        case = wl.kelvin_helmholtz_strip(n0=n0, ny0=n0 // 8, seed=0, nlev=4, steps=0)
+    else:
+        case = wl.kelvin_helmholtz(n0=n0, seed=0, nlev=4, steps=0, dynamic=True)
+    thr, buf = DYNAMIC[key]["threshold"], args.amr_buffer
+    mn, mx = args.amr_min_box, args.amr_max_box or DYNAMIC[key]["max_box"]
     g = vlbm.Solver.from_case(case, precision=prec, stream=stream)
     g.set_tuning(*DYNAMIC["kh4096"]["tuning"])
     for _ in range(case.nlev - 1):
@@ -355,12 +361,14 @@ def cpu_baseline_kh_downscale(args, prec, stream, n0=256):
         err = {"gpu_vs_oracle_smooth_rel_err": float(e.max()), "per_component": e.max(axis=0).tolist(),
                "per_level": e.max(axis=1).tolist(), "smooth_cells_per_level": cells}
     g.close()
+    what = (f"kelvin_helmholtz strip down-scaled to {n0}x{n0 // 8} coarse, 3 dynamic levels (finest "
+            f"{n0 * 8}x{n0}), whose dense oracle arrays fit in 8 GB" if strip else
+            f"kelvin_helmholtz down-scaled to {n0}^2 coarse, 3 dynamic levels (finest {n0 * 8}^2), "
+            "the largest down-scale whose dense oracle arrays fit in 8 GB")
     return {"value": case.fine_equivalent_per_coarse_step() * n / el, "unit": "fine-equiv cell updates/s",
             "cores": 1, "kind": "oracle",
-            "sample": f"kelvin_helmholtz down-scaled to {n0}^2 coarse, 3 dynamic levels (finest {n0 * 8}^2), "
-                      f"the largest down-scale whose dense oracle arrays fit in 8 GB: {n} coarse steps "
-                      f"({el:.1f} s) with a regrid every {args.regrid_every} on the GPU run's boxes, FP64, "
-                      "one thread; the value is the down-scale's fine-equivalent rate",
+            "sample": f"{what}: {n} coarse steps ({el:.1f} s) with a regrid every {args.regrid_every} on the GPU "
+                      "run's boxes, FP64, one thread; the value is the down-scale's fine-equivalent rate",
             "actual_updates_per_s": float(upd) * n / el, "host": host_cpu(), **err}
 
 
@@ -707,6 +715,8 @@ def main():
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         if args.workload == "kh4096":
             out["cpu_baseline"] = cpu_baseline_kh_downscale(args, prec, stream)
+        elif args.workload == "kh_strip":
+            out["cpu_baseline"] = cpu_baseline_kh_downscale(args, prec, stream, n0=1024, strip=True)
         else:
             out["cpu_baseline"] = cpu_baseline(build_case(args.workload, 10 ** 6), args.cpu_budget,
                                                boxes=timed_boxes if dynamic else None, sensor=sensor,
