@@ -1447,6 +1447,19 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
     if (st) return st;
     auto old_cov = [&](int l, const int q[3]) { return cov_in(c->lv, onlev, l, q); };
     auto new_cov = [&](int l, const int q[3]) { return cov_in(nl, nnlev, l, q); };
+    // coverage row (y, z) of level l of `lv` (null: not in its frame), indexed
+    // by x - f0[0] over the frame's columns
+    auto cov_row = [](const Level3 *lv, int nlev, int l, int y, int z) -> const uint8_t * {
+      if (l >= nlev || !lv[l].present) return nullptr;
+      const Level3 &L = lv[l];
+      if (y < L.f0[1] || y >= L.f0[1] + L.fn[1] || z < L.f0[2] || z >= L.f0[2] + L.fn[2]) return nullptr;
+      const int q[3] = {L.f0[0], y, z};
+      return &L.cov[L.fidx(q)];
+    };
+    auto in_row = [](const Level3 *lv, int l, const uint8_t *row, int x) {
+      const Level3 &L = lv[l];
+      return row && x >= L.f0[0] && x < L.f0[0] + L.fn[0] && row[x - L.f0[0]];
+    };
     std::vector<void *> scratch;  // device op lists, freed after the final sync
     auto upload_ops = [&](const std::vector<RegridOp3> &ops, RegridOp3 *&d) -> vlbm_status {
       ALLOC3(d, sizeof(RegridOp3) * std::max<size_t>(1, ops.size()));
@@ -1461,16 +1474,18 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
       const int nzs = (F.fn[2] - 2 + r - 1) / r;  // r-grid planes (the frame's first interior cell is aligned)
       const std::vector<RegridOp3> ops = par_collect<RegridOp3>((size_t)std::max(nzs, 0), [&](size_t iz, std::vector<RegridOp3> &out) {
         const int z = F.f0[2] + 1 + (int)iz * r;
-        for (int y = F.f0[1] + 1; y < F.f0[1] + F.fn[1] - 1; y += r)
+        for (int y = F.f0[1] + 1; y < F.f0[1] + F.fn[1] - 1; y += r) {
+          const uint8_t *fo = cov_row(c->lv, onlev, l, y, z), *fn = cov_row(nl, nnlev, l, y, z);
           for (int x = F.f0[0] + 1; x < F.f0[0] + F.fn[0] - 1; x += r) {
+            if (!fo[x - F.f0[0]] || in_row(nl, l, fn, x)) continue;
             const int q[3] = {x, y, z};
-            if (!F.cov[F.fidx(q)] || new_cov(l, q)) continue;
             const int P[3] = {x / r, y / r, z / r};
             RegridOp3 o{};
             o.dst = (int32_t)Cl.off(P);
             o.src = (int32_t)F.off(q);
             out.push_back(o);
           }
+        }
       });
       if (ops.empty()) continue;
       RegridArgs3 a{};
@@ -1551,10 +1566,11 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
       const int nzs = (F.fn[2] - 2 + r - 1) / r;
       const std::vector<RegridOp3> ops = par_collect<RegridOp3>((size_t)std::max(nzs, 0), [&](size_t iz, std::vector<RegridOp3> &out) {
         const int z = F.f0[2] + 1 + (int)iz * r;
-        for (int y = F.f0[1] + 1; y < F.f0[1] + F.fn[1] - 1; y += r)
+        for (int y = F.f0[1] + 1; y < F.f0[1] + F.fn[1] - 1; y += r) {
+          const uint8_t *fn = cov_row(nl, nnlev, l + 1, y, z), *fo = cov_row(c->lv, onlev, l + 1, y, z);
           for (int x = F.f0[0] + 1; x < F.f0[0] + F.fn[0] - 1; x += r) {
+            if (!fn[x - F.f0[0]] || in_row(c->lv, l + 1, fo, x)) continue;
             const int q[3] = {x, y, z};
-            if (!F.cov[F.fidx(q)] || old_cov(l + 1, q)) continue;
             const int P[3] = {x / r, y / r, z / r};
             RegridOp3 o{};
             o.dst = (int32_t)F.off(q);
@@ -1569,6 +1585,7 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
             }
             out.push_back(o);
           }
+        }
       });
       if (ops.empty()) continue;
       RegridArgs3 a{};
