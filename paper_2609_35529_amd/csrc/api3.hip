@@ -968,6 +968,27 @@ void kadd3(double &s, double &cmp, double v) {
   s = t;
 }
 
+// The boundary ledger of every level, summed as vlbm3_conserved_totals sums
+// it (compensated, level by level, slot by slot), without the audit of the
+// populations.
+vlbm_status ledger_sum3(vlbm3_ctx *c, double ledger[5]) {
+  double ls[5] = {}, lc[5] = {};
+  std::vector<std::vector<double>> led(c->nlev);
+  for (int l = 0; l < c->nlev; ++l) {
+    const Level3 &L = c->lv[l];
+    if (!L.nledger) continue;
+    led[l].resize(5 * (size_t)L.nledger);
+    HIPCHK3(hipMemcpyAsync(led[l].data(), L.dledger, sizeof(double) * led[l].size(), hipMemcpyDeviceToHost,
+                           c->stream));
+  }
+  HIPCHK3(hipStreamSynchronize(c->stream));
+  for (int l = 0; l < c->nlev; ++l)
+    for (int k = 0; k < 5; ++k)
+      for (int t = 0; t < c->lv[l].nledger; ++t) kadd3(ls[k], lc[k], led[l][5 * (size_t)t + k]);
+  for (int k = 0; k < 5; ++k) ledger[k] = ls[k] + lc[k];
+  return VLBM_OK;
+}
+
 bool wrap_in(const vlbm3_params &p, const Level3 *lv, int l, int q[3]) {
   for (int a = 0; a < 3; ++a) {
     const int n = lv[l].N[a];
@@ -1442,8 +1463,8 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
     tm.mark("geometry");
     const int r = c->p.r, onlev = c->nlev;
     // the boundary ledger survives the rebuild of its slots
-    double tot[5], led[5] = {};
-    st = vlbm3_conserved_totals(c, tot, led);
+    double led[5] = {};
+    st = ledger_sum3(c, led);
     if (st) return st;
     auto old_cov = [&](int l, const int q[3]) { return cov_in(c->lv, onlev, l, q); };
     auto new_cov = [&](int l, const int q[3]) { return cov_in(nl, nnlev, l, q); };
@@ -1737,8 +1758,8 @@ vlbm_status vlbm3_set_tuning(vlbm3_ctx *c, int tile_cells, int flags) {
   HIPCHK3(hipStreamSynchronize(c->stream));
   // the accumulators hold nothing between coarse steps and the ledger is
   // carried through the rebuild
-  double led[5] = {}, tot[5];
-  vlbm_status st = vlbm3_conserved_totals(c, tot, led);
+  double led[5] = {};
+  vlbm_status st = ledger_sum3(c, led);
   if (st) return st;
   for (int l = 0; l < c->nlev; ++l) free_lists3(c->mem, c->lv[l]);
   st = guard3([&] { return build_lists3(c); });
