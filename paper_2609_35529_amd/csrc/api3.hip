@@ -19,10 +19,12 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <new>
 #include <string>
 #include <thread>
 #include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "../../include/vlbm3.h"
@@ -80,6 +82,29 @@ vlbm_status guard3(F &&f) {
 constexpr int kL = VLBM3_MAX_LEVELS;
 const int E3[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
 
+// An allocator whose resize leaves new elements uninitialised: the frame-sized
+// host arrays (hundreds of MB on a large level) are then written once, by
+// their builders, in parallel.
+template <class T>
+struct NoInit : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInit<U>;
+  };
+  NoInit() = default;
+  template <class U>
+  NoInit(const NoInit<U> &) noexcept {}
+  template <class U>
+  void construct(U *q) noexcept {
+    ::new (static_cast<void *>(q)) U;
+  }
+  template <class U, class... A>
+  void construct(U *q, A &&...a) {
+    ::new (static_cast<void *>(q)) U(std::forward<A>(a)...);
+  }
+};
+using Bytes = std::vector<uint8_t, NoInit<uint8_t>>;
+
 struct Level3 {
   bool present = false;
   int N[3] = {0, 0, 0};
@@ -89,8 +114,8 @@ struct Level3 {
   int esz = 8;  // bytes per stored element
   int64_t slab = 0, plane = 0;
   void *buf[2] = {nullptr, nullptr};
-  std::vector<uint8_t> cov;     // per frame cell: covered at this level
-  std::vector<uint8_t> status;  // 0 none, 1 active, 2 hole
+  Bytes cov;     // per frame cell: covered at this level
+  Bytes status;  // 0 none, 1 active, 2 hole
   uint8_t *dstatus = nullptr;
   std::vector<Tile3> tiles;
   std::vector<Task3> tasks;
@@ -1018,27 +1043,34 @@ vlbm_status build_geometry3(const vlbm3_params &p, const vlbm3_box *boxes, int n
     if (lv[l].present && lv[l].plane >= (int64_t(1) << 31))
       return fail3(VLBM_EINVAL, "level %d frame too large for 32-bit offsets", l);
   }
+  // coverage, on the pool by frame planes: each thread clears its planes and
+  // fills the part of every box (level 0: the domain) that lies in them
   for (int l = 0; l < nlev; ++l) {
     Level3 &L = lv[l];
-    L.cov.assign((size_t)L.fn[0] * L.fn[1] * L.fn[2], 0);
-    auto fill = [&](const int lo[3], const int ext[3]) {
-      for (int z = lo[2]; z < lo[2] + ext[2]; ++z)
-        for (int y = lo[1]; y < lo[1] + ext[1]; ++y) {
-          int p0[3] = {lo[0], y, z};
-          memset(&L.cov[L.fidx(p0)], 1, ext[0]);
-        }
-    };
-    if (l == 0) {
-      const int lo[3] = {0, 0, 0};
-      fill(lo, L.N);
-    } else {
-      for (int b = 0; b < nboxes; ++b)
-        if (boxes[b].level == l) {
-          const int lo[3] = {boxes[b].i0, boxes[b].j0, boxes[b].k0};
-          const int ext[3] = {boxes[b].nx, boxes[b].ny, boxes[b].nz};
-          fill(lo, ext);
-        }
-    }
+    const size_t slab = (size_t)L.fn[0] * L.fn[1];
+    L.cov.resize(slab * L.fn[2]);
+    par_ranges((size_t)L.fn[2], 1, [&](size_t z0, size_t z1) {
+      memset(L.cov.data() + z0 * slab, 0, (z1 - z0) * slab);
+      const int za = L.f0[2] + (int)z0, zb = L.f0[2] + (int)z1;  // frame planes [za, zb)
+      auto fill = [&](const int lo[3], const int ext[3]) {
+        for (int z = std::max(lo[2], za); z < std::min(lo[2] + ext[2], zb); ++z)
+          for (int y = lo[1]; y < lo[1] + ext[1]; ++y) {
+            int p0[3] = {lo[0], y, z};
+            memset(&L.cov[L.fidx(p0)], 1, ext[0]);
+          }
+      };
+      if (l == 0) {
+        const int lo[3] = {0, 0, 0};
+        fill(lo, L.N);
+      } else {
+        for (int b = 0; b < nboxes; ++b)
+          if (boxes[b].level == l) {
+            const int lo[3] = {boxes[b].i0, boxes[b].j0, boxes[b].k0};
+            const int ext[3] = {boxes[b].nx, boxes[b].ny, boxes[b].nz};
+            fill(lo, ext);
+          }
+      }
+    });
   }
   // proper nesting: the parent of every covered cell and its face neighbours
   const int r = p.r;
@@ -1066,16 +1098,21 @@ vlbm_status build_geometry3(const vlbm3_params &p, const vlbm3_box *boxes, int n
   // whose parent cells form a block of whole level-l cells, are holes (2)
   for (int l = 0; l < nlev; ++l) {
     Level3 &L = lv[l];
-    L.status = L.cov;
-    for (int b = 0; b < nboxes; ++b) {
-      const vlbm3_box &B = boxes[b];
-      if (B.level != l + 1) continue;
-      for (int z = B.k0 / r; z < (B.k0 + B.nz) / r; ++z)
-        for (int y = B.j0 / r; y < (B.j0 + B.ny) / r; ++y) {
-          const int p0[3] = {B.i0 / r, y, z};
-          memset(&L.status[L.fidx(p0)], 2, B.nx / r);
-        }
-    }
+    const size_t slab = (size_t)L.fn[0] * L.fn[1];
+    L.status.resize(L.cov.size());
+    par_ranges((size_t)L.fn[2], 1, [&](size_t z0, size_t z1) {
+      memcpy(L.status.data() + z0 * slab, L.cov.data() + z0 * slab, (z1 - z0) * slab);
+      const int za = L.f0[2] + (int)z0, zb = L.f0[2] + (int)z1;
+      for (int b = 0; b < nboxes; ++b) {
+        const vlbm3_box &B = boxes[b];
+        if (B.level != l + 1) continue;
+        for (int z = std::max(B.k0 / r, za); z < std::min((B.k0 + B.nz) / r, zb); ++z)
+          for (int y = B.j0 / r; y < (B.j0 + B.ny) / r; ++y) {
+            const int p0[3] = {B.i0 / r, y, z};
+            memset(&L.status[L.fidx(p0)], 2, B.nx / r);
+          }
+      }
+    });
   }
   return VLBM_OK;
 }
