@@ -240,6 +240,24 @@ struct vlbm3_ctx {
   std::vector<std::pair<int, double>> pend;
   double prof_ms[kL] = {}, prof_cells[kL] = {};
   long prof_calls[kL] = {};
+  // pinned host buffer for reading the ledger slots back (grown on demand)
+  double *pin = nullptr;
+  size_t pin_cap = 0;  // doubles
+  double *pinned(size_t n) {
+    if (n > pin_cap) {
+      if (pin) (void)hipHostFree(pin);
+      pin = nullptr;
+      pin_cap = 0;
+      void *h = nullptr;
+      if (hipHostMalloc(&h, sizeof(double) * n, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+      pin = static_cast<double *>(h);
+      pin_cap = n;
+    }
+    return pin;
+  }
 
   bool periodic(int a) const { return p.bc[2 * a] == VLBM_BC_PERIODIC; }
   // wrap p (level l) by the periodic axes; false if outside a non-periodic side
@@ -998,18 +1016,28 @@ void kadd3(double &s, double &cmp, double v) {
 // populations.
 vlbm_status ledger_sum3(vlbm3_ctx *c, double ledger[5]) {
   double ls[5] = {}, lc[5] = {};
-  std::vector<std::vector<double>> led(c->nlev);
+  // every level's slots into one pinned buffer (a face of a 256^3 level has
+  // some 400,000 slots: 16 MB that a pageable copy takes milliseconds over)
+  size_t at[kL] = {}, total = 0;
+  for (int l = 0; l < c->nlev; ++l) {
+    at[l] = total;
+    total += 5 * (size_t)c->lv[l].nledger;
+  }
+  std::vector<double> pageable;
+  double *h = c->pinned(std::max<size_t>(total, 1));
+  if (!h) {
+    pageable.resize(std::max<size_t>(total, 1));
+    h = pageable.data();
+  }
   for (int l = 0; l < c->nlev; ++l) {
     const Level3 &L = c->lv[l];
     if (!L.nledger) continue;
-    led[l].resize(5 * (size_t)L.nledger);
-    HIPCHK3(hipMemcpyAsync(led[l].data(), L.dledger, sizeof(double) * led[l].size(), hipMemcpyDeviceToHost,
-                           c->stream));
+    HIPCHK3(hipMemcpyAsync(h + at[l], L.dledger, sizeof(double) * 5 * L.nledger, hipMemcpyDeviceToHost, c->stream));
   }
   HIPCHK3(hipStreamSynchronize(c->stream));
   for (int l = 0; l < c->nlev; ++l)
     for (int k = 0; k < 5; ++k)
-      for (int t = 0; t < c->lv[l].nledger; ++t) kadd3(ls[k], lc[k], led[l][5 * (size_t)t + k]);
+      for (int t = 0; t < c->lv[l].nledger; ++t) kadd3(ls[k], lc[k], h[at[l] + 5 * (size_t)t + k]);
   for (int k = 0; k < 5; ++k) ledger[k] = ls[k] + lc[k];
   return VLBM_OK;
 }
@@ -1433,6 +1461,7 @@ void vlbm3_destroy(vlbm3_ctx *c) {
   for (hipEvent_t ev : c->pev) (void)hipEventDestroy(ev);
   for (int l = 0; l < kL; ++l) free_level3(c->mem, c->lv[l]);
   dfree(c->mem, c->ddesc);
+  if (c->pin) (void)hipHostFree(c->pin);
   delete c;
 }
 
@@ -1503,6 +1532,7 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
     double led[5] = {};
     st = ledger_sum3(c, led);
     if (st) return st;
+    tm.mark("ledger");
     auto old_cov = [&](int l, const int q[3]) { return cov_in(c->lv, onlev, l, q); };
     auto new_cov = [&](int l, const int q[3]) { return cov_in(nl, nnlev, l, q); };
     // coverage row (y, z) of level l of `lv` (null: not in its frame), indexed
@@ -1545,6 +1575,7 @@ vlbm_status vlbm3_regrid(vlbm3_ctx *c, const vlbm3_box *boxes, int nboxes) {
           }
         }
       });
+      tm.mark("merge plan");
       if (ops.empty()) continue;
       RegridArgs3 a{};
       a.fine_cur = F.buf[F.cur()];
