@@ -672,21 +672,34 @@ vlbm_status build_lists3(vlbm3_ctx *c) {
         if (wst[w]) return fail3(wst[w], "%s", wmsg[w].c_str());
     }
     lt.mark("tasks");
-    for (size_t ti = 0; ti < L.tiles.size(); ++ti) {  // slots in tile order
-      const int acc0 = L.nacc, led0 = L.nledger;
-      for (Task3 &t : per[ti]) {
-        const int kind = t.kind & 0xFF;
-        if (kind == K3_REFLUX)
-          t.slot += acc0;
-        else if (kind == K3_OUTFLOW || kind == K3_REFLECT)
-          t.slot += led0;
+    // slots in tile order: each tile's first reflux and ledger slot from a
+    // prefix over the tiles, then its tasks renumbered on the pool
+    {
+      const size_t nt = L.tiles.size();
+      std::vector<int> acc0(nt + 1, 0), led0(nt + 1, 0);
+      for (size_t ti = 0; ti < nt; ++ti) {
+        acc0[ti + 1] = acc0[ti] + (int)trefl[ti].size();
+        led0[ti + 1] = led0[ti] + tled[ti];
       }
-      for (RefluxKey3 k : trefl[ti]) {
-        k.slot += acc0;
-        refl.push_back(k);
-      }
-      L.nacc += (int)trefl[ti].size();
-      L.nledger += tled[ti];
+      refl.resize(acc0[nt]);
+      par_ranges(nt, 64, [&](size_t t0, size_t t1) {
+        for (size_t ti = t0; ti < t1; ++ti) {
+          for (Task3 &t : per[ti]) {
+            const int kind = t.kind & 0xFF;
+            if (kind == K3_REFLUX)
+              t.slot += acc0[ti];
+            else if (kind == K3_OUTFLOW || kind == K3_REFLECT)
+              t.slot += led0[ti];
+          }
+          for (size_t j = 0; j < trefl[ti].size(); ++j) {
+            RefluxKey3 k = trefl[ti][j];
+            k.slot += acc0[ti];
+            refl[acc0[ti] + j] = k;
+          }
+        }
+      });
+      L.nacc = acc0[nt];
+      L.nledger = led0[nt];
     }
     lt.mark("slots");
     // captures of this level for the parent's reflux slots
@@ -752,14 +765,21 @@ vlbm_status build_lists3(vlbm3_ctx *c) {
     std::sort(L.face_key.begin(), L.face_key.end());
     lt.mark("face sort");
     caps_from_parent.swap(refl);
-    L.tasks.clear();
-    size_t ntask = 0;
-    for (const auto &v : per) ntask += v.size();
-    L.tasks.reserve(ntask);
-    for (size_t ti = 0; ti < L.tiles.size(); ++ti) {
-      L.tiles[ti].task0 = (int32_t)L.tasks.size();
-      L.tiles[ti].ntask = (int32_t)per[ti].size();
-      L.tasks.insert(L.tasks.end(), per[ti].begin(), per[ti].end());
+    // tasks grouped by tile, in tile order: offsets by a prefix, copies on
+    // the pool
+    {
+      const size_t nt = L.tiles.size();
+      size_t ntask = 0;
+      for (size_t ti = 0; ti < nt; ++ti) {
+        L.tiles[ti].task0 = (int32_t)ntask;
+        L.tiles[ti].ntask = (int32_t)per[ti].size();
+        ntask += per[ti].size();
+      }
+      L.tasks.resize(ntask);
+      par_ranges(nt, 64, [&](size_t t0, size_t t1) {
+        for (size_t ti = t0; ti < t1; ++ti)
+          std::copy(per[ti].begin(), per[ti].end(), L.tasks.begin() + L.tiles[ti].task0);
+      });
     }
     lt.mark("faces+order");
   }
