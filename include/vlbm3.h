@@ -20,8 +20,11 @@
  *
  * Conventions shared with include/vlbm.h: vlbm_status codes, vlbm_last_error,
  * every call returns a status and never throws, host arrays stay caller-owned,
- * device memory is the library's. Calls that return data synchronise the
- * context's stream; vlbm3_advance is asynchronous.
+ * device memory is the library's (and a pinned host buffer through which the
+ * boundary ledger is read back, grown on demand and freed by vlbm3_destroy).
+ * Calls that return data synchronise the context's stream; vlbm3_advance is
+ * asynchronous. Host work of hierarchy changes runs on a pool of worker
+ * threads shared by every context of the process.
  *
  * Host arrays: U[5][nz][ny][nx] (rho, rho u, rho v, rho w, E) and
  * F[30][nz][ny][nx] with plane index q * 5 + k, q in (+x, -x, +y, -y, +z, -z),
