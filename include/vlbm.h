@@ -38,7 +38,7 @@
  *   none is bound, allocated by the library; vlbm_destroy releases it. Table
  *   uploads go through a pinned host staging area of the context (4-64 MB,
  *   grown on demand, freed by vlbm_destroy). Host work of hierarchy changes
- *   (coverage, lists, clustering) runs on a pool of worker threads shared by
+ *   (coverage, tile and task lists) runs on a pool of worker threads shared by
  *   every context of the process. Work is
  *   issued on the HIP stream given at creation (NULL: the default stream);
  *   vlbm_advance returns before the GPU finishes, every call that returns data
